@@ -1,0 +1,208 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module only draws random numbers and lays out input arrays.  It holds
+none of the deblurring arithmetic (no wavelet transform, no blur, no sparse
+operator algebra), so that the CPU oracle and the GPU library can both be fed
+from it without sharing any step of the method.
+
+Everything is drawn with numpy's PCG64 (``numpy.random.default_rng``) in
+float64.  The paper's test images (Sec. 5, the 1024x1024 "book" and "confocal"
+pictures) are not available; the piecewise-smooth generator below stands in
+for them with values in [0, 1], the range the paper rescales its images to
+(Sec. 5).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Dict
+
+import numpy as np
+
+__all__ = [
+    "piecewise_image", "noise", "psf_isotropic", "psf_rotating", "PsfField",
+    "power_start", "banded_operator", "Workload", "WORKLOADS", "batched_problems",
+]
+
+
+def piecewise_image(n: int, seed: int) -> np.ndarray:
+    """n x n float64 image in [0, 1]: a linear ramp with 8 painted shapes.
+
+    Draw order (fixed, so the image is a function of ``seed`` only):
+    background c0 ~ U[0, .5], c1, c2 ~ U[-.25, .25] giving
+    c0 + c1*col/n + c2*row/n; then 8 shapes, each a disk (probability 1/2:
+    centre ~ U over the image, radius ~ U[n/16, n/4]) or an axis-aligned
+    rectangle (two corners ~ U over the image), filled with its own intensity
+    ~ U[0, 1] and overwriting what is below; finally clipped to [0, 1].
+    """
+    rng = np.random.default_rng(seed)
+    row, col = np.meshgrid(np.arange(n, dtype=np.float64),
+                           np.arange(n, dtype=np.float64), indexing="ij")
+    c0 = rng.uniform(0.0, 0.5)
+    c1 = rng.uniform(-0.25, 0.25)
+    c2 = rng.uniform(-0.25, 0.25)
+    img = c0 + c1 * col / n + c2 * row / n
+    for _ in range(8):
+        if rng.random() < 0.5:
+            cy, cx = rng.uniform(0.0, n, size=2)
+            rad = rng.uniform(n / 16.0, n / 4.0)
+            mask = (row - cy) ** 2 + (col - cx) ** 2 <= rad * rad
+        else:
+            ys = np.sort(rng.uniform(0.0, n, size=2))
+            xs = np.sort(rng.uniform(0.0, n, size=2))
+            mask = (row >= ys[0]) & (row <= ys[1]) & (col >= xs[0]) & (col <= xs[1])
+        img[mask] = rng.uniform(0.0, 1.0)
+    return np.clip(img, 0.0, 1.0)
+
+
+def noise(n: int, sigma: float, seed: int) -> np.ndarray:
+    """White Gaussian noise b ~ N(0, sigma^2 I) on an n x n grid (Sec. 1.1)."""
+    return np.random.default_rng(seed).normal(0.0, sigma, size=(n, n))
+
+
+@dataclass
+class PsfField:
+    """Per-source-pixel Gaussian PSF parameters, row-major (row, col) arrays.
+
+    ``sig_major``/``sig_minor`` are the standard deviations (pixels) along the
+    principal axes; ``angle`` (radians) turns the major axis from the column
+    (x) axis toward the row (y) axis.  ``trunc`` is the Mahalanobis radius at
+    which each PSF is cut off.
+    """
+    n: int
+    sig_major: np.ndarray
+    sig_minor: np.ndarray
+    angle: np.ndarray
+    trunc: float = 3.0
+
+    @property
+    def radius(self) -> int:
+        """Largest integer offset any truncated PSF of the field can reach."""
+        return int(math.floor(self.trunc * float(max(self.sig_major.max(), self.sig_minor.max()))))
+
+
+def psf_isotropic(n: int, s0: float = 1.0, s1: float = 3.0, trunc: float = 3.0) -> PsfField:
+    """Isotropic field sigma(col) = s0 + (s1 - s0) * col / n (constant down columns)."""
+    col = np.arange(n, dtype=np.float64)[None, :].repeat(n, axis=0)
+    sig = s0 + (s1 - s0) * col / n
+    return PsfField(n, sig.copy(), sig.copy(), np.zeros((n, n)), trunc)
+
+
+def psf_rotating(n: int, major: float, minor: float, trunc: float = 3.0) -> PsfField:
+    """Anisotropic field with fixed axis lengths whose angle is pi * col / n."""
+    col = np.arange(n, dtype=np.float64)[None, :].repeat(n, axis=0)
+    return PsfField(n, np.full((n, n), float(major)), np.full((n, n), float(minor)),
+                    math.pi * col / n, trunc)
+
+
+def power_start(size: int, seed: int) -> np.ndarray:
+    """Seeded N(0, 1) start vector for the power iteration."""
+    return np.random.default_rng(seed).standard_normal(size)
+
+
+def banded_operator(size: int, nnz_per_row: float, seed: int, far_fraction: float = 0.1,
+                    band: int = 64):
+    """A seeded random sparse square matrix (CSR, float64) with a dominant
+    diagonal, a band of near entries and a few far entries per row.
+
+    It mimics the storage-relevant structure of a thresholded wavelet-domain
+    operator (strong diagonal, entries concentrated near it, uneven row
+    lengths) so that full-size kernel parity can run on inputs the oracle did
+    not have to build.  Returns (rowptr int64, col int32, val float64).
+    """
+    rng = np.random.default_rng(seed)
+    lens = rng.geometric(1.0 / max(nnz_per_row - 1.0, 1.0), size=size)
+    lens = np.minimum(lens, 8 * int(nnz_per_row) + 1)
+    rows = np.repeat(np.arange(size, dtype=np.int64), lens)
+    m = rows.size
+    far = rng.random(m) < far_fraction
+    off = rng.integers(-band, band + 1, size=m)
+    offf = rng.integers(0, size, size=m)
+    cols = np.where(far, offf, (rows + off) % size)
+    key = np.unique(np.concatenate([rows * size + cols,
+                                    np.arange(size, dtype=np.int64) * (size + 1)]))
+    r = key // size
+    c = (key % size).astype(np.int32)
+    val = rng.normal(0.0, 0.3 / math.sqrt(nnz_per_row), size=key.size)
+    diag = r == c
+    val[diag] = rng.uniform(0.4, 1.0, size=int(diag.sum()))
+    rowptr = np.zeros(size + 1, dtype=np.int64)
+    np.add.at(rowptr, r + 1, 1)
+    rowptr = np.cumsum(rowptr)
+    return rowptr, c, val
+
+
+@dataclass
+class Workload:
+    """One named synthetic workload: image, blur field, basis and solver settings."""
+    name: str
+    n: int
+    wavelet: str            # "haar" or "db4"
+    levels: int
+    nnz_per_px: int
+    lam: float
+    noise_sigma: float
+    image_seed: int
+    noise_seed: int
+    power_seed: int
+    iters: int
+    field: str              # "isotropic" or "rotating"
+    field_args: Dict[str, float] = field(default_factory=dict)
+
+    @property
+    def nnz(self) -> int:
+        return self.nnz_per_px * self.n * self.n
+
+    def psf(self) -> PsfField:
+        if self.field == "isotropic":
+            return psf_isotropic(self.n, **self.field_args)
+        return psf_rotating(self.n, **self.field_args)
+
+    def image(self) -> np.ndarray:
+        return piecewise_image(self.n, self.image_seed)
+
+    def noise(self) -> np.ndarray:
+        return noise(self.n, self.noise_sigma, self.noise_seed)
+
+
+WORKLOADS: Dict[str, Workload] = {
+    # 64^2 parity case: Haar, 3 levels, sigma = 1 + 2 col/n, 40 nnz/px, 200 iterations.
+    "parity64": Workload("parity64", 64, "haar", 3, 40, 2e-3, 0.01, 1, 2, 3, 200,
+                         "isotropic", {"s0": 1.0, "s1": 3.0}),
+    # 512^2 precision case: db4, 5 levels, rotating 4/1 field, 30 nnz/px, 500 iterations.
+    "precision512": Workload("precision512", 512, "db4", 5, 30, 1e-3, 0.01, 11, 12, 13, 500,
+                             "rotating", {"major": 4.0, "minor": 1.0}),
+    # 1024^2 case: db4, 6 levels, rotating 6/1 field, 20 nnz/px, gap-checked stop.
+    "scale1024": Workload("scale1024", 1024, "db4", 6, 20, 5e-4, 0.005, 21, 22, 23, 2000,
+                          "rotating", {"major": 6.0, "minor": 1.0}),
+    # 256^2 warm-start case: db4, 4 levels, sigma = 1 + 2 col/n, 30 nnz/px.
+    "learned256": Workload("learned256", 256, "db4", 4, 30, 1e-3, 0.01, 50000, 150000, 53, 500,
+                           "isotropic", {"s0": 1.0, "s1": 3.0}),
+}
+
+
+def batched_problems(seed: int = 41, groups: int = 8, rhs: int = 8):
+    """Draw the uneven batched case: ``groups`` operators, each shared by ``rhs``
+    right-hand sides.  Per group: n ~ U{128, 256, 512, 1024}, levels = log2(n) - 4,
+    nnz/px ~ U{20..40}, a PSF field (isotropic ramp a..b with a, b ~ U[1, 5], or
+    rotating with minor ~ U[1, 2.5], major ~ U[minor, 5], each with probability
+    1/2) and per right-hand side lambda ~ logU[1e-4, 1e-2] plus image/noise seeds.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for g in range(groups):
+        n = int(rng.choice([128, 256, 512, 1024]))
+        levels = int(round(math.log2(n))) - 4
+        nnz_px = int(rng.integers(20, 41))
+        if rng.random() < 0.5:
+            a, b = rng.uniform(1.0, 5.0, size=2)
+            psf = ("isotropic", {"s0": float(a), "s1": float(b)})
+        else:
+            mn = rng.uniform(1.0, 2.5)
+            mj = rng.uniform(mn, 5.0)
+            psf = ("rotating", {"major": float(mj), "minor": float(mn)})
+        lams = np.exp(rng.uniform(math.log(1e-4), math.log(1e-2), size=rhs))
+        seeds = rng.integers(0, 2**31 - 1, size=(rhs, 2))
+        out.append({"n": n, "levels": levels, "nnz_per_px": nnz_px, "field": psf,
+                    "lams": lams.tolist(), "seeds": seeds.tolist()})
+    return out
