@@ -1,0 +1,261 @@
+/*
+ * wdb — wavelet-domain l1-l2 deblurring on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the hot path of Escande & Weiss, "Real-time l1-l2 deblurring
+ * using wavelet expansions of operators".  The method solves
+ *
+ *     min_x  1/2 || Theta_K x - Psi^* u ||_2^2 + lambda || x ||_1        (Sec. 1.3)
+ *
+ * where Theta = Psi^* H Psi is the blur H written in an orthogonal wavelet
+ * basis (Sec. 3.4) and Theta_K keeps its K largest-magnitude entries
+ * (Sec. 3.7), by the accelerated proximal gradient of Alg. 1 (Alg. 2 with a
+ * diagonal preconditioner, Sec. 4).  The deblurred image is Psi x.
+ *
+ * Conventions
+ *  - Images are n x n, n a power of two, row-major (index row * n + col),
+ *    float32, on the torus (circular boundaries, Sec. 2).
+ *  - Wavelet coefficient vectors have N = n*n float32 entries in this
+ *    order: the coarsest approximation A_J, then for level l = J..1 the three
+ *    detail subbands e = (0,1), (1,0), (1,1) (e_row, e_col: 1 = high-pass
+ *    along that axis), each row-major with side n / 2^l.  Level l = 1 is
+ *    the finest; the paper's scale index is j = log2(n) - l.
+ *  - Theta[a, b] = <psi_a, H psi_b>: row a is the output coefficient, column
+ *    b the input coefficient, so (Theta x)_a = sum_b Theta[a,b] x_b.
+ *  - The blur is H[i, s] = k_s(i - s): column s is the point spread function
+ *    of source pixel s (Sec. 3.1, kernel K(., y) is the PSF at y).  Each k_s
+ *    is a Gaussian with axes sig_major, sig_minor, the major axis turned by
+ *    `angle` from the column (x) axis toward the row (y) axis, cut where the
+ *    Mahalanobis distance exceeds `trunc`, normalised to unit sum.
+ *  - Pointers documented "device" must be HIP device memory of the current
+ *    device (e.g. from torch tensors); "host" pointers are ordinary memory.
+ *    The caller owns every buffer it passes; handles are owned by the
+ *    library until freed with wdb_theta_free.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *    Work is ordered on that stream; calls return once their work is queued
+ *    unless documented to synchronise.
+ *  - Every call returns a wdb_status; on failure it is negative, outputs are
+ *    left untouched where possible, and wdb_last_error() describes it.
+ *  - One handle must not be used by two calls at the same time.
+ */
+#ifndef WDB_H
+#define WDB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  WDB_OK = 0,
+  WDB_ERR_ARG = -1,          /* null pointer or invalid enum/parameter       */
+  WDB_ERR_SIZE = -2,         /* n not a power of two, PSF wider than image   */
+  WDB_ERR_LEVELS = -3,       /* too many levels for n and the filter length  */
+  WDB_ERR_NONFINITE = -4,    /* NaN/Inf in an input                           */
+  WDB_ERR_OOM = -5,          /* device or host allocation failed             */
+  WDB_ERR_HIP = -6,          /* a HIP runtime call failed                    */
+  WDB_ERR_DIVERGED = -7,     /* non-finite objective during a solve          */
+  WDB_ERR_NOT_CONVERGED = -8,/* tolerance not met within max_iters           */
+  WDB_ERR_FORMAT = -9        /* malformed sparse input                       */
+} wdb_status;
+
+typedef enum {
+  WDB_HAAR = 0,   /* Haar, 2 taps                                      */
+  WDB_DB4 = 1     /* Daubechies, 4 vanishing moments, 8 taps (Sec. 3.5) */
+} wdb_wavelet;
+
+/* Spatially varying Gaussian PSF field (Sec. 3.1).  Host arrays of n*n
+ * doubles indexed by SOURCE pixel (row * n + col).  Requirements: every
+ * sigma > 0 and finite, trunc > 0, and 2 * floor(trunc * max sig_major) + 1
+ * <= n (a PSF may not wrap onto itself). */
+typedef struct {
+  int32_t n;
+  const double* sig_major;
+  const double* sig_minor;
+  const double* angle;
+  double trunc;
+} wdb_psf_field;
+
+typedef struct wdb_theta wdb_theta;   /* opaque operator handle */
+
+/* Description of an operator handle. */
+typedef struct {
+  int32_t n;           /* image side                                   */
+  int32_t levels;      /* decomposition levels J                        */
+  int32_t wavelet;     /* wdb_wavelet                                   */
+  int32_t has_lipschitz;
+  int64_t nnz;         /* K, kept entries                               */
+  int64_t stored;      /* stored slots per copy including padding       */
+  double lipschitz;    /* L = ||Theta_K||_2^2 (valid if has_lipschitz)  */
+  double threshold;    /* smallest kept |Theta| (0 for imported)        */
+  double lipschitz_p;  /* lambda_max(P^-1/2 Theta_K^T Theta_K P^-1/2)    */
+  int32_t precond;     /* 0 none, else the wdb_precond kind in use      */
+  int32_t pad_;
+} wdb_theta_desc;
+
+/* ---------------------------------------------------------------------------
+ * Operator construction.
+ * ------------------------------------------------------------------------- */
+
+/* Theta = Psi^* H Psi (Sec. 3.4) for the PSF field, thresholded to the
+ * nnz_budget entries of largest magnitude (Sec. 3.7, naive rule; equal
+ * magnitudes at the cut keep the smaller linear index a*N + b; fewer
+ * non-zeros than the budget keeps them all).  Every entry is computed in
+ * float64 from its definition <psi_a, H psi_b> on the GPU; the kept values
+ * are stored as float32 for the solver and as float64 for export.
+ * `field` and its arrays are host memory, read during the call.
+ * Synchronises `stream`.  Errors: WDB_ERR_ARG, _SIZE, _LEVELS, _NONFINITE,
+ * _OOM, _HIP. */
+wdb_status wdb_build_theta(const wdb_psf_field* field, int32_t wavelet, int32_t levels,
+                           int64_t nnz_budget, void* stream, wdb_theta** out);
+
+/* Operator from a host CSR matrix (N = n*n rows, strictly increasing column
+ * indices within each row, values float64 rounded to float32 for the
+ * solver).  rowptr has N+1 entries with rowptr[0] = 0, rowptr[N] = nnz.
+ * Synchronises `stream`.  Errors: WDB_ERR_ARG, _SIZE, _LEVELS, _FORMAT,
+ * _NONFINITE, _OOM, _HIP. */
+wdb_status wdb_theta_import(int32_t n, int32_t wavelet, int32_t levels, int64_t nnz,
+                            const int64_t* rowptr, const int32_t* col, const double* val,
+                            void* stream, wdb_theta** out);
+
+/* Copy the kept entries to host CSR arrays sized from wdb_theta_info
+ * (rowptr: N+1, col/val: nnz).  val receives the float64 values (for a
+ * built operator, the values before rounding to float32).  Any of the three
+ * pointers may be NULL to skip it.  Synchronises. */
+wdb_status wdb_theta_export(const wdb_theta* th, int64_t* rowptr, int32_t* col, double* val);
+
+wdb_status wdb_theta_info(const wdb_theta* th, wdb_theta_desc* out);
+
+/* L = lambda_max(Theta_K^T Theta_K) = ||Theta_K||_2^2, the step 1/L of
+ * Alg. 1, by power iteration in float64 on the float32-stored operator:
+ * v_0 = start/||start||; w = Theta_K v, rho_k = ||w||^2, v = Theta_K^T w /
+ * ||Theta_K^T w||; stops at the first k >= 2 with |rho_k - rho_{k-1}| <=
+ * tol * rho_k, or at max_iters.  `start` is a host array of N doubles (NULL:
+ * a fixed SplitMix64-derived vector).  Stores L in the handle and returns it.
+ * Synchronises. */
+wdb_status wdb_theta_lipschitz(wdb_theta* th, const double* start, double tol,
+                               int32_t max_iters, double* L_out, int32_t* iters_out);
+
+/* Diagonal preconditioner P for Alg. 2 (Sec. 4), from M = Theta_K^T Theta_K:
+ *   WDB_PRECOND_NONE      remove it;
+ *   WDB_PRECOND_SPAI      P_ii = M^2_ii / M_ii (Sec. 4.3 lemma; 1 where M_ii = 0);
+ *   WDB_PRECOND_SPAI_SCALE one value per scale (A_J its own group),
+ *                         p_s = sum_s M^2_ii / sum_s M_ii, the minimiser of the
+ *                         same Frobenius objective under that constraint;
+ *   WDB_PRECOND_JACOBI    P = max(M_ii, eps) (Sec. 4.2).
+ * Also computes L_P = lambda_max(P^-1/2 M P^-1/2) by the power iteration
+ * above (start as in wdb_theta_lipschitz).  Synchronises. */
+typedef enum {
+  WDB_PRECOND_NONE = 0,
+  WDB_PRECOND_SPAI = 1,
+  WDB_PRECOND_SPAI_SCALE = 2,
+  WDB_PRECOND_JACOBI = 3
+} wdb_precond;
+wdb_status wdb_set_precond(wdb_theta* th, int32_t kind, double eps, const double* start,
+                           double tol, int32_t max_iters);
+
+/* Copy the diagonal P (N doubles, host) of the active preconditioner. */
+wdb_status wdb_get_precond(const wdb_theta* th, double* p_out);
+
+void wdb_theta_free(wdb_theta* th);
+
+/* ---------------------------------------------------------------------------
+ * Solver (Alg. 1 / Alg. 2).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t max_iters;     /* iterations to run (upper bound when tol > 0)           */
+  int32_t check_every;   /* float64 objective + duality gap every c iterations;
+                            0 = only once after the last iteration               */
+  double tol_rel_gap;    /* stop at the first check with gap/E <= tol (0: never)  */
+  const float* x_init;   /* device, N coefficients, or NULL for x = 0             */
+  int32_t k0;            /* index of the first iteration (>= 1; resume), 0 = 1     */
+  int32_t use_precond;   /* 1: Alg. 2 with the handle's preconditioner            */
+  void* stream;
+  double* trace;         /* host, optional: (k, E, rel_gap) per check             */
+  int32_t trace_cap;     /* number of triples `trace` can hold                    */
+  int32_t use_graph;     /* 1: replay the iterations between checks as a HIP graph */
+} wdb_solve_opts;
+
+typedef struct {
+  int32_t iters;         /* iterations run                                         */
+  int32_t checks;        /* float64 checks done                                     */
+  double objective;      /* E(x) = 1/2||Theta_K x - x0||^2 + lambda||x||_1 (float64) */
+  double rel_gap;        /* duality gap / E at the last check                       */
+  double lipschitz;      /* L (or L_P) used                                         */
+  double tau;            /* step 1/L                                                */
+} wdb_solve_info;
+
+/* Solve from a blurred image: x0 = Psi^* u (forward transform on the GPU),
+ * then FISTA iterations from x_init, x_out receives x^(k).  u: device n*n
+ * image; x_out: device N coefficients.  Computes L on first use if the
+ * handle has none (default start).  Every iteration is one fused
+ * r = Theta_K y - x0 kernel and one fused Theta_K^T r + soft-threshold +
+ * momentum kernel; the float64 check adds one product pair per check.
+ * Synchronises at each check.  Errors: WDB_ERR_ARG, _NONFINITE (lambda),
+ * _DIVERGED, _NOT_CONVERGED (tol > 0 not reached; x_out still written), _HIP. */
+wdb_status wdb_solve(wdb_theta* th, const float* u, float lambda, const wdb_solve_opts* opts,
+                     float* x_out, wdb_solve_info* info);
+
+/* Same as wdb_solve with the wavelet-domain data x0 (device, N) given directly. */
+wdb_status wdb_solve_coeffs(wdb_theta* th, const float* x0, float lambda,
+                            const wdb_solve_opts* opts, float* x_out, wdb_solve_info* info);
+
+/* Float64 objective E(x) and relative duality gap for coefficients x and data
+ * x0 (device arrays of N float32).  With r = Theta_K x - x0,
+ * s = min(1, lambda / ||Theta_K^T r||_inf): D = -s^2||r||^2/2 - s<r, x0>,
+ * gap = E - D.  Synchronises `stream`. */
+wdb_status wdb_objective(wdb_theta* th, const float* x, const float* x0, float lambda,
+                         void* stream, double* E_out, double* rel_gap_out);
+
+/* y = Theta_K x - b (transpose = 0) or y = Theta_K^T x - b (transpose = 1),
+ * float32, one kernel launch per repetition (repeat >= 1 launches the same
+ * product `repeat` times, for timing).  b may be NULL (treated as 0).
+ * x, b, y: device, N floats; y must not alias x. */
+wdb_status wdb_theta_apply(wdb_theta* th, int32_t transpose, const float* x, const float* b,
+                           float* y, int32_t repeat, void* stream);
+
+/* One fused proximal-gradient step (Alg. 1, steps 3-4) given the residual r:
+ * g = Theta_K^T r; z = y - tau * g / P; x_new = S_{tau*lambda/P}(z);
+ * y = x_new + beta (x_new - x); x = x_new  (P = 1 unless use_precond). */
+wdb_status wdb_prox_step(wdb_theta* th, const float* r, float* x, float* y, float tau,
+                         float lambda, float beta, int32_t use_precond, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Transforms.
+ * ------------------------------------------------------------------------- */
+
+/* Psi x: inverse transform of N coefficients to an n x n image (Sec. 2). */
+wdb_status wdb_synthesize(const wdb_theta* th, const float* x, float* u_hat, void* stream);
+
+/* Forward (inverse = 0: out = Psi^* in) or inverse (inverse = 1: out = Psi in)
+ * periodic orthogonal 2D transform with `levels` levels; in/out: device, n*n
+ * floats, must not alias.  Errors: WDB_ERR_ARG, _SIZE, _LEVELS, _HIP. */
+wdb_status wdb_dwt(int32_t n, int32_t wavelet, int32_t levels, const float* in, float* out,
+                   int32_t inverse, void* stream);
+
+/* out = H u for the PSF field (Sec. 3.1, column convention), float64
+ * arithmetic, float32 storage; u, out: device n*n floats, must not alias.
+ * Synchronises `stream` (uploads the field).  Errors: as wdb_build_theta. */
+wdb_status wdb_blur(const wdb_psf_field* field, const float* u, float* out, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Misc.
+ * ------------------------------------------------------------------------- */
+
+/* Message for the last failed call on this thread ("" if none). */
+const char* wdb_last_error(void);
+
+/* Library version string. */
+const char* wdb_version(void);
+
+/* Low-pass analysis filter the library uses for `wavelet` (derived in
+ * float64; Daubechies by spectral factorisation), written to h_out (host,
+ * room for 8 doubles); *len_out receives the number of taps.  Host only: no
+ * device is touched. */
+wdb_status wdb_wavelet_filter(int32_t wavelet, double* h_out, int32_t* len_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WDB_H */

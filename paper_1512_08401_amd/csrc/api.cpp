@@ -1,0 +1,113 @@
+// Error reporting, version and handle-level entry points of the wdb C ABI.
+#include <cstring>
+
+#include "common.hpp"
+
+namespace wdb {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void fail(wdb_status code, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  throw Error{code, std::string(buf)};
+}
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+void clear_last_error() { g_last_error.clear(); }
+
+void Sell::free_all() {
+  if (slice_off) (void)hipFree(slice_off);
+  if (val) (void)hipFree(val);
+  if (col) (void)hipFree(col);
+  slice_off = nullptr;
+  val = nullptr;
+  col = nullptr;
+  nrows = nslices = stored = 0;
+}
+
+void Csr::free_all() {
+  if (rowptr) (void)hipFree(rowptr);
+  if (col) (void)hipFree(col);
+  if (val) (void)hipFree(val);
+  rowptr = nullptr;
+  col = nullptr;
+  val = nullptr;
+  nrows = nnz = 0;
+}
+
+void free_workspace(wdb_theta* th) {
+  float* fs[] = {th->ws_x0, th->ws_r, th->ws_y, th->ws_img, th->ws_img2, th->pinv};
+  for (float* p : fs)
+    if (p) (void)hipFree(p);
+  double* ds[] = {th->ws_r64, th->ws_v64, th->ws_partial, th->ws_scalar, th->p64};
+  for (double* p : ds)
+    if (p) (void)hipFree(p);
+  if (th->host_scalar) (void)hipHostFree(th->host_scalar);
+  if (th->ws_k) (void)hipFree(th->ws_k);
+  if (th->ws_rho) (void)hipFree(th->ws_rho);
+  if (th->capture_stream) (void)hipStreamDestroy(th->capture_stream);
+  th->ws_k = nullptr;
+  th->ws_rho = nullptr;
+  th->capture_stream = nullptr;
+  th->ws_x0 = th->ws_r = th->ws_y = th->ws_img = th->ws_img2 = th->pinv = nullptr;
+  th->ws_r64 = th->ws_v64 = th->ws_partial = th->ws_scalar = th->p64 = nullptr;
+  th->host_scalar = nullptr;
+}
+
+}  // namespace wdb
+
+extern "C" {
+
+const char* wdb_last_error(void) { return wdb::g_last_error.c_str(); }
+
+const char* wdb_version(void) { return "wdb 0.1 (gfx950)"; }
+
+wdb_status wdb_theta_info(const wdb_theta* th, wdb_theta_desc* out) {
+  WDB_API_BEGIN
+  WDB_REQUIRE(th && out, WDB_ERR_ARG, "null handle or output");
+  std::memset(out, 0, sizeof(*out));
+  out->n = th->n;
+  out->levels = th->levels;
+  out->wavelet = th->wavelet;
+  out->has_lipschitz = th->has_L ? 1 : 0;
+  out->nnz = th->nnz;
+  out->stored = th->A.stored;
+  out->lipschitz = th->L;
+  out->threshold = th->threshold;
+  out->lipschitz_p = th->Lp;
+  out->precond = th->precond;
+  WDB_API_END
+}
+
+wdb_status wdb_theta_export(const wdb_theta* th, int64_t* rowptr, int32_t* col, double* val) {
+  WDB_API_BEGIN
+  WDB_REQUIRE(th, WDB_ERR_ARG, "null handle");
+  WDB_HIP(hipSetDevice(th->device));
+  WDB_HIP(hipDeviceSynchronize());
+  if (rowptr)
+    WDB_HIP(hipMemcpy(rowptr, th->csr.rowptr, (th->N + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+  if (col && th->nnz)
+    WDB_HIP(hipMemcpy(col, th->csr.col, th->nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (val && th->nnz)
+    WDB_HIP(hipMemcpy(val, th->csr.val, th->nnz * sizeof(double), hipMemcpyDeviceToHost));
+  WDB_API_END
+}
+
+void wdb_theta_free(wdb_theta* th) {
+  if (!th) return;
+  (void)hipSetDevice(th->device);
+  (void)hipDeviceSynchronize();
+  th->csr.free_all();
+  th->A.free_all();
+  th->At.free_all();
+  wdb::free_workspace(th);
+  delete th;
+}
+
+}  // extern "C"

@@ -1,0 +1,190 @@
+// Internal declarations shared by the wdb library sources (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/wdb.h"
+
+namespace wdb {
+
+// ---------------------------------------------------------------------------
+// Errors: internal code throws wdb::Error; every extern "C" entry point
+// catches it, records the message for wdb_last_error() and returns the code.
+// ---------------------------------------------------------------------------
+struct Error {
+  wdb_status code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(wdb_status code, const char* fmt, ...);
+void set_last_error(const std::string& msg);
+void clear_last_error();
+
+#define WDB_HIP(call)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      ::wdb::fail(e_ == hipErrorOutOfMemory ? WDB_ERR_OOM : WDB_ERR_HIP, "%s: %s (%s:%d)", \
+                  #call, hipGetErrorString(e_), __FILE__, __LINE__);                    \
+  } while (0)
+
+#define WDB_REQUIRE(cond, code, ...) \
+  do {                               \
+    if (!(cond)) ::wdb::fail(code, __VA_ARGS__); \
+  } while (0)
+
+#define WDB_API_BEGIN try { ::wdb::clear_last_error();
+#define WDB_API_END                                        \
+  }                                                        \
+  catch (const ::wdb::Error& e_) {                         \
+    ::wdb::set_last_error(e_.msg);                         \
+    return e_.code;                                        \
+  }                                                        \
+  catch (const std::bad_alloc&) {                          \
+    ::wdb::set_last_error("host allocation failed");       \
+    return WDB_ERR_OOM;                                    \
+  }                                                        \
+  catch (...) {                                            \
+    ::wdb::set_last_error("unexpected internal exception"); \
+    return WDB_ERR_HIP;                                    \
+  }                                                        \
+  return WDB_OK;
+
+// Device allocation owned by RAII (frees on scope exit unless released).
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t count) { alloc(count); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    reset();
+    p = o.p; n = o.n; o.p = nullptr; o.n = 0;
+    return *this;
+  }
+  ~DevBuf() { reset(); }
+  void alloc(size_t count) {
+    reset();
+    n = count;
+    if (count) WDB_HIP(hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T)));
+  }
+  void reset() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  T* release() { T* q = p; p = nullptr; n = 0; return q; }
+  size_t bytes() const { return n * sizeof(T); }
+};
+
+// ---------------------------------------------------------------------------
+// Filters (host, float64).
+// ---------------------------------------------------------------------------
+struct Filter {
+  std::vector<double> h;  // low-pass analysis taps
+  std::vector<double> g;  // high-pass g[m] = (-1)^m h[L-1-m]
+};
+Filter make_filter(int wavelet);  // throws WDB_ERR_ARG for unknown wavelets
+
+// Validate n (power of two >= 2) and levels against the filter length.
+void check_geometry(int32_t n, int32_t levels, int flen);
+
+// Canonical coefficient layout: subband k has (level, e_row, e_col, offset, side).
+struct Subband {
+  int level, erow, ecol;
+  int64_t offset;
+  int side;
+};
+std::vector<Subband> layout(int32_t n, int32_t levels);
+
+// ---------------------------------------------------------------------------
+// Sliced-ELL storage of one sparse N x N matrix (rows = output index).
+// Rows are grouped in slices of 64 (one wavefront, one row per lane).  Slice
+// s holds width w_s (a multiple of 4) entries per row, laid out as
+// [w_s/4][64 lanes][4], so each lane reads one 16-byte vector of values and
+// one of column indices per step and a wavefront's step is 1 KiB contiguous.
+// Padding slots have value 0 and repeat a valid column of the same row.
+// ---------------------------------------------------------------------------
+constexpr int kSlice = 64;
+
+struct Sell {
+  int64_t nrows = 0, nslices = 0, stored = 0;
+  int64_t* slice_off = nullptr;  // device, nslices + 1 (element offsets)
+  float* val = nullptr;          // device, stored
+  int32_t* col = nullptr;        // device, stored
+  void free_all();
+};
+
+// Device CSR (sorted columns) of one matrix.
+struct Csr {
+  int64_t nrows = 0, nnz = 0;
+  int64_t* rowptr = nullptr;  // device, nrows + 1
+  int32_t* col = nullptr;     // device, nnz
+  double* val = nullptr;      // device, nnz
+  void free_all();
+};
+
+// Build a SELL copy of a device CSR (float64 values rounded to float32).
+void csr_to_sell(const Csr& a, Sell* out, hipStream_t s);
+// Transpose a device CSR (sorted output).
+void csr_transpose(const Csr& a, Csr* out, hipStream_t s);
+// Sort device COO triples by (row, col) into a CSR; consumes nothing.
+void coo_to_csr(int64_t nrows, int64_t nnz, const int32_t* row, const int32_t* col,
+                const double* val, Csr* out, hipStream_t s);
+
+}  // namespace wdb
+
+// Operator handle.
+struct wdb_theta {
+  int device = 0;
+  int32_t n = 0, levels = 0, wavelet = 0;
+  int64_t N = 0, nnz = 0;
+  double threshold = 0.0;
+  wdb::Csr csr;        // Theta_K, float64 values (export)
+  wdb::Sell A;         // Theta_K   (rows = output coefficient)
+  wdb::Sell At;        // Theta_K^T (rows = input coefficient)
+  bool has_L = false;
+  double L = 0.0;
+  int precond = 0;
+  double Lp = 0.0;
+  double* p64 = nullptr;    // device, N: diagonal P
+  float* pinv = nullptr;    // device, N: 1/P as float32
+  // Solver workspace (allocated on first solve).
+  float* ws_x0 = nullptr;
+  float* ws_r = nullptr;
+  float* ws_y = nullptr;
+  double* ws_r64 = nullptr;
+  double* ws_v64 = nullptr;
+  double* ws_partial = nullptr;  // per-block partial reductions (4 per block)
+  double* ws_scalar = nullptr;   // device scalars
+  double* host_scalar = nullptr; // pinned host mirror
+  float* ws_img = nullptr;       // n*n scratch for transforms
+  float* ws_img2 = nullptr;
+  int* ws_k = nullptr;           // device iteration counter
+  double* ws_rho = nullptr;      // power-iteration history (64 entries)
+  int64_t ws_nblocks = 0;
+  hipStream_t capture_stream = nullptr;
+};
+
+namespace wdb {
+void ensure_workspace(wdb_theta* th);
+void free_workspace(wdb_theta* th);
+void finish_theta(wdb_theta* th, hipStream_t s);   // builds A/At from csr
+// Power iteration on D^-1/2 A^T A D^-1/2 (d = nullptr: identity), float64.
+double power_iteration(wdb_theta* th, const double* start_host, const double* dinv_sqrt,
+                       double tol, int max_iters, int* iters_out, hipStream_t s);
+// Forward/inverse float32 transform on device (scratch of n*n/4 * 2 floats).
+void dwt_forward(int n, int levels, const Filter& f, const float* in, float* out,
+                 float* scratch_a, float* scratch_b, hipStream_t s);
+void dwt_inverse(int n, int levels, const Filter& f, const float* in, float* out,
+                 float* scratch_a, float* scratch_b, hipStream_t s);
+}  // namespace wdb

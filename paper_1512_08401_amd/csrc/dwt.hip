@@ -1,0 +1,171 @@
+// Periodic separable 2D orthogonal wavelet transform on the GPU (Sec. 2:
+// tensor-product wavelets at one scale, circular boundaries), float32.
+//
+// One launch per level.  Forward: every thread owns one output position
+// (i, j) of the four subbands of the level and evaluates
+//   c_e[i][j] = sum_{m, m'} f_erow[m] f_ecol[m'] A[(2i+m) mod M][(2j+m') mod M]
+// with f_0 = h (low-pass) and f_1 = g (high-pass), reading the L x L input
+// footprint once for all four subbands (the footprints of neighbouring
+// threads overlap and are served by the L1/L2 caches).  Inverse: every thread
+// owns one output pixel and gathers the (L/2)^2 coefficients of each subband
+// whose footprint covers it (the transpose of the forward map).
+#include "common.hpp"
+
+namespace wdb {
+namespace {
+
+struct Taps {
+  float h[8];
+  float g[8];
+  int L;
+};
+
+Taps to_taps(const Filter& f) {
+  Taps t{};
+  t.L = static_cast<int>(f.h.size());
+  for (int i = 0; i < t.L; ++i) {
+    t.h[i] = static_cast<float>(f.h[i]);
+    t.g[i] = static_cast<float>(f.g[i]);
+  }
+  return t;
+}
+
+__global__ __launch_bounds__(256) void k_dwt_fwd_level(const float* __restrict__ A, int M,
+                                                       float* __restrict__ LL, float* __restrict__ d01,
+                                                       float* __restrict__ d10, float* __restrict__ d11,
+                                                       Taps t) {
+  const int Mh = M >> 1;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j >= Mh) return;
+  float a00 = 0.f, a01 = 0.f, a10 = 0.f, a11 = 0.f;
+  for (int m = 0; m < t.L; ++m) {
+    const float* row = A + static_cast<size_t>((2 * i + m) & (M - 1)) * M;
+    float lo = 0.f, hi = 0.f;
+    for (int m2 = 0; m2 < t.L; ++m2) {
+      const float v = row[(2 * j + m2) & (M - 1)];
+      lo = fmaf(t.h[m2], v, lo);
+      hi = fmaf(t.g[m2], v, hi);
+    }
+    a00 = fmaf(t.h[m], lo, a00);
+    a01 = fmaf(t.h[m], hi, a01);
+    a10 = fmaf(t.g[m], lo, a10);
+    a11 = fmaf(t.g[m], hi, a11);
+  }
+  const size_t o = static_cast<size_t>(i) * Mh + j;
+  LL[o] = a00;
+  d01[o] = a01;
+  d10[o] = a10;
+  d11[o] = a11;
+}
+
+__global__ __launch_bounds__(256) void k_dwt_inv_level(const float* __restrict__ LL,
+                                                       const float* __restrict__ d01,
+                                                       const float* __restrict__ d10,
+                                                       const float* __restrict__ d11, int Mh,
+                                                       float* __restrict__ out, Taps t) {
+  const int M = Mh << 1;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (q >= M) return;
+  float acc = 0.f;
+  for (int m = p & 1; m < t.L; m += 2) {
+    const int i = ((p - m) >> 1) & (Mh - 1);
+    const float hr = t.h[m], gr = t.g[m];
+    for (int m2 = q & 1; m2 < t.L; m2 += 2) {
+      const int jj = ((q - m2) >> 1) & (Mh - 1);
+      const size_t idx = static_cast<size_t>(i) * Mh + jj;
+      acc = fmaf(hr * t.h[m2], LL[idx], acc);
+      acc = fmaf(hr * t.g[m2], d01[idx], acc);
+      acc = fmaf(gr * t.h[m2], d10[idx], acc);
+      acc = fmaf(gr * t.g[m2], d11[idx], acc);
+    }
+  }
+  out[static_cast<size_t>(p) * M + q] = acc;
+}
+
+dim3 grid_for(int cols, int rows, int block) { return dim3((cols + block - 1) / block, rows); }
+
+}  // namespace
+
+// Detail subband offsets of level `lev` in the canonical layout.
+static void level_offsets(int n, int levels, int lev, int64_t off[3]) {
+  for (const Subband& sb : layout(n, levels))
+    if (sb.level == lev && !(sb.erow == 0 && sb.ecol == 0)) {
+      const int k = sb.erow * 2 + sb.ecol - 1;  // (0,1)->0, (1,0)->1, (1,1)->2
+      off[k] = sb.offset;
+    }
+}
+
+void dwt_forward(int n, int levels, const Filter& f, const float* in, float* out, float* scratch_a,
+                 float* scratch_b, hipStream_t s) {
+  const Taps t = to_taps(f);
+  const float* src = in;
+  float* bufs[2] = {scratch_a, scratch_b};
+  for (int lev = 1; lev <= levels; ++lev) {
+    const int M = n >> (lev - 1);
+    const int Mh = M >> 1;
+    int64_t off[3];
+    level_offsets(n, levels, lev, off);
+    float* ll = (lev == levels) ? out : bufs[lev & 1];
+    const int block = Mh < 256 ? Mh : 256;
+    hipLaunchKernelGGL(k_dwt_fwd_level, grid_for(Mh, Mh, block), dim3(block), 0, s, src, M, ll,
+                       out + off[0], out + off[1], out + off[2], t);
+    WDB_HIP(hipGetLastError());
+    src = ll;
+  }
+}
+
+void dwt_inverse(int n, int levels, const Filter& f, const float* in, float* out, float* scratch_a,
+                 float* scratch_b, hipStream_t s) {
+  const Taps t = to_taps(f);
+  const float* ll = in;  // A_J sits at offset 0
+  float* bufs[2] = {scratch_a, scratch_b};
+  for (int lev = levels; lev >= 1; --lev) {
+    const int Mh = n >> lev;
+    const int M = Mh << 1;
+    int64_t off[3];
+    level_offsets(n, levels, lev, off);
+    float* dst = (lev == 1) ? out : bufs[lev & 1];
+    const int block = M < 256 ? M : 256;
+    hipLaunchKernelGGL(k_dwt_inv_level, grid_for(M, M, block), dim3(block), 0, s, ll, in + off[0],
+                       in + off[1], in + off[2], Mh, dst, t);
+    WDB_HIP(hipGetLastError());
+    ll = dst;
+  }
+}
+
+}  // namespace wdb
+
+extern "C" wdb_status wdb_dwt(int32_t n, int32_t wavelet, int32_t levels, const float* in, float* out,
+                              int32_t inverse, void* stream) {
+  WDB_API_BEGIN
+  WDB_REQUIRE(in && out, WDB_ERR_ARG, "null buffer");
+  WDB_REQUIRE(in != out, WDB_ERR_ARG, "in and out must not alias");
+  wdb::Filter f = wdb::make_filter(wavelet);
+  wdb::check_geometry(n, levels, static_cast<int>(f.h.size()));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t q = static_cast<size_t>(n / 2) * (n / 2);
+  wdb::DevBuf<float> scratch(2 * q);
+  if (inverse)
+    wdb::dwt_inverse(n, levels, f, in, out, scratch.p, scratch.p + q, s);
+  else
+    wdb::dwt_forward(n, levels, f, in, out, scratch.p, scratch.p + q, s);
+  WDB_HIP(hipStreamSynchronize(s));
+  WDB_API_END
+}
+
+extern "C" wdb_status wdb_synthesize(const wdb_theta* th, const float* x, float* u_hat, void* stream) {
+  WDB_API_BEGIN
+  WDB_REQUIRE(th && x && u_hat, WDB_ERR_ARG, "null argument");
+  WDB_REQUIRE(static_cast<const void*>(x) != static_cast<const void*>(u_hat), WDB_ERR_ARG,
+              "x and u_hat must not alias");
+  WDB_HIP(hipSetDevice(th->device));
+  wdb_theta* t = const_cast<wdb_theta*>(th);
+  wdb::ensure_workspace(t);
+  wdb::Filter f = wdb::make_filter(th->wavelet);
+  const size_t q = static_cast<size_t>(th->n / 2) * (th->n / 2);
+  wdb::dwt_inverse(th->n, th->levels, f, x, u_hat, t->ws_img, t->ws_img + q,
+                   static_cast<hipStream_t>(stream));
+  WDB_API_END
+}

@@ -1,0 +1,606 @@
+// Accelerated proximal gradient (Alg. 1; Alg. 2 with a diagonal P) on the
+// wavelet-domain problem of Sec. 1.3, plus its float64 companions: the power
+// iteration for the step 1/||Theta_K||^2 and the objective / duality-gap test.
+//
+// One FISTA iteration is two kernels over the sliced-ELL copies:
+//   k_res  : r = Theta_K y - x0                      (first half of the gradient)
+//   k_prox : g = Theta_K^T r; z = y - tau g / P;
+//            x_k = S_{tau lambda / P}(z);
+//            y = x_k + (k-1)/(k+2) (x_k - x_{k-1})   (rest of Alg. 1, fused)
+// Each lane of a wavefront owns one row of a 64-row slice, streams its 16-byte
+// value and index vectors (1 KiB per wavefront step, contiguous), gathers the
+// vector entries through the caches and accumulates in float32 in storage
+// order, so results are bitwise reproducible (no atomics on values).
+#include <cmath>
+#include <cstdlib>
+
+#include "common.hpp"
+
+namespace wdb {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kSlicesPerBlock = kBlock / kSlice;
+constexpr int kRhoChunk = 64;
+
+inline dim3 slice_grid(int64_t nslices) {
+  return dim3(static_cast<unsigned>((nslices + kSlicesPerBlock - 1) / kSlicesPerBlock));
+}
+inline dim3 vec_grid(int64_t n) { return dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock)); }
+
+struct SellView {
+  const int64_t* __restrict__ soff;
+  const float4* __restrict__ val;
+  const int4* __restrict__ col;
+  int64_t nslices, nrows;
+};
+
+SellView view(const Sell& m) {
+  return SellView{m.slice_off, reinterpret_cast<const float4*>(m.val), reinterpret_cast<const int4*>(m.col),
+                  m.nslices, m.nrows};
+}
+
+// Row sum of one lane's row in float32, storage order.
+template <typename T>
+__device__ __forceinline__ float row_dot_f32(const SellView& A, int64_t sl, int lane, const T* __restrict__ x) {
+  const int64_t beg = A.soff[sl] >> 2, end = A.soff[sl + 1] >> 2;
+  float acc = 0.f;
+#pragma unroll 2
+  for (int64_t j = beg + lane; j < end; j += kSlice) {
+    const float4 v = A.val[j];
+    const int4 c = A.col[j];
+    acc = fmaf(v.x, x[c.x], acc);
+    acc = fmaf(v.y, x[c.y], acc);
+    acc = fmaf(v.z, x[c.z], acc);
+    acc = fmaf(v.w, x[c.w], acc);
+  }
+  return acc;
+}
+
+// Row sum in float64 (values promoted), storage order.
+template <typename T>
+__device__ __forceinline__ double row_dot_f64(const SellView& A, int64_t sl, int lane, const T* __restrict__ x) {
+  const int64_t beg = A.soff[sl] >> 2, end = A.soff[sl + 1] >> 2;
+  double acc = 0.0;
+  for (int64_t j = beg + lane; j < end; j += kSlice) {
+    const float4 v = A.val[j];
+    const int4 c = A.col[j];
+    acc = fma(static_cast<double>(v.x), static_cast<double>(x[c.x]), acc);
+    acc = fma(static_cast<double>(v.y), static_cast<double>(x[c.y]), acc);
+    acc = fma(static_cast<double>(v.z), static_cast<double>(x[c.z]), acc);
+    acc = fma(static_cast<double>(v.w), static_cast<double>(x[c.w]), acc);
+  }
+  return acc;
+}
+
+// Deterministic block reduction of NV values; bit k of MAXMASK selects max
+// instead of sum.  Writes partial[k * nblocks + blockIdx.x].
+template <int NV, unsigned MAXMASK>
+__device__ __forceinline__ void block_partials(double (&v)[NV], double* __restrict__ partial, int64_t nblocks) {
+  __shared__ double sh[kSlicesPerBlock][NV];
+  const int lane = threadIdx.x & (kSlice - 1), wid = threadIdx.x / kSlice;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double x = v[k];
+    for (int off = kSlice / 2; off > 0; off >>= 1) {
+      const double y = __shfl_xor(x, off);
+      x = ((MAXMASK >> k) & 1u) ? fmax(x, y) : x + y;
+    }
+    if (lane == 0) sh[wid][k] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double acc = sh[0][k];
+      for (int w = 1; w < kSlicesPerBlock; ++w) acc = ((MAXMASK >> k) & 1u) ? fmax(acc, sh[w][k]) : acc + sh[w][k];
+      partial[k * nblocks + blockIdx.x] = acc;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FISTA kernels (float32).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_res(SellView A, const float* __restrict__ y, const float* __restrict__ b,
+                                                float* __restrict__ r, int* __restrict__ kdev) {
+  if (kdev && blockIdx.x == 0 && threadIdx.x == 0) *kdev += 1;
+  const int lane = threadIdx.x & (kSlice - 1);
+  const int64_t sl = static_cast<int64_t>(blockIdx.x) * kSlicesPerBlock + threadIdx.x / kSlice;
+  if (sl >= A.nslices) return;
+  const float acc = row_dot_f32(A, sl, lane, y);
+  const int64_t row = sl * kSlice + lane;
+  if (row < A.nrows) r[row] = b ? acc - b[row] : acc;
+}
+
+// beta from the device counter (kdev) or, if kdev is null, from `beta`.
+template <bool PRE>
+__global__ __launch_bounds__(kBlock) void k_prox(SellView At, const float* __restrict__ r, float* __restrict__ x,
+                                                 float* __restrict__ y, float tau, float thr, float beta,
+                                                 const int* __restrict__ kdev, const float* __restrict__ pinv) {
+  const int lane = threadIdx.x & (kSlice - 1);
+  const int64_t sl = static_cast<int64_t>(blockIdx.x) * kSlicesPerBlock + threadIdx.x / kSlice;
+  if (sl >= At.nslices) return;
+  const float g = row_dot_f32(At, sl, lane, r);
+  const int64_t row = sl * kSlice + lane;
+  if (row >= At.nrows) return;
+  if (kdev) {
+    const int k = *kdev;
+    beta = static_cast<float>((static_cast<double>(k) - 1.0) / (static_cast<double>(k) + 2.0));
+  }
+  const float pi = PRE ? pinv[row] : 1.0f;
+  const float z = y[row] - (tau * pi) * g;
+  const float t = thr * pi;
+  const float xn = copysignf(fmaxf(fabsf(z) - t, 0.0f), z);
+  const float xo = x[row];
+  x[row] = xn;
+  y[row] = xn + beta * (xn - xo);
+}
+
+// ---------------------------------------------------------------------------
+// Float64 objective and duality gap.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_obj_fwd(SellView A, const float* __restrict__ x, const float* __restrict__ b,
+                                                    double* __restrict__ r64, double* __restrict__ partial,
+                                                    int64_t nblocks) {
+  const int lane = threadIdx.x & (kSlice - 1);
+  const int64_t sl = static_cast<int64_t>(blockIdx.x) * kSlicesPerBlock + threadIdx.x / kSlice;
+  double v[3] = {0.0, 0.0, 0.0};
+  if (sl < A.nslices) {
+    const double acc = row_dot_f64(A, sl, lane, x);
+    const int64_t row = sl * kSlice + lane;
+    if (row < A.nrows) {
+      const double bb = static_cast<double>(b[row]);
+      const double rr = acc - bb;
+      r64[row] = rr;
+      v[0] = rr * rr;
+      v[1] = rr * bb;
+      v[2] = fabs(static_cast<double>(x[row]));
+    }
+  }
+  block_partials<3, 0u>(v, partial, nblocks);
+}
+
+__global__ __launch_bounds__(kBlock) void k_obj_bwd(SellView At, const double* __restrict__ r64,
+                                                    double* __restrict__ partial, int64_t nblocks) {
+  const int lane = threadIdx.x & (kSlice - 1);
+  const int64_t sl = static_cast<int64_t>(blockIdx.x) * kSlicesPerBlock + threadIdx.x / kSlice;
+  double v[1] = {0.0};
+  if (sl < At.nslices) {
+    const int64_t row = sl * kSlice + lane;
+    const double g = row_dot_f64(At, sl, lane, r64);
+    if (row < At.nrows) v[0] = fabs(g);
+  }
+  block_partials<1, 1u>(v, partial, nblocks);
+}
+
+// Single block: out[k] = reduction of partial[k * nblocks ...] in a fixed order.
+__global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ partial, int64_t nblocks, int nv,
+                                                   unsigned maxmask, double* __restrict__ out) {
+  __shared__ double sh[kBlock];
+  for (int k = 0; k < nv; ++k) {
+    const bool mx = (maxmask >> k) & 1u;
+    double acc = mx ? 0.0 : 0.0;
+    for (int64_t i = threadIdx.x; i < nblocks; i += kBlock) {
+      const double p = partial[k * nblocks + i];
+      acc = mx ? fmax(acc, p) : acc + p;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w) sh[threadIdx.x] = mx ? fmax(sh[threadIdx.x], sh[threadIdx.x + w]) : sh[threadIdx.x] + sh[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[k] = sh[0];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Power iteration (float64): w = A vd; u = d .* (A^T w); vd = d .* u / ||u||.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_pi_fwd(SellView A, const double* __restrict__ vd, double* __restrict__ w,
+                                                   double* __restrict__ partial, int64_t nblocks) {
+  const int lane = threadIdx.x & (kSlice - 1);
+  const int64_t sl = static_cast<int64_t>(blockIdx.x) * kSlicesPerBlock + threadIdx.x / kSlice;
+  double v[1] = {0.0};
+  if (sl < A.nslices) {
+    const int64_t row = sl * kSlice + lane;
+    const double acc = row_dot_f64(A, sl, lane, vd);
+    if (row < A.nrows) {
+      w[row] = acc;
+      v[0] = acc * acc;
+    }
+  }
+  block_partials<1, 0u>(v, partial, nblocks);
+}
+
+__global__ __launch_bounds__(kBlock) void k_pi_bwd(SellView At, const double* __restrict__ w,
+                                                   const double* __restrict__ d, double* __restrict__ u,
+                                                   double* __restrict__ partial, int64_t nblocks) {
+  const int lane = threadIdx.x & (kSlice - 1);
+  const int64_t sl = static_cast<int64_t>(blockIdx.x) * kSlicesPerBlock + threadIdx.x / kSlice;
+  double v[1] = {0.0};
+  if (sl < At.nslices) {
+    const int64_t row = sl * kSlice + lane;
+    double acc = row_dot_f64(At, sl, lane, w);
+    if (row < At.nrows) {
+      if (d) acc *= d[row];
+      u[row] = acc;
+      v[0] = acc * acc;
+    }
+  }
+  block_partials<1, 0u>(v, partial, nblocks);
+}
+
+__global__ __launch_bounds__(kBlock) void k_pi_finish(const double* __restrict__ partial, int64_t nblocks,
+                                                      double* __restrict__ rho_hist, int slot,
+                                                      double* __restrict__ scal) {
+  __shared__ double sh[2][kBlock];
+  double a = 0.0, b = 0.0;
+  for (int64_t i = threadIdx.x; i < nblocks; i += kBlock) {
+    a += partial[i];
+    b += partial[nblocks + i];
+  }
+  sh[0][threadIdx.x] = a;
+  sh[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    rho_hist[slot] = sh[0][0];
+    scal[0] = sh[1][0] > 0.0 ? 1.0 / sqrt(sh[1][0]) : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pi_scale(const double* __restrict__ u, const double* __restrict__ d,
+                                                     const double* __restrict__ scal, double* __restrict__ vd,
+                                                     int64_t N) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= N) return;
+  const double v = u[i] * scal[0];
+  vd[i] = d ? v * d[i] : v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_mul(double* __restrict__ v, const double* __restrict__ d, int64_t N) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < N) v[i] *= d[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy_or_zero(const float* __restrict__ src, float* __restrict__ a,
+                                                         float* __restrict__ b, int64_t N) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= N) return;
+  const float v = src ? src[i] : 0.0f;
+  a[i] = v;
+  b[i] = v;
+}
+
+__global__ void k_set_int(int* p, int v) { *p = v; }
+
+uint64_t splitmix64(uint64_t& state) {
+  uint64_t z = (state += 0x9e3779b97f4a7c15ull);
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+}  // namespace
+
+void ensure_workspace(wdb_theta* th) {
+  if (th->ws_x0) return;
+  const int64_t N = th->N;
+  const int64_t nb = (th->A.nslices + kSlicesPerBlock - 1) / kSlicesPerBlock;
+  th->ws_nblocks = std::max<int64_t>(nb, 1);
+  try {
+    WDB_HIP(hipMalloc(reinterpret_cast<void**>(&th->ws_x0), N * sizeof(float)));
+    WDB_HIP(hipMalloc(reinterpret_cast<void**>(&th->ws_r), N * sizeof(float)));
+    WDB_HIP(hipMalloc(reinterpret_cast<void**>(&th->ws_y), N * sizeof(float)));
+    WDB_HIP(hipMalloc(reinterpret_cast<void**>(&th->ws_img), N * sizeof(float)));
+    WDB_HIP(hipMalloc(reinterpret_cast<void**>(&th->ws_img2), N * sizeof(float)));
+    WDB_HIP(hipMalloc(reinterpret_cast<void**>(&th->ws_r64), N * sizeof(double)));
+    WDB_HIP(hipMalloc(reinterpret_cast<void**>(&th->ws_v64), 3 * N * sizeof(double)));
+    WDB_HIP(hipMalloc(reinterpret_cast<void**>(&th->ws_partial), 4 * th->ws_nblocks * sizeof(double)));
+    WDB_HIP(hipMalloc(reinterpret_cast<void**>(&th->ws_scalar), 16 * sizeof(double)));
+    WDB_HIP(hipMalloc(reinterpret_cast<void**>(&th->ws_rho), kRhoChunk * sizeof(double)));
+    WDB_HIP(hipMalloc(reinterpret_cast<void**>(&th->ws_k), sizeof(int)));
+    WDB_HIP(hipHostMalloc(reinterpret_cast<void**>(&th->host_scalar), 16 * sizeof(double), hipHostMallocDefault));
+  } catch (...) {
+    free_workspace(th);
+    throw;
+  }
+}
+
+double power_iteration(wdb_theta* th, const double* start_host, const double* dinv_sqrt, double tol, int max_iters,
+                       int* iters_out, hipStream_t s) {
+  ensure_workspace(th);
+  const int64_t N = th->N;
+  WDB_REQUIRE(max_iters >= 1, WDB_ERR_ARG, "max_iters must be >= 1");
+  WDB_REQUIRE(tol >= 0 && std::isfinite(tol), WDB_ERR_ARG, "tol must be finite and >= 0");
+  std::vector<double> v(N);
+  if (start_host) {
+    for (int64_t i = 0; i < N; ++i) {
+      WDB_REQUIRE(std::isfinite(start_host[i]), WDB_ERR_NONFINITE, "non-finite start vector");
+      v[i] = start_host[i];
+    }
+  } else {
+    uint64_t st = 0x5eedull;
+    for (int64_t i = 0; i < N; ++i) v[i] = static_cast<double>(splitmix64(st) >> 11) * 0x1.0p-52 - 1.0;
+  }
+  double nrm = 0.0;
+  for (double x : v) nrm += x * x;
+  nrm = std::sqrt(nrm);
+  WDB_REQUIRE(nrm > 0.0, WDB_ERR_ARG, "power-iteration start vector is zero");
+  for (double& x : v) x /= nrm;
+  double* vd = th->ws_v64;
+  double* w = vd + N;
+  double* u = w + N;
+  WDB_HIP(hipMemcpyAsync(vd, v.data(), N * sizeof(double), hipMemcpyHostToDevice, s));
+  if (dinv_sqrt) hipLaunchKernelGGL(k_mul, vec_grid(N), dim3(kBlock), 0, s, vd, dinv_sqrt, N);
+  const SellView A = view(th->A), At = view(th->At);
+  const int64_t nb = th->ws_nblocks;
+  double* part = th->ws_partial;
+  std::vector<double> hist(kRhoChunk);
+  double prev = 0.0, rho = 0.0;
+  int k = 0;
+  while (k < max_iters) {
+    const int m = std::min(kRhoChunk, max_iters - k);
+    for (int j = 0; j < m; ++j) {
+      hipLaunchKernelGGL(k_pi_fwd, slice_grid(A.nslices), dim3(kBlock), 0, s, A, vd, w, part, nb);
+      hipLaunchKernelGGL(k_pi_bwd, slice_grid(At.nslices), dim3(kBlock), 0, s, At, w, dinv_sqrt, u, part + nb, nb);
+      hipLaunchKernelGGL(k_pi_finish, dim3(1), dim3(kBlock), 0, s, part, nb, th->ws_rho, j, th->ws_scalar);
+      hipLaunchKernelGGL(k_pi_scale, vec_grid(N), dim3(kBlock), 0, s, u, dinv_sqrt, th->ws_scalar, vd, N);
+    }
+    WDB_HIP(hipGetLastError());
+    WDB_HIP(hipMemcpyAsync(hist.data(), th->ws_rho, m * sizeof(double), hipMemcpyDeviceToHost, s));
+    WDB_HIP(hipStreamSynchronize(s));
+    for (int j = 0; j < m; ++j) {
+      const int kk = k + j + 1;
+      rho = hist[j];
+      WDB_REQUIRE(std::isfinite(rho), WDB_ERR_DIVERGED, "power iteration produced a non-finite value");
+      if (kk >= 2 && std::fabs(rho - prev) <= tol * rho) {
+        if (iters_out) *iters_out = kk;
+        return rho;
+      }
+      prev = rho;
+    }
+    k += m;
+  }
+  if (iters_out) *iters_out = max_iters;
+  return rho;
+}
+
+namespace {
+
+struct Check {
+  double E, rel_gap;
+};
+
+Check objective_check(wdb_theta* th, const float* x, const float* x0, double lambda, hipStream_t s) {
+  const SellView A = view(th->A), At = view(th->At);
+  const int64_t nb = th->ws_nblocks;
+  double* part = th->ws_partial;
+  hipLaunchKernelGGL(k_obj_fwd, slice_grid(A.nslices), dim3(kBlock), 0, s, A, x, x0, th->ws_r64, part, nb);
+  hipLaunchKernelGGL(k_obj_bwd, slice_grid(At.nslices), dim3(kBlock), 0, s, At, th->ws_r64, part + 3 * nb, nb);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, part, nb, 4, 0x8u, th->ws_scalar);
+  WDB_HIP(hipGetLastError());
+  WDB_HIP(hipMemcpyAsync(th->host_scalar, th->ws_scalar, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+  WDB_HIP(hipStreamSynchronize(s));
+  const double rr = th->host_scalar[0], rb = th->host_scalar[1], l1 = th->host_scalar[2], gmax = th->host_scalar[3];
+  const double E = 0.5 * rr + lambda * l1;
+  const double sc = gmax <= lambda ? 1.0 : lambda / gmax;
+  const double D = -0.5 * sc * sc * rr - sc * rb;
+  const double gap = E - D;
+  return Check{E, E > 0 ? gap / E : 0.0};
+}
+
+void launch_iteration(wdb_theta* th, float* x, bool pre, float tau, float thr, hipStream_t s) {
+  const SellView A = view(th->A), At = view(th->At);
+  hipLaunchKernelGGL(k_res, slice_grid(A.nslices), dim3(kBlock), 0, s, A, th->ws_y, th->ws_x0, th->ws_r, th->ws_k);
+  if (pre)
+    hipLaunchKernelGGL(k_prox<true>, slice_grid(At.nslices), dim3(kBlock), 0, s, At, th->ws_r, x, th->ws_y, tau,
+                       thr, 0.0f, th->ws_k, th->pinv);
+  else
+    hipLaunchKernelGGL(k_prox<false>, slice_grid(At.nslices), dim3(kBlock), 0, s, At, th->ws_r, x, th->ws_y, tau,
+                       thr, 0.0f, th->ws_k, nullptr);
+}
+
+void ensure_lipschitz(wdb_theta* th, hipStream_t s) {
+  if (th->has_L) return;
+  int it = 0;
+  th->L = power_iteration(th, nullptr, nullptr, 1e-12, 20000, &it, s);
+  th->has_L = true;
+}
+
+wdb_status solve_impl(wdb_theta* th, const float* x0_src, bool from_image, float lambda, const wdb_solve_opts* opts,
+                      float* x_out, wdb_solve_info* info) {
+  WDB_REQUIRE(th && x0_src && opts && x_out, WDB_ERR_ARG, "null argument");
+  WDB_REQUIRE(std::isfinite(lambda) && lambda >= 0.0f, WDB_ERR_NONFINITE, "lambda must be finite and >= 0");
+  WDB_REQUIRE(opts->max_iters >= 0, WDB_ERR_ARG, "max_iters must be >= 0");
+  WDB_REQUIRE(opts->check_every >= 0, WDB_ERR_ARG, "check_every must be >= 0");
+  WDB_REQUIRE(opts->k0 >= 0, WDB_ERR_ARG, "k0 must be >= 0");
+  const bool pre = opts->use_precond != 0;
+  WDB_REQUIRE(!pre || th->precond != 0, WDB_ERR_ARG, "no preconditioner set on this operator");
+  WDB_HIP(hipSetDevice(th->device));
+  hipStream_t s = static_cast<hipStream_t>(opts->stream);
+  ensure_workspace(th);
+  ensure_lipschitz(th, s);
+  const double Luse = pre ? th->Lp : th->L;
+  WDB_REQUIRE(Luse > 0.0 && std::isfinite(Luse), WDB_ERR_ARG, "operator has no positive Lipschitz constant");
+  const double tau = 1.0 / Luse;
+  const float tau_f = static_cast<float>(tau);
+  const float thr_f = static_cast<float>(tau * static_cast<double>(lambda));
+  const int64_t N = th->N;
+  if (from_image) {
+    const Filter f = make_filter(th->wavelet);
+    const size_t q = static_cast<size_t>(th->n / 2) * (th->n / 2);
+    dwt_forward(th->n, th->levels, f, x0_src, th->ws_x0, th->ws_img, th->ws_img + q, s);
+  } else {
+    WDB_HIP(hipMemcpyAsync(th->ws_x0, x0_src, N * sizeof(float), hipMemcpyDeviceToDevice, s));
+  }
+  hipLaunchKernelGGL(k_copy_or_zero, vec_grid(N), dim3(kBlock), 0, s, opts->x_init, x_out, th->ws_y, N);
+  const int k0 = opts->k0 > 0 ? opts->k0 : 1;
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, th->ws_k, k0 - 1);
+  WDB_HIP(hipGetLastError());
+
+  const int c = opts->check_every;
+  const int total = opts->max_iters;
+  int done = 0, checks = 0;
+  Check last{0.0, 0.0};
+  bool converged = false;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  auto cleanup = [&]() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  };
+  try {
+    const bool use_graph = opts->use_graph && c > 1;
+    if (use_graph && total >= c) {
+      if (!th->capture_stream) WDB_HIP(hipStreamCreateWithFlags(&th->capture_stream, hipStreamNonBlocking));
+      WDB_HIP(hipStreamBeginCapture(th->capture_stream, hipStreamCaptureModeThreadLocal));
+      for (int i = 0; i < c; ++i) launch_iteration(th, x_out, pre, tau_f, thr_f, th->capture_stream);
+      WDB_HIP(hipStreamEndCapture(th->capture_stream, &graph));
+      WDB_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    }
+    while (done < total) {
+      int step = total - done;
+      if (c > 0) step = std::min(step, c - (done % c));
+      if (exec && step == c) {
+        WDB_HIP(hipGraphLaunch(exec, s));
+      } else {
+        for (int i = 0; i < step; ++i) launch_iteration(th, x_out, pre, tau_f, thr_f, s);
+        WDB_HIP(hipGetLastError());
+      }
+      done += step;
+      const bool at_check = (c > 0 && done % c == 0) || done == total;
+      if (at_check) {
+        last = objective_check(th, x_out, th->ws_x0, lambda, s);
+        ++checks;
+        if (opts->trace && checks <= opts->trace_cap) {
+          opts->trace[3 * (checks - 1) + 0] = static_cast<double>(k0 - 1 + done);
+          opts->trace[3 * (checks - 1) + 1] = last.E;
+          opts->trace[3 * (checks - 1) + 2] = last.rel_gap;
+        }
+        WDB_REQUIRE(std::isfinite(last.E), WDB_ERR_DIVERGED, "objective became non-finite at iteration %d",
+                    k0 - 1 + done);
+        if (opts->tol_rel_gap > 0 && last.rel_gap <= opts->tol_rel_gap) {
+          converged = true;
+          break;
+        }
+      }
+    }
+    if (total == 0) {
+      last = objective_check(th, x_out, th->ws_x0, lambda, s);
+      ++checks;
+    }
+  } catch (...) {
+    cleanup();
+    throw;
+  }
+  cleanup();
+  if (info) {
+    info->iters = done;
+    info->checks = checks;
+    info->objective = last.E;
+    info->rel_gap = last.rel_gap;
+    info->lipschitz = Luse;
+    info->tau = tau;
+  }
+  if (opts->tol_rel_gap > 0 && !converged)
+    fail(WDB_ERR_NOT_CONVERGED, "relative gap %.3e above tolerance %.3e after %d iterations", last.rel_gap,
+         opts->tol_rel_gap, done);
+  return WDB_OK;
+}
+
+}  // namespace
+
+}  // namespace wdb
+
+extern "C" {
+
+wdb_status wdb_theta_lipschitz(wdb_theta* th, const double* start, double tol, int32_t max_iters, double* L_out,
+                               int32_t* iters_out) {
+  WDB_API_BEGIN
+  WDB_REQUIRE(th, WDB_ERR_ARG, "null handle");
+  WDB_HIP(hipSetDevice(th->device));
+  int it = 0;
+  const double L = wdb::power_iteration(th, start, nullptr, tol, max_iters, &it, nullptr);
+  th->L = L;
+  th->has_L = true;
+  if (L_out) *L_out = L;
+  if (iters_out) *iters_out = it;
+  WDB_API_END
+}
+
+wdb_status wdb_solve(wdb_theta* th, const float* u, float lambda, const wdb_solve_opts* opts, float* x_out,
+                     wdb_solve_info* info) {
+  WDB_API_BEGIN
+  return wdb::solve_impl(th, u, true, lambda, opts, x_out, info);
+  WDB_API_END
+}
+
+wdb_status wdb_solve_coeffs(wdb_theta* th, const float* x0, float lambda, const wdb_solve_opts* opts, float* x_out,
+                            wdb_solve_info* info) {
+  WDB_API_BEGIN
+  return wdb::solve_impl(th, x0, false, lambda, opts, x_out, info);
+  WDB_API_END
+}
+
+wdb_status wdb_objective(wdb_theta* th, const float* x, const float* x0, float lambda, void* stream, double* E_out,
+                         double* rel_gap_out) {
+  WDB_API_BEGIN
+  WDB_REQUIRE(th && x && x0, WDB_ERR_ARG, "null argument");
+  WDB_REQUIRE(std::isfinite(lambda) && lambda >= 0.0f, WDB_ERR_NONFINITE, "lambda must be finite and >= 0");
+  WDB_HIP(hipSetDevice(th->device));
+  wdb::ensure_workspace(th);
+  const auto c = wdb::objective_check(th, x, x0, lambda, static_cast<hipStream_t>(stream));
+  if (E_out) *E_out = c.E;
+  if (rel_gap_out) *rel_gap_out = c.rel_gap;
+  WDB_API_END
+}
+
+wdb_status wdb_theta_apply(wdb_theta* th, int32_t transpose, const float* x, const float* b, float* y,
+                           int32_t repeat, void* stream) {
+  WDB_API_BEGIN
+  WDB_REQUIRE(th && x && y, WDB_ERR_ARG, "null argument");
+  WDB_REQUIRE(x != y, WDB_ERR_ARG, "x and y must not alias");
+  WDB_REQUIRE(repeat >= 1, WDB_ERR_ARG, "repeat must be >= 1");
+  WDB_HIP(hipSetDevice(th->device));
+  const wdb::SellView M = wdb::view(transpose ? th->At : th->A);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (int i = 0; i < repeat; ++i)
+    hipLaunchKernelGGL(wdb::k_res, wdb::slice_grid(M.nslices), dim3(wdb::kBlock), 0, s, M, x, b, y,
+                       static_cast<int*>(nullptr));
+  WDB_HIP(hipGetLastError());
+  WDB_API_END
+}
+
+wdb_status wdb_prox_step(wdb_theta* th, const float* r, float* x, float* y, float tau, float lambda, float beta,
+                         int32_t use_precond, void* stream) {
+  WDB_API_BEGIN
+  WDB_REQUIRE(th && r && x && y, WDB_ERR_ARG, "null argument");
+  WDB_REQUIRE(!use_precond || th->pinv, WDB_ERR_ARG, "no preconditioner set on this operator");
+  WDB_HIP(hipSetDevice(th->device));
+  const wdb::SellView At = wdb::view(th->At);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const float thr = tau * lambda;
+  if (use_precond)
+    hipLaunchKernelGGL(wdb::k_prox<true>, wdb::slice_grid(At.nslices), dim3(wdb::kBlock), 0, s, At, r, x, y, tau,
+                       thr, beta, static_cast<const int*>(nullptr), th->pinv);
+  else
+    hipLaunchKernelGGL(wdb::k_prox<false>, wdb::slice_grid(At.nslices), dim3(wdb::kBlock), 0, s, At, r, x, y, tau,
+                       thr, beta, static_cast<const int*>(nullptr), static_cast<const float*>(nullptr));
+  WDB_HIP(hipGetLastError());
+  WDB_API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,321 @@
+"""Thin Python binding of the wdb C ABI (``include/wdb.h``).
+
+Argument marshalling only: every numerical step runs in libwdb's HIP
+kernels.  Device buffers are torch tensors on a ROCm device (float32,
+contiguous); the current torch stream is passed to the library.  If
+``libwdb.so`` is missing, importing this module raises ImportError: there is
+no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwdb.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1512_08401_amd.build`")
+
+_lib = C.CDLL(LIB_PATH)
+
+WAVELETS = {"haar": 0, "db4": 1}
+PRECOND = {"none": 0, "spai": 1, "spai_scale": 2, "jacobi": 3}
+
+WDB_OK = 0
+WDB_ERR_ARG, WDB_ERR_SIZE, WDB_ERR_LEVELS, WDB_ERR_NONFINITE = -1, -2, -3, -4
+WDB_ERR_OOM, WDB_ERR_HIP, WDB_ERR_DIVERGED, WDB_ERR_NOT_CONVERGED, WDB_ERR_FORMAT = -5, -6, -7, -8, -9
+
+
+class WdbError(RuntimeError):
+    def __init__(self, fn: str, code: int, msg: str):
+        super().__init__(f"{fn} failed with status {code}: {msg}")
+        self.code = code
+        self.msg = msg
+
+
+class PsfFieldC(C.Structure):
+    _fields_ = [("n", C.c_int32), ("sig_major", C.POINTER(C.c_double)),
+                ("sig_minor", C.POINTER(C.c_double)), ("angle", C.POINTER(C.c_double)),
+                ("trunc", C.c_double)]
+
+
+class ThetaDesc(C.Structure):
+    _fields_ = [("n", C.c_int32), ("levels", C.c_int32), ("wavelet", C.c_int32),
+                ("has_lipschitz", C.c_int32), ("nnz", C.c_int64), ("stored", C.c_int64),
+                ("lipschitz", C.c_double), ("threshold", C.c_double), ("lipschitz_p", C.c_double),
+                ("precond", C.c_int32), ("pad_", C.c_int32)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("max_iters", C.c_int32), ("check_every", C.c_int32), ("tol_rel_gap", C.c_double),
+                ("x_init", C.c_void_p), ("k0", C.c_int32), ("use_precond", C.c_int32),
+                ("stream", C.c_void_p), ("trace", C.POINTER(C.c_double)), ("trace_cap", C.c_int32),
+                ("use_graph", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("checks", C.c_int32), ("objective", C.c_double),
+                ("rel_gap", C.c_double), ("lipschitz", C.c_double), ("tau", C.c_double)]
+
+
+_vp, _i32, _i64, _f32, _f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_double
+_pd = C.POINTER(C.c_double)
+
+_SIGS = {
+    "wdb_build_theta": [C.POINTER(PsfFieldC), _i32, _i32, _i64, _vp, C.POINTER(_vp)],
+    "wdb_theta_import": [_i32, _i32, _i32, _i64, _vp, _vp, _vp, _vp, C.POINTER(_vp)],
+    "wdb_theta_export": [_vp, _vp, _vp, _vp],
+    "wdb_theta_info": [_vp, C.POINTER(ThetaDesc)],
+    "wdb_theta_lipschitz": [_vp, _vp, _f64, _i32, _pd, C.POINTER(_i32)],
+    "wdb_set_precond": [_vp, _i32, _f64, _vp, _f64, _i32],
+    "wdb_get_precond": [_vp, _vp],
+    "wdb_solve": [_vp, _vp, _f32, C.POINTER(SolveOpts), _vp, C.POINTER(SolveInfo)],
+    "wdb_solve_coeffs": [_vp, _vp, _f32, C.POINTER(SolveOpts), _vp, C.POINTER(SolveInfo)],
+    "wdb_objective": [_vp, _vp, _vp, _f32, _vp, _pd, _pd],
+    "wdb_theta_apply": [_vp, _i32, _vp, _vp, _vp, _i32, _vp],
+    "wdb_prox_step": [_vp, _vp, _vp, _vp, _f32, _f32, _f32, _i32, _vp],
+    "wdb_synthesize": [_vp, _vp, _vp, _vp],
+    "wdb_dwt": [_i32, _i32, _i32, _vp, _vp, _i32, _vp],
+    "wdb_blur": [C.POINTER(PsfFieldC), _vp, _vp, _vp],
+    "wdb_wavelet_filter": [_i32, _pd, C.POINTER(_i32)],
+}
+for _name, _args in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.argtypes = _args
+    _fn.restype = C.c_int
+_lib.wdb_theta_free.argtypes = [_vp]
+_lib.wdb_theta_free.restype = None
+_lib.wdb_last_error.restype = C.c_char_p
+_lib.wdb_version.restype = C.c_char_p
+
+
+def _check(fn: str, status: int) -> None:
+    if status != WDB_OK:
+        raise WdbError(fn, status, _lib.wdb_last_error().decode(errors="replace"))
+
+
+def version() -> str:
+    return _lib.wdb_version().decode()
+
+
+def wavelet_filter(name: str) -> np.ndarray:
+    """Low-pass analysis filter the library derives for ``name`` (host only)."""
+    h = np.zeros(16)
+    ln = C.c_int32(0)
+    _check("wdb_wavelet_filter", _lib.wdb_wavelet_filter(WAVELETS[name], h.ctypes.data_as(_pd), C.byref(ln)))
+    return h[: ln.value].copy()
+
+
+# --------------------------------------------------------------------------
+# helpers
+# --------------------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    if stream is not None:
+        return C.c_void_p(int(stream))
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, numel=None, name="tensor"):
+    """Device pointer of a contiguous float32 ROCm tensor (checked)."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous float32")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _field_struct(field):
+    n = int(field.n)
+    arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(n * n))
+            for a in (field.sig_major, field.sig_minor, field.angle)]
+    st = PsfFieldC(n, arrs[0].ctypes.data_as(_pd), arrs[1].ctypes.data_as(_pd),
+                   arrs[2].ctypes.data_as(_pd), float(getattr(field, "trunc", 3.0)))
+    return st, arrs   # keep arrays alive with the struct
+
+
+def _f64ptr(a):
+    if a is None:
+        return None, None
+    arr = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    return C.c_void_p(arr.ctypes.data), arr
+
+
+# --------------------------------------------------------------------------
+# operator handle
+# --------------------------------------------------------------------------
+class Theta:
+    """Owns a wdb_theta handle."""
+
+    def __init__(self, handle: C.c_void_p):
+        self._h = handle
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.wdb_theta_free(h)
+            self._h = None
+
+    def free(self):
+        self.__del__()
+
+    @property
+    def handle(self):
+        return self._h
+
+    @classmethod
+    def build(cls, field, wavelet: str, levels: int, nnz_budget: int, stream=None) -> "Theta":
+        st, keep = _field_struct(field)
+        out = C.c_void_p()
+        _check("wdb_build_theta", _lib.wdb_build_theta(C.byref(st), WAVELETS[wavelet], levels, int(nnz_budget),
+                                                       _stream(stream), C.byref(out)))
+        del keep
+        return cls(out)
+
+    @classmethod
+    def from_csr(cls, n: int, wavelet: str, levels: int, rowptr, col, val, stream=None) -> "Theta":
+        rp = np.ascontiguousarray(np.asarray(rowptr, dtype=np.int64))
+        cc = np.ascontiguousarray(np.asarray(col, dtype=np.int32))
+        vv = np.ascontiguousarray(np.asarray(val, dtype=np.float64))
+        out = C.c_void_p()
+        _check("wdb_theta_import", _lib.wdb_theta_import(n, WAVELETS[wavelet], levels, int(vv.size),
+                                                         C.c_void_p(rp.ctypes.data), C.c_void_p(cc.ctypes.data),
+                                                         C.c_void_p(vv.ctypes.data), _stream(stream), C.byref(out)))
+        return cls(out)
+
+    def info(self) -> dict:
+        d = ThetaDesc()
+        _check("wdb_theta_info", _lib.wdb_theta_info(self._h, C.byref(d)))
+        return {k: getattr(d, k) for k, _ in ThetaDesc._fields_ if k != "pad_"}
+
+    def export(self):
+        """(rowptr int64, col int32, val float64) host arrays."""
+        d = self.info()
+        N = d["n"] * d["n"]
+        rp = np.zeros(N + 1, dtype=np.int64)
+        cc = np.zeros(max(d["nnz"], 1), dtype=np.int32)
+        vv = np.zeros(max(d["nnz"], 1), dtype=np.float64)
+        _check("wdb_theta_export", _lib.wdb_theta_export(self._h, C.c_void_p(rp.ctypes.data),
+                                                         C.c_void_p(cc.ctypes.data), C.c_void_p(vv.ctypes.data)))
+        return rp, cc[: d["nnz"]], vv[: d["nnz"]]
+
+    def lipschitz(self, start=None, tol: float = 1e-12, max_iters: int = 20000):
+        p, keep = _f64ptr(start)
+        L = C.c_double(0.0)
+        it = C.c_int32(0)
+        _check("wdb_theta_lipschitz", _lib.wdb_theta_lipschitz(self._h, p, tol, max_iters, C.byref(L), C.byref(it)))
+        return L.value, it.value
+
+    def set_precond(self, kind: str, eps: float = 0.0, start=None, tol: float = 1e-12, max_iters: int = 20000):
+        p, keep = _f64ptr(start)
+        _check("wdb_set_precond", _lib.wdb_set_precond(self._h, PRECOND[kind], eps, p, tol, max_iters))
+
+    def precond(self) -> np.ndarray:
+        d = self.info()
+        out = np.zeros(d["n"] * d["n"])
+        _check("wdb_get_precond", _lib.wdb_get_precond(self._h, C.c_void_p(out.ctypes.data)))
+        return out
+
+    @property
+    def N(self) -> int:
+        d = self.info()
+        return d["n"] * d["n"]
+
+    def apply(self, x, b=None, transpose: bool = False, out=None, repeat: int = 1, stream=None):
+        torch = _torch()
+        N = self.N
+        y = torch.empty(N, device=x.device, dtype=torch.float32) if out is None else out
+        _check("wdb_theta_apply", _lib.wdb_theta_apply(self._h, 1 if transpose else 0, _dev(x, N, "x"),
+                                                       None if b is None else _dev(b, N, "b"), _dev(y, N, "out"),
+                                                       repeat, _stream(stream)))
+        return y
+
+    def prox_step(self, r, x, y, tau: float, lam: float, beta: float, use_precond: bool = False, stream=None):
+        N = self.N
+        _check("wdb_prox_step", _lib.wdb_prox_step(self._h, _dev(r, N, "r"), _dev(x, N, "x"), _dev(y, N, "y"),
+                                                   tau, lam, beta, 1 if use_precond else 0, _stream(stream)))
+
+    def objective(self, x, x0, lam: float, stream=None):
+        N = self.N
+        E = C.c_double(0.0)
+        g = C.c_double(0.0)
+        _check("wdb_objective", _lib.wdb_objective(self._h, _dev(x, N, "x"), _dev(x0, N, "x0"), lam,
+                                                   _stream(stream), C.byref(E), C.byref(g)))
+        return E.value, g.value
+
+    def _solve(self, fn, src, lam, iters, check_every, tol, x_init, k0, precond, use_graph, trace_cap, out,
+               stream):
+        torch = _torch()
+        N = self.N
+        x = torch.empty(N, device=src.device, dtype=torch.float32) if out is None else out
+        trace = np.zeros(3 * max(trace_cap, 1))
+        o = SolveOpts(int(iters), int(check_every), float(tol),
+                      None if x_init is None else _dev(x_init, N, "x_init").value, int(k0),
+                      1 if precond else 0, _stream(stream).value, trace.ctypes.data_as(_pd), int(trace_cap),
+                      1 if use_graph else 0)
+        info = SolveInfo()
+        st = getattr(_lib, fn)(self._h, _dev(src, name="input"), float(lam), C.byref(o), _dev(x, N, "x_out"),
+                               C.byref(info))
+        res = {k: getattr(info, k) for k, _ in SolveInfo._fields_}
+        res["trace"] = trace[: 3 * min(info.checks, trace_cap)].reshape(-1, 3)
+        if st == WDB_ERR_NOT_CONVERGED:
+            res["converged"] = False
+            return x, res
+        _check(fn, st)
+        res["converged"] = tol > 0
+        return x, res
+
+    def solve(self, u, lam: float, iters: int, check_every: int = 20, tol: float = 0.0, x_init=None, k0: int = 1,
+              precond: bool = False, use_graph: bool = False, trace_cap: int = 0, out=None, stream=None):
+        """FISTA from a blurred image u (device n*n float32); returns (x, info)."""
+        return self._solve("wdb_solve", u, lam, iters, check_every, tol, x_init, k0, precond, use_graph,
+                           trace_cap, out, stream)
+
+    def solve_coeffs(self, x0, lam: float, iters: int, check_every: int = 20, tol: float = 0.0, x_init=None,
+                     k0: int = 1, precond: bool = False, use_graph: bool = False, trace_cap: int = 0, out=None,
+                     stream=None):
+        """FISTA from wavelet-domain data x0 (device N float32); returns (x, info)."""
+        return self._solve("wdb_solve_coeffs", x0, lam, iters, check_every, tol, x_init, k0, precond, use_graph,
+                           trace_cap, out, stream)
+
+    def synthesize(self, x, out=None, stream=None):
+        torch = _torch()
+        d = self.info()
+        n = d["n"]
+        u = torch.empty((n, n), device=x.device, dtype=torch.float32) if out is None else out
+        _check("wdb_synthesize", _lib.wdb_synthesize(self._h, _dev(x, n * n, "x"), _dev(u, n * n, "u_hat"),
+                                                     _stream(stream)))
+        return u
+
+
+def build_theta(field, wavelet: str, levels: int, nnz_budget: int, stream=None) -> Theta:
+    return Theta.build(field, wavelet, levels, nnz_budget, stream)
+
+
+def dwt(u, wavelet: str, levels: int, inverse: bool = False, out=None, stream=None):
+    torch = _torch()
+    n = int(round(u.numel() ** 0.5))
+    y = torch.empty(n * n, device=u.device, dtype=torch.float32) if out is None else out
+    _check("wdb_dwt", _lib.wdb_dwt(n, WAVELETS[wavelet], levels, _dev(u, n * n, "in"), _dev(y, n * n, "out"),
+                                   1 if inverse else 0, _stream(stream)))
+    return y
+
+
+def blur(field, u, out=None, stream=None):
+    torch = _torch()
+    n = int(field.n)
+    y = torch.empty((n, n), device=u.device, dtype=torch.float32) if out is None else out
+    st, keep = _field_struct(field)
+    _check("wdb_blur", _lib.wdb_blur(C.byref(st), _dev(u, n * n, "u"), _dev(y, n * n, "out"), _stream(stream)))
+    return y

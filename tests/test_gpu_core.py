@@ -1,0 +1,334 @@
+"""GPU parity: the HIP path (called through the C ABI) against the FP64 oracle.
+
+Sizes here span several 64-row slices and every subband; the full-size
+workloads are covered in test_gpu_fullsize.py.  Float32 tolerances are stated
+per test; the solver gates are those of the 64x64 parity case: relative
+objective within 1e-5 and relative ||x - x_oracle|| <= 1e-4 after 200
+iterations.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+from oracle import blur, dwt, filters, fista, lipschitz, pipeline, precond, theta
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def W():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_1512_08401_amd import wdb
+    return wdb
+
+
+@pytest.fixture(scope="module")
+def p64():
+    """Oracle problem of the 64x64 parity workload (Haar, 3 levels, 40 nnz/px)."""
+    wl = synth.WORKLOADS["parity64"]
+    P = pipeline.build_problem(wl)
+    P["wl"] = wl
+    A = P["A"]
+    P["A32"] = sp.csr_matrix((A.data.astype(np.float32).astype(np.float64), A.indices, A.indptr), shape=A.shape)
+    return P
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def imported(W, P):
+    rp, cc, vv = theta.csr_arrays(P["A"])
+    wl = P["wl"]
+    return W.Theta.from_csr(wl.n, wl.wavelet, wl.levels, rp, cc, vv)
+
+
+# ---------------------------------------------------------------------------
+# transforms and blur
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name,n,J", [("haar", 64, 3), ("db4", 64, 3), ("db4", 256, 4), ("db4", 16, 1),
+                                      ("haar", 8, 3)])
+def test_dwt_forward_inverse(W, name, n, J):
+    print(f"dwt {name} n={n} J={J}", flush=True)
+    u = np.random.default_rng(n + J).random((n, n)).astype(np.float32)
+    x = host(W.dwt(dev(u).reshape(-1), name, J))
+    xo = dwt.dwt2(u.astype(np.float64), filters.by_name(name), J)
+    assert np.max(np.abs(x - xo)) <= 2e-6 * np.max(np.abs(xo))
+    c = np.random.default_rng(1).standard_normal(n * n).astype(np.float32)
+    v = host(W.dwt(dev(c), name, J, inverse=True))
+    vo = dwt.idwt2(c.astype(np.float64), filters.by_name(name), J, n).ravel()
+    assert np.max(np.abs(v - vo)) <= 2e-6 * np.max(np.abs(vo))
+
+
+@pytest.mark.parametrize("field", [synth.psf_isotropic(64, 1.0, 3.0), synth.psf_rotating(128, 4.0, 1.0),
+                                   synth.psf_rotating(32, 2.5, 0.7)])
+def test_blur_matches_oracle(W, field):
+    print(f"blur n={field.n}", flush=True)
+    u = synth.piecewise_image(field.n, 5).astype(np.float32)
+    out = host(W.blur(field, dev(u)))
+    ref = blur.blur(field, u.astype(np.float64))
+    assert np.max(np.abs(out - ref)) <= 1e-6
+
+
+# ---------------------------------------------------------------------------
+# Theta_K construction
+# ---------------------------------------------------------------------------
+def _compare_kept(rp, cc, vv, T, K, tol_rel=1e-12):
+    N = T.shape[0]
+    rows = np.repeat(np.arange(N), np.diff(rp))
+    got = rows.astype(np.int64) * N + cc
+    r, c, v = theta.top_k(T, K)
+    want = r * N + c
+    amax = np.max(np.abs(T))
+    thr = theta.threshold_value(T, K)
+    sym = np.setxor1d(got, want)
+    # kept sets may differ only where |Theta| is within rounding of the cut
+    if sym.size:
+        mags = np.abs(T.ravel()[sym])
+        assert np.all(np.abs(mags - thr) <= tol_rel * amax), f"{sym.size} kept entries differ away from the cut"
+    common, ig, iw = np.intersect1d(got, want, return_indices=True)
+    assert np.max(np.abs(vv[ig] - T.ravel()[common])) <= 1e-13 * amax
+    return sym.size
+
+
+@pytest.mark.parametrize("case", ["parity64", "db4_32_rot", "haar_16", "db4_16_wrap"])
+def test_build_theta_matches_dense_oracle(W, p64, case):
+    print(f"build {case}", flush=True)
+    if case == "parity64":
+        wl = p64["wl"]
+        field, name, J, K, T = wl.psf(), wl.wavelet, wl.levels, wl.nnz, p64["T"]
+    else:
+        field, name, J = {"db4_32_rot": (synth.psf_rotating(32, 2.5, 1.0), "db4", 2),
+                          "haar_16": (synth.psf_isotropic(16, 1.0, 2.0), "haar", 2),
+                          "db4_16_wrap": (synth.psf_rotating(16, 2.0, 0.8), "db4", 1)}[case]
+        K = 20 * field.n ** 2
+        T = theta.theta_dense(field, filters.by_name(name), J)
+    th = W.build_theta(field, name, J, K)
+    info = th.info()
+    assert info["nnz"] == K
+    rp, cc, vv = th.export()
+    _compare_kept(rp, cc, vv, T, K)
+    assert abs(info["threshold"] - theta.threshold_value(T, K)) <= 1e-12 * np.max(np.abs(T))
+
+
+def test_build_theta_budget_edges(W):
+    field = synth.psf_rotating(32, 2.5, 1.0)
+    T = theta.theta_dense(field, filters.db4(), 2)
+    # one entry: the largest magnitude
+    th = W.build_theta(field, "db4", 2, 1)
+    rp, cc, vv = th.export()
+    a = int(np.searchsorted(rp, 1, side="right") - 1)
+    assert (a, int(cc[0])) == np.unravel_index(np.argmax(np.abs(T)), T.shape)
+    # budget beyond the non-zeros keeps every non-zero of the column windows
+    th = W.build_theta(field, "db4", 2, 1024 * 1024)
+    rp, cc, vv = th.export()
+    N = 1024
+    rows = np.repeat(np.arange(N), np.diff(rp))
+    assert np.max(np.abs(vv - T[rows, cc])) <= 1e-13
+    mask = np.ones_like(T, dtype=bool)
+    mask[rows, cc] = False
+    assert np.max(np.abs(T[mask])) <= 1e-14          # only rounding-level values are absent
+
+
+# ---------------------------------------------------------------------------
+# kernels on an imported oracle Theta_K
+# ---------------------------------------------------------------------------
+def test_apply_matches_oracle(W, p64):
+    th = imported(W, p64)
+    A32 = p64["A32"]
+    N = A32.shape[0]
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(N).astype(np.float32)
+    b = rng.standard_normal(N).astype(np.float32)
+    y = host(th.apply(dev(x), dev(b)))
+    ref = A32 @ x.astype(np.float64) - b
+    assert np.max(np.abs(y - ref)) <= 1e-5 * np.max(np.abs(ref))
+    yt = host(th.apply(dev(x), None, transpose=True, repeat=3))
+    reft = A32.T @ x.astype(np.float64)
+    assert np.max(np.abs(yt - reft)) <= 1e-5 * np.max(np.abs(reft))
+
+
+def test_empty_and_ragged_operator(W):
+    """Rows of very different lengths (0 .. 700) and an empty operator."""
+    n, N = 32, 1024
+    rng = np.random.default_rng(9)
+    lens = np.zeros(N, dtype=np.int64)
+    lens[rng.choice(N, 40, replace=False)] = rng.integers(1, 700, 40)
+    lens[5] = N
+    cols, vals = [], []
+    for r in range(N):
+        c = np.sort(rng.choice(N, lens[r], replace=False)).astype(np.int32)
+        cols.append(c)
+        vals.append(rng.standard_normal(lens[r]))
+    rp = np.concatenate([[0], np.cumsum(lens)])
+    cc, vv = np.concatenate(cols), np.concatenate(vals)
+    th = W.Theta.from_csr(n, "haar", 2, rp, cc, vv)
+    A = sp.csr_matrix((vv.astype(np.float32).astype(np.float64), cc, rp), shape=(N, N))
+    x = rng.standard_normal(N).astype(np.float32)
+    assert np.max(np.abs(host(th.apply(dev(x))) - A @ x)) <= 1e-4
+    assert np.max(np.abs(host(th.apply(dev(x), transpose=True)) - A.T @ x)) <= 1e-4
+    e = W.Theta.from_csr(n, "haar", 2, np.zeros(N + 1, dtype=np.int64), np.zeros(0, np.int32), np.zeros(0))
+    b = rng.standard_normal(N).astype(np.float32)
+    assert np.array_equal(host(e.apply(dev(x), dev(b))), -b.astype(np.float64))
+
+
+def test_prox_step_matches_oracle(W, p64):
+    th = imported(W, p64)
+    A32 = p64["A32"]
+    N = A32.shape[0]
+    rng = np.random.default_rng(4)
+    r, x, y = (rng.standard_normal(N).astype(np.float32) for _ in range(3))
+    tau, lam, beta = 0.9, 0.05, 0.4
+    xd, yd = dev(x), dev(y)
+    th.prox_step(dev(r), xd, yd, tau, lam, beta)
+    g = A32.T @ r.astype(np.float64)
+    xn = fista.soft_threshold(y - tau * g, tau * lam)
+    yn = xn + beta * (xn - x)
+    assert np.max(np.abs(host(xd) - xn)) <= 1e-5 * np.max(np.abs(xn))
+    assert np.max(np.abs(host(yd) - yn)) <= 1e-5 * np.max(np.abs(yn))
+
+
+def test_lipschitz_matches_oracle(W, p64):
+    th = imported(W, p64)
+    start = synth.power_start(4096, p64["wl"].power_seed)
+    L, its = th.lipschitz(start)
+    Lo, itso = lipschitz.lipschitz(p64["A32"], start)
+    assert abs(L - Lo) <= 1e-9 * Lo
+    assert abs(its - itso) <= 1
+    # independent pin: the largest singular value squared
+    ev = np.linalg.norm(p64["A32"].toarray(), 2) ** 2
+    assert abs(L - ev) <= 1e-8 * ev
+
+
+def test_objective_and_gap_match_oracle(W, p64):
+    th = imported(W, p64)
+    A32 = p64["A32"]
+    x0 = p64["x0"].astype(np.float32)
+    lam = p64["wl"].lam
+    for seed in (0, 1):
+        x = (np.random.default_rng(seed).standard_normal(4096) * 0.01).astype(np.float32)
+        E, rel = th.objective(dev(x), dev(x0), lam)
+        Eo, Do, gap, relo = fista.duality_gap(A32, x0.astype(np.float64), np.float64(np.float32(lam)), x.astype(np.float64))
+        assert abs(E - Eo) <= 1e-12 * Eo
+        assert abs(rel - relo) <= 1e-10
+
+
+# ---------------------------------------------------------------------------
+# the solver
+# ---------------------------------------------------------------------------
+def _oracle_fista(P, iters, x0=None, p=None, Lp=None):
+    A32 = P["A32"]
+    wl = P["wl"]
+    x0 = P["x0"].astype(np.float32).astype(np.float64) if x0 is None else x0
+    lam = float(np.float32(wl.lam))
+    if p is None:
+        L, _ = lipschitz.lipschitz(A32, synth.power_start(4096, wl.power_seed))
+    else:
+        L = Lp
+    x, _, _ = fista.fista(A32, x0, lam, 1.0 / L, iters, p=p)
+    return x, fista.objective(A32, x0, lam, x)
+
+
+def _gate(A32, x0, lam, x_gpu, x_o, E_o):
+    E_g = fista.objective(A32, x0, lam, x_gpu)
+    assert abs(E_g - E_o) <= 1e-5 * E_o, (E_g, E_o)
+    assert np.linalg.norm(x_gpu - x_o) <= 1e-4 * np.linalg.norm(x_o)
+
+
+def test_fista_200_iterations_parity(W, p64):
+    th = imported(W, p64)
+    wl = p64["wl"]
+    th.lipschitz(synth.power_start(4096, wl.power_seed))
+    x0 = p64["x0"].astype(np.float32)
+    x, info = th.solve_coeffs(dev(x0), wl.lam, wl.iters, check_every=20, trace_cap=20)
+    assert info["iters"] == 200 and info["checks"] == 10
+    x_o, E_o = _oracle_fista(p64, wl.iters)
+    _gate(p64["A32"], x0.astype(np.float64), float(np.float32(wl.lam)), host(x), x_o, E_o)
+    # the trace is the float64 objective of the iterates
+    assert abs(info["trace"][-1, 1] - info["objective"]) == 0.0
+    assert np.all(np.diff(info["trace"][:, 0]) == 20)
+
+
+def test_end_to_end_parity64(W, p64):
+    """GPU build + GPU transform + GPU solve against the oracle pipeline."""
+    wl = p64["wl"]
+    th = W.build_theta(wl.psf(), wl.wavelet, wl.levels, wl.nnz)
+    th.lipschitz(synth.power_start(4096, wl.power_seed))
+    u0 = p64["u0"]
+    x, info = th.solve(dev(u0).reshape(-1), wl.lam, wl.iters, check_every=50)
+    x_o, E_o = _oracle_fista(p64, wl.iters)
+    _gate(p64["A32"], p64["x0"], float(np.float32(wl.lam)), host(x), x_o, E_o)
+    img = host(th.synthesize(x)).reshape(64, 64)
+    assert np.max(np.abs(img - dwt.idwt2(host(x), filters.haar(), 3, 64))) <= 1e-5
+
+
+def test_solver_is_deterministic_and_graph_matches_eager(W, p64):
+    th = imported(W, p64)
+    wl = p64["wl"]
+    x0 = dev(p64["x0"])
+    a, _ = th.solve_coeffs(x0, wl.lam, 120, check_every=20)
+    b, _ = th.solve_coeffs(x0, wl.lam, 120, check_every=20)
+    c, _ = th.solve_coeffs(x0, wl.lam, 120, check_every=20, use_graph=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert torch.equal(a, c)
+
+
+def test_resume_matches_single_run(W, p64):
+    """x^(k) only depends on (x, x_prev, k); resuming from x^(60) with k0 = 61 and
+    y = x^(60) differs from one run only through the momentum term, so compare
+    the resumed path with the oracle doing the same thing."""
+    th = imported(W, p64)
+    wl = p64["wl"]
+    x0 = p64["x0"].astype(np.float32)
+    x60, _ = th.solve_coeffs(dev(x0), wl.lam, 60, check_every=0)
+    x, _ = th.solve_coeffs(dev(x0), wl.lam, 40, check_every=0, x_init=x60, k0=61)
+    A32 = p64["A32"]
+    lam = float(np.float32(wl.lam))
+    L, _ = lipschitz.lipschitz(A32, synth.power_start(4096, wl.power_seed))
+    xo60, _, _ = fista.fista(A32, x0.astype(np.float64), lam, 1 / L, 60)
+    xo, _, _ = fista.fista(A32, x0.astype(np.float64), lam, 1 / L, 40, x_init=xo60, k0=61)
+    assert np.linalg.norm(host(x) - xo) <= 1e-4 * np.linalg.norm(xo)
+
+
+def test_tolerance_stop(W, p64):
+    th = imported(W, p64)
+    wl = p64["wl"]
+    x, info = th.solve_coeffs(dev(p64["x0"]), wl.lam, 5000, check_every=20, tol=1e-3)
+    assert info["converged"] and info["rel_gap"] <= 1e-3 and info["iters"] % 20 == 0
+    E, D, gap, rel = fista.duality_gap(p64["A32"], p64["x0"].astype(np.float32).astype(np.float64),
+                                       float(np.float32(wl.lam)), host(x))
+    assert abs(rel - info["rel_gap"]) <= 1e-9
+    x, info = th.solve_coeffs(dev(p64["x0"]), wl.lam, 20, check_every=20, tol=1e-9)
+    assert not info["converged"]
+
+
+@pytest.mark.parametrize("kind", ["spai", "spai_scale", "jacobi"])
+def test_preconditioner_matches_oracle(W, p64, kind):
+    th = imported(W, p64)
+    wl = p64["wl"]
+    A32 = p64["A32"]
+    start = synth.power_start(4096, wl.power_seed)
+    th.set_precond(kind, eps=0.05, start=start)
+    p = th.precond()
+    if kind == "spai":
+        po = precond.spai(A32)
+    elif kind == "jacobi":
+        po = precond.jacobi(A32, 0.05)
+    else:
+        po = precond.spai_grouped(A32, precond.scale_groups(64, 3))
+    assert np.max(np.abs(p - po) / po) <= 1e-10
+    Lp, _ = lipschitz.lipschitz_precond(A32, po, start)
+    assert abs(th.info()["lipschitz_p"] - Lp) <= 1e-9 * Lp
+    x0 = p64["x0"].astype(np.float32)
+    x, info = th.solve_coeffs(dev(x0), wl.lam, 100, check_every=20, precond=True)
+    x_o, E_o = _oracle_fista(p64, 100, p=po, Lp=Lp)
+    _gate(A32, x0.astype(np.float64), float(np.float32(wl.lam)), host(x), x_o, E_o)
