@@ -81,6 +81,8 @@ def main():
     ap.add_argument("--iters", type=int, default=None, help="FISTA iterations per step (default: workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=200)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU runs are not part of this build",
@@ -168,6 +170,12 @@ def main():
                 "kernel_us": round(k_us, 2), "algorithmic_bytes": alg_bytes,
                 "stored_slots": info["stored"], "transpose_kernel_us": round(kt_us, 2)}
 
+    if args.copy_calib:
+        src = torch.ones(64 * 1024 * 1024, device=dev, dtype=torch.float32)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
     out = {
         "metric": "FISTA iters/s", "value": round(value, 1), "unit": "iters/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),

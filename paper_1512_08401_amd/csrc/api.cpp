@@ -1,4 +1,5 @@
 // Error reporting, version and handle-level entry points of the wdb C ABI.
+#include <cstdlib>
 #include <cstring>
 
 #include "common.hpp"
@@ -19,9 +20,20 @@ void fail(wdb_status code, const char* fmt, ...) {
 }
 
 void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+int64_t sell_sort_window() {
+  static const int64_t w = [] {
+    const char* e = std::getenv("WDB_SELL_SORT");
+    const long long v = e ? std::atoll(e) : 0;
+    return static_cast<int64_t>(v < 0 ? 0 : v);
+  }();
+  return w;
+}
 void clear_last_error() { g_last_error.clear(); }
 
 void Sell::free_all() {
+  if (perm) (void)hipFree(perm);
+  perm = nullptr;
   if (slice_off) (void)hipFree(slice_off);
   if (val) (void)hipFree(val);
   if (col) (void)hipFree(col);
@@ -29,6 +41,25 @@ void Sell::free_all() {
   val = nullptr;
   col = nullptr;
   nrows = nslices = stored = 0;
+}
+
+void Csr32::free_all() {
+  if (rowptr) (void)hipFree(rowptr);
+  if (col) (void)hipFree(col);
+  if (val) (void)hipFree(val);
+  rowptr = nullptr;
+  col = nullptr;
+  val = nullptr;
+  nrows = nnz = 0;
+}
+
+int spmv_group() {
+  static const int g = [] {
+    const char* e = std::getenv("WDB_SPMV_GROUP");
+    const int v = e ? std::atoi(e) : 0;
+    return (v == 2 || v == 4 || v == 8 || v == 16 || v == 32 || v == 64) ? v : 0;
+  }();
+  return g;
 }
 
 void Csr::free_all() {
@@ -106,6 +137,8 @@ void wdb_theta_free(wdb_theta* th) {
   th->csr.free_all();
   th->A.free_all();
   th->At.free_all();
+  th->cA.free_all();
+  th->cAt.free_all();
   wdb::free_workspace(th);
   delete th;
 }

@@ -113,6 +113,9 @@ std::vector<Subband> layout(int32_t n, int32_t levels);
 // [w_s/4][64 lanes][4], so each lane reads one 16-byte vector of values and
 // one of column indices per step and a wavefront's step is 1 KiB contiguous.
 // Padding slots have value 0 and repeat a valid column of the same row.
+// Rows may be reordered inside windows of `sort_window` rows by decreasing
+// length (sliced ELL with local sorting), so that the rows sharing a slice
+// have similar lengths; `perm` then maps each slot row to its matrix row.
 // ---------------------------------------------------------------------------
 constexpr int kSlice = 64;
 
@@ -121,8 +124,12 @@ struct Sell {
   int64_t* slice_off = nullptr;  // device, nslices + 1 (element offsets)
   float* val = nullptr;          // device, stored
   int32_t* col = nullptr;        // device, stored
+  int32_t* perm = nullptr;       // device, nslices * 64 (-1: empty slot row), or null = identity
   void free_all();
 };
+
+// Rows per sorting window of the sliced-ELL layout (0 or 64: no reordering).
+int64_t sell_sort_window();
 
 // Device CSR (sorted columns) of one matrix.
 struct Csr {
@@ -133,8 +140,20 @@ struct Csr {
   void free_all();
 };
 
+// Float32 CSR copy used by the row-group ("vector CSR") kernels.
+struct Csr32 {
+  int64_t nrows = 0, nnz = 0;
+  int64_t* rowptr = nullptr;  // device, nrows + 1
+  int32_t* col = nullptr;     // device, nnz
+  float* val = nullptr;       // device, nnz
+  void free_all();
+};
+void csr_to_csr32(const Csr& a, Csr32* out, hipStream_t s);
+// Lanes per row of the vector-CSR kernels (0: sliced-ELL kernels).
+int spmv_group();
+
 // Build a SELL copy of a device CSR (float64 values rounded to float32).
-void csr_to_sell(const Csr& a, Sell* out, hipStream_t s);
+void csr_to_sell(const Csr& a, Sell* out, hipStream_t s, int64_t sort_window);
 // Transpose a device CSR (sorted output).
 void csr_transpose(const Csr& a, Csr* out, hipStream_t s);
 // Sort device COO triples by (row, col) into a CSR; consumes nothing.
@@ -152,6 +171,7 @@ struct wdb_theta {
   wdb::Csr csr;        // Theta_K, float64 values (export)
   wdb::Sell A;         // Theta_K   (rows = output coefficient)
   wdb::Sell At;        // Theta_K^T (rows = input coefficient)
+  wdb::Csr32 cA, cAt;  // float32 CSR of Theta_K and Theta_K^T
   bool has_L = false;
   double L = 0.0;
   int precond = 0;

@@ -20,7 +20,9 @@ constexpr int kBlock = 256;
 
 __global__ __launch_bounds__(kBlock) void k_hessian_diag(const int64_t* __restrict__ soffT,
                                                          const float* __restrict__ valT,
-                                                         const int32_t* __restrict__ colT, int64_t N,
+                                                         const int32_t* __restrict__ colT,
+                                                         const int32_t* __restrict__ permT, int64_t nslots,
+                                                         int64_t N,
                                                          const int64_t* __restrict__ rowptr,
                                                          const int32_t* __restrict__ col,
                                                          const double* __restrict__ val,
@@ -28,9 +30,11 @@ __global__ __launch_bounds__(kBlock) void k_hessian_diag(const int64_t* __restri
                                                          double* __restrict__ m2) {
   __shared__ double red[kBlock];
   double* acc = scratch + static_cast<size_t>(blockIdx.x) * N;
-  for (int64_t i = blockIdx.x; i < N; i += gridDim.x) {
-    const int64_t sl = i / kSlice;
-    const int lane = static_cast<int>(i % kSlice);
+  for (int64_t q = blockIdx.x; q < nslots; q += gridDim.x) {
+    const int64_t i = permT ? static_cast<int64_t>(permT[q]) : (q < N ? q : -1);
+    if (i < 0) continue;  // uniform across the block
+    const int64_t sl = q / kSlice;
+    const int lane = static_cast<int>(q % kSlice);
     const int64_t base = soffT[sl];
     const int64_t w = (soffT[sl + 1] - base) / kSlice;
     double s1 = 0.0;
@@ -108,7 +112,8 @@ extern "C" wdb_status wdb_set_precond(wdb_theta* th, int32_t kind, double eps, c
     const int nwg = static_cast<int>(std::min<int64_t>(N, 256));
     DevBuf<double> scratch(static_cast<size_t>(nwg) * N);
     WDB_HIP(hipMemsetAsync(scratch.p, 0, scratch.bytes(), s));
-    hipLaunchKernelGGL(k_hessian_diag, dim3(nwg), dim3(kBlock), 0, s, th->At.slice_off, th->At.val, th->At.col, N,
+    hipLaunchKernelGGL(k_hessian_diag, dim3(nwg), dim3(kBlock), 0, s, th->At.slice_off, th->At.val, th->At.col,
+                       th->At.perm, th->At.nslices * kSlice, N,
                        th->csr.rowptr, th->csr.col, th->csr.val, scratch.p, m1.p, m2.p);
     WDB_HIP(hipGetLastError());
     WDB_HIP(hipStreamSynchronize(s));

@@ -33,12 +33,26 @@ struct SellView {
   const int64_t* __restrict__ soff;
   const float4* __restrict__ val;
   const int4* __restrict__ col;
+  const int32_t* __restrict__ perm;
   int64_t nslices, nrows;
 };
 
 SellView view(const Sell& m) {
   return SellView{m.slice_off, reinterpret_cast<const float4*>(m.val), reinterpret_cast<const int4*>(m.col),
-                  m.nslices, m.nrows};
+                  m.perm, m.nslices, m.nrows};
+}
+
+// Matrix row held by lane `lane` of slice `sl` (-1 for an empty slot row).
+__device__ __forceinline__ int64_t slot_row(const SellView& A, int64_t sl, int lane) {
+  const int64_t q = sl * kSlice + lane;
+  if (A.perm) return A.perm[q];
+  return q < A.nrows ? q : -1;
+}
+
+// Padding slots hold value 0 and a valid column of the same row, so they
+// are processed like real entries (a branch per entry serialises the gathers).
+__device__ __forceinline__ float gather_fma(float v, int c, const float* __restrict__ x, float acc) {
+  return fmaf(v, x[c], acc);
 }
 
 // Row sum of one lane's row in float32, storage order.
@@ -50,10 +64,10 @@ __device__ __forceinline__ float row_dot_f32(const SellView& A, int64_t sl, int 
   for (int64_t j = beg + lane; j < end; j += kSlice) {
     const float4 v = A.val[j];
     const int4 c = A.col[j];
-    acc = fmaf(v.x, x[c.x], acc);
-    acc = fmaf(v.y, x[c.y], acc);
-    acc = fmaf(v.z, x[c.z], acc);
-    acc = fmaf(v.w, x[c.w], acc);
+    acc = gather_fma(v.x, c.x, x, acc);
+    acc = gather_fma(v.y, c.y, x, acc);
+    acc = gather_fma(v.z, c.z, x, acc);
+    acc = gather_fma(v.w, c.w, x, acc);
   }
   return acc;
 }
@@ -110,8 +124,8 @@ __global__ __launch_bounds__(kBlock) void k_res(SellView A, const float* __restr
   const int64_t sl = static_cast<int64_t>(blockIdx.x) * kSlicesPerBlock + threadIdx.x / kSlice;
   if (sl >= A.nslices) return;
   const float acc = row_dot_f32(A, sl, lane, y);
-  const int64_t row = sl * kSlice + lane;
-  if (row < A.nrows) r[row] = b ? acc - b[row] : acc;
+  const int64_t row = slot_row(A, sl, lane);
+  if (row >= 0) r[row] = b ? acc - b[row] : acc;
 }
 
 // beta from the device counter (kdev) or, if kdev is null, from `beta`.
@@ -123,8 +137,8 @@ __global__ __launch_bounds__(kBlock) void k_prox(SellView At, const float* __res
   const int64_t sl = static_cast<int64_t>(blockIdx.x) * kSlicesPerBlock + threadIdx.x / kSlice;
   if (sl >= At.nslices) return;
   const float g = row_dot_f32(At, sl, lane, r);
-  const int64_t row = sl * kSlice + lane;
-  if (row >= At.nrows) return;
+  const int64_t row = slot_row(At, sl, lane);
+  if (row < 0) return;
   if (kdev) {
     const int k = *kdev;
     beta = static_cast<float>((static_cast<double>(k) - 1.0) / (static_cast<double>(k) + 2.0));
@@ -139,6 +153,120 @@ __global__ __launch_bounds__(kBlock) void k_prox(SellView At, const float* __res
 }
 
 // ---------------------------------------------------------------------------
+// Vector-CSR variants: G consecutive lanes share one row and read its
+// consecutive entries (whose columns are spatial neighbours), then reduce with
+// a fixed butterfly inside the group.
+// ---------------------------------------------------------------------------
+struct CsrView {
+  const int64_t* __restrict__ rp;
+  const int32_t* __restrict__ col;
+  const float* __restrict__ val;
+  int64_t nrows;
+};
+
+CsrView cview(const Csr32& m) { return CsrView{m.rowptr, m.col, m.val, m.nrows}; }
+
+template <int G>
+__device__ __forceinline__ float group_dot(const CsrView& A, int64_t row, int gl, const float* __restrict__ x) {
+  float acc = 0.f;
+  if (row < A.nrows) {
+    const int64_t end = A.rp[row + 1];
+#pragma unroll 2
+    for (int64_t k = A.rp[row] + gl; k < end; k += G) acc = fmaf(A.val[k], x[A.col[k]], acc);
+  }
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+  return acc;
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_res_csr(CsrView A, const float* __restrict__ y,
+                                                    const float* __restrict__ b, float* __restrict__ r,
+                                                    int* __restrict__ kdev) {
+  if (kdev && blockIdx.x == 0 && threadIdx.x == 0) *kdev += 1;
+  const int64_t row = static_cast<int64_t>(blockIdx.x) * (kBlock / G) + threadIdx.x / G;
+  const int gl = threadIdx.x % G;
+  const float acc = group_dot<G>(A, row, gl, y);
+  if (gl == 0 && row < A.nrows) r[row] = b ? acc - b[row] : acc;
+}
+
+template <int G, bool PRE>
+__global__ __launch_bounds__(kBlock) void k_prox_csr(CsrView At, const float* __restrict__ r,
+                                                     float* __restrict__ x, float* __restrict__ y, float tau,
+                                                     float thr, float beta, const int* __restrict__ kdev,
+                                                     const float* __restrict__ pinv) {
+  const int64_t row = static_cast<int64_t>(blockIdx.x) * (kBlock / G) + threadIdx.x / G;
+  const int gl = threadIdx.x % G;
+  const float g = group_dot<G>(At, row, gl, r);
+  if (gl != 0 || row >= At.nrows) return;
+  if (kdev) {
+    const int k = *kdev;
+    beta = static_cast<float>((static_cast<double>(k) - 1.0) / (static_cast<double>(k) + 2.0));
+  }
+  const float pi = PRE ? pinv[row] : 1.0f;
+  const float z = y[row] - (tau * pi) * g;
+  const float t = thr * pi;
+  const float xn = copysignf(fmaxf(fabsf(z) - t, 0.0f), z);
+  const float xo = x[row];
+  x[row] = xn;
+  y[row] = xn + beta * (xn - xo);
+}
+
+template <int G>
+void launch_res_csr(const CsrView& A, const float* y, const float* b, float* r, int* kdev, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>((A.nrows + kBlock / G - 1) / (kBlock / G)));
+  hipLaunchKernelGGL(k_res_csr<G>, grid, dim3(kBlock), 0, s, A, y, b, r, kdev);
+}
+
+template <int G>
+void launch_prox_csr(const CsrView& At, const float* r, float* x, float* y, float tau, float thr, float beta,
+                     const int* kdev, const float* pinv, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>((At.nrows + kBlock / G - 1) / (kBlock / G)));
+  if (pinv)
+    hipLaunchKernelGGL((k_prox_csr<G, true>), grid, dim3(kBlock), 0, s, At, r, x, y, tau, thr, beta, kdev, pinv);
+  else
+    hipLaunchKernelGGL((k_prox_csr<G, false>), grid, dim3(kBlock), 0, s, At, r, x, y, tau, thr, beta, kdev, pinv);
+}
+
+// r = A y - b with the configured kernel family.
+void launch_res(const Sell& sell, const Csr32& csr, const float* y, const float* b, float* r, int* kdev,
+                hipStream_t s) {
+  switch (spmv_group()) {
+    case 2: launch_res_csr<2>(cview(csr), y, b, r, kdev, s); return;
+    case 4: launch_res_csr<4>(cview(csr), y, b, r, kdev, s); return;
+    case 8: launch_res_csr<8>(cview(csr), y, b, r, kdev, s); return;
+    case 16: launch_res_csr<16>(cview(csr), y, b, r, kdev, s); return;
+    case 32: launch_res_csr<32>(cview(csr), y, b, r, kdev, s); return;
+    case 64: launch_res_csr<64>(cview(csr), y, b, r, kdev, s); return;
+    default: {
+      const SellView A = view(sell);
+      hipLaunchKernelGGL(k_res, slice_grid(A.nslices), dim3(kBlock), 0, s, A, y, b, r, kdev);
+    }
+  }
+}
+
+void launch_prox(const Sell& sell, const Csr32& csr, const float* r, float* x, float* y, float tau, float thr,
+                 float beta, const int* kdev, const float* pinv, hipStream_t s) {
+  switch (spmv_group()) {
+    case 2: launch_prox_csr<2>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, s); return;
+    case 4: launch_prox_csr<4>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, s); return;
+    case 8: launch_prox_csr<8>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, s); return;
+    case 16: launch_prox_csr<16>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, s); return;
+    case 32: launch_prox_csr<32>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, s); return;
+    case 64: launch_prox_csr<64>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, s); return;
+    default: {
+      const SellView At = view(sell);
+      if (pinv)
+        hipLaunchKernelGGL(k_prox<true>, slice_grid(At.nslices), dim3(kBlock), 0, s, At, r, x, y, tau, thr, beta,
+                           kdev, pinv);
+      else
+        hipLaunchKernelGGL(k_prox<false>, slice_grid(At.nslices), dim3(kBlock), 0, s, At, r, x, y, tau, thr,
+                           beta, kdev, pinv);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Float64 objective and duality gap.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_obj_fwd(SellView A, const float* __restrict__ x, const float* __restrict__ b,
@@ -149,8 +277,8 @@ __global__ __launch_bounds__(kBlock) void k_obj_fwd(SellView A, const float* __r
   double v[3] = {0.0, 0.0, 0.0};
   if (sl < A.nslices) {
     const double acc = row_dot_f64(A, sl, lane, x);
-    const int64_t row = sl * kSlice + lane;
-    if (row < A.nrows) {
+    const int64_t row = slot_row(A, sl, lane);
+    if (row >= 0) {
       const double bb = static_cast<double>(b[row]);
       const double rr = acc - bb;
       r64[row] = rr;
@@ -168,9 +296,9 @@ __global__ __launch_bounds__(kBlock) void k_obj_bwd(SellView At, const double* _
   const int64_t sl = static_cast<int64_t>(blockIdx.x) * kSlicesPerBlock + threadIdx.x / kSlice;
   double v[1] = {0.0};
   if (sl < At.nslices) {
-    const int64_t row = sl * kSlice + lane;
+    const int64_t row = slot_row(At, sl, lane);
     const double g = row_dot_f64(At, sl, lane, r64);
-    if (row < At.nrows) v[0] = fabs(g);
+    if (row >= 0) v[0] = fabs(g);
   }
   block_partials<1, 1u>(v, partial, nblocks);
 }
@@ -206,9 +334,9 @@ __global__ __launch_bounds__(kBlock) void k_pi_fwd(SellView A, const double* __r
   const int64_t sl = static_cast<int64_t>(blockIdx.x) * kSlicesPerBlock + threadIdx.x / kSlice;
   double v[1] = {0.0};
   if (sl < A.nslices) {
-    const int64_t row = sl * kSlice + lane;
+    const int64_t row = slot_row(A, sl, lane);
     const double acc = row_dot_f64(A, sl, lane, vd);
-    if (row < A.nrows) {
+    if (row >= 0) {
       w[row] = acc;
       v[0] = acc * acc;
     }
@@ -223,9 +351,9 @@ __global__ __launch_bounds__(kBlock) void k_pi_bwd(SellView At, const double* __
   const int64_t sl = static_cast<int64_t>(blockIdx.x) * kSlicesPerBlock + threadIdx.x / kSlice;
   double v[1] = {0.0};
   if (sl < At.nslices) {
-    const int64_t row = sl * kSlice + lane;
+    const int64_t row = slot_row(At, sl, lane);
     double acc = row_dot_f64(At, sl, lane, w);
-    if (row < At.nrows) {
+    if (row >= 0) {
       if (d) acc *= d[row];
       u[row] = acc;
       v[0] = acc * acc;
@@ -401,14 +529,8 @@ Check objective_check(wdb_theta* th, const float* x, const float* x0, double lam
 }
 
 void launch_iteration(wdb_theta* th, float* x, bool pre, float tau, float thr, hipStream_t s) {
-  const SellView A = view(th->A), At = view(th->At);
-  hipLaunchKernelGGL(k_res, slice_grid(A.nslices), dim3(kBlock), 0, s, A, th->ws_y, th->ws_x0, th->ws_r, th->ws_k);
-  if (pre)
-    hipLaunchKernelGGL(k_prox<true>, slice_grid(At.nslices), dim3(kBlock), 0, s, At, th->ws_r, x, th->ws_y, tau,
-                       thr, 0.0f, th->ws_k, th->pinv);
-  else
-    hipLaunchKernelGGL(k_prox<false>, slice_grid(At.nslices), dim3(kBlock), 0, s, At, th->ws_r, x, th->ws_y, tau,
-                       thr, 0.0f, th->ws_k, nullptr);
+  launch_res(th->A, th->cA, th->ws_y, th->ws_x0, th->ws_r, th->ws_k, s);
+  launch_prox(th->At, th->cAt, th->ws_r, x, th->ws_y, tau, thr, 0.0f, th->ws_k, pre ? th->pinv : nullptr, s);
 }
 
 void ensure_lipschitz(wdb_theta* th, hipStream_t s) {
@@ -575,11 +697,9 @@ wdb_status wdb_theta_apply(wdb_theta* th, int32_t transpose, const float* x, con
   WDB_REQUIRE(x != y, WDB_ERR_ARG, "x and y must not alias");
   WDB_REQUIRE(repeat >= 1, WDB_ERR_ARG, "repeat must be >= 1");
   WDB_HIP(hipSetDevice(th->device));
-  const wdb::SellView M = wdb::view(transpose ? th->At : th->A);
   hipStream_t s = static_cast<hipStream_t>(stream);
   for (int i = 0; i < repeat; ++i)
-    hipLaunchKernelGGL(wdb::k_res, wdb::slice_grid(M.nslices), dim3(wdb::kBlock), 0, s, M, x, b, y,
-                       static_cast<int*>(nullptr));
+    wdb::launch_res(transpose ? th->At : th->A, transpose ? th->cAt : th->cA, x, b, y, nullptr, s);
   WDB_HIP(hipGetLastError());
   WDB_API_END
 }
@@ -590,15 +710,9 @@ wdb_status wdb_prox_step(wdb_theta* th, const float* r, float* x, float* y, floa
   WDB_REQUIRE(th && r && x && y, WDB_ERR_ARG, "null argument");
   WDB_REQUIRE(!use_precond || th->pinv, WDB_ERR_ARG, "no preconditioner set on this operator");
   WDB_HIP(hipSetDevice(th->device));
-  const wdb::SellView At = wdb::view(th->At);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const float thr = tau * lambda;
-  if (use_precond)
-    hipLaunchKernelGGL(wdb::k_prox<true>, wdb::slice_grid(At.nslices), dim3(wdb::kBlock), 0, s, At, r, x, y, tau,
-                       thr, beta, static_cast<const int*>(nullptr), th->pinv);
-  else
-    hipLaunchKernelGGL(wdb::k_prox<false>, wdb::slice_grid(At.nslices), dim3(wdb::kBlock), 0, s, At, r, x, y, tau,
-                       thr, beta, static_cast<const int*>(nullptr), static_cast<const float*>(nullptr));
+  wdb::launch_prox(th->At, th->cAt, r, x, y, tau, thr, beta, nullptr, use_precond ? th->pinv : nullptr, s);
   WDB_HIP(hipGetLastError());
   WDB_API_END
 }

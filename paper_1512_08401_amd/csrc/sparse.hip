@@ -52,33 +52,29 @@ __global__ void k_expand_rows(const int64_t* __restrict__ rowptr, int64_t N, int
   for (int64_t k = rowptr[r]; k < rowptr[r + 1]; ++k) row[k] = static_cast<int32_t>(r);
 }
 
-__global__ void k_slice_width(const int64_t* __restrict__ rowptr, int64_t N, int64_t nslices,
-                              int64_t* __restrict__ width) {
-  const int64_t sl = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (sl >= nslices) return;
-  int64_t w = 0;
-  for (int l = 0; l < kSlice; ++l) {
-    const int64_t r = sl * kSlice + l;
-    if (r < N) w = max(w, rowptr[r + 1] - rowptr[r]);
-  }
-  width[sl] = (w + 3) & ~int64_t(3);
+__global__ void k_row_lengths(const int64_t* __restrict__ rowptr, int64_t N, int32_t* __restrict__ len) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r < N) len[r] = static_cast<int32_t>(rowptr[r + 1] - rowptr[r]);
 }
 
+// One thread per slot row q: copies matrix row perm[q] (or q) into the slice.
 __global__ void k_fill_sell(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ ccol,
                             const double* __restrict__ cval, int64_t N, int64_t nslices,
-                            const int64_t* __restrict__ soff, float* __restrict__ val, int32_t* __restrict__ col) {
-  const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (r >= nslices * kSlice) return;
-  const int64_t sl = r / kSlice;
-  const int lane = static_cast<int>(r % kSlice);
+                            const int64_t* __restrict__ soff, const int32_t* __restrict__ perm,
+                            float* __restrict__ val, int32_t* __restrict__ col) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= nslices * kSlice) return;
+  const int64_t sl = q / kSlice;
+  const int lane = static_cast<int>(q % kSlice);
   const int64_t base = soff[sl];
   const int64_t w = (soff[sl + 1] - base) / kSlice;
+  const int64_t r = perm ? static_cast<int64_t>(perm[q]) : (q < N ? q : -1);
   int64_t beg = 0, len = 0;
-  if (r < N) {
+  if (r >= 0) {
     beg = rowptr[r];
     len = rowptr[r + 1] - beg;
   }
-  const int32_t pad_col = len ? ccol[beg + len - 1] : static_cast<int32_t>(r < N ? r : 0);
+  const int32_t pad_col = len ? ccol[beg + len - 1] : static_cast<int32_t>(r >= 0 ? r : 0);
   for (int64_t k = 0; k < w; ++k) {
     const int64_t idx = base + (k >> 2) * (4 * kSlice) + lane * 4 + (k & 3);
     if (k < len) {
@@ -89,6 +85,11 @@ __global__ void k_fill_sell(const int64_t* __restrict__ rowptr, const int32_t* _
       col[idx] = pad_col;
     }
   }
+}
+
+__global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = static_cast<float>(a[i]);
 }
 
 inline dim3 blocks_for(int64_t n, int b = 256) { return dim3(static_cast<unsigned>((n + b - 1) / b)); }
@@ -144,39 +145,93 @@ void csr_transpose(const Csr& a, Csr* out, hipStream_t s) {
   coo_to_csr(a.nrows, a.nnz, a.col, rows.p, a.val, out, s);
 }
 
-void csr_to_sell(const Csr& a, Sell* out, hipStream_t s) {
+void csr_to_sell(const Csr& a, Sell* out, hipStream_t s, int64_t sort_window) {
   Sell m;
   m.nrows = a.nrows;
   m.nslices = (a.nrows + kSlice - 1) / kSlice;
-  DevBuf<int64_t> width(m.nslices);
-  hipLaunchKernelGGL(k_slice_width, blocks_for(m.nslices), dim3(256), 0, s, a.rowptr, a.nrows, m.nslices, width.p);
-  WDB_HIP(hipGetLastError());
-  std::vector<int64_t> w(m.nslices), off(m.nslices + 1, 0);
-  WDB_HIP(hipMemcpyAsync(w.data(), width.p, m.nslices * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  WDB_HIP(hipStreamSynchronize(s));
-  for (int64_t i = 0; i < m.nslices; ++i) off[i + 1] = off[i] + w[i] * kSlice;
+  const int64_t slots = m.nslices * kSlice;
+  std::vector<int32_t> len(a.nrows);
+  if (a.nrows) {
+    DevBuf<int32_t> dlen(a.nrows);
+    hipLaunchKernelGGL(k_row_lengths, blocks_for(a.nrows), dim3(256), 0, s, a.rowptr, a.nrows, dlen.p);
+    WDB_HIP(hipGetLastError());
+    WDB_HIP(hipMemcpyAsync(len.data(), dlen.p, a.nrows * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    WDB_HIP(hipStreamSynchronize(s));
+  }
+  // slot row -> matrix row: identity, or sorted by decreasing length inside
+  // windows of sort_window rows (stable, so equal lengths keep their order)
+  std::vector<int32_t> perm;
+  const bool sorted = sort_window > kSlice;
+  if (sorted) {
+    const int64_t W = (sort_window + kSlice - 1) / kSlice * kSlice;
+    perm.assign(slots, -1);
+    std::vector<int32_t> idx;
+    for (int64_t w0 = 0; w0 < a.nrows; w0 += W) {
+      const int64_t w1 = std::min(a.nrows, w0 + W);
+      idx.resize(w1 - w0);
+      for (int64_t r = w0; r < w1; ++r) idx[r - w0] = static_cast<int32_t>(r);
+      std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) { return len[x] > len[y]; });
+      for (int64_t t = 0; t < w1 - w0; ++t) perm[w0 + t] = idx[t];
+    }
+  }
+  std::vector<int64_t> off(m.nslices + 1, 0);
+  for (int64_t sl = 0; sl < m.nslices; ++sl) {
+    int64_t w = 0;
+    for (int l = 0; l < kSlice; ++l) {
+      const int64_t q = sl * kSlice + l;
+      const int64_t r = sorted ? perm[q] : (q < a.nrows ? q : -1);
+      if (r >= 0) w = std::max<int64_t>(w, len[r]);
+    }
+    off[sl + 1] = off[sl] + ((w + 3) & ~int64_t(3)) * kSlice;
+  }
   m.stored = off[m.nslices];
   DevBuf<int64_t> soff(m.nslices + 1);
+  DevBuf<int32_t> dperm(sorted ? slots : 0);
   DevBuf<float> val(std::max<int64_t>(m.stored, 4));
   DevBuf<int32_t> col(std::max<int64_t>(m.stored, 4));
   WDB_HIP(hipMemcpyAsync(soff.p, off.data(), (m.nslices + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_fill_sell, blocks_for(m.nslices * kSlice), dim3(256), 0, s, a.rowptr, a.col, a.val, a.nrows,
-                     m.nslices, soff.p, val.p, col.p);
+  if (sorted) WDB_HIP(hipMemcpyAsync(dperm.p, perm.data(), slots * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_fill_sell, blocks_for(slots), dim3(256), 0, s, a.rowptr, a.col, a.val, a.nrows, m.nslices,
+                     soff.p, sorted ? dperm.p : static_cast<const int32_t*>(nullptr), val.p, col.p);
   WDB_HIP(hipGetLastError());
   WDB_HIP(hipStreamSynchronize(s));
   out->free_all();
   m.slice_off = soff.release();
   m.val = val.release();
   m.col = col.release();
+  m.perm = sorted ? dperm.release() : nullptr;
   *out = m;
 }
 
+void csr_to_csr32(const Csr& a, Csr32* out, hipStream_t s) {
+  Csr32 c;
+  c.nrows = a.nrows;
+  c.nnz = a.nnz;
+  DevBuf<int64_t> rp(a.nrows + 1);
+  DevBuf<int32_t> col(std::max<int64_t>(a.nnz, 1));
+  DevBuf<float> val(std::max<int64_t>(a.nnz, 1));
+  WDB_HIP(hipMemcpyAsync(rp.p, a.rowptr, (a.nrows + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+  if (a.nnz) {
+    WDB_HIP(hipMemcpyAsync(col.p, a.col, a.nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_to_f32, blocks_for(a.nnz), dim3(256), 0, s, a.val, val.p, a.nnz);
+    WDB_HIP(hipGetLastError());
+  }
+  WDB_HIP(hipStreamSynchronize(s));
+  out->free_all();
+  c.rowptr = rp.release();
+  c.col = col.release();
+  c.val = val.release();
+  *out = c;
+}
+
 void finish_theta(wdb_theta* th, hipStream_t s) {
-  csr_to_sell(th->csr, &th->A, s);
+  csr_to_sell(th->csr, &th->A, s, sell_sort_window());
+  csr_to_csr32(th->csr, &th->cA, s);
   Csr t;
   try {
     csr_transpose(th->csr, &t, s);
-    csr_to_sell(t, &th->At, s);
+    csr_to_sell(t, &th->At, s, sell_sort_window());
+    csr_to_csr32(t, &th->cAt, s);
   } catch (...) {
     t.free_all();
     throw;
