@@ -78,6 +78,15 @@ typedef struct {
 
 typedef struct wdb_theta wdb_theta;   /* opaque operator handle */
 
+/* Storage of Theta_K's values for the iteration (not in the paper, which
+ * states no GPU precision): float32, or 16 bits with per-block power-of-two
+ * scales and float32 accumulation. */
+typedef enum {
+  WDB_VAL_F32 = 0,
+  WDB_VAL_BF16 = 1,
+  WDB_VAL_F16 = 2
+} wdb_valtype;
+
 /* Description of an operator handle. */
 typedef struct {
   int32_t n;           /* image side                                   */
@@ -90,7 +99,7 @@ typedef struct {
   double threshold;    /* smallest kept |Theta| (0 for imported)        */
   double lipschitz_p;  /* lambda_max(P^-1/2 Theta_K^T Theta_K P^-1/2)    */
   int32_t precond;     /* 0 none, else the wdb_precond kind in use      */
-  int32_t pad_;
+  int32_t valtype;     /* wdb_valtype of the iteration values            */
 } wdb_theta_desc;
 
 /* ---------------------------------------------------------------------------
@@ -154,6 +163,18 @@ typedef enum {
 wdb_status wdb_set_precond(wdb_theta* th, int32_t kind, double eps, const double* start,
                            double tol, int32_t max_iters);
 
+/* Mixed precision.  valtype = WDB_VAL_F16 / WDB_VAL_BF16 makes the solver's
+ * iteration stream 16-bit copies of Theta_K's values (same slots and column
+ * indices as the float32 copy), accumulating in float32; WDB_VAL_F32 goes back
+ * to float32 values.  Rule: each value v (the float32-stored value) of a row in
+ * subband A is stored as q = round16(v * u_A), u_A = 2^-floor(log2 m_A), m_A the
+ * largest |v| among the rows of subband A (1 if none), rounding to nearest-even;
+ * the iteration then uses q / u_A exactly.  The block scale of block (A, B) is
+ * u_A for every column subband B.  The float64 objective and duality-gap
+ * checks keep using the float32 values, so they score iterates against the
+ * unquantised Theta_K.  Synchronises.  Errors: WDB_ERR_ARG, _OOM, _HIP. */
+wdb_status wdb_set_precision(wdb_theta* th, int32_t valtype);
+
 /* Copy the diagonal P (N doubles, host) of the active preconditioner. */
 wdb_status wdb_get_precond(const wdb_theta* th, double* p_out);
 
@@ -200,6 +221,31 @@ wdb_status wdb_solve(wdb_theta* th, const float* u, float lambda, const wdb_solv
 wdb_status wdb_solve_coeffs(wdb_theta* th, const float* x0, float lambda,
                             const wdb_solve_opts* opts, float* x_out, wdb_solve_info* info);
 
+/* One problem of a batched solve. */
+typedef struct {
+  wdb_theta* theta;      /* operator; problems may share one                 */
+  const float* u;        /* device, n*n blurred image                        */
+  float lambda;
+  const float* x_init;   /* device, N coefficients, or NULL for x = 0         */
+  float* x_out;          /* device, N coefficients (written at the end)      */
+} wdb_problem;
+
+/* Solve many problems in one call (Alg. 1 for each).  Problems sharing a
+ * handle are packed eight at a time so each iteration reads every stored
+ * entry of Theta_K once for eight right-hand sides; all packs of all
+ * operators run in one launch per phase (two launches per iteration for the
+ * whole batch), replayed from a HIP graph between float64 checks when
+ * opts->use_graph is set.  opts is shared (its x_init must be NULL; use the
+ * per-problem x_init), each problem has its own lambda, step 1/L of its
+ * handle (computed on first use if absent), and its own stop flag: with
+ * tol_rel_gap > 0 a problem stops updating at the first check where its gap
+ * is below tolerance.  infos (optional) receives nprob entries.  Handles must
+ * hold float32 values.  Synchronises at each check.  Errors: as wdb_solve;
+ * WDB_ERR_NOT_CONVERGED if any problem missed the tolerance (all outputs are
+ * still written). */
+wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs, const wdb_solve_opts* opts,
+                             wdb_solve_info* infos);
+
 /* Float64 objective E(x) and relative duality gap for coefficients x and data
  * x0 (device arrays of N float32).  With r = Theta_K x - x0,
  * s = min(1, lambda / ||Theta_K^T r||_inf): D = -s^2||r||^2/2 - s<r, x0>,
@@ -214,7 +260,12 @@ wdb_status wdb_objective(wdb_theta* th, const float* x, const float* x0, float l
 wdb_status wdb_theta_apply(wdb_theta* th, int32_t transpose, const float* x, const float* b,
                            float* y, int32_t repeat, void* stream);
 
-/* One fused proximal-gradient step (Alg. 1, steps 3-4) given the residual r:
+/* With 16-bit values set (wdb_set_precision), transpose = 0 uses them
+ * (y = Theta~_K x - b with the dequantised values); transpose = 1 is refused
+ * (WDB_ERR_ARG) in that mode. */
+
+/* One fused proximal-gradient step (Alg. 1, steps 3-4) given the residual r
+ * (float32 values only: WDB_ERR_ARG when 16-bit values are set):
  * g = Theta_K^T r; z = y - tau * g / P; x_new = S_{tau*lambda/P}(z);
  * y = x_new + beta (x_new - x); x = x_new  (P = 1 unless use_precond). */
 wdb_status wdb_prox_step(wdb_theta* th, const float* r, float* x, float* y, float tau,

@@ -113,6 +113,7 @@ wdb_status wdb_theta_info(const wdb_theta* th, wdb_theta_desc* out) {
   out->threshold = th->threshold;
   out->lipschitz_p = th->Lp;
   out->precond = th->precond;
+  out->valtype = th->valtype;
   WDB_API_END
 }
 
@@ -139,6 +140,9 @@ void wdb_theta_free(wdb_theta* th) {
   th->At.free_all();
   th->cA.free_all();
   th->cAt.free_all();
+  if (th->val16) (void)hipFree(th->val16);
+  if (th->val16T) (void)hipFree(th->val16T);
+  if (th->wrow) (void)hipFree(th->wrow);
   wdb::free_workspace(th);
   delete th;
 }

@@ -1,0 +1,498 @@
+// Batched solve: many deblurring problems (Alg. 1 each) in one call.
+//
+// Problems that share an operator handle are packed eight at a time into a
+// "chunk": their vectors are stored row-interleaved ([N][8] floats), so one
+// pass over Theta_K's sliced-ELL slots serves all eight right-hand sides (a
+// sparse-times-dense product): each stored entry is read once and its column
+// gathers 32 contiguous bytes (two 16-byte loads).  All chunks of all
+// operators run in one launch per phase -- the residual kernel, then the
+// transposed kernel with the soft-threshold and momentum epilogue -- so an
+// iteration of the whole batch is two launches, and the iterations between
+// float64 checks can be replayed from a captured HIP graph.  Each right-hand
+// side has its own lambda and its own stop flag (a converged problem keeps
+// its iterate while the others continue).
+#include <cmath>
+#include <map>
+
+#include "common.hpp"
+
+namespace wdb {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kSPB = kBlock / kSlice;  // slices per block
+constexpr int kR = 8;                  // right-hand sides per chunk
+
+struct ChunkDev {
+  const int64_t* soff;
+  const float4* val;
+  const int4* col;
+  const int32_t* perm;
+  int64_t nslices, nrows;
+  const int64_t* soffT;
+  const float4* valT;
+  const int4* colT;
+  const int32_t* permT;
+  int64_t nslicesT;
+  float* X;          // [N][8] iterate
+  float* Y;          // [N][8] extrapolated point
+  const float* X0;   // [N][8] data
+  float* Rr;         // [N][8] residual
+  const float* pinv; // N or null
+  float tau;
+  float thr[kR];     // tau * lambda_j
+  const int* act;    // stop flags (1 = keep iterating), written by the host between replays
+  double* r64;       // [N][8] float64 residual for the checks
+};
+
+__device__ __forceinline__ int chunk_of(const int* __restrict__ first, int nchunks, int blk) {
+  int c = 0;
+  while (c + 1 < nchunks && blk >= first[c + 1]) ++c;
+  return c;
+}
+
+__device__ __forceinline__ int64_t slot_row_c(const int32_t* perm, int64_t nrows, int64_t q) {
+  if (perm) return perm[q];
+  return q < nrows ? q : -1;
+}
+
+__device__ __forceinline__ void gather8(const float* __restrict__ V, int c, float w, float (&acc)[kR]) {
+  const float4* p = reinterpret_cast<const float4*>(V + static_cast<int64_t>(c) * kR);
+  const float4 a = p[0], b = p[1];
+  acc[0] = fmaf(w, a.x, acc[0]);
+  acc[1] = fmaf(w, a.y, acc[1]);
+  acc[2] = fmaf(w, a.z, acc[2]);
+  acc[3] = fmaf(w, a.w, acc[3]);
+  acc[4] = fmaf(w, b.x, acc[4]);
+  acc[5] = fmaf(w, b.y, acc[5]);
+  acc[6] = fmaf(w, b.z, acc[6]);
+  acc[7] = fmaf(w, b.w, acc[7]);
+}
+
+__device__ __forceinline__ void slice_mm(const int64_t* __restrict__ soff, const float4* __restrict__ val,
+                                         const int4* __restrict__ col, int64_t sl, int lane,
+                                         const float* __restrict__ V, float (&acc)[kR]) {
+  const int64_t beg = soff[sl] >> 2, end = soff[sl + 1] >> 2;
+  for (int64_t j = beg + lane; j < end; j += kSlice) {
+    const float4 v = val[j];
+    const int4 c = col[j];
+    gather8(V, c.x, v.x, acc);
+    gather8(V, c.y, v.y, acc);
+    gather8(V, c.z, v.z, acc);
+    gather8(V, c.w, v.w, acc);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_res_batched(const ChunkDev* __restrict__ ch, const int* __restrict__ first,
+                                                        int nchunks, int* __restrict__ kdev) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *kdev += 1;
+  const int c = chunk_of(first, nchunks, blockIdx.x);
+  const ChunkDev& C = ch[c];
+  const int lane = threadIdx.x & (kSlice - 1);
+  const int64_t sl = static_cast<int64_t>(blockIdx.x - first[c]) * kSPB + threadIdx.x / kSlice;
+  if (sl >= C.nslices) return;
+  float acc[kR] = {0, 0, 0, 0, 0, 0, 0, 0};
+  slice_mm(C.soff, C.val, C.col, sl, lane, C.Y, acc);
+  const int64_t row = slot_row_c(C.perm, C.nrows, sl * kSlice + lane);
+  if (row < 0) return;
+  const float4* b = reinterpret_cast<const float4*>(C.X0 + row * kR);
+  float4* r = reinterpret_cast<float4*>(C.Rr + row * kR);
+  const float4 b0 = b[0], b1 = b[1];
+  r[0] = make_float4(acc[0] - b0.x, acc[1] - b0.y, acc[2] - b0.z, acc[3] - b0.w);
+  r[1] = make_float4(acc[4] - b1.x, acc[5] - b1.y, acc[6] - b1.z, acc[7] - b1.w);
+}
+
+__global__ __launch_bounds__(kBlock) void k_prox_batched(const ChunkDev* __restrict__ ch, const int* __restrict__ first,
+                                                         int nchunks, const int* __restrict__ kdev) {
+  const int c = chunk_of(first, nchunks, blockIdx.x);
+  const ChunkDev& C = ch[c];
+  const int lane = threadIdx.x & (kSlice - 1);
+  const int64_t sl = static_cast<int64_t>(blockIdx.x - first[c]) * kSPB + threadIdx.x / kSlice;
+  if (sl >= C.nslicesT) return;
+  float g[kR] = {0, 0, 0, 0, 0, 0, 0, 0};
+  slice_mm(C.soffT, C.valT, C.colT, sl, lane, C.Rr, g);
+  const int64_t row = slot_row_c(C.permT, C.nrows, sl * kSlice + lane);
+  if (row < 0) return;
+  const int k = *kdev;
+  const float beta = static_cast<float>((static_cast<double>(k) - 1.0) / (static_cast<double>(k) + 2.0));
+  const float pi = C.pinv ? C.pinv[row] : 1.0f;
+  float* X = C.X + row * kR;
+  float* Y = C.Y + row * kR;
+#pragma unroll
+  for (int j = 0; j < kR; ++j) {
+    if (!C.act[j]) continue;
+    const float z = Y[j] - (C.tau * pi) * g[j];
+    const float t = C.thr[j] * pi;
+    const float xn = copysignf(fmaxf(fabsf(z) - t, 0.0f), z);
+    const float xo = X[j];
+    X[j] = xn;
+    Y[j] = xn + beta * (xn - xo);
+  }
+}
+
+// float64 checks: per right-hand side sums of r^2, r.x0, |x| (forward) and
+// max |A^T r| (backward); partial[(v * kR + j) * nblocks + block].
+__device__ __forceinline__ void block_reduce8(double (&v)[kR], bool is_max, double* __restrict__ out) {
+  __shared__ double sh[kSPB][kR];
+  const int lane = threadIdx.x & (kSlice - 1), wid = threadIdx.x / kSlice;
+#pragma unroll
+  for (int j = 0; j < kR; ++j) {
+    double x = v[j];
+    for (int off = kSlice / 2; off > 0; off >>= 1) {
+      const double y = __shfl_xor(x, off);
+      x = is_max ? fmax(x, y) : x + y;
+    }
+    if (lane == 0) sh[wid][j] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < kR) {
+    double a = sh[0][threadIdx.x];
+    for (int w = 1; w < kSPB; ++w) a = is_max ? fmax(a, sh[w][threadIdx.x]) : a + sh[w][threadIdx.x];
+    out[threadIdx.x] = a;
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kBlock) void k_check_fwd(const ChunkDev* __restrict__ ch, const int* __restrict__ first,
+                                                      int nchunks, double* __restrict__ part, int64_t nblocks) {
+  const int c = chunk_of(first, nchunks, blockIdx.x);
+  const ChunkDev& C = ch[c];
+  const int lane = threadIdx.x & (kSlice - 1);
+  const int64_t sl = static_cast<int64_t>(blockIdx.x - first[c]) * kSPB + threadIdx.x / kSlice;
+  double a[kR], rr[kR], rb[kR], l1[kR];
+  for (int j = 0; j < kR; ++j) a[j] = rr[j] = rb[j] = l1[j] = 0.0;
+  int64_t row = -1;
+  if (sl < C.nslices) {
+    const int64_t beg = C.soff[sl] >> 2, end = C.soff[sl + 1] >> 2;
+    for (int64_t jj = beg + lane; jj < end; jj += kSlice) {
+      const float4 v = C.val[jj];
+      const int4 cc = C.col[jj];
+      const float vv[4] = {v.x, v.y, v.z, v.w};
+      const int ci[4] = {cc.x, cc.y, cc.z, cc.w};
+      for (int t = 0; t < 4; ++t)
+        for (int j = 0; j < kR; ++j)
+          a[j] = fma(static_cast<double>(vv[t]), static_cast<double>(C.X[static_cast<int64_t>(ci[t]) * kR + j]), a[j]);
+    }
+    row = slot_row_c(C.perm, C.nrows, sl * kSlice + lane);
+  }
+  if (row >= 0) {
+    for (int j = 0; j < kR; ++j) {
+      const double b = static_cast<double>(C.X0[row * kR + j]);
+      const double r = a[j] - b;
+      C.r64[row * kR + j] = r;
+      rr[j] = r * r;
+      rb[j] = r * b;
+      l1[j] = fabs(static_cast<double>(C.X[row * kR + j]));
+    }
+  }
+  double out[kR];
+  block_reduce8(rr, false, out);
+  if (threadIdx.x < kR) part[(0 * kR + threadIdx.x) * nblocks + blockIdx.x] = out[threadIdx.x];
+  block_reduce8(rb, false, out);
+  if (threadIdx.x < kR) part[(1 * kR + threadIdx.x) * nblocks + blockIdx.x] = out[threadIdx.x];
+  block_reduce8(l1, false, out);
+  if (threadIdx.x < kR) part[(2 * kR + threadIdx.x) * nblocks + blockIdx.x] = out[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kBlock) void k_check_bwd(const ChunkDev* __restrict__ ch, const int* __restrict__ first,
+                                                      int nchunks, double* __restrict__ part, int64_t nblocks) {
+  const int c = chunk_of(first, nchunks, blockIdx.x);
+  const ChunkDev& C = ch[c];
+  const int lane = threadIdx.x & (kSlice - 1);
+  const int64_t sl = static_cast<int64_t>(blockIdx.x - first[c]) * kSPB + threadIdx.x / kSlice;
+  double g[kR];
+  for (int j = 0; j < kR; ++j) g[j] = 0.0;
+  if (sl < C.nslicesT) {
+    const int64_t beg = C.soffT[sl] >> 2, end = C.soffT[sl + 1] >> 2;
+    for (int64_t jj = beg + lane; jj < end; jj += kSlice) {
+      const float4 v = C.valT[jj];
+      const int4 cc = C.colT[jj];
+      const float vv[4] = {v.x, v.y, v.z, v.w};
+      const int ci[4] = {cc.x, cc.y, cc.z, cc.w};
+      for (int t = 0; t < 4; ++t)
+        for (int j = 0; j < kR; ++j) g[j] = fma(static_cast<double>(vv[t]), C.r64[static_cast<int64_t>(ci[t]) * kR + j], g[j]);
+    }
+    if (slot_row_c(C.permT, C.nrows, sl * kSlice + lane) < 0)
+      for (int j = 0; j < kR; ++j) g[j] = 0.0;
+  }
+  for (int j = 0; j < kR; ++j) g[j] = fabs(g[j]);
+  double out[kR];
+  block_reduce8(g, true, out);
+  if (threadIdx.x < kR) part[(3 * kR + threadIdx.x) * nblocks + blockIdx.x] = out[threadIdx.x];
+}
+
+// One block per chunk: reduce that chunk's block range for 4 x 8 values.
+__global__ __launch_bounds__(kBlock) void k_check_reduce(const int* __restrict__ first, const double* __restrict__ part,
+                                                         int64_t nblocks, double* __restrict__ out) {
+  __shared__ double sh[kBlock];
+  const int c = blockIdx.x;
+  const int b0 = first[c], b1 = first[c + 1];
+  for (int v = 0; v < 4 * kR; ++v) {
+    const bool mx = v >= 3 * kR;
+    double acc = 0.0;
+    for (int b = b0 + threadIdx.x; b < b1; b += kBlock) {
+      const double p = part[static_cast<int64_t>(v) * nblocks + b];
+      acc = mx ? fmax(acc, p) : acc + p;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w) sh[threadIdx.x] = mx ? fmax(sh[threadIdx.x], sh[threadIdx.x + w]) : sh[threadIdx.x] + sh[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[c * 4 * kR + v] = sh[0];
+    __syncthreads();
+  }
+}
+
+__global__ void k_interleave(const float* __restrict__ src, float* __restrict__ dst, int64_t N, int j) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < N) dst[i * kR + j] = src ? src[i] : 0.0f;
+}
+
+__global__ void k_deinterleave(const float* __restrict__ src, float* __restrict__ dst, int64_t N, int j) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < N) dst[i] = src[i * kR + j];
+}
+
+__global__ void k_set(int* p, int v) { *p = v; }
+
+}  // namespace
+
+}  // namespace wdb
+
+extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs, const wdb_solve_opts* opts,
+                                        wdb_solve_info* infos) {
+  using namespace wdb;
+  WDB_API_BEGIN
+  WDB_REQUIRE(nprob >= 1 && probs && opts, WDB_ERR_ARG, "need at least one problem and options");
+  WDB_REQUIRE(opts->max_iters >= 0 && opts->check_every >= 0, WDB_ERR_ARG, "bad iteration counts");
+  WDB_REQUIRE(opts->x_init == nullptr, WDB_ERR_ARG, "x_init is per problem in a batch (wdb_problem.x_init)");
+  const bool pre = opts->use_precond != 0;
+  hipStream_t s = static_cast<hipStream_t>(opts->stream);
+  // group by operator, in first-seen order, then split into chunks of 8
+  std::vector<wdb_theta*> order;
+  std::map<wdb_theta*, std::vector<int>> members;
+  for (int i = 0; i < nprob; ++i) {
+    const wdb_problem& p = probs[i];
+    WDB_REQUIRE(p.theta && p.u && p.x_out, WDB_ERR_ARG, "problem %d has a null pointer", i);
+    WDB_REQUIRE(std::isfinite(p.lambda) && p.lambda >= 0.0f, WDB_ERR_NONFINITE, "problem %d: bad lambda", i);
+    WDB_REQUIRE(p.theta->valtype == WDB_VAL_F32, WDB_ERR_ARG, "batched solve uses float32 values");
+    WDB_REQUIRE(!pre || p.theta->precond != 0, WDB_ERR_ARG, "problem %d: no preconditioner set", i);
+    if (!members.count(p.theta)) order.push_back(p.theta);
+    members[p.theta].push_back(i);
+  }
+  struct Host {
+    wdb_theta* th;
+    std::vector<int> idx;
+    DevBuf<float> X, Y, X0, Rr;
+    DevBuf<double> r64;
+    DevBuf<int> act;
+    int blocks_res, blocks_prox, blocks;
+  };
+  std::vector<Host> chunks;
+  for (wdb_theta* th : order) {
+    WDB_HIP(hipSetDevice(th->device));
+    ensure_workspace(th);
+    if (!th->has_L) {
+      int it = 0;
+      th->L = power_iteration(th, nullptr, nullptr, 1e-12, 20000, &it, s);
+      th->has_L = true;
+    }
+    const std::vector<int>& m = members[th];
+    for (size_t b = 0; b < m.size(); b += kR) {
+      Host h;
+      h.th = th;
+      h.idx.assign(m.begin() + b, m.begin() + std::min(m.size(), b + kR));
+      const int64_t N = th->N;
+      h.X.alloc(N * kR);
+      h.Y.alloc(N * kR);
+      h.X0.alloc(N * kR);
+      h.Rr.alloc(N * kR);
+      h.r64.alloc(N * kR);
+      h.act.alloc(kR);
+      h.blocks_res = static_cast<int>((th->A.nslices + kSPB - 1) / kSPB);
+      h.blocks_prox = static_cast<int>((th->At.nslices + kSPB - 1) / kSPB);
+      h.blocks = std::max(h.blocks_res, h.blocks_prox);
+      chunks.push_back(std::move(h));
+    }
+  }
+  const int nch = static_cast<int>(chunks.size());
+  std::vector<ChunkDev> hd(nch);
+  std::vector<int> first(nch + 1, 0);
+  for (int c = 0; c < nch; ++c) first[c + 1] = first[c] + chunks[c].blocks;
+  const int64_t nblocks = first[nch];
+  DevBuf<ChunkDev> dch(nch);
+  DevBuf<int> dfirst(nch + 1);
+  DevBuf<double> part(static_cast<size_t>(4 * kR) * nblocks), red(static_cast<size_t>(nch) * 4 * kR);
+  DevBuf<int> kdev(1);
+  std::vector<float> tmp;
+  for (int c = 0; c < nch; ++c) {
+    Host& h = chunks[c];
+    wdb_theta* th = h.th;
+    const int64_t N = th->N;
+    const double L = pre ? th->Lp : th->L;
+    WDB_REQUIRE(L > 0.0 && std::isfinite(L), WDB_ERR_ARG, "operator has no positive Lipschitz constant");
+    const double tau = 1.0 / L;
+    ChunkDev& d = hd[c];
+    d.soff = th->A.slice_off;
+    d.val = reinterpret_cast<const float4*>(th->A.val);
+    d.col = reinterpret_cast<const int4*>(th->A.col);
+    d.perm = th->A.perm;
+    d.nslices = th->A.nslices;
+    d.nrows = N;
+    d.soffT = th->At.slice_off;
+    d.valT = reinterpret_cast<const float4*>(th->At.val);
+    d.colT = reinterpret_cast<const int4*>(th->At.col);
+    d.permT = th->At.perm;
+    d.nslicesT = th->At.nslices;
+    d.X = h.X.p;
+    d.Y = h.Y.p;
+    d.X0 = h.X0.p;
+    d.Rr = h.Rr.p;
+    d.pinv = pre ? th->pinv : nullptr;
+    d.tau = static_cast<float>(tau);
+    d.act = h.act.p;
+    d.r64 = h.r64.p;
+    const Filter f = make_filter(th->wavelet);
+    const size_t q = static_cast<size_t>(th->n / 2) * (th->n / 2);
+    std::vector<int> act(kR, 0);
+    for (int j = 0; j < kR; ++j) {
+      d.thr[j] = 0.0f;
+      if (j < static_cast<int>(h.idx.size())) {
+        const wdb_problem& p = probs[h.idx[j]];
+        d.thr[j] = static_cast<float>(tau * static_cast<double>(p.lambda));
+        act[j] = 1;
+        dwt_forward(th->n, th->levels, f, p.u, th->ws_x0, th->ws_img, th->ws_img + q, s);
+        hipLaunchKernelGGL(k_interleave, dim3((N + 255) / 256), dim3(256), 0, s, th->ws_x0, h.X0.p, N, j);
+        hipLaunchKernelGGL(k_interleave, dim3((N + 255) / 256), dim3(256), 0, s, p.x_init, h.X.p, N, j);
+        hipLaunchKernelGGL(k_interleave, dim3((N + 255) / 256), dim3(256), 0, s, p.x_init, h.Y.p, N, j);
+      } else {
+        hipLaunchKernelGGL(k_interleave, dim3((N + 255) / 256), dim3(256), 0, s, static_cast<const float*>(nullptr),
+                           h.X0.p, N, j);
+        hipLaunchKernelGGL(k_interleave, dim3((N + 255) / 256), dim3(256), 0, s, static_cast<const float*>(nullptr),
+                           h.X.p, N, j);
+        hipLaunchKernelGGL(k_interleave, dim3((N + 255) / 256), dim3(256), 0, s, static_cast<const float*>(nullptr),
+                           h.Y.p, N, j);
+      }
+    }
+    WDB_HIP(hipGetLastError());
+    WDB_HIP(hipMemcpyAsync(h.act.p, act.data(), kR * sizeof(int), hipMemcpyHostToDevice, s));
+  }
+  WDB_HIP(hipMemcpyAsync(dch.p, hd.data(), nch * sizeof(ChunkDev), hipMemcpyHostToDevice, s));
+  WDB_HIP(hipMemcpyAsync(dfirst.p, first.data(), (nch + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+  const int k0 = opts->k0 > 0 ? opts->k0 : 1;
+  hipLaunchKernelGGL(k_set, dim3(1), dim3(1), 0, s, kdev.p, k0 - 1);
+
+  auto iterate = [&](hipStream_t st) {
+    hipLaunchKernelGGL(k_res_batched, dim3(static_cast<unsigned>(nblocks)), dim3(kBlock), 0, st, dch.p, dfirst.p, nch,
+                       kdev.p);
+    hipLaunchKernelGGL(k_prox_batched, dim3(static_cast<unsigned>(nblocks)), dim3(kBlock), 0, st, dch.p, dfirst.p,
+                       nch, kdev.p);
+  };
+  const int c = opts->check_every;
+  const int total = opts->max_iters;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap = nullptr;
+  std::vector<double> hred(static_cast<size_t>(nch) * 4 * kR);
+  std::vector<double> lastE(nprob, 0.0), lastG(nprob, 0.0);
+  std::vector<int> done_at(nprob, -1);
+  int done = 0, checks = 0;
+  bool all_conv = false;
+  try {
+    if (opts->use_graph && c > 1 && total >= c) {
+      WDB_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+      WDB_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+      for (int i = 0; i < c; ++i) iterate(cap);
+      WDB_HIP(hipStreamEndCapture(cap, &graph));
+      WDB_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    }
+    while (done < total || (total == 0 && checks == 0)) {
+      int step = total - done;
+      if (c > 0) step = std::min(step, c - (done % c));
+      if (exec && step == c) {
+        WDB_HIP(hipGraphLaunch(exec, s));
+      } else {
+        for (int i = 0; i < step; ++i) iterate(s);
+      }
+      WDB_HIP(hipGetLastError());
+      done += step;
+      const bool at_check = (c > 0 && done % c == 0) || done == total;
+      if (!at_check) continue;
+      hipLaunchKernelGGL(k_check_fwd, dim3(static_cast<unsigned>(nblocks)), dim3(kBlock), 0, s, dch.p, dfirst.p, nch,
+                         part.p, nblocks);
+      hipLaunchKernelGGL(k_check_bwd, dim3(static_cast<unsigned>(nblocks)), dim3(kBlock), 0, s, dch.p, dfirst.p, nch,
+                         part.p, nblocks);
+      hipLaunchKernelGGL(k_check_reduce, dim3(nch), dim3(kBlock), 0, s, dfirst.p, part.p, nblocks, red.p);
+      WDB_HIP(hipGetLastError());
+      WDB_HIP(hipMemcpyAsync(hred.data(), red.p, hred.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      WDB_HIP(hipStreamSynchronize(s));
+      ++checks;
+      bool any_active = false;
+      for (int ci = 0; ci < nch; ++ci) {
+        Host& h = chunks[ci];
+        std::vector<int> act(kR, 0);
+        bool changed = false;
+        for (int j = 0; j < static_cast<int>(h.idx.size()); ++j) {
+          const int pi = h.idx[j];
+          if (done_at[pi] >= 0) continue;  // already stopped
+          const double lam = static_cast<double>(probs[pi].lambda);
+          const double rr = hred[ci * 4 * kR + 0 * kR + j], rb = hred[ci * 4 * kR + 1 * kR + j];
+          const double l1 = hred[ci * 4 * kR + 2 * kR + j], gm = hred[ci * 4 * kR + 3 * kR + j];
+          const double E = 0.5 * rr + lam * l1;
+          const double sc = gm <= lam ? 1.0 : lam / gm;
+          const double D = -0.5 * sc * sc * rr - sc * rb;
+          lastE[pi] = E;
+          lastG[pi] = E > 0 ? (E - D) / E : 0.0;
+          WDB_REQUIRE(std::isfinite(E), WDB_ERR_DIVERGED, "problem %d diverged", pi);
+          if (opts->tol_rel_gap > 0 && lastG[pi] <= opts->tol_rel_gap) {
+            done_at[pi] = done;
+            changed = true;
+          }
+        }
+        for (int j = 0; j < static_cast<int>(h.idx.size()); ++j) {
+          act[j] = done_at[h.idx[j]] < 0 ? 1 : 0;
+          any_active |= act[j] != 0;
+        }
+        if (changed) WDB_HIP(hipMemcpyAsync(h.act.p, act.data(), kR * sizeof(int), hipMemcpyHostToDevice, s));
+      }
+      if (opts->tol_rel_gap > 0 && !any_active) {
+        all_conv = true;
+        break;
+      }
+    }
+  } catch (...) {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+    throw;
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (cap) (void)hipStreamDestroy(cap);
+  for (int ci = 0; ci < nch; ++ci) {
+    Host& h = chunks[ci];
+    const int64_t N = h.th->N;
+    for (int j = 0; j < static_cast<int>(h.idx.size()); ++j)
+      hipLaunchKernelGGL(k_deinterleave, dim3((N + 255) / 256), dim3(256), 0, s, h.X.p, probs[h.idx[j]].x_out, N, j);
+  }
+  WDB_HIP(hipGetLastError());
+  WDB_HIP(hipStreamSynchronize(s));
+  if (infos) {
+    for (int i = 0; i < nprob; ++i) {
+      wdb_theta* th = probs[i].theta;
+      infos[i].iters = done_at[i] >= 0 ? done_at[i] : done;
+      infos[i].checks = checks;
+      infos[i].objective = lastE[i];
+      infos[i].rel_gap = lastG[i];
+      infos[i].lipschitz = pre ? th->Lp : th->L;
+      infos[i].tau = 1.0 / infos[i].lipschitz;
+    }
+  }
+  if (opts->tol_rel_gap > 0 && !all_conv)
+    fail(WDB_ERR_NOT_CONVERGED, "not every problem reached relative gap %.3e in %d iterations", opts->tol_rel_gap,
+         done);
+  WDB_API_END
+}

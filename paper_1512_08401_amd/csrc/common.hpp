@@ -172,6 +172,12 @@ struct wdb_theta {
   wdb::Sell A;         // Theta_K   (rows = output coefficient)
   wdb::Sell At;        // Theta_K^T (rows = input coefficient)
   wdb::Csr32 cA, cAt;  // float32 CSR of Theta_K and Theta_K^T
+  // 16-bit iteration values (same slots as A / At) and per-row dequantisation
+  // factors (a power of two per row subband); valtype 0 = float32 iteration.
+  int valtype = 0;
+  uint16_t* val16 = nullptr;
+  uint16_t* val16T = nullptr;
+  float* wrow = nullptr;
   bool has_L = false;
   double L = 0.0;
   int precond = 0;

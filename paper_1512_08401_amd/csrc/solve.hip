@@ -153,6 +153,89 @@ __global__ __launch_bounds__(kBlock) void k_prox(SellView At, const float* __res
 }
 
 // ---------------------------------------------------------------------------
+// 16-bit value variants (mixed precision): the same slots and indices, values
+// as binary16 / bfloat16 (four per 8-byte lane load), float32 accumulation.
+// Row sums are multiplied by the row's power-of-two factor w (exact).
+// ---------------------------------------------------------------------------
+template <int FMT>
+__device__ __forceinline__ float dq16(uint32_t h) {
+  if constexpr (FMT == WDB_VAL_BF16) return __uint_as_float(h << 16);
+  else return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(h)));
+}
+
+template <int FMT>
+__device__ __forceinline__ float row_dot_q(const SellView& A, const uint2* __restrict__ v16, int64_t sl, int lane,
+                                           const float* __restrict__ x) {
+  const int64_t beg = A.soff[sl] >> 2, end = A.soff[sl + 1] >> 2;
+  float acc = 0.f;
+#pragma unroll 2
+  for (int64_t j = beg + lane; j < end; j += kSlice) {
+    const uint2 v = v16[j];
+    const int4 c = A.col[j];
+    acc = fmaf(dq16<FMT>(v.x & 0xFFFFu), x[c.x], acc);
+    acc = fmaf(dq16<FMT>(v.x >> 16), x[c.y], acc);
+    acc = fmaf(dq16<FMT>(v.y & 0xFFFFu), x[c.z], acc);
+    acc = fmaf(dq16<FMT>(v.y >> 16), x[c.w], acc);
+  }
+  return acc;
+}
+
+// r = w * (Q y) - b; stores w * r when scale_out (input of the transposed kernel).
+template <int FMT>
+__global__ __launch_bounds__(kBlock) void k_res_q(SellView A, const uint2* __restrict__ v16,
+                                                  const float* __restrict__ wrow, const float* __restrict__ y,
+                                                  const float* __restrict__ b, float* __restrict__ r,
+                                                  int* __restrict__ kdev, int scale_out) {
+  if (kdev && blockIdx.x == 0 && threadIdx.x == 0) *kdev += 1;
+  const int lane = threadIdx.x & (kSlice - 1);
+  const int64_t sl = static_cast<int64_t>(blockIdx.x) * kSlicesPerBlock + threadIdx.x / kSlice;
+  if (sl >= A.nslices) return;
+  const float acc = row_dot_q<FMT>(A, v16, sl, lane, y);
+  const int64_t row = slot_row(A, sl, lane);
+  if (row < 0) return;
+  const float w = wrow[row];
+  const float rr = b ? w * acc - b[row] : w * acc;
+  r[row] = scale_out ? rr * w : rr;
+}
+
+template <int FMT, bool PRE>
+__global__ __launch_bounds__(kBlock) void k_prox_q(SellView At, const uint2* __restrict__ v16T,
+                                                   const float* __restrict__ rs, float* __restrict__ x,
+                                                   float* __restrict__ y, float tau, float thr,
+                                                   const int* __restrict__ kdev, const float* __restrict__ pinv) {
+  const int lane = threadIdx.x & (kSlice - 1);
+  const int64_t sl = static_cast<int64_t>(blockIdx.x) * kSlicesPerBlock + threadIdx.x / kSlice;
+  if (sl >= At.nslices) return;
+  const float g = row_dot_q<FMT>(At, v16T, sl, lane, rs);
+  const int64_t row = slot_row(At, sl, lane);
+  if (row < 0) return;
+  const int k = *kdev;
+  const float beta = static_cast<float>((static_cast<double>(k) - 1.0) / (static_cast<double>(k) + 2.0));
+  const float pi = PRE ? pinv[row] : 1.0f;
+  const float z = y[row] - (tau * pi) * g;
+  const float t = thr * pi;
+  const float xn = copysignf(fmaxf(fabsf(z) - t, 0.0f), z);
+  const float xo = x[row];
+  x[row] = xn;
+  y[row] = xn + beta * (xn - xo);
+}
+
+template <int FMT>
+void launch_iteration_q(wdb_theta* th, float* x, bool pre, float tau, float thr, hipStream_t s) {
+  const SellView A = view(th->A), At = view(th->At);
+  const uint2* v16 = reinterpret_cast<const uint2*>(th->val16);
+  const uint2* v16T = reinterpret_cast<const uint2*>(th->val16T);
+  hipLaunchKernelGGL(k_res_q<FMT>, slice_grid(A.nslices), dim3(kBlock), 0, s, A, v16, th->wrow, th->ws_y,
+                     th->ws_x0, th->ws_r, th->ws_k, 1);
+  if (pre)
+    hipLaunchKernelGGL((k_prox_q<FMT, true>), slice_grid(At.nslices), dim3(kBlock), 0, s, At, v16T, th->ws_r, x,
+                       th->ws_y, tau, thr, th->ws_k, th->pinv);
+  else
+    hipLaunchKernelGGL((k_prox_q<FMT, false>), slice_grid(At.nslices), dim3(kBlock), 0, s, At, v16T, th->ws_r, x,
+                       th->ws_y, tau, thr, th->ws_k, static_cast<const float*>(nullptr));
+}
+
+// ---------------------------------------------------------------------------
 // Vector-CSR variants: G consecutive lanes share one row and read its
 // consecutive entries (whose columns are spatial neighbours), then reduce with
 // a fixed butterfly inside the group.
@@ -529,6 +612,8 @@ Check objective_check(wdb_theta* th, const float* x, const float* x0, double lam
 }
 
 void launch_iteration(wdb_theta* th, float* x, bool pre, float tau, float thr, hipStream_t s) {
+  if (th->valtype == WDB_VAL_BF16) return launch_iteration_q<WDB_VAL_BF16>(th, x, pre, tau, thr, s);
+  if (th->valtype == WDB_VAL_F16) return launch_iteration_q<WDB_VAL_F16>(th, x, pre, tau, thr, s);
   launch_res(th->A, th->cA, th->ws_y, th->ws_x0, th->ws_r, th->ws_k, s);
   launch_prox(th->At, th->cAt, th->ws_r, x, th->ws_y, tau, thr, 0.0f, th->ws_k, pre ? th->pinv : nullptr, s);
 }
@@ -698,6 +783,21 @@ wdb_status wdb_theta_apply(wdb_theta* th, int32_t transpose, const float* x, con
   WDB_REQUIRE(repeat >= 1, WDB_ERR_ARG, "repeat must be >= 1");
   WDB_HIP(hipSetDevice(th->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (th->valtype != WDB_VAL_F32) {
+    WDB_REQUIRE(!transpose, WDB_ERR_ARG, "transposed apply is not available with 16-bit values");
+    const wdb::SellView A = wdb::view(th->A);
+    const uint2* v16 = reinterpret_cast<const uint2*>(th->val16);
+    for (int i = 0; i < repeat; ++i) {
+      if (th->valtype == WDB_VAL_BF16)
+        hipLaunchKernelGGL(wdb::k_res_q<WDB_VAL_BF16>, wdb::slice_grid(A.nslices), dim3(wdb::kBlock), 0, s, A, v16,
+                           th->wrow, x, b, y, static_cast<int*>(nullptr), 0);
+      else
+        hipLaunchKernelGGL(wdb::k_res_q<WDB_VAL_F16>, wdb::slice_grid(A.nslices), dim3(wdb::kBlock), 0, s, A, v16,
+                           th->wrow, x, b, y, static_cast<int*>(nullptr), 0);
+    }
+    WDB_HIP(hipGetLastError());
+    return WDB_OK;
+  }
   for (int i = 0; i < repeat; ++i)
     wdb::launch_res(transpose ? th->At : th->A, transpose ? th->cAt : th->cA, x, b, y, nullptr, s);
   WDB_HIP(hipGetLastError());
@@ -709,6 +809,7 @@ wdb_status wdb_prox_step(wdb_theta* th, const float* r, float* x, float* y, floa
   WDB_API_BEGIN
   WDB_REQUIRE(th && r && x && y, WDB_ERR_ARG, "null argument");
   WDB_REQUIRE(!use_precond || th->pinv, WDB_ERR_ARG, "no preconditioner set on this operator");
+  WDB_REQUIRE(th->valtype == WDB_VAL_F32, WDB_ERR_ARG, "prox_step needs float32 values");
   WDB_HIP(hipSetDevice(th->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
   const float thr = tau * lambda;

@@ -22,6 +22,7 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 WAVELETS = {"haar": 0, "db4": 1}
+VALTYPES = {"f32": 0, "bf16": 1, "f16": 2}
 PRECOND = {"none": 0, "spai": 1, "spai_scale": 2, "jacobi": 3}
 
 WDB_OK = 0
@@ -46,7 +47,7 @@ class ThetaDesc(C.Structure):
     _fields_ = [("n", C.c_int32), ("levels", C.c_int32), ("wavelet", C.c_int32),
                 ("has_lipschitz", C.c_int32), ("nnz", C.c_int64), ("stored", C.c_int64),
                 ("lipschitz", C.c_double), ("threshold", C.c_double), ("lipschitz_p", C.c_double),
-                ("precond", C.c_int32), ("pad_", C.c_int32)]
+                ("precond", C.c_int32), ("valtype", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -54,6 +55,11 @@ class SolveOpts(C.Structure):
                 ("x_init", C.c_void_p), ("k0", C.c_int32), ("use_precond", C.c_int32),
                 ("stream", C.c_void_p), ("trace", C.POINTER(C.c_double)), ("trace_cap", C.c_int32),
                 ("use_graph", C.c_int32)]
+
+
+class ProblemC(C.Structure):
+    _fields_ = [("theta", C.c_void_p), ("u", C.c_void_p), ("lam", C.c_float), ("x_init", C.c_void_p),
+                ("x_out", C.c_void_p)]
 
 
 class SolveInfo(C.Structure):
@@ -81,6 +87,8 @@ _SIGS = {
     "wdb_dwt": [_i32, _i32, _i32, _vp, _vp, _i32, _vp],
     "wdb_blur": [C.POINTER(PsfFieldC), _vp, _vp, _vp],
     "wdb_wavelet_filter": [_i32, _pd, C.POINTER(_i32)],
+    "wdb_set_precision": [_vp, _i32],
+    "wdb_solve_batched": [_i32, C.POINTER(ProblemC), C.POINTER(SolveOpts), C.POINTER(SolveInfo)],
 }
 for _name, _args in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -197,7 +205,7 @@ class Theta:
     def info(self) -> dict:
         d = ThetaDesc()
         _check("wdb_theta_info", _lib.wdb_theta_info(self._h, C.byref(d)))
-        return {k: getattr(d, k) for k, _ in ThetaDesc._fields_ if k != "pad_"}
+        return {k: getattr(d, k) for k, _ in ThetaDesc._fields_}
 
     def export(self):
         """(rowptr int64, col int32, val float64) host arrays."""
@@ -220,6 +228,10 @@ class Theta:
     def set_precond(self, kind: str, eps: float = 0.0, start=None, tol: float = 1e-12, max_iters: int = 20000):
         p, keep = _f64ptr(start)
         _check("wdb_set_precond", _lib.wdb_set_precond(self._h, PRECOND[kind], eps, p, tol, max_iters))
+
+    def set_precision(self, valtype: str):
+        """Iteration values in float32, bfloat16 or binary16 ("f32" | "bf16" | "f16")."""
+        _check("wdb_set_precision", _lib.wdb_set_precision(self._h, VALTYPES[valtype]))
 
     def precond(self) -> np.ndarray:
         d = self.info()
@@ -297,6 +309,37 @@ class Theta:
         _check("wdb_synthesize", _lib.wdb_synthesize(self._h, _dev(x, n * n, "x"), _dev(u, n * n, "u_hat"),
                                                      _stream(stream)))
         return u
+
+
+def solve_batched(problems, iters: int, check_every: int = 20, tol: float = 0.0, k0: int = 1,
+                  precond: bool = False, use_graph: bool = False, outs=None, stream=None):
+    """Batched Alg. 1.  ``problems``: list of (theta, u, lam) or (theta, u, lam, x_init).
+    Returns (list of x tensors, list of info dicts)."""
+    torch = _torch()
+    n = len(problems)
+    arr = (ProblemC * n)()
+    xs = []
+    for i, p in enumerate(problems):
+        th, u, lam = p[0], p[1], p[2]
+        xi = p[3] if len(p) > 3 else None
+        N = th.N
+        x = torch.empty(N, device=u.device, dtype=torch.float32) if outs is None else outs[i]
+        xs.append(x)
+        arr[i] = ProblemC(th.handle.value, _dev(u, N, "u").value, float(lam),
+                          None if xi is None else _dev(xi, N, "x_init").value, _dev(x, N, "x_out").value)
+    o = SolveOpts(int(iters), int(check_every), float(tol), None, int(k0), 1 if precond else 0,
+                  _stream(stream).value, None, 0, 1 if use_graph else 0)
+    infos = (SolveInfo * n)()
+    st = _lib.wdb_solve_batched(n, arr, C.byref(o), infos)
+    res = [{k: getattr(inf, k) for k, _ in SolveInfo._fields_} for inf in infos]
+    if st == WDB_ERR_NOT_CONVERGED:
+        for r in res:
+            r["converged"] = False
+        return xs, res
+    _check("wdb_solve_batched", st)
+    for r in res:
+        r["converged"] = tol > 0
+    return xs, res
 
 
 def build_theta(field, wavelet: str, levels: int, nnz_budget: int, stream=None) -> Theta:

@@ -335,3 +335,91 @@ def test_preconditioner_matches_oracle(W, p64, kind):
     x, info = th.solve_coeffs(dev(x0), wl.lam, 100, check_every=20, precond=True)
     x_o, E_o = _oracle_fista(p64, 100, p=po, Lp=Lp)
     _gate(A32, x0.astype(np.float64), float(np.float32(wl.lam)), host(x), x_o, E_o)
+
+
+# ---------------------------------------------------------------------------
+# mixed precision: 16-bit values, float32 accumulation
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("fmt", ["f16", "bf16"])
+def test_mixed_precision_matches_oracle_on_dequantised_theta(W, p64, fmt):
+    from oracle import quant
+    th = imported(W, p64)
+    wl = p64["wl"]
+    start = synth.power_start(4096, wl.power_seed)
+    L, _ = th.lipschitz(start)
+    th.set_precision(fmt)
+    assert th.info()["valtype"] == {"f16": 2, "bf16": 1}[fmt]
+    Q = quant.quantize(p64["A"], 64, 3, fmt)
+    # one product with the 16-bit values
+    x = np.random.default_rng(8).standard_normal(4096).astype(np.float32)
+    b = np.random.default_rng(9).standard_normal(4096).astype(np.float32)
+    y = host(th.apply(dev(x), dev(b)))
+    ref = Q @ x.astype(np.float64) - b
+    assert np.max(np.abs(y - ref)) <= 1e-5 * np.max(np.abs(ref))
+    # 200 iterations against the oracle on the dequantised operator (same step 1/L)
+    x0 = p64["x0"].astype(np.float32)
+    lam = float(np.float32(wl.lam))
+    xg, info = th.solve_coeffs(dev(x0), wl.lam, 200, check_every=20)
+    Lo, _ = lipschitz.lipschitz(p64["A32"], start)
+    assert abs(L - Lo) <= 1e-9 * Lo
+    xo, _, _ = fista.fista(Q, x0.astype(np.float64), lam, 1.0 / Lo, 200)
+    _gate(Q, x0.astype(np.float64), lam, host(xg), xo, fista.objective(Q, x0.astype(np.float64), lam, xo))
+    # the float64 check scores the iterate against the unquantised operator
+    Eu = fista.objective(p64["A32"], x0.astype(np.float64), lam, host(xg))
+    assert abs(info["objective"] - Eu) <= 1e-10 * Eu
+    # error of the 16-bit form against the float64 oracle solve, reported
+    x64, E64 = _oracle_fista(p64, 200)
+    print(f"{fmt}: rel objective vs FP64 oracle {abs(Eu - E64) / E64:.3e}, "
+          f"rel ||x - x64|| {np.linalg.norm(host(xg) - x64) / np.linalg.norm(x64):.3e}")
+    th.set_precision("f32")
+    assert th.info()["valtype"] == 0
+
+
+# ---------------------------------------------------------------------------
+# batched solve (packs of 8 right-hand sides per operator, one launch per phase)
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def small32():
+    field = synth.psf_isotropic(32, 1.0, 2.5)
+    h = filters.haar()
+    T = theta.theta_dense(field, h, 2)
+    r, c, v = theta.top_k(T, 20 * 1024)
+    A = theta.to_csr(r, c, v, 1024)
+    A32 = sp.csr_matrix((A.data.astype(np.float32).astype(np.float64), A.indices, A.indptr), shape=A.shape)
+    return {"field": field, "h": h, "A": A, "A32": A32, "H": blur.blur_matrix(field)}
+
+
+def test_batched_matches_oracle_per_problem(W, p64, small32):
+    th64 = imported(W, p64)
+    rp, cc, vv = theta.csr_arrays(small32["A"])
+    th32 = W.Theta.from_csr(32, "haar", 2, rp, cc, vv)
+    wl = p64["wl"]
+    start64, start32 = synth.power_start(4096, 3), synth.power_start(1024, 4)
+    th64.lipschitz(start64)
+    th32.lipschitz(start32)
+    H64 = blur.blur_matrix(wl.psf())
+    probs, oracle_inputs = [], []
+    for i in range(13):
+        if i < 10:
+            n, th, H, A32, h, J, start = 64, th64, H64, p64["A32"], filters.haar(), 3, start64
+        else:
+            n, th, H, A32, h, J, start = 32, th32, small32["H"], small32["A32"], small32["h"], 2, start32
+        u0 = (blur.blur(None, synth.piecewise_image(n, 100 + i), H) + synth.noise(n, 0.01, 200 + i)).astype(np.float32)
+        lam = float(np.float32(10.0 ** (-3.5 + 0.15 * i)))
+        probs.append((th, dev(u0).reshape(-1), lam))
+        oracle_inputs.append((A32, dwt.dwt2(u0.astype(np.float64), h, J), lam, start))
+    xs, infos = W.solve_batched(probs, 150, check_every=50, use_graph=True)
+    for i, (A32, x0, lam, start) in enumerate(oracle_inputs):
+        L, _ = lipschitz.lipschitz(A32, start)
+        xo, _, _ = fista.fista(A32, x0, lam, 1.0 / L, 150)
+        _gate(A32, x0, lam, host(xs[i]), xo, fista.objective(A32, x0, lam, xo))
+        E, _, _, rel = fista.duality_gap(A32, x0, lam, host(xs[i]))
+        assert abs(infos[i]["objective"] - E) <= 1e-9 * E and abs(infos[i]["rel_gap"] - rel) <= 1e-8
+    # per-problem stop flags: every problem ends below the tolerance, frozen at its own check
+    xs, infos = W.solve_batched(probs, 3000, check_every=20, tol=2e-3)
+    assert all(r["converged"] for r in infos)
+    its = [r["iters"] for r in infos]
+    assert len(set(its)) > 1 and all(k % 20 == 0 for k in its)
+    for i, (A32, x0, lam, start) in enumerate(oracle_inputs):
+        _, _, _, rel = fista.duality_gap(A32, x0, lam, host(xs[i]))
+        assert rel <= 2e-3 * (1 + 1e-6)
