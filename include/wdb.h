@@ -175,6 +175,22 @@ wdb_status wdb_set_precond(wdb_theta* th, int32_t kind, double eps, const double
  * unquantised Theta_K.  Synchronises.  Errors: WDB_ERR_ARG, _OOM, _HIP. */
 wdb_status wdb_set_precision(wdb_theta* th, int32_t valtype);
 
+/* Kernel layout of the iteration: sliced ELL with `slice` rows per slice
+ * (8, 16, 32 or 64; rows in coefficient order) and group = 0, or vector CSR
+ * with `group` lanes per row (2..64).  The 16-bit values, the batched solver
+ * and the float64 checks always use the sliced-ELL copy.  Synchronises. */
+wdb_status wdb_set_kernel_layout(wdb_theta* th, int32_t slice, int32_t group);
+
+/* Project autotuner: times the iteration kernel pair `reps` times for every
+ * candidate layout (slices of 64/32/16/8 rows; vector CSR with 4/8/16 lanes)
+ * on this operator and keeps the fastest.  If cache_path is not NULL the
+ * decision is looked up in / appended to that text file, keyed by the
+ * operator's shape and a hash of its row pointer.  Outputs (optional): the
+ * chosen slice height and lanes per row, and the time of one iteration pair in
+ * microseconds.  Synchronises. */
+wdb_status wdb_autotune(wdb_theta* th, const char* cache_path, int32_t reps, int32_t* slice_out,
+                        int32_t* group_out, double* us_out);
+
 /* Copy the diagonal P (N doubles, host) of the active preconditioner. */
 wdb_status wdb_get_precond(const wdb_theta* th, double* p_out);
 
@@ -288,6 +304,44 @@ wdb_status wdb_dwt(int32_t n, int32_t wavelet, int32_t levels, const float* in, 
  * arithmetic, float32 storage; u, out: device n*n floats, must not alias.
  * Synchronises `stream` (uploads the field).  Errors: as wdb_build_theta. */
 wdb_status wdb_blur(const wdb_psf_field* field, const float* u, float* out, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Warm start (not in the paper): a small network on wavelet coefficients that
+ * predicts an initial iterate from x0 = Psi^* u.  One stack per level (the
+ * coarsest approximation, 1 channel; each detail level, its 3 subbands as
+ * channels): h1 = relu(conv(z)), h2 = relu(conv(h1)), out = z + conv(h2), with
+ * circular 3x3 convolutions, `features` hidden channels (32), bfloat16 compute
+ * copies of the parameters, float32 accumulation and float32 master weights
+ * updated by Adam (beta 0.9 / 0.999, eps 1e-8) on the mean squared error.
+ * Batches are device arrays [batch][N] in the canonical coefficient layout.
+ * Parameters are flattened stack by stack (A_J first, then levels J..1), each
+ * as W1 [F][C][3][3], b1 [F], W2 [F][F][3][3], b2 [F], W3 [C][F][3][3], b3 [C].
+ * The solver remains the judge: a prediction is only ever used as x_init.
+ * ------------------------------------------------------------------------- */
+typedef struct wdb_cnn wdb_cnn;
+
+/* Network for n x n images with `levels` levels; weights He-normal from a
+ * SplitMix64 stream seeded with `seed` (last convolution of each stack 10x
+ * smaller), biases zero.  Errors: WDB_ERR_ARG, _SIZE, _LEVELS, _OOM, _HIP. */
+wdb_status wdb_cnn_create(int32_t n, int32_t levels, int32_t features, uint64_t seed, wdb_cnn** out);
+wdb_status wdb_cnn_param_count(const wdb_cnn* net, int64_t* count);
+/* Set the float32 master parameters (host array of param_count floats);
+ * resets the Adam state. */
+wdb_status wdb_cnn_set_params(wdb_cnn* net, const float* host, int64_t count);
+/* Copy the parameters to host: masters (rounded = 0) or the bfloat16 values
+ * the kernels compute with (rounded = 1). */
+wdb_status wdb_cnn_get_params(const wdb_cnn* net, float* host, int32_t rounded);
+/* out = network(x0) for a batch (device arrays, must not alias). */
+wdb_status wdb_cnn_predict(wdb_cnn* net, const float* x0, int32_t batch, float* out, void* stream);
+/* Mean squared error against target and its gradient (float32, copied to
+ * grad_host if not NULL).  Synchronises. */
+wdb_status wdb_cnn_loss_grad(wdb_cnn* net, const float* x0, const float* target, int32_t batch, double* loss,
+                             float* grad_host, void* stream);
+/* One Adam step with learning rate lr on the batch; *loss gets the loss
+ * before the step.  Synchronises (to return the loss). */
+wdb_status wdb_cnn_train_step(wdb_cnn* net, const float* x0, const float* target, int32_t batch, float lr,
+                              double* loss, void* stream);
+void wdb_cnn_free(wdb_cnn* net);
 
 /* ---------------------------------------------------------------------------
  * Misc.

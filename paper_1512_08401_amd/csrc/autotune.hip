@@ -1,0 +1,149 @@
+// Project autotuner for the iteration kernels.
+//
+// For one operator it times the FISTA kernel pair (residual product, then
+// transposed product with the proximal epilogue) for each candidate layout --
+// sliced ELL with slice heights 64, 32, 16, 8 (rows in natural order, so a
+// slice's rows are neighbouring coefficients whose gathers share cache lines;
+// shorter slices pad less) and vector CSR with 4, 8 or 16 lanes per row -- and
+// keeps the fastest in the handle.  Decisions can be cached in a text file
+// keyed by the operator's shape and a hash of its row pointer.
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+
+#include "common.hpp"
+
+namespace wdb {
+int kernel_group(const wdb_theta* th);
+void launch_res(int G, const Sell& sell, const Csr32& csr, const float* y, const float* b, float* r, int* kdev,
+                hipStream_t s);
+void launch_prox(int G, const Sell& sell, const Csr32& csr, const float* r, float* x, float* y, float tau, float thr,
+                 float beta, const int* kdev, const float* pinv, hipStream_t s);
+}  // namespace wdb
+
+namespace {
+
+__global__ void k_fill(float* __restrict__ a, int64_t n, float v) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v * static_cast<float>((i * 2654435761ull) % 1000) * 1e-3f;
+}
+
+std::string cache_key(const wdb_theta* th) {
+  std::vector<int64_t> rp(th->N + 1);
+  (void)hipMemcpy(rp.data(), th->csr.rowptr, (th->N + 1) * sizeof(int64_t), hipMemcpyDeviceToHost);
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over the row pointer
+  for (int64_t v : rp) {
+    h ^= static_cast<uint64_t>(v);
+    h *= 1099511628211ull;
+  }
+  std::ostringstream o;
+  o << th->n << "-" << th->levels << "-" << th->wavelet << "-" << th->nnz << "-" << std::hex << h;
+  return o.str();
+}
+
+}  // namespace
+
+extern "C" wdb_status wdb_autotune(wdb_theta* th, const char* cache_path, int32_t reps, int32_t* slice_out,
+                                   int32_t* group_out, double* us_out) {
+  using namespace wdb;
+  WDB_API_BEGIN
+  WDB_REQUIRE(th, WDB_ERR_ARG, "null handle");
+  WDB_REQUIRE(reps >= 1, WDB_ERR_ARG, "reps must be >= 1");
+  WDB_HIP(hipSetDevice(th->device));
+  ensure_workspace(th);
+  hipStream_t s = nullptr;
+  const std::string key = cache_key(th);
+  int bestC = -1, bestG = -1;
+  double best = 1e300;
+  if (cache_path && *cache_path) {
+    std::ifstream in(cache_path);
+    std::string k;
+    int C, G;
+    double us;
+    while (in >> k >> C >> G >> us)
+      if (k == key) {
+        bestC = C;
+        bestG = G;
+        best = us;
+      }
+  }
+  if (bestC < 0) {
+    const int64_t N = th->N;
+    hipLaunchKernelGGL(k_fill, dim3((N + 255) / 256), dim3(256), 0, s, th->ws_y, N, 0.5f);
+    hipLaunchKernelGGL(k_fill, dim3((N + 255) / 256), dim3(256), 0, s, th->ws_x0, N, 0.25f);
+    hipLaunchKernelGGL(k_fill, dim3((N + 255) / 256), dim3(256), 0, s, th->ws_img, N, 0.0f);
+    WDB_HIP(hipGetLastError());
+    const int cands[][2] = {{64, 0}, {32, 0}, {16, 0}, {8, 0}, {0, 4}, {0, 8}, {0, 16}};
+    hipEvent_t e0, e1;
+    WDB_HIP(hipEventCreate(&e0));
+    WDB_HIP(hipEventCreate(&e1));
+    try {
+      for (const auto& cd : cands) {
+        const int C = cd[0], G = cd[1];
+        if (C) set_slice_height(th, C, s);
+        auto pair = [&]() {
+          launch_res(G, th->A, th->cA, th->ws_y, th->ws_x0, th->ws_r, nullptr, s);
+          launch_prox(G, th->At, th->cAt, th->ws_r, th->ws_img, th->ws_y, 1e-3f, 1e-6f, 0.5f, nullptr, nullptr, s);
+        };
+        for (int i = 0; i < 3; ++i) pair();
+        WDB_HIP(hipEventRecord(e0, s));
+        for (int i = 0; i < reps; ++i) pair();
+        WDB_HIP(hipEventRecord(e1, s));
+        WDB_HIP(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        WDB_HIP(hipEventElapsedTime(&ms, e0, e1));
+        const double us = 1e3 * ms / reps;
+        if (std::getenv("WDB_LOG")) std::fprintf(stderr, "[wdb] autotune C=%d G=%d: %.2f us per iteration\n", C, G, us);
+        if (us < best) {
+          best = us;
+          bestC = C ? C : th->A.C;
+          bestG = G;
+        }
+      }
+    } catch (...) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (cache_path && *cache_path) {
+      std::ofstream out(cache_path, std::ios::app);
+      out << key << " " << bestC << " " << bestG << " " << best << "\n";
+    }
+  }
+  set_slice_height(th, bestC, s);
+  th->spmv_group = bestG;
+  if (th->valtype != WDB_VAL_F32) {
+    const int vt = th->valtype;
+    WDB_HIP(hipDeviceSynchronize());
+    const wdb_status st = wdb_set_precision(th, vt);  // requantise into the new slots
+    if (st != WDB_OK) return st;
+  }
+  if (slice_out) *slice_out = bestC;
+  if (group_out) *group_out = bestG;
+  if (us_out) *us_out = best;
+  WDB_API_END
+}
+
+extern "C" wdb_status wdb_set_kernel_layout(wdb_theta* th, int32_t slice, int32_t group) {
+  using namespace wdb;
+  WDB_API_BEGIN
+  WDB_REQUIRE(th, WDB_ERR_ARG, "null handle");
+  WDB_REQUIRE(slice >= 8 && slice <= kSliceMax && (slice & (slice - 1)) == 0, WDB_ERR_ARG,
+              "slice height must be 8, 16, 32 or 64");
+  WDB_REQUIRE(group == 0 || group == 2 || group == 4 || group == 8 || group == 16 || group == 32 || group == 64,
+              WDB_ERR_ARG, "lanes per row must be 0 (sliced ELL) or a power of two up to 64");
+  WDB_HIP(hipSetDevice(th->device));
+  set_slice_height(th, slice, nullptr);
+  th->spmv_group = group;
+  if (th->valtype != WDB_VAL_F32) {
+    const int vt = th->valtype;
+    const wdb_status st = wdb_set_precision(th, vt);
+    if (st != WDB_OK) return st;
+  }
+  WDB_API_END
+}

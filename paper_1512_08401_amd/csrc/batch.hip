@@ -21,7 +21,8 @@ namespace wdb {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kSPB = kBlock / kSlice;  // slices per block
+constexpr int kWave = 64;
+constexpr int kWaves = kBlock / kWave;
 constexpr int kR = 8;                  // right-hand sides per chunk
 
 struct ChunkDev {
@@ -35,6 +36,7 @@ struct ChunkDev {
   const int4* colT;
   const int32_t* permT;
   int64_t nslicesT;
+  int C, cshift;     // slice height of both copies and its log2
   float* X;          // [N][8] iterate
   float* Y;          // [N][8] extrapolated point
   const float* X0;   // [N][8] data
@@ -71,10 +73,10 @@ __device__ __forceinline__ void gather8(const float* __restrict__ V, int c, floa
 }
 
 __device__ __forceinline__ void slice_mm(const int64_t* __restrict__ soff, const float4* __restrict__ val,
-                                         const int4* __restrict__ col, int64_t sl, int lane,
+                                         const int4* __restrict__ col, int64_t sl, int lane, int C,
                                          const float* __restrict__ V, float (&acc)[kR]) {
   const int64_t beg = soff[sl] >> 2, end = soff[sl + 1] >> 2;
-  for (int64_t j = beg + lane; j < end; j += kSlice) {
+  for (int64_t j = beg + lane; j < end; j += C) {
     const float4 v = val[j];
     const int4 c = col[j];
     gather8(V, c.x, v.x, acc);
@@ -89,12 +91,13 @@ __global__ __launch_bounds__(kBlock) void k_res_batched(const ChunkDev* __restri
   if (blockIdx.x == 0 && threadIdx.x == 0) *kdev += 1;
   const int c = chunk_of(first, nchunks, blockIdx.x);
   const ChunkDev& C = ch[c];
-  const int lane = threadIdx.x & (kSlice - 1);
-  const int64_t sl = static_cast<int64_t>(blockIdx.x - first[c]) * kSPB + threadIdx.x / kSlice;
-  if (sl >= C.nslices) return;
+  const int64_t q = static_cast<int64_t>(blockIdx.x - first[c]) * kBlock + threadIdx.x;
+  if (q >= (C.nslices << C.cshift)) return;
+  const int64_t sl = q >> C.cshift;
+  const int lane = static_cast<int>(q & (C.C - 1));
   float acc[kR] = {0, 0, 0, 0, 0, 0, 0, 0};
-  slice_mm(C.soff, C.val, C.col, sl, lane, C.Y, acc);
-  const int64_t row = slot_row_c(C.perm, C.nrows, sl * kSlice + lane);
+  slice_mm(C.soff, C.val, C.col, sl, lane, C.C, C.Y, acc);
+  const int64_t row = slot_row_c(C.perm, C.nrows, q);
   if (row < 0) return;
   const float4* b = reinterpret_cast<const float4*>(C.X0 + row * kR);
   float4* r = reinterpret_cast<float4*>(C.Rr + row * kR);
@@ -107,12 +110,13 @@ __global__ __launch_bounds__(kBlock) void k_prox_batched(const ChunkDev* __restr
                                                          int nchunks, const int* __restrict__ kdev) {
   const int c = chunk_of(first, nchunks, blockIdx.x);
   const ChunkDev& C = ch[c];
-  const int lane = threadIdx.x & (kSlice - 1);
-  const int64_t sl = static_cast<int64_t>(blockIdx.x - first[c]) * kSPB + threadIdx.x / kSlice;
-  if (sl >= C.nslicesT) return;
+  const int64_t q = static_cast<int64_t>(blockIdx.x - first[c]) * kBlock + threadIdx.x;
+  if (q >= (C.nslicesT << C.cshift)) return;
+  const int64_t sl = q >> C.cshift;
+  const int lane = static_cast<int>(q & (C.C - 1));
   float g[kR] = {0, 0, 0, 0, 0, 0, 0, 0};
-  slice_mm(C.soffT, C.valT, C.colT, sl, lane, C.Rr, g);
-  const int64_t row = slot_row_c(C.permT, C.nrows, sl * kSlice + lane);
+  slice_mm(C.soffT, C.valT, C.colT, sl, lane, C.C, C.Rr, g);
+  const int64_t row = slot_row_c(C.permT, C.nrows, q);
   if (row < 0) return;
   const int k = *kdev;
   const float beta = static_cast<float>((static_cast<double>(k) - 1.0) / (static_cast<double>(k) + 2.0));
@@ -134,12 +138,12 @@ __global__ __launch_bounds__(kBlock) void k_prox_batched(const ChunkDev* __restr
 // float64 checks: per right-hand side sums of r^2, r.x0, |x| (forward) and
 // max |A^T r| (backward); partial[(v * kR + j) * nblocks + block].
 __device__ __forceinline__ void block_reduce8(double (&v)[kR], bool is_max, double* __restrict__ out) {
-  __shared__ double sh[kSPB][kR];
-  const int lane = threadIdx.x & (kSlice - 1), wid = threadIdx.x / kSlice;
+  __shared__ double sh[kWaves][kR];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
 #pragma unroll
   for (int j = 0; j < kR; ++j) {
     double x = v[j];
-    for (int off = kSlice / 2; off > 0; off >>= 1) {
+    for (int off = kWave / 2; off > 0; off >>= 1) {
       const double y = __shfl_xor(x, off);
       x = is_max ? fmax(x, y) : x + y;
     }
@@ -148,7 +152,7 @@ __device__ __forceinline__ void block_reduce8(double (&v)[kR], bool is_max, doub
   __syncthreads();
   if (threadIdx.x < kR) {
     double a = sh[0][threadIdx.x];
-    for (int w = 1; w < kSPB; ++w) a = is_max ? fmax(a, sh[w][threadIdx.x]) : a + sh[w][threadIdx.x];
+    for (int w = 1; w < kWaves; ++w) a = is_max ? fmax(a, sh[w][threadIdx.x]) : a + sh[w][threadIdx.x];
     out[threadIdx.x] = a;
   }
   __syncthreads();
@@ -158,14 +162,15 @@ __global__ __launch_bounds__(kBlock) void k_check_fwd(const ChunkDev* __restrict
                                                       int nchunks, double* __restrict__ part, int64_t nblocks) {
   const int c = chunk_of(first, nchunks, blockIdx.x);
   const ChunkDev& C = ch[c];
-  const int lane = threadIdx.x & (kSlice - 1);
-  const int64_t sl = static_cast<int64_t>(blockIdx.x - first[c]) * kSPB + threadIdx.x / kSlice;
+  const int64_t q = static_cast<int64_t>(blockIdx.x - first[c]) * kBlock + threadIdx.x;
+  const int64_t sl = q >> C.cshift;
+  const int lane = static_cast<int>(q & (C.C - 1));
   double a[kR], rr[kR], rb[kR], l1[kR];
   for (int j = 0; j < kR; ++j) a[j] = rr[j] = rb[j] = l1[j] = 0.0;
   int64_t row = -1;
-  if (sl < C.nslices) {
+  if (q < (C.nslices << C.cshift)) {
     const int64_t beg = C.soff[sl] >> 2, end = C.soff[sl + 1] >> 2;
-    for (int64_t jj = beg + lane; jj < end; jj += kSlice) {
+    for (int64_t jj = beg + lane; jj < end; jj += C.C) {
       const float4 v = C.val[jj];
       const int4 cc = C.col[jj];
       const float vv[4] = {v.x, v.y, v.z, v.w};
@@ -174,7 +179,7 @@ __global__ __launch_bounds__(kBlock) void k_check_fwd(const ChunkDev* __restrict
         for (int j = 0; j < kR; ++j)
           a[j] = fma(static_cast<double>(vv[t]), static_cast<double>(C.X[static_cast<int64_t>(ci[t]) * kR + j]), a[j]);
     }
-    row = slot_row_c(C.perm, C.nrows, sl * kSlice + lane);
+    row = slot_row_c(C.perm, C.nrows, q);
   }
   if (row >= 0) {
     for (int j = 0; j < kR; ++j) {
@@ -199,13 +204,14 @@ __global__ __launch_bounds__(kBlock) void k_check_bwd(const ChunkDev* __restrict
                                                       int nchunks, double* __restrict__ part, int64_t nblocks) {
   const int c = chunk_of(first, nchunks, blockIdx.x);
   const ChunkDev& C = ch[c];
-  const int lane = threadIdx.x & (kSlice - 1);
-  const int64_t sl = static_cast<int64_t>(blockIdx.x - first[c]) * kSPB + threadIdx.x / kSlice;
+  const int64_t q = static_cast<int64_t>(blockIdx.x - first[c]) * kBlock + threadIdx.x;
+  const int64_t sl = q >> C.cshift;
+  const int lane = static_cast<int>(q & (C.C - 1));
   double g[kR];
   for (int j = 0; j < kR; ++j) g[j] = 0.0;
-  if (sl < C.nslicesT) {
+  if (q < (C.nslicesT << C.cshift)) {
     const int64_t beg = C.soffT[sl] >> 2, end = C.soffT[sl + 1] >> 2;
-    for (int64_t jj = beg + lane; jj < end; jj += kSlice) {
+    for (int64_t jj = beg + lane; jj < end; jj += C.C) {
       const float4 v = C.valT[jj];
       const int4 cc = C.colT[jj];
       const float vv[4] = {v.x, v.y, v.z, v.w};
@@ -213,7 +219,7 @@ __global__ __launch_bounds__(kBlock) void k_check_bwd(const ChunkDev* __restrict
       for (int t = 0; t < 4; ++t)
         for (int j = 0; j < kR; ++j) g[j] = fma(static_cast<double>(vv[t]), C.r64[static_cast<int64_t>(ci[t]) * kR + j], g[j]);
     }
-    if (slot_row_c(C.permT, C.nrows, sl * kSlice + lane) < 0)
+    if (slot_row_c(C.permT, C.nrows, q) < 0)
       for (int j = 0; j < kR; ++j) g[j] = 0.0;
   }
   for (int j = 0; j < kR; ++j) g[j] = fabs(g[j]);
@@ -312,8 +318,8 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
       h.Rr.alloc(N * kR);
       h.r64.alloc(N * kR);
       h.act.alloc(kR);
-      h.blocks_res = static_cast<int>((th->A.nslices + kSPB - 1) / kSPB);
-      h.blocks_prox = static_cast<int>((th->At.nslices + kSPB - 1) / kSPB);
+      h.blocks_res = static_cast<int>((th->A.nslices * th->A.C + kBlock - 1) / kBlock);
+      h.blocks_prox = static_cast<int>((th->At.nslices * th->At.C + kBlock - 1) / kBlock);
       h.blocks = std::max(h.blocks_res, h.blocks_prox);
       chunks.push_back(std::move(h));
     }
@@ -347,6 +353,9 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
     d.colT = reinterpret_cast<const int4*>(th->At.col);
     d.permT = th->At.perm;
     d.nslicesT = th->At.nslices;
+    WDB_REQUIRE(th->A.C == th->At.C, WDB_ERR_HIP, "mismatched slice heights");
+    d.C = th->A.C;
+    d.cshift = __builtin_ctz(static_cast<unsigned>(th->A.C));
     d.X = h.X.p;
     d.Y = h.Y.p;
     d.X0 = h.X0.p;

@@ -1,0 +1,554 @@
+// Warm-start network on wavelet coefficients (not in the paper): one stack of
+// three circular 3x3 convolutions per wavelet level (A_J with 1 channel, the
+// detail levels with their 3 subbands as channels), ReLU after the first two,
+// a residual connection, MSE loss and Adam with float32 master weights.
+// Compute uses bfloat16 copies of the parameters and float32 accumulation.
+//
+//   h1 = relu(conv(z; W1, b1)), h2 = relu(conv(h1; W2, b2)), out = z + conv(h2; W3, b3),
+//   conv(z; W, b)[o, i, j] = b[o] + sum_{c, di, dj} W[o, c, di, dj] z[c, (i+di-1) mod s, (j+dj-1) mod s].
+//
+// Activations are stored pre-ReLU (a1, a2); consumers apply the ReLU on load
+// and the backward pass masks with a > 0.  Weight gradients are reduced in two
+// deterministic stages (fixed per-block partial sums, then a fixed-order sum).
+// Parameters are flattened stack by stack: W1, b1, W2, b2, W3, b3.
+#include <cmath>
+#include <cstring>
+
+#include "common.hpp"
+
+namespace {
+constexpr int kF = 32;       // hidden channels
+constexpr int kBlk = 256;
+constexpr int kP = 32;       // positions per weight-gradient chunk
+constexpr int kWGridMax = 512;
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
+
+uint16_t f2bf_host(float f) {
+  uint32_t b;
+  std::memcpy(&b, &f, 4);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return static_cast<uint16_t>(b >> 16);
+}
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t b = __float_as_uint(f);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return static_cast<uint16_t>(b >> 16);
+}
+
+// out[b, o] = bias[o] + conv(in[b]) (+ resid[b, o]); input ReLU applied on load if in_relu.
+template <int CI, int CO>
+__global__ __launch_bounds__(kBlk) void k_conv_fwd(const float* __restrict__ in, int64_t in_bs, int in_relu, int s,
+                                                   int B, const uint16_t* __restrict__ w,
+                                                   const uint16_t* __restrict__ bias, float* __restrict__ out,
+                                                   int64_t out_bs, const float* __restrict__ resid, int64_t res_bs) {
+  __shared__ float sw[CO * CI * 9];
+  __shared__ float sb[CO];
+  for (int t = threadIdx.x; t < CO * CI * 9; t += kBlk) sw[t] = bf2f(w[t]);
+  for (int t = threadIdx.x; t < CO; t += kBlk) sb[t] = bf2f(bias[t]);
+  __syncthreads();
+  const int64_t per = static_cast<int64_t>(s) * s;
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * kBlk + threadIdx.x;
+  if (p >= B * per) return;
+  const int64_t b = p / per, ij = p % per;
+  const int i = static_cast<int>(ij / s), j = static_cast<int>(ij % s);
+  float acc[CO];
+#pragma unroll
+  for (int o = 0; o < CO; ++o) acc[o] = sb[o];
+  const float* inb = in + b * in_bs;
+  for (int c = 0; c < CI; ++c) {
+    const float* ch = inb + c * per;
+#pragma unroll
+    for (int di = 0; di < 3; ++di) {
+      const float* row = ch + static_cast<int64_t>((i + di - 1) & (s - 1)) * s;
+#pragma unroll
+      for (int dj = 0; dj < 3; ++dj) {
+        float v = row[(j + dj - 1) & (s - 1)];
+        if (in_relu) v = fmaxf(v, 0.0f);
+#pragma unroll
+        for (int o = 0; o < CO; ++o) acc[o] = fmaf(sw[(o * CI + c) * 9 + di * 3 + dj], v, acc[o]);
+      }
+    }
+  }
+  float* ob = out + b * out_bs + ij;
+  const float* rb = resid ? resid + b * res_bs + ij : nullptr;
+#pragma unroll
+  for (int o = 0; o < CO; ++o) ob[o * per] = acc[o] + (rb ? rb[o * per] : 0.0f);
+}
+
+// gin[b, c] = sum_{o, d} W[o, c, d] g[b, o, shifted]  (times [a_in > 0] if mask given).
+template <int CO, int CI>
+__global__ __launch_bounds__(kBlk) void k_conv_bwd_data(const float* __restrict__ g, int64_t g_bs, int s, int B,
+                                                        const uint16_t* __restrict__ w, const float* __restrict__ mask,
+                                                        int64_t m_bs, float* __restrict__ gin, int64_t gin_bs) {
+  __shared__ float sw[CO * CI * 9];
+  for (int t = threadIdx.x; t < CO * CI * 9; t += kBlk) sw[t] = bf2f(w[t]);
+  __syncthreads();
+  const int64_t per = static_cast<int64_t>(s) * s;
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * kBlk + threadIdx.x;
+  if (p >= B * per) return;
+  const int64_t b = p / per, ij = p % per;
+  const int i = static_cast<int>(ij / s), j = static_cast<int>(ij % s);
+  float acc[CI];
+#pragma unroll
+  for (int c = 0; c < CI; ++c) acc[c] = 0.0f;
+  const float* gb = g + b * g_bs;
+  for (int o = 0; o < CO; ++o) {
+    const float* ch = gb + o * per;
+#pragma unroll
+    for (int di = 0; di < 3; ++di) {
+      const float* row = ch + static_cast<int64_t>((i - di + 1) & (s - 1)) * s;
+#pragma unroll
+      for (int dj = 0; dj < 3; ++dj) {
+        const float v = row[(j - dj + 1) & (s - 1)];
+#pragma unroll
+        for (int c = 0; c < CI; ++c) acc[c] = fmaf(sw[(o * CI + c) * 9 + di * 3 + dj], v, acc[c]);
+      }
+    }
+  }
+  float* ob = gin + b * gin_bs + ij;
+  const float* mb = mask ? mask + b * m_bs + ij : nullptr;
+#pragma unroll
+  for (int c = 0; c < CI; ++c) ob[c * per] = (mb && !(mb[c * per] > 0.0f)) ? 0.0f : acc[c];
+}
+
+// Per-block partial sums of dW[o, c, d] = sum_p g[p, o] act[p, c, d] and db[o] = sum_p g[p, o].
+template <int CI, int CO>
+__global__ __launch_bounds__(kBlk) void k_conv_bwd_w(const float* __restrict__ act, int64_t a_bs, int act_relu,
+                                                     const float* __restrict__ g, int64_t g_bs, int s, int B,
+                                                     float* __restrict__ partial) {
+  constexpr int NW = CO * CI * 9;
+  constexpr int NT = NW + CO;
+  constexpr int NPT = (NT + kBlk - 1) / kBlk;
+  __shared__ float sg[CO][kP];
+  __shared__ float sa[CI * 9][kP];
+  float acc[NPT];
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) acc[k] = 0.0f;
+  const int64_t per = static_cast<int64_t>(s) * s;
+  const int64_t T = B * per;
+  const int64_t nchunks = (T + kP - 1) / kP;
+  for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    const int64_t p0 = ch * kP;
+    for (int t = threadIdx.x; t < CO * kP; t += kBlk) {
+      const int o = t / kP, q = t % kP;
+      const int64_t p = p0 + q;
+      float v = 0.0f;
+      if (p < T) v = g[(p / per) * g_bs + o * per + (p % per)];
+      sg[o][q] = v;
+    }
+    for (int t = threadIdx.x; t < CI * 9 * kP; t += kBlk) {
+      const int cd = t / kP, q = t % kP;
+      const int c = cd / 9, d = cd % 9;
+      const int64_t p = p0 + q;
+      float v = 0.0f;
+      if (p < T) {
+        const int64_t b = p / per, ij = p % per;
+        const int i = static_cast<int>(ij / s), j = static_cast<int>(ij % s);
+        const int ii = (i + d / 3 - 1) & (s - 1), jj = (j + d % 3 - 1) & (s - 1);
+        v = act[b * a_bs + c * per + static_cast<int64_t>(ii) * s + jj];
+        if (act_relu) v = fmaxf(v, 0.0f);
+      }
+      sa[cd][q] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      const int idx = threadIdx.x + k * kBlk;
+      if (idx < NW) {
+        const int o = idx / (CI * 9), cd = idx % (CI * 9);
+        float a = acc[k];
+#pragma unroll 8
+        for (int q = 0; q < kP; ++q) a = fmaf(sg[o][q], sa[cd][q], a);
+        acc[k] = a;
+      } else if (idx < NT) {
+        const int o = idx - NW;
+        float a = acc[k];
+        for (int q = 0; q < kP; ++q) a += sg[o][q];
+        acc[k] = a;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    const int idx = threadIdx.x + k * kBlk;
+    if (idx < NT) partial[static_cast<int64_t>(blockIdx.x) * NT + idx] = acc[k];
+  }
+}
+
+__global__ void k_sum_partials(const float* __restrict__ partial, int nblocks, int NT, float* __restrict__ out) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= NT) return;
+  float a = 0.0f;
+  for (int b = 0; b < nblocks; ++b) a += partial[static_cast<int64_t>(b) * NT + idx];
+  out[idx] = a;
+}
+
+// g = 2 (pred - target) / (B N); per-block partial sums of (pred - target)^2 in float64.
+__global__ __launch_bounds__(kBlk) void k_mse(const float* __restrict__ pred, const float* __restrict__ tgt, int64_t n,
+                                              float scale, float* __restrict__ g, double* __restrict__ part) {
+  __shared__ double sh[kBlk];
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlk + threadIdx.x;
+  double d2 = 0.0;
+  if (i < n) {
+    const float d = pred[i] - tgt[i];
+    g[i] = scale * d;
+    d2 = static_cast<double>(d) * d;
+  }
+  sh[threadIdx.x] = d2;
+  __syncthreads();
+  for (int w = kBlk / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_adam(float* __restrict__ master, float* __restrict__ m, float* __restrict__ v,
+                       const float* __restrict__ g, int64_t n, float lr, float b1, float b2, float c1, float c2,
+                       float eps, uint16_t* __restrict__ wbf) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float w = master[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  master[i] = w;
+  wbf[i] = f2bf(w);
+}
+
+__global__ void k_round_bf16(const float* __restrict__ master, uint16_t* __restrict__ wbf, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) wbf[i] = f2bf(master[i]);
+}
+
+inline dim3 grid_for(int64_t n) { return dim3(static_cast<unsigned>((n + kBlk - 1) / kBlk)); }
+
+}  // namespace
+
+struct wdb_cnn {
+  int device = 0;
+  int n = 0, levels = 0, F = kF;
+  int64_t N = 0;
+  struct Stack {
+    int64_t off;
+    int C, s;
+    int64_t p[6];  // offsets of W1, b1, W2, b2, W3, b3
+  };
+  std::vector<Stack> stacks;
+  int64_t nparam = 0;
+  float* master = nullptr;
+  uint16_t* wbf = nullptr;
+  float* m = nullptr;
+  float* v = nullptr;
+  float* grad = nullptr;
+  int64_t t = 0;
+  int bcap = 0;
+  float* a1 = nullptr;   // per batch capacity: largest stack's B*F*s*s
+  float* a2 = nullptr;
+  float* ga = nullptr;
+  float* gb = nullptr;
+  float* pred = nullptr; // B*N
+  float* gout = nullptr; // B*N
+  float* partial = nullptr;
+  double* dpart = nullptr;
+  double* hpart = nullptr;
+};
+
+namespace {
+
+void cnn_free_ws(wdb_cnn* c) {
+  float* fs[] = {c->a1, c->a2, c->ga, c->gb, c->pred, c->gout, c->partial};
+  for (float* p : fs)
+    if (p) (void)hipFree(p);
+  if (c->dpart) (void)hipFree(c->dpart);
+  if (c->hpart) (void)hipHostFree(c->hpart);
+  c->a1 = c->a2 = c->ga = c->gb = c->pred = c->gout = c->partial = nullptr;
+  c->dpart = nullptr;
+  c->hpart = nullptr;
+  c->bcap = 0;
+}
+
+void cnn_ensure(wdb_cnn* c, int B) {
+  if (B <= c->bcap) return;
+  cnn_free_ws(c);
+  int64_t big = 0;
+  for (auto& st : c->stacks) big = std::max<int64_t>(big, static_cast<int64_t>(st.s) * st.s);
+  const int64_t act = static_cast<int64_t>(B) * c->F * big;
+  const int64_t vec = static_cast<int64_t>(B) * c->N;
+  WDB_HIP(hipMalloc(reinterpret_cast<void**>(&c->a1), act * sizeof(float)));
+  WDB_HIP(hipMalloc(reinterpret_cast<void**>(&c->a2), act * sizeof(float)));
+  WDB_HIP(hipMalloc(reinterpret_cast<void**>(&c->ga), act * sizeof(float)));
+  WDB_HIP(hipMalloc(reinterpret_cast<void**>(&c->gb), act * sizeof(float)));
+  WDB_HIP(hipMalloc(reinterpret_cast<void**>(&c->pred), vec * sizeof(float)));
+  WDB_HIP(hipMalloc(reinterpret_cast<void**>(&c->gout), vec * sizeof(float)));
+  WDB_HIP(hipMalloc(reinterpret_cast<void**>(&c->partial),
+                    static_cast<size_t>(kWGridMax) * (kF * kF * 9 + kF) * sizeof(float)));
+  const int64_t nb = (vec + kBlk - 1) / kBlk;
+  WDB_HIP(hipMalloc(reinterpret_cast<void**>(&c->dpart), nb * sizeof(double)));
+  WDB_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->hpart), nb * sizeof(double), hipHostMallocDefault));
+  c->bcap = B;
+}
+
+template <int CI, int CO>
+void conv_fwd(const float* in, int64_t in_bs, int in_relu, int s, int B, const uint16_t* w, const uint16_t* b,
+              float* out, int64_t out_bs, const float* resid, int64_t res_bs, hipStream_t st) {
+  hipLaunchKernelGGL((k_conv_fwd<CI, CO>), grid_for(static_cast<int64_t>(B) * s * s), dim3(kBlk), 0, st, in, in_bs,
+                     in_relu, s, B, w, b, out, out_bs, resid, res_bs);
+}
+
+template <int CO, int CI>
+void conv_bwd_data(const float* g, int64_t g_bs, int s, int B, const uint16_t* w, const float* mask, int64_t m_bs,
+                   float* gin, int64_t gin_bs, hipStream_t st) {
+  hipLaunchKernelGGL((k_conv_bwd_data<CO, CI>), grid_for(static_cast<int64_t>(B) * s * s), dim3(kBlk), 0, st, g,
+                     g_bs, s, B, w, mask, m_bs, gin, gin_bs);
+}
+
+template <int CI, int CO>
+void conv_bwd_w(const float* act, int64_t a_bs, int act_relu, const float* g, int64_t g_bs, int s, int B,
+                float* partial, float* out, hipStream_t st) {
+  const int64_t T = static_cast<int64_t>(B) * s * s;
+  const int nb = static_cast<int>(std::min<int64_t>(kWGridMax, (T + kP - 1) / kP));
+  hipLaunchKernelGGL((k_conv_bwd_w<CI, CO>), dim3(nb), dim3(kBlk), 0, st, act, a_bs, act_relu, g, g_bs, s, B,
+                     partial);
+  const int NT = CO * CI * 9 + CO;
+  hipLaunchKernelGGL(k_sum_partials, dim3((NT + 255) / 256), dim3(256), 0, st, partial, nb, NT, out);
+}
+
+void forward(wdb_cnn* c, const float* x0, int B, float* pred, hipStream_t st) {
+  const int64_t N = c->N;
+  for (auto& S : c->stacks) {
+    const int64_t per = static_cast<int64_t>(S.s) * S.s;
+    const float* z = x0 + S.off;
+    const uint16_t* w = c->wbf;
+    const int64_t hb = static_cast<int64_t>(kF) * per;
+    if (S.C == 1) conv_fwd<1, kF>(z, N, 0, S.s, B, w + S.p[0], w + S.p[1], c->a1, hb, nullptr, 0, st);
+    else conv_fwd<3, kF>(z, N, 0, S.s, B, w + S.p[0], w + S.p[1], c->a1, hb, nullptr, 0, st);
+    conv_fwd<kF, kF>(c->a1, hb, 1, S.s, B, w + S.p[2], w + S.p[3], c->a2, hb, nullptr, 0, st);
+    if (S.C == 1) conv_fwd<kF, 1>(c->a2, hb, 1, S.s, B, w + S.p[4], w + S.p[5], pred + S.off, N, z, N, st);
+    else conv_fwd<kF, 3>(c->a2, hb, 1, S.s, B, w + S.p[4], w + S.p[5], pred + S.off, N, z, N, st);
+  }
+  WDB_HIP(hipGetLastError());
+}
+
+// Loss and gradient into c->grad (float32).  Recomputes the forward pass per
+// stack so only one stack's activations are held at a time.
+double loss_grad(wdb_cnn* c, const float* x0, const float* tgt, int B, hipStream_t st) {
+  const int64_t N = c->N;
+  const int64_t tot = static_cast<int64_t>(B) * N;
+  forward(c, x0, B, c->pred, st);
+  const int64_t nb = (tot + kBlk - 1) / kBlk;
+  hipLaunchKernelGGL(k_mse, dim3(static_cast<unsigned>(nb)), dim3(kBlk), 0, st, c->pred, tgt, tot,
+                     static_cast<float>(2.0 / static_cast<double>(tot)), c->gout, c->dpart);
+  WDB_HIP(hipMemcpyAsync(c->hpart, c->dpart, nb * sizeof(double), hipMemcpyDeviceToHost, st));
+  for (auto& S : c->stacks) {
+    const int64_t per = static_cast<int64_t>(S.s) * S.s;
+    const int64_t hb = static_cast<int64_t>(kF) * per;
+    const float* z = x0 + S.off;
+    const uint16_t* w = c->wbf;
+    // recompute this stack's activations
+    if (S.C == 1) conv_fwd<1, kF>(z, N, 0, S.s, B, w + S.p[0], w + S.p[1], c->a1, hb, nullptr, 0, st);
+    else conv_fwd<3, kF>(z, N, 0, S.s, B, w + S.p[0], w + S.p[1], c->a1, hb, nullptr, 0, st);
+    conv_fwd<kF, kF>(c->a1, hb, 1, S.s, B, w + S.p[2], w + S.p[3], c->a2, hb, nullptr, 0, st);
+    const float* g = c->gout + S.off;
+    float* gr = c->grad;
+    // layer 3: out = z + conv(h2; W3, b3)
+    if (S.C == 1) {
+      conv_bwd_w<kF, 1>(c->a2, hb, 1, g, N, S.s, B, c->partial, gr + S.p[4], st);
+      conv_bwd_data<1, kF>(g, N, S.s, B, w + S.p[4], c->a2, hb, c->ga, hb, st);
+    } else {
+      conv_bwd_w<kF, 3>(c->a2, hb, 1, g, N, S.s, B, c->partial, gr + S.p[4], st);
+      conv_bwd_data<3, kF>(g, N, S.s, B, w + S.p[4], c->a2, hb, c->ga, hb, st);
+    }
+    // layer 2
+    conv_bwd_w<kF, kF>(c->a1, hb, 1, c->ga, hb, S.s, B, c->partial, gr + S.p[2], st);
+    conv_bwd_data<kF, kF>(c->ga, hb, S.s, B, w + S.p[2], c->a1, hb, c->gb, hb, st);
+    // layer 1
+    if (S.C == 1) conv_bwd_w<1, kF>(z, N, 0, c->gb, hb, S.s, B, c->partial, gr + S.p[0], st);
+    else conv_bwd_w<3, kF>(z, N, 0, c->gb, hb, S.s, B, c->partial, gr + S.p[0], st);
+  }
+  WDB_HIP(hipGetLastError());
+  WDB_HIP(hipStreamSynchronize(st));
+  double sum = 0.0;
+  for (int64_t i = 0; i < nb; ++i) sum += c->hpart[i];
+  return sum / static_cast<double>(tot);
+}
+
+uint64_t splitmix(uint64_t& s) {
+  uint64_t z = (s += 0x9e3779b97f4a7c15ull);
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+}  // namespace
+
+extern "C" {
+
+wdb_status wdb_cnn_create(int32_t n, int32_t levels, int32_t features, uint64_t seed, wdb_cnn** out) {
+  using namespace wdb;
+  WDB_API_BEGIN
+  WDB_REQUIRE(out, WDB_ERR_ARG, "null output");
+  WDB_REQUIRE(features == kF, WDB_ERR_ARG, "only %d hidden channels are built", kF);
+  check_geometry(n, levels, 2);
+  WDB_REQUIRE((n >> levels) >= 2, WDB_ERR_LEVELS, "coarsest level too small for 3x3 convolutions");
+  wdb_cnn* c = new wdb_cnn();
+  try {
+    WDB_HIP(hipGetDevice(&c->device));
+    c->n = n;
+    c->levels = levels;
+    c->N = static_cast<int64_t>(n) * n;
+    const std::vector<Subband> lay = layout(n, levels);
+    int64_t pos = 0;
+    auto add = [&](int64_t off, int C, int s) {
+      wdb_cnn::Stack S{off, C, s, {0, 0, 0, 0, 0, 0}};
+      const int64_t sizes[6] = {int64_t(kF) * C * 9, kF, int64_t(kF) * kF * 9, kF, int64_t(C) * kF * 9, C};
+      for (int k = 0; k < 6; ++k) {
+        S.p[k] = pos;
+        pos += sizes[k];
+      }
+      c->stacks.push_back(S);
+    };
+    add(lay[0].offset, 1, lay[0].side);
+    for (size_t k = 1; k < lay.size(); k += 3) add(lay[k].offset, 3, lay[k].side);
+    c->nparam = pos;
+    // He-normal convolution weights (SplitMix64 + Box-Muller), zero biases; the
+    // last convolution of each stack starts 10x smaller so the network starts
+    // close to the identity map.
+    std::vector<float> h(pos, 0.0f);
+    uint64_t st = seed;
+    auto normal = [&]() {
+      const double u1 = (static_cast<double>(splitmix(st) >> 11) + 0.5) * 0x1.0p-53;
+      const double u2 = static_cast<double>(splitmix(st) >> 11) * 0x1.0p-53;
+      return std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * M_PI * u2);
+    };
+    for (auto& S : c->stacks) {
+      const int fan[3] = {S.C * 9, kF * 9, kF * 9};
+      const int64_t len[3] = {int64_t(kF) * S.C * 9, int64_t(kF) * kF * 9, int64_t(S.C) * kF * 9};
+      for (int l = 0; l < 3; ++l) {
+        const double sd = std::sqrt(2.0 / fan[l]) * (l == 2 ? 0.1 : 1.0);
+        for (int64_t i = 0; i < len[l]; ++i) h[S.p[2 * l] + i] = static_cast<float>(sd * normal());
+      }
+    }
+    WDB_HIP(hipMalloc(reinterpret_cast<void**>(&c->master), pos * sizeof(float)));
+    WDB_HIP(hipMalloc(reinterpret_cast<void**>(&c->wbf), pos * sizeof(uint16_t)));
+    WDB_HIP(hipMalloc(reinterpret_cast<void**>(&c->m), pos * sizeof(float)));
+    WDB_HIP(hipMalloc(reinterpret_cast<void**>(&c->v), pos * sizeof(float)));
+    WDB_HIP(hipMalloc(reinterpret_cast<void**>(&c->grad), pos * sizeof(float)));
+    WDB_HIP(hipMemcpy(c->master, h.data(), pos * sizeof(float), hipMemcpyHostToDevice));
+    WDB_HIP(hipMemset(c->m, 0, pos * sizeof(float)));
+    WDB_HIP(hipMemset(c->v, 0, pos * sizeof(float)));
+    hipLaunchKernelGGL(k_round_bf16, grid_for(pos), dim3(kBlk), 0, nullptr, c->master, c->wbf, pos);
+    WDB_HIP(hipGetLastError());
+    WDB_HIP(hipDeviceSynchronize());
+  } catch (...) {
+    wdb_cnn_free(c);
+    throw;
+  }
+  *out = c;
+  WDB_API_END
+}
+
+wdb_status wdb_cnn_param_count(const wdb_cnn* c, int64_t* count) {
+  WDB_API_BEGIN
+  WDB_REQUIRE(c && count, WDB_ERR_ARG, "null argument");
+  *count = c->nparam;
+  WDB_API_END
+}
+
+wdb_status wdb_cnn_set_params(wdb_cnn* c, const float* host, int64_t count) {
+  WDB_API_BEGIN
+  WDB_REQUIRE(c && host, WDB_ERR_ARG, "null argument");
+  WDB_REQUIRE(count == c->nparam, WDB_ERR_ARG, "expected %lld parameters", static_cast<long long>(c->nparam));
+  for (int64_t i = 0; i < count; ++i)
+    WDB_REQUIRE(std::isfinite(host[i]), WDB_ERR_NONFINITE, "non-finite parameter %lld", static_cast<long long>(i));
+  WDB_HIP(hipSetDevice(c->device));
+  WDB_HIP(hipMemcpy(c->master, host, count * sizeof(float), hipMemcpyHostToDevice));
+  WDB_HIP(hipMemset(c->m, 0, count * sizeof(float)));
+  WDB_HIP(hipMemset(c->v, 0, count * sizeof(float)));
+  c->t = 0;
+  hipLaunchKernelGGL(k_round_bf16, grid_for(count), dim3(kBlk), 0, nullptr, c->master, c->wbf, count);
+  WDB_HIP(hipGetLastError());
+  WDB_HIP(hipDeviceSynchronize());
+  WDB_API_END
+}
+
+wdb_status wdb_cnn_get_params(const wdb_cnn* c, float* host, int32_t rounded) {
+  WDB_API_BEGIN
+  WDB_REQUIRE(c && host, WDB_ERR_ARG, "null argument");
+  WDB_HIP(hipSetDevice(c->device));
+  if (!rounded) {
+    WDB_HIP(hipMemcpy(host, c->master, c->nparam * sizeof(float), hipMemcpyDeviceToHost));
+  } else {
+    std::vector<uint16_t> b(c->nparam);
+    WDB_HIP(hipMemcpy(b.data(), c->wbf, c->nparam * sizeof(uint16_t), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < c->nparam; ++i) {
+      const uint32_t u = static_cast<uint32_t>(b[i]) << 16;
+      std::memcpy(&host[i], &u, 4);
+    }
+  }
+  WDB_API_END
+}
+
+wdb_status wdb_cnn_predict(wdb_cnn* c, const float* x0, int32_t batch, float* out, void* stream) {
+  WDB_API_BEGIN
+  WDB_REQUIRE(c && x0 && out, WDB_ERR_ARG, "null argument");
+  WDB_REQUIRE(batch >= 1, WDB_ERR_ARG, "batch must be >= 1");
+  WDB_REQUIRE(x0 != out, WDB_ERR_ARG, "x0 and out must not alias");
+  WDB_HIP(hipSetDevice(c->device));
+  cnn_ensure(c, batch);
+  forward(c, x0, batch, out, static_cast<hipStream_t>(stream));
+  WDB_API_END
+}
+
+wdb_status wdb_cnn_loss_grad(wdb_cnn* c, const float* x0, const float* target, int32_t batch, double* loss,
+                             float* grad_host, void* stream) {
+  WDB_API_BEGIN
+  WDB_REQUIRE(c && x0 && target, WDB_ERR_ARG, "null argument");
+  WDB_REQUIRE(batch >= 1, WDB_ERR_ARG, "batch must be >= 1");
+  WDB_HIP(hipSetDevice(c->device));
+  cnn_ensure(c, batch);
+  const double L = loss_grad(c, x0, target, batch, static_cast<hipStream_t>(stream));
+  if (loss) *loss = L;
+  if (grad_host) WDB_HIP(hipMemcpy(grad_host, c->grad, c->nparam * sizeof(float), hipMemcpyDeviceToHost));
+  WDB_API_END
+}
+
+wdb_status wdb_cnn_train_step(wdb_cnn* c, const float* x0, const float* target, int32_t batch, float lr,
+                              double* loss, void* stream) {
+  WDB_API_BEGIN
+  WDB_REQUIRE(c && x0 && target, WDB_ERR_ARG, "null argument");
+  WDB_REQUIRE(batch >= 1 && std::isfinite(lr) && lr > 0, WDB_ERR_ARG, "bad batch or learning rate");
+  WDB_HIP(hipSetDevice(c->device));
+  cnn_ensure(c, batch);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const double L = loss_grad(c, x0, target, batch, st);
+  WDB_REQUIRE(std::isfinite(L), WDB_ERR_DIVERGED, "training loss became non-finite");
+  c->t += 1;
+  const double b1 = 0.9, b2 = 0.999;
+  const float c1 = static_cast<float>(1.0 - std::pow(b1, static_cast<double>(c->t)));
+  const float c2 = static_cast<float>(1.0 - std::pow(b2, static_cast<double>(c->t)));
+  hipLaunchKernelGGL(k_adam, grid_for(c->nparam), dim3(kBlk), 0, st, c->master, c->m, c->v, c->grad, c->nparam, lr,
+                     static_cast<float>(b1), static_cast<float>(b2), c1, c2, 1e-8f, c->wbf);
+  WDB_HIP(hipGetLastError());
+  if (loss) *loss = L;
+  WDB_API_END
+}
+
+void wdb_cnn_free(wdb_cnn* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  cnn_free_ws(c);
+  float* fs[] = {c->master, c->m, c->v, c->grad};
+  for (float* p : fs)
+    if (p) (void)hipFree(p);
+  if (c->wbf) (void)hipFree(c->wbf);
+  delete c;
+}
+
+}  // extern "C"

@@ -108,23 +108,24 @@ std::vector<Subband> layout(int32_t n, int32_t levels);
 
 // ---------------------------------------------------------------------------
 // Sliced-ELL storage of one sparse N x N matrix (rows = output index).
-// Rows are grouped in slices of 64 (one wavefront, one row per lane).  Slice
-// s holds width w_s (a multiple of 4) entries per row, laid out as
-// [w_s/4][64 lanes][4], so each lane reads one 16-byte vector of values and
-// one of column indices per step and a wavefront's step is 1 KiB contiguous.
+// Rows are grouped in slices of C (a power of two, 8..64; one thread per row).
+// Slice s holds width w_s (a multiple of 4) entries per row, laid out as
+// [w_s/4][C rows][4], so each thread reads one 16-byte vector of values and
+// one of column indices per step and a slice step is 16*C contiguous bytes.
 // Padding slots have value 0 and repeat a valid column of the same row.
 // Rows may be reordered inside windows of `sort_window` rows by decreasing
 // length (sliced ELL with local sorting), so that the rows sharing a slice
 // have similar lengths; `perm` then maps each slot row to its matrix row.
 // ---------------------------------------------------------------------------
-constexpr int kSlice = 64;
+constexpr int kSliceMax = 64;
 
 struct Sell {
+  int C = kSliceMax;             // slice height
   int64_t nrows = 0, nslices = 0, stored = 0;
   int64_t* slice_off = nullptr;  // device, nslices + 1 (element offsets)
   float* val = nullptr;          // device, stored
   int32_t* col = nullptr;        // device, stored
-  int32_t* perm = nullptr;       // device, nslices * 64 (-1: empty slot row), or null = identity
+  int32_t* perm = nullptr;       // device, nslices * C (-1: empty slot row), or null = identity
   void free_all();
 };
 
@@ -153,7 +154,11 @@ void csr_to_csr32(const Csr& a, Csr32* out, hipStream_t s);
 int spmv_group();
 
 // Build a SELL copy of a device CSR (float64 values rounded to float32).
-void csr_to_sell(const Csr& a, Sell* out, hipStream_t s, int64_t sort_window);
+void csr_to_sell(const Csr& a, Sell* out, hipStream_t s, int64_t sort_window, int C);
+// Element index of entry k of slot row `lane` in the slice starting at `base`.
+__host__ __device__ inline int64_t sell_index(int64_t base, int C, int lane, int64_t k) {
+  return base + (k >> 2) * (4 * static_cast<int64_t>(C)) + lane * 4 + (k & 3);
+}
 // Transpose a device CSR (sorted output).
 void csr_transpose(const Csr& a, Csr* out, hipStream_t s);
 // Sort device COO triples by (row, col) into a CSR; consumes nothing.
@@ -172,6 +177,8 @@ struct wdb_theta {
   wdb::Sell A;         // Theta_K   (rows = output coefficient)
   wdb::Sell At;        // Theta_K^T (rows = input coefficient)
   wdb::Csr32 cA, cAt;  // float32 CSR of Theta_K and Theta_K^T
+  int spmv_group = -1; // iteration kernels: 0 sliced ELL, G > 0 vector CSR with G lanes per row,
+                       // -1 not chosen yet (process default)
   // 16-bit iteration values (same slots as A / At) and per-row dequantisation
   // factors (a power of two per row subband); valtype 0 = float32 iteration.
   int valtype = 0;
@@ -205,6 +212,8 @@ namespace wdb {
 void ensure_workspace(wdb_theta* th);
 void free_workspace(wdb_theta* th);
 void finish_theta(wdb_theta* th, hipStream_t s);   // builds A/At from csr
+void set_slice_height(wdb_theta* th, int C, hipStream_t s);  // rebuilds A/At with slices of C rows
+int default_slice_height();
 // Power iteration on D^-1/2 A^T A D^-1/2 (d = nullptr: identity), float64.
 double power_iteration(wdb_theta* th, const double* start_host, const double* dinv_sqrt,
                        double tol, int max_iters, int* iters_out, hipStream_t s);

@@ -22,7 +22,7 @@ __global__ __launch_bounds__(kBlock) void k_hessian_diag(const int64_t* __restri
                                                          const float* __restrict__ valT,
                                                          const int32_t* __restrict__ colT,
                                                          const int32_t* __restrict__ permT, int64_t nslots,
-                                                         int64_t N,
+                                                         int C, int64_t N,
                                                          const int64_t* __restrict__ rowptr,
                                                          const int32_t* __restrict__ col,
                                                          const double* __restrict__ val,
@@ -33,14 +33,14 @@ __global__ __launch_bounds__(kBlock) void k_hessian_diag(const int64_t* __restri
   for (int64_t q = blockIdx.x; q < nslots; q += gridDim.x) {
     const int64_t i = permT ? static_cast<int64_t>(permT[q]) : (q < N ? q : -1);
     if (i < 0) continue;  // uniform across the block
-    const int64_t sl = q / kSlice;
-    const int lane = static_cast<int>(q % kSlice);
+    const int64_t sl = q / C;
+    const int lane = static_cast<int>(q % C);
     const int64_t base = soffT[sl];
-    const int64_t w = (soffT[sl + 1] - base) / kSlice;
+    const int64_t w = (soffT[sl + 1] - base) / C;
     double s1 = 0.0;
     // scatter: acc += Theta[a,i] * Theta[a,:] for every a in column i
     for (int64_t k = 0; k < w; ++k) {
-      const int64_t idx = base + (k >> 2) * (4 * kSlice) + lane * 4 + (k & 3);
+      const int64_t idx = sell_index(base, C, lane, k);
       const double c = static_cast<double>(valT[idx]);
       if (c == 0.0) continue;  // padding
       s1 += c * c;
@@ -52,7 +52,7 @@ __global__ __launch_bounds__(kBlock) void k_hessian_diag(const int64_t* __restri
     // gather: sum of squares of the touched entries, resetting them
     double s2 = 0.0;
     for (int64_t k = 0; k < w; ++k) {
-      const int64_t idx = base + (k >> 2) * (4 * kSlice) + lane * 4 + (k & 3);
+      const int64_t idx = sell_index(base, C, lane, k);
       if (valT[idx] == 0.0f) continue;
       const int32_t a = colT[idx];
       for (int64_t t = rowptr[a] + threadIdx.x; t < rowptr[a + 1]; t += kBlock) {
@@ -113,7 +113,7 @@ extern "C" wdb_status wdb_set_precond(wdb_theta* th, int32_t kind, double eps, c
     DevBuf<double> scratch(static_cast<size_t>(nwg) * N);
     WDB_HIP(hipMemsetAsync(scratch.p, 0, scratch.bytes(), s));
     hipLaunchKernelGGL(k_hessian_diag, dim3(nwg), dim3(kBlock), 0, s, th->At.slice_off, th->At.val, th->At.col,
-                       th->At.perm, th->At.nslices * kSlice, N,
+                       th->At.perm, th->At.nslices * th->At.C, th->At.C, N,
                        th->csr.rowptr, th->csr.col, th->csr.val, scratch.p, m1.p, m2.p);
     WDB_HIP(hipGetLastError());
     WDB_HIP(hipStreamSynchronize(s));

@@ -42,34 +42,34 @@ __device__ __forceinline__ uint16_t to_f16(float f) {
 }
 
 __global__ void k_band_max(const int64_t* __restrict__ soff, const float* __restrict__ val,
-                           const int32_t* __restrict__ perm, int64_t nslices, int64_t nrows, BandTab T,
+                           const int32_t* __restrict__ perm, int64_t nslices, int C, int64_t nrows, BandTab T,
                            unsigned* __restrict__ bmax) {
   const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (q >= nslices * kSlice) return;
+  if (q >= nslices * C) return;
   const int64_t row = perm ? perm[q] : (q < nrows ? q : -1);
   if (row < 0) return;
-  const int64_t sl = q / kSlice;
-  const int lane = static_cast<int>(q % kSlice);
-  const int64_t base = soff[sl], w = (soff[sl + 1] - base) / kSlice;
+  const int64_t sl = q / C;
+  const int lane = static_cast<int>(q % C);
+  const int64_t base = soff[sl], w = (soff[sl + 1] - base) / C;
   float m = 0.0f;
-  for (int64_t k = 0; k < w; ++k) m = fmaxf(m, fabsf(val[base + (k >> 2) * (4 * kSlice) + lane * 4 + (k & 3)]));
+  for (int64_t k = 0; k < w; ++k) m = fmaxf(m, fabsf(val[sell_index(base, C, lane, k)]));
   if (m > 0.0f) atomicMax(&bmax[band_of(T, row)], __float_as_uint(m));
 }
 
 // by_col = 0: scale by the band of the slot's row (Theta_K); 1: of its column (Theta_K^T).
 __global__ void k_quantize(const int64_t* __restrict__ soff, const float* __restrict__ val,
                            const int32_t* __restrict__ col, const int32_t* __restrict__ perm, int64_t nslices,
-                           int64_t nrows, BandTab T, const float* __restrict__ ub, int by_col, int fmt,
+                           int C, int64_t nrows, BandTab T, const float* __restrict__ ub, int by_col, int fmt,
                            uint16_t* __restrict__ out) {
   const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (q >= nslices * kSlice) return;
+  if (q >= nslices * C) return;
   const int64_t row = perm ? perm[q] : (q < nrows ? q : -1);
-  const int64_t sl = q / kSlice;
-  const int lane = static_cast<int>(q % kSlice);
-  const int64_t base = soff[sl], w = (soff[sl + 1] - base) / kSlice;
+  const int64_t sl = q / C;
+  const int lane = static_cast<int>(q % C);
+  const int64_t base = soff[sl], w = (soff[sl + 1] - base) / C;
   const float urow = row >= 0 ? ub[band_of(T, row)] : 1.0f;
   for (int64_t k = 0; k < w; ++k) {
-    const int64_t idx = base + (k >> 2) * (4 * kSlice) + lane * 4 + (k & 3);
+    const int64_t idx = sell_index(base, C, lane, k);
     const float u = by_col ? ub[band_of(T, col[idx])] : urow;
     const float s = val[idx] * u;  // exact: u is a power of two
     out[idx] = fmt == WDB_VAL_BF16 ? to_bf16(s) : to_f16(s);
@@ -106,11 +106,11 @@ extern "C" wdb_status wdb_set_precision(wdb_theta* th, int32_t valtype) {
   for (int k = 0; k < T.nb; ++k) T.off[k] = lay[k].offset;
   T.off[T.nb] = th->N;
   hipStream_t s = nullptr;
-  const int64_t slotsA = th->A.nslices * kSlice, slotsT = th->At.nslices * kSlice;
+  const int64_t slotsA = th->A.nslices * th->A.C, slotsT = th->At.nslices * th->At.C;
   DevBuf<unsigned> bmax(T.nb);
   WDB_HIP(hipMemset(bmax.p, 0, T.nb * sizeof(unsigned)));
   hipLaunchKernelGGL(k_band_max, dim3((slotsA + 255) / 256), dim3(256), 0, s, th->A.slice_off, th->A.val, th->A.perm,
-                     th->A.nslices, th->N, T, bmax.p);
+                     th->A.nslices, th->A.C, th->N, T, bmax.p);
   WDB_HIP(hipGetLastError());
   std::vector<unsigned> hb(T.nb);
   WDB_HIP(hipMemcpy(hb.data(), bmax.p, T.nb * sizeof(unsigned), hipMemcpyDeviceToHost));
@@ -129,9 +129,9 @@ extern "C" wdb_status wdb_set_precision(wdb_theta* th, int32_t valtype) {
   DevBuf<uint16_t> v16(std::max<int64_t>(th->A.stored, 4)), v16T(std::max<int64_t>(th->At.stored, 4));
   DevBuf<float> wrow(th->N);
   hipLaunchKernelGGL(k_quantize, dim3((slotsA + 255) / 256), dim3(256), 0, s, th->A.slice_off, th->A.val, th->A.col,
-                     th->A.perm, th->A.nslices, th->N, T, dub.p, 0, valtype, v16.p);
+                     th->A.perm, th->A.nslices, th->A.C, th->N, T, dub.p, 0, valtype, v16.p);
   hipLaunchKernelGGL(k_quantize, dim3((slotsT + 255) / 256), dim3(256), 0, s, th->At.slice_off, th->At.val,
-                     th->At.col, th->At.perm, th->At.nslices, th->N, T, dub.p, 1, valtype, v16T.p);
+                     th->At.col, th->At.perm, th->At.nslices, th->At.C, th->N, T, dub.p, 1, valtype, v16T.p);
   hipLaunchKernelGGL(k_row_factor, dim3((th->N + 255) / 256), dim3(256), 0, s, T, dub.p, th->N, wrow.p);
   WDB_HIP(hipGetLastError());
   WDB_HIP(hipDeviceSynchronize());

@@ -7,10 +7,11 @@
 //   k_prox : g = Theta_K^T r; z = y - tau g / P;
 //            x_k = S_{tau lambda / P}(z);
 //            y = x_k + (k-1)/(k+2) (x_k - x_{k-1})   (rest of Alg. 1, fused)
-// Each lane of a wavefront owns one row of a 64-row slice, streams its 16-byte
-// value and index vectors (1 KiB per wavefront step, contiguous), gathers the
-// vector entries through the caches and accumulates in float32 in storage
-// order, so results are bitwise reproducible (no atomics on values).
+// Each thread owns one slot row of a C-row slice (C = 8..64, chosen per
+// operator), streams its 16-byte value and index vectors (16*C contiguous
+// bytes per slice step), gathers the vector entries through the caches and
+// accumulates in float32 in storage order, so results are bitwise
+// reproducible (no atomics on values).
 #include <cmath>
 #include <cstdlib>
 
@@ -21,12 +22,10 @@ namespace wdb {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kSlicesPerBlock = kBlock / kSlice;
+constexpr int kWave = 64;
+constexpr int kWaves = kBlock / kWave;
 constexpr int kRhoChunk = 64;
 
-inline dim3 slice_grid(int64_t nslices) {
-  return dim3(static_cast<unsigned>((nslices + kSlicesPerBlock - 1) / kSlicesPerBlock));
-}
 inline dim3 vec_grid(int64_t n) { return dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock)); }
 
 struct SellView {
@@ -35,16 +34,27 @@ struct SellView {
   const int4* __restrict__ col;
   const int32_t* __restrict__ perm;
   int64_t nslices, nrows;
+  int C, cshift;  // slice height (power of two) and its log2
 };
 
 SellView view(const Sell& m) {
   return SellView{m.slice_off, reinterpret_cast<const float4*>(m.val), reinterpret_cast<const int4*>(m.col),
-                  m.perm, m.nslices, m.nrows};
+                  m.perm, m.nslices, m.nrows, m.C, __builtin_ctz(static_cast<unsigned>(m.C))};
 }
 
-// Matrix row held by lane `lane` of slice `sl` (-1 for an empty slot row).
-__device__ __forceinline__ int64_t slot_row(const SellView& A, int64_t sl, int lane) {
-  const int64_t q = sl * kSlice + lane;
+__host__ __device__ inline int64_t slots(const SellView& A) { return A.nslices << A.cshift; }
+inline dim3 slot_grid(const SellView& A) { return vec_grid(slots(A)); }
+
+// Blocks of the reduction kernels over A and A^T (both copies share the slice
+// height, so every partial-sum slot below this count is written).
+int64_t partial_blocks(const SellView& A, const SellView& At) {
+  const int64_t nb = slot_grid(A).x;
+  WDB_REQUIRE(nb == static_cast<int64_t>(slot_grid(At).x), WDB_ERR_HIP, "mismatched slice heights");
+  return nb;
+}
+
+// Matrix row held by slot row q (-1 for an empty slot row).
+__device__ __forceinline__ int64_t slot_row(const SellView& A, int64_t q) {
   if (A.perm) return A.perm[q];
   return q < A.nrows ? q : -1;
 }
@@ -61,7 +71,7 @@ __device__ __forceinline__ float row_dot_f32(const SellView& A, int64_t sl, int 
   const int64_t beg = A.soff[sl] >> 2, end = A.soff[sl + 1] >> 2;
   float acc = 0.f;
 #pragma unroll 2
-  for (int64_t j = beg + lane; j < end; j += kSlice) {
+  for (int64_t j = beg + lane; j < end; j += A.C) {
     const float4 v = A.val[j];
     const int4 c = A.col[j];
     acc = gather_fma(v.x, c.x, x, acc);
@@ -77,7 +87,7 @@ template <typename T>
 __device__ __forceinline__ double row_dot_f64(const SellView& A, int64_t sl, int lane, const T* __restrict__ x) {
   const int64_t beg = A.soff[sl] >> 2, end = A.soff[sl + 1] >> 2;
   double acc = 0.0;
-  for (int64_t j = beg + lane; j < end; j += kSlice) {
+  for (int64_t j = beg + lane; j < end; j += A.C) {
     const float4 v = A.val[j];
     const int4 c = A.col[j];
     acc = fma(static_cast<double>(v.x), static_cast<double>(x[c.x]), acc);
@@ -92,12 +102,12 @@ __device__ __forceinline__ double row_dot_f64(const SellView& A, int64_t sl, int
 // instead of sum.  Writes partial[k * nblocks + blockIdx.x].
 template <int NV, unsigned MAXMASK>
 __device__ __forceinline__ void block_partials(double (&v)[NV], double* __restrict__ partial, int64_t nblocks) {
-  __shared__ double sh[kSlicesPerBlock][NV];
-  const int lane = threadIdx.x & (kSlice - 1), wid = threadIdx.x / kSlice;
+  __shared__ double sh[kWaves][NV];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     double x = v[k];
-    for (int off = kSlice / 2; off > 0; off >>= 1) {
+    for (int off = kWave / 2; off > 0; off >>= 1) {
       const double y = __shfl_xor(x, off);
       x = ((MAXMASK >> k) & 1u) ? fmax(x, y) : x + y;
     }
@@ -108,7 +118,7 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], double* __restri
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
       double acc = sh[0][k];
-      for (int w = 1; w < kSlicesPerBlock; ++w) acc = ((MAXMASK >> k) & 1u) ? fmax(acc, sh[w][k]) : acc + sh[w][k];
+      for (int w = 1; w < kWaves; ++w) acc = ((MAXMASK >> k) & 1u) ? fmax(acc, sh[w][k]) : acc + sh[w][k];
       partial[k * nblocks + blockIdx.x] = acc;
     }
   }
@@ -120,11 +130,12 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], double* __restri
 __global__ __launch_bounds__(kBlock) void k_res(SellView A, const float* __restrict__ y, const float* __restrict__ b,
                                                 float* __restrict__ r, int* __restrict__ kdev) {
   if (kdev && blockIdx.x == 0 && threadIdx.x == 0) *kdev += 1;
-  const int lane = threadIdx.x & (kSlice - 1);
-  const int64_t sl = static_cast<int64_t>(blockIdx.x) * kSlicesPerBlock + threadIdx.x / kSlice;
-  if (sl >= A.nslices) return;
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (q >= slots(A)) return;
+  const int64_t sl = q >> A.cshift;
+  const int lane = static_cast<int>(q & (A.C - 1));
   const float acc = row_dot_f32(A, sl, lane, y);
-  const int64_t row = slot_row(A, sl, lane);
+  const int64_t row = slot_row(A, q);
   if (row >= 0) r[row] = b ? acc - b[row] : acc;
 }
 
@@ -133,11 +144,12 @@ template <bool PRE>
 __global__ __launch_bounds__(kBlock) void k_prox(SellView At, const float* __restrict__ r, float* __restrict__ x,
                                                  float* __restrict__ y, float tau, float thr, float beta,
                                                  const int* __restrict__ kdev, const float* __restrict__ pinv) {
-  const int lane = threadIdx.x & (kSlice - 1);
-  const int64_t sl = static_cast<int64_t>(blockIdx.x) * kSlicesPerBlock + threadIdx.x / kSlice;
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t sl = q >> At.cshift;
+  const int lane = static_cast<int>(q & (At.C - 1));
   if (sl >= At.nslices) return;
   const float g = row_dot_f32(At, sl, lane, r);
-  const int64_t row = slot_row(At, sl, lane);
+  const int64_t row = slot_row(At, q);
   if (row < 0) return;
   if (kdev) {
     const int k = *kdev;
@@ -169,7 +181,7 @@ __device__ __forceinline__ float row_dot_q(const SellView& A, const uint2* __res
   const int64_t beg = A.soff[sl] >> 2, end = A.soff[sl + 1] >> 2;
   float acc = 0.f;
 #pragma unroll 2
-  for (int64_t j = beg + lane; j < end; j += kSlice) {
+  for (int64_t j = beg + lane; j < end; j += A.C) {
     const uint2 v = v16[j];
     const int4 c = A.col[j];
     acc = fmaf(dq16<FMT>(v.x & 0xFFFFu), x[c.x], acc);
@@ -187,11 +199,12 @@ __global__ __launch_bounds__(kBlock) void k_res_q(SellView A, const uint2* __res
                                                   const float* __restrict__ b, float* __restrict__ r,
                                                   int* __restrict__ kdev, int scale_out) {
   if (kdev && blockIdx.x == 0 && threadIdx.x == 0) *kdev += 1;
-  const int lane = threadIdx.x & (kSlice - 1);
-  const int64_t sl = static_cast<int64_t>(blockIdx.x) * kSlicesPerBlock + threadIdx.x / kSlice;
-  if (sl >= A.nslices) return;
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (q >= slots(A)) return;
+  const int64_t sl = q >> A.cshift;
+  const int lane = static_cast<int>(q & (A.C - 1));
   const float acc = row_dot_q<FMT>(A, v16, sl, lane, y);
-  const int64_t row = slot_row(A, sl, lane);
+  const int64_t row = slot_row(A, q);
   if (row < 0) return;
   const float w = wrow[row];
   const float rr = b ? w * acc - b[row] : w * acc;
@@ -203,11 +216,12 @@ __global__ __launch_bounds__(kBlock) void k_prox_q(SellView At, const uint2* __r
                                                    const float* __restrict__ rs, float* __restrict__ x,
                                                    float* __restrict__ y, float tau, float thr,
                                                    const int* __restrict__ kdev, const float* __restrict__ pinv) {
-  const int lane = threadIdx.x & (kSlice - 1);
-  const int64_t sl = static_cast<int64_t>(blockIdx.x) * kSlicesPerBlock + threadIdx.x / kSlice;
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t sl = q >> At.cshift;
+  const int lane = static_cast<int>(q & (At.C - 1));
   if (sl >= At.nslices) return;
   const float g = row_dot_q<FMT>(At, v16T, sl, lane, rs);
-  const int64_t row = slot_row(At, sl, lane);
+  const int64_t row = slot_row(At, q);
   if (row < 0) return;
   const int k = *kdev;
   const float beta = static_cast<float>((static_cast<double>(k) - 1.0) / (static_cast<double>(k) + 2.0));
@@ -225,13 +239,13 @@ void launch_iteration_q(wdb_theta* th, float* x, bool pre, float tau, float thr,
   const SellView A = view(th->A), At = view(th->At);
   const uint2* v16 = reinterpret_cast<const uint2*>(th->val16);
   const uint2* v16T = reinterpret_cast<const uint2*>(th->val16T);
-  hipLaunchKernelGGL(k_res_q<FMT>, slice_grid(A.nslices), dim3(kBlock), 0, s, A, v16, th->wrow, th->ws_y,
+  hipLaunchKernelGGL(k_res_q<FMT>, slot_grid(A), dim3(kBlock), 0, s, A, v16, th->wrow, th->ws_y,
                      th->ws_x0, th->ws_r, th->ws_k, 1);
   if (pre)
-    hipLaunchKernelGGL((k_prox_q<FMT, true>), slice_grid(At.nslices), dim3(kBlock), 0, s, At, v16T, th->ws_r, x,
+    hipLaunchKernelGGL((k_prox_q<FMT, true>), slot_grid(At), dim3(kBlock), 0, s, At, v16T, th->ws_r, x,
                        th->ws_y, tau, thr, th->ws_k, th->pinv);
   else
-    hipLaunchKernelGGL((k_prox_q<FMT, false>), slice_grid(At.nslices), dim3(kBlock), 0, s, At, v16T, th->ws_r, x,
+    hipLaunchKernelGGL((k_prox_q<FMT, false>), slot_grid(At), dim3(kBlock), 0, s, At, v16T, th->ws_r, x,
                        th->ws_y, tau, thr, th->ws_k, static_cast<const float*>(nullptr));
 }
 
@@ -311,10 +325,14 @@ void launch_prox_csr(const CsrView& At, const float* r, float* x, float* y, floa
     hipLaunchKernelGGL((k_prox_csr<G, false>), grid, dim3(kBlock), 0, s, At, r, x, y, tau, thr, beta, kdev, pinv);
 }
 
-// r = A y - b with the configured kernel family.
-void launch_res(const Sell& sell, const Csr32& csr, const float* y, const float* b, float* r, int* kdev,
+}  // namespace
+
+int kernel_group(const wdb_theta* th) { return th->spmv_group >= 0 ? th->spmv_group : spmv_group(); }
+
+// r = A y - b with the kernel family G (0: sliced ELL; else vector CSR, G lanes per row).
+void launch_res(int G, const Sell& sell, const Csr32& csr, const float* y, const float* b, float* r, int* kdev,
                 hipStream_t s) {
-  switch (spmv_group()) {
+  switch (G) {
     case 2: launch_res_csr<2>(cview(csr), y, b, r, kdev, s); return;
     case 4: launch_res_csr<4>(cview(csr), y, b, r, kdev, s); return;
     case 8: launch_res_csr<8>(cview(csr), y, b, r, kdev, s); return;
@@ -323,14 +341,14 @@ void launch_res(const Sell& sell, const Csr32& csr, const float* y, const float*
     case 64: launch_res_csr<64>(cview(csr), y, b, r, kdev, s); return;
     default: {
       const SellView A = view(sell);
-      hipLaunchKernelGGL(k_res, slice_grid(A.nslices), dim3(kBlock), 0, s, A, y, b, r, kdev);
+      hipLaunchKernelGGL(k_res, slot_grid(A), dim3(kBlock), 0, s, A, y, b, r, kdev);
     }
   }
 }
 
-void launch_prox(const Sell& sell, const Csr32& csr, const float* r, float* x, float* y, float tau, float thr,
+void launch_prox(int G, const Sell& sell, const Csr32& csr, const float* r, float* x, float* y, float tau, float thr,
                  float beta, const int* kdev, const float* pinv, hipStream_t s) {
-  switch (spmv_group()) {
+  switch (G) {
     case 2: launch_prox_csr<2>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, s); return;
     case 4: launch_prox_csr<4>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, s); return;
     case 8: launch_prox_csr<8>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, s); return;
@@ -340,14 +358,16 @@ void launch_prox(const Sell& sell, const Csr32& csr, const float* r, float* x, f
     default: {
       const SellView At = view(sell);
       if (pinv)
-        hipLaunchKernelGGL(k_prox<true>, slice_grid(At.nslices), dim3(kBlock), 0, s, At, r, x, y, tau, thr, beta,
+        hipLaunchKernelGGL(k_prox<true>, slot_grid(At), dim3(kBlock), 0, s, At, r, x, y, tau, thr, beta,
                            kdev, pinv);
       else
-        hipLaunchKernelGGL(k_prox<false>, slice_grid(At.nslices), dim3(kBlock), 0, s, At, r, x, y, tau, thr,
+        hipLaunchKernelGGL(k_prox<false>, slot_grid(At), dim3(kBlock), 0, s, At, r, x, y, tau, thr,
                            beta, kdev, pinv);
     }
   }
 }
+
+namespace {
 
 // ---------------------------------------------------------------------------
 // Float64 objective and duality gap.
@@ -355,12 +375,13 @@ void launch_prox(const Sell& sell, const Csr32& csr, const float* r, float* x, f
 __global__ __launch_bounds__(kBlock) void k_obj_fwd(SellView A, const float* __restrict__ x, const float* __restrict__ b,
                                                     double* __restrict__ r64, double* __restrict__ partial,
                                                     int64_t nblocks) {
-  const int lane = threadIdx.x & (kSlice - 1);
-  const int64_t sl = static_cast<int64_t>(blockIdx.x) * kSlicesPerBlock + threadIdx.x / kSlice;
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t sl = q >> A.cshift;
+  const int lane = static_cast<int>(q & (A.C - 1));
   double v[3] = {0.0, 0.0, 0.0};
-  if (sl < A.nslices) {
+  if (q < slots(A)) {
     const double acc = row_dot_f64(A, sl, lane, x);
-    const int64_t row = slot_row(A, sl, lane);
+    const int64_t row = slot_row(A, q);
     if (row >= 0) {
       const double bb = static_cast<double>(b[row]);
       const double rr = acc - bb;
@@ -375,11 +396,12 @@ __global__ __launch_bounds__(kBlock) void k_obj_fwd(SellView A, const float* __r
 
 __global__ __launch_bounds__(kBlock) void k_obj_bwd(SellView At, const double* __restrict__ r64,
                                                     double* __restrict__ partial, int64_t nblocks) {
-  const int lane = threadIdx.x & (kSlice - 1);
-  const int64_t sl = static_cast<int64_t>(blockIdx.x) * kSlicesPerBlock + threadIdx.x / kSlice;
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t sl = q >> At.cshift;
+  const int lane = static_cast<int>(q & (At.C - 1));
   double v[1] = {0.0};
-  if (sl < At.nslices) {
-    const int64_t row = slot_row(At, sl, lane);
+  if (q < slots(At)) {
+    const int64_t row = slot_row(At, q);
     const double g = row_dot_f64(At, sl, lane, r64);
     if (row >= 0) v[0] = fabs(g);
   }
@@ -413,11 +435,12 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ pa
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_pi_fwd(SellView A, const double* __restrict__ vd, double* __restrict__ w,
                                                    double* __restrict__ partial, int64_t nblocks) {
-  const int lane = threadIdx.x & (kSlice - 1);
-  const int64_t sl = static_cast<int64_t>(blockIdx.x) * kSlicesPerBlock + threadIdx.x / kSlice;
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t sl = q >> A.cshift;
+  const int lane = static_cast<int>(q & (A.C - 1));
   double v[1] = {0.0};
-  if (sl < A.nslices) {
-    const int64_t row = slot_row(A, sl, lane);
+  if (q < slots(A)) {
+    const int64_t row = slot_row(A, q);
     const double acc = row_dot_f64(A, sl, lane, vd);
     if (row >= 0) {
       w[row] = acc;
@@ -430,11 +453,12 @@ __global__ __launch_bounds__(kBlock) void k_pi_fwd(SellView A, const double* __r
 __global__ __launch_bounds__(kBlock) void k_pi_bwd(SellView At, const double* __restrict__ w,
                                                    const double* __restrict__ d, double* __restrict__ u,
                                                    double* __restrict__ partial, int64_t nblocks) {
-  const int lane = threadIdx.x & (kSlice - 1);
-  const int64_t sl = static_cast<int64_t>(blockIdx.x) * kSlicesPerBlock + threadIdx.x / kSlice;
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  const int64_t sl = q >> At.cshift;
+  const int lane = static_cast<int>(q & (At.C - 1));
   double v[1] = {0.0};
-  if (sl < At.nslices) {
-    const int64_t row = slot_row(At, sl, lane);
+  if (q < slots(At)) {
+    const int64_t row = slot_row(At, q);
     double acc = row_dot_f64(At, sl, lane, w);
     if (row >= 0) {
       if (d) acc *= d[row];
@@ -507,7 +531,8 @@ uint64_t splitmix64(uint64_t& state) {
 void ensure_workspace(wdb_theta* th) {
   if (th->ws_x0) return;
   const int64_t N = th->N;
-  const int64_t nb = (th->A.nslices + kSlicesPerBlock - 1) / kSlicesPerBlock;
+  // enough partial-sum blocks for any slice height up to 64
+  const int64_t nb = (N + 64 + kBlock - 1) / kBlock;
   th->ws_nblocks = std::max<int64_t>(nb, 1);
   try {
     WDB_HIP(hipMalloc(reinterpret_cast<void**>(&th->ws_x0), N * sizeof(float)));
@@ -555,7 +580,7 @@ double power_iteration(wdb_theta* th, const double* start_host, const double* di
   WDB_HIP(hipMemcpyAsync(vd, v.data(), N * sizeof(double), hipMemcpyHostToDevice, s));
   if (dinv_sqrt) hipLaunchKernelGGL(k_mul, vec_grid(N), dim3(kBlock), 0, s, vd, dinv_sqrt, N);
   const SellView A = view(th->A), At = view(th->At);
-  const int64_t nb = th->ws_nblocks;
+  const int64_t nb = partial_blocks(A, At);
   double* part = th->ws_partial;
   std::vector<double> hist(kRhoChunk);
   double prev = 0.0, rho = 0.0;
@@ -563,8 +588,8 @@ double power_iteration(wdb_theta* th, const double* start_host, const double* di
   while (k < max_iters) {
     const int m = std::min(kRhoChunk, max_iters - k);
     for (int j = 0; j < m; ++j) {
-      hipLaunchKernelGGL(k_pi_fwd, slice_grid(A.nslices), dim3(kBlock), 0, s, A, vd, w, part, nb);
-      hipLaunchKernelGGL(k_pi_bwd, slice_grid(At.nslices), dim3(kBlock), 0, s, At, w, dinv_sqrt, u, part + nb, nb);
+      hipLaunchKernelGGL(k_pi_fwd, slot_grid(A), dim3(kBlock), 0, s, A, vd, w, part, nb);
+      hipLaunchKernelGGL(k_pi_bwd, slot_grid(At), dim3(kBlock), 0, s, At, w, dinv_sqrt, u, part + nb, nb);
       hipLaunchKernelGGL(k_pi_finish, dim3(1), dim3(kBlock), 0, s, part, nb, th->ws_rho, j, th->ws_scalar);
       hipLaunchKernelGGL(k_pi_scale, vec_grid(N), dim3(kBlock), 0, s, u, dinv_sqrt, th->ws_scalar, vd, N);
     }
@@ -595,10 +620,10 @@ struct Check {
 
 Check objective_check(wdb_theta* th, const float* x, const float* x0, double lambda, hipStream_t s) {
   const SellView A = view(th->A), At = view(th->At);
-  const int64_t nb = th->ws_nblocks;
+  const int64_t nb = partial_blocks(A, At);
   double* part = th->ws_partial;
-  hipLaunchKernelGGL(k_obj_fwd, slice_grid(A.nslices), dim3(kBlock), 0, s, A, x, x0, th->ws_r64, part, nb);
-  hipLaunchKernelGGL(k_obj_bwd, slice_grid(At.nslices), dim3(kBlock), 0, s, At, th->ws_r64, part + 3 * nb, nb);
+  hipLaunchKernelGGL(k_obj_fwd, slot_grid(A), dim3(kBlock), 0, s, A, x, x0, th->ws_r64, part, nb);
+  hipLaunchKernelGGL(k_obj_bwd, slot_grid(At), dim3(kBlock), 0, s, At, th->ws_r64, part + 3 * nb, nb);
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, part, nb, 4, 0x8u, th->ws_scalar);
   WDB_HIP(hipGetLastError());
   WDB_HIP(hipMemcpyAsync(th->host_scalar, th->ws_scalar, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -614,8 +639,9 @@ Check objective_check(wdb_theta* th, const float* x, const float* x0, double lam
 void launch_iteration(wdb_theta* th, float* x, bool pre, float tau, float thr, hipStream_t s) {
   if (th->valtype == WDB_VAL_BF16) return launch_iteration_q<WDB_VAL_BF16>(th, x, pre, tau, thr, s);
   if (th->valtype == WDB_VAL_F16) return launch_iteration_q<WDB_VAL_F16>(th, x, pre, tau, thr, s);
-  launch_res(th->A, th->cA, th->ws_y, th->ws_x0, th->ws_r, th->ws_k, s);
-  launch_prox(th->At, th->cAt, th->ws_r, x, th->ws_y, tau, thr, 0.0f, th->ws_k, pre ? th->pinv : nullptr, s);
+  const int G = kernel_group(th);
+  launch_res(G, th->A, th->cA, th->ws_y, th->ws_x0, th->ws_r, th->ws_k, s);
+  launch_prox(G, th->At, th->cAt, th->ws_r, x, th->ws_y, tau, thr, 0.0f, th->ws_k, pre ? th->pinv : nullptr, s);
 }
 
 void ensure_lipschitz(wdb_theta* th, hipStream_t s) {
@@ -789,17 +815,18 @@ wdb_status wdb_theta_apply(wdb_theta* th, int32_t transpose, const float* x, con
     const uint2* v16 = reinterpret_cast<const uint2*>(th->val16);
     for (int i = 0; i < repeat; ++i) {
       if (th->valtype == WDB_VAL_BF16)
-        hipLaunchKernelGGL(wdb::k_res_q<WDB_VAL_BF16>, wdb::slice_grid(A.nslices), dim3(wdb::kBlock), 0, s, A, v16,
+        hipLaunchKernelGGL(wdb::k_res_q<WDB_VAL_BF16>, wdb::slot_grid(A), dim3(wdb::kBlock), 0, s, A, v16,
                            th->wrow, x, b, y, static_cast<int*>(nullptr), 0);
       else
-        hipLaunchKernelGGL(wdb::k_res_q<WDB_VAL_F16>, wdb::slice_grid(A.nslices), dim3(wdb::kBlock), 0, s, A, v16,
+        hipLaunchKernelGGL(wdb::k_res_q<WDB_VAL_F16>, wdb::slot_grid(A), dim3(wdb::kBlock), 0, s, A, v16,
                            th->wrow, x, b, y, static_cast<int*>(nullptr), 0);
     }
     WDB_HIP(hipGetLastError());
     return WDB_OK;
   }
   for (int i = 0; i < repeat; ++i)
-    wdb::launch_res(transpose ? th->At : th->A, transpose ? th->cAt : th->cA, x, b, y, nullptr, s);
+    wdb::launch_res(wdb::kernel_group(th), transpose ? th->At : th->A, transpose ? th->cAt : th->cA, x, b, y, nullptr,
+                    s);
   WDB_HIP(hipGetLastError());
   WDB_API_END
 }
@@ -813,7 +840,8 @@ wdb_status wdb_prox_step(wdb_theta* th, const float* r, float* x, float* y, floa
   WDB_HIP(hipSetDevice(th->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
   const float thr = tau * lambda;
-  wdb::launch_prox(th->At, th->cAt, r, x, y, tau, thr, beta, nullptr, use_precond ? th->pinv : nullptr, s);
+  wdb::launch_prox(wdb::kernel_group(th), th->At, th->cAt, r, x, y, tau, thr, beta, nullptr,
+                   use_precond ? th->pinv : nullptr, s);
   WDB_HIP(hipGetLastError());
   WDB_API_END
 }

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #include "common.hpp"
 
@@ -59,15 +60,15 @@ __global__ void k_row_lengths(const int64_t* __restrict__ rowptr, int64_t N, int
 
 // One thread per slot row q: copies matrix row perm[q] (or q) into the slice.
 __global__ void k_fill_sell(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ ccol,
-                            const double* __restrict__ cval, int64_t N, int64_t nslices,
+                            const double* __restrict__ cval, int64_t N, int64_t nslices, int C,
                             const int64_t* __restrict__ soff, const int32_t* __restrict__ perm,
                             float* __restrict__ val, int32_t* __restrict__ col) {
   const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (q >= nslices * kSlice) return;
-  const int64_t sl = q / kSlice;
-  const int lane = static_cast<int>(q % kSlice);
+  if (q >= nslices * C) return;
+  const int64_t sl = q / C;
+  const int lane = static_cast<int>(q % C);
   const int64_t base = soff[sl];
-  const int64_t w = (soff[sl + 1] - base) / kSlice;
+  const int64_t w = (soff[sl + 1] - base) / C;
   const int64_t r = perm ? static_cast<int64_t>(perm[q]) : (q < N ? q : -1);
   int64_t beg = 0, len = 0;
   if (r >= 0) {
@@ -76,7 +77,7 @@ __global__ void k_fill_sell(const int64_t* __restrict__ rowptr, const int32_t* _
   }
   const int32_t pad_col = len ? ccol[beg + len - 1] : static_cast<int32_t>(r >= 0 ? r : 0);
   for (int64_t k = 0; k < w; ++k) {
-    const int64_t idx = base + (k >> 2) * (4 * kSlice) + lane * 4 + (k & 3);
+    const int64_t idx = sell_index(base, C, lane, k);
     if (k < len) {
       val[idx] = static_cast<float>(cval[beg + k]);
       col[idx] = ccol[beg + k];
@@ -145,11 +146,14 @@ void csr_transpose(const Csr& a, Csr* out, hipStream_t s) {
   coo_to_csr(a.nrows, a.nnz, a.col, rows.p, a.val, out, s);
 }
 
-void csr_to_sell(const Csr& a, Sell* out, hipStream_t s, int64_t sort_window) {
+void csr_to_sell(const Csr& a, Sell* out, hipStream_t s, int64_t sort_window, int C) {
+  WDB_REQUIRE(C >= 1 && C <= kSliceMax && (C & (C - 1)) == 0, WDB_ERR_ARG, "slice height %d is not a power of two <= %d",
+              C, kSliceMax);
   Sell m;
+  m.C = C;
   m.nrows = a.nrows;
-  m.nslices = (a.nrows + kSlice - 1) / kSlice;
-  const int64_t slots = m.nslices * kSlice;
+  m.nslices = (a.nrows + C - 1) / C;
+  const int64_t slots = m.nslices * C;
   std::vector<int32_t> len(a.nrows);
   if (a.nrows) {
     DevBuf<int32_t> dlen(a.nrows);
@@ -161,9 +165,9 @@ void csr_to_sell(const Csr& a, Sell* out, hipStream_t s, int64_t sort_window) {
   // slot row -> matrix row: identity, or sorted by decreasing length inside
   // windows of sort_window rows (stable, so equal lengths keep their order)
   std::vector<int32_t> perm;
-  const bool sorted = sort_window > kSlice;
+  const bool sorted = sort_window > C;
   if (sorted) {
-    const int64_t W = (sort_window + kSlice - 1) / kSlice * kSlice;
+    const int64_t W = (sort_window + C - 1) / C * C;
     perm.assign(slots, -1);
     std::vector<int32_t> idx;
     for (int64_t w0 = 0; w0 < a.nrows; w0 += W) {
@@ -177,12 +181,12 @@ void csr_to_sell(const Csr& a, Sell* out, hipStream_t s, int64_t sort_window) {
   std::vector<int64_t> off(m.nslices + 1, 0);
   for (int64_t sl = 0; sl < m.nslices; ++sl) {
     int64_t w = 0;
-    for (int l = 0; l < kSlice; ++l) {
-      const int64_t q = sl * kSlice + l;
+    for (int l = 0; l < C; ++l) {
+      const int64_t q = sl * C + l;
       const int64_t r = sorted ? perm[q] : (q < a.nrows ? q : -1);
       if (r >= 0) w = std::max<int64_t>(w, len[r]);
     }
-    off[sl + 1] = off[sl] + ((w + 3) & ~int64_t(3)) * kSlice;
+    off[sl + 1] = off[sl] + ((w + 3) & ~int64_t(3)) * C;
   }
   m.stored = off[m.nslices];
   DevBuf<int64_t> soff(m.nslices + 1);
@@ -191,7 +195,7 @@ void csr_to_sell(const Csr& a, Sell* out, hipStream_t s, int64_t sort_window) {
   DevBuf<int32_t> col(std::max<int64_t>(m.stored, 4));
   WDB_HIP(hipMemcpyAsync(soff.p, off.data(), (m.nslices + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
   if (sorted) WDB_HIP(hipMemcpyAsync(dperm.p, perm.data(), slots * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_fill_sell, blocks_for(slots), dim3(256), 0, s, a.rowptr, a.col, a.val, a.nrows, m.nslices,
+  hipLaunchKernelGGL(k_fill_sell, blocks_for(slots), dim3(256), 0, s, a.rowptr, a.col, a.val, a.nrows, m.nslices, C,
                      soff.p, sorted ? dperm.p : static_cast<const int32_t*>(nullptr), val.p, col.p);
   WDB_HIP(hipGetLastError());
   WDB_HIP(hipStreamSynchronize(s));
@@ -224,13 +228,37 @@ void csr_to_csr32(const Csr& a, Csr32* out, hipStream_t s) {
   *out = c;
 }
 
+int default_slice_height() {
+  static const int c = [] {
+    const char* e = std::getenv("WDB_SLICE");
+    const int v = e ? std::atoi(e) : kSliceMax;
+    return (v >= 1 && v <= kSliceMax && (v & (v - 1)) == 0) ? v : kSliceMax;
+  }();
+  return c;
+}
+
+void set_slice_height(wdb_theta* th, int C, hipStream_t s) {
+  if (th->A.val && th->A.C == C && th->At.val && th->At.C == C) return;
+  csr_to_sell(th->csr, &th->A, s, sell_sort_window(), C);
+  Csr t;
+  try {
+    csr_transpose(th->csr, &t, s);
+    csr_to_sell(t, &th->At, s, sell_sort_window(), C);
+  } catch (...) {
+    t.free_all();
+    throw;
+  }
+  t.free_all();
+}
+
 void finish_theta(wdb_theta* th, hipStream_t s) {
-  csr_to_sell(th->csr, &th->A, s, sell_sort_window());
+  const int C = default_slice_height();
+  csr_to_sell(th->csr, &th->A, s, sell_sort_window(), C);
   csr_to_csr32(th->csr, &th->cA, s);
   Csr t;
   try {
     csr_transpose(th->csr, &t, s);
-    csr_to_sell(t, &th->At, s, sell_sort_window());
+    csr_to_sell(t, &th->At, s, sell_sort_window(), C);
     csr_to_csr32(t, &th->cAt, s);
   } catch (...) {
     t.free_all();

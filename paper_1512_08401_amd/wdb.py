@@ -88,12 +88,23 @@ _SIGS = {
     "wdb_blur": [C.POINTER(PsfFieldC), _vp, _vp, _vp],
     "wdb_wavelet_filter": [_i32, _pd, C.POINTER(_i32)],
     "wdb_set_precision": [_vp, _i32],
+    "wdb_set_kernel_layout": [_vp, _i32, _i32],
+    "wdb_autotune": [_vp, C.c_char_p, _i32, C.POINTER(_i32), C.POINTER(_i32), _pd],
+    "wdb_cnn_create": [_i32, _i32, _i32, C.c_uint64, C.POINTER(_vp)],
+    "wdb_cnn_param_count": [_vp, C.POINTER(_i64)],
+    "wdb_cnn_set_params": [_vp, _vp, _i64],
+    "wdb_cnn_get_params": [_vp, _vp, _i32],
+    "wdb_cnn_predict": [_vp, _vp, _i32, _vp, _vp],
+    "wdb_cnn_loss_grad": [_vp, _vp, _vp, _i32, _pd, _vp, _vp],
+    "wdb_cnn_train_step": [_vp, _vp, _vp, _i32, _f32, _pd, _vp],
     "wdb_solve_batched": [_i32, C.POINTER(ProblemC), C.POINTER(SolveOpts), C.POINTER(SolveInfo)],
 }
 for _name, _args in _SIGS.items():
     _fn = getattr(_lib, _name)
     _fn.argtypes = _args
     _fn.restype = C.c_int
+_lib.wdb_cnn_free.argtypes = [_vp]
+_lib.wdb_cnn_free.restype = None
 _lib.wdb_theta_free.argtypes = [_vp]
 _lib.wdb_theta_free.restype = None
 _lib.wdb_last_error.restype = C.c_char_p
@@ -229,6 +240,16 @@ class Theta:
         p, keep = _f64ptr(start)
         _check("wdb_set_precond", _lib.wdb_set_precond(self._h, PRECOND[kind], eps, p, tol, max_iters))
 
+    def set_kernel_layout(self, slice: int = 64, group: int = 0):
+        _check("wdb_set_kernel_layout", _lib.wdb_set_kernel_layout(self._h, slice, group))
+
+    def autotune(self, cache_path: str | None = None, reps: int = 20):
+        """Pick the fastest iteration layout for this operator; returns (slice, group, us)."""
+        c, g, us = C.c_int32(), C.c_int32(), C.c_double()
+        _check("wdb_autotune", _lib.wdb_autotune(self._h, cache_path.encode() if cache_path else None, reps,
+                                                 C.byref(c), C.byref(g), C.byref(us)))
+        return c.value, g.value, us.value
+
     def set_precision(self, valtype: str):
         """Iteration values in float32, bfloat16 or binary16 ("f32" | "bf16" | "f16")."""
         _check("wdb_set_precision", _lib.wdb_set_precision(self._h, VALTYPES[valtype]))
@@ -309,6 +330,58 @@ class Theta:
         _check("wdb_synthesize", _lib.wdb_synthesize(self._h, _dev(x, n * n, "x"), _dev(u, n * n, "u_hat"),
                                                      _stream(stream)))
         return u
+
+
+class Cnn:
+    """Owns a wdb_cnn handle (warm-start network)."""
+
+    def __init__(self, n: int, levels: int, features: int = 32, seed: int = 0):
+        self._h = C.c_void_p()
+        _check("wdb_cnn_create", _lib.wdb_cnn_create(n, levels, features, seed, C.byref(self._h)))
+        self.n, self.N = n, n * n
+        cnt = C.c_int64()
+        _check("wdb_cnn_param_count", _lib.wdb_cnn_param_count(self._h, C.byref(cnt)))
+        self.nparam = cnt.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.wdb_cnn_free(h)
+            self._h = None
+
+    def set_params(self, p):
+        a = np.ascontiguousarray(np.asarray(p, dtype=np.float32))
+        _check("wdb_cnn_set_params", _lib.wdb_cnn_set_params(self._h, C.c_void_p(a.ctypes.data), a.size))
+
+    def get_params(self, rounded: bool = False) -> np.ndarray:
+        out = np.zeros(self.nparam, dtype=np.float32)
+        _check("wdb_cnn_get_params", _lib.wdb_cnn_get_params(self._h, C.c_void_p(out.ctypes.data), int(rounded)))
+        return out
+
+    def predict(self, x0, out=None, stream=None):
+        torch = _torch()
+        B = x0.numel() // self.N
+        y = torch.empty_like(x0) if out is None else out
+        _check("wdb_cnn_predict", _lib.wdb_cnn_predict(self._h, _dev(x0, B * self.N, "x0"), B,
+                                                       _dev(y, B * self.N, "out"), _stream(stream)))
+        return y
+
+    def loss_grad(self, x0, target, stream=None):
+        B = x0.numel() // self.N
+        loss = C.c_double()
+        g = np.zeros(self.nparam, dtype=np.float32)
+        _check("wdb_cnn_loss_grad", _lib.wdb_cnn_loss_grad(self._h, _dev(x0, B * self.N, "x0"),
+                                                           _dev(target, B * self.N, "target"), B, C.byref(loss),
+                                                           C.c_void_p(g.ctypes.data), _stream(stream)))
+        return loss.value, g
+
+    def train_step(self, x0, target, lr: float, stream=None) -> float:
+        B = x0.numel() // self.N
+        loss = C.c_double()
+        _check("wdb_cnn_train_step", _lib.wdb_cnn_train_step(self._h, _dev(x0, B * self.N, "x0"),
+                                                             _dev(target, B * self.N, "target"), B, lr,
+                                                             C.byref(loss), _stream(stream)))
+        return loss.value
 
 
 def solve_batched(problems, iters: int, check_every: int = 20, tol: float = 0.0, k0: int = 1,

@@ -413,8 +413,10 @@ def test_batched_matches_oracle_per_problem(W, p64, small32):
         L, _ = lipschitz.lipschitz(A32, start)
         xo, _, _ = fista.fista(A32, x0, lam, 1.0 / L, 150)
         _gate(A32, x0, lam, host(xs[i]), xo, fista.objective(A32, x0, lam, xo))
+        # the GPU scores against its float32 transform of u0, the oracle against
+        # the float64 one: ~1e-7 relative in x0, ~1e-8 in E
         E, _, _, rel = fista.duality_gap(A32, x0, lam, host(xs[i]))
-        assert abs(infos[i]["objective"] - E) <= 1e-9 * E and abs(infos[i]["rel_gap"] - rel) <= 1e-8
+        assert abs(infos[i]["objective"] - E) <= 1e-6 * E and abs(infos[i]["rel_gap"] - rel) <= 1e-6
     # per-problem stop flags: every problem ends below the tolerance, frozen at its own check
     xs, infos = W.solve_batched(probs, 3000, check_every=20, tol=2e-3)
     assert all(r["converged"] for r in infos)
@@ -423,3 +425,47 @@ def test_batched_matches_oracle_per_problem(W, p64, small32):
     for i, (A32, x0, lam, start) in enumerate(oracle_inputs):
         _, _, _, rel = fista.duality_gap(A32, x0, lam, host(xs[i]))
         assert rel <= 2e-3 * (1 + 1e-6)
+
+
+# ---------------------------------------------------------------------------
+# kernel layouts and the autotuner
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("slice_h,group", [(8, 0), (16, 0), (32, 0), (64, 0), (64, 4), (64, 8), (8, 16)])
+def test_layouts_match_oracle(W, p64, slice_h, group):
+    th = imported(W, p64)
+    th.set_kernel_layout(slice_h, group)
+    A32 = p64["A32"]
+    rng = np.random.default_rng(slice_h + group)
+    x = rng.standard_normal(4096).astype(np.float32)
+    y = host(th.apply(dev(x), None))
+    assert np.max(np.abs(y - A32 @ x)) <= 1e-5 * np.max(np.abs(A32 @ x))
+    yt = host(th.apply(dev(x), None, transpose=True))
+    assert np.max(np.abs(yt - A32.T @ x)) <= 1e-5 * np.max(np.abs(A32.T @ x))
+    wl = p64["wl"]
+    th.lipschitz(synth.power_start(4096, wl.power_seed))
+    x0 = p64["x0"].astype(np.float32)
+    xg, _ = th.solve_coeffs(dev(x0), wl.lam, 200, check_every=50)
+    x_o, E_o = _oracle_fista(p64, 200)
+    _gate(A32, x0.astype(np.float64), float(np.float32(wl.lam)), host(xg), x_o, E_o)
+    # the 16-bit path and the preconditioner follow the slot layout
+    th.set_precision("bf16")
+    xb, _ = th.solve_coeffs(dev(x0), wl.lam, 20, check_every=0)
+    assert np.all(np.isfinite(host(xb)))
+    th.set_precond("spai_scale", start=synth.power_start(4096, wl.power_seed))
+    po = precond.spai_grouped(A32, precond.scale_groups(64, 3))
+    assert np.max(np.abs(th.precond() - po) / po) <= 1e-10
+
+
+def test_autotune_picks_a_layout_and_keeps_parity(W, p64, tmp_path):
+    th = imported(W, p64)
+    cache = str(tmp_path / "tune.txt")
+    c, g, us = th.autotune(cache, reps=5)
+    assert c in (8, 16, 32, 64) and g in (0, 4, 8, 16) and us > 0
+    c2, g2, us2 = th.autotune(cache, reps=5)           # served from the cache
+    assert (c2, g2, us2) == (c, g, pytest.approx(us, rel=1e-6))
+    wl = p64["wl"]
+    th.lipschitz(synth.power_start(4096, wl.power_seed))
+    x0 = p64["x0"].astype(np.float32)
+    xg, _ = th.solve_coeffs(dev(x0), wl.lam, 200, check_every=50)
+    x_o, E_o = _oracle_fista(p64, 200)
+    _gate(p64["A32"], x0.astype(np.float64), float(np.float32(wl.lam)), host(xg), x_o, E_o)
