@@ -82,6 +82,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance measurement")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default kernel layout")
+    ap.add_argument("--form", default="plain", choices=["plain", "batched", "learned"],
+                    help="plain: the single-problem solve (default); batched / learned: the extension workloads")
+    ap.add_argument("--train-images", type=int, default=4096)
+    ap.add_argument("--heldout-images", type=int, default=512)
+    ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -95,6 +101,10 @@ def main():
     from paper_1512_08401_amd import wdb
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.form != "plain":
+        res = run_batched(args) if args.form == "batched" else run_learned(args)
+        print(json.dumps(res), flush=True)
+        return
     dev = torch.device("cuda:0")
     wl = synth.WORKLOADS[args.workload]
     iters = wl.iters if args.iters is None else args.iters
@@ -116,6 +126,11 @@ def main():
     t0 = time.perf_counter()
     L, l_iters = th.lipschitz(synth.power_start(N, wl.power_seed))
     t_lip = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    if not args.no_autotune:
+        th.autotune(reps=10)
+    layout = (th.info()["slice"], th.info()["group"])
+    t_tune = time.perf_counter() - t0
     info = th.info()
     log(f"Theta_K built in {t_build:.2f} s (nnz {info['nnz']}, stored {info['stored']}), "
         f"L = {L:.9f} in {l_iters} power iterations / {t_lip:.2f} s")
@@ -162,6 +177,17 @@ def main():
     kt1.record(stream)
     torch.cuda.synchronize()
     kt_us = kt0.elapsed_time(kt1) * 1e3 / reps
+    half_us = {}
+    for vt in ("bf16", "f16"):
+        th.set_precision(vt)
+        th.apply(y, u0, out=r, repeat=20)
+        h0, h1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        h0.record(stream)
+        th.apply(y, u0, out=r, repeat=reps)
+        h1.record(stream)
+        torch.cuda.synchronize()
+        half_us[vt] = h0.elapsed_time(h1) * 1e3 / reps
+    th.set_precision("f32")
     nnz = info["nnz"]
     alg_bytes = 8 * nnz + 12 * N          # values + indices once, y/x0 read once, r written once
     achieved = alg_bytes / (k_us * 1e-6) / 1e9
@@ -169,7 +195,10 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "kernel": "k_res (r = Theta_K y - x0, sliced-ELL float32)",
                 "kernel_us": round(k_us, 2), "algorithmic_bytes": alg_bytes,
-                "stored_slots": info["stored"], "transpose_kernel_us": round(kt_us, 2)}
+                "stored_slots": info["stored"], "transpose_kernel_us": round(kt_us, 2),
+                "layout": {"slice": layout[0], "lanes_per_row": layout[1]},
+                "k_res_16bit_us": {k: round(v, 2) for k, v in half_us.items()},
+                "k_res_16bit_gbs": {k: round((6 * nnz + 12 * N) / (v * 1e-6) / 1e9, 1) for k, v in half_us.items()}}
 
     ttt = None if args.no_ttt else time_to_tolerance(th, u0, wl, torch, wdb, synth, N)
 
@@ -190,6 +219,7 @@ def main():
                    "n": n, "nnz": nnz, "iters_per_step": iters},
         "spmv_gbps": round(achieved, 1),
         "offline": {"theta_build_s": round(t_build, 3), "lipschitz_s": round(t_lip, 3),
+                    "autotune_s": round(t_tune, 3),
                     "lipschitz_iters": l_iters, "L": L},
         "final_objective": E, "final_rel_gap": rel_gap,
         "roofline": roofline,
@@ -216,13 +246,16 @@ def time_to_tolerance(th, u0, wl, torch, wdb, synth, N, target=1e-4):
     Estar, gap_star = inf["objective"], inf["rel_gap"]
     res = {"E_star": Estar, "E_star_rel_gap": gap_star, "E0": E0, "target": target}
     stream = torch.cuda.current_stream()
-    for form, pre in (("plain_f32", False), ("spai_scale_f32", True)):
+    forms = (("plain_f32", False, "f32"), ("spai_scale_f32", True, "f32"), ("plain_bf16", False, "bf16"),
+             ("spai_scale_bf16", True, "bf16"), ("plain_f16", False, "f16"))
+    for form, pre, vt in forms:
+        th.set_precision(vt)
         cap = 4000
         _, tr = th.solve(u0, wl.lam, cap, check_every=10, precond=pre, trace_cap=cap // 10)
         rho = (tr["trace"][:, 1] - Estar) / E0
         hit = np.nonzero(rho <= target)[0]
         if hit.size == 0:
-            res[form] = {"reached": False, "iters_checked": cap}
+            res[form] = {"reached": False, "iters_checked": cap, "best_rel_objective": float(rho.min())}
             continue
         k = int(tr["trace"][hit[0], 0])
         x = torch.empty(N, device=u0.device)
@@ -235,8 +268,133 @@ def time_to_tolerance(th, u0, wl, torch, wdb, synth, N, target=1e-4):
         torch.cuda.synchronize()
         res[form] = {"reached": True, "iters": k, "seconds": e0.elapsed_time(e1) / 1e3,
                      "rel_objective": (fin["objective"] - Estar) / E0}
+    th.set_precision("f32")
     th.set_precond("none")
     return res
+
+
+def _observe(wdb, torch, field, n, seed, noise_seed, sigma):
+    img = torch.as_tensor(__import__("synth").piecewise_image(n, seed).astype(np.float32), device="cuda")
+    b = torch.as_tensor(__import__("synth").noise(n, sigma, noise_seed).astype(np.float32), device="cuda")
+    return (wdb.blur(field, img) + b).reshape(-1).contiguous()
+
+
+def run_batched(args):
+    """64 problems: 8 operators of uneven size (128..1024), 8 right-hand sides each,
+    per-problem lambda; time to relative objective 1e-4 for the whole batch in
+    one batched call vs 64 single solves, on the same GPU."""
+    import torch
+    import synth
+    from paper_1512_08401_amd import wdb
+    groups = synth.batched_problems(41)
+    probs, meta = [], []
+    t0 = time.perf_counter()
+    total_nnz = 0
+    for gi, g in enumerate(groups):
+        n = g["n"]
+        kind, kw = g["field"]
+        field = synth.psf_isotropic(n, **kw) if kind == "isotropic" else synth.psf_rotating(n, **kw)
+        th = wdb.build_theta(field, "db4", g["levels"], g["nnz_per_px"] * n * n)
+        th.lipschitz(synth.power_start(n * n, 1000 + gi))
+        th.autotune(reps=5)
+        total_nnz += th.info()["nnz"]
+        for j in range(8):
+            u0 = _observe(wdb, torch, field, n, g["seeds"][j][0] % 100000, g["seeds"][j][1] % 100000, 0.01)
+            probs.append([th, u0, g["lams"][j]])
+            meta.append((gi, n))
+        log(f"group {gi}: n={n} levels={g['levels']} nnz/px={g['nnz_per_px']} field={kind}")
+    t_setup = time.perf_counter() - t0
+    # E* per problem: long batched run to a relative gap of 1e-9
+    xs, inf = wdb.solve_batched([p[:3] for p in probs], 20000, check_every=100, tol=1e-9, use_graph=True)
+    for i, p in enumerate(probs):
+        x0 = wdb.dwt(p[1], "db4", p[0].info()["levels"])
+        E0 = 0.5 * float(torch.dot(x0.double(), x0.double()))
+        p.append(inf[i]["objective"] + 1e-4 * E0)   # stop target: (E - E*)/E(0) <= 1e-4
+    torch.cuda.synchronize()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    wdb.solve_batched([(p[0], p[1], p[2], None, p[3]) for p in probs], 20000, check_every=10, use_graph=True)
+    e0, e1 = ev(), ev()
+    e0.record()
+    _, binf = wdb.solve_batched([(p[0], p[1], p[2], None, p[3]) for p in probs], 20000, check_every=10,
+                                use_graph=True)
+    e1.record()
+    torch.cuda.synchronize()
+    t_batched = e0.elapsed_time(e1) / 1e3
+    e0, e1 = ev(), ev()
+    e0.record()
+    single_iters = []
+    for p in probs:
+        _, r = p[0].solve(p[1], p[2], 20000, check_every=10, use_graph=True, target=p[3])
+        single_iters.append(r["iters"])
+    e1.record()
+    torch.cuda.synchronize()
+    t_single = e0.elapsed_time(e1) / 1e3
+    return {"metric": "time to rel. objective 1e-4, 64 problems (batched vs single)", "value": round(t_batched, 4),
+            "unit": "s", "higher_is_better": False, "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "batched: 8 operators (n in {128,256,512,1024}, db4, levels log2(n)-4, "
+                                   "20-40 nnz/px) x 8 right-hand sides, lambda logU[1e-4,1e-2]",
+                       "total_nnz": total_nnz},
+            "single_solves_s": round(t_single, 4), "speedup": round(t_single / t_batched, 2),
+            "iters_batched_mean": float(np.mean([r["iters"] for r in binf])),
+            "iters_single_mean": float(np.mean(single_iters)), "setup_s": round(t_setup, 2)}
+
+
+def run_learned(args):
+    """Warm start: train on solver-generated targets (4096 images), then time to
+    relative objective 1e-4 on 512 held-out images from the prediction vs from zero."""
+    import torch
+    import synth
+    from paper_1512_08401_amd import wdb, warmstart
+    wl = synth.WORKLOADS["learned256"]
+    n, J, lam = wl.n, wl.levels, wl.lam
+    field = wl.psf()
+    th = wdb.build_theta(field, wl.wavelet, J, wl.nnz)
+    th.lipschitz(synth.power_start(n * n, wl.power_seed))
+    th.autotune(reps=5)
+    ntrain = args.train_images
+    t0 = time.perf_counter()
+    U = [_observe(wdb, torch, field, n, 50000 + i, 150000 + i, wl.noise_sigma) for i in range(ntrain)]
+    X0 = torch.stack([wdb.dwt(u, wl.wavelet, J) for u in U])
+    T = torch.empty_like(X0)
+    for b in range(0, ntrain, 512):
+        xs, _ = wdb.solve_batched([(th, u, lam) for u in U[b:b + 512]], 30000, check_every=50, tol=1e-6,
+                                  use_graph=True, outs=[T[i] for i in range(b, min(ntrain, b + 512))])
+        log(f"targets {min(ntrain, b + 512)}/{ntrain}")
+    t_targets = time.perf_counter() - t0
+    del U
+    net = wdb.Cnn(n, J, 32, seed=1)
+    t0 = time.perf_counter()
+    hist = warmstart.train(net, X0, T, args.epochs, 32, 1e-3, seed=2, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    nh = args.heldout_images
+    Uh = [_observe(wdb, torch, field, n, 60000 + i, 160000 + i, wl.noise_sigma) for i in range(nh)]
+    X0h = torch.stack([wdb.dwt(u, wl.wavelet, J) for u in Uh])
+    _, star = wdb.solve_batched([(th, u, lam) for u in Uh], 30000, check_every=100, tol=1e-9, use_graph=True)
+    E0 = 0.5 * (X0h.double() ** 2).sum(dim=1).cpu().numpy()
+    tgt = [star[i]["objective"] + 1e-4 * E0[i] for i in range(nh)]
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    out = {}
+    for form in ("zero", "warm"):
+        e0, e1 = ev(), ev()
+        torch.cuda.synchronize()
+        e0.record()
+        init = net.predict(X0h.reshape(-1).contiguous()).reshape(nh, -1) if form == "warm" else None
+        _, r = wdb.solve_batched([(th, Uh[i], lam, None if init is None else init[i].contiguous(), tgt[i])
+                                  for i in range(nh)], 30000, check_every=10, use_graph=True)
+        e1.record()
+        torch.cuda.synchronize()
+        out[form] = {"seconds": e0.elapsed_time(e1) / 1e3, "iters_mean": float(np.mean([x["iters"] for x in r])),
+                     "iters_median": float(np.median([x["iters"] for x in r]))}
+    return {"metric": "time to rel. objective 1e-4, held-out images (warm start vs zero)",
+            "value": round(out["warm"]["seconds"], 4), "unit": "s", "higher_is_better": False, "n_gpus": 1,
+            "dtype": "f32 solver, bf16 network", "data": "synthetic",
+            "config": {"workload": f"learned256: {n}x{n}, db4 {J} levels, isotropic 1..3 field, {wl.nnz} nnz, "
+                                   f"lambda {lam}; {ntrain} training / {nh} held-out images; {args.epochs} epochs"},
+            "zero_start": out["zero"], "warm_start": out["warm"],
+            "speedup": round(out["zero"]["seconds"] / out["warm"]["seconds"], 3),
+            "train_loss_first_last": [hist[0], hist[-1]], "targets_s": round(t_targets, 2),
+            "train_s": round(t_train, 2)}
 
 
 def th_x0(th, u0, wl, wdb):

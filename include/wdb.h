@@ -100,6 +100,8 @@ typedef struct {
   double lipschitz_p;  /* lambda_max(P^-1/2 Theta_K^T Theta_K P^-1/2)    */
   int32_t precond;     /* 0 none, else the wdb_precond kind in use      */
   int32_t valtype;     /* wdb_valtype of the iteration values            */
+  int32_t slice;       /* sliced-ELL slice height of the iteration copies */
+  int32_t group;       /* lanes per row of the vector-CSR kernels (0: sliced ELL) */
 } wdb_theta_desc;
 
 /* ---------------------------------------------------------------------------
@@ -211,6 +213,7 @@ typedef struct {
   double* trace;         /* host, optional: (k, E, rel_gap) per check             */
   int32_t trace_cap;     /* number of triples `trace` can hold                    */
   int32_t use_graph;     /* 1: replay the iterations between checks as a HIP graph */
+  double target_objective; /* > 0: also stop at the first check with E <= target     */
 } wdb_solve_opts;
 
 typedef struct {
@@ -221,6 +224,10 @@ typedef struct {
   double lipschitz;      /* L (or L_P) used                                         */
   double tau;            /* step 1/L                                                */
 } wdb_solve_info;
+
+/* Stopping: with tol_rel_gap > 0 or target_objective > 0 the solve ends at the
+ * first check meeting either; WDB_ERR_NOT_CONVERGED if neither was met within
+ * max_iters (x_out is still written). */
 
 /* Solve from a blurred image: x0 = Psi^* u (forward transform on the GPU),
  * then FISTA iterations from x_init, x_out receives x^(k).  u: device n*n
@@ -244,6 +251,7 @@ typedef struct {
   float lambda;
   const float* x_init;   /* device, N coefficients, or NULL for x = 0         */
   float* x_out;          /* device, N coefficients (written at the end)      */
+  double target_objective; /* > 0: this problem stops at the first check with E <= target */
 } wdb_problem;
 
 /* Solve many problems in one call (Alg. 1 for each).  Problems sharing a
@@ -255,7 +263,7 @@ typedef struct {
  * per-problem x_init), each problem has its own lambda, step 1/L of its
  * handle (computed on first use if absent), and its own stop flag: with
  * tol_rel_gap > 0 a problem stops updating at the first check where its gap
- * is below tolerance.  infos (optional) receives nprob entries.  Handles must
+ * is below tolerance (or, with its target_objective > 0, where E <= target).  infos (optional) receives nprob entries.  Handles must
  * hold float32 values.  Synchronises at each check.  Errors: as wdb_solve;
  * WDB_ERR_NOT_CONVERGED if any problem missed the tolerance (all outputs are
  * still written). */

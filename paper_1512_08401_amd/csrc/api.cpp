@@ -114,6 +114,8 @@ wdb_status wdb_theta_info(const wdb_theta* th, wdb_theta_desc* out) {
   out->lipschitz_p = th->Lp;
   out->precond = th->precond;
   out->valtype = th->valtype;
+  out->slice = th->A.C;
+  out->group = wdb::kernel_group(th);
   WDB_API_END
 }
 

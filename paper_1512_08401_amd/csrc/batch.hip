@@ -276,6 +276,8 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
   WDB_REQUIRE(opts->max_iters >= 0 && opts->check_every >= 0, WDB_ERR_ARG, "bad iteration counts");
   WDB_REQUIRE(opts->x_init == nullptr, WDB_ERR_ARG, "x_init is per problem in a batch (wdb_problem.x_init)");
   const bool pre = opts->use_precond != 0;
+  bool stopping = opts->tol_rel_gap > 0;
+  for (int i = 0; i < nprob; ++i) stopping |= probs[i].target_objective > 0;
   hipStream_t s = static_cast<hipStream_t>(opts->stream);
   // group by operator, in first-seen order, then split into chunks of 8
   std::vector<wdb_theta*> order;
@@ -456,7 +458,8 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
           lastE[pi] = E;
           lastG[pi] = E > 0 ? (E - D) / E : 0.0;
           WDB_REQUIRE(std::isfinite(E), WDB_ERR_DIVERGED, "problem %d diverged", pi);
-          if (opts->tol_rel_gap > 0 && lastG[pi] <= opts->tol_rel_gap) {
+          if ((opts->tol_rel_gap > 0 && lastG[pi] <= opts->tol_rel_gap) ||
+              (probs[pi].target_objective > 0 && E <= probs[pi].target_objective)) {
             done_at[pi] = done;
             changed = true;
           }
@@ -467,7 +470,7 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
         }
         if (changed) WDB_HIP(hipMemcpyAsync(h.act.p, act.data(), kR * sizeof(int), hipMemcpyHostToDevice, s));
       }
-      if (opts->tol_rel_gap > 0 && !any_active) {
+      if (stopping && !any_active) {
         all_conv = true;
         break;
       }
@@ -500,8 +503,7 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
       infos[i].tau = 1.0 / infos[i].lipschitz;
     }
   }
-  if (opts->tol_rel_gap > 0 && !all_conv)
-    fail(WDB_ERR_NOT_CONVERGED, "not every problem reached relative gap %.3e in %d iterations", opts->tol_rel_gap,
-         done);
+  if (stopping && !all_conv)
+    fail(WDB_ERR_NOT_CONVERGED, "not every problem met its stopping test in %d iterations", done);
   WDB_API_END
 }

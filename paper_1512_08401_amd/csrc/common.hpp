@@ -214,6 +214,7 @@ void free_workspace(wdb_theta* th);
 void finish_theta(wdb_theta* th, hipStream_t s);   // builds A/At from csr
 void set_slice_height(wdb_theta* th, int C, hipStream_t s);  // rebuilds A/At with slices of C rows
 int default_slice_height();
+int kernel_group(const wdb_theta* th);  // lanes per row in use (0: sliced ELL)
 // Power iteration on D^-1/2 A^T A D^-1/2 (d = nullptr: identity), float64.
 double power_iteration(wdb_theta* th, const double* start_host, const double* dinv_sqrt,
                        double tol, int max_iters, int* iters_out, hipStream_t s);

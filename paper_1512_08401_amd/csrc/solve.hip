@@ -725,7 +725,8 @@ wdb_status solve_impl(wdb_theta* th, const float* x0_src, bool from_image, float
         }
         WDB_REQUIRE(std::isfinite(last.E), WDB_ERR_DIVERGED, "objective became non-finite at iteration %d",
                     k0 - 1 + done);
-        if (opts->tol_rel_gap > 0 && last.rel_gap <= opts->tol_rel_gap) {
+        if ((opts->tol_rel_gap > 0 && last.rel_gap <= opts->tol_rel_gap) ||
+            (opts->target_objective > 0 && last.E <= opts->target_objective)) {
           converged = true;
           break;
         }
@@ -748,9 +749,9 @@ wdb_status solve_impl(wdb_theta* th, const float* x0_src, bool from_image, float
     info->lipschitz = Luse;
     info->tau = tau;
   }
-  if (opts->tol_rel_gap > 0 && !converged)
-    fail(WDB_ERR_NOT_CONVERGED, "relative gap %.3e above tolerance %.3e after %d iterations", last.rel_gap,
-         opts->tol_rel_gap, done);
+  if ((opts->tol_rel_gap > 0 || opts->target_objective > 0) && !converged)
+    fail(WDB_ERR_NOT_CONVERGED, "stopping test not met after %d iterations (relative gap %.3e, objective %.9e)",
+         done, last.rel_gap, last.E);
   return WDB_OK;
 }
 

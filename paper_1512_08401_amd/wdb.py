@@ -47,19 +47,19 @@ class ThetaDesc(C.Structure):
     _fields_ = [("n", C.c_int32), ("levels", C.c_int32), ("wavelet", C.c_int32),
                 ("has_lipschitz", C.c_int32), ("nnz", C.c_int64), ("stored", C.c_int64),
                 ("lipschitz", C.c_double), ("threshold", C.c_double), ("lipschitz_p", C.c_double),
-                ("precond", C.c_int32), ("valtype", C.c_int32)]
+                ("precond", C.c_int32), ("valtype", C.c_int32), ("slice", C.c_int32), ("group", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
     _fields_ = [("max_iters", C.c_int32), ("check_every", C.c_int32), ("tol_rel_gap", C.c_double),
                 ("x_init", C.c_void_p), ("k0", C.c_int32), ("use_precond", C.c_int32),
                 ("stream", C.c_void_p), ("trace", C.POINTER(C.c_double)), ("trace_cap", C.c_int32),
-                ("use_graph", C.c_int32)]
+                ("use_graph", C.c_int32), ("target_objective", C.c_double)]
 
 
 class ProblemC(C.Structure):
     _fields_ = [("theta", C.c_void_p), ("u", C.c_void_p), ("lam", C.c_float), ("x_init", C.c_void_p),
-                ("x_out", C.c_void_p)]
+                ("x_out", C.c_void_p), ("target_objective", C.c_double)]
 
 
 class SolveInfo(C.Structure):
@@ -288,7 +288,7 @@ class Theta:
         return E.value, g.value
 
     def _solve(self, fn, src, lam, iters, check_every, tol, x_init, k0, precond, use_graph, trace_cap, out,
-               stream):
+               stream, target=0.0):
         torch = _torch()
         N = self.N
         x = torch.empty(N, device=src.device, dtype=torch.float32) if out is None else out
@@ -296,7 +296,7 @@ class Theta:
         o = SolveOpts(int(iters), int(check_every), float(tol),
                       None if x_init is None else _dev(x_init, N, "x_init").value, int(k0),
                       1 if precond else 0, _stream(stream).value, trace.ctypes.data_as(_pd), int(trace_cap),
-                      1 if use_graph else 0)
+                      1 if use_graph else 0, float(target))
         info = SolveInfo()
         st = getattr(_lib, fn)(self._h, _dev(src, name="input"), float(lam), C.byref(o), _dev(x, N, "x_out"),
                                C.byref(info))
@@ -306,21 +306,22 @@ class Theta:
             res["converged"] = False
             return x, res
         _check(fn, st)
-        res["converged"] = tol > 0
+        res["converged"] = tol > 0 or target > 0
         return x, res
 
     def solve(self, u, lam: float, iters: int, check_every: int = 20, tol: float = 0.0, x_init=None, k0: int = 1,
-              precond: bool = False, use_graph: bool = False, trace_cap: int = 0, out=None, stream=None):
+              precond: bool = False, use_graph: bool = False, trace_cap: int = 0, out=None, stream=None,
+              target: float = 0.0):
         """FISTA from a blurred image u (device n*n float32); returns (x, info)."""
         return self._solve("wdb_solve", u, lam, iters, check_every, tol, x_init, k0, precond, use_graph,
-                           trace_cap, out, stream)
+                           trace_cap, out, stream, target)
 
     def solve_coeffs(self, x0, lam: float, iters: int, check_every: int = 20, tol: float = 0.0, x_init=None,
                      k0: int = 1, precond: bool = False, use_graph: bool = False, trace_cap: int = 0, out=None,
-                     stream=None):
+                     stream=None, target: float = 0.0):
         """FISTA from wavelet-domain data x0 (device N float32); returns (x, info)."""
         return self._solve("wdb_solve_coeffs", x0, lam, iters, check_every, tol, x_init, k0, precond, use_graph,
-                           trace_cap, out, stream)
+                           trace_cap, out, stream, target)
 
     def synthesize(self, x, out=None, stream=None):
         torch = _torch()
@@ -386,7 +387,7 @@ class Cnn:
 
 def solve_batched(problems, iters: int, check_every: int = 20, tol: float = 0.0, k0: int = 1,
                   precond: bool = False, use_graph: bool = False, outs=None, stream=None):
-    """Batched Alg. 1.  ``problems``: list of (theta, u, lam) or (theta, u, lam, x_init).
+    """Batched Alg. 1.  ``problems``: list of (theta, u, lam[, x_init[, target_objective]]).
     Returns (list of x tensors, list of info dicts)."""
     torch = _torch()
     n = len(problems)
@@ -395,13 +396,14 @@ def solve_batched(problems, iters: int, check_every: int = 20, tol: float = 0.0,
     for i, p in enumerate(problems):
         th, u, lam = p[0], p[1], p[2]
         xi = p[3] if len(p) > 3 else None
+        tgt = float(p[4]) if len(p) > 4 else 0.0
         N = th.N
         x = torch.empty(N, device=u.device, dtype=torch.float32) if outs is None else outs[i]
         xs.append(x)
         arr[i] = ProblemC(th.handle.value, _dev(u, N, "u").value, float(lam),
-                          None if xi is None else _dev(xi, N, "x_init").value, _dev(x, N, "x_out").value)
+                          None if xi is None else _dev(xi, N, "x_init").value, _dev(x, N, "x_out").value, tgt)
     o = SolveOpts(int(iters), int(check_every), float(tol), None, int(k0), 1 if precond else 0,
-                  _stream(stream).value, None, 0, 1 if use_graph else 0)
+                  _stream(stream).value, None, 0, 1 if use_graph else 0, 0.0)
     infos = (SolveInfo * n)()
     st = _lib.wdb_solve_batched(n, arr, C.byref(o), infos)
     res = [{k: getattr(inf, k) for k, _ in SolveInfo._fields_} for inf in infos]
@@ -410,8 +412,9 @@ def solve_batched(problems, iters: int, check_every: int = 20, tol: float = 0.0,
             r["converged"] = False
         return xs, res
     _check("wdb_solve_batched", st)
+    stopping = tol > 0 or any(len(p) > 4 and p[4] > 0 for p in problems)
     for r in res:
-        r["converged"] = tol > 0
+        r["converged"] = stopping
     return xs, res
 
 
