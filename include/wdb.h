@@ -247,11 +247,13 @@ wdb_status wdb_solve_coeffs(wdb_theta* th, const float* x0, float lambda,
 /* One problem of a batched solve. */
 typedef struct {
   wdb_theta* theta;      /* operator; problems may share one                 */
-  const float* u;        /* device, n*n blurred image                        */
+  const float* u;        /* device, n*n blurred image; may be NULL when x0 is set */
   float lambda;
   const float* x_init;   /* device, N coefficients, or NULL for x = 0         */
   float* x_out;          /* device, N coefficients (written at the end)      */
   double target_objective; /* > 0: this problem stops at the first check with E <= target */
+  const float* x0;       /* device, N coefficients Psi^* u given directly (u is then
+                            not read), or NULL to transform u on the device   */
 } wdb_problem;
 
 /* Solve many problems in one call (Alg. 1 for each).  Problems sharing a

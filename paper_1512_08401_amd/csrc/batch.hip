@@ -284,7 +284,7 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
   std::map<wdb_theta*, std::vector<int>> members;
   for (int i = 0; i < nprob; ++i) {
     const wdb_problem& p = probs[i];
-    WDB_REQUIRE(p.theta && p.u && p.x_out, WDB_ERR_ARG, "problem %d has a null pointer", i);
+    WDB_REQUIRE(p.theta && (p.u || p.x0) && p.x_out, WDB_ERR_ARG, "problem %d has a null pointer", i);
     WDB_REQUIRE(std::isfinite(p.lambda) && p.lambda >= 0.0f, WDB_ERR_NONFINITE, "problem %d: bad lambda", i);
     WDB_REQUIRE(p.theta->valtype == WDB_VAL_F32, WDB_ERR_ARG, "batched solve uses float32 values");
     WDB_REQUIRE(!pre || p.theta->precond != 0, WDB_ERR_ARG, "problem %d: no preconditioner set", i);
@@ -375,8 +375,12 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
         const wdb_problem& p = probs[h.idx[j]];
         d.thr[j] = static_cast<float>(tau * static_cast<double>(p.lambda));
         act[j] = 1;
-        dwt_forward(th->n, th->levels, f, p.u, th->ws_x0, th->ws_img, th->ws_img + q, s);
-        hipLaunchKernelGGL(k_interleave, dim3((N + 255) / 256), dim3(256), 0, s, th->ws_x0, h.X0.p, N, j);
+        const float* x0 = p.x0;
+        if (!x0) {
+          dwt_forward(th->n, th->levels, f, p.u, th->ws_x0, th->ws_img, th->ws_img + q, s);
+          x0 = th->ws_x0;
+        }
+        hipLaunchKernelGGL(k_interleave, dim3((N + 255) / 256), dim3(256), 0, s, x0, h.X0.p, N, j);
         hipLaunchKernelGGL(k_interleave, dim3((N + 255) / 256), dim3(256), 0, s, p.x_init, h.X.p, N, j);
         hipLaunchKernelGGL(k_interleave, dim3((N + 255) / 256), dim3(256), 0, s, p.x_init, h.Y.p, N, j);
       } else {

@@ -59,7 +59,7 @@ class SolveOpts(C.Structure):
 
 class ProblemC(C.Structure):
     _fields_ = [("theta", C.c_void_p), ("u", C.c_void_p), ("lam", C.c_float), ("x_init", C.c_void_p),
-                ("x_out", C.c_void_p), ("target_objective", C.c_double)]
+                ("x_out", C.c_void_p), ("target_objective", C.c_double), ("x0", C.c_void_p)]
 
 
 class SolveInfo(C.Structure):
@@ -386,8 +386,10 @@ class Cnn:
 
 
 def solve_batched(problems, iters: int, check_every: int = 20, tol: float = 0.0, k0: int = 1,
-                  precond: bool = False, use_graph: bool = False, outs=None, stream=None):
+                  precond: bool = False, use_graph: bool = False, outs=None, stream=None, coeffs: bool = False):
     """Batched Alg. 1.  ``problems``: list of (theta, u, lam[, x_init[, target_objective]]).
+    With ``coeffs`` the second entry of every problem is the wavelet-domain
+    data x0 = Psi^* u (N coefficients) instead of the image.
     Returns (list of x tensors, list of info dicts)."""
     torch = _torch()
     n = len(problems)
@@ -400,8 +402,10 @@ def solve_batched(problems, iters: int, check_every: int = 20, tol: float = 0.0,
         N = th.N
         x = torch.empty(N, device=u.device, dtype=torch.float32) if outs is None else outs[i]
         xs.append(x)
-        arr[i] = ProblemC(th.handle.value, _dev(u, N, "u").value, float(lam),
-                          None if xi is None else _dev(xi, N, "x_init").value, _dev(x, N, "x_out").value, tgt)
+        data = _dev(u, N, "x0" if coeffs else "u").value
+        arr[i] = ProblemC(th.handle.value, None if coeffs else data, float(lam),
+                          None if xi is None else _dev(xi, N, "x_init").value, _dev(x, N, "x_out").value, tgt,
+                          data if coeffs else None)
     o = SolveOpts(int(iters), int(check_every), float(tol), None, int(k0), 1 if precond else 0,
                   _stream(stream).value, None, 0, 1 if use_graph else 0, 0.0)
     infos = (SolveInfo * n)()

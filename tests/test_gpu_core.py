@@ -409,14 +409,26 @@ def test_batched_matches_oracle_per_problem(W, p64, small32):
         probs.append((th, dev(u0).reshape(-1), lam))
         oracle_inputs.append((A32, dwt.dwt2(u0.astype(np.float64), h, J), lam, start))
     xs, infos = W.solve_batched(probs, 150, check_every=50, use_graph=True)
+    # the same problems with x0 handed over directly (the oracle's transform, in float32)
+    x0s = [x0.astype(np.float32) for (_A, x0, _l, _s) in oracle_inputs]
+    xc, infc = W.solve_batched([(p[0], dev(x0s[i]), p[2]) for i, p in enumerate(probs)], 150, check_every=50,
+                               use_graph=True, coeffs=True)
     for i, (A32, x0, lam, start) in enumerate(oracle_inputs):
         L, _ = lipschitz.lipschitz(A32, start)
         xo, _, _ = fista.fista(A32, x0, lam, 1.0 / L, 150)
         _gate(A32, x0, lam, host(xs[i]), xo, fista.objective(A32, x0, lam, xo))
-        # the GPU scores against its float32 transform of u0, the oracle against
-        # the float64 one: ~1e-7 relative in x0, ~1e-8 in E
+        # From the image, the GPU scores against its own float32 transform of u0
+        # (about 1e-6 absolute per coefficient away from the float64 one): E moves
+        # by ~1e-7 relative, but the dual scaling s = lam / ||A^T r||_inf magnifies
+        # the shift of the relative gap to ~2.5e-4 on these problems.
         E, _, _, rel = fista.duality_gap(A32, x0, lam, host(xs[i]))
-        assert abs(infos[i]["objective"] - E) <= 1e-6 * E and abs(infos[i]["rel_gap"] - rel) <= 1e-6
+        assert abs(infos[i]["objective"] - E) <= 1e-6 * E and abs(infos[i]["rel_gap"] - rel) <= 1e-3
+        # From identical float32 coefficients the float64 checks agree to rounding.
+        x0f = x0s[i].astype(np.float64)
+        xof, _, _ = fista.fista(A32, x0f, lam, 1.0 / L, 150)
+        _gate(A32, x0f, lam, host(xc[i]), xof, fista.objective(A32, x0f, lam, xof))
+        E, _, _, rel = fista.duality_gap(A32, x0f, lam, host(xc[i]))
+        assert abs(infc[i]["objective"] - E) <= 1e-9 * E and abs(infc[i]["rel_gap"] - rel) <= 1e-8
     # per-problem stop flags: every problem ends below the tolerance, frozen at its own check
     xs, infos = W.solve_batched(probs, 3000, check_every=20, tol=2e-3)
     assert all(r["converged"] for r in infos)
