@@ -35,6 +35,35 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def kernel_label(layout):
+    slice_h, group = layout
+    if group > 0:
+        return f"k_res_csr<{group}>", f"r = Theta_K y - x0, float32 CSR, {group} lanes per row"
+    return "k_res", f"r = Theta_K y - x0, float32 sliced-ELL, {slice_h} rows per slice"
+
+
+def profiled_traffic(workload, kernel, layout):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when that
+    summary was taken on other kernel sources, another layout or workload."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_res_{workload}.md")
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    fields = dict(line.strip().split(": ", 1) for line in text.splitlines()
+                  if line.startswith("    ") and ": " in line)
+    dig = hashlib.sha256()
+    for rel in ("paper_1512_08401_amd/csrc/solve.hip", "paper_1512_08401_amd/csrc/common.hpp"):
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            dig.update(f.read())
+    if (fields.get("source_sha256") != dig.hexdigest() or fields.get("kernel") != kernel
+            or fields.get("layout") != f"slice={layout[0]} group={layout[1]}" or fields.get("workload") != workload):
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -191,9 +220,11 @@ def main():
     nnz = info["nnz"]
     alg_bytes = 8 * nnz + 12 * N          # values + indices once, y/x0 read once, r written once
     achieved = alg_bytes / (k_us * 1e-6) / 1e9
+    kname, kdesc = kernel_label(layout)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_res (r = Theta_K y - x0, sliced-ELL float32)",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": profiled_traffic(wl.name, kname, layout),
+                "kernel": f"{kname} ({kdesc})",
                 "kernel_us": round(k_us, 2), "algorithmic_bytes": alg_bytes,
                 "stored_slots": info["stored"], "transpose_kernel_us": round(kt_us, 2),
                 "layout": {"slice": layout[0], "lanes_per_row": layout[1]},
