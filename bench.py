@@ -256,49 +256,58 @@ def main():
         "roofline": roofline,
     }
     if ttt is not None:
-        out["time_to_rel_objective_1e-4"] = ttt
+        out["time_to_rel_objective"] = ttt
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host")
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)
 
 
-def time_to_tolerance(th, u0, wl, torch, wdb, synth, N, target=1e-4):
-    """Seconds (and iterations) to reach (E(x_k) - E*)/E(0) <= target, E(0) = ||x0||^2/2.
+def time_to_tolerance(th, u0, wl, torch, wdb, synth, N, targets=(1e-4, 1e-6)):
+    """Seconds (and iterations) to reach rho_k = (E(x_k) - E*)/E(0) <= target,
+    E(0) = ||x0||^2/2 (the same normaliser for every form).
 
-    E* comes from a long preconditioned run driven to a relative duality gap of
-    1e-10 (or 20000 iterations); k* is located from a run traced every 10
-    iterations, then a clean solve of k* iterations (forward transform
-    included, one float64 check at the end) is timed with HIP events."""
+    E* is the smallest objective seen along a long preconditioned run (20000
+    iterations, checks every 100); its change over the second half of that run
+    is reported as its uncertainty.  For each form, k* is located from a run
+    traced every 10 iterations, then a clean solve of k* iterations (forward
+    transform included, one float64 check at the end) is timed with HIP events.
+    The 16-bit forms are scored with the float64 objective of the float32
+    operator, like the others."""
     x0 = wdb.dwt(u0, wl.wavelet, wl.levels)
     E0 = 0.5 * float(torch.dot(x0.double(), x0.double()))
     th.set_precond("spai_scale", start=synth.power_start(N, wl.power_seed))
-    xs, inf = th.solve(u0, wl.lam, 20000, check_every=100, tol=1e-10, precond=True)
-    Estar, gap_star = inf["objective"], inf["rel_gap"]
-    res = {"E_star": Estar, "E_star_rel_gap": gap_star, "E0": E0, "target": target}
+    _, inf = th.solve(u0, wl.lam, 20000, check_every=100, precond=True, trace_cap=200)
+    trE = inf["trace"][:, 1]
+    Estar = float(trE.min())
+    res = {"E_star": Estar, "E_star_change_last_half": float(trE[len(trE) // 2:].max() - Estar) / E0,
+           "E_star_rel_gap": inf["rel_gap"], "E0": E0, "normaliser": "E(0) = ||x0||^2/2"}
     stream = torch.cuda.current_stream()
     forms = (("plain_f32", False, "f32"), ("spai_scale_f32", True, "f32"), ("plain_bf16", False, "bf16"),
              ("spai_scale_bf16", True, "bf16"), ("plain_f16", False, "f16"))
+    x = torch.empty(N, device=u0.device)
     for form, pre, vt in forms:
         th.set_precision(vt)
-        cap = 4000
+        cap = 6000
         _, tr = th.solve(u0, wl.lam, cap, check_every=10, precond=pre, trace_cap=cap // 10)
         rho = (tr["trace"][:, 1] - Estar) / E0
-        hit = np.nonzero(rho <= target)[0]
-        if hit.size == 0:
-            res[form] = {"reached": False, "iters_checked": cap, "best_rel_objective": float(rho.min())}
-            continue
-        k = int(tr["trace"][hit[0], 0])
-        x = torch.empty(N, device=u0.device)
-        th.solve(u0, wl.lam, k, check_every=k, precond=pre, out=x)      # warm
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        _, fin = th.solve(u0, wl.lam, k, check_every=k, precond=pre, out=x, use_graph=True)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        res[form] = {"reached": True, "iters": k, "seconds": e0.elapsed_time(e1) / 1e3,
-                     "rel_objective": (fin["objective"] - Estar) / E0}
+        res[form] = {"best_rel_objective": float(rho.min())}
+        for target in targets:
+            hit = np.nonzero(rho <= target)[0]
+            key = f"{target:.0e}"
+            if hit.size == 0:
+                res[form][key] = {"reached": False, "iters_checked": cap}
+                continue
+            k = int(tr["trace"][hit[0], 0])
+            th.solve(u0, wl.lam, k, check_every=k, precond=pre, out=x)      # warm
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            _, fin = th.solve(u0, wl.lam, k, check_every=k, precond=pre, out=x, use_graph=True)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            res[form][key] = {"reached": True, "iters": k, "seconds": e0.elapsed_time(e1) / 1e3,
+                              "rel_objective": (fin["objective"] - Estar) / E0}
     th.set_precision("f32")
     th.set_precond("none")
     return res
@@ -337,37 +346,45 @@ def run_batched(args):
     t_setup = time.perf_counter() - t0
     # E* per problem: long batched run to a relative gap of 1e-9
     xs, inf = wdb.solve_batched([p[:3] for p in probs], 20000, check_every=100, tol=1e-9, use_graph=True)
+    E0 = []
     for i, p in enumerate(probs):
         x0 = wdb.dwt(p[1], "db4", p[0].info()["levels"])
-        E0 = 0.5 * float(torch.dot(x0.double(), x0.double()))
-        p.append(inf[i]["objective"] + 1e-4 * E0)   # stop target: (E - E*)/E(0) <= 1e-4
+        E0.append(0.5 * float(torch.dot(x0.double(), x0.double())))
     torch.cuda.synchronize()
     ev = lambda: torch.cuda.Event(enable_timing=True)
-    wdb.solve_batched([(p[0], p[1], p[2], None, p[3]) for p in probs], 20000, check_every=10, use_graph=True)
-    e0, e1 = ev(), ev()
-    e0.record()
-    _, binf = wdb.solve_batched([(p[0], p[1], p[2], None, p[3]) for p in probs], 20000, check_every=10,
-                                use_graph=True)
-    e1.record()
-    torch.cuda.synchronize()
-    t_batched = e0.elapsed_time(e1) / 1e3
-    e0, e1 = ev(), ev()
-    e0.record()
-    single_iters = []
-    for p in probs:
-        _, r = p[0].solve(p[1], p[2], 20000, check_every=10, use_graph=True, target=p[3])
-        single_iters.append(r["iters"])
-    e1.record()
-    torch.cuda.synchronize()
-    t_single = e0.elapsed_time(e1) / 1e3
-    return {"metric": "time to rel. objective 1e-4, 64 problems (batched vs single)", "value": round(t_batched, 4),
-            "unit": "s", "higher_is_better": False, "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+    res = {}
+    for target in (1e-4, 1e-6):
+        # stop target per problem: (E - E*)/E(0) <= target
+        tg = [inf[i]["objective"] + target * E0[i] for i in range(len(probs))]
+        batch = [(p[0], p[1], p[2], None, tg[i]) for i, p in enumerate(probs)]
+        wdb.solve_batched(batch, 20000, check_every=10, use_graph=True)
+        e0, e1 = ev(), ev()
+        e0.record()
+        _, binf = wdb.solve_batched(batch, 20000, check_every=10, use_graph=True)
+        e1.record()
+        torch.cuda.synchronize()
+        t_batched = e0.elapsed_time(e1) / 1e3
+        e0, e1 = ev(), ev()
+        e0.record()
+        single_iters = []
+        for i, p in enumerate(probs):
+            _, r = p[0].solve(p[1], p[2], 20000, check_every=10, use_graph=True, target=tg[i])
+            single_iters.append(r["iters"])
+        e1.record()
+        torch.cuda.synchronize()
+        t_single = e0.elapsed_time(e1) / 1e3
+        res[f"{target:.0e}"] = {"batched_s": round(t_batched, 4), "single_solves_s": round(t_single, 4),
+                                "speedup": round(t_single / t_batched, 2),
+                                "iters_batched_mean": float(np.mean([r["iters"] for r in binf])),
+                                "iters_single_mean": float(np.mean(single_iters))}
+        log(f"target {target:.0e}: batched {t_batched:.3f} s, 64 single solves {t_single:.3f} s")
+    return {"metric": "time to rel. objective 1e-4, 64 problems (batched vs single)",
+            "value": res["1e-04"]["batched_s"], "unit": "s", "higher_is_better": False, "n_gpus": 1,
+            "dtype": "f32", "data": "synthetic",
             "config": {"workload": "batched: 8 operators (n in {128,256,512,1024}, db4, levels log2(n)-4, "
                                    "20-40 nnz/px) x 8 right-hand sides, lambda logU[1e-4,1e-2]",
                        "total_nnz": total_nnz},
-            "single_solves_s": round(t_single, 4), "speedup": round(t_single / t_batched, 2),
-            "iters_batched_mean": float(np.mean([r["iters"] for r in binf])),
-            "iters_single_mean": float(np.mean(single_iters)), "setup_s": round(t_setup, 2)}
+            "targets": res, "E_star_converged": all(r["converged"] for r in inf), "setup_s": round(t_setup, 2)}
 
 
 def run_learned(args):
@@ -403,28 +420,32 @@ def run_learned(args):
     X0h = torch.stack([wdb.dwt(u, wl.wavelet, J) for u in Uh])
     _, star = wdb.solve_batched([(th, u, lam) for u in Uh], 30000, check_every=100, tol=1e-9, use_graph=True)
     E0 = 0.5 * (X0h.double() ** 2).sum(dim=1).cpu().numpy()
-    tgt = [star[i]["objective"] + 1e-4 * E0[i] for i in range(nh)]
     ev = lambda: torch.cuda.Event(enable_timing=True)
     out = {}
-    for form in ("zero", "warm"):
-        e0, e1 = ev(), ev()
-        torch.cuda.synchronize()
-        e0.record()
-        init = net.predict(X0h.reshape(-1).contiguous()).reshape(nh, -1) if form == "warm" else None
-        _, r = wdb.solve_batched([(th, Uh[i], lam, None if init is None else init[i].contiguous(), tgt[i])
-                                  for i in range(nh)], 30000, check_every=10, use_graph=True)
-        e1.record()
-        torch.cuda.synchronize()
-        out[form] = {"seconds": e0.elapsed_time(e1) / 1e3, "iters_mean": float(np.mean([x["iters"] for x in r])),
-                     "iters_median": float(np.median([x["iters"] for x in r]))}
+    for target in (1e-4, 1e-6):
+        tgt = [star[i]["objective"] + target * E0[i] for i in range(nh)]
+        out[f"{target:.0e}"] = {}
+        for form in ("zero", "warm"):
+            e0, e1 = ev(), ev()
+            torch.cuda.synchronize()
+            e0.record()
+            init = net.predict(X0h.reshape(-1).contiguous()).reshape(nh, -1) if form == "warm" else None
+            _, r = wdb.solve_batched([(th, Uh[i], lam, None if init is None else init[i].contiguous(), tgt[i])
+                                      for i in range(nh)], 30000, check_every=10, use_graph=True)
+            e1.record()
+            torch.cuda.synchronize()
+            out[f"{target:.0e}"][form] = {"seconds": e0.elapsed_time(e1) / 1e3,
+                                          "iters_mean": float(np.mean([x["iters"] for x in r])),
+                                          "iters_median": float(np.median([x["iters"] for x in r]))}
+        o = out[f"{target:.0e}"]
+        o["speedup"] = round(o["zero"]["seconds"] / o["warm"]["seconds"], 3)
+        log(f"target {target:.0e}: zero {o['zero']}, warm {o['warm']}")
     return {"metric": "time to rel. objective 1e-4, held-out images (warm start vs zero)",
-            "value": round(out["warm"]["seconds"], 4), "unit": "s", "higher_is_better": False, "n_gpus": 1,
+            "value": round(out["1e-04"]["warm"]["seconds"], 4), "unit": "s", "higher_is_better": False, "n_gpus": 1,
             "dtype": "f32 solver, bf16 network", "data": "synthetic",
             "config": {"workload": f"learned256: {n}x{n}, db4 {J} levels, isotropic 1..3 field, {wl.nnz} nnz, "
                                    f"lambda {lam}; {ntrain} training / {nh} held-out images; {args.epochs} epochs"},
-            "zero_start": out["zero"], "warm_start": out["warm"],
-            "speedup": round(out["zero"]["seconds"] / out["warm"]["seconds"], 3),
-            "train_loss_first_last": [hist[0], hist[-1]], "targets_s": round(t_targets, 2),
+            "targets": out, "train_loss_first_last": [hist[0], hist[-1]], "targets_s": round(t_targets, 2),
             "train_s": round(t_train, 2)}
 
 

@@ -102,6 +102,8 @@ typedef struct {
   int32_t valtype;     /* wdb_valtype of the iteration values            */
   int32_t slice;       /* sliced-ELL slice height of the iteration copies */
   int32_t group;       /* lanes per row of the vector-CSR kernels (0: sliced ELL) */
+  int32_t group16;     /* lanes per row of the packed 16-bit kernels (0: not in use) */
+  int64_t escapes;     /* entries of Theta_K and Theta_K^T outside the packed column code */
 } wdb_theta_desc;
 
 /* ---------------------------------------------------------------------------
@@ -172,20 +174,35 @@ wdb_status wdb_set_precond(wdb_theta* th, int32_t kind, double eps, const double
  * subband A is stored as q = round16(v * u_A), u_A = 2^-floor(log2 m_A), m_A the
  * largest |v| among the rows of subband A (1 if none), rounding to nearest-even;
  * the iteration then uses q / u_A exactly.  The block scale of block (A, B) is
- * u_A for every column subband B.  The float64 objective and duality-gap
- * checks keep using the float32 values, so they score iterates against the
- * unquantised Theta_K.  Synchronises.  Errors: WDB_ERR_ARG, _OOM, _HIP. */
+ * u_A for every column subband B.  The iteration reads a packed copy: one
+ * 32-bit word per entry, q in the high half and a band-relative column code in
+ * the low half (column level minus row level in [-3, 3], orientation, and the
+ * 2-D displacement in [-22, 22]^2 from the point of that level nearest to the
+ * row's atom, modulo the subband side), so 4 bytes per entry; entries outside
+ * the code (counted in wdb_theta_desc.escapes) are read from a per-row list
+ * with int32 columns.  The columns decode exactly, so the product is that of
+ * the dequantised matrix.  The float64 objective and duality-gap checks keep
+ * using the float32 values, so they score iterates against the unquantised
+ * Theta_K.  Synchronises.  Errors: WDB_ERR_ARG, _OOM, _HIP. */
 wdb_status wdb_set_precision(wdb_theta* th, int32_t valtype);
+
+/* Lanes per row of the packed 16-bit kernels: 2, 4, 8 or 16, or 0 for the
+ * default (4, or the environment variable WDB_Q_GROUP, where 0 selects the
+ * slot-layout 16-bit kernels).  Changes only the summation order.  Errors:
+ * WDB_ERR_ARG. */
+wdb_status wdb_set_packed_group(wdb_theta* th, int32_t group);
 
 /* Kernel layout of the iteration: sliced ELL with `slice` rows per slice
  * (8, 16, 32 or 64; rows in coefficient order) and group = 0, or vector CSR
- * with `group` lanes per row (2..64).  The 16-bit values, the batched solver
- * and the float64 checks always use the sliced-ELL copy.  Synchronises. */
+ * with `group` lanes per row (2..64).  The float64 checks and the power
+ * iteration follow the same choice; the batched solver always uses the
+ * sliced-ELL copy and the 16-bit iteration its packed copy.  Synchronises. */
 wdb_status wdb_set_kernel_layout(wdb_theta* th, int32_t slice, int32_t group);
 
 /* Project autotuner: times the iteration kernel pair `reps` times for every
  * candidate layout (slices of 64/32/16/8 rows; vector CSR with 4/8/16 lanes)
- * on this operator and keeps the fastest.  If cache_path is not NULL the
+ * on this operator and keeps the fastest; with 16-bit values set it then also
+ * picks the packed kernels' lanes per row (2/4/8/16).  If cache_path is not NULL the
  * decision is looked up in / appended to that text file, keyed by the
  * operator's shape and a hash of its row pointer.  Outputs (optional): the
  * chosen slice height and lanes per row, and the time of one iteration pair in

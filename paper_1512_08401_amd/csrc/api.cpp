@@ -116,6 +116,8 @@ wdb_status wdb_theta_info(const wdb_theta* th, wdb_theta_desc* out) {
   out->valtype = th->valtype;
   out->slice = th->A.C;
   out->group = wdb::kernel_group(th);
+  out->group16 = th->valtype != WDB_VAL_F32 && th->pA.word ? wdb::packed_group(th) : 0;
+  out->escapes = th->pA.nesc + th->pAt.nesc;
   WDB_API_END
 }
 
@@ -145,6 +147,8 @@ void wdb_theta_free(wdb_theta* th) {
   if (th->val16) (void)hipFree(th->val16);
   if (th->val16T) (void)hipFree(th->val16T);
   if (th->wrow) (void)hipFree(th->wrow);
+  th->pA.free_all();
+  th->pAt.free_all();
   wdb::free_workspace(th);
   delete th;
 }

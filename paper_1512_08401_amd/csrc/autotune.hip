@@ -26,6 +26,8 @@ void launch_prox(int G, const Sell& sell, const Csr32& csr, const float* r, floa
 
 namespace {
 
+__global__ void k_set_one(int* p) { *p = 1; }
+
 __global__ void k_fill(float* __restrict__ a, int64_t n, float v) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) a[i] = v * static_cast<float>((i * 2654435761ull) % 1000) * 1e-3f;
@@ -42,6 +44,69 @@ std::string cache_key(const wdb_theta* th) {
   std::ostringstream o;
   o << th->n << "-" << th->levels << "-" << th->wavelet << "-" << th->nnz << "-" << std::hex << h;
   return o.str();
+}
+
+// Lanes per row of the packed 16-bit kernels: the fastest of 2/4/8/16 for
+// the residual + proximal pair (cached under the operator's key and format).
+void tune_packed(wdb_theta* th, const char* cache_path, const std::string& key, int reps, hipStream_t s) {
+  using namespace wdb;
+  const std::string qkey = key + "-q" + std::to_string(th->valtype);
+  int bestG = 0;
+  double best = 1e300;
+  if (cache_path && *cache_path) {
+    std::ifstream in(cache_path);
+    std::string k;
+    int C, G;
+    double us;
+    while (in >> k >> C >> G >> us)
+      if (k == qkey) {
+        bestG = G;
+        best = us;
+      }
+  }
+  if (bestG == 0) {
+    const int64_t N = th->N;
+    hipLaunchKernelGGL(k_fill, dim3((N + 255) / 256), dim3(256), 0, s, th->ws_y, N, 0.5f);
+    hipLaunchKernelGGL(k_fill, dim3((N + 255) / 256), dim3(256), 0, s, th->ws_x0, N, 0.25f);
+    hipLaunchKernelGGL(k_fill, dim3((N + 255) / 256), dim3(256), 0, s, th->ws_img, N, 0.0f);
+    hipLaunchKernelGGL(k_set_one, dim3(1), dim3(1), 0, s, th->ws_k);
+    WDB_HIP(hipGetLastError());
+    hipEvent_t e0, e1;
+    WDB_HIP(hipEventCreate(&e0));
+    WDB_HIP(hipEventCreate(&e1));
+    try {
+      for (int G : {2, 4, 8, 16}) {
+        auto pair = [&]() {
+          launch_res_packed(th, G, th->ws_y, th->ws_x0, th->ws_r, nullptr, 1, s);
+          launch_prox_packed(th, G, th->ws_r, th->ws_img, th->ws_y, 1e-3f, 1e-6f, th->ws_k, nullptr, s);
+        };
+        for (int i = 0; i < 3; ++i) pair();
+        WDB_HIP(hipEventRecord(e0, s));
+        for (int i = 0; i < reps; ++i) pair();
+        WDB_HIP(hipEventRecord(e1, s));
+        WDB_HIP(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        WDB_HIP(hipEventElapsedTime(&ms, e0, e1));
+        const double us = 1e3 * ms / reps;
+        if (std::getenv("WDB_LOG")) std::fprintf(stderr, "[wdb] autotune packed G=%d: %.2f us per iteration\n", G, us);
+        if (us < best) {
+          best = us;
+          bestG = G;
+        }
+      }
+    } catch (...) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (cache_path && *cache_path) {
+      std::ofstream out(cache_path, std::ios::app);
+      out << qkey << " 0 " << bestG << " " << best << "\n";
+    }
+  }
+  th->q_group = bestG;
 }
 
 }  // namespace
@@ -122,6 +187,7 @@ extern "C" wdb_status wdb_autotune(wdb_theta* th, const char* cache_path, int32_
     WDB_HIP(hipDeviceSynchronize());
     const wdb_status st = wdb_set_precision(th, vt);  // requantise into the new slots
     if (st != WDB_OK) return st;
+    if (th->pA.word) tune_packed(th, cache_path, key, reps, s);
   }
   if (slice_out) *slice_out = bestC;
   if (group_out) *group_out = bestG;

@@ -44,7 +44,7 @@ struct ChunkDev {
   const float* pinv; // N or null
   float tau;
   float thr[kR];     // tau * lambda_j
-  const int* act;    // stop flags (1 = keep iterating), written by the host between replays
+  const int* act;    // stop flags (1 = keep iterating) and, at [8], "any active"; written by the host between replays
   double* r64;       // [N][8] float64 residual for the checks
 };
 
@@ -91,6 +91,7 @@ __global__ __launch_bounds__(kBlock) void k_res_batched(const ChunkDev* __restri
   if (blockIdx.x == 0 && threadIdx.x == 0) *kdev += 1;
   const int c = chunk_of(first, nchunks, blockIdx.x);
   const ChunkDev& C = ch[c];
+  if (!C.act[kR]) return;  // every problem of this chunk has stopped
   const int64_t q = static_cast<int64_t>(blockIdx.x - first[c]) * kBlock + threadIdx.x;
   if (q >= (C.nslices << C.cshift)) return;
   const int64_t sl = q >> C.cshift;
@@ -110,6 +111,7 @@ __global__ __launch_bounds__(kBlock) void k_prox_batched(const ChunkDev* __restr
                                                          int nchunks, const int* __restrict__ kdev) {
   const int c = chunk_of(first, nchunks, blockIdx.x);
   const ChunkDev& C = ch[c];
+  if (!C.act[kR]) return;  // every problem of this chunk has stopped
   const int64_t q = static_cast<int64_t>(blockIdx.x - first[c]) * kBlock + threadIdx.x;
   if (q >= (C.nslicesT << C.cshift)) return;
   const int64_t sl = q >> C.cshift;
@@ -162,6 +164,7 @@ __global__ __launch_bounds__(kBlock) void k_check_fwd(const ChunkDev* __restrict
                                                       int nchunks, double* __restrict__ part, int64_t nblocks) {
   const int c = chunk_of(first, nchunks, blockIdx.x);
   const ChunkDev& C = ch[c];
+  if (!C.act[kR]) return;  // every problem of this chunk has stopped
   const int64_t q = static_cast<int64_t>(blockIdx.x - first[c]) * kBlock + threadIdx.x;
   const int64_t sl = q >> C.cshift;
   const int lane = static_cast<int>(q & (C.C - 1));
@@ -204,6 +207,7 @@ __global__ __launch_bounds__(kBlock) void k_check_bwd(const ChunkDev* __restrict
                                                       int nchunks, double* __restrict__ part, int64_t nblocks) {
   const int c = chunk_of(first, nchunks, blockIdx.x);
   const ChunkDev& C = ch[c];
+  if (!C.act[kR]) return;  // every problem of this chunk has stopped
   const int64_t q = static_cast<int64_t>(blockIdx.x - first[c]) * kBlock + threadIdx.x;
   const int64_t sl = q >> C.cshift;
   const int lane = static_cast<int>(q & (C.C - 1));
@@ -297,6 +301,7 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
     DevBuf<float> X, Y, X0, Rr;
     DevBuf<double> r64;
     DevBuf<int> act;
+    std::vector<int> act_host;  // flags of the eight slots, then "any slot active"
     int blocks_res, blocks_prox, blocks;
   };
   std::vector<Host> chunks;
@@ -319,7 +324,8 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
       h.X0.alloc(N * kR);
       h.Rr.alloc(N * kR);
       h.r64.alloc(N * kR);
-      h.act.alloc(kR);
+      h.act.alloc(kR + 1);
+      h.act_host.assign(kR + 1, 0);
       h.blocks_res = static_cast<int>((th->A.nslices * th->A.C + kBlock - 1) / kBlock);
       h.blocks_prox = static_cast<int>((th->At.nslices * th->At.C + kBlock - 1) / kBlock);
       h.blocks = std::max(h.blocks_res, h.blocks_prox);
@@ -368,7 +374,7 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
     d.r64 = h.r64.p;
     const Filter f = make_filter(th->wavelet);
     const size_t q = static_cast<size_t>(th->n / 2) * (th->n / 2);
-    std::vector<int> act(kR, 0);
+    std::vector<int>& act = h.act_host;
     for (int j = 0; j < kR; ++j) {
       d.thr[j] = 0.0f;
       if (j < static_cast<int>(h.idx.size())) {
@@ -392,8 +398,9 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
                            h.Y.p, N, j);
       }
     }
+    act[kR] = h.idx.empty() ? 0 : 1;
     WDB_HIP(hipGetLastError());
-    WDB_HIP(hipMemcpyAsync(h.act.p, act.data(), kR * sizeof(int), hipMemcpyHostToDevice, s));
+    WDB_HIP(hipMemcpyAsync(h.act.p, act.data(), (kR + 1) * sizeof(int), hipMemcpyHostToDevice, s));
   }
   WDB_HIP(hipMemcpyAsync(dch.p, hd.data(), nch * sizeof(ChunkDev), hipMemcpyHostToDevice, s));
   WDB_HIP(hipMemcpyAsync(dfirst.p, first.data(), (nch + 1) * sizeof(int), hipMemcpyHostToDevice, s));
@@ -448,7 +455,7 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
       bool any_active = false;
       for (int ci = 0; ci < nch; ++ci) {
         Host& h = chunks[ci];
-        std::vector<int> act(kR, 0);
+        std::vector<int>& act = h.act_host;
         bool changed = false;
         for (int j = 0; j < static_cast<int>(h.idx.size()); ++j) {
           const int pi = h.idx[j];
@@ -468,11 +475,13 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
             changed = true;
           }
         }
+        act[kR] = 0;
         for (int j = 0; j < static_cast<int>(h.idx.size()); ++j) {
           act[j] = done_at[h.idx[j]] < 0 ? 1 : 0;
-          any_active |= act[j] != 0;
+          act[kR] |= act[j];
         }
-        if (changed) WDB_HIP(hipMemcpyAsync(h.act.p, act.data(), kR * sizeof(int), hipMemcpyHostToDevice, s));
+        any_active |= act[kR] != 0;
+        if (changed) WDB_HIP(hipMemcpyAsync(h.act.p, act.data(), (kR + 1) * sizeof(int), hipMemcpyHostToDevice, s));
       }
       if (stopping && !any_active) {
         all_conv = true;

@@ -150,6 +150,20 @@ struct Csr32 {
   void free_all();
 };
 void csr_to_csr32(const Csr& a, Csr32* out, hipStream_t s);
+
+// Packed 16-bit form of one matrix (CSR order): per entry a 32-bit word holding
+// the scaled 16-bit value (high half) and a band-relative column code (low
+// half); entries whose column does not fit the code go to a per-row escape
+// list.  Row r owns words [meta[r].x, meta[r+1].x) and escapes
+// [meta[r].y, meta[r+1].y).
+struct Packed {
+  int64_t nrows = 0, npacked = 0, nesc = 0;
+  int2* meta = nullptr;      // device, nrows + 1
+  uint32_t* word = nullptr;  // device, npacked
+  uint16_t* ev = nullptr;    // device, nesc: escape values
+  int32_t* ec = nullptr;     // device, nesc: escape columns
+  void free_all();
+};
 // Lanes per row of the vector-CSR kernels (0: sliced-ELL kernels).
 int spmv_group();
 
@@ -185,6 +199,8 @@ struct wdb_theta {
   uint16_t* val16 = nullptr;
   uint16_t* val16T = nullptr;
   float* wrow = nullptr;
+  wdb::Packed pA, pAt;  // packed 16-bit forms (CSR order), when valtype != 0
+  int q_group = 0;      // lanes per row of the packed kernels (0: default)
   bool has_L = false;
   double L = 0.0;
   int precond = 0;
@@ -213,6 +229,16 @@ void ensure_workspace(wdb_theta* th);
 void free_workspace(wdb_theta* th);
 void finish_theta(wdb_theta* th, hipStream_t s);   // builds A/At from csr
 void set_slice_height(wdb_theta* th, int C, hipStream_t s);  // rebuilds A/At with slices of C rows
+// Packed 16-bit forms: build from cA / cAt with per-subband scales ub (device,
+// canonical subband order) and value format fmt; launchers of the packed
+// residual (Theta_K) and proximal (Theta_K^T) kernels with G lanes per row.
+bool packed_supported(const wdb_theta* th);
+void build_packed(wdb_theta* th, const float* ub, int fmt, hipStream_t s);
+int packed_group(const wdb_theta* th);
+void launch_res_packed(const wdb_theta* th, int G, const float* y, const float* b, float* r, int* kdev,
+                       int scale_out, hipStream_t s);
+void launch_prox_packed(const wdb_theta* th, int G, const float* rs, float* x, float* y, float tau, float thr,
+                        const int* kdev, const float* pinv, hipStream_t s);
 int default_slice_height();
 int kernel_group(const wdb_theta* th);  // lanes per row in use (0: sliced ELL)
 // Power iteration on D^-1/2 A^T A D^-1/2 (d = nullptr: identity), float64.

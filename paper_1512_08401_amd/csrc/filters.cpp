@@ -92,7 +92,8 @@ Filter make_filter(int wavelet) {
     const double s = 1.0 / std::sqrt(2.0);
     f.h = {s, s};
   } else if (wavelet == WDB_DB4) {
-    f.h = daubechies(4);
+    static const std::vector<double> taps = daubechies(4);  // factorised once per process
+    f.h = taps;
   } else {
     fail(WDB_ERR_ARG, "unknown wavelet %d", wavelet);
   }

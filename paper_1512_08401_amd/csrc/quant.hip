@@ -7,7 +7,9 @@
 // scale of block (A, B) is therefore u_A for every column subband B.  Because
 // u_A is a power of two, dequantisation is exact: the residual kernel multiplies
 // its row sum by w_A = 1/u_A, and writes the residual pre-multiplied by w_A so the
-// transposed kernel's gathers see exactly (q / u_A) * r.
+// transposed kernel's gathers see exactly (q / u_A) * r.  The same values are
+// also stored in the packed CSR form (value and column code in one 32-bit
+// word), which the iteration uses by default.
 #include <cmath>
 #include <cstring>
 
@@ -97,6 +99,8 @@ extern "C" wdb_status wdb_set_precision(wdb_theta* th, int32_t valtype) {
   if (th->wrow) (void)hipFree(th->wrow);
   th->val16 = th->val16T = nullptr;
   th->wrow = nullptr;
+  th->pA.free_all();
+  th->pAt.free_all();
   th->valtype = WDB_VAL_F32;
   if (valtype == WDB_VAL_F32) return WDB_OK;
   const std::vector<Subband> lay = layout(th->n, th->levels);
@@ -134,6 +138,7 @@ extern "C" wdb_status wdb_set_precision(wdb_theta* th, int32_t valtype) {
                      th->At.col, th->At.perm, th->At.nslices, th->At.C, th->N, T, dub.p, 1, valtype, v16T.p);
   hipLaunchKernelGGL(k_row_factor, dim3((th->N + 255) / 256), dim3(256), 0, s, T, dub.p, th->N, wrow.p);
   WDB_HIP(hipGetLastError());
+  if (packed_supported(th)) build_packed(th, dub.p, valtype, s);
   WDB_HIP(hipDeviceSynchronize());
   th->val16 = v16.release();
   th->val16T = v16T.release();

@@ -14,6 +14,7 @@
 // reproducible (no atomics on values).
 #include <cmath>
 #include <cstdlib>
+#include <type_traits>
 
 #include "common.hpp"
 
@@ -517,6 +518,119 @@ __global__ __launch_bounds__(kBlock) void k_copy_or_zero(const float* __restrict
   b[i] = v;
 }
 
+// ---------------------------------------------------------------------------
+// The same float64 passes over the vector-CSR copies (G lanes per row).  Each
+// block walks row tiles with a grid stride so the partial-sum count stays
+// within the workspace; the result depends only on the grid, not on timing.
+// ---------------------------------------------------------------------------
+template <int G, typename T>
+__device__ __forceinline__ double group_dot64(const CsrView& A, int64_t row, int gl, const T* __restrict__ x) {
+  double acc = 0.0;
+  if (row < A.nrows) {
+    const int64_t end = A.rp[row + 1];
+    for (int64_t k = A.rp[row] + gl; k < end; k += G)
+      acc = fma(static_cast<double>(A.val[k]), static_cast<double>(x[A.col[k]]), acc);
+  }
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+  return acc;
+}
+
+template <int G>
+__device__ __forceinline__ int64_t csr_tiles(const CsrView& A) {
+  return (A.nrows + kBlock / G - 1) / (kBlock / G);
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_obj_fwd_csr(CsrView A, const float* __restrict__ x,
+                                                        const float* __restrict__ b, double* __restrict__ r64,
+                                                        double* __restrict__ partial, int64_t nblocks) {
+  double v[3] = {0.0, 0.0, 0.0};
+  const int gl = threadIdx.x % G;
+  for (int64_t t = blockIdx.x; t < csr_tiles<G>(A); t += gridDim.x) {
+    const int64_t row = t * (kBlock / G) + threadIdx.x / G;
+    const double acc = group_dot64<G>(A, row, gl, x);
+    if (gl == 0 && row < A.nrows) {
+      const double bb = static_cast<double>(b[row]);
+      const double rr = acc - bb;
+      r64[row] = rr;
+      v[0] += rr * rr;
+      v[1] += rr * bb;
+      v[2] += fabs(static_cast<double>(x[row]));
+    }
+  }
+  block_partials<3, 0u>(v, partial, nblocks);
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_obj_bwd_csr(CsrView At, const double* __restrict__ r64,
+                                                        double* __restrict__ partial, int64_t nblocks) {
+  double v[1] = {0.0};
+  const int gl = threadIdx.x % G;
+  for (int64_t t = blockIdx.x; t < csr_tiles<G>(At); t += gridDim.x) {
+    const int64_t row = t * (kBlock / G) + threadIdx.x / G;
+    const double g = group_dot64<G>(At, row, gl, r64);
+    if (gl == 0 && row < At.nrows) v[0] = fmax(v[0], fabs(g));
+  }
+  block_partials<1, 1u>(v, partial, nblocks);
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_pi_fwd_csr(CsrView A, const double* __restrict__ vd,
+                                                       double* __restrict__ w, double* __restrict__ partial,
+                                                       int64_t nblocks) {
+  double v[1] = {0.0};
+  const int gl = threadIdx.x % G;
+  for (int64_t t = blockIdx.x; t < csr_tiles<G>(A); t += gridDim.x) {
+    const int64_t row = t * (kBlock / G) + threadIdx.x / G;
+    const double acc = group_dot64<G>(A, row, gl, vd);
+    if (gl == 0 && row < A.nrows) {
+      w[row] = acc;
+      v[0] += acc * acc;
+    }
+  }
+  block_partials<1, 0u>(v, partial, nblocks);
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_pi_bwd_csr(CsrView At, const double* __restrict__ w,
+                                                       const double* __restrict__ d, double* __restrict__ u,
+                                                       double* __restrict__ partial, int64_t nblocks) {
+  double v[1] = {0.0};
+  const int gl = threadIdx.x % G;
+  for (int64_t t = blockIdx.x; t < csr_tiles<G>(At); t += gridDim.x) {
+    const int64_t row = t * (kBlock / G) + threadIdx.x / G;
+    double acc = group_dot64<G>(At, row, gl, w);
+    if (gl == 0 && row < At.nrows) {
+      if (d) acc *= d[row];
+      u[row] = acc;
+      v[0] += acc * acc;
+    }
+  }
+  block_partials<1, 0u>(v, partial, nblocks);
+}
+
+// Calls f(std::integral_constant<int, G>) for a vector-CSR group size G.
+template <typename F>
+void with_group(int G, F&& f) {
+  switch (G) {
+    case 2: f(std::integral_constant<int, 2>{}); return;
+    case 4: f(std::integral_constant<int, 4>{}); return;
+    case 8: f(std::integral_constant<int, 8>{}); return;
+    case 16: f(std::integral_constant<int, 16>{}); return;
+    case 32: f(std::integral_constant<int, 32>{}); return;
+    case 64: f(std::integral_constant<int, 64>{}); return;
+    default: fail(WDB_ERR_ARG, "unsupported lanes per row %d", G);
+  }
+}
+
+// Grid of the float64 vector-CSR passes: one block per row tile, at most the
+// workspace's partial-sum capacity.
+int64_t csr_check_blocks(const wdb_theta* th, int G) {
+  const int64_t tiles = (th->N + kBlock / G - 1) / (kBlock / G);
+  return std::max<int64_t>(1, std::min(tiles, th->ws_nblocks));
+}
+
 __global__ void k_set_int(int* p, int v) { *p = v; }
 
 uint64_t splitmix64(uint64_t& state) {
@@ -580,7 +694,8 @@ double power_iteration(wdb_theta* th, const double* start_host, const double* di
   WDB_HIP(hipMemcpyAsync(vd, v.data(), N * sizeof(double), hipMemcpyHostToDevice, s));
   if (dinv_sqrt) hipLaunchKernelGGL(k_mul, vec_grid(N), dim3(kBlock), 0, s, vd, dinv_sqrt, N);
   const SellView A = view(th->A), At = view(th->At);
-  const int64_t nb = partial_blocks(A, At);
+  const int G = kernel_group(th);
+  const int64_t nb = G > 0 ? csr_check_blocks(th, G) : partial_blocks(A, At);
   double* part = th->ws_partial;
   std::vector<double> hist(kRhoChunk);
   double prev = 0.0, rho = 0.0;
@@ -588,8 +703,18 @@ double power_iteration(wdb_theta* th, const double* start_host, const double* di
   while (k < max_iters) {
     const int m = std::min(kRhoChunk, max_iters - k);
     for (int j = 0; j < m; ++j) {
-      hipLaunchKernelGGL(k_pi_fwd, slot_grid(A), dim3(kBlock), 0, s, A, vd, w, part, nb);
-      hipLaunchKernelGGL(k_pi_bwd, slot_grid(At), dim3(kBlock), 0, s, At, w, dinv_sqrt, u, part + nb, nb);
+      if (G > 0) {
+        with_group(G, [&](auto g) {
+          constexpr int GG = decltype(g)::value;
+          hipLaunchKernelGGL(k_pi_fwd_csr<GG>, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, cview(th->cA),
+                             vd, w, part, nb);
+          hipLaunchKernelGGL(k_pi_bwd_csr<GG>, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, cview(th->cAt),
+                             w, dinv_sqrt, u, part + nb, nb);
+        });
+      } else {
+        hipLaunchKernelGGL(k_pi_fwd, slot_grid(A), dim3(kBlock), 0, s, A, vd, w, part, nb);
+        hipLaunchKernelGGL(k_pi_bwd, slot_grid(At), dim3(kBlock), 0, s, At, w, dinv_sqrt, u, part + nb, nb);
+      }
       hipLaunchKernelGGL(k_pi_finish, dim3(1), dim3(kBlock), 0, s, part, nb, th->ws_rho, j, th->ws_scalar);
       hipLaunchKernelGGL(k_pi_scale, vec_grid(N), dim3(kBlock), 0, s, u, dinv_sqrt, th->ws_scalar, vd, N);
     }
@@ -620,10 +745,21 @@ struct Check {
 
 Check objective_check(wdb_theta* th, const float* x, const float* x0, double lambda, hipStream_t s) {
   const SellView A = view(th->A), At = view(th->At);
-  const int64_t nb = partial_blocks(A, At);
+  const int G = kernel_group(th);
+  const int64_t nb = G > 0 ? csr_check_blocks(th, G) : partial_blocks(A, At);
   double* part = th->ws_partial;
-  hipLaunchKernelGGL(k_obj_fwd, slot_grid(A), dim3(kBlock), 0, s, A, x, x0, th->ws_r64, part, nb);
-  hipLaunchKernelGGL(k_obj_bwd, slot_grid(At), dim3(kBlock), 0, s, At, th->ws_r64, part + 3 * nb, nb);
+  if (G > 0) {
+    with_group(G, [&](auto g) {
+      constexpr int GG = decltype(g)::value;
+      hipLaunchKernelGGL(k_obj_fwd_csr<GG>, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, cview(th->cA), x,
+                         x0, th->ws_r64, part, nb);
+      hipLaunchKernelGGL(k_obj_bwd_csr<GG>, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, cview(th->cAt),
+                         th->ws_r64, part + 3 * nb, nb);
+    });
+  } else {
+    hipLaunchKernelGGL(k_obj_fwd, slot_grid(A), dim3(kBlock), 0, s, A, x, x0, th->ws_r64, part, nb);
+    hipLaunchKernelGGL(k_obj_bwd, slot_grid(At), dim3(kBlock), 0, s, At, th->ws_r64, part + 3 * nb, nb);
+  }
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, part, nb, 4, 0x8u, th->ws_scalar);
   WDB_HIP(hipGetLastError());
   WDB_HIP(hipMemcpyAsync(th->host_scalar, th->ws_scalar, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -637,6 +773,12 @@ Check objective_check(wdb_theta* th, const float* x, const float* x0, double lam
 }
 
 void launch_iteration(wdb_theta* th, float* x, bool pre, float tau, float thr, hipStream_t s) {
+  if (th->valtype != WDB_VAL_F32 && th->pA.word && packed_group(th) > 0) {
+    const int G = packed_group(th);
+    launch_res_packed(th, G, th->ws_y, th->ws_x0, th->ws_r, th->ws_k, 1, s);
+    launch_prox_packed(th, G, th->ws_r, x, th->ws_y, tau, thr, th->ws_k, pre ? th->pinv : nullptr, s);
+    return;
+  }
   if (th->valtype == WDB_VAL_BF16) return launch_iteration_q<WDB_VAL_BF16>(th, x, pre, tau, thr, s);
   if (th->valtype == WDB_VAL_F16) return launch_iteration_q<WDB_VAL_F16>(th, x, pre, tau, thr, s);
   const int G = kernel_group(th);
@@ -812,6 +954,11 @@ wdb_status wdb_theta_apply(wdb_theta* th, int32_t transpose, const float* x, con
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (th->valtype != WDB_VAL_F32) {
     WDB_REQUIRE(!transpose, WDB_ERR_ARG, "transposed apply is not available with 16-bit values");
+    if (th->pA.word && wdb::packed_group(th) > 0) {
+      for (int i = 0; i < repeat; ++i) wdb::launch_res_packed(th, wdb::packed_group(th), x, b, y, nullptr, 0, s);
+      WDB_HIP(hipGetLastError());
+      return WDB_OK;
+    }
     const wdb::SellView A = wdb::view(th->A);
     const uint2* v16 = reinterpret_cast<const uint2*>(th->val16);
     for (int i = 0; i < repeat; ++i) {

@@ -47,7 +47,8 @@ class ThetaDesc(C.Structure):
     _fields_ = [("n", C.c_int32), ("levels", C.c_int32), ("wavelet", C.c_int32),
                 ("has_lipschitz", C.c_int32), ("nnz", C.c_int64), ("stored", C.c_int64),
                 ("lipschitz", C.c_double), ("threshold", C.c_double), ("lipschitz_p", C.c_double),
-                ("precond", C.c_int32), ("valtype", C.c_int32), ("slice", C.c_int32), ("group", C.c_int32)]
+                ("precond", C.c_int32), ("valtype", C.c_int32), ("slice", C.c_int32), ("group", C.c_int32),
+                ("group16", C.c_int32), ("escapes", C.c_int64)]
 
 
 class SolveOpts(C.Structure):
@@ -89,6 +90,7 @@ _SIGS = {
     "wdb_wavelet_filter": [_i32, _pd, C.POINTER(_i32)],
     "wdb_set_precision": [_vp, _i32],
     "wdb_set_kernel_layout": [_vp, _i32, _i32],
+    "wdb_set_packed_group": [_vp, _i32],
     "wdb_autotune": [_vp, C.c_char_p, _i32, C.POINTER(_i32), C.POINTER(_i32), _pd],
     "wdb_cnn_create": [_i32, _i32, _i32, C.c_uint64, C.POINTER(_vp)],
     "wdb_cnn_param_count": [_vp, C.POINTER(_i64)],
@@ -242,6 +244,10 @@ class Theta:
 
     def set_kernel_layout(self, slice: int = 64, group: int = 0):
         _check("wdb_set_kernel_layout", _lib.wdb_set_kernel_layout(self._h, slice, group))
+
+    def set_packed_group(self, group: int = 0):
+        """Lanes per row of the packed 16-bit kernels (2/4/8/16; 0 = default)."""
+        _check("wdb_set_packed_group", _lib.wdb_set_packed_group(self._h, int(group)))
 
     def autotune(self, cache_path: str | None = None, reps: int = 20):
         """Pick the fastest iteration layout for this operator; returns (slice, group, us)."""

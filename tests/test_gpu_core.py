@@ -375,6 +375,90 @@ def test_mixed_precision_matches_oracle_on_dequantised_theta(W, p64, fmt):
     assert th.info()["valtype"] == 0
 
 
+@pytest.fixture(scope="module")
+def db4_64():
+    """Oracle problem on 64x64 with the 8-tap filter (3 levels) and a rotating
+    anisotropic field: exercises the packed column code's centring for L = 8."""
+    field = synth.psf_rotating(64, 3.0, 1.0)
+    h = filters.db4()
+    T = theta.theta_dense(field, h, 3)
+    r, c, v = theta.top_k(T, 30 * 4096)
+    A = theta.to_csr(r, c, v, 4096)
+    u0 = (blur.blur(field, synth.piecewise_image(64, 31)) + synth.noise(64, 0.01, 32)).astype(np.float32)
+    return {"A": A, "x0": dwt.dwt2(u0.astype(np.float64), h, 3)}
+
+
+@pytest.mark.parametrize("fmt", ["f16", "bf16"])
+def test_packed_16bit_db4_matches_oracle(W, db4_64, fmt):
+    from oracle import quant
+    A = db4_64["A"]
+    rp, cc, vv = theta.csr_arrays(A)
+    th = W.Theta.from_csr(64, "db4", 3, rp, cc, vv)
+    start = synth.power_start(4096, 5)
+    L, _ = th.lipschitz(start)
+    th.set_precision(fmt)
+    info = th.info()
+    assert info["group16"] > 0 and info["escapes"] == 0
+    Q = quant.quantize(A, 64, 3, fmt)
+    x = np.random.default_rng(18).standard_normal(4096).astype(np.float32)
+    b = np.random.default_rng(19).standard_normal(4096).astype(np.float32)
+    ref = Q @ x.astype(np.float64) - b
+    for G in (2, 4, 8, 16):   # every lane count of the packed kernels gives the same product
+        th.set_packed_group(G)
+        y = host(th.apply(dev(x), dev(b)))
+        assert np.max(np.abs(y - ref)) <= 1e-5 * np.max(np.abs(ref)), G
+    th.set_packed_group(0)
+    lam = 1e-3
+    x0 = db4_64["x0"].astype(np.float32)
+    xg, _ = th.solve_coeffs(dev(x0), lam, 150, check_every=50)
+    A32 = sp.csr_matrix((A.data.astype(np.float32).astype(np.float64), A.indices, A.indptr), shape=A.shape)
+    Lo, _ = lipschitz.lipschitz(A32, start)
+    lam32 = float(np.float32(lam))
+    xo, _, _ = fista.fista(Q, x0.astype(np.float64), lam32, 1.0 / Lo, 150)
+    _gate(Q, x0.astype(np.float64), lam32, host(xg), xo, fista.objective(Q, x0.astype(np.float64), lam32, xo))
+
+
+def test_packed_escapes_match_oracle(W):
+    """Columns far from the row's position (random, seeded) do not fit the
+    16-bit code and are read from the per-row escape lists (the level-1
+    subbands of a 128 x 128 image are 64 wide, beyond the code's +-22)."""
+    from oracle import quant
+    n, J, N = 128, 2, 16384
+    rng = np.random.default_rng(23)
+    rows, cols = [], []
+    for r in range(N):
+        near = (r + rng.integers(-3, 4, 6)) % N          # mostly same-band neighbours (some escape too)
+        far = rng.integers(0, N, rng.integers(0, 4))     # arbitrary columns
+        cs = np.unique(np.concatenate([near, far]))
+        rows.append(np.full(cs.size, r))
+        cols.append(cs)
+    rows, cols = np.concatenate(rows), np.concatenate(cols)
+    vals = rng.standard_normal(rows.size) * 0.1
+    A = sp.csr_matrix((vals, (rows, cols)), shape=(N, N))
+    A.sort_indices()
+    th = W.Theta.from_csr(n, "haar", J, A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data)
+    th.set_precision("f16")
+    assert th.info()["escapes"] > 0
+    Q = quant.quantize(A, n, J, "f16")
+    x = rng.standard_normal(N).astype(np.float32)
+    for G in (2, 4, 8, 16):
+        th.set_packed_group(G)
+        y = host(th.apply(dev(x)))
+        ref = Q @ x.astype(np.float64)
+        assert np.max(np.abs(y - ref)) <= 1e-5 * np.max(np.abs(ref)), G
+    # the transposed packed product runs inside the solver: compare 50 iterations
+    th.set_packed_group(4)
+    start = synth.power_start(N, 6)
+    th.lipschitz(start)
+    x0 = rng.standard_normal(N).astype(np.float32)
+    xg, _ = th.solve_coeffs(dev(x0), 0.05, 50, check_every=0)
+    A32 = sp.csr_matrix((A.data.astype(np.float32).astype(np.float64), A.indices, A.indptr), shape=A.shape)
+    Lo, _ = lipschitz.lipschitz(A32, start)
+    xo, _, _ = fista.fista(Q, x0.astype(np.float64), float(np.float32(0.05)), 1.0 / Lo, 50)
+    _gate(Q, x0.astype(np.float64), float(np.float32(0.05)), host(xg), xo,
+          fista.objective(Q, x0.astype(np.float64), float(np.float32(0.05)), xo))
+
+
 # ---------------------------------------------------------------------------
 # batched solve (packs of 8 right-hand sides per operator, one launch per phase)
 # ---------------------------------------------------------------------------
