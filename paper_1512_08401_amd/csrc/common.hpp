@@ -141,12 +141,15 @@ struct Csr {
   void free_all();
 };
 
-// Float32 CSR copy used by the row-group ("vector CSR") kernels.
+// Float32 CSR copy used by the row-group ("vector CSR") kernels, with every
+// row padded to a multiple of 4 entries (value 0, column = the row index) so
+// row starts are 16-byte aligned and a lane can load 4 values and 4 columns at
+// once.  rowptr holds the padded offsets (multiples of 4).
 struct Csr32 {
-  int64_t nrows = 0, nnz = 0;
+  int64_t nrows = 0, nnz = 0, stored = 0;
   int64_t* rowptr = nullptr;  // device, nrows + 1
-  int32_t* col = nullptr;     // device, nnz
-  float* val = nullptr;       // device, nnz
+  int32_t* col = nullptr;     // device, stored
+  float* val = nullptr;       // device, stored
   void free_all();
 };
 void csr_to_csr32(const Csr& a, Csr32* out, hipStream_t s);
@@ -154,8 +157,8 @@ void csr_to_csr32(const Csr& a, Csr32* out, hipStream_t s);
 // Packed 16-bit form of one matrix (CSR order): per entry a 32-bit word holding
 // the scaled 16-bit value (high half) and a band-relative column code (low
 // half); entries whose column does not fit the code go to a per-row escape
-// list.  Row r owns words [meta[r].x, meta[r+1].x) and escapes
-// [meta[r].y, meta[r+1].y).
+// list.  Row r owns words [meta[r].x, meta[r+1].x) (a multiple of 4, padded
+// with value-0 words) and escapes [meta[r].y, meta[r+1].y).
 struct Packed {
   int64_t nrows = 0, npacked = 0, nesc = 0;
   int2* meta = nullptr;      // device, nrows + 1

@@ -13,17 +13,18 @@
 // coefficient a at level la, position (ia, ja), and a column coefficient b at
 // level lb, orientation o, position (ib, jb), the code stores
 //   dL = lb - la in [-3, 3], o in {0, 1, 2 (details), 3 (approximation)},
-//   (di, dj) in [-22, 22]^2: b's position minus the point of level lb whose
+//   (di, dj) in [-16, 15]^2: b's position minus the point of level lb whose
 //   atom is centred nearest to a's atom, modulo the side of b's subband,
-// packed as ((dL + 3) << 13) | (o << 11) | ((di + 22) * 45 + (dj + 22)).
-// Decoding is exact integer arithmetic on the power-of-two subband sides, so
-// the packed operator has exactly the columns of Theta_K.  Entries outside this
-// range are kept per row in an escape list (16-bit value, int32 column) that
-// the kernels read after the packed words.
+// as bit fields ((dL + 3) << 13) | (o << 11) | ((di + 16) << 5) | (dj + 16).
+// Decoding is exact 32-bit integer arithmetic on the power-of-two subband
+// sides (a few shifts and masks), so the packed operator has exactly the
+// columns of Theta_K.  Entries outside this range are kept per row in an
+// escape list (16-bit value, int32 column) read after the packed words.
 //
-// Kernels: vector CSR, G lanes per row; each lane loads 32/G words per step
-// before its gathers, float32 accumulation in a fixed order, butterfly
-// reduction inside the group.
+// Rows are padded to whole groups of 4 words (value 0).  Kernels: G lanes per
+// row; each lane loads two 16-byte groups of 4 words per step before its
+// gathers, float32 accumulation in a fixed order, butterfly reduction inside
+// the group.
 #include <algorithm>
 #include <cstdlib>
 #include <type_traits>
@@ -36,11 +37,10 @@ namespace wdb {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kDMax = 22;
-constexpr int kDSpan = 2 * kDMax + 1;
+constexpr int kDOff = 16;  // displacements in [-16, 15]
 constexpr int kLMax = 3;
 // Padding word of a partial step: value 0, column = a valid coefficient.
-constexpr uint32_t kPadCode = (static_cast<uint32_t>(kLMax) << 13) | (kDMax * kDSpan + kDMax);
+constexpr uint32_t kPadCode = (static_cast<uint32_t>(kLMax) << 13) | (kDOff << 5) | kDOff;
 
 struct Geo {
   int logn, J, L1;  // log2 of the image side, levels, filter length - 1
@@ -72,23 +72,34 @@ __host__ __device__ inline int band_index(const Geo& g, int level, int orient) {
 
 // Point of level lb whose atom is centred nearest to the atom at index i of
 // level la (atoms of level l at index i are centred at 2^l i + L1 (2^l - 1) / 2),
-// not yet reduced modulo the side.
+// not yet reduced modulo the side.  With P = (i << (la + 1)) + L1 2^la this is
+// (P + (1 - L1) 2^lb) >> (lb + 1).
 __host__ __device__ inline int centre_at(const Geo& g, int i, int la, int lb) {
   return ((i << (la + 1)) + g.L1 * ((1 << la) - (1 << lb)) + (1 << lb)) >> (lb + 1);
 }
 
-__host__ __device__ inline int64_t decode_col(const Geo& g, const Pos& p, uint32_t code) {
-  const int dL = static_cast<int>((code >> 13) & 7u) - kLMax;
+// Row quantities shared by every decode in the row.
+struct RowKey {
+  int level, Pi, Pj;
+};
+
+__host__ __device__ inline RowKey row_key(const Geo& g, const Pos& p) {
+  const int t = g.L1 * (1 << p.level);
+  return RowKey{p.level, (p.i << (p.level + 1)) + t, (p.j << (p.level + 1)) + t};
+}
+
+__host__ __device__ inline int decode_col(const Geo& g, const RowKey& k, uint32_t code) {
+  const int lb = k.level + static_cast<int>((code >> 13) & 7u) - kLMax;
   const int o = static_cast<int>((code >> 11) & 3u);
-  const int c = static_cast<int>(code & 2047u);
-  const int di = c / kDSpan - kDMax, dj = c % kDSpan - kDMax;
-  const int lb = p.level + dL;
+  const int di = static_cast<int>((code >> 5) & 31u) - kDOff;
+  const int dj = static_cast<int>(code & 31u) - kDOff;
   const int ls = g.logn - lb;
   const int m = (1 << ls) - 1;
-  const int ib = (centre_at(g, p.i, p.level, lb) + di) & m;
-  const int jb = (centre_at(g, p.j, p.level, lb) + dj) & m;
-  const int64_t base = o == 3 ? 0 : (static_cast<int64_t>(o) + 1) << (2 * ls);
-  return base + (static_cast<int64_t>(ib) << ls) + jb;
+  const int adj = (1 - g.L1) * (1 << lb);
+  const int ib = (((k.Pi + adj) >> (lb + 1)) + di) & m;
+  const int jb = (((k.Pj + adj) >> (lb + 1)) + dj) & m;
+  const int base = o == 3 ? 0 : (o + 1) << (2 * ls);
+  return base + (ib << ls) + jb;
 }
 
 // Code of column `col` for row position p, or -1 if it does not fit.
@@ -100,8 +111,8 @@ __host__ __device__ inline int encode_col(const Geo& g, const Pos& p, int64_t co
   const int s = 1 << ls, m = s - 1, h = s >> 1;
   const int di = ((q.i - centre_at(g, p.i, p.level, q.level) + h) & m) - h;
   const int dj = ((q.j - centre_at(g, p.j, p.level, q.level) + h) & m) - h;
-  if (di < -kDMax || di > kDMax || dj < -kDMax || dj > kDMax) return -1;
-  return ((dL + kLMax) << 13) | (q.orient << 11) | ((di + kDMax) * kDSpan + (dj + kDMax));
+  if (di < -kDOff || di >= kDOff || dj < -kDOff || dj >= kDOff) return -1;
+  return ((dL + kLMax) << 13) | (q.orient << 11) | ((di + kDOff) << 5) | (dj + kDOff);
 }
 
 __device__ __forceinline__ uint16_t q_bf16(float f) {
@@ -122,15 +133,22 @@ __device__ __forceinline__ float dq(uint32_t h) {
 }
 
 // ---------------------------------------------------------------------------
-// Encoding (one thread per row).
+// Encoding (one thread per row) from the padded float32 CSR copy; entries
+// whose value is 0 (the copy's padding) are dropped.
 // ---------------------------------------------------------------------------
-__global__ void k_count_escapes(const int64_t* __restrict__ rp, const int32_t* __restrict__ col, int64_t nrows, Geo g,
-                                int32_t* __restrict__ nesc) {
+__global__ void k_count(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                        const float* __restrict__ val, int64_t nrows, Geo g, int32_t* __restrict__ npk,
+                        int32_t* __restrict__ nesc) {
   const int64_t row = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (row >= nrows) return;
   const Pos p = pos_of(g, row);
-  int e = 0;
-  for (int64_t k = rp[row]; k < rp[row + 1]; ++k) e += encode_col(g, p, col[k]) < 0 ? 1 : 0;
+  int a = 0, e = 0;
+  for (int64_t k = rp[row]; k < rp[row + 1]; ++k) {
+    if (val[k] == 0.0f) continue;
+    if (encode_col(g, p, col[k]) >= 0) ++a;
+    else ++e;
+  }
+  npk[row] = a;
   nesc[row] = e;
 }
 
@@ -145,6 +163,7 @@ __global__ void k_encode(const int64_t* __restrict__ rp, const int32_t* __restri
   const float urow = ub[band_index(g, p.level, p.orient)];
   int64_t wk = meta[row].x, ek = meta[row].y;
   for (int64_t k = rp[row]; k < rp[row + 1]; ++k) {
+    if (val[k] == 0.0f) continue;
     const int64_t c = col[k];
     float u = urow;
     if (by_col) {
@@ -161,6 +180,7 @@ __global__ void k_encode(const int64_t* __restrict__ rp, const int32_t* __restri
       ec[ek++] = static_cast<int32_t>(c);
     }
   }
+  for (; wk < meta[row + 1].x; ++wk) word[wk] = kPadCode;  // row padding: value 0
 }
 
 // ---------------------------------------------------------------------------
@@ -179,17 +199,24 @@ PackedView pview(const Packed& m) { return PackedView{m.meta, m.word, m.ev, m.ec
 template <int G, int FMT>
 __device__ __forceinline__ float packed_dot(const PackedView& P, const Geo& g, int64_t row, int gl,
                                             const float* __restrict__ x) {
-  constexpr int B = 32 / G;
+  constexpr int U = 2;
   float acc = 0.f;
   if (row < P.nrows) {
-    const Pos p = pos_of(g, row);
+    const RowKey rk = row_key(g, pos_of(g, row));
     const int2 m0 = P.meta[row], m1 = P.meta[row + 1];
-    for (int k = m0.x + gl; k < m1.x; k += G * B) {
-      uint32_t w[B];
+    const uint4* __restrict__ w4 = reinterpret_cast<const uint4*>(P.word);
+    const int end = m1.x >> 2;
+    for (int k = (m0.x >> 2) + gl; k < end; k += G * U) {
+      uint4 e[U];
 #pragma unroll
-      for (int t = 0; t < B; ++t) w[t] = k + t * G < m1.x ? P.word[k + t * G] : kPadCode;
+      for (int t = 0; t < U; ++t) e[t] = k + t * G < end ? w4[k + t * G] : make_uint4(kPadCode, kPadCode, kPadCode, kPadCode);
 #pragma unroll
-      for (int t = 0; t < B; ++t) acc = fmaf(dq<FMT>(w[t] >> 16), x[decode_col(g, p, w[t] & 0xFFFFu)], acc);
+      for (int t = 0; t < U; ++t) {
+        acc = fmaf(dq<FMT>(e[t].x >> 16), x[decode_col(g, rk, e[t].x & 0xFFFFu)], acc);
+        acc = fmaf(dq<FMT>(e[t].y >> 16), x[decode_col(g, rk, e[t].y & 0xFFFFu)], acc);
+        acc = fmaf(dq<FMT>(e[t].z >> 16), x[decode_col(g, rk, e[t].z & 0xFFFFu)], acc);
+        acc = fmaf(dq<FMT>(e[t].w >> 16), x[decode_col(g, rk, e[t].w & 0xFFFFu)], acc);
+      }
     }
     for (int k = m0.y + gl; k < m1.y; k += G) acc = fmaf(dq<FMT>(P.ev[k]), x[P.ec[k]], acc);
   }
@@ -256,29 +283,31 @@ void encode_one(const wdb_theta* th, const Csr32& src, const float* ub, int by_c
                 hipStream_t s) {
   const Geo g = geo_of(th);
   const int64_t nrows = src.nrows;
-  DevBuf<int32_t> nesc(std::max<int64_t>(nrows, 1));
+  DevBuf<int32_t> npk(std::max<int64_t>(nrows, 1)), nesc(std::max<int64_t>(nrows, 1));
   const dim3 grid(static_cast<unsigned>((nrows + kBlock - 1) / kBlock));
-  hipLaunchKernelGGL(k_count_escapes, grid, dim3(kBlock), 0, s, src.rowptr, src.col, nrows, g, nesc.p);
+  hipLaunchKernelGGL(k_count, grid, dim3(kBlock), 0, s, src.rowptr, src.col, src.val, nrows, g, npk.p, nesc.p);
   WDB_HIP(hipGetLastError());
-  std::vector<int32_t> he(nrows);
-  std::vector<int64_t> rp(nrows + 1);
+  std::vector<int32_t> ha(nrows), he(nrows);
+  WDB_HIP(hipMemcpyAsync(ha.data(), npk.p, nrows * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   WDB_HIP(hipMemcpyAsync(he.data(), nesc.p, nrows * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  WDB_HIP(hipMemcpyAsync(rp.data(), src.rowptr, (nrows + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   WDB_HIP(hipStreamSynchronize(s));
-  WDB_REQUIRE(rp[nrows] < (int64_t{1} << 31), WDB_ERR_ARG, "too many entries for the packed form");
   std::vector<int2> meta(nrows + 1);
-  int64_t e = 0;
+  int64_t w = 0, e = 0;
   for (int64_t r = 0; r <= nrows; ++r) {
-    meta[r] = make_int2(static_cast<int>(rp[r] - e), static_cast<int>(e));
-    if (r < nrows) e += he[r];
+    WDB_REQUIRE(w < (int64_t{1} << 31) && e < (int64_t{1} << 31), WDB_ERR_ARG, "too many entries for the packed form");
+    meta[r] = make_int2(static_cast<int>(w), static_cast<int>(e));
+    if (r < nrows) {
+      w += (ha[r] + 3) / 4 * 4;  // rows padded to whole 16-byte groups
+      e += he[r];
+    }
   }
   Packed p;
   p.nrows = nrows;
   p.nesc = e;
-  p.npacked = rp[nrows] - e;
+  p.npacked = w;
   try {
     WDB_HIP(hipMalloc(reinterpret_cast<void**>(&p.meta), (nrows + 1) * sizeof(int2)));
-    WDB_HIP(hipMalloc(reinterpret_cast<void**>(&p.word), std::max<int64_t>(p.npacked, 1) * sizeof(uint32_t)));
+    WDB_HIP(hipMalloc(reinterpret_cast<void**>(&p.word), std::max<int64_t>(p.npacked, 4) * sizeof(uint32_t)));
     WDB_HIP(hipMalloc(reinterpret_cast<void**>(&p.ev), std::max<int64_t>(p.nesc, 1) * sizeof(uint16_t)));
     WDB_HIP(hipMalloc(reinterpret_cast<void**>(&p.ec), std::max<int64_t>(p.nesc, 1) * sizeof(int32_t)));
     WDB_HIP(hipMemcpyAsync(p.meta, meta.data(), (nrows + 1) * sizeof(int2), hipMemcpyHostToDevice, s));

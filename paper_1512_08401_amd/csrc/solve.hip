@@ -2,16 +2,17 @@
 // wavelet-domain problem of Sec. 1.3, plus its float64 companions: the power
 // iteration for the step 1/||Theta_K||^2 and the objective / duality-gap test.
 //
-// One FISTA iteration is two kernels over the sliced-ELL copies:
+// One FISTA iteration is two kernels over copies of Theta_K and Theta_K^T:
 //   k_res  : r = Theta_K y - x0                      (first half of the gradient)
 //   k_prox : g = Theta_K^T r; z = y - tau g / P;
 //            x_k = S_{tau lambda / P}(z);
 //            y = x_k + (k-1)/(k+2) (x_k - x_{k-1})   (rest of Alg. 1, fused)
-// Each thread owns one slot row of a C-row slice (C = 8..64, chosen per
-// operator), streams its 16-byte value and index vectors (16*C contiguous
-// bytes per slice step), gathers the vector entries through the caches and
-// accumulates in float32 in storage order, so results are bitwise
-// reproducible (no atomics on values).
+// in one of two layouts chosen per operator: sliced ELL (one thread per row
+// of a C-row slice, C = 8..64, streaming 16-byte value and index vectors) or
+// padded CSR (G lanes per row, 16-byte loads of 4 values and 4 indices).
+// Gathers go through the caches and every row is accumulated in float32 in a
+// fixed order, so results are bitwise reproducible (no atomics on values).
+// The 16-bit form uses the packed kernels of packed.hip instead.
 #include <cmath>
 #include <cstdlib>
 #include <type_traits>
@@ -251,9 +252,11 @@ void launch_iteration_q(wdb_theta* th, float* x, bool pre, float tau, float thr,
 }
 
 // ---------------------------------------------------------------------------
-// Vector-CSR variants: G consecutive lanes share one row and read its
-// consecutive entries (whose columns are spatial neighbours), then reduce with
-// a fixed butterfly inside the group.
+// Vector-CSR variants over the padded CSR copy: G consecutive lanes share one
+// row; each lane loads two 16-byte groups of 4 values and 4 columns (chunks
+// c and c + G of the row) before its gathers, so a lane has 8 entries in
+// flight per step and a row of 4k entries takes k / (2G) steps.  Partial sums
+// are reduced with a fixed butterfly inside the group.
 // ---------------------------------------------------------------------------
 struct CsrView {
   const int64_t* __restrict__ rp;
@@ -266,11 +269,29 @@ CsrView cview(const Csr32& m) { return CsrView{m.rowptr, m.col, m.val, m.nrows};
 
 template <int G>
 __device__ __forceinline__ float group_dot(const CsrView& A, int64_t row, int gl, const float* __restrict__ x) {
+  constexpr int U = 2;
   float acc = 0.f;
   if (row < A.nrows) {
-    const int64_t end = A.rp[row + 1];
-#pragma unroll 2
-    for (int64_t k = A.rp[row] + gl; k < end; k += G) acc = fmaf(A.val[k], x[A.col[k]], acc);
+    const float4* __restrict__ v4 = reinterpret_cast<const float4*>(A.val);
+    const int4* __restrict__ c4 = reinterpret_cast<const int4*>(A.col);
+    const int64_t end = A.rp[row + 1] >> 2;
+    for (int64_t k = (A.rp[row] >> 2) + gl; k < end; k += G * U) {
+      float4 v[U];
+      int4 c[U];
+#pragma unroll
+      for (int t = 0; t < U; ++t) {
+        const bool ok = k + t * G < end;
+        v[t] = ok ? v4[k + t * G] : make_float4(0.f, 0.f, 0.f, 0.f);
+        c[t] = ok ? c4[k + t * G] : make_int4(0, 0, 0, 0);
+      }
+#pragma unroll
+      for (int t = 0; t < U; ++t) {
+        acc = fmaf(v[t].x, x[c[t].x], acc);
+        acc = fmaf(v[t].y, x[c[t].y], acc);
+        acc = fmaf(v[t].z, x[c[t].z], acc);
+        acc = fmaf(v[t].w, x[c[t].w], acc);
+      }
+    }
   }
 #pragma unroll
   for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);

@@ -207,22 +207,43 @@ void csr_to_sell(const Csr& a, Sell* out, hipStream_t s, int64_t sort_window, in
   *out = m;
 }
 
+// Row r's entries go to [rowptr[r], rowptr[r] + len) and the rest of its
+// padded range (a multiple of 4) holds value 0 with column r.
+__global__ void k_fill_padded(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                              const double* __restrict__ val, const int64_t* __restrict__ prp, int64_t nrows,
+                              int32_t* __restrict__ pcol, float* __restrict__ pval) {
+  const int64_t row = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (row >= nrows) return;
+  const int64_t b = rp[row], len = rp[row + 1] - b, d = prp[row], plen = prp[row + 1] - d;
+  for (int64_t k = 0; k < plen; ++k) {
+    pcol[d + k] = k < len ? col[b + k] : static_cast<int32_t>(row);
+    pval[d + k] = k < len ? static_cast<float>(val[b + k]) : 0.0f;
+  }
+}
+
 void csr_to_csr32(const Csr& a, Csr32* out, hipStream_t s) {
   Csr32 c;
   c.nrows = a.nrows;
   c.nnz = a.nnz;
-  DevBuf<int64_t> rp(a.nrows + 1);
-  DevBuf<int32_t> col(std::max<int64_t>(a.nnz, 1));
-  DevBuf<float> val(std::max<int64_t>(a.nnz, 1));
-  WDB_HIP(hipMemcpyAsync(rp.p, a.rowptr, (a.nrows + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
-  if (a.nnz) {
-    WDB_HIP(hipMemcpyAsync(col.p, a.col, a.nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(k_to_f32, blocks_for(a.nnz), dim3(256), 0, s, a.val, val.p, a.nnz);
+  std::vector<int64_t> rp(a.nrows + 1), prp(a.nrows + 1);
+  WDB_HIP(hipMemcpyAsync(rp.data(), a.rowptr, (a.nrows + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  WDB_HIP(hipStreamSynchronize(s));
+  prp[0] = 0;
+  for (int64_t r = 0; r < a.nrows; ++r) prp[r + 1] = prp[r] + (rp[r + 1] - rp[r] + 3) / 4 * 4;
+  c.stored = prp[a.nrows];
+  WDB_REQUIRE(c.stored / 4 < (int64_t{1} << 31), WDB_ERR_ARG, "operator too large for the padded CSR copy");
+  DevBuf<int64_t> drp(a.nrows + 1);
+  DevBuf<int32_t> col(std::max<int64_t>(c.stored, 4));
+  DevBuf<float> val(std::max<int64_t>(c.stored, 4));
+  WDB_HIP(hipMemcpyAsync(drp.p, prp.data(), (a.nrows + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  if (a.nrows) {
+    hipLaunchKernelGGL(k_fill_padded, blocks_for(a.nrows), dim3(256), 0, s, a.rowptr, a.col, a.val, drp.p, a.nrows,
+                       col.p, val.p);
     WDB_HIP(hipGetLastError());
   }
   WDB_HIP(hipStreamSynchronize(s));
   out->free_all();
-  c.rowptr = rp.release();
+  c.rowptr = drp.release();
   c.col = col.release();
   c.val = val.release();
   *out = c;
