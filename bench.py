@@ -153,13 +153,13 @@ def main():
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
     t0 = time.perf_counter()
-    L, l_iters = th.lipschitz(synth.power_start(N, wl.power_seed))
-    t_lip = time.perf_counter() - t0
-    t0 = time.perf_counter()
     if not args.no_autotune:
         th.autotune(reps=10)
     layout = (th.info()["slice"], th.info()["group"])
     t_tune = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    L, l_iters = th.lipschitz(synth.power_start(N, wl.power_seed))
+    t_lip = time.perf_counter() - t0
     info = th.info()
     log(f"Theta_K built in {t_build:.2f} s (nnz {info['nnz']}, stored {info['stored']}), "
         f"L = {L:.9f} in {l_iters} power iterations / {t_lip:.2f} s")

@@ -12,14 +12,18 @@
 // the distance between the atoms' supports and in |j - k|).  For a row
 // coefficient a at level la, position (ia, ja), and a column coefficient b at
 // level lb, orientation o, position (ib, jb), the code stores
-//   dL = lb - la in [-3, 3], o in {0, 1, 2 (details), 3 (approximation)},
-//   (di, dj) in [-16, 15]^2: b's position minus the point of level lb whose
-//   atom is centred nearest to a's atom, modulo the side of b's subband,
-// as bit fields ((dL + 3) << 13) | (o << 11) | ((di + 16) << 5) | (dj + 16).
-// Decoding is exact 32-bit integer arithmetic on the power-of-two subband
-// sides (a few shifts and masks), so the packed operator has exactly the
-// columns of Theta_K.  Entries outside this range are kept per row in an
-// escape list (16-bit value, int32 column) read after the packed words.
+//   dL = lb - la in [-3, 3], band slot q in {0 (approximation), 1, 2, 3
+//   (details (0,1), (1,0), (1,1))}, and (di, dj) in [-16, 15]^2: b's position
+//   minus the point of level lb whose atom is centred nearest to a's atom,
+//   modulo the side s of b's subband,
+// as bit fields ((dL + 3) << 13) | (q << 11) | ((di + 16) << 5) | (dj + 16).
+// b's index is then q s^2 + ((ci + di) mod s) s + ((cj + dj) mod s), exact
+// integer arithmetic on power-of-two sides, so the packed operator has
+// exactly the columns of Theta_K.  The kernels tabulate (ci - 16, cj - 16,
+// s - 1, log2 s) per row and level difference in LDS once, so a decode is one
+// LDS read and a few masks and shifts.  Entries outside this range are kept
+// per row in an escape list (16-bit value, int32 column) read after the
+// packed words.
 //
 // Rows are padded to whole groups of 4 words (value 0).  Kernels: G lanes per
 // row; each lane loads two 16-byte groups of 4 words per step before its
@@ -39,8 +43,9 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kDOff = 16;  // displacements in [-16, 15]
 constexpr int kLMax = 3;
-// Padding word of a partial step: value 0, column = a valid coefficient.
-constexpr uint32_t kPadCode = (static_cast<uint32_t>(kLMax) << 13) | (kDOff << 5) | kDOff;
+// Padding word of a partial step: value 0, column = a valid coefficient (a
+// detail subband of the row's own level, which every level has).
+constexpr uint32_t kPadCode = (static_cast<uint32_t>(kLMax) << 13) | (1u << 11) | (kDOff << 5) | kDOff;
 
 struct Geo {
   int logn, J, L1;  // log2 of the image side, levels, filter length - 1
@@ -78,28 +83,24 @@ __host__ __device__ inline int centre_at(const Geo& g, int i, int la, int lb) {
   return ((i << (la + 1)) + g.L1 * ((1 << la) - (1 << lb)) + (1 << lb)) >> (lb + 1);
 }
 
-// Row quantities shared by every decode in the row.
-struct RowKey {
-  int level, Pi, Pj;
-};
-
-__host__ __device__ inline RowKey row_key(const Geo& g, const Pos& p) {
-  const int t = g.L1 * (1 << p.level);
-  return RowKey{p.level, (p.i << (p.level + 1)) + t, (p.j << (p.level + 1)) + t};
+// Decode table entry of a row for one level difference: (ci - 16, cj - 16,
+// s - 1, log2 s) of the column level lb (all zero when lb is not a level).
+__host__ __device__ inline int4 decode_entry(const Geo& g, const Pos& p, int dL) {
+  const int lb = p.level + dL;
+  if (lb < 1 || lb > g.J) return make_int4(0, 0, 0, 0);
+  const int ls = g.logn - lb;
+  return make_int4(centre_at(g, p.i, p.level, lb) - kDOff, centre_at(g, p.j, p.level, lb) - kDOff, (1 << ls) - 1, ls);
 }
 
-__host__ __device__ inline int decode_col(const Geo& g, const RowKey& k, uint32_t code) {
-  const int lb = k.level + static_cast<int>((code >> 13) & 7u) - kLMax;
-  const int o = static_cast<int>((code >> 11) & 3u);
-  const int di = static_cast<int>((code >> 5) & 31u) - kDOff;
-  const int dj = static_cast<int>(code & 31u) - kDOff;
-  const int ls = g.logn - lb;
-  const int m = (1 << ls) - 1;
-  const int adj = (1 - g.L1) * (1 << lb);
-  const int ib = (((k.Pi + adj) >> (lb + 1)) + di) & m;
-  const int jb = (((k.Pj + adj) >> (lb + 1)) + dj) & m;
-  const int base = o == 3 ? 0 : (o + 1) << (2 * ls);
-  return base + (ib << ls) + jb;
+__host__ __device__ inline int decode_with(const int4& t, uint32_t code) {
+  const int q = static_cast<int>((code >> 11) & 3u);
+  const int ib = (t.x + static_cast<int>((code >> 5) & 31u)) & t.z;
+  const int jb = (t.y + static_cast<int>(code & 31u)) & t.z;
+  return (q << (2 * t.w)) + (ib << t.w) + jb;
+}
+
+__host__ __device__ inline int decode_col(const Geo& g, const Pos& p, uint32_t code) {
+  return decode_with(decode_entry(g, p, static_cast<int>((code >> 13) & 7u) - kLMax), code);
 }
 
 // Code of column `col` for row position p, or -1 if it does not fit.
@@ -112,7 +113,8 @@ __host__ __device__ inline int encode_col(const Geo& g, const Pos& p, int64_t co
   const int di = ((q.i - centre_at(g, p.i, p.level, q.level) + h) & m) - h;
   const int dj = ((q.j - centre_at(g, p.j, p.level, q.level) + h) & m) - h;
   if (di < -kDOff || di >= kDOff || dj < -kDOff || dj >= kDOff) return -1;
-  return ((dL + kLMax) << 13) | (q.orient << 11) | ((di + kDOff) << 5) | (dj + kDOff);
+  const int slot = q.orient == 3 ? 0 : q.orient + 1;
+  return ((dL + kLMax) << 13) | (slot << 11) | ((di + kDOff) << 5) | (dj + kDOff);
 }
 
 __device__ __forceinline__ uint16_t q_bf16(float f) {
@@ -196,13 +198,25 @@ struct PackedView {
 
 PackedView pview(const Packed& m) { return PackedView{m.meta, m.word, m.ev, m.ec, m.nrows}; }
 
+// The G lanes of each row first fill the row's decode table (7 level
+// differences) in LDS; `tab` holds kBlock / G rows of 8 entries.
+template <int G>
+__device__ __forceinline__ void fill_table(const Geo& g, int64_t row, int64_t nrows, int gl, int4 (*tab)[8]) {
+  const int lr = threadIdx.x / G;
+  if (row < nrows) {
+    const Pos p = pos_of(g, row);
+    for (int d = gl; d < 2 * kLMax + 1; d += G) tab[lr][d] = decode_entry(g, p, d - kLMax);
+  }
+  __syncthreads();
+}
+
 template <int G, int FMT>
-__device__ __forceinline__ float packed_dot(const PackedView& P, const Geo& g, int64_t row, int gl,
+__device__ __forceinline__ float packed_dot(const PackedView& P, int64_t row, int gl, const int4 (*tab)[8],
                                             const float* __restrict__ x) {
   constexpr int U = 2;
   float acc = 0.f;
   if (row < P.nrows) {
-    const RowKey rk = row_key(g, pos_of(g, row));
+    const int4* __restrict__ rt = tab[threadIdx.x / G];
     const int2 m0 = P.meta[row], m1 = P.meta[row + 1];
     const uint4* __restrict__ w4 = reinterpret_cast<const uint4*>(P.word);
     const int end = m1.x >> 2;
@@ -212,10 +226,12 @@ __device__ __forceinline__ float packed_dot(const PackedView& P, const Geo& g, i
       for (int t = 0; t < U; ++t) e[t] = k + t * G < end ? w4[k + t * G] : make_uint4(kPadCode, kPadCode, kPadCode, kPadCode);
 #pragma unroll
       for (int t = 0; t < U; ++t) {
-        acc = fmaf(dq<FMT>(e[t].x >> 16), x[decode_col(g, rk, e[t].x & 0xFFFFu)], acc);
-        acc = fmaf(dq<FMT>(e[t].y >> 16), x[decode_col(g, rk, e[t].y & 0xFFFFu)], acc);
-        acc = fmaf(dq<FMT>(e[t].z >> 16), x[decode_col(g, rk, e[t].z & 0xFFFFu)], acc);
-        acc = fmaf(dq<FMT>(e[t].w >> 16), x[decode_col(g, rk, e[t].w & 0xFFFFu)], acc);
+        const uint32_t q[4] = {e[t].x, e[t].y, e[t].z, e[t].w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int4 te = rt[(q[u] >> 13) & 7u];
+          acc = fmaf(dq<FMT>(q[u] >> 16), x[decode_with(te, q[u])], acc);
+        }
       }
     }
     for (int k = m0.y + gl; k < m1.y; k += G) acc = fmaf(dq<FMT>(P.ev[k]), x[P.ec[k]], acc);
@@ -231,9 +247,11 @@ __global__ __launch_bounds__(kBlock) void k_res_pk(PackedView P, Geo g, const fl
                                                    const float* __restrict__ y, const float* __restrict__ b,
                                                    float* __restrict__ r, int* __restrict__ kdev, int scale_out) {
   if (kdev && blockIdx.x == 0 && threadIdx.x == 0) *kdev += 1;
+  __shared__ int4 tab[kBlock / G][8];
   const int64_t row = static_cast<int64_t>(blockIdx.x) * (kBlock / G) + threadIdx.x / G;
   const int gl = threadIdx.x % G;
-  const float acc = packed_dot<G, FMT>(P, g, row, gl, y);
+  fill_table<G>(g, row, P.nrows, gl, tab);
+  const float acc = packed_dot<G, FMT>(P, row, gl, tab, y);
   if (gl != 0 || row >= P.nrows) return;
   const float w = wrow[row];
   const float rr = b ? w * acc - b[row] : w * acc;
@@ -246,9 +264,11 @@ __global__ __launch_bounds__(kBlock) void k_prox_pk(PackedView P, Geo g, const f
                                                     float* __restrict__ x, float* __restrict__ y, float tau,
                                                     float thr, const int* __restrict__ kdev,
                                                     const float* __restrict__ pinv) {
+  __shared__ int4 tab[kBlock / G][8];
   const int64_t row = static_cast<int64_t>(blockIdx.x) * (kBlock / G) + threadIdx.x / G;
   const int gl = threadIdx.x % G;
-  const float gr = packed_dot<G, FMT>(P, g, row, gl, rs);
+  fill_table<G>(g, row, P.nrows, gl, tab);
+  const float gr = packed_dot<G, FMT>(P, row, gl, tab, rs);
   if (gl != 0 || row >= P.nrows) return;
   const int k = *kdev;
   const float beta = static_cast<float>((static_cast<double>(k) - 1.0) / (static_cast<double>(k) + 2.0));

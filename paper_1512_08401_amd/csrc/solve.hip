@@ -546,11 +546,29 @@ __global__ __launch_bounds__(kBlock) void k_copy_or_zero(const float* __restrict
 // ---------------------------------------------------------------------------
 template <int G, typename T>
 __device__ __forceinline__ double group_dot64(const CsrView& A, int64_t row, int gl, const T* __restrict__ x) {
+  constexpr int U = 2;
   double acc = 0.0;
   if (row < A.nrows) {
-    const int64_t end = A.rp[row + 1];
-    for (int64_t k = A.rp[row] + gl; k < end; k += G)
-      acc = fma(static_cast<double>(A.val[k]), static_cast<double>(x[A.col[k]]), acc);
+    const float4* __restrict__ v4 = reinterpret_cast<const float4*>(A.val);
+    const int4* __restrict__ c4 = reinterpret_cast<const int4*>(A.col);
+    const int64_t end = A.rp[row + 1] >> 2;
+    for (int64_t k = (A.rp[row] >> 2) + gl; k < end; k += G * U) {
+      float4 v[U];
+      int4 c[U];
+#pragma unroll
+      for (int t = 0; t < U; ++t) {
+        const bool ok = k + t * G < end;
+        v[t] = ok ? v4[k + t * G] : make_float4(0.f, 0.f, 0.f, 0.f);
+        c[t] = ok ? c4[k + t * G] : make_int4(0, 0, 0, 0);
+      }
+#pragma unroll
+      for (int t = 0; t < U; ++t) {
+        acc = fma(static_cast<double>(v[t].x), static_cast<double>(x[c[t].x]), acc);
+        acc = fma(static_cast<double>(v[t].y), static_cast<double>(x[c[t].y]), acc);
+        acc = fma(static_cast<double>(v[t].z), static_cast<double>(x[c[t].z]), acc);
+        acc = fma(static_cast<double>(v[t].w), static_cast<double>(x[c[t].w]), acc);
+      }
+    }
   }
 #pragma unroll
   for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
