@@ -95,6 +95,12 @@ def psf_rotating(n: int, major: float, minor: float, trunc: float = 3.0) -> PsfF
                     math.pi * col / n, trunc)
 
 
+def psf_stationary(n: int, major: float, minor: float, angle: float = 0.0, trunc: float = 3.0) -> PsfField:
+    """The same Gaussian PSF at every pixel: H is a circular convolution."""
+    return PsfField(n, np.full((n, n), float(major)), np.full((n, n), float(minor)),
+                    np.full((n, n), float(angle)), trunc)
+
+
 def power_start(size: int, seed: int) -> np.ndarray:
     """Seeded N(0, 1) start vector for the power iteration."""
     return np.random.default_rng(seed).standard_normal(size)
