@@ -134,6 +134,13 @@ def level_of(n: int, levels: int):
     return out
 
 
+def scale_index(n: int, levels: int):
+    """Per-coefficient scale j(i) = log2(n) - level in the paper's convention
+    (a subband of scale j has 2^j x 2^j coefficients; the approximation has the
+    scale of level J)."""
+    return int(np.log2(n)) - level_of(n, levels)
+
+
 def subband_of(n: int, levels: int):
     """Per-coefficient subband index (canonical order: 0 = A_J, then details)."""
     out = np.empty(n * n, dtype=np.int64)

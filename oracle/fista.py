@@ -68,15 +68,19 @@ def objective(A, x0: np.ndarray, lam: float, x: np.ndarray, w=None) -> float:
     return 0.5 * float(r @ r) + lam * float(np.sum(wt * np.abs(x)))
 
 
-def duality_gap(A, x0: np.ndarray, lam: float, x: np.ndarray):
-    """(E, D, gap, rel_gap) for uniform weights.
+def duality_gap(A, x0: np.ndarray, lam: float, x: np.ndarray, w=None):
+    """(E, D, gap, rel_gap).
 
-    r = A x - x0, s = min(1, lam / ||A^T r||_inf), nu = s r,
-    D(nu) = -1/2 ||nu||^2 - <nu, x0>;  gap = E - D >= 0 (weak duality).
+    r = A x - x0.  The dual of the weighted problem is max -1/2 ||nu||^2 - <nu, x0>
+    over |(A^T nu)_i| <= lam w_i; nu = s r with the largest s <= 1 that is
+    feasible, s = min(1, lam / max_i(|(A^T r)_i| / w_i)), gives
+    D(nu) = -1/2 s^2 ||r||^2 - s <r, x0> and gap = E - D >= 0 (weak duality).
+    Uniform weights when w is None.
     """
     r = A @ x - x0
-    E = 0.5 * float(r @ r) + lam * float(np.sum(np.abs(x)))
-    gmax = float(np.max(np.abs(A.T @ r))) if r.size else 0.0
+    wt = np.ones(A.shape[1]) if w is None else np.asarray(w, dtype=np.float64)
+    E = 0.5 * float(r @ r) + lam * float(np.sum(wt * np.abs(x)))
+    gmax = float(np.max(np.abs(A.T @ r) / wt)) if r.size else 0.0
     s = 1.0 if gmax <= lam else lam / gmax
     D = -0.5 * s * s * float(r @ r) - s * float(r @ x0)
     gap = E - D

@@ -45,6 +45,28 @@ def theta_entry(field, h: np.ndarray, levels: int, a: int, b: int, H=None) -> fl
     return float(np.sum(psi_a * _blur.blur(field, psi_b, H)))
 
 
+def top_k_weighted(T: np.ndarray, K: int, sigma: np.ndarray):
+    """Weighted thresholding of Sec. 3.7: keep the K entries whose
+    |sigma_b Theta[a, b]| are largest (sigma on the column, i.e. the input
+    coefficient the operator acts on; ties: smaller linear index first);
+    the kept values are Theta's own.  Returns (rows, cols, vals) by (row, col)."""
+    S = np.abs(T) * np.asarray(sigma, dtype=np.float64)[None, :]
+    flat = S.ravel()
+    nz = int(np.count_nonzero(flat))
+    K = min(int(K), nz)
+    order = np.argsort(-flat, kind="stable")[:K]
+    order.sort()
+    N = T.shape[1]
+    rows = order // N
+    cols = order % N
+    return rows, cols, T.ravel()[order]
+
+
+def column_scale_weights(n: int, levels: int) -> np.ndarray:
+    """sigma_b = 2^-k for a column b of paper scale k (Sec. 3.7)."""
+    return 2.0 ** (-_dwt.scale_index(n, levels).astype(np.float64))
+
+
 def top_k(T: np.ndarray, K: int):
     """Keep the K largest |T| (ties: smaller linear index first).
 
