@@ -104,6 +104,9 @@ typedef struct {
   int32_t group;       /* lanes per row of the vector-CSR kernels (0: sliced ELL) */
   int32_t group16;     /* lanes per row of the packed 16-bit kernels (0: not in use) */
   int64_t escapes;     /* entries of Theta_K and Theta_K^T outside the packed column code */
+  int32_t conv_build;  /* 1 if wdb_build_theta took the convolution fast path */
+  int32_t l1_weights;  /* wdb_l1_weights kind in use */
+  int32_t rule;        /* wdb_threshold_rule of the build (threshold is then the ranked value) */
 } wdb_theta_desc;
 
 /* ---------------------------------------------------------------------------
@@ -116,11 +119,30 @@ typedef struct {
  * non-zeros than the budget keeps them all).  Every entry is computed in
  * float64 from its definition <psi_a, H psi_b> on the GPU; the kept values
  * are stored as float32 for the solver and as float64 for export.
+ * When every pixel carries the same PSF (H is a convolution) the build takes
+ * the fast path of Alg. 3: the subband blocks of Theta are circulant (Sec.
+ * 3.6), so only one column per subband (3J + 1 columns) is computed and the
+ * kept entries are copied out of them; set the environment variable
+ * WDB_BUILD_GENERAL=1 to force the general build.  The result is the same
+ * Theta_K up to rounding of the values (and the order of near-equal
+ * magnitudes at the cut).
  * `field` and its arrays are host memory, read during the call.
  * Synchronises `stream`.  Errors: WDB_ERR_ARG, _SIZE, _LEVELS, _NONFINITE,
  * _OOM, _HIP. */
 wdb_status wdb_build_theta(const wdb_psf_field* field, int32_t wavelet, int32_t levels,
                            int64_t nnz_budget, void* stream, wdb_theta** out);
+
+/* Thresholding rules of Sec. 3.7: WDB_THRESH_NAIVE keeps the K largest
+ * |Theta[a, b]|; WDB_THRESH_SCALE keeps the K largest sigma_b |Theta[a, b]|
+ * with sigma_b = 2^-k for a column b of scale k (the weights the paper
+ * recommends; sigma weighs the input coefficient the operator acts on, which
+ * is the closed form of the paper's minimax problem with the input measured
+ * in the norm sum_b |x_b| / sigma_b).  Equal ranked values at the cut keep
+ * the smaller a*N + b; the kept values are Theta's own.  wdb_build_theta is
+ * this call with WDB_THRESH_NAIVE. */
+typedef enum { WDB_THRESH_NAIVE = 0, WDB_THRESH_SCALE = 1 } wdb_threshold_rule;
+wdb_status wdb_build_theta_rule(const wdb_psf_field* field, int32_t wavelet, int32_t levels,
+                                int64_t nnz_budget, int32_t rule, void* stream, wdb_theta** out);
 
 /* Operator from a host CSR matrix (N = n*n rows, strictly increasing column
  * indices within each row, values float64 rounded to float32 for the
@@ -185,6 +207,18 @@ wdb_status wdb_set_precond(wdb_theta* th, int32_t kind, double eps, const double
  * using the float32 values, so they score iterates against the unquantised
  * Theta_K.  Synchronises.  Errors: WDB_ERR_ARG, _OOM, _HIP. */
 wdb_status wdb_set_precision(wdb_theta* th, int32_t valtype);
+
+/* Weights w of the l1 term, G(x) = sum_i w[i] |x[i]| (Sec. 1.3), used by the
+ * single-problem solver (proximal threshold tau lambda w_i / P_i) and by its
+ * float64 checks (E = 1/2 ||r||^2 + lambda sum_i w_i |x_i|; the dual point is
+ * scaled by s = min(1, lambda / max_i |(Theta_K^T r)_i| / w_i)).
+ * kind WDB_L1_UNIFORM: w = 1 (default); WDB_L1_SCALE: w[i] = j(i), the scale
+ * of coefficient i (log2 n - level; the weights of the experiments of Sec. 5);
+ * WDB_L1_GIVEN: w = the N floats at `w` (host, finite, > 0).  The batched
+ * solver refuses handles with non-uniform weights.  Synchronises.  Errors:
+ * WDB_ERR_ARG, _NONFINITE, _OOM, _HIP. */
+typedef enum { WDB_L1_UNIFORM = 0, WDB_L1_SCALE = 1, WDB_L1_GIVEN = 2 } wdb_l1_weights;
+wdb_status wdb_set_l1_weights(wdb_theta* th, int32_t kind, const float* w);
 
 /* Lanes per row of the packed 16-bit kernels: 2, 4, 8 or 16, or 0 for the
  * default (4, or the environment variable WDB_Q_GROUP, where 0 selects the

@@ -118,6 +118,9 @@ wdb_status wdb_theta_info(const wdb_theta* th, wdb_theta_desc* out) {
   out->group = wdb::kernel_group(th);
   out->group16 = th->valtype != WDB_VAL_F32 && th->pA.word ? wdb::packed_group(th) : 0;
   out->escapes = th->pA.nesc + th->pAt.nesc;
+  out->conv_build = th->conv_build;
+  out->l1_weights = th->l1_kind;
+  out->rule = th->rule;
   WDB_API_END
 }
 
@@ -149,6 +152,8 @@ void wdb_theta_free(wdb_theta* th) {
   if (th->wrow) (void)hipFree(th->wrow);
   th->pA.free_all();
   th->pAt.free_all();
+  if (th->l1w) (void)hipFree(th->l1w);
+  if (th->l1w_pre) (void)hipFree(th->l1w_pre);
   wdb::free_workspace(th);
   delete th;
 }

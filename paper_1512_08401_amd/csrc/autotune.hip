@@ -21,7 +21,7 @@ int kernel_group(const wdb_theta* th);
 void launch_res(int G, const Sell& sell, const Csr32& csr, const float* y, const float* b, float* r, int* kdev,
                 hipStream_t s);
 void launch_prox(int G, const Sell& sell, const Csr32& csr, const float* r, float* x, float* y, float tau, float thr,
-                 float beta, const int* kdev, const float* pinv, hipStream_t s);
+                 float beta, const int* kdev, const float* pinv, const float* tw, hipStream_t s);
 }  // namespace wdb
 
 namespace {
@@ -78,7 +78,7 @@ void tune_packed(wdb_theta* th, const char* cache_path, const std::string& key, 
       for (int G : {2, 4, 8, 16}) {
         auto pair = [&]() {
           launch_res_packed(th, G, th->ws_y, th->ws_x0, th->ws_r, nullptr, 1, s);
-          launch_prox_packed(th, G, th->ws_r, th->ws_img, th->ws_y, 1e-3f, 1e-6f, th->ws_k, nullptr, s);
+          launch_prox_packed(th, G, th->ws_r, th->ws_img, th->ws_y, 1e-3f, 1e-6f, th->ws_k, nullptr, nullptr, s);
         };
         for (int i = 0; i < 3; ++i) pair();
         WDB_HIP(hipEventRecord(e0, s));
@@ -151,7 +151,8 @@ extern "C" wdb_status wdb_autotune(wdb_theta* th, const char* cache_path, int32_
         if (C) set_slice_height(th, C, s);
         auto pair = [&]() {
           launch_res(G, th->A, th->cA, th->ws_y, th->ws_x0, th->ws_r, nullptr, s);
-          launch_prox(G, th->At, th->cAt, th->ws_r, th->ws_img, th->ws_y, 1e-3f, 1e-6f, 0.5f, nullptr, nullptr, s);
+          launch_prox(G, th->At, th->cAt, th->ws_r, th->ws_img, th->ws_y, 1e-3f, 1e-6f, 0.5f, nullptr, nullptr,
+                      nullptr, s);
         };
         for (int i = 0; i < 3; ++i) pair();
         WDB_HIP(hipEventRecord(e0, s));

@@ -291,6 +291,7 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
     WDB_REQUIRE(p.theta && (p.u || p.x0) && p.x_out, WDB_ERR_ARG, "problem %d has a null pointer", i);
     WDB_REQUIRE(std::isfinite(p.lambda) && p.lambda >= 0.0f, WDB_ERR_NONFINITE, "problem %d: bad lambda", i);
     WDB_REQUIRE(p.theta->valtype == WDB_VAL_F32, WDB_ERR_ARG, "batched solve uses float32 values");
+    WDB_REQUIRE(p.theta->l1w == nullptr, WDB_ERR_ARG, "batched solve uses uniform l1 weights");
     WDB_REQUIRE(!pre || p.theta->precond != 0, WDB_ERR_ARG, "problem %d: no preconditioner set", i);
     if (!members.count(p.theta)) order.push_back(p.theta);
     members[p.theta].push_back(i);

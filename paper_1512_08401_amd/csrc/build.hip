@@ -51,6 +51,7 @@ struct Geom {
 
 struct Select {
   int mode;   // 0: histogram, 1: emit above prefix + collect prefix, 2: emit every non-zero
+  int scaled; // 1: rank by sigma_b |theta| with sigma_b = 2^-k = 1 / (side of b's subband) (Sec. 3.7)
   int pbits;  // bits of the key already fixed
   int shift;  // histogram digit position
   unsigned long long prefix;
@@ -104,10 +105,12 @@ __device__ inline void emit_one(bool want, int a, int b, double v, const Emit& E
   }
 }
 
-__device__ inline void handle(const Select& S, double v, int a, int b, unsigned* lhist, const Emit& out,
+// sb: the column's ranking weight (1, or sigma_b; a power of two, so the
+// scaled magnitude is exact).
+__device__ inline void handle(const Select& S, double v, double sb, int a, int b, unsigned* lhist, const Emit& out,
                               const Emit& bnd, int* err) {
   const bool nz = v != 0.0;
-  const unsigned long long key = static_cast<unsigned long long>(__double_as_longlong(fabs(v)));
+  const unsigned long long key = static_cast<unsigned long long>(__double_as_longlong(fabs(v) * sb));
   if (S.mode == 0) {
     if (nz && (S.pbits == 0 || (key >> (64 - S.pbits)) == S.prefix))
       atomicAdd(&lhist[(key >> S.shift) & S.dmask], 1u);
@@ -137,6 +140,7 @@ __global__ __launch_bounds__(256) void k_theta_columns(Geom G, PsfDev P, const d
     int k = 0;
     while (k + 1 < G.nsub && b >= G.sub_off[k + 1]) ++k;
     const int lev = G.sub_level[k], side = G.sub_side[k];
+    const double sb = S.scaled ? 1.0 / static_cast<double>(side) : 1.0;
     const int64_t pos = b - G.sub_off[k];
     const int p = static_cast<int>(pos / side), q = static_cast<int>(pos % side);
     const int wl = G.flen[lev];
@@ -202,10 +206,10 @@ __global__ __launch_bounds__(256) void k_theta_columns(Geom G, PsfDev P, const d
         }
         ob[o] = a00;
         const int64_t loc = static_cast<int64_t>(I) * Mh + Jc;
-        handle(S, a01, static_cast<int>(G.sub_off[ks] + loc), static_cast<int>(b), lhist, out, bnd, err);
-        handle(S, a10, static_cast<int>(G.sub_off[ks + 1] + loc), static_cast<int>(b), lhist, out, bnd, err);
-        handle(S, a11, static_cast<int>(G.sub_off[ks + 2] + loc), static_cast<int>(b), lhist, out, bnd, err);
-        if (lv == G.J) handle(S, a00, static_cast<int>(G.sub_off[0] + loc), static_cast<int>(b), lhist, out, bnd, err);
+        handle(S, a01, sb, static_cast<int>(G.sub_off[ks] + loc), static_cast<int>(b), lhist, out, bnd, err);
+        handle(S, a10, sb, static_cast<int>(G.sub_off[ks + 1] + loc), static_cast<int>(b), lhist, out, bnd, err);
+        handle(S, a11, sb, static_cast<int>(G.sub_off[ks + 2] + loc), static_cast<int>(b), lhist, out, bnd, err);
+        if (lv == G.J) handle(S, a00, sb, static_cast<int>(G.sub_off[0] + loc), static_cast<int>(b), lhist, out, bnd, err);
       }
       __syncthreads();
       double* t = in;
@@ -296,15 +300,215 @@ struct Builder {
   }
 };
 
+// ---------------------------------------------------------------------------
+// Convolution fast path (Alg. 3; circulant subband blocks, Sec. 3.6).
+//
+// With the same PSF at every pixel, H is a circular convolution with a kernel
+// symmetric under x -> -x (the Gaussian of psf.hip), so H = H^* and Theta is
+// symmetric.  Every block (R, C) of Theta is then a rectangular circulant
+// matrix generated by the column gamma_k = Psi^*(H psi_k0) of one atom per
+// subband k:
+//   * C coarser than R:  Theta[(R, p + r q), (C, q)] = gamma_C[(R, p)],
+//   * C as fine as R or finer: Theta[(R, m), (C, p + r m)] = gamma_R[(C, p)]
+// (r the ratio of the two sides, positions taken modulo the finer side).  So
+// the 3J + 1 representative columns are computed exactly as the general
+// build computes any column, each non-zero becomes a generator with a known
+// number of copies, the K largest magnitudes are selected on the generators
+// (equal magnitudes at the cut ordered by a * N + b like the general build)
+// and the kept copies are written out in parallel.
+// ---------------------------------------------------------------------------
+bool field_is_stationary(const wdb_psf_field* f) {
+  const int64_t N = static_cast<int64_t>(f->n) * f->n;
+  for (int64_t i = 1; i < N; ++i)
+    if (f->sig_major[i] != f->sig_major[0] || f->sig_minor[i] != f->sig_minor[0] || f->angle[i] != f->angle[0])
+      return false;
+  return true;
+}
+
+struct GenDev {
+  int64_t off_k, off_b;  // subband offsets: k enumerates the copies, b holds the moving position
+  int side_k, side_b;
+  int p1, p2, r, form;   // form 0: row in k, column in b; 1: row in b, column in k
+  double v;
+};
+
+__device__ __host__ inline void gen_entry(const GenDev& g, int64_t idx, int32_t* row, int32_t* col) {
+  const int i1 = static_cast<int>(idx / g.side_k), i2 = static_cast<int>(idx % g.side_k);
+  const int q1 = (g.p1 + g.r * i1) & (g.side_b - 1), q2 = (g.p2 + g.r * i2) & (g.side_b - 1);
+  const int64_t ak = g.off_k + static_cast<int64_t>(i1) * g.side_k + i2;
+  const int64_t ab = g.off_b + static_cast<int64_t>(q1) * g.side_b + q2;
+  *row = static_cast<int32_t>(g.form == 0 ? ak : ab);
+  *col = static_cast<int32_t>(g.form == 0 ? ab : ak);
+}
+
+__global__ void k_expand(const GenDev* __restrict__ gens, const int64_t* __restrict__ first, int ngen,
+                         int64_t total, int32_t* __restrict__ row, int32_t* __restrict__ col,
+                         double* __restrict__ val) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  int lo = 0, hi = ngen - 1;  // last generator with first[g] <= t
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (first[mid] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  gen_entry(gens[lo], t - first[lo], row + t, col + t);
+  val[t] = gens[lo].v;
+}
+
+// Builds Theta_K of a stationary field; returns the handle's CSR pieces.
+void build_stationary(Builder& B, int64_t nnz_budget, int scaled, unsigned long long* K_out, double* thr_out,
+                      DevBuf<int32_t>& orow, DevBuf<int32_t>& ocol, DevBuf<double>& oval) {
+  const Geom& G = B.G;
+  const int64_t N = static_cast<int64_t>(G.n) * G.n;
+  hipStream_t s = B.s;
+  // 1. representative columns gamma_k (every non-zero, float64)
+  DevBuf<int32_t> er(N), ec(N);
+  DevBuf<double> ev(N);
+  std::vector<GenDev> gens;
+  std::vector<int32_t> hr;
+  std::vector<double> hv;
+  auto band_of = [&](int64_t a) {
+    int k = 0;
+    while (k + 1 < G.nsub && a >= G.sub_off[k + 1]) ++k;
+    return k;
+  };
+  for (int k = 0; k < G.nsub; ++k) {
+    WDB_HIP(hipMemsetAsync(B.counters.p, 0, sizeof(unsigned long long), s));
+    Emit out{er.p, ec.p, ev.p, B.counters.p, static_cast<unsigned long long>(N)};
+    Emit none{nullptr, nullptr, nullptr, B.counters.p + 1, 0};
+    Select S{2, 0, 0, 0, 0, 0};
+    hipLaunchKernelGGL(k_theta_columns, dim3(1), dim3(256), 0, s, G, B.psf.dev(), B.ftab.p, B.scratch.p, B.cap,
+                       G.sub_off[k], G.sub_off[k] + 1, S, B.hist.p, out, none, B.err.p);
+    WDB_HIP(hipGetLastError());
+    unsigned long long cnt = 0;
+    WDB_HIP(hipMemcpyAsync(&cnt, B.counters.p, sizeof(cnt), hipMemcpyDeviceToHost, s));
+    WDB_HIP(hipStreamSynchronize(s));
+    int e = 0;
+    WDB_HIP(hipMemcpy(&e, B.err.p, sizeof(int), hipMemcpyDeviceToHost));
+    WDB_REQUIRE(e == 0 && cnt <= static_cast<unsigned long long>(N), WDB_ERR_HIP,
+                "representative column %d failed (code %d)", k, e);
+    hr.resize(cnt);
+    hv.resize(cnt);
+    WDB_HIP(hipMemcpy(hr.data(), er.p, cnt * sizeof(int32_t), hipMemcpyDeviceToHost));
+    WDB_HIP(hipMemcpy(hv.data(), ev.p, cnt * sizeof(double), hipMemcpyDeviceToHost));
+    const int sk = G.sub_side[k];
+    for (unsigned long long i = 0; i < cnt; ++i) {
+      const int b = band_of(hr[i]);
+      const int sb = G.sub_side[b];
+      const int64_t pos = hr[i] - G.sub_off[b];
+      GenDev g{G.sub_off[k], G.sub_off[b], sk, sb, static_cast<int>(pos / sb), static_cast<int>(pos % sb),
+               sb / sk, 0, hv[i]};
+      if (sb > sk) {  // block (R = b, C = k), C coarser: copies over the columns of k
+        g.form = 1;
+        gens.push_back(g);
+      }
+      if (sb >= sk) {  // block (R = k, C = b), C as fine or finer: copies over the rows of k
+        g.form = 0;
+        gens.push_back(g);
+      }
+    }
+  }
+  // 2. the K largest (weighted) magnitudes over the generators and their copies
+  auto mag = [scaled](const GenDev& g) {
+    const int side_col = g.form == 0 ? g.side_b : g.side_k;
+    return scaled ? std::fabs(g.v) / side_col : std::fabs(g.v);
+  };
+  std::sort(gens.begin(), gens.end(), [&](const GenDev& x, const GenDev& y) { return mag(x) > mag(y); });
+  const unsigned long long budget = static_cast<unsigned long long>(nnz_budget);
+  unsigned long long cum = 0;
+  size_t full = 0;
+  std::vector<std::pair<int64_t, std::pair<int32_t, int32_t>>> tie;  // (a*N + b, (a, b))
+  double tie_v = 0.0, threshold = 0.0;
+  std::vector<double> tie_val;
+  while (full < gens.size()) {
+    size_t e = full;
+    unsigned long long grp = 0;
+    while (e < gens.size() && mag(gens[e]) == mag(gens[full])) {
+      grp += static_cast<unsigned long long>(gens[e].side_k) * gens[e].side_k;
+      ++e;
+    }
+    if (cum + grp <= budget) {
+      cum += grp;
+      threshold = mag(gens[full]);
+      full = e;
+      continue;
+    }
+    // equal magnitudes straddle the cut: keep the smallest linear indices
+    const unsigned long long need = budget - cum;
+    if (need == 0) break;
+    std::vector<std::pair<int64_t, size_t>> cand;  // (a*N + b, generator * 2^32 + copy)
+    cand.reserve(grp);
+    for (size_t g = full; g < e; ++g) {
+      const int64_t m = static_cast<int64_t>(gens[g].side_k) * gens[g].side_k;
+      for (int64_t i = 0; i < m; ++i) {
+        int32_t a, b;
+        gen_entry(gens[g], i, &a, &b);
+        cand.push_back({static_cast<int64_t>(a) * N + b, ((g - full) << 32) | static_cast<size_t>(i)});
+      }
+    }
+    std::nth_element(cand.begin(), cand.begin() + (need - 1), cand.end());
+    for (unsigned long long i = 0; i < need; ++i) {
+      const size_t g = full + (cand[i].second >> 32);
+      tie.push_back({cand[i].first, {static_cast<int32_t>(cand[i].first / N), static_cast<int32_t>(cand[i].first % N)}});
+      tie_val.push_back(gens[g].v);
+    }
+    tie_v = mag(gens[full]);
+    threshold = tie_v;
+    cum += need;
+    break;
+  }
+  // 3. write the kept copies
+  const unsigned long long K = cum;
+  const int ngen = static_cast<int>(full);
+  std::vector<int64_t> first(ngen + 1, 0);
+  for (int g = 0; g < ngen; ++g) first[g + 1] = first[g] + static_cast<int64_t>(gens[g].side_k) * gens[g].side_k;
+  orow.alloc(std::max<unsigned long long>(K, 1));
+  ocol.alloc(std::max<unsigned long long>(K, 1));
+  oval.alloc(std::max<unsigned long long>(K, 1));
+  if (ngen > 0) {
+    DevBuf<GenDev> dg(ngen);
+    DevBuf<int64_t> df(ngen + 1);
+    WDB_HIP(hipMemcpy(dg.p, gens.data(), ngen * sizeof(GenDev), hipMemcpyHostToDevice));
+    WDB_HIP(hipMemcpy(df.p, first.data(), (ngen + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+    const int64_t tot = first[ngen];
+    hipLaunchKernelGGL(k_expand, dim3(static_cast<unsigned>((tot + 255) / 256)), dim3(256), 0, s, dg.p, df.p, ngen,
+                       tot, orow.p, ocol.p, oval.p);
+    WDB_HIP(hipGetLastError());
+    WDB_HIP(hipStreamSynchronize(s));
+  }
+  if (!tie.empty()) {
+    std::vector<int32_t> tr(tie.size()), tc(tie.size());
+    for (size_t i = 0; i < tie.size(); ++i) {
+      tr[i] = tie[i].second.first;
+      tc[i] = tie[i].second.second;
+    }
+    const int64_t at = first[ngen];
+    WDB_HIP(hipMemcpy(orow.p + at, tr.data(), tie.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    WDB_HIP(hipMemcpy(ocol.p + at, tc.data(), tie.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    WDB_HIP(hipMemcpy(oval.p + at, tie_val.data(), tie.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  (void)tie_v;
+  *K_out = K;
+  *thr_out = threshold;
+}
+
 }  // namespace
 
 }  // namespace wdb
 
 extern "C" wdb_status wdb_build_theta(const wdb_psf_field* field, int32_t wavelet, int32_t levels,
                                       int64_t nnz_budget, void* stream, wdb_theta** out) {
+  return wdb_build_theta_rule(field, wavelet, levels, nnz_budget, WDB_THRESH_NAIVE, stream, out);
+}
+
+extern "C" wdb_status wdb_build_theta_rule(const wdb_psf_field* field, int32_t wavelet, int32_t levels,
+                                           int64_t nnz_budget, int32_t rule, void* stream, wdb_theta** out) {
   using namespace wdb;
   WDB_API_BEGIN
   WDB_REQUIRE(field && out, WDB_ERR_ARG, "null argument");
+  WDB_REQUIRE(rule == WDB_THRESH_NAIVE || rule == WDB_THRESH_SCALE, WDB_ERR_ARG, "unknown thresholding rule %d", rule);
+  const int scaled = rule == WDB_THRESH_SCALE ? 1 : 0;
   const Filter f = make_filter(wavelet);
   const int n = field->n;
   check_geometry(n, levels, static_cast<int>(f.h.size()));
@@ -351,6 +555,35 @@ extern "C" wdb_status wdb_build_theta(const wdb_psf_field* field, int32_t wavele
   B.err.alloc(1);
   WDB_HIP(hipMemset(B.err.p, 0, sizeof(int)));
 
+  const char* force_general = std::getenv("WDB_BUILD_GENERAL");
+  if (field_is_stationary(field) && !(force_general && *force_general == '1')) {
+    unsigned long long K = 0;
+    double threshold = 0.0;
+    DevBuf<int32_t> orow, ocol;
+    DevBuf<double> oval;
+    build_stationary(B, nnz_budget, scaled, &K, &threshold, orow, ocol, oval);
+    B.scratch.reset();
+    wdb_theta* th = new wdb_theta();
+    try {
+      th->device = dev;
+      th->n = n;
+      th->levels = levels;
+      th->wavelet = wavelet;
+      th->N = N;
+      th->nnz = static_cast<int64_t>(K);
+      th->threshold = threshold;
+      th->conv_build = 1;
+      th->rule = rule;
+      coo_to_csr(N, th->nnz, orow.p, ocol.p, oval.p, &th->csr, s);
+      finish_theta(th, s);
+    } catch (...) {
+      wdb_theta_free(th);
+      throw;
+    }
+    *out = th;
+    return WDB_OK;
+  }
+
   Emit none{nullptr, nullptr, nullptr, B.counters.p, 0};
   // Radix select of the nnz_budget-th largest |theta|.
   unsigned long long need = static_cast<unsigned long long>(nnz_budget);
@@ -360,7 +593,7 @@ extern "C" wdb_status wdb_build_theta(const wdb_psf_field* field, int32_t wavele
   std::vector<unsigned long long> h(kDigits);
   while (true) {
     const int w = std::min(12, 64 - pbits);
-    Select S{0, pbits, 64 - pbits - w, prefix, (1ull << w) - 1ull};
+    Select S{0, scaled, pbits, 64 - pbits - w, prefix, (1ull << w) - 1ull};
     WDB_HIP(hipMemsetAsync(B.hist.p, 0, kDigits * sizeof(unsigned long long), s));
     B.run(S, none, none);
     WDB_HIP(hipMemcpy(h.data(), B.hist.p, kDigits * sizeof(unsigned long long), hipMemcpyDeviceToHost));
@@ -398,7 +631,7 @@ extern "C" wdb_status wdb_build_theta(const wdb_psf_field* field, int32_t wavele
   WDB_HIP(hipMemsetAsync(B.counters.p, 0, 2 * sizeof(unsigned long long), s));
   Emit eo{orow.p, ocol.p, oval.p, B.counters.p, above};
   Emit eb{brow.p, bcol.p, bval.p, B.counters.p + 1, keep_all ? 0 : bcount};
-  Select S{keep_all ? 2 : 1, pbits, 0, prefix, 0};
+  Select S{keep_all ? 2 : 1, scaled, pbits, 0, prefix, 0};
   B.run(S, eo, eb);
   unsigned long long cnt[2];
   WDB_HIP(hipMemcpy(cnt, B.counters.p, sizeof(cnt), hipMemcpyDeviceToHost));
@@ -414,8 +647,15 @@ extern "C" wdb_status wdb_build_theta(const wdb_psf_field* field, int32_t wavele
     WDB_HIP(hipMemcpy(hv.data(), bval.p, bcount * sizeof(double), hipMemcpyDeviceToHost));
     std::vector<size_t> idx(bcount);
     std::iota(idx.begin(), idx.end(), size_t(0));
+    const std::vector<Subband> lay = layout(n, levels);
+    auto rank = [&](size_t x) {  // the ranked magnitude (times sigma_b of the column when scaled)
+      if (!scaled) return std::fabs(hv[x]);
+      int k = 0;
+      while (k + 1 < static_cast<int>(lay.size()) && hc[x] >= lay[k + 1].offset) ++k;
+      return std::fabs(hv[x]) / lay[k].side;
+    };
     std::sort(idx.begin(), idx.end(), [&](size_t x, size_t y) {
-      const double ax = std::fabs(hv[x]), ay = std::fabs(hv[y]);
+      const double ax = rank(x), ay = rank(y);
       if (ax != ay) return ax > ay;
       return static_cast<int64_t>(hr[x]) * N + hc[x] < static_cast<int64_t>(hr[y]) * N + hc[y];
     });
@@ -426,7 +666,7 @@ extern "C" wdb_status wdb_build_theta(const wdb_psf_field* field, int32_t wavele
       sc[i] = hc[idx[i]];
       sv[i] = hv[idx[i]];
     }
-    threshold = std::fabs(sv[need - 1]);
+    threshold = rank(idx[need - 1]);
     WDB_HIP(hipMemcpy(orow.p + above, sr.data(), need * sizeof(int32_t), hipMemcpyHostToDevice));
     WDB_HIP(hipMemcpy(ocol.p + above, sc.data(), need * sizeof(int32_t), hipMemcpyHostToDevice));
     WDB_HIP(hipMemcpy(oval.p + above, sv.data(), need * sizeof(double), hipMemcpyHostToDevice));
@@ -442,6 +682,7 @@ extern "C" wdb_status wdb_build_theta(const wdb_psf_field* field, int32_t wavele
     th->N = N;
     th->nnz = static_cast<int64_t>(K);
     th->threshold = threshold;
+    th->rule = rule;
     coo_to_csr(N, th->nnz, orow.p, ocol.p, oval.p, &th->csr, s);
     finish_theta(th, s);
   } catch (...) {

@@ -190,6 +190,8 @@ struct wdb_theta {
   int32_t n = 0, levels = 0, wavelet = 0;
   int64_t N = 0, nnz = 0;
   double threshold = 0.0;
+  int conv_build = 0;  // 1 when built by the convolution fast path
+  int rule = 0;        // thresholding rule of the build (wdb_threshold_rule)
   wdb::Csr csr;        // Theta_K, float64 values (export)
   wdb::Sell A;         // Theta_K   (rows = output coefficient)
   wdb::Sell At;        // Theta_K^T (rows = input coefficient)
@@ -210,6 +212,9 @@ struct wdb_theta {
   double Lp = 0.0;
   double* p64 = nullptr;    // device, N: diagonal P
   float* pinv = nullptr;    // device, N: 1/P as float32
+  int l1_kind = 0;          // l1 weights: 0 uniform, 1 scale index j(i), 2 caller's
+  float* l1w = nullptr;     // device, N: w (null when uniform)
+  float* l1w_pre = nullptr; // device, N: w / P (null when uniform or no P)
   // Solver workspace (allocated on first solve).
   float* ws_x0 = nullptr;
   float* ws_r = nullptr;
@@ -241,7 +246,12 @@ int packed_group(const wdb_theta* th);
 void launch_res_packed(const wdb_theta* th, int G, const float* y, const float* b, float* r, int* kdev,
                        int scale_out, hipStream_t s);
 void launch_prox_packed(const wdb_theta* th, int G, const float* rs, float* x, float* y, float tau, float thr,
-                        const int* kdev, const float* pinv, hipStream_t s);
+                        const int* kdev, const float* pinv, const float* tw, hipStream_t s);
+// Per-row threshold multipliers of the proximal step: w (l1 weights) or w / P
+// (with the preconditioner), or null for uniform weights.
+const float* threshold_weights(const wdb_theta* th, bool pre);
+// Recompute w / P after the weights or the preconditioner changed.
+void refresh_threshold_weights(wdb_theta* th);
 int default_slice_height();
 int kernel_group(const wdb_theta* th);  // lanes per row in use (0: sliced ELL)
 // Power iteration on D^-1/2 A^T A D^-1/2 (d = nullptr: identity), float64.

@@ -263,7 +263,7 @@ template <int G, int FMT, bool PRE>
 __global__ __launch_bounds__(kBlock) void k_prox_pk(PackedView P, Geo g, const float* __restrict__ rs,
                                                     float* __restrict__ x, float* __restrict__ y, float tau,
                                                     float thr, const int* __restrict__ kdev,
-                                                    const float* __restrict__ pinv) {
+                                                    const float* __restrict__ pinv, const float* __restrict__ tw) {
   __shared__ int4 tab[kBlock / G][8];
   const int64_t row = static_cast<int64_t>(blockIdx.x) * (kBlock / G) + threadIdx.x / G;
   const int gl = threadIdx.x % G;
@@ -274,7 +274,7 @@ __global__ __launch_bounds__(kBlock) void k_prox_pk(PackedView P, Geo g, const f
   const float beta = static_cast<float>((static_cast<double>(k) - 1.0) / (static_cast<double>(k) + 2.0));
   const float pi = PRE ? pinv[row] : 1.0f;
   const float z = y[row] - (tau * pi) * gr;
-  const float t = thr * pi;
+  const float t = thr * (tw ? tw[row] : pi);
   const float xn = copysignf(fmaxf(fabsf(z) - t, 0.0f), z);
   const float xo = x[row];
   x[row] = xn;
@@ -393,7 +393,7 @@ void launch_res_packed(const wdb_theta* th, int G, const float* y, const float* 
 }
 
 void launch_prox_packed(const wdb_theta* th, int G, const float* rs, float* x, float* y, float tau, float thr,
-                        const int* kdev, const float* pinv, hipStream_t s) {
+                        const int* kdev, const float* pinv, const float* tw, hipStream_t s) {
   const PackedView P = pview(th->pAt);
   const Geo g = geo_of(th);
   with_group16(G, [&](auto gg) {
@@ -402,17 +402,17 @@ void launch_prox_packed(const wdb_theta* th, int G, const float* rs, float* x, f
     if (th->valtype == WDB_VAL_BF16) {
       if (pinv)
         hipLaunchKernelGGL((k_prox_pk<GG, WDB_VAL_BF16, true>), grid, dim3(kBlock), 0, s, P, g, rs, x, y, tau, thr,
-                           kdev, pinv);
+                           kdev, pinv, tw);
       else
         hipLaunchKernelGGL((k_prox_pk<GG, WDB_VAL_BF16, false>), grid, dim3(kBlock), 0, s, P, g, rs, x, y, tau, thr,
-                           kdev, pinv);
+                           kdev, pinv, tw);
     } else {
       if (pinv)
         hipLaunchKernelGGL((k_prox_pk<GG, WDB_VAL_F16, true>), grid, dim3(kBlock), 0, s, P, g, rs, x, y, tau, thr,
-                           kdev, pinv);
+                           kdev, pinv, tw);
       else
         hipLaunchKernelGGL((k_prox_pk<GG, WDB_VAL_F16, false>), grid, dim3(kBlock), 0, s, P, g, rs, x, y, tau, thr,
-                           kdev, pinv);
+                           kdev, pinv, tw);
     }
   });
 }

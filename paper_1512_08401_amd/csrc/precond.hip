@@ -100,6 +100,7 @@ extern "C" wdb_status wdb_set_precond(wdb_theta* th, int32_t kind, double eps, c
   if (kind == WDB_PRECOND_NONE) {
     th->precond = 0;
     th->Lp = 0.0;
+    refresh_threshold_weights(th);
     return WDB_OK;
   }
   WDB_REQUIRE(kind != WDB_PRECOND_JACOBI || (std::isfinite(eps) && eps > 0), WDB_ERR_ARG,
@@ -159,6 +160,7 @@ extern "C" wdb_status wdb_set_precond(wdb_theta* th, int32_t kind, double eps, c
   int it = 0;
   th->Lp = power_iteration(th, start, dsq.p, tol, max_iters, &it, s);
   th->precond = kind;
+  refresh_threshold_weights(th);
   WDB_API_END
 }
 

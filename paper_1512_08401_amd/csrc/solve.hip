@@ -141,11 +141,14 @@ __global__ __launch_bounds__(kBlock) void k_res(SellView A, const float* __restr
   if (row >= 0) r[row] = b ? acc - b[row] : acc;
 }
 
-// beta from the device counter (kdev) or, if kdev is null, from `beta`.
+// beta from the device counter (kdev) or, if kdev is null, from `beta`.  The
+// threshold of row i is thr * tw[i] (tw = w / P, the l1 weights over the
+// preconditioner), or thr / P_i when tw is null (uniform weights).
 template <bool PRE>
 __global__ __launch_bounds__(kBlock) void k_prox(SellView At, const float* __restrict__ r, float* __restrict__ x,
                                                  float* __restrict__ y, float tau, float thr, float beta,
-                                                 const int* __restrict__ kdev, const float* __restrict__ pinv) {
+                                                 const int* __restrict__ kdev, const float* __restrict__ pinv,
+                                                 const float* __restrict__ tw) {
   const int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   const int64_t sl = q >> At.cshift;
   const int lane = static_cast<int>(q & (At.C - 1));
@@ -159,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_prox(SellView At, const float* __res
   }
   const float pi = PRE ? pinv[row] : 1.0f;
   const float z = y[row] - (tau * pi) * g;
-  const float t = thr * pi;
+  const float t = thr * (tw ? tw[row] : pi);
   const float xn = copysignf(fmaxf(fabsf(z) - t, 0.0f), z);
   const float xo = x[row];
   x[row] = xn;
@@ -217,7 +220,8 @@ template <int FMT, bool PRE>
 __global__ __launch_bounds__(kBlock) void k_prox_q(SellView At, const uint2* __restrict__ v16T,
                                                    const float* __restrict__ rs, float* __restrict__ x,
                                                    float* __restrict__ y, float tau, float thr,
-                                                   const int* __restrict__ kdev, const float* __restrict__ pinv) {
+                                                   const int* __restrict__ kdev, const float* __restrict__ pinv,
+                                                   const float* __restrict__ tw) {
   const int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   const int64_t sl = q >> At.cshift;
   const int lane = static_cast<int>(q & (At.C - 1));
@@ -229,7 +233,7 @@ __global__ __launch_bounds__(kBlock) void k_prox_q(SellView At, const uint2* __r
   const float beta = static_cast<float>((static_cast<double>(k) - 1.0) / (static_cast<double>(k) + 2.0));
   const float pi = PRE ? pinv[row] : 1.0f;
   const float z = y[row] - (tau * pi) * g;
-  const float t = thr * pi;
+  const float t = thr * (tw ? tw[row] : pi);
   const float xn = copysignf(fmaxf(fabsf(z) - t, 0.0f), z);
   const float xo = x[row];
   x[row] = xn;
@@ -245,10 +249,11 @@ void launch_iteration_q(wdb_theta* th, float* x, bool pre, float tau, float thr,
                      th->ws_x0, th->ws_r, th->ws_k, 1);
   if (pre)
     hipLaunchKernelGGL((k_prox_q<FMT, true>), slot_grid(At), dim3(kBlock), 0, s, At, v16T, th->ws_r, x,
-                       th->ws_y, tau, thr, th->ws_k, th->pinv);
+                       th->ws_y, tau, thr, th->ws_k, th->pinv, threshold_weights(th, true));
   else
     hipLaunchKernelGGL((k_prox_q<FMT, false>), slot_grid(At), dim3(kBlock), 0, s, At, v16T, th->ws_r, x,
-                       th->ws_y, tau, thr, th->ws_k, static_cast<const float*>(nullptr));
+                       th->ws_y, tau, thr, th->ws_k, static_cast<const float*>(nullptr),
+                       threshold_weights(th, false));
 }
 
 // ---------------------------------------------------------------------------
@@ -313,7 +318,7 @@ template <int G, bool PRE>
 __global__ __launch_bounds__(kBlock) void k_prox_csr(CsrView At, const float* __restrict__ r,
                                                      float* __restrict__ x, float* __restrict__ y, float tau,
                                                      float thr, float beta, const int* __restrict__ kdev,
-                                                     const float* __restrict__ pinv) {
+                                                     const float* __restrict__ pinv, const float* __restrict__ tw) {
   const int64_t row = static_cast<int64_t>(blockIdx.x) * (kBlock / G) + threadIdx.x / G;
   const int gl = threadIdx.x % G;
   const float g = group_dot<G>(At, row, gl, r);
@@ -324,7 +329,7 @@ __global__ __launch_bounds__(kBlock) void k_prox_csr(CsrView At, const float* __
   }
   const float pi = PRE ? pinv[row] : 1.0f;
   const float z = y[row] - (tau * pi) * g;
-  const float t = thr * pi;
+  const float t = thr * (tw ? tw[row] : pi);
   const float xn = copysignf(fmaxf(fabsf(z) - t, 0.0f), z);
   const float xo = x[row];
   x[row] = xn;
@@ -339,12 +344,13 @@ void launch_res_csr(const CsrView& A, const float* y, const float* b, float* r, 
 
 template <int G>
 void launch_prox_csr(const CsrView& At, const float* r, float* x, float* y, float tau, float thr, float beta,
-                     const int* kdev, const float* pinv, hipStream_t s) {
+                     const int* kdev, const float* pinv, const float* tw, hipStream_t s) {
   const dim3 grid(static_cast<unsigned>((At.nrows + kBlock / G - 1) / (kBlock / G)));
   if (pinv)
-    hipLaunchKernelGGL((k_prox_csr<G, true>), grid, dim3(kBlock), 0, s, At, r, x, y, tau, thr, beta, kdev, pinv);
+    hipLaunchKernelGGL((k_prox_csr<G, true>), grid, dim3(kBlock), 0, s, At, r, x, y, tau, thr, beta, kdev, pinv, tw);
   else
-    hipLaunchKernelGGL((k_prox_csr<G, false>), grid, dim3(kBlock), 0, s, At, r, x, y, tau, thr, beta, kdev, pinv);
+    hipLaunchKernelGGL((k_prox_csr<G, false>), grid, dim3(kBlock), 0, s, At, r, x, y, tau, thr, beta, kdev, pinv,
+                       tw);
 }
 
 }  // namespace
@@ -369,22 +375,22 @@ void launch_res(int G, const Sell& sell, const Csr32& csr, const float* y, const
 }
 
 void launch_prox(int G, const Sell& sell, const Csr32& csr, const float* r, float* x, float* y, float tau, float thr,
-                 float beta, const int* kdev, const float* pinv, hipStream_t s) {
+                 float beta, const int* kdev, const float* pinv, const float* tw, hipStream_t s) {
   switch (G) {
-    case 2: launch_prox_csr<2>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, s); return;
-    case 4: launch_prox_csr<4>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, s); return;
-    case 8: launch_prox_csr<8>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, s); return;
-    case 16: launch_prox_csr<16>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, s); return;
-    case 32: launch_prox_csr<32>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, s); return;
-    case 64: launch_prox_csr<64>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, s); return;
+    case 2: launch_prox_csr<2>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, tw, s); return;
+    case 4: launch_prox_csr<4>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, tw, s); return;
+    case 8: launch_prox_csr<8>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, tw, s); return;
+    case 16: launch_prox_csr<16>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, tw, s); return;
+    case 32: launch_prox_csr<32>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, tw, s); return;
+    case 64: launch_prox_csr<64>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, tw, s); return;
     default: {
       const SellView At = view(sell);
       if (pinv)
         hipLaunchKernelGGL(k_prox<true>, slot_grid(At), dim3(kBlock), 0, s, At, r, x, y, tau, thr, beta,
-                           kdev, pinv);
+                           kdev, pinv, tw);
       else
         hipLaunchKernelGGL(k_prox<false>, slot_grid(At), dim3(kBlock), 0, s, At, r, x, y, tau, thr,
-                           beta, kdev, pinv);
+                           beta, kdev, pinv, tw);
     }
   }
 }
@@ -394,9 +400,11 @@ namespace {
 // ---------------------------------------------------------------------------
 // Float64 objective and duality gap.
 // ---------------------------------------------------------------------------
+// With l1 weights w (null = uniform): the l1 sum is sum_i w_i |x_i| and the
+// dual scaling uses max_i |g_i| / w_i.
 __global__ __launch_bounds__(kBlock) void k_obj_fwd(SellView A, const float* __restrict__ x, const float* __restrict__ b,
-                                                    double* __restrict__ r64, double* __restrict__ partial,
-                                                    int64_t nblocks) {
+                                                    const float* __restrict__ w, double* __restrict__ r64,
+                                                    double* __restrict__ partial, int64_t nblocks) {
   const int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   const int64_t sl = q >> A.cshift;
   const int lane = static_cast<int>(q & (A.C - 1));
@@ -410,14 +418,15 @@ __global__ __launch_bounds__(kBlock) void k_obj_fwd(SellView A, const float* __r
       r64[row] = rr;
       v[0] = rr * rr;
       v[1] = rr * bb;
-      v[2] = fabs(static_cast<double>(x[row]));
+      v[2] = fabs(static_cast<double>(x[row])) * (w ? static_cast<double>(w[row]) : 1.0);
     }
   }
   block_partials<3, 0u>(v, partial, nblocks);
 }
 
 __global__ __launch_bounds__(kBlock) void k_obj_bwd(SellView At, const double* __restrict__ r64,
-                                                    double* __restrict__ partial, int64_t nblocks) {
+                                                    const float* __restrict__ w, double* __restrict__ partial,
+                                                    int64_t nblocks) {
   const int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   const int64_t sl = q >> At.cshift;
   const int lane = static_cast<int>(q & (At.C - 1));
@@ -425,7 +434,7 @@ __global__ __launch_bounds__(kBlock) void k_obj_bwd(SellView At, const double* _
   if (q < slots(At)) {
     const int64_t row = slot_row(At, q);
     const double g = row_dot_f64(At, sl, lane, r64);
-    if (row >= 0) v[0] = fabs(g);
+    if (row >= 0) v[0] = fabs(g) / (w ? static_cast<double>(w[row]) : 1.0);
   }
   block_partials<1, 1u>(v, partial, nblocks);
 }
@@ -582,8 +591,9 @@ __device__ __forceinline__ int64_t csr_tiles(const CsrView& A) {
 
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_obj_fwd_csr(CsrView A, const float* __restrict__ x,
-                                                        const float* __restrict__ b, double* __restrict__ r64,
-                                                        double* __restrict__ partial, int64_t nblocks) {
+                                                        const float* __restrict__ b, const float* __restrict__ w,
+                                                        double* __restrict__ r64, double* __restrict__ partial,
+                                                        int64_t nblocks) {
   double v[3] = {0.0, 0.0, 0.0};
   const int gl = threadIdx.x % G;
   for (int64_t t = blockIdx.x; t < csr_tiles<G>(A); t += gridDim.x) {
@@ -595,7 +605,7 @@ __global__ __launch_bounds__(kBlock) void k_obj_fwd_csr(CsrView A, const float* 
       r64[row] = rr;
       v[0] += rr * rr;
       v[1] += rr * bb;
-      v[2] += fabs(static_cast<double>(x[row]));
+      v[2] += fabs(static_cast<double>(x[row])) * (w ? static_cast<double>(w[row]) : 1.0);
     }
   }
   block_partials<3, 0u>(v, partial, nblocks);
@@ -603,13 +613,14 @@ __global__ __launch_bounds__(kBlock) void k_obj_fwd_csr(CsrView A, const float* 
 
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_obj_bwd_csr(CsrView At, const double* __restrict__ r64,
-                                                        double* __restrict__ partial, int64_t nblocks) {
+                                                        const float* __restrict__ w, double* __restrict__ partial,
+                                                        int64_t nblocks) {
   double v[1] = {0.0};
   const int gl = threadIdx.x % G;
   for (int64_t t = blockIdx.x; t < csr_tiles<G>(At); t += gridDim.x) {
     const int64_t row = t * (kBlock / G) + threadIdx.x / G;
     const double g = group_dot64<G>(At, row, gl, r64);
-    if (gl == 0 && row < At.nrows) v[0] = fmax(v[0], fabs(g));
+    if (gl == 0 && row < At.nrows) v[0] = fmax(v[0], fabs(g) / (w ? static_cast<double>(w[row]) : 1.0));
   }
   block_partials<1, 1u>(v, partial, nblocks);
 }
@@ -791,13 +802,13 @@ Check objective_check(wdb_theta* th, const float* x, const float* x0, double lam
     with_group(G, [&](auto g) {
       constexpr int GG = decltype(g)::value;
       hipLaunchKernelGGL(k_obj_fwd_csr<GG>, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, cview(th->cA), x,
-                         x0, th->ws_r64, part, nb);
+                         x0, th->l1w, th->ws_r64, part, nb);
       hipLaunchKernelGGL(k_obj_bwd_csr<GG>, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, cview(th->cAt),
-                         th->ws_r64, part + 3 * nb, nb);
+                         th->ws_r64, th->l1w, part + 3 * nb, nb);
     });
   } else {
-    hipLaunchKernelGGL(k_obj_fwd, slot_grid(A), dim3(kBlock), 0, s, A, x, x0, th->ws_r64, part, nb);
-    hipLaunchKernelGGL(k_obj_bwd, slot_grid(At), dim3(kBlock), 0, s, At, th->ws_r64, part + 3 * nb, nb);
+    hipLaunchKernelGGL(k_obj_fwd, slot_grid(A), dim3(kBlock), 0, s, A, x, x0, th->l1w, th->ws_r64, part, nb);
+    hipLaunchKernelGGL(k_obj_bwd, slot_grid(At), dim3(kBlock), 0, s, At, th->ws_r64, th->l1w, part + 3 * nb, nb);
   }
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, part, nb, 4, 0x8u, th->ws_scalar);
   WDB_HIP(hipGetLastError());
@@ -815,14 +826,16 @@ void launch_iteration(wdb_theta* th, float* x, bool pre, float tau, float thr, h
   if (th->valtype != WDB_VAL_F32 && th->pA.word && packed_group(th) > 0) {
     const int G = packed_group(th);
     launch_res_packed(th, G, th->ws_y, th->ws_x0, th->ws_r, th->ws_k, 1, s);
-    launch_prox_packed(th, G, th->ws_r, x, th->ws_y, tau, thr, th->ws_k, pre ? th->pinv : nullptr, s);
+    launch_prox_packed(th, G, th->ws_r, x, th->ws_y, tau, thr, th->ws_k, pre ? th->pinv : nullptr,
+                       threshold_weights(th, pre), s);
     return;
   }
   if (th->valtype == WDB_VAL_BF16) return launch_iteration_q<WDB_VAL_BF16>(th, x, pre, tau, thr, s);
   if (th->valtype == WDB_VAL_F16) return launch_iteration_q<WDB_VAL_F16>(th, x, pre, tau, thr, s);
   const int G = kernel_group(th);
   launch_res(G, th->A, th->cA, th->ws_y, th->ws_x0, th->ws_r, th->ws_k, s);
-  launch_prox(G, th->At, th->cAt, th->ws_r, x, th->ws_y, tau, thr, 0.0f, th->ws_k, pre ? th->pinv : nullptr, s);
+  launch_prox(G, th->At, th->cAt, th->ws_r, x, th->ws_y, tau, thr, 0.0f, th->ws_k, pre ? th->pinv : nullptr,
+              threshold_weights(th, pre), s);
 }
 
 void ensure_lipschitz(wdb_theta* th, hipStream_t s) {
@@ -1028,7 +1041,7 @@ wdb_status wdb_prox_step(wdb_theta* th, const float* r, float* x, float* y, floa
   hipStream_t s = static_cast<hipStream_t>(stream);
   const float thr = tau * lambda;
   wdb::launch_prox(wdb::kernel_group(th), th->At, th->cAt, r, x, y, tau, thr, beta, nullptr,
-                   use_precond ? th->pinv : nullptr, s);
+                   use_precond ? th->pinv : nullptr, wdb::threshold_weights(th, use_precond != 0), s);
   WDB_HIP(hipGetLastError());
   WDB_API_END
 }

@@ -48,7 +48,8 @@ class ThetaDesc(C.Structure):
                 ("has_lipschitz", C.c_int32), ("nnz", C.c_int64), ("stored", C.c_int64),
                 ("lipschitz", C.c_double), ("threshold", C.c_double), ("lipschitz_p", C.c_double),
                 ("precond", C.c_int32), ("valtype", C.c_int32), ("slice", C.c_int32), ("group", C.c_int32),
-                ("group16", C.c_int32), ("escapes", C.c_int64)]
+                ("group16", C.c_int32), ("escapes", C.c_int64), ("conv_build", C.c_int32),
+                ("l1_weights", C.c_int32), ("rule", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -73,6 +74,7 @@ _pd = C.POINTER(C.c_double)
 
 _SIGS = {
     "wdb_build_theta": [C.POINTER(PsfFieldC), _i32, _i32, _i64, _vp, C.POINTER(_vp)],
+    "wdb_build_theta_rule": [C.POINTER(PsfFieldC), _i32, _i32, _i64, _i32, _vp, C.POINTER(_vp)],
     "wdb_theta_import": [_i32, _i32, _i32, _i64, _vp, _vp, _vp, _vp, C.POINTER(_vp)],
     "wdb_theta_export": [_vp, _vp, _vp, _vp],
     "wdb_theta_info": [_vp, C.POINTER(ThetaDesc)],
@@ -91,6 +93,7 @@ _SIGS = {
     "wdb_set_precision": [_vp, _i32],
     "wdb_set_kernel_layout": [_vp, _i32, _i32],
     "wdb_set_packed_group": [_vp, _i32],
+    "wdb_set_l1_weights": [_vp, _i32, _vp],
     "wdb_autotune": [_vp, C.c_char_p, _i32, C.POINTER(_i32), C.POINTER(_i32), _pd],
     "wdb_cnn_create": [_i32, _i32, _i32, C.c_uint64, C.POINTER(_vp)],
     "wdb_cnn_param_count": [_vp, C.POINTER(_i64)],
@@ -196,11 +199,14 @@ class Theta:
         return self._h
 
     @classmethod
-    def build(cls, field, wavelet: str, levels: int, nnz_budget: int, stream=None) -> "Theta":
+    def build(cls, field, wavelet: str, levels: int, nnz_budget: int, stream=None, rule: str = "naive") -> "Theta":
+        """Theta_K of a PSF field; rule "naive" (K largest |Theta|) or "scale"
+        (K largest 2^-k |Theta[a, b]| for column b of scale k, Sec. 3.7)."""
         st, keep = _field_struct(field)
         out = C.c_void_p()
-        _check("wdb_build_theta", _lib.wdb_build_theta(C.byref(st), WAVELETS[wavelet], levels, int(nnz_budget),
-                                                       _stream(stream), C.byref(out)))
+        _check("wdb_build_theta_rule", _lib.wdb_build_theta_rule(C.byref(st), WAVELETS[wavelet], levels,
+                                                                 int(nnz_budget), {"naive": 0, "scale": 1}[rule],
+                                                                 _stream(stream), C.byref(out)))
         del keep
         return cls(out)
 
@@ -244,6 +250,17 @@ class Theta:
 
     def set_kernel_layout(self, slice: int = 64, group: int = 0):
         _check("wdb_set_kernel_layout", _lib.wdb_set_kernel_layout(self._h, slice, group))
+
+    def set_l1_weights(self, kind="uniform", w=None):
+        """l1 weights: "uniform", "scale" (w[i] = j(i), Sec. 5) or "given" with a host array of N floats."""
+        k = {"uniform": 0, "scale": 1, "given": 2}[kind]
+        arr = None
+        if k == 2:
+            arr = np.ascontiguousarray(w, dtype=np.float32)
+            if arr.size != self.N:
+                raise ValueError(f"weights have {arr.size} entries, expected {self.N}")
+        _check("wdb_set_l1_weights", _lib.wdb_set_l1_weights(self._h, k, None if arr is None else
+                                                             arr.ctypes.data_as(C.c_void_p)))
 
     def set_packed_group(self, group: int = 0):
         """Lanes per row of the packed 16-bit kernels (2/4/8/16; 0 = default)."""
@@ -428,8 +445,8 @@ def solve_batched(problems, iters: int, check_every: int = 20, tol: float = 0.0,
     return xs, res
 
 
-def build_theta(field, wavelet: str, levels: int, nnz_budget: int, stream=None) -> Theta:
-    return Theta.build(field, wavelet, levels, nnz_budget, stream)
+def build_theta(field, wavelet: str, levels: int, nnz_budget: int, stream=None, rule: str = "naive") -> Theta:
+    return Theta.build(field, wavelet, levels, nnz_budget, stream, rule)
 
 
 def dwt(u, wavelet: str, levels: int, inverse: bool = False, out=None, stream=None):

@@ -119,6 +119,84 @@ def test_build_theta_matches_dense_oracle(W, p64, case):
     assert abs(info["threshold"] - theta.threshold_value(T, K)) <= 1e-12 * np.max(np.abs(T))
 
 
+@pytest.mark.parametrize("case", ["haar64_iso", "db4_32_aniso", "haar16_cut"])
+def test_convolution_build_matches_alg3_oracle(W, case):
+    """A stationary field takes the fast path (one column per subband, circulant
+    copies); the kept set and values match the oracle's Alg. 3 Theta."""
+    from oracle import theta_conv
+    field, name, J, K = {"haar64_iso": (synth.psf_stationary(64, 1.5, 1.5), "haar", 3, 40 * 4096),
+                         "db4_32_aniso": (synth.psf_stationary(32, 2.5, 1.0, 0.6), "db4", 2, 30 * 1024),
+                         "haar16_cut": (synth.psf_stationary(16, 1.2, 1.2), "haar", 2, 777)}[case]
+    print(f"conv build {case}", flush=True)
+    T = theta_conv.theta_convolution(field, filters.by_name(name), J)
+    th = W.build_theta(field, name, J, K)
+    info = th.info()
+    assert info["conv_build"] == 1 and info["nnz"] == K
+    rp, cc, vv = th.export()
+    _compare_kept(rp, cc, vv, T, K)
+    assert abs(info["threshold"] - theta.threshold_value(T, K)) <= 1e-12 * np.max(np.abs(T))
+
+
+def test_convolution_build_agrees_with_general_build(W, monkeypatch):
+    """At 128 x 128 (db4, 3 levels) the fast path and the column-by-column
+    build give the same Theta_K up to rounding at the cut."""
+    field = synth.psf_stationary(128, 2.0, 1.0, 0.3)
+    K = 25 * 128 * 128
+    fast = W.build_theta(field, "db4", 3, K)
+    monkeypatch.setenv("WDB_BUILD_GENERAL", "1")
+    slow = W.build_theta(field, "db4", 3, K)
+    assert fast.info()["conv_build"] == 1 and slow.info()["conv_build"] == 0
+    N = 128 * 128
+    (rf, cf, vf), (rs, cs, vs) = fast.export(), slow.export()
+    kf = np.repeat(np.arange(N), np.diff(rf)).astype(np.int64) * N + cf
+    ks = np.repeat(np.arange(N), np.diff(rs)).astype(np.int64) * N + cs
+    amax = np.max(np.abs(vs))
+    thr = slow.info()["threshold"]
+    diff = np.setxor1d(kf, ks)
+    if diff.size:   # only entries at the cut (to rounding) may differ
+        vals = np.concatenate([np.abs(vf[np.isin(kf, diff)]), np.abs(vs[np.isin(ks, diff)])])
+        assert np.all(np.abs(vals - thr) <= 1e-12 * amax)
+    common, i_f, i_s = np.intersect1d(kf, ks, return_indices=True)
+    assert np.max(np.abs(vf[i_f] - vs[i_s])) <= 1e-13 * amax
+
+
+@pytest.mark.parametrize("case", ["rot32_db4", "conv64_haar"])
+def test_scale_weighted_threshold_matches_oracle(W, case):
+    """Sec. 3.7 weighted rule: keep the K largest 2^-k |Theta[a, b]| (k the scale of column b),
+    by the general build (spatially varying field) and by the convolution fast path."""
+    field, name, J, K = {"rot32_db4": (synth.psf_rotating(32, 2.5, 1.0), "db4", 2, 20 * 1024),
+                         "conv64_haar": (synth.psf_stationary(64, 1.5, 1.0, 0.7), "haar", 3, 30 * 4096)}[case]
+    print(f"scale rule {case}", flush=True)
+    T = theta.theta_dense(field, filters.by_name(name), J)
+    n = field.n
+    N = n * n
+    sig = theta.column_scale_weights(n, J)
+    th = W.build_theta(field, name, J, K, rule="scale")
+    info = th.info()
+    assert info["rule"] == 1 and info["nnz"] == K
+    assert info["conv_build"] == (1 if case.startswith("conv") else 0)
+    rp, cc, vv = th.export()
+    got = np.repeat(np.arange(N), np.diff(rp)).astype(np.int64) * N + cc
+    r, c, _ = theta.top_k_weighted(T, K, sig)
+    want = r * N + c
+    S = np.abs(T) * sig[None, :]
+    order = np.sort(S.ravel())[::-1]
+    thr = order[K - 1]
+    amax = S.max()
+    sym = np.setxor1d(got, want)
+    if sym.size:
+        assert np.all(np.abs(S.ravel()[sym] - thr) <= 1e-12 * amax), f"{sym.size} entries differ away from the cut"
+    common, ig, _ = np.intersect1d(got, want, return_indices=True)
+    assert np.max(np.abs(vv[ig] - T.ravel()[common])) <= 1e-13 * np.max(np.abs(T))
+    assert abs(info["threshold"] - thr) <= 1e-12 * amax
+    # the weighted rule keeps more coarse-column entries than the naive one
+    naive = W.build_theta(field, name, J, K)
+    rn, cn, _ = naive.export()
+    coarse = sig[cc] >= np.median(sig)
+    coarse_n = sig[cn] >= np.median(sig)
+    assert coarse.sum() >= coarse_n.sum()
+
+
 def test_build_theta_budget_edges(W):
     field = synth.psf_rotating(32, 2.5, 1.0)
     T = theta.theta_dense(field, filters.db4(), 2)
@@ -335,6 +413,45 @@ def test_preconditioner_matches_oracle(W, p64, kind):
     x, info = th.solve_coeffs(dev(x0), wl.lam, 100, check_every=20, precond=True)
     x_o, E_o = _oracle_fista(p64, 100, p=po, Lp=Lp)
     _gate(A32, x0.astype(np.float64), float(np.float32(wl.lam)), host(x), x_o, E_o)
+
+
+# ---------------------------------------------------------------------------
+# l1 weights w[i] = j(i) (the weights of the experiments of Sec. 5)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("pre", [False, True])
+def test_weighted_l1_solve_matches_oracle(W, p64, pre):
+    th = imported(W, p64)
+    wl = p64["wl"]
+    start = synth.power_start(4096, wl.power_seed)
+    th.lipschitz(start)
+    A32 = p64["A32"]
+    w = dwt.scale_index(64, 3).astype(np.float64)
+    th.set_l1_weights("scale")
+    assert th.info()["l1_weights"] == 1
+    p = Lp = None
+    if pre:
+        th.set_precond("spai_scale", start=start)
+        p = precond.spai_grouped(A32, precond.scale_groups(64, 3))
+        Lp, _ = lipschitz.lipschitz_precond(A32, p, start)
+    x0 = p64["x0"].astype(np.float32)
+    lam = float(np.float32(wl.lam))
+    xg, info = th.solve_coeffs(dev(x0), wl.lam, 200, check_every=50, precond=pre)
+    L, _ = lipschitz.lipschitz(A32, start)
+    xo, _, _ = fista.fista(A32, x0.astype(np.float64), lam, 1.0 / (Lp if pre else L), 200, p=p, w=w)
+    Eo = fista.objective(A32, x0.astype(np.float64), lam, xo, w)
+    Eg = fista.objective(A32, x0.astype(np.float64), lam, host(xg), w)
+    assert abs(Eg - Eo) <= 1e-5 * Eo
+    assert np.linalg.norm(host(xg) - xo) <= 1e-4 * np.linalg.norm(xo)
+    # the float64 check is the weighted objective and gap of the returned iterate
+    E, _, _, rel = fista.duality_gap(A32, x0.astype(np.float64), lam, host(xg), w)
+    assert abs(info["objective"] - E) <= 1e-10 * E and abs(info["rel_gap"] - rel) <= 1e-9
+    # uniform weights again give the unweighted solve
+    th.set_l1_weights("uniform")
+    if pre:
+        th.set_precond("none")
+    xu, _ = th.solve_coeffs(dev(x0), wl.lam, 200, check_every=50)
+    x_o, E_o = _oracle_fista(p64, 200)
+    _gate(A32, x0.astype(np.float64), lam, host(xu), x_o, E_o)
 
 
 # ---------------------------------------------------------------------------
