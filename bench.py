@@ -112,7 +112,7 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance measurement")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default kernel layout")
-    ap.add_argument("--form", default="plain", choices=["plain", "batched", "learned"],
+    ap.add_argument("--form", default="plain", choices=["plain", "batched", "learned", "conv", "tuned"],
                     help="plain: the single-problem solve (default); batched / learned: the extension workloads")
     ap.add_argument("--train-images", type=int, default=4096)
     ap.add_argument("--heldout-images", type=int, default=512)
@@ -133,7 +133,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.form != "plain":
-        res = run_batched(args) if args.form == "batched" else run_learned(args)
+        res = {"batched": run_batched, "learned": run_learned, "conv": run_conv, "tuned": run_tuned}[args.form](args)
         print(json.dumps(res), flush=True)
         return
     dev = torch.device("cuda:0")
@@ -459,6 +459,97 @@ def run_learned(args):
             "targets": out, "heldout_mse_to_solution": mse,
             "train_loss_first_last": [hist[0], hist[-1]], "targets_s": round(t_targets, 2),
             "train_s": round(t_train, 2)}
+
+
+def _solve_rate(th, u0, lam, iters, torch, steps=3):
+    x = torch.empty_like(u0)
+    th.solve(u0, lam, iters, check_every=20, out=x, use_graph=True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        _, info = th.solve(u0, lam, iters, check_every=20, out=x, use_graph=True)
+    e1.record()
+    torch.cuda.synchronize()
+    return iters * steps / (e0.elapsed_time(e1) / 1e3), info
+
+
+def run_conv(args):
+    """Stationary blur (a convolution): the Theta build by the fast path of
+    Alg. 3 against the column-by-column build, then the solve rate."""
+    import torch
+    import synth
+    from paper_1512_08401_amd import wdb
+    n, J, sig, lam = 1024, 6, 5.0, 5e-4
+    field = synth.psf_stationary(n, sig, sig)
+    K = 20 * n * n
+    out = {}
+    for name, general in (("fast", "0"), ("general", "1")):
+        os.environ["WDB_BUILD_GENERAL"] = general
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        th = wdb.build_theta(field, "db4", J, K)
+        torch.cuda.synchronize()
+        out[name] = {"build_s": round(time.perf_counter() - t0, 3), "threshold": th.info()["threshold"],
+                     "conv_build": th.info()["conv_build"]}
+        log(f"{name} build: {out[name]}")
+        if name == "general":
+            del th
+    os.environ.pop("WDB_BUILD_GENERAL", None)
+    th = wdb.build_theta(field, "db4", J, K)
+    th.autotune(reps=5)
+    th.lipschitz(synth.power_start(n * n, 22))
+    u0 = _observe(wdb, torch, field, n, 21, 22, 0.005)
+    rate, info = _solve_rate(th, u0, lam, 500, torch)
+    return {"metric": "Theta build time, stationary blur (Alg. 3 fast path)", "value": out["fast"]["build_s"],
+            "unit": "s", "higher_is_better": False, "n_gpus": 1, "dtype": "f64 build, f32 solve",
+            "data": "synthetic",
+            "config": {"workload": f"conv1024: {n}x{n}, db4 {J} levels, isotropic Gaussian sigma {sig} at every "
+                                   f"pixel, Theta_K 20 nnz/px ({K}), lambda {lam}"},
+            "builds": out, "speedup": round(out["general"]["build_s"] / out["fast"]["build_s"], 2),
+            "fista_iters_per_s": round(rate, 1), "layout": [th.info()["slice"], th.info()["group"]]}
+
+
+def run_tuned(args):
+    """The paper's own tuning on the 512x512 workload: Symmlet 6, the weighted
+    thresholding rule sigma = 2^-k and l1 weights w[i] = j(i), against the
+    plain db4 / naive / uniform setup: build time, FISTA rate and time to a
+    relative objective for each."""
+    import torch
+    import synth
+    from paper_1512_08401_amd import wdb
+    wl = synth.WORKLOADS["precision512"]
+    n, lam = wl.n, wl.lam
+    field = wl.psf()
+    u0 = _observe(wdb, torch, field, n, wl.image_seed, wl.noise_seed, wl.noise_sigma)
+    res = {}
+    for form, wav, J, rule, weights in (("plain", "db4", 5, "naive", "uniform"), ("tuned", "sym6", 5, "scale", "scale")):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        th = wdb.build_theta(field, wav, J, wl.nnz, rule=rule)
+        torch.cuda.synchronize()
+        t_build = time.perf_counter() - t0
+        th.autotune(reps=5)
+        th.lipschitz(synth.power_start(n * n, wl.power_seed))
+        th.set_l1_weights(weights)
+        rate, _ = _solve_rate(th, u0, lam, 500, torch)
+        x0 = wdb.dwt(u0, wav, J)
+        E0 = 0.5 * float(torch.dot(x0.double(), x0.double()))
+        _, star = th.solve(u0, lam, 6000, check_every=100, trace_cap=60)
+        Estar = float(star["trace"][:, 1].min())
+        _, tr = th.solve(u0, lam, 3000, check_every=10, trace_cap=300)
+        rho = (tr["trace"][:, 1] - Estar) / E0
+        hit = {f"{t:.0e}": (int(tr["trace"][np.nonzero(rho <= t)[0][0], 0]) if np.any(rho <= t) else None)
+               for t in (1e-4, 1e-6, 1e-7)}
+        res[form] = {"wavelet": wav, "rule": rule, "weights": weights, "build_s": round(t_build, 3),
+                     "fista_iters_per_s": round(rate, 1), "iters_to_rel_objective": hit,
+                     "layout": [th.info()["slice"], th.info()["group"]]}
+        log(f"{form}: {res[form]}")
+        del th
+    return {"metric": "FISTA iters/s with the paper's tuning (Symmlet 6, sigma = 2^-k thresholding, w = j(i))",
+            "value": res["tuned"]["fista_iters_per_s"], "unit": "iters/s", "higher_is_better": True, "n_gpus": 1,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"precision512 field and image, {wl.nnz} nnz, lambda {lam}"}, "forms": res}
 
 
 def th_x0(th, u0, wl, wdb):

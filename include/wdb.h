@@ -61,7 +61,9 @@ typedef enum {
 
 typedef enum {
   WDB_HAAR = 0,   /* Haar, 2 taps                                      */
-  WDB_DB4 = 1     /* Daubechies, 4 vanishing moments, 8 taps (Sec. 3.5) */
+  WDB_DB4 = 1,    /* Daubechies, 4 vanishing moments, 8 taps (Sec. 3.5) */
+  WDB_SYM6 = 2    /* Symmlet, 6 vanishing moments, 12 taps: the least-asymmetric
+                     factor of the Daubechies response (the wavelet of Sec. 5) */
 } wdb_wavelet;
 
 /* Spatially varying Gaussian PSF field (Sec. 3.1).  Host arrays of n*n

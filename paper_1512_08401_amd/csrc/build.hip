@@ -46,7 +46,7 @@ struct Geom {
   int64_t sub_off[kMaxSub + 1];
   int flen[kMaxLev];
   int64_t foff[kMaxLev];
-  double h[8], g[8];
+  double h[kMaxTaps], g[kMaxTaps];
 };
 
 struct Select {

@@ -89,6 +89,8 @@ struct DevBuf {
 // ---------------------------------------------------------------------------
 // Filters (host, float64).
 // ---------------------------------------------------------------------------
+constexpr int kMaxTaps = 12;  // longest filter (Symmlet 6)
+
 struct Filter {
   std::vector<double> h;  // low-pass analysis taps
   std::vector<double> g;  // high-pass g[m] = (-1)^m h[L-1-m]

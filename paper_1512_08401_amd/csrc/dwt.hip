@@ -15,8 +15,8 @@ namespace wdb {
 namespace {
 
 struct Taps {
-  float h[8];
-  float g[8];
+  float h[kMaxTaps];
+  float g[kMaxTaps];
   int L;
 };
 

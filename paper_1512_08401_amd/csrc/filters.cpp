@@ -8,7 +8,9 @@
 // Weierstrass (Durand-Kerner) simultaneous iteration in long double; each root
 // y gives the reciprocal pair z + 1/z = 2 - 4y, of which the root inside the
 // unit circle is kept (minimum phase).  Expanding (1 + w)^p prod (1 - z_i w)
-// in w = 1/z and scaling the taps to sum sqrt(2) yields h.
+// in w = 1/z and scaling the taps to sum sqrt(2) yields h.  The Symmlet of
+// the experiments of Sec. 5 is another factor of the same polynomial (below).
+#include <algorithm>
 #include <cmath>
 #include <complex>
 
@@ -84,6 +86,109 @@ std::vector<double> daubechies(int p) {
   return h;
 }
 
+// Least-asymmetric ("Symmlet") filter with p vanishing moments: a spectral
+// factor of the same |m0|^2 whose phase is closest to linear (Daubechies'
+// Symmlets).  Every root y of P offers z or 1/z; complex-conjugate roots take
+// the same choice so the taps stay real.  The phase of
+// Q(w) = prod (1 - z_i e^{-iw}) (the rest of m0, (1 + e^{-iw})^p, has exactly
+// linear phase) is unwrapped on 2049 points of [0, pi] and the largest distance
+// to its chord scores a choice; the smallest score wins.  A choice and its
+// mirror image (every zero inverted: the time-reversed filter) score the
+// same; the one taking the inner zero of the root with the smallest real part
+// (then imaginary part) is kept.
+std::vector<double> symlet(int p) {
+  std::vector<long double> P(p);
+  for (int k = 0; k < p; ++k) P[k] = binom(p - 1 + k, k);
+  std::vector<cplx> ys = poly_roots(P);
+  std::sort(ys.begin(), ys.end(), [](const cplx& a, const cplx& b) {
+    const long double ar = std::round(a.real() * 1e12L), br = std::round(b.real() * 1e12L);
+    if (ar != br) return ar < br;
+    return std::round(a.imag() * 1e12L) < std::round(b.imag() * 1e12L);
+  });
+  struct Pair { cplx in, out; };
+  std::vector<Pair> pr;
+  for (const cplx& y : ys) {
+    const cplx b = 2.0L - 4.0L * y;
+    const cplx disc = std::sqrt(b * b - 4.0L);
+    cplx z1 = (b + disc) / 2.0L, z2 = (b - disc) / 2.0L;
+    if (std::abs(z1) > std::abs(z2)) std::swap(z1, z2);
+    pr.push_back({z1, z2});
+  }
+  std::vector<std::vector<int>> groups;
+  std::vector<bool> used(ys.size(), false);
+  for (size_t i = 0; i < ys.size(); ++i) {
+    if (used[i]) continue;
+    used[i] = true;
+    std::vector<int> g{static_cast<int>(i)};
+    if (std::fabs(ys[i].imag()) > 1e-12L)
+      for (size_t j = i + 1; j < ys.size(); ++j)
+        if (!used[j] && std::abs(ys[j] - std::conj(ys[i])) < 1e-9L) {
+          used[j] = true;
+          g.push_back(static_cast<int>(j));
+          break;
+        }
+    groups.push_back(g);
+  }
+  const long double pi = 3.141592653589793238462643383279502884L;
+  auto score = [&](const std::vector<cplx>& zs) {
+    const int M = 2048;
+    std::vector<long double> ph(M + 1);
+    long double prev = 0, acc = 0;
+    for (int t = 0; t <= M; ++t) {
+      const long double w = pi * t / M;
+      const cplx e(std::cos(w), -std::sin(w));
+      cplx q = 1;
+      for (const cplx& z : zs) q *= (1.0L - z * e);
+      const long double a = std::arg(q);
+      if (t == 0) acc = a;
+      else {
+        long double d = a - prev;
+        while (d > pi) d -= 2 * pi;
+        while (d < -pi) d += 2 * pi;
+        acc += d;
+      }
+      prev = a;
+      ph[t] = acc;
+    }
+    long double worst = 0;
+    for (int t = 0; t <= M; ++t) {
+      const long double chord = ph[0] + (ph[M] - ph[0]) * t / M;
+      worst = std::max(worst, std::fabs(ph[t] - chord));
+    }
+    return worst;
+  };
+  std::vector<cplx> best;
+  long double best_score = 0;
+  for (unsigned mask = 0; mask < (1u << groups.size()); ++mask) {
+    if (mask & 1u) continue;  // mirror images: the first group keeps its inner zero
+    std::vector<cplx> zs;
+    for (size_t gi = 0; gi < groups.size(); ++gi)
+      for (int i : groups[gi]) zs.push_back(((mask >> gi) & 1u) ? pr[i].out : pr[i].in);
+    const long double sc = score(zs);
+    if (best.empty() || sc < best_score - 1e-12L) {
+      best = zs;
+      best_score = sc;
+    }
+  }
+  std::vector<cplx> coeffs{cplx(1)};
+  auto mul = [&](cplx a0, cplx a1) {
+    std::vector<cplx> out(coeffs.size() + 1, cplx(0));
+    for (size_t i = 0; i < coeffs.size(); ++i) {
+      out[i] += coeffs[i] * a0;
+      out[i + 1] += coeffs[i] * a1;
+    }
+    coeffs.swap(out);
+  };
+  for (int i = 0; i < p; ++i) mul(1, 1);
+  for (const cplx& z : best) mul(1, -z);
+  long double sum = 0;
+  for (auto& c : coeffs) sum += c.real();
+  const long double scale = std::sqrt(2.0L) / sum;
+  std::vector<double> h(coeffs.size());
+  for (size_t i = 0; i < coeffs.size(); ++i) h[i] = static_cast<double>(coeffs[i].real() * scale);
+  return h;
+}
+
 }  // namespace
 
 Filter make_filter(int wavelet) {
@@ -93,6 +198,9 @@ Filter make_filter(int wavelet) {
     f.h = {s, s};
   } else if (wavelet == WDB_DB4) {
     static const std::vector<double> taps = daubechies(4);  // factorised once per process
+    f.h = taps;
+  } else if (wavelet == WDB_SYM6) {
+    static const std::vector<double> taps = symlet(6);
     f.h = taps;
   } else {
     fail(WDB_ERR_ARG, "unknown wavelet %d", wavelet);

@@ -21,7 +21,7 @@ if not os.path.exists(LIB_PATH):
 
 _lib = C.CDLL(LIB_PATH)
 
-WAVELETS = {"haar": 0, "db4": 1}
+WAVELETS = {"haar": 0, "db4": 1, "sym6": 2}
 VALTYPES = {"f32": 0, "bf16": 1, "f16": 2}
 PRECOND = {"none": 0, "spai": 1, "spai_scale": 2, "jacobi": 3}
 

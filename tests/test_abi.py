@@ -38,6 +38,14 @@ def test_library_filter_matches_published_table():
     assert np.allclose(wavelet_filter("haar"), [2 ** -0.5] * 2, rtol=1e-15, atol=0)
 
 
+def test_library_symlet_matches_oracle():
+    """The library's Symmlet 6 (own root finder and phase criterion) equals the oracle's."""
+    from paper_1512_08401_amd import wavelet_filter
+    from oracle import filters
+    h = wavelet_filter("sym6")
+    assert len(h) == 12 and np.max(np.abs(h - filters.sym6())) < 1e-13
+
+
 def test_host_validation_errors(lib):
     from paper_1512_08401_amd import wdb
     fake = C.c_void_p(16)   # never dereferenced: validation fails first

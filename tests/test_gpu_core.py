@@ -55,7 +55,7 @@ def imported(W, P):
 # transforms and blur
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("name,n,J", [("haar", 64, 3), ("db4", 64, 3), ("db4", 256, 4), ("db4", 16, 1),
-                                      ("haar", 8, 3)])
+                                      ("haar", 8, 3), ("sym6", 64, 3), ("sym6", 512, 6)])
 def test_dwt_forward_inverse(W, name, n, J):
     print(f"dwt {name} n={n} J={J}", flush=True)
     u = np.random.default_rng(n + J).random((n, n)).astype(np.float32)
@@ -99,7 +99,7 @@ def _compare_kept(rp, cc, vv, T, K, tol_rel=1e-12):
     return sym.size
 
 
-@pytest.mark.parametrize("case", ["parity64", "db4_32_rot", "haar_16", "db4_16_wrap"])
+@pytest.mark.parametrize("case", ["parity64", "db4_32_rot", "haar_16", "db4_16_wrap", "sym6_64"])
 def test_build_theta_matches_dense_oracle(W, p64, case):
     print(f"build {case}", flush=True)
     if case == "parity64":
@@ -108,7 +108,8 @@ def test_build_theta_matches_dense_oracle(W, p64, case):
     else:
         field, name, J = {"db4_32_rot": (synth.psf_rotating(32, 2.5, 1.0), "db4", 2),
                           "haar_16": (synth.psf_isotropic(16, 1.0, 2.0), "haar", 2),
-                          "db4_16_wrap": (synth.psf_rotating(16, 2.0, 0.8), "db4", 1)}[case]
+                          "db4_16_wrap": (synth.psf_rotating(16, 2.0, 0.8), "db4", 1),
+                          "sym6_64": (synth.psf_rotating(64, 3.0, 1.0), "sym6", 2)}[case]
         K = 20 * field.n ** 2
         T = theta.theta_dense(field, filters.by_name(name), J)
     th = W.build_theta(field, name, J, K)
@@ -503,6 +504,24 @@ def db4_64():
     A = theta.to_csr(r, c, v, 4096)
     u0 = (blur.blur(field, synth.piecewise_image(64, 31)) + synth.noise(64, 0.01, 32)).astype(np.float32)
     return {"A": A, "x0": dwt.dwt2(u0.astype(np.float64), h, 3)}
+
+
+def test_packed_16bit_sym6_matches_oracle(W):
+    """The column code with the 12-tap filter's centring (L - 1 = 11)."""
+    from oracle import quant
+    field = synth.psf_rotating(64, 3.0, 1.0)
+    h = filters.sym6()
+    T = theta.theta_dense(field, h, 2)
+    r, c, v = theta.top_k(T, 30 * 4096)
+    A = theta.to_csr(r, c, v, 4096)
+    rp, cc, vv = theta.csr_arrays(A)
+    th = W.Theta.from_csr(64, "sym6", 2, rp, cc, vv)
+    th.set_precision("f16")
+    Q = quant.quantize(A, 64, 2, "f16")
+    x = np.random.default_rng(28).standard_normal(4096).astype(np.float32)
+    y = host(th.apply(dev(x)))
+    ref = Q @ x.astype(np.float64)
+    assert np.max(np.abs(y - ref)) <= 1e-5 * np.max(np.abs(ref))
 
 
 @pytest.mark.parametrize("fmt", ["f16", "bf16"])
