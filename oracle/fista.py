@@ -15,6 +15,7 @@ with A = Theta_K and x0 = Psi^* u0.
       y = x_k + (k - 1)/(k + 2) (x_k - x_{k-1})
   with x^(0) = y^(1) = x_init (zero by default).  Alg. 2 prints u0 where x0
   is meant in the gradient; x0 is used.
+* ``ista``: the same step without extrapolation (y = x).
 * ``soft_threshold``: S_t(z) = sign(z) max(|z| - t, 0).
 * ``objective``, ``duality_gap``: E and the textbook Lasso dual bound (the
   paper stops on E(x) - E* instead, Sec. 5.5; the gap is a computable
@@ -60,6 +61,22 @@ def fista(A, x0: np.ndarray, lam: float, tau: float, iters: int, x_init=None,
         if callback is not None:
             callback(k, x)
     return x, x_prev, y
+
+
+def ista(A, x0: np.ndarray, lam: float, tau: float, iters: int, x_init=None, p=None, w=None):
+    """Proximal gradient without extrapolation (ISTA; the un-accelerated
+    baseline of the preconditioner comparison, Sec. 5): x_k = S(x_{k-1} -
+    tau g(x_{k-1}) / P) with threshold tau lam w / P."""
+    x0 = np.asarray(x0, dtype=np.float64)
+    N = A.shape[1]
+    x = np.zeros(N) if x_init is None else np.asarray(x_init, dtype=np.float64).copy()
+    At = A.T
+    pinv = np.ones(N) if p is None else 1.0 / np.asarray(p, dtype=np.float64)
+    wt = np.ones(N) if w is None else np.asarray(w, dtype=np.float64)
+    for _ in range(iters):
+        g = At @ (A @ x - x0)
+        x = soft_threshold(x - tau * pinv * g, tau * lam * wt * pinv)
+    return x
 
 
 def objective(A, x0: np.ndarray, lam: float, x: np.ndarray, w=None) -> float:

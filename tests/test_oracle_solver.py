@@ -157,3 +157,27 @@ def test_planted_gradient_transpose_mistake_is_caught():
         x, _, _ = fista.fista(Wrong(Asq), bsq, lam, 1.0 / L, 3000)
     E = fista.objective(Asq, bsq, lam, x) if np.all(np.isfinite(x)) else np.inf
     assert not abs(E - Esq) < 1e-8
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_ista_descends_and_reaches_the_bruteforce_optimum(seed):
+    """ISTA with tau = 1/L is a descent method (the objective never increases)
+    and converges to the exact Lasso minimiser."""
+    from oracle import lasso
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((9, 7))
+    b = rng.standard_normal(9)
+    lam = 0.25
+    L = np.linalg.norm(A, 2) ** 2
+    x = np.zeros(7)
+    E_prev = fista.objective(A, b, lam, x)
+    for _ in range(300):
+        x = fista.ista(A, b, lam, 1.0 / L, 1, x_init=x)
+        E = fista.objective(A, b, lam, x)
+        assert E <= E_prev + 1e-12
+        E_prev = E
+    x_star, _ = lasso.lasso_bruteforce(A, b, lam)
+    x = fista.ista(A, b, lam, 1.0 / L, 50000, x_init=x)
+    assert np.max(np.abs(x - x_star)) <= 1e-7
+    # its first step is FISTA's first step (the extrapolation weight of k = 1 is 0)
+    assert np.array_equal(fista.ista(A, b, lam, 1.0 / L, 1), fista.fista(A, b, lam, 1.0 / L, 1)[0])
