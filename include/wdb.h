@@ -109,6 +109,8 @@ typedef struct {
   int32_t conv_build;  /* 1 if wdb_build_theta took the convolution fast path */
   int32_t l1_weights;  /* wdb_l1_weights kind in use */
   int32_t rule;        /* wdb_threshold_rule of the build (threshold is then the ranked value) */
+  int64_t circulant;   /* -1: no circulant storage; else the explicit entries beside it (the
+                          part of the cut's tie group that breaks the circulant pattern) */
 } wdb_theta_desc;
 
 /* ---------------------------------------------------------------------------
@@ -229,8 +231,10 @@ wdb_status wdb_set_l1_weights(wdb_theta* th, int32_t kind, const float* w);
 wdb_status wdb_set_packed_group(wdb_theta* th, int32_t group);
 
 /* Kernel layout of the iteration: sliced ELL with `slice` rows per slice
- * (8, 16, 32 or 64; rows in coefficient order) and group = 0, or vector CSR
- * with `group` lanes per row (2..64).  The float64 checks and the power
+ * (8, 16, 32 or 64; rows in coefficient order) and group = 0, vector CSR
+ * with `group` lanes per row (2..64), or group = 1: the circulant storage of
+ * a convolution build (Alg. 3 fast path; per subband block one list of
+ * offsets and values shared by all rows, no per-entry indices).  The float64 checks and the power
  * iteration follow the same choice; the batched solver always uses the
  * sliced-ELL copy and the 16-bit iteration its packed copy.  Synchronises. */
 wdb_status wdb_set_kernel_layout(wdb_theta* th, int32_t slice, int32_t group);
@@ -267,6 +271,8 @@ typedef struct {
   int32_t trace_cap;     /* number of triples `trace` can hold                    */
   int32_t use_graph;     /* 1: replay the iterations between checks as a HIP graph */
   double target_objective; /* > 0: also stop at the first check with E <= target     */
+  int32_t ista;          /* 1: no extrapolation, x_k = prox(x_{k-1} - tau grad) (ISTA, the
+                            un-accelerated baseline of the paper's comparison)     */
 } wdb_solve_opts;
 
 typedef struct {

@@ -121,6 +121,7 @@ wdb_status wdb_theta_info(const wdb_theta* th, wdb_theta_desc* out) {
   out->conv_build = th->conv_build;
   out->l1_weights = th->l1_kind;
   out->rule = th->rule;
+  out->circulant = th->st.seg ? th->st.nextra : -1;
   WDB_API_END
 }
 
@@ -152,6 +153,8 @@ void wdb_theta_free(wdb_theta* th) {
   if (th->wrow) (void)hipFree(th->wrow);
   th->pA.free_all();
   th->pAt.free_all();
+  th->st.free_all();
+  th->stT.free_all();
   if (th->l1w) (void)hipFree(th->l1w);
   if (th->l1w_pre) (void)hipFree(th->l1w_pre);
   wdb::free_workspace(th);

@@ -7,6 +7,7 @@
 // shorter slices pad less) and vector CSR with 4, 8 or 16 lanes per row -- and
 // keeps the fastest in the handle.  Decisions can be cached in a text file
 // keyed by the operator's shape and a hash of its row pointer.
+#include <array>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -141,7 +142,8 @@ extern "C" wdb_status wdb_autotune(wdb_theta* th, const char* cache_path, int32_
     hipLaunchKernelGGL(k_fill, dim3((N + 255) / 256), dim3(256), 0, s, th->ws_x0, N, 0.25f);
     hipLaunchKernelGGL(k_fill, dim3((N + 255) / 256), dim3(256), 0, s, th->ws_img, N, 0.0f);
     WDB_HIP(hipGetLastError());
-    const int cands[][2] = {{64, 0}, {32, 0}, {16, 0}, {8, 0}, {0, 4}, {0, 8}, {0, 16}};
+    std::vector<std::array<int, 2>> cands = {{64, 0}, {32, 0}, {16, 0}, {8, 0}, {0, 2}, {0, 4}, {0, 8}, {0, 16}};
+    if (th->st.seg) cands.push_back({0, kStencil});  // circulant storage (convolution fast path)
     hipEvent_t e0, e1;
     WDB_HIP(hipEventCreate(&e0));
     WDB_HIP(hipEventCreate(&e1));
@@ -150,6 +152,11 @@ extern "C" wdb_status wdb_autotune(wdb_theta* th, const char* cache_path, int32_
         const int C = cd[0], G = cd[1];
         if (C) set_slice_height(th, C, s);
         auto pair = [&]() {
+          if (G == kStencil) {
+            launch_res_stencil(th, false, th->ws_y, th->ws_x0, th->ws_r, nullptr, s);
+            launch_prox_stencil(th, th->ws_r, th->ws_img, th->ws_y, 1e-3f, 1e-6f, 0.5f, nullptr, nullptr, nullptr, s);
+            return;
+          }
           launch_res(G, th->A, th->cA, th->ws_y, th->ws_x0, th->ws_r, nullptr, s);
           launch_prox(G, th->At, th->cAt, th->ws_r, th->ws_img, th->ws_y, 1e-3f, 1e-6f, 0.5f, nullptr, nullptr,
                       nullptr, s);
@@ -202,8 +209,10 @@ extern "C" wdb_status wdb_set_kernel_layout(wdb_theta* th, int32_t slice, int32_
   WDB_REQUIRE(th, WDB_ERR_ARG, "null handle");
   WDB_REQUIRE(slice >= 8 && slice <= kSliceMax && (slice & (slice - 1)) == 0, WDB_ERR_ARG,
               "slice height must be 8, 16, 32 or 64");
-  WDB_REQUIRE(group == 0 || group == 2 || group == 4 || group == 8 || group == 16 || group == 32 || group == 64,
-              WDB_ERR_ARG, "lanes per row must be 0 (sliced ELL) or a power of two up to 64");
+  WDB_REQUIRE(group == 0 || group == 2 || group == 4 || group == 8 || group == 16 || group == 32 || group == 64 ||
+                  (group == kStencil && th->st.seg),
+              WDB_ERR_ARG, "lanes per row must be 0 (sliced ELL), a power of two up to 64, or 1 (circulant "
+                           "storage, convolution builds only)");
   WDB_HIP(hipSetDevice(th->device));
   set_slice_height(th, slice, nullptr);
   th->spmv_group = group;

@@ -279,6 +279,7 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
   WDB_REQUIRE(nprob >= 1 && probs && opts, WDB_ERR_ARG, "need at least one problem and options");
   WDB_REQUIRE(opts->max_iters >= 0 && opts->check_every >= 0, WDB_ERR_ARG, "bad iteration counts");
   WDB_REQUIRE(opts->x_init == nullptr, WDB_ERR_ARG, "x_init is per problem in a batch (wdb_problem.x_init)");
+  WDB_REQUIRE(opts->ista == 0, WDB_ERR_ARG, "the batched solver runs Alg. 1 (ista must be 0)");
   const bool pre = opts->use_precond != 0;
   bool stopping = opts->tol_rel_gap > 0;
   for (int i = 0; i < nprob; ++i) stopping |= probs[i].target_objective > 0;

@@ -358,7 +358,9 @@ __global__ void k_expand(const GenDev* __restrict__ gens, const int64_t* __restr
 
 // Builds Theta_K of a stationary field; returns the handle's CSR pieces.
 void build_stationary(Builder& B, int64_t nnz_budget, int scaled, unsigned long long* K_out, double* thr_out,
-                      DevBuf<int32_t>& orow, DevBuf<int32_t>& ocol, DevBuf<double>& oval) {
+                      DevBuf<int32_t>& orow, DevBuf<int32_t>& ocol, DevBuf<double>& oval,
+                      std::vector<CircGen>& kept, std::vector<int32_t>& tie_r, std::vector<int32_t>& tie_c,
+                      std::vector<double>& tie_v) {
   const Geom& G = B.G;
   const int64_t N = static_cast<int64_t>(G.n) * G.n;
   hipStream_t s = B.s;
@@ -419,7 +421,7 @@ void build_stationary(Builder& B, int64_t nnz_budget, int scaled, unsigned long 
   unsigned long long cum = 0;
   size_t full = 0;
   std::vector<std::pair<int64_t, std::pair<int32_t, int32_t>>> tie;  // (a*N + b, (a, b))
-  double tie_v = 0.0, threshold = 0.0;
+  double threshold = 0.0;
   std::vector<double> tie_val;
   while (full < gens.size()) {
     size_t e = full;
@@ -453,8 +455,7 @@ void build_stationary(Builder& B, int64_t nnz_budget, int scaled, unsigned long 
       tie.push_back({cand[i].first, {static_cast<int32_t>(cand[i].first / N), static_cast<int32_t>(cand[i].first % N)}});
       tie_val.push_back(gens[g].v);
     }
-    tie_v = mag(gens[full]);
-    threshold = tie_v;
+    threshold = mag(gens[full]);
     cum += need;
     break;
   }
@@ -488,7 +489,19 @@ void build_stationary(Builder& B, int64_t nnz_budget, int scaled, unsigned long 
     WDB_HIP(hipMemcpy(ocol.p + at, tc.data(), tie.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     WDB_HIP(hipMemcpy(oval.p + at, tie_val.data(), tie.size() * sizeof(double), hipMemcpyHostToDevice));
   }
-  (void)tie_v;
+  kept.clear();
+  for (int g = 0; g < ngen; ++g) {
+    const GenDev& d = gens[g];
+    kept.push_back(CircGen{d.off_k, d.off_b, d.side_k, d.side_b, d.p1, d.p2, d.r, d.form, d.v});
+  }
+  tie_r.clear();
+  tie_c.clear();
+  tie_v.clear();
+  for (size_t i = 0; i < tie.size(); ++i) {
+    tie_r.push_back(tie[i].second.first);
+    tie_c.push_back(tie[i].second.second);
+    tie_v.push_back(tie_val[i]);
+  }
   *K_out = K;
   *thr_out = threshold;
 }
@@ -561,7 +574,10 @@ extern "C" wdb_status wdb_build_theta_rule(const wdb_psf_field* field, int32_t w
     double threshold = 0.0;
     DevBuf<int32_t> orow, ocol;
     DevBuf<double> oval;
-    build_stationary(B, nnz_budget, scaled, &K, &threshold, orow, ocol, oval);
+    std::vector<CircGen> kept;
+    std::vector<int32_t> tie_r, tie_c;
+    std::vector<double> tie_v;
+    build_stationary(B, nnz_budget, scaled, &K, &threshold, orow, ocol, oval, kept, tie_r, tie_c, tie_v);
     B.scratch.reset();
     wdb_theta* th = new wdb_theta();
     try {
@@ -576,6 +592,7 @@ extern "C" wdb_status wdb_build_theta_rule(const wdb_psf_field* field, int32_t w
       th->rule = rule;
       coo_to_csr(N, th->nnz, orow.p, ocol.p, oval.p, &th->csr, s);
       finish_theta(th, s);
+      build_stencils(th, kept, tie_r, tie_c, tie_v);
     } catch (...) {
       wdb_theta_free(th);
       throw;

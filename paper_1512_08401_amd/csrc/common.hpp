@@ -156,6 +156,30 @@ struct Csr32 {
 };
 void csr_to_csr32(const Csr& a, Csr32* out, hipStream_t s);
 
+// Circulant (stencil) storage of a convolution's Theta_K, built by the fast
+// path: per row subband, segments of (offset, value) generators shared by all
+// rows, plus explicit entries of the cut's partial tie group.
+struct Stencil {
+  int* seg_ptr = nullptr;  // device, nsub + 1
+  void* seg = nullptr;     // device, nseg segment records
+  int* gp = nullptr;       // device, ngen (offset, value bits) pairs
+  int* res = nullptr;      // device, residue tables
+  int* xrp = nullptr;      // device, N + 1 (null: no explicit entries)
+  int* xc = nullptr;
+  float* xv = nullptr;
+  int64_t nseg = 0, ngen = 0, nextra = 0;
+  void free_all();
+};
+// One kept generator of the fast build: `form` 0 = rows in subband k (at
+// offset off_k), columns in b; 1 = rows in b, columns in k; p the offset in
+// b, r the side ratio.
+struct CircGen {
+  int64_t off_k, off_b;
+  int side_k, side_b, p1, p2, r, form;
+  double v;
+};
+
+
 // Packed 16-bit form of one matrix (CSR order): per entry a 32-bit word holding
 // the scaled 16-bit value (high half) and a band-relative column code (low
 // half); entries whose column does not fit the code go to a per-row escape
@@ -207,6 +231,7 @@ struct wdb_theta {
   uint16_t* val16T = nullptr;
   float* wrow = nullptr;
   wdb::Packed pA, pAt;  // packed 16-bit forms (CSR order), when valtype != 0
+  wdb::Stencil st, stT; // circulant storage of Theta_K and Theta_K^T (convolution fast path only)
   int q_group = 0;      // lanes per row of the packed kernels (0: default)
   bool has_L = false;
   double L = 0.0;
@@ -249,6 +274,14 @@ void launch_res_packed(const wdb_theta* th, int G, const float* y, const float* 
                        int scale_out, hipStream_t s);
 void launch_prox_packed(const wdb_theta* th, int G, const float* rs, float* x, float* y, float tau, float thr,
                         const int* kdev, const float* pinv, const float* tw, hipStream_t s);
+void build_stencils(wdb_theta* th, const std::vector<CircGen>& gens, const std::vector<int32_t>& tie_rows,
+                    const std::vector<int32_t>& tie_cols, const std::vector<double>& tie_vals);
+constexpr int kStencil = 1;  // kernel "group" value selecting the stencil kernels
+void launch_res_stencil(const wdb_theta* th, bool transpose, const float* y, const float* b, float* r, int* kdev,
+                        hipStream_t s);
+void launch_prox_stencil(const wdb_theta* th, const float* r, float* x, float* y, float tau, float thr, float beta,
+                         const int* kdev, const float* pinv, const float* tw, hipStream_t s);
+
 // Per-row threshold multipliers of the proximal step: w (l1 weights) or w / P
 // (with the preconditioner), or null for uniform weights.
 const float* threshold_weights(const wdb_theta* th, bool pre);

@@ -270,8 +270,11 @@ __global__ __launch_bounds__(kBlock) void k_prox_pk(PackedView P, Geo g, const f
   fill_table<G>(g, row, P.nrows, gl, tab);
   const float gr = packed_dot<G, FMT>(P, row, gl, tab, rs);
   if (gl != 0 || row >= P.nrows) return;
-  const int k = *kdev;
-  const float beta = static_cast<float>((static_cast<double>(k) - 1.0) / (static_cast<double>(k) + 2.0));
+  float beta = 0.0f;  // no counter: no extrapolation (ISTA)
+  if (kdev) {
+    const int k = *kdev;
+    beta = static_cast<float>((static_cast<double>(k) - 1.0) / (static_cast<double>(k) + 2.0));
+  }
   const float pi = PRE ? pinv[row] : 1.0f;
   const float z = y[row] - (tau * pi) * gr;
   const float t = thr * (tw ? tw[row] : pi);

@@ -229,8 +229,11 @@ __global__ __launch_bounds__(kBlock) void k_prox_q(SellView At, const uint2* __r
   const float g = row_dot_q<FMT>(At, v16T, sl, lane, rs);
   const int64_t row = slot_row(At, q);
   if (row < 0) return;
-  const int k = *kdev;
-  const float beta = static_cast<float>((static_cast<double>(k) - 1.0) / (static_cast<double>(k) + 2.0));
+  float beta = 0.0f;  // no counter: no extrapolation (ISTA)
+  if (kdev) {
+    const int k = *kdev;
+    beta = static_cast<float>((static_cast<double>(k) - 1.0) / (static_cast<double>(k) + 2.0));
+  }
   const float pi = PRE ? pinv[row] : 1.0f;
   const float z = y[row] - (tau * pi) * g;
   const float t = thr * (tw ? tw[row] : pi);
@@ -241,7 +244,7 @@ __global__ __launch_bounds__(kBlock) void k_prox_q(SellView At, const uint2* __r
 }
 
 template <int FMT>
-void launch_iteration_q(wdb_theta* th, float* x, bool pre, float tau, float thr, hipStream_t s) {
+void launch_iteration_q(wdb_theta* th, float* x, bool pre, const int* kp, float tau, float thr, hipStream_t s) {
   const SellView A = view(th->A), At = view(th->At);
   const uint2* v16 = reinterpret_cast<const uint2*>(th->val16);
   const uint2* v16T = reinterpret_cast<const uint2*>(th->val16T);
@@ -249,10 +252,10 @@ void launch_iteration_q(wdb_theta* th, float* x, bool pre, float tau, float thr,
                      th->ws_x0, th->ws_r, th->ws_k, 1);
   if (pre)
     hipLaunchKernelGGL((k_prox_q<FMT, true>), slot_grid(At), dim3(kBlock), 0, s, At, v16T, th->ws_r, x,
-                       th->ws_y, tau, thr, th->ws_k, th->pinv, threshold_weights(th, true));
+                       th->ws_y, tau, thr, kp, th->pinv, threshold_weights(th, true));
   else
     hipLaunchKernelGGL((k_prox_q<FMT, false>), slot_grid(At), dim3(kBlock), 0, s, At, v16T, th->ws_r, x,
-                       th->ws_y, tau, thr, th->ws_k, static_cast<const float*>(nullptr),
+                       th->ws_y, tau, thr, kp, static_cast<const float*>(nullptr),
                        threshold_weights(th, false));
 }
 
@@ -355,7 +358,16 @@ void launch_prox_csr(const CsrView& At, const float* r, float* x, float* y, floa
 
 }  // namespace
 
-int kernel_group(const wdb_theta* th) { return th->spmv_group >= 0 ? th->spmv_group : spmv_group(); }
+int kernel_group(const wdb_theta* th) {
+  const int G = th->spmv_group >= 0 ? th->spmv_group : spmv_group();
+  return (G == kStencil && !th->st.seg) ? 0 : G;
+}
+
+// Lanes per row of the float64 CSR passes (the stencil layout checks on CSR).
+int check_group(const wdb_theta* th) {
+  const int G = kernel_group(th);
+  return G == kStencil ? 4 : G;
+}
 
 // r = A y - b with the kernel family G (0: sliced ELL; else vector CSR, G lanes per row).
 void launch_res(int G, const Sell& sell, const Csr32& csr, const float* y, const float* b, float* r, int* kdev,
@@ -744,7 +756,7 @@ double power_iteration(wdb_theta* th, const double* start_host, const double* di
   WDB_HIP(hipMemcpyAsync(vd, v.data(), N * sizeof(double), hipMemcpyHostToDevice, s));
   if (dinv_sqrt) hipLaunchKernelGGL(k_mul, vec_grid(N), dim3(kBlock), 0, s, vd, dinv_sqrt, N);
   const SellView A = view(th->A), At = view(th->At);
-  const int G = kernel_group(th);
+  const int G = check_group(th);
   const int64_t nb = G > 0 ? csr_check_blocks(th, G) : partial_blocks(A, At);
   double* part = th->ws_partial;
   std::vector<double> hist(kRhoChunk);
@@ -795,7 +807,7 @@ struct Check {
 
 Check objective_check(wdb_theta* th, const float* x, const float* x0, double lambda, hipStream_t s) {
   const SellView A = view(th->A), At = view(th->At);
-  const int G = kernel_group(th);
+  const int G = check_group(th);
   const int64_t nb = G > 0 ? csr_check_blocks(th, G) : partial_blocks(A, At);
   double* part = th->ws_partial;
   if (G > 0) {
@@ -822,19 +834,28 @@ Check objective_check(wdb_theta* th, const float* x, const float* x0, double lam
   return Check{E, E > 0 ? gap / E : 0.0};
 }
 
-void launch_iteration(wdb_theta* th, float* x, bool pre, float tau, float thr, hipStream_t s) {
+// One iteration of Alg. 1 (Alg. 2 with `pre`); with `ista` the proximal kernel
+// gets no counter and extrapolates with beta = 0 (plain proximal gradient).
+void launch_iteration(wdb_theta* th, float* x, bool pre, bool ista, float tau, float thr, hipStream_t s) {
+  const int* kp = ista ? nullptr : th->ws_k;
   if (th->valtype != WDB_VAL_F32 && th->pA.word && packed_group(th) > 0) {
     const int G = packed_group(th);
     launch_res_packed(th, G, th->ws_y, th->ws_x0, th->ws_r, th->ws_k, 1, s);
-    launch_prox_packed(th, G, th->ws_r, x, th->ws_y, tau, thr, th->ws_k, pre ? th->pinv : nullptr,
+    launch_prox_packed(th, G, th->ws_r, x, th->ws_y, tau, thr, kp, pre ? th->pinv : nullptr,
                        threshold_weights(th, pre), s);
     return;
   }
-  if (th->valtype == WDB_VAL_BF16) return launch_iteration_q<WDB_VAL_BF16>(th, x, pre, tau, thr, s);
-  if (th->valtype == WDB_VAL_F16) return launch_iteration_q<WDB_VAL_F16>(th, x, pre, tau, thr, s);
+  if (th->valtype == WDB_VAL_BF16) return launch_iteration_q<WDB_VAL_BF16>(th, x, pre, kp, tau, thr, s);
+  if (th->valtype == WDB_VAL_F16) return launch_iteration_q<WDB_VAL_F16>(th, x, pre, kp, tau, thr, s);
   const int G = kernel_group(th);
+  if (G == kStencil) {
+    launch_res_stencil(th, false, th->ws_y, th->ws_x0, th->ws_r, th->ws_k, s);
+    launch_prox_stencil(th, th->ws_r, x, th->ws_y, tau, thr, 0.0f, kp, pre ? th->pinv : nullptr,
+                        threshold_weights(th, pre), s);
+    return;
+  }
   launch_res(G, th->A, th->cA, th->ws_y, th->ws_x0, th->ws_r, th->ws_k, s);
-  launch_prox(G, th->At, th->cAt, th->ws_r, x, th->ws_y, tau, thr, 0.0f, th->ws_k, pre ? th->pinv : nullptr,
+  launch_prox(G, th->At, th->cAt, th->ws_r, x, th->ws_y, tau, thr, 0.0f, kp, pre ? th->pinv : nullptr,
               threshold_weights(th, pre), s);
 }
 
@@ -894,7 +915,7 @@ wdb_status solve_impl(wdb_theta* th, const float* x0_src, bool from_image, float
     if (use_graph && total >= c) {
       if (!th->capture_stream) WDB_HIP(hipStreamCreateWithFlags(&th->capture_stream, hipStreamNonBlocking));
       WDB_HIP(hipStreamBeginCapture(th->capture_stream, hipStreamCaptureModeThreadLocal));
-      for (int i = 0; i < c; ++i) launch_iteration(th, x_out, pre, tau_f, thr_f, th->capture_stream);
+      for (int i = 0; i < c; ++i) launch_iteration(th, x_out, pre, opts->ista != 0, tau_f, thr_f, th->capture_stream);
       WDB_HIP(hipStreamEndCapture(th->capture_stream, &graph));
       WDB_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
     }
@@ -904,7 +925,7 @@ wdb_status solve_impl(wdb_theta* th, const float* x0_src, bool from_image, float
       if (exec && step == c) {
         WDB_HIP(hipGraphLaunch(exec, s));
       } else {
-        for (int i = 0; i < step; ++i) launch_iteration(th, x_out, pre, tau_f, thr_f, s);
+        for (int i = 0; i < step; ++i) launch_iteration(th, x_out, pre, opts->ista != 0, tau_f, thr_f, s);
         WDB_HIP(hipGetLastError());
       }
       done += step;
@@ -1024,9 +1045,13 @@ wdb_status wdb_theta_apply(wdb_theta* th, int32_t transpose, const float* x, con
     WDB_HIP(hipGetLastError());
     return WDB_OK;
   }
-  for (int i = 0; i < repeat; ++i)
-    wdb::launch_res(wdb::kernel_group(th), transpose ? th->At : th->A, transpose ? th->cAt : th->cA, x, b, y, nullptr,
-                    s);
+  const int G = wdb::kernel_group(th);
+  for (int i = 0; i < repeat; ++i) {
+    if (G == wdb::kStencil)
+      wdb::launch_res_stencil(th, transpose != 0, x, b, y, nullptr, s);
+    else
+      wdb::launch_res(G, transpose ? th->At : th->A, transpose ? th->cAt : th->cA, x, b, y, nullptr, s);
+  }
   WDB_HIP(hipGetLastError());
   WDB_API_END
 }
@@ -1040,8 +1065,12 @@ wdb_status wdb_prox_step(wdb_theta* th, const float* r, float* x, float* y, floa
   WDB_HIP(hipSetDevice(th->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
   const float thr = tau * lambda;
-  wdb::launch_prox(wdb::kernel_group(th), th->At, th->cAt, r, x, y, tau, thr, beta, nullptr,
-                   use_precond ? th->pinv : nullptr, wdb::threshold_weights(th, use_precond != 0), s);
+  if (wdb::kernel_group(th) == wdb::kStencil)
+    wdb::launch_prox_stencil(th, r, x, y, tau, thr, beta, nullptr, use_precond ? th->pinv : nullptr,
+                             wdb::threshold_weights(th, use_precond != 0), s);
+  else
+    wdb::launch_prox(wdb::kernel_group(th), th->At, th->cAt, r, x, y, tau, thr, beta, nullptr,
+                     use_precond ? th->pinv : nullptr, wdb::threshold_weights(th, use_precond != 0), s);
   WDB_HIP(hipGetLastError());
   WDB_API_END
 }

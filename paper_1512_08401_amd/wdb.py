@@ -49,14 +49,14 @@ class ThetaDesc(C.Structure):
                 ("lipschitz", C.c_double), ("threshold", C.c_double), ("lipschitz_p", C.c_double),
                 ("precond", C.c_int32), ("valtype", C.c_int32), ("slice", C.c_int32), ("group", C.c_int32),
                 ("group16", C.c_int32), ("escapes", C.c_int64), ("conv_build", C.c_int32),
-                ("l1_weights", C.c_int32), ("rule", C.c_int32)]
+                ("l1_weights", C.c_int32), ("rule", C.c_int32), ("circulant", C.c_int64)]
 
 
 class SolveOpts(C.Structure):
     _fields_ = [("max_iters", C.c_int32), ("check_every", C.c_int32), ("tol_rel_gap", C.c_double),
                 ("x_init", C.c_void_p), ("k0", C.c_int32), ("use_precond", C.c_int32),
                 ("stream", C.c_void_p), ("trace", C.POINTER(C.c_double)), ("trace_cap", C.c_int32),
-                ("use_graph", C.c_int32), ("target_objective", C.c_double)]
+                ("use_graph", C.c_int32), ("target_objective", C.c_double), ("ista", C.c_int32)]
 
 
 class ProblemC(C.Structure):
@@ -311,7 +311,7 @@ class Theta:
         return E.value, g.value
 
     def _solve(self, fn, src, lam, iters, check_every, tol, x_init, k0, precond, use_graph, trace_cap, out,
-               stream, target=0.0):
+               stream, target=0.0, ista=False):
         torch = _torch()
         N = self.N
         x = torch.empty(N, device=src.device, dtype=torch.float32) if out is None else out
@@ -319,7 +319,7 @@ class Theta:
         o = SolveOpts(int(iters), int(check_every), float(tol),
                       None if x_init is None else _dev(x_init, N, "x_init").value, int(k0),
                       1 if precond else 0, _stream(stream).value, trace.ctypes.data_as(_pd), int(trace_cap),
-                      1 if use_graph else 0, float(target))
+                      1 if use_graph else 0, float(target), 1 if ista else 0)
         info = SolveInfo()
         st = getattr(_lib, fn)(self._h, _dev(src, name="input"), float(lam), C.byref(o), _dev(x, N, "x_out"),
                                C.byref(info))
@@ -334,17 +334,17 @@ class Theta:
 
     def solve(self, u, lam: float, iters: int, check_every: int = 20, tol: float = 0.0, x_init=None, k0: int = 1,
               precond: bool = False, use_graph: bool = False, trace_cap: int = 0, out=None, stream=None,
-              target: float = 0.0):
-        """FISTA from a blurred image u (device n*n float32); returns (x, info)."""
+              target: float = 0.0, ista: bool = False):
+        """FISTA (ISTA with ista=True) from a blurred image u (device n*n float32); returns (x, info)."""
         return self._solve("wdb_solve", u, lam, iters, check_every, tol, x_init, k0, precond, use_graph,
-                           trace_cap, out, stream, target)
+                           trace_cap, out, stream, target, ista)
 
     def solve_coeffs(self, x0, lam: float, iters: int, check_every: int = 20, tol: float = 0.0, x_init=None,
                      k0: int = 1, precond: bool = False, use_graph: bool = False, trace_cap: int = 0, out=None,
-                     stream=None, target: float = 0.0):
-        """FISTA from wavelet-domain data x0 (device N float32); returns (x, info)."""
+                     stream=None, target: float = 0.0, ista: bool = False):
+        """FISTA (ISTA with ista=True) from wavelet-domain data x0 (device N float32); returns (x, info)."""
         return self._solve("wdb_solve_coeffs", x0, lam, iters, check_every, tol, x_init, k0, precond, use_graph,
-                           trace_cap, out, stream, target)
+                           trace_cap, out, stream, target, ista)
 
     def synthesize(self, x, out=None, stream=None):
         torch = _torch()
@@ -430,7 +430,7 @@ def solve_batched(problems, iters: int, check_every: int = 20, tol: float = 0.0,
                           None if xi is None else _dev(xi, N, "x_init").value, _dev(x, N, "x_out").value, tgt,
                           data if coeffs else None)
     o = SolveOpts(int(iters), int(check_every), float(tol), None, int(k0), 1 if precond else 0,
-                  _stream(stream).value, None, 0, 1 if use_graph else 0, 0.0)
+                  _stream(stream).value, None, 0, 1 if use_graph else 0, 0.0, 0)
     infos = (SolveInfo * n)()
     st = _lib.wdb_solve_batched(n, arr, C.byref(o), infos)
     res = [{k: getattr(inf, k) for k, _ in SolveInfo._fields_} for inf in infos]
