@@ -35,8 +35,11 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_label(layout):
+def kernel_label(layout, waves=4):
     slice_h, group = layout
+    if group == 3:
+        return (f"k_res_tl<{waves}>", f"r = Theta_K y - x0, float32 tiled pattern storage (8x8 coefficient tiles, "
+                f"{waves} wavefronts per tile)")
     if group > 0:
         return f"k_res_csr<{group}>", f"r = Theta_K y - x0, float32 CSR, {group} lanes per row"
     return "k_res", f"r = Theta_K y - x0, float32 sliced-ELL, {slice_h} rows per slice"
@@ -222,13 +225,14 @@ def main():
     nnz = info["nnz"]
     alg_bytes = 8 * nnz + 12 * N          # values + indices once, y/x0 read once, r written once
     achieved = alg_bytes / (k_us * 1e-6) / 1e9
-    kname, kdesc = kernel_label(layout)
+    kname, kdesc = kernel_label(layout, info["tile_waves"])
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": profiled_traffic(wl.name, kname, layout),
                 "kernel": f"{kname} ({kdesc})",
                 "kernel_us": round(k_us, 2), "algorithmic_bytes": alg_bytes,
-                "stored_slots": info["stored"], "transpose_kernel_us": round(kt_us, 2),
+                "stored_slots": th.info()["tile_slots"] // 2 if layout[1] == 3 else info["stored"],
+                "transpose_kernel_us": round(kt_us, 2),
                 "layout": {"slice": layout[0], "lanes_per_row": layout[1]},
                 "k_res_16bit_us": {k: round(v, 2) for k, v in half_us.items()},
                 "k_res_16bit_gbs": {k: round((6 * nnz + 12 * N) / (v * 1e-6) / 1e9, 1) for k, v in half_us.items()}}

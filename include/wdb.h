@@ -103,7 +103,8 @@ typedef struct {
   int32_t precond;     /* 0 none, else the wdb_precond kind in use      */
   int32_t valtype;     /* wdb_valtype of the iteration values            */
   int32_t slice;       /* sliced-ELL slice height of the iteration copies */
-  int32_t group;       /* lanes per row of the vector-CSR kernels (0: sliced ELL) */
+  int32_t group;       /* lanes per row of the vector-CSR kernels (0: sliced ELL; 1: circulant,
+                          3: tiled pattern storage) */
   int32_t group16;     /* lanes per row of the packed 16-bit kernels (0: not in use) */
   int64_t escapes;     /* entries of Theta_K and Theta_K^T outside the packed column code */
   int32_t conv_build;  /* 1 if wdb_build_theta took the convolution fast path */
@@ -111,6 +112,8 @@ typedef struct {
   int32_t rule;        /* wdb_threshold_rule of the build (threshold is then the ranked value) */
   int64_t circulant;   /* -1: no circulant storage; else the explicit entries beside it (the
                           part of the cut's tie group that breaks the circulant pattern) */
+  int32_t tile_waves;  /* wavefronts per tile of the tiled layout (group 3) */
+  int64_t tile_slots;  /* stored values of the tiled copies of Theta_K and Theta_K^T (0: not built) */
 } wdb_theta_desc;
 
 /* ---------------------------------------------------------------------------
@@ -232,12 +235,25 @@ wdb_status wdb_set_packed_group(wdb_theta* th, int32_t group);
 
 /* Kernel layout of the iteration: sliced ELL with `slice` rows per slice
  * (8, 16, 32 or 64; rows in coefficient order) and group = 0, vector CSR
- * with `group` lanes per row (2..64), or group = 1: the circulant storage of
+ * with `group` lanes per row (2..64), group = 1: the circulant storage of
  * a convolution build (Alg. 3 fast path; per subband block one list of
- * offsets and values shared by all rows, no per-entry indices).  The float64 checks and the power
- * iteration follow the same choice; the batched solver always uses the
- * sliced-ELL copy and the 16-bit iteration its packed copy.  Synchronises. */
+ * offsets and values shared by all rows, no per-entry indices), or
+ * group = 3: the tiled pattern storage (tiles of 64 coefficients of one
+ * subband -- 8 x 8 positions, or a whole subband of side < 8 -- share one
+ * sorted list of band-relative column codes, values stored per code and row
+ * with zeros where a row lacks the entry; one wavefront per tile, lane = row;
+ * built on first use, about 1.6 x K float32 values per matrix for the
+ * smoothly varying fields of Sec. 5).  The float64 checks and the power
+ * iteration use vector CSR under layouts 1 and 3, else the same choice; the
+ * batched solver always uses the sliced-ELL copy and the 16-bit iteration
+ * its packed copy.  Synchronises.  Errors: WDB_ERR_ARG, _OOM, _HIP. */
 wdb_status wdb_set_kernel_layout(wdb_theta* th, int32_t slice, int32_t group);
+
+/* Wavefronts per tile of the tiled layout (1, 2, 4 or 8; default 4): the
+ * codes of a tile are dealt round-robin to the wavefronts and their partial
+ * sums added in wavefront order.  Changes only the summation order.  Errors:
+ * WDB_ERR_ARG. */
+wdb_status wdb_set_tile_waves(wdb_theta* th, int32_t waves);
 
 /* Project autotuner: times the iteration kernel pair `reps` times for every
  * candidate layout (slices of 64/32/16/8 rows; vector CSR with 4/8/16 lanes)

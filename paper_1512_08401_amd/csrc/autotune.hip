@@ -4,9 +4,14 @@
 // transposed product with the proximal epilogue) for each candidate layout --
 // sliced ELL with slice heights 64, 32, 16, 8 (rows in natural order, so a
 // slice's rows are neighbouring coefficients whose gathers share cache lines;
-// shorter slices pad less) and vector CSR with 4, 8 or 16 lanes per row -- and
-// keeps the fastest in the handle.  Decisions can be cached in a text file
+// shorter slices pad less), vector CSR with 2, 4, 8 or 16 lanes per row, the
+// circulant storage of convolution builds and the tiled pattern storage with
+// 1, 2, 4 or 8 wavefronts per tile -- and
+// keeps the fastest in the handle (each candidate timed in two alternating
+// passes, its best pass counted, so that one slow pass from a clock or
+// cache transient does not decide).  Decisions can be cached in a text file
 // keyed by the operator's shape and a hash of its row pointer.
+#include <algorithm>
 #include <array>
 #include <cstdio>
 #include <cstdlib>
@@ -75,8 +80,12 @@ void tune_packed(wdb_theta* th, const char* cache_path, const std::string& key, 
     hipEvent_t e0, e1;
     WDB_HIP(hipEventCreate(&e0));
     WDB_HIP(hipEventCreate(&e1));
+    double t_min[4] = {1e300, 1e300, 1e300, 1e300};
+    const int groups[4] = {2, 4, 8, 16};
     try {
-      for (int G : {2, 4, 8, 16}) {
+      for (int pass = 0; pass < 2; ++pass)
+      for (int gi = 0; gi < 4; ++gi) {
+        const int G = groups[gi];
         auto pair = [&]() {
           launch_res_packed(th, G, th->ws_y, th->ws_x0, th->ws_r, nullptr, 1, s);
           launch_prox_packed(th, G, th->ws_r, th->ws_img, th->ws_y, 1e-3f, 1e-6f, th->ws_k, nullptr, nullptr, s);
@@ -90,11 +99,14 @@ void tune_packed(wdb_theta* th, const char* cache_path, const std::string& key, 
         WDB_HIP(hipEventElapsedTime(&ms, e0, e1));
         const double us = 1e3 * ms / reps;
         if (std::getenv("WDB_LOG")) std::fprintf(stderr, "[wdb] autotune packed G=%d: %.2f us per iteration\n", G, us);
-        if (us < best) {
-          best = us;
-          bestG = G;
-        }
+        t_min[gi] = std::min(t_min[gi], us);
       }
+      for (int gi = 0; gi < 4; ++gi)
+        if (t_min[gi] < best) {
+          best = t_min[gi];
+          bestG = groups[gi];
+        }
+
     } catch (...) {
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
@@ -122,7 +134,7 @@ extern "C" wdb_status wdb_autotune(wdb_theta* th, const char* cache_path, int32_
   ensure_workspace(th);
   hipStream_t s = nullptr;
   const std::string key = cache_key(th);
-  int bestC = -1, bestG = -1;
+  int bestC = -1, bestG = -1, bestW = 0;
   double best = 1e300;
   if (cache_path && *cache_path) {
     std::ifstream in(cache_path);
@@ -132,26 +144,41 @@ extern "C" wdb_status wdb_autotune(wdb_theta* th, const char* cache_path, int32_
     while (in >> k >> C >> G >> us)
       if (k == key) {
         bestC = C;
-        bestG = G;
+        bestG = G % 100;
+        bestW = G / 100;
         best = us;
       }
   }
+  if (bestC > 0 && bestG == kTiled) build_tiled(th);
   if (bestC < 0) {
     const int64_t N = th->N;
     hipLaunchKernelGGL(k_fill, dim3((N + 255) / 256), dim3(256), 0, s, th->ws_y, N, 0.5f);
     hipLaunchKernelGGL(k_fill, dim3((N + 255) / 256), dim3(256), 0, s, th->ws_x0, N, 0.25f);
     hipLaunchKernelGGL(k_fill, dim3((N + 255) / 256), dim3(256), 0, s, th->ws_img, N, 0.0f);
     WDB_HIP(hipGetLastError());
-    std::vector<std::array<int, 2>> cands = {{64, 0}, {32, 0}, {16, 0}, {8, 0}, {0, 2}, {0, 4}, {0, 8}, {0, 16}};
-    if (th->st.seg) cands.push_back({0, kStencil});  // circulant storage (convolution fast path)
+    std::vector<std::array<int, 3>> cands = {{64, 0, 0}, {32, 0, 0}, {16, 0, 0}, {8, 0, 0},
+                                             {0, 2, 0},  {0, 4, 0},  {0, 8, 0},  {0, 16, 0}};
+    if (th->st.seg) cands.push_back({0, kStencil, 0});  // circulant storage (convolution fast path)
+    if (tiled_supported(th)) {
+      build_tiled(th);
+      for (int W : {1, 2, 4, 8}) cands.push_back({0, kTiled, W});
+    }
     hipEvent_t e0, e1;
     WDB_HIP(hipEventCreate(&e0));
     WDB_HIP(hipEventCreate(&e1));
+    std::vector<double> t_min(cands.size(), 1e300);
     try {
-      for (const auto& cd : cands) {
-        const int C = cd[0], G = cd[1];
+      for (int pass = 0; pass < 2; ++pass)
+      for (size_t ci = 0; ci < cands.size(); ++ci) {
+        const int C = cands[ci][0], G = cands[ci][1];
         if (C) set_slice_height(th, C, s);
+        if (G == kTiled) th->tile_waves = cands[ci][2];
         auto pair = [&]() {
+          if (G == kTiled) {
+            launch_res_tiled(th, false, th->ws_y, th->ws_x0, th->ws_r, nullptr, s);
+            launch_prox_tiled(th, th->ws_r, th->ws_img, th->ws_y, 1e-3f, 1e-6f, 0.5f, nullptr, nullptr, nullptr, s);
+            return;
+          }
           if (G == kStencil) {
             launch_res_stencil(th, false, th->ws_y, th->ws_x0, th->ws_r, nullptr, s);
             launch_prox_stencil(th, th->ws_r, th->ws_img, th->ws_y, 1e-3f, 1e-6f, 0.5f, nullptr, nullptr, nullptr, s);
@@ -169,13 +196,19 @@ extern "C" wdb_status wdb_autotune(wdb_theta* th, const char* cache_path, int32_
         float ms = 0.0f;
         WDB_HIP(hipEventElapsedTime(&ms, e0, e1));
         const double us = 1e3 * ms / reps;
-        if (std::getenv("WDB_LOG")) std::fprintf(stderr, "[wdb] autotune C=%d G=%d: %.2f us per iteration\n", C, G, us);
-        if (us < best) {
-          best = us;
-          bestC = C ? C : th->A.C;
-          bestG = G;
-        }
+        if (std::getenv("WDB_LOG"))
+          std::fprintf(stderr, "[wdb] autotune C=%d G=%d W=%d: %.2f us per iteration\n", C, G, cands[ci][2], us);
+        t_min[ci] = std::min(t_min[ci], us);
       }
+      for (size_t ci = 0; ci < cands.size(); ++ci)
+        if (t_min[ci] < best) {
+          best = t_min[ci];
+          bestC = cands[ci][0];
+          bestG = cands[ci][1];
+          bestW = cands[ci][2];
+        }
+      if (bestC == 0) bestC = th->A.C;  // a CSR or circulant layout keeps the current slice height
+
     } catch (...) {
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
@@ -185,11 +218,17 @@ extern "C" wdb_status wdb_autotune(wdb_theta* th, const char* cache_path, int32_
     (void)hipEventDestroy(e1);
     if (cache_path && *cache_path) {
       std::ofstream out(cache_path, std::ios::app);
-      out << key << " " << bestC << " " << bestG << " " << best << "\n";
+      out << key << " " << bestC << " " << (bestG == kTiled ? bestG + 100 * bestW : bestG) << " " << best << "\n";
     }
   }
   set_slice_height(th, bestC, s);
   th->spmv_group = bestG;
+  if (bestG == kTiled) {
+    th->tile_waves = bestW;
+  } else {  // the tiled copies are only kept when they are the layout in use
+    th->tA.free_all();
+    th->tAt.free_all();
+  }
   if (th->valtype != WDB_VAL_F32) {
     const int vt = th->valtype;
     WDB_HIP(hipDeviceSynchronize());
@@ -210,11 +249,12 @@ extern "C" wdb_status wdb_set_kernel_layout(wdb_theta* th, int32_t slice, int32_
   WDB_REQUIRE(slice >= 8 && slice <= kSliceMax && (slice & (slice - 1)) == 0, WDB_ERR_ARG,
               "slice height must be 8, 16, 32 or 64");
   WDB_REQUIRE(group == 0 || group == 2 || group == 4 || group == 8 || group == 16 || group == 32 || group == 64 ||
-                  (group == kStencil && th->st.seg),
-              WDB_ERR_ARG, "lanes per row must be 0 (sliced ELL), a power of two up to 64, or 1 (circulant "
-                           "storage, convolution builds only)");
+                  (group == kStencil && th->st.seg) || (group == kTiled && tiled_supported(th)),
+              WDB_ERR_ARG, "lanes per row must be 0 (sliced ELL), a power of two up to 64, 1 (circulant "
+                           "storage, convolution builds only) or 3 (tiled pattern storage)");
   WDB_HIP(hipSetDevice(th->device));
   set_slice_height(th, slice, nullptr);
+  if (group == kTiled) build_tiled(th);
   th->spmv_group = group;
   if (th->valtype != WDB_VAL_F32) {
     const int vt = th->valtype;

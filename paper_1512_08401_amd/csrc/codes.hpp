@@ -1,0 +1,112 @@
+// Band-relative column codes shared by the packed 16-bit form and the tiled
+// pattern storage.
+//
+// An entry theta[a, b] is only large when the supports of the two atoms are
+// close in space and in scale (the decay bound of Sec. 3.2).  For a row
+// coefficient a at level la, position (ia, ja), and a column coefficient b at
+// level lb, orientation o, position (ib, jb), the 16-bit code stores
+//   dL = lb - la in [-3, 3], band slot q in {0 (approximation), 1, 2, 3
+//   (details (0,1), (1,0), (1,1))}, and (di, dj) in [-16, 15]^2: b's position
+//   minus the point of level lb whose atom is centred nearest to a's atom,
+//   modulo the side s of b's subband,
+// as bit fields ((dL + 3) << 13) | (q << 11) | ((di + 16) << 5) | (dj + 16).
+// b's index is then q s^2 + ((ci + di) mod s) s + ((cj + dj) mod s), exact
+// integer arithmetic on power-of-two sides.
+#pragma once
+
+#include <cstdint>
+
+#include "common.hpp"
+
+namespace wdb {
+
+constexpr int kDOff = 16;  // displacements in [-16, 15]
+constexpr int kLMax = 3;
+// Padding word of a partial step: value 0, column = a valid coefficient (a
+// detail subband of the row's own level, which every level has).
+constexpr uint32_t kPadCode = (static_cast<uint32_t>(kLMax) << 13) | (1u << 11) | (kDOff << 5) | kDOff;
+
+struct Geo {
+  int logn, J, L1;  // log2 of the image side, levels, filter length - 1
+};
+
+struct Pos {
+  int level, orient, i, j;  // orient 0..2: details (0,1), (1,0), (1,1); 3: approximation
+};
+
+__host__ __device__ inline int floor_log2(uint64_t v) { return 63 - __builtin_clzll(v); }
+
+// Subband position of canonical index r.  Level l details of side s = n >> l
+// sit at offsets s^2, 2 s^2, 3 s^2; the approximation of side n >> J at 0.
+__host__ __device__ inline Pos pos_of(const Geo& g, int64_t r) {
+  const int lsJ = g.logn - g.J;
+  if (r < (int64_t{1} << (2 * lsJ)))
+    return Pos{g.J, 3, static_cast<int>(r >> lsJ), static_cast<int>(r & ((int64_t{1} << lsJ) - 1))};
+  const int ls = floor_log2(static_cast<uint64_t>(r)) >> 1;
+  const int o = static_cast<int>(r >> (2 * ls)) - 1;
+  const int64_t p = r - (static_cast<int64_t>(o) + 1) * (int64_t{1} << (2 * ls));
+  return Pos{g.logn - ls, o, static_cast<int>(p >> ls), static_cast<int>(p & ((int64_t{1} << ls) - 1))};
+}
+
+// Index of the subband (canonical order: approximation, then per level J..1
+// the three detail orientations).
+__host__ __device__ inline int band_index(const Geo& g, int level, int orient) {
+  return orient == 3 ? 0 : 1 + 3 * (g.J - level) + orient;
+}
+
+// Point of level lb whose atom is centred nearest to the atom at index i of
+// level la (atoms of level l at index i are centred at 2^l i + L1 (2^l - 1) / 2),
+// not yet reduced modulo the side.  With P = (i << (la + 1)) + L1 2^la this is
+// (P + (1 - L1) 2^lb) >> (lb + 1).
+__host__ __device__ inline int centre_at(const Geo& g, int i, int la, int lb) {
+  return ((i << (la + 1)) + g.L1 * ((1 << la) - (1 << lb)) + (1 << lb)) >> (lb + 1);
+}
+
+// Per-row constants of the decode: the numerators of the row atom's centre,
+// (i << (la + 1)) + L1 2^la and the same in j, and la - 3.
+struct RowCode {
+  int pi, pj, lb0;
+};
+
+__host__ __device__ inline RowCode row_code(const Geo& g, const Pos& p) {
+  return RowCode{(p.i << (p.level + 1)) + g.L1 * (1 << p.level), (p.j << (p.level + 1)) + g.L1 * (1 << p.level),
+                 p.level - kLMax};
+}
+
+// Column of a code for the row of `rc`: the centre of the column level
+// lb = la + dL is (num + (1 - L1) 2^lb) >> (lb + 1) (centre_at), then the
+// displacement is added modulo the side.  lb is clamped to [1, J] so that
+// any code decodes to an index below n^2 (the encoder only emits levels in
+// range, where the clamp is the identity).
+__host__ __device__ inline int decode_col(const Geo& g, const RowCode& rc, uint32_t code) {
+  const int lb = min(max(rc.lb0 + static_cast<int>((code >> 13) & 7u), 1), g.J);
+  const int ls = g.logn - lb;
+  const int t = (1 - g.L1) * (1 << lb);
+  const int ci = (rc.pi + t) >> (lb + 1);
+  const int cj = (rc.pj + t) >> (lb + 1);
+  const int m = (1 << ls) - 1;
+  const int ib = (ci - kDOff + static_cast<int>((code >> 5) & 31u)) & m;
+  const int jb = (cj - kDOff + static_cast<int>(code & 31u)) & m;
+  return (static_cast<int>((code >> 11) & 3u) << (2 * ls)) + (ib << ls) + jb;
+}
+
+// Code of column `col` for row position p, or -1 if it does not fit.
+__host__ __device__ inline int encode_col(const Geo& g, const Pos& p, int64_t col) {
+  const Pos q = pos_of(g, col);
+  const int dL = q.level - p.level;
+  if (dL < -kLMax || dL > kLMax) return -1;
+  const int ls = g.logn - q.level;
+  const int s = 1 << ls, m = s - 1, h = s >> 1;
+  const int di = ((q.i - centre_at(g, p.i, p.level, q.level) + h) & m) - h;
+  const int dj = ((q.j - centre_at(g, p.j, p.level, q.level) + h) & m) - h;
+  if (di < -kDOff || di >= kDOff || dj < -kDOff || dj >= kDOff) return -1;
+  const int slot = q.orient == 3 ? 0 : q.orient + 1;
+  return ((dL + kLMax) << 13) | (slot << 11) | ((di + kDOff) << 5) | (dj + kDOff);
+}
+
+inline Geo geo_of(const wdb_theta* th) {
+  return Geo{floor_log2(static_cast<uint64_t>(th->n)), th->levels,
+             static_cast<int>(make_filter(th->wavelet).h.size()) - 1};
+}
+
+}  // namespace wdb

@@ -193,6 +193,22 @@ struct Packed {
   int32_t* ec = nullptr;     // device, nesc: escape columns
   void free_all();
 };
+// Tiled pattern storage of one matrix: tiles of up to 64 rows of one subband
+// share a sorted list of band-relative column codes; values are stored per
+// (code, row) with zeros where a row lacks the entry.  Tile t owns codes
+// [desc[t].x, desc[t].y) and values [desc[t].x * 64, desc[t].y * 64) laid out
+// [group of 4 codes][lane][4]; rows with entries that have no code keep them
+// in a per-row escape list (erp null when there are none).
+struct Tiled {
+  int64_t ntiles = 0, npat = 0, nesc = 0, nkept = 0;
+  int* desc = nullptr;       // device, 4 * ntiles (int4 per tile)
+  uint32_t* code = nullptr;  // device, npat
+  float* val = nullptr;      // device, 64 * npat
+  int* erp = nullptr;        // device, nrows + 1
+  int* ec = nullptr;         // device, nesc
+  float* ev = nullptr;       // device, nesc
+  void free_all();
+};
 // Lanes per row of the vector-CSR kernels (0: sliced-ELL kernels).
 int spmv_group();
 
@@ -232,6 +248,8 @@ struct wdb_theta {
   float* wrow = nullptr;
   wdb::Packed pA, pAt;  // packed 16-bit forms (CSR order), when valtype != 0
   wdb::Stencil st, stT; // circulant storage of Theta_K and Theta_K^T (convolution fast path only)
+  wdb::Tiled tA, tAt;   // tiled pattern storage of Theta_K and Theta_K^T (built on demand)
+  int tile_waves = 4;   // wavefronts per tile of the tiled kernels
   int q_group = 0;      // lanes per row of the packed kernels (0: default)
   bool has_L = false;
   double L = 0.0;
@@ -277,6 +295,13 @@ void launch_prox_packed(const wdb_theta* th, int G, const float* rs, float* x, f
 void build_stencils(wdb_theta* th, const std::vector<CircGen>& gens, const std::vector<int32_t>& tie_rows,
                     const std::vector<int32_t>& tie_cols, const std::vector<double>& tie_vals);
 constexpr int kStencil = 1;  // kernel "group" value selecting the stencil kernels
+constexpr int kTiled = 3;    // kernel "group" value selecting the tiled pattern kernels
+bool tiled_supported(const wdb_theta* th);
+void build_tiled(wdb_theta* th);  // builds tA / tAt from cA / cAt if not built yet
+void launch_res_tiled(const wdb_theta* th, bool transpose, const float* y, const float* b, float* r, int* kdev,
+                      hipStream_t s);
+void launch_prox_tiled(const wdb_theta* th, const float* r, float* x, float* y, float tau, float thr, float beta,
+                       const int* kdev, const float* pinv, const float* tw, hipStream_t s);
 void launch_res_stencil(const wdb_theta* th, bool transpose, const float* y, const float* b, float* r, int* kdev,
                         hipStream_t s);
 void launch_prox_stencil(const wdb_theta* th, const float* r, float* x, float* y, float tau, float thr, float beta,

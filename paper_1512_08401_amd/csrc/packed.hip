@@ -7,23 +7,11 @@
 // its scale block (row subband for Theta_K, column subband for Theta_K^T),
 // rounded to binary16 or bfloat16.
 //
-// Column code.  An entry theta[a, b] is only large when the supports of the
-// two atoms are close in space and in scale (the decay bound of Sec. 3.2, in
-// the distance between the atoms' supports and in |j - k|).  For a row
-// coefficient a at level la, position (ia, ja), and a column coefficient b at
-// level lb, orientation o, position (ib, jb), the code stores
-//   dL = lb - la in [-3, 3], band slot q in {0 (approximation), 1, 2, 3
-//   (details (0,1), (1,0), (1,1))}, and (di, dj) in [-16, 15]^2: b's position
-//   minus the point of level lb whose atom is centred nearest to a's atom,
-//   modulo the side s of b's subband,
-// as bit fields ((dL + 3) << 13) | (q << 11) | ((di + 16) << 5) | (dj + 16).
-// b's index is then q s^2 + ((ci + di) mod s) s + ((cj + dj) mod s), exact
-// integer arithmetic on power-of-two sides, so the packed operator has
-// exactly the columns of Theta_K.  The kernels tabulate (ci - 16, cj - 16,
-// s - 1, log2 s) per row and level difference in LDS once, so a decode is one
-// LDS read and a few masks and shifts.  Entries outside this range are kept
-// per row in an escape list (16-bit value, int32 column) read after the
-// packed words.
+// Column code: the band-relative 16-bit code of codes.hpp.  The kernels keep
+// the row's two centre numerators in registers and decode each word with
+// integer shifts, adds and masks.  Entries whose column does not fit the code
+// are kept per row in an escape list (16-bit value, int32 column) read after
+// the packed words.
 //
 // Rows are padded to whole groups of 4 words (value 0).  Kernels: G lanes per
 // row; each lane loads two 16-byte groups of 4 words per step before its
@@ -34,6 +22,7 @@
 #include <type_traits>
 #include <vector>
 
+#include "codes.hpp"
 #include "common.hpp"
 
 namespace wdb {
@@ -41,82 +30,6 @@ namespace wdb {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kDOff = 16;  // displacements in [-16, 15]
-constexpr int kLMax = 3;
-// Padding word of a partial step: value 0, column = a valid coefficient (a
-// detail subband of the row's own level, which every level has).
-constexpr uint32_t kPadCode = (static_cast<uint32_t>(kLMax) << 13) | (1u << 11) | (kDOff << 5) | kDOff;
-
-struct Geo {
-  int logn, J, L1;  // log2 of the image side, levels, filter length - 1
-};
-
-struct Pos {
-  int level, orient, i, j;  // orient 0..2: details (0,1), (1,0), (1,1); 3: approximation
-};
-
-__host__ __device__ inline int floor_log2(uint64_t v) { return 63 - __builtin_clzll(v); }
-
-// Subband position of canonical index r.  Level l details of side s = n >> l
-// sit at offsets s^2, 2 s^2, 3 s^2; the approximation of side n >> J at 0.
-__host__ __device__ inline Pos pos_of(const Geo& g, int64_t r) {
-  const int lsJ = g.logn - g.J;
-  if (r < (int64_t{1} << (2 * lsJ)))
-    return Pos{g.J, 3, static_cast<int>(r >> lsJ), static_cast<int>(r & ((int64_t{1} << lsJ) - 1))};
-  const int ls = floor_log2(static_cast<uint64_t>(r)) >> 1;
-  const int o = static_cast<int>(r >> (2 * ls)) - 1;
-  const int64_t p = r - (static_cast<int64_t>(o) + 1) * (int64_t{1} << (2 * ls));
-  return Pos{g.logn - ls, o, static_cast<int>(p >> ls), static_cast<int>(p & ((int64_t{1} << ls) - 1))};
-}
-
-// Index of the subband (canonical order: approximation, then per level J..1
-// the three detail orientations).
-__host__ __device__ inline int band_index(const Geo& g, int level, int orient) {
-  return orient == 3 ? 0 : 1 + 3 * (g.J - level) + orient;
-}
-
-// Point of level lb whose atom is centred nearest to the atom at index i of
-// level la (atoms of level l at index i are centred at 2^l i + L1 (2^l - 1) / 2),
-// not yet reduced modulo the side.  With P = (i << (la + 1)) + L1 2^la this is
-// (P + (1 - L1) 2^lb) >> (lb + 1).
-__host__ __device__ inline int centre_at(const Geo& g, int i, int la, int lb) {
-  return ((i << (la + 1)) + g.L1 * ((1 << la) - (1 << lb)) + (1 << lb)) >> (lb + 1);
-}
-
-// Decode table entry of a row for one level difference: (ci - 16, cj - 16,
-// s - 1, log2 s) of the column level lb (all zero when lb is not a level).
-__host__ __device__ inline int4 decode_entry(const Geo& g, const Pos& p, int dL) {
-  const int lb = p.level + dL;
-  if (lb < 1 || lb > g.J) return make_int4(0, 0, 0, 0);
-  const int ls = g.logn - lb;
-  return make_int4(centre_at(g, p.i, p.level, lb) - kDOff, centre_at(g, p.j, p.level, lb) - kDOff, (1 << ls) - 1, ls);
-}
-
-__host__ __device__ inline int decode_with(const int4& t, uint32_t code) {
-  const int q = static_cast<int>((code >> 11) & 3u);
-  const int ib = (t.x + static_cast<int>((code >> 5) & 31u)) & t.z;
-  const int jb = (t.y + static_cast<int>(code & 31u)) & t.z;
-  return (q << (2 * t.w)) + (ib << t.w) + jb;
-}
-
-__host__ __device__ inline int decode_col(const Geo& g, const Pos& p, uint32_t code) {
-  return decode_with(decode_entry(g, p, static_cast<int>((code >> 13) & 7u) - kLMax), code);
-}
-
-// Code of column `col` for row position p, or -1 if it does not fit.
-__host__ __device__ inline int encode_col(const Geo& g, const Pos& p, int64_t col) {
-  const Pos q = pos_of(g, col);
-  const int dL = q.level - p.level;
-  if (dL < -kLMax || dL > kLMax) return -1;
-  const int ls = g.logn - q.level;
-  const int s = 1 << ls, m = s - 1, h = s >> 1;
-  const int di = ((q.i - centre_at(g, p.i, p.level, q.level) + h) & m) - h;
-  const int dj = ((q.j - centre_at(g, p.j, p.level, q.level) + h) & m) - h;
-  if (di < -kDOff || di >= kDOff || dj < -kDOff || dj >= kDOff) return -1;
-  const int slot = q.orient == 3 ? 0 : q.orient + 1;
-  return ((dL + kLMax) << 13) | (slot << 11) | ((di + kDOff) << 5) | (dj + kDOff);
-}
-
 __device__ __forceinline__ uint16_t q_bf16(float f) {
   uint32_t b = __float_as_uint(f);
   b += 0x7FFFu + ((b >> 16) & 1u);
@@ -198,25 +111,13 @@ struct PackedView {
 
 PackedView pview(const Packed& m) { return PackedView{m.meta, m.word, m.ev, m.ec, m.nrows}; }
 
-// The G lanes of each row first fill the row's decode table (7 level
-// differences) in LDS; `tab` holds kBlock / G rows of 8 entries.
-template <int G>
-__device__ __forceinline__ void fill_table(const Geo& g, int64_t row, int64_t nrows, int gl, int4 (*tab)[8]) {
-  const int lr = threadIdx.x / G;
-  if (row < nrows) {
-    const Pos p = pos_of(g, row);
-    for (int d = gl; d < 2 * kLMax + 1; d += G) tab[lr][d] = decode_entry(g, p, d - kLMax);
-  }
-  __syncthreads();
-}
-
 template <int G, int FMT>
-__device__ __forceinline__ float packed_dot(const PackedView& P, int64_t row, int gl, const int4 (*tab)[8],
+__device__ __forceinline__ float packed_dot(const PackedView& P, const Geo& g, int64_t row, int gl,
                                             const float* __restrict__ x) {
   constexpr int U = 2;
   float acc = 0.f;
   if (row < P.nrows) {
-    const int4* __restrict__ rt = tab[threadIdx.x / G];
+    const RowCode rc = row_code(g, pos_of(g, row));
     const int2 m0 = P.meta[row], m1 = P.meta[row + 1];
     const uint4* __restrict__ w4 = reinterpret_cast<const uint4*>(P.word);
     const int end = m1.x >> 2;
@@ -229,8 +130,7 @@ __device__ __forceinline__ float packed_dot(const PackedView& P, int64_t row, in
         const uint32_t q[4] = {e[t].x, e[t].y, e[t].z, e[t].w};
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const int4 te = rt[(q[u] >> 13) & 7u];
-          acc = fmaf(dq<FMT>(q[u] >> 16), x[decode_with(te, q[u])], acc);
+          acc = fmaf(dq<FMT>(q[u] >> 16), x[decode_col(g, rc, q[u])], acc);
         }
       }
     }
@@ -247,11 +147,9 @@ __global__ __launch_bounds__(kBlock) void k_res_pk(PackedView P, Geo g, const fl
                                                    const float* __restrict__ y, const float* __restrict__ b,
                                                    float* __restrict__ r, int* __restrict__ kdev, int scale_out) {
   if (kdev && blockIdx.x == 0 && threadIdx.x == 0) *kdev += 1;
-  __shared__ int4 tab[kBlock / G][8];
   const int64_t row = static_cast<int64_t>(blockIdx.x) * (kBlock / G) + threadIdx.x / G;
   const int gl = threadIdx.x % G;
-  fill_table<G>(g, row, P.nrows, gl, tab);
-  const float acc = packed_dot<G, FMT>(P, row, gl, tab, y);
+  const float acc = packed_dot<G, FMT>(P, g, row, gl, y);
   if (gl != 0 || row >= P.nrows) return;
   const float w = wrow[row];
   const float rr = b ? w * acc - b[row] : w * acc;
@@ -264,11 +162,9 @@ __global__ __launch_bounds__(kBlock) void k_prox_pk(PackedView P, Geo g, const f
                                                     float* __restrict__ x, float* __restrict__ y, float tau,
                                                     float thr, const int* __restrict__ kdev,
                                                     const float* __restrict__ pinv, const float* __restrict__ tw) {
-  __shared__ int4 tab[kBlock / G][8];
   const int64_t row = static_cast<int64_t>(blockIdx.x) * (kBlock / G) + threadIdx.x / G;
   const int gl = threadIdx.x % G;
-  fill_table<G>(g, row, P.nrows, gl, tab);
-  const float gr = packed_dot<G, FMT>(P, row, gl, tab, rs);
+  const float gr = packed_dot<G, FMT>(P, g, row, gl, rs);
   if (gl != 0 || row >= P.nrows) return;
   float beta = 0.0f;  // no counter: no extrapolation (ISTA)
   if (kdev) {
@@ -284,10 +180,6 @@ __global__ __launch_bounds__(kBlock) void k_prox_pk(PackedView P, Geo g, const f
   y[row] = xn + beta * (xn - xo);
 }
 
-Geo geo_of(const wdb_theta* th) {
-  return Geo{floor_log2(static_cast<uint64_t>(th->n)), th->levels,
-             static_cast<int>(make_filter(th->wavelet).h.size()) - 1};
-}
 
 dim3 row_grid(int64_t nrows, int G) { return dim3(static_cast<unsigned>((nrows + kBlock / G - 1) / (kBlock / G))); }
 

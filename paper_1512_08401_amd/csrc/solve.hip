@@ -360,13 +360,15 @@ void launch_prox_csr(const CsrView& At, const float* r, float* x, float* y, floa
 
 int kernel_group(const wdb_theta* th) {
   const int G = th->spmv_group >= 0 ? th->spmv_group : spmv_group();
-  return (G == kStencil && !th->st.seg) ? 0 : G;
+  if (G == kStencil && !th->st.seg) return 0;
+  if (G == kTiled && !th->tA.desc) return 0;
+  return G;
 }
 
 // Lanes per row of the float64 CSR passes (the stencil layout checks on CSR).
 int check_group(const wdb_theta* th) {
   const int G = kernel_group(th);
-  return G == kStencil ? 4 : G;
+  return (G == kStencil || G == kTiled) ? 4 : G;
 }
 
 // r = A y - b with the kernel family G (0: sliced ELL; else vector CSR, G lanes per row).
@@ -848,6 +850,12 @@ void launch_iteration(wdb_theta* th, float* x, bool pre, bool ista, float tau, f
   if (th->valtype == WDB_VAL_BF16) return launch_iteration_q<WDB_VAL_BF16>(th, x, pre, kp, tau, thr, s);
   if (th->valtype == WDB_VAL_F16) return launch_iteration_q<WDB_VAL_F16>(th, x, pre, kp, tau, thr, s);
   const int G = kernel_group(th);
+  if (G == kTiled) {
+    launch_res_tiled(th, false, th->ws_y, th->ws_x0, th->ws_r, th->ws_k, s);
+    launch_prox_tiled(th, th->ws_r, x, th->ws_y, tau, thr, 0.0f, kp, pre ? th->pinv : nullptr,
+                      threshold_weights(th, pre), s);
+    return;
+  }
   if (G == kStencil) {
     launch_res_stencil(th, false, th->ws_y, th->ws_x0, th->ws_r, th->ws_k, s);
     launch_prox_stencil(th, th->ws_r, x, th->ws_y, tau, thr, 0.0f, kp, pre ? th->pinv : nullptr,
@@ -1047,7 +1055,9 @@ wdb_status wdb_theta_apply(wdb_theta* th, int32_t transpose, const float* x, con
   }
   const int G = wdb::kernel_group(th);
   for (int i = 0; i < repeat; ++i) {
-    if (G == wdb::kStencil)
+    if (G == wdb::kTiled)
+      wdb::launch_res_tiled(th, transpose != 0, x, b, y, nullptr, s);
+    else if (G == wdb::kStencil)
       wdb::launch_res_stencil(th, transpose != 0, x, b, y, nullptr, s);
     else
       wdb::launch_res(G, transpose ? th->At : th->A, transpose ? th->cAt : th->cA, x, b, y, nullptr, s);
@@ -1065,7 +1075,10 @@ wdb_status wdb_prox_step(wdb_theta* th, const float* r, float* x, float* y, floa
   WDB_HIP(hipSetDevice(th->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
   const float thr = tau * lambda;
-  if (wdb::kernel_group(th) == wdb::kStencil)
+  if (wdb::kernel_group(th) == wdb::kTiled)
+    wdb::launch_prox_tiled(th, r, x, y, tau, thr, beta, nullptr, use_precond ? th->pinv : nullptr,
+                           wdb::threshold_weights(th, use_precond != 0), s);
+  else if (wdb::kernel_group(th) == wdb::kStencil)
     wdb::launch_prox_stencil(th, r, x, y, tau, thr, beta, nullptr, use_precond ? th->pinv : nullptr,
                              wdb::threshold_weights(th, use_precond != 0), s);
   else

@@ -1,0 +1,388 @@
+// Tiled pattern storage of Theta_K and Theta_K^T for the float32 iteration.
+//
+// Rows are grouped in tiles of up to 64 coefficients of one subband: an 8 x 8
+// block of positions when the subband's side is at least 8, else the whole
+// subband.  The blur field varies slowly in space, so neighbouring
+// coefficients of one subband keep entries at nearly the same band-relative
+// displacements (the codes of codes.hpp).  A tile stores the sorted union of
+// its rows' codes once, and one float32 value per (code, row): zero where that
+// row did not keep the entry.  No column index is stored.
+//
+// One wavefront covers a tile's rows (lane t = row t).  For each code every
+// lane decodes its own column with a few integer operations on the row's
+// centre numerators, so the x loads of one instruction fall on 8 runs of 8
+// consecutive coefficients (column level = row level), on repeated
+// coefficients (coarser columns) or on a comb of stride 2^k (finer columns),
+// instead of 64 unrelated addresses as in a row-wise CSR product.
+//
+// Layout per matrix: per tile an int4 {first pattern, end pattern (both
+// multiples of 4), first row, log2 side | flags}; codes as uint32 in groups
+// of 4 (padded with a code of value 0); values as [group][lane][4] float32 so
+// that a lane loads one 16-byte vector per group of 4 codes.  The groups of a
+// tile are dealt round-robin to the W wavefronts of its block and the W
+// partial sums are added in LDS in wavefront order (deterministic).  Entries
+// whose code does not fit (displacement beyond 16 or level gap beyond 3) go to
+// a per-row escape list read by the first wavefront.
+#include <algorithm>
+#include <exception>
+#include <thread>
+#include <tuple>
+#include <type_traits>
+#include <vector>
+
+#include "codes.hpp"
+#include "common.hpp"
+
+namespace wdb {
+
+namespace {
+
+constexpr int kSmall = 1 << 8;   // flag: tile = a whole subband of side < 8, rows first + t for t < count
+constexpr int kHasEsc = 1 << 30; // flag: some row of the tile has escape entries
+
+struct TiledView {
+  const int4* __restrict__ desc;
+  const uint4* __restrict__ code;
+  const float4* __restrict__ val;
+  const int* __restrict__ erp;
+  const int* __restrict__ ec;
+  const float* __restrict__ ev;
+};
+
+TiledView tview(const Tiled& t) {
+  return TiledView{reinterpret_cast<const int4*>(t.desc), reinterpret_cast<const uint4*>(t.code),
+                   reinterpret_cast<const float4*>(t.val), t.erp, t.ec, t.ev};
+}
+
+// Row of lane t of a tile, or -1 for an idle lane of a small subband.
+__host__ __device__ inline int tile_row(const int4& d, int t) {
+  if (d.w & kSmall) return t < ((d.w >> 16) & 0x7F) ? d.z + t : -1;
+  const int ls = d.w & 0xFF;
+  return d.z + ((t >> 3) << ls) + (t & 7);
+}
+
+// Dot product of the lane's row with x, summed over the W wavefronts of the
+// block; the result is complete in wavefront 0.
+template <int W>
+__device__ __forceinline__ float tile_dot(const TiledView& T, const Geo& g, const int4& d, int row, int lane,
+                                          int wv, const float* __restrict__ x) {
+  __shared__ float part[W > 1 ? W : 1][64];
+  const RowCode rc = row_code(g, pos_of(g, row >= 0 ? row : d.z));
+  constexpr int U = 2;
+  float acc = 0.f;
+  const int g1 = d.y >> 2;
+  for (int k = (d.x >> 2) + wv; k < g1; k += W * U) {
+    uint4 c[U];
+    float4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool ok = k + u * W < g1;
+      c[u] = ok ? T.code[k + u * W] : make_uint4(kPadCode, kPadCode, kPadCode, kPadCode);
+      v[u] = ok ? T.val[static_cast<int64_t>(k + u * W) * 64 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      acc = fmaf(v[u].x, x[decode_col(g, rc, c[u].x)], acc);
+      acc = fmaf(v[u].y, x[decode_col(g, rc, c[u].y)], acc);
+      acc = fmaf(v[u].z, x[decode_col(g, rc, c[u].z)], acc);
+      acc = fmaf(v[u].w, x[decode_col(g, rc, c[u].w)], acc);
+    }
+  }
+  if constexpr (W > 1) {
+    part[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0) {
+#pragma unroll
+      for (int w = 1; w < W; ++w) acc += part[w][lane];
+    }
+  }
+  if (wv == 0 && row >= 0 && (d.w & kHasEsc))
+    for (int k = T.erp[row]; k < T.erp[row + 1]; ++k) acc = fmaf(T.ev[k], x[T.ec[k]], acc);
+  return acc;
+}
+
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_res_tl(TiledView T, Geo g, const float* __restrict__ y,
+                                                   const float* __restrict__ b, float* __restrict__ r,
+                                                   int* __restrict__ kdev) {
+  if (kdev && blockIdx.x == 0 && threadIdx.x == 0) *kdev += 1;
+  const int4 d = T.desc[blockIdx.x];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int row = tile_row(d, lane);
+  const float acc = tile_dot<W>(T, g, d, row, lane, wv, y);
+  if (wv == 0 && row >= 0) r[row] = b ? acc - b[row] : acc;
+}
+
+template <int W, bool PRE>
+__global__ __launch_bounds__(64 * W) void k_prox_tl(TiledView T, Geo g, const float* __restrict__ r,
+                                                    float* __restrict__ x, float* __restrict__ y, float tau,
+                                                    float thr, float beta, const int* __restrict__ kdev,
+                                                    const float* __restrict__ pinv, const float* __restrict__ tw) {
+  const int4 d = T.desc[blockIdx.x];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int row = tile_row(d, lane);
+  const float gr = tile_dot<W>(T, g, d, row, lane, wv, r);
+  if (wv != 0 || row < 0) return;
+  if (kdev) {
+    const int k = *kdev;
+    beta = static_cast<float>((static_cast<double>(k) - 1.0) / (static_cast<double>(k) + 2.0));
+  }
+  const float pi = PRE ? pinv[row] : 1.0f;
+  const float z = y[row] - (tau * pi) * gr;
+  const float t = thr * (tw ? tw[row] : pi);
+  const float xn = copysignf(fmaxf(fabsf(z) - t, 0.0f), z);
+  const float xo = x[row];
+  x[row] = xn;
+  y[row] = xn + beta * (xn - xo);
+}
+
+template <typename F>
+void with_waves(int W, F&& f) {
+  switch (W) {
+    case 1: f(std::integral_constant<int, 1>{}); return;
+    case 2: f(std::integral_constant<int, 2>{}); return;
+    case 4: f(std::integral_constant<int, 4>{}); return;
+    case 8: f(std::integral_constant<int, 8>{}); return;
+    default: fail(WDB_ERR_ARG, "unsupported wavefronts per tile %d (1, 2, 4 or 8)", W);
+  }
+}
+
+// Tiles in canonical band order: 8 x 8 position blocks of subbands of side
+// >= 8 (row-major over blocks), one tile per smaller subband; desc.x and
+// desc.y are filled by the encoder.
+std::vector<int4> tile_list(const Geo& g) {
+  std::vector<int4> tiles;
+  for (int b = 0; b <= 3 * g.J; ++b) {
+    const int level = b == 0 ? g.J : g.J - (b - 1) / 3;
+    const int o = b == 0 ? 3 : (b - 1) % 3;
+    const int ls = g.logn - level, s = 1 << ls;
+    const int base = o == 3 ? 0 : (o + 1) << (2 * ls);
+    if (s >= 8) {
+      for (int bi = 0; bi < s / 8; ++bi)
+        for (int bj = 0; bj < s / 8; ++bj) tiles.push_back(make_int4(0, 0, base + ((8 * bi) << ls) + 8 * bj, ls));
+    } else {
+      tiles.push_back(make_int4(0, 0, base, ls | kSmall | ((s * s) << 16)));
+    }
+  }
+  return tiles;
+}
+
+struct TileOut {
+  std::vector<int4> desc;
+  std::vector<uint32_t> code;
+  std::vector<float> val;
+  std::vector<int32_t> erow, ecol;
+  std::vector<float> eval;
+};
+
+// Encode the tiles [t0, t1) of the tile list into `o` (pattern indices local
+// to `o`; the caller rebases them).
+void encode_tiles(const Geo& g, const std::vector<int4>& tiles, size_t t0, size_t t1,
+                  const std::vector<int64_t>& rp, const std::vector<int32_t>& col, const std::vector<float>& val,
+                  TileOut& o) {
+  std::vector<std::pair<uint32_t, int>> ent;  // (code, lane) per kept entry of the tile
+  std::vector<float> ent_v;
+  std::vector<uint32_t> u;
+  for (size_t ti = t0; ti < t1; ++ti) {
+    int4 d = tiles[ti];
+    ent.clear();
+    ent_v.clear();
+    bool esc = false;
+    for (int t = 0; t < 64; ++t) {
+      const int row = tile_row(d, t);
+      if (row < 0) continue;
+      const Pos p = pos_of(g, row);
+      for (int64_t k = rp[row]; k < rp[row + 1]; ++k) {
+        if (val[k] == 0.0f) continue;  // padding of the float32 copy
+        const int c = encode_col(g, p, col[k]);
+        if (c < 0) {
+          o.erow.push_back(row);
+          o.ecol.push_back(col[k]);
+          o.eval.push_back(val[k]);
+          esc = true;
+        } else {
+          ent.emplace_back(static_cast<uint32_t>(c), t);
+          ent_v.push_back(val[k]);
+        }
+      }
+    }
+    u.clear();
+    for (const auto& e : ent) u.push_back(e.first);
+    std::sort(u.begin(), u.end());
+    u.erase(std::unique(u.begin(), u.end()), u.end());
+    const size_t npat = u.size();
+    while (u.size() % 4) u.push_back(kPadCode);
+    const int pb = static_cast<int>(o.code.size());
+    o.code.insert(o.code.end(), u.begin(), u.end());
+    o.val.resize(o.val.size() + u.size() * 64, 0.0f);
+    for (size_t e = 0; e < ent.size(); ++e) {
+      const int p = static_cast<int>(std::lower_bound(u.begin(), u.begin() + npat, ent[e].first) - u.begin());
+      const int64_t q = pb + p;
+      o.val[((q >> 2) * 64 + ent[e].second) * 4 + (q & 3)] = ent_v[e];
+    }
+    d.x = pb;
+    d.y = pb + static_cast<int>(u.size());
+    if (esc) d.w |= kHasEsc;
+    o.desc.push_back(d);
+  }
+}
+
+void build_one(const wdb_theta* th, const Csr32& src, Tiled* out) {
+  const Geo g = geo_of(th);
+  const int64_t N = src.nrows;
+  std::vector<int64_t> rp(N + 1);
+  std::vector<int32_t> col(src.stored);
+  std::vector<float> val(src.stored);
+  WDB_HIP(hipMemcpy(rp.data(), src.rowptr, (N + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+  if (src.stored) {
+    WDB_HIP(hipMemcpy(col.data(), src.col, src.stored * sizeof(int32_t), hipMemcpyDeviceToHost));
+    WDB_HIP(hipMemcpy(val.data(), src.val, src.stored * sizeof(float), hipMemcpyDeviceToHost));
+  }
+  const std::vector<int4> tiles = tile_list(g);
+  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const size_t nt = tiles.size(), parts = std::min<size_t>(hw, std::max<size_t>(1, nt / 64));
+  std::vector<TileOut> res(parts);
+  std::vector<std::thread> pool;
+  std::vector<std::exception_ptr> errs(parts);
+  for (size_t p = 0; p < parts; ++p)
+    pool.emplace_back([&, p]() {
+      try {
+        encode_tiles(g, tiles, nt * p / parts, nt * (p + 1) / parts, rp, col, val, res[p]);
+      } catch (...) {
+        errs[p] = std::current_exception();
+      }
+    });
+  for (auto& t : pool) t.join();
+  for (auto& e : errs)
+    if (e) std::rethrow_exception(e);
+  std::vector<int4> desc;
+  std::vector<uint32_t> code;
+  int64_t nval = 0;
+  for (auto& r : res) {
+    const int off = static_cast<int>(code.size());
+    WDB_REQUIRE(code.size() + r.code.size() < (size_t{1} << 31) / 64, WDB_ERR_ARG, "too many tile patterns");
+    for (int4 d : r.desc) desc.push_back(make_int4(d.x + off, d.y + off, d.z, d.w));
+    code.insert(code.end(), r.code.begin(), r.code.end());
+    nval += static_cast<int64_t>(r.val.size());
+  }
+  // Escapes as a CSR over rows.
+  std::vector<int32_t> erp(N + 1, 0);
+  int64_t nesc = 0;
+  for (auto& r : res) {
+    for (int32_t row : r.erow) ++erp[row + 1];
+    nesc += static_cast<int64_t>(r.erow.size());
+  }
+  for (int64_t i = 0; i < N; ++i) erp[i + 1] += erp[i];
+  std::vector<int32_t> ec(nesc);
+  std::vector<float> ev(nesc);
+  {
+    std::vector<int32_t> at(erp.begin(), erp.end() - 1);
+    std::vector<std::tuple<int32_t, int32_t, float>> all;
+    all.reserve(nesc);
+    for (auto& r : res)
+      for (size_t k = 0; k < r.erow.size(); ++k) all.emplace_back(r.erow[k], r.ecol[k], r.eval[k]);
+    std::sort(all.begin(), all.end(), [](const auto& a, const auto& b) {
+      return std::get<0>(a) != std::get<0>(b) ? std::get<0>(a) < std::get<0>(b) : std::get<1>(a) < std::get<1>(b);
+    });
+    for (const auto& e : all) {
+      ec[at[std::get<0>(e)]] = std::get<1>(e);
+      ev[at[std::get<0>(e)]++] = std::get<2>(e);
+    }
+  }
+  Tiled t;
+  try {
+    t.ntiles = static_cast<int64_t>(desc.size());
+    t.npat = static_cast<int64_t>(code.size());
+    t.nesc = nesc;
+    t.nkept = src.nnz;
+    WDB_HIP(hipMalloc(reinterpret_cast<void**>(&t.desc), std::max<size_t>(desc.size(), 1) * sizeof(int4)));
+    WDB_HIP(hipMalloc(reinterpret_cast<void**>(&t.code), std::max<size_t>(code.size(), 4) * sizeof(uint32_t)));
+    WDB_HIP(hipMalloc(reinterpret_cast<void**>(&t.val), std::max<int64_t>(nval, 4) * sizeof(float)));
+    WDB_HIP(hipMemcpy(t.desc, desc.data(), desc.size() * sizeof(int4), hipMemcpyHostToDevice));
+    if (!code.empty()) WDB_HIP(hipMemcpy(t.code, code.data(), code.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    int64_t at = 0;
+    for (auto& r : res) {
+      if (!r.val.empty())
+        WDB_HIP(hipMemcpy(t.val + at, r.val.data(), r.val.size() * sizeof(float), hipMemcpyHostToDevice));
+      at += static_cast<int64_t>(r.val.size());
+    }
+    if (nesc) {
+      WDB_HIP(hipMalloc(reinterpret_cast<void**>(&t.erp), (N + 1) * sizeof(int32_t)));
+      WDB_HIP(hipMalloc(reinterpret_cast<void**>(&t.ec), nesc * sizeof(int32_t)));
+      WDB_HIP(hipMalloc(reinterpret_cast<void**>(&t.ev), nesc * sizeof(float)));
+      WDB_HIP(hipMemcpy(t.erp, erp.data(), (N + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+      WDB_HIP(hipMemcpy(t.ec, ec.data(), nesc * sizeof(int32_t), hipMemcpyHostToDevice));
+      WDB_HIP(hipMemcpy(t.ev, ev.data(), nesc * sizeof(float), hipMemcpyHostToDevice));
+    }
+  } catch (...) {
+    t.free_all();
+    throw;
+  }
+  out->free_all();
+  *out = t;
+}
+
+}  // namespace
+
+void Tiled::free_all() {
+  for (void* p : {static_cast<void*>(desc), static_cast<void*>(code), static_cast<void*>(val),
+                  static_cast<void*>(erp), static_cast<void*>(ec), static_cast<void*>(ev)})
+    if (p) (void)hipFree(p);
+  desc = nullptr;
+  code = nullptr;
+  val = nullptr;
+  erp = ec = nullptr;
+  ev = nullptr;
+  ntiles = npat = nesc = nkept = 0;
+}
+
+bool tiled_supported(const wdb_theta* th) { return packed_supported(th); }
+
+void build_tiled(wdb_theta* th) {
+  WDB_REQUIRE(tiled_supported(th), WDB_ERR_ARG, "tiled storage needs subbands of side >= 1 at every level");
+  if (th->tA.desc && th->tAt.desc) return;
+  build_one(th, th->cA, &th->tA);
+  build_one(th, th->cAt, &th->tAt);
+}
+
+void launch_res_tiled(const wdb_theta* th, bool transpose, const float* y, const float* b, float* r, int* kdev,
+                      hipStream_t s) {
+  const Tiled& T = transpose ? th->tAt : th->tA;
+  WDB_REQUIRE(T.desc, WDB_ERR_ARG, "tiled storage not built");
+  const Geo g = geo_of(th);
+  with_waves(th->tile_waves, [&](auto Wc) {
+    constexpr int W = decltype(Wc)::value;
+    hipLaunchKernelGGL(k_res_tl<W>, dim3(static_cast<unsigned>(T.ntiles)), dim3(64 * W), 0, s, tview(T), g, y, b,
+                       r, kdev);
+  });
+}
+
+void launch_prox_tiled(const wdb_theta* th, const float* r, float* x, float* y, float tau, float thr, float beta,
+                       const int* kdev, const float* pinv, const float* tw, hipStream_t s) {
+  const Tiled& T = th->tAt;
+  WDB_REQUIRE(T.desc, WDB_ERR_ARG, "tiled storage not built");
+  const Geo g = geo_of(th);
+  with_waves(th->tile_waves, [&](auto Wc) {
+    constexpr int W = decltype(Wc)::value;
+    const dim3 grid(static_cast<unsigned>(T.ntiles)), block(64 * W);
+    if (pinv)
+      hipLaunchKernelGGL((k_prox_tl<W, true>), grid, block, 0, s, tview(T), g, r, x, y, tau, thr, beta, kdev, pinv,
+                         tw);
+    else
+      hipLaunchKernelGGL((k_prox_tl<W, false>), grid, block, 0, s, tview(T), g, r, x, y, tau, thr, beta, kdev,
+                         pinv, tw);
+  });
+}
+
+}  // namespace wdb
+
+extern "C" wdb_status wdb_set_tile_waves(wdb_theta* th, int32_t waves) {
+  WDB_API_BEGIN
+  WDB_REQUIRE(th, WDB_ERR_ARG, "null handle");
+  WDB_REQUIRE(waves == 1 || waves == 2 || waves == 4 || waves == 8, WDB_ERR_ARG,
+              "wavefronts per tile must be 1, 2, 4 or 8");
+  th->tile_waves = waves;
+  WDB_API_END
+}

@@ -49,7 +49,8 @@ class ThetaDesc(C.Structure):
                 ("lipschitz", C.c_double), ("threshold", C.c_double), ("lipschitz_p", C.c_double),
                 ("precond", C.c_int32), ("valtype", C.c_int32), ("slice", C.c_int32), ("group", C.c_int32),
                 ("group16", C.c_int32), ("escapes", C.c_int64), ("conv_build", C.c_int32),
-                ("l1_weights", C.c_int32), ("rule", C.c_int32), ("circulant", C.c_int64)]
+                ("l1_weights", C.c_int32), ("rule", C.c_int32), ("circulant", C.c_int64),
+                ("tile_waves", C.c_int32), ("tile_slots", C.c_int64)]
 
 
 class SolveOpts(C.Structure):
@@ -93,6 +94,7 @@ _SIGS = {
     "wdb_set_precision": [_vp, _i32],
     "wdb_set_kernel_layout": [_vp, _i32, _i32],
     "wdb_set_packed_group": [_vp, _i32],
+    "wdb_set_tile_waves": [_vp, _i32],
     "wdb_set_l1_weights": [_vp, _i32, _vp],
     "wdb_autotune": [_vp, C.c_char_p, _i32, C.POINTER(_i32), C.POINTER(_i32), _pd],
     "wdb_cnn_create": [_i32, _i32, _i32, C.c_uint64, C.POINTER(_vp)],
@@ -265,6 +267,10 @@ class Theta:
     def set_packed_group(self, group: int = 0):
         """Lanes per row of the packed 16-bit kernels (2/4/8/16; 0 = default)."""
         _check("wdb_set_packed_group", _lib.wdb_set_packed_group(self._h, int(group)))
+
+    def set_tile_waves(self, waves: int = 4):
+        """Wavefronts per tile of the tiled layout (group 3): 1, 2, 4 or 8."""
+        _check("wdb_set_tile_waves", _lib.wdb_set_tile_waves(self._h, int(waves)))
 
     def autotune(self, cache_path: str | None = None, reps: int = 20):
         """Pick the fastest iteration layout for this operator; returns (slice, group, us)."""
