@@ -105,7 +105,8 @@ typedef struct {
   int32_t slice;       /* sliced-ELL slice height of the iteration copies */
   int32_t group;       /* lanes per row of the vector-CSR kernels (0: sliced ELL; 1: circulant,
                           3: tiled pattern storage) */
-  int32_t group16;     /* lanes per row of the packed 16-bit kernels (0: not in use) */
+  int32_t group16;     /* lanes per row of the packed 16-bit kernels (0: not in use; 3: 16-bit
+                          tiled pattern storage) */
   int64_t escapes;     /* entries of Theta_K and Theta_K^T outside the packed column code */
   int32_t conv_build;  /* 1 if wdb_build_theta took the convolution fast path */
   int32_t l1_weights;  /* wdb_l1_weights kind in use */
@@ -114,6 +115,7 @@ typedef struct {
                           part of the cut's tie group that breaks the circulant pattern) */
   int32_t tile_waves;  /* wavefronts per tile of the tiled layout (group 3) */
   int64_t tile_slots;  /* stored values of the tiled copies of Theta_K and Theta_K^T (0: not built) */
+  int32_t tile_waves16; /* wavefronts per tile of the 16-bit tiled layout (group16 3) */
 } wdb_theta_desc;
 
 /* ---------------------------------------------------------------------------

@@ -123,6 +123,7 @@ wdb_status wdb_theta_info(const wdb_theta* th, wdb_theta_desc* out) {
   out->rule = th->rule;
   out->circulant = th->st.seg ? th->st.nextra : -1;
   out->tile_waves = th->tile_waves;
+  out->tile_waves16 = th->tile_waves16;
   out->tile_slots = 64 * (th->tA.npat + th->tAt.npat);
   WDB_API_END
 }
@@ -159,6 +160,8 @@ void wdb_theta_free(wdb_theta* th) {
   th->stT.free_all();
   th->tA.free_all();
   th->tAt.free_all();
+  th->qA.free_all();
+  th->qAt.free_all();
   if (th->l1w) (void)hipFree(th->l1w);
   if (th->l1w_pre) (void)hipFree(th->l1w_pre);
   wdb::free_workspace(th);

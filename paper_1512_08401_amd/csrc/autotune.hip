@@ -52,12 +52,14 @@ std::string cache_key(const wdb_theta* th) {
   return o.str();
 }
 
-// Lanes per row of the packed 16-bit kernels: the fastest of 2/4/8/16 for
-// the residual + proximal pair (cached under the operator's key and format).
+// Layout of the 16-bit iteration: the fastest residual + proximal pair among
+// the packed kernels with 2/4/8/16 lanes per row and the 16-bit tiled layout
+// with 1/2/4/8 wavefronts per tile (cached under the operator's key and
+// format).
 void tune_packed(wdb_theta* th, const char* cache_path, const std::string& key, int reps, hipStream_t s) {
   using namespace wdb;
   const std::string qkey = key + "-q" + std::to_string(th->valtype);
-  int bestG = 0;
+  int bestG = 0, bestW = 0;
   double best = 1e300;
   if (cache_path && *cache_path) {
     std::ifstream in(cache_path);
@@ -66,7 +68,8 @@ void tune_packed(wdb_theta* th, const char* cache_path, const std::string& key, 
     double us;
     while (in >> k >> C >> G >> us)
       if (k == qkey) {
-        bestG = G;
+        bestG = G % 100;
+        bestW = G / 100;
         best = us;
       }
   }
@@ -77,36 +80,48 @@ void tune_packed(wdb_theta* th, const char* cache_path, const std::string& key, 
     hipLaunchKernelGGL(k_fill, dim3((N + 255) / 256), dim3(256), 0, s, th->ws_img, N, 0.0f);
     hipLaunchKernelGGL(k_set_one, dim3(1), dim3(1), 0, s, th->ws_k);
     WDB_HIP(hipGetLastError());
+    // (lanes per row, 0) for the packed kernels; (3, wavefronts per tile) for the 16-bit tiled layout
+    std::vector<std::array<int, 2>> cands = {{2, 0}, {4, 0}, {8, 0}, {16, 0}};
+    if (tiled_supported(th)) {
+      build_tiled16(th);
+      for (int W : {1, 2, 4, 8}) cands.push_back({kTiled, W});
+    }
+    std::vector<double> t_min(cands.size(), 1e300);
     hipEvent_t e0, e1;
     WDB_HIP(hipEventCreate(&e0));
     WDB_HIP(hipEventCreate(&e1));
-    double t_min[4] = {1e300, 1e300, 1e300, 1e300};
-    const int groups[4] = {2, 4, 8, 16};
     try {
       for (int pass = 0; pass < 2; ++pass)
-      for (int gi = 0; gi < 4; ++gi) {
-        const int G = groups[gi];
-        auto pair = [&]() {
-          launch_res_packed(th, G, th->ws_y, th->ws_x0, th->ws_r, nullptr, 1, s);
-          launch_prox_packed(th, G, th->ws_r, th->ws_img, th->ws_y, 1e-3f, 1e-6f, th->ws_k, nullptr, nullptr, s);
-        };
-        for (int i = 0; i < 3; ++i) pair();
-        WDB_HIP(hipEventRecord(e0, s));
-        for (int i = 0; i < reps; ++i) pair();
-        WDB_HIP(hipEventRecord(e1, s));
-        WDB_HIP(hipEventSynchronize(e1));
-        float ms = 0.0f;
-        WDB_HIP(hipEventElapsedTime(&ms, e0, e1));
-        const double us = 1e3 * ms / reps;
-        if (std::getenv("WDB_LOG")) std::fprintf(stderr, "[wdb] autotune packed G=%d: %.2f us per iteration\n", G, us);
-        t_min[gi] = std::min(t_min[gi], us);
-      }
-      for (int gi = 0; gi < 4; ++gi)
-        if (t_min[gi] < best) {
-          best = t_min[gi];
-          bestG = groups[gi];
+        for (size_t ci = 0; ci < cands.size(); ++ci) {
+          const int G = cands[ci][0];
+          if (G == kTiled) th->tile_waves16 = cands[ci][1];
+          auto pair = [&]() {
+            if (G == kTiled) {
+              launch_res_tiled16(th, th->ws_y, th->ws_x0, th->ws_r, nullptr, 1, s);
+              launch_prox_tiled16(th, th->ws_r, th->ws_img, th->ws_y, 1e-3f, 1e-6f, th->ws_k, nullptr, nullptr, s);
+              return;
+            }
+            launch_res_packed(th, G, th->ws_y, th->ws_x0, th->ws_r, nullptr, 1, s);
+            launch_prox_packed(th, G, th->ws_r, th->ws_img, th->ws_y, 1e-3f, 1e-6f, th->ws_k, nullptr, nullptr, s);
+          };
+          for (int i = 0; i < 3; ++i) pair();
+          WDB_HIP(hipEventRecord(e0, s));
+          for (int i = 0; i < reps; ++i) pair();
+          WDB_HIP(hipEventRecord(e1, s));
+          WDB_HIP(hipEventSynchronize(e1));
+          float ms = 0.0f;
+          WDB_HIP(hipEventElapsedTime(&ms, e0, e1));
+          const double us = 1e3 * ms / reps;
+          if (std::getenv("WDB_LOG"))
+            std::fprintf(stderr, "[wdb] autotune packed G=%d W=%d: %.2f us per iteration\n", G, cands[ci][1], us);
+          t_min[ci] = std::min(t_min[ci], us);
         }
-
+      for (size_t ci = 0; ci < cands.size(); ++ci)
+        if (t_min[ci] < best) {
+          best = t_min[ci];
+          bestG = cands[ci][0];
+          bestW = cands[ci][1];
+        }
     } catch (...) {
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
@@ -116,10 +131,17 @@ void tune_packed(wdb_theta* th, const char* cache_path, const std::string& key, 
     (void)hipEventDestroy(e1);
     if (cache_path && *cache_path) {
       std::ofstream out(cache_path, std::ios::app);
-      out << qkey << " 0 " << bestG << " " << best << "\n";
+      out << qkey << " 0 " << bestG + 100 * bestW << " " << best << "\n";
     }
   }
   th->q_group = bestG;
+  if (bestG == kTiled) {
+    th->tile_waves16 = bestW;
+    build_tiled16(th);
+  } else {  // the 16-bit tiled copies are only kept when they are the layout in use
+    th->qA.free_all();
+    th->qAt.free_all();
+  }
 }
 
 }  // namespace

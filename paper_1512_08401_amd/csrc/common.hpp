@@ -203,7 +203,8 @@ struct Tiled {
   int64_t ntiles = 0, npat = 0, nesc = 0, nkept = 0;
   int* desc = nullptr;       // device, 4 * ntiles (int4 per tile)
   uint32_t* code = nullptr;  // device, npat
-  float* val = nullptr;      // device, 64 * npat
+  float* val = nullptr;      // device, 64 * npat (float32 copies)
+  uint16_t* val16 = nullptr; // device, 64 * npat (16-bit copies: groups of 8 codes, scaled values)
   int* erp = nullptr;        // device, nrows + 1
   int* ec = nullptr;         // device, nesc
   float* ev = nullptr;       // device, nesc
@@ -250,6 +251,9 @@ struct wdb_theta {
   wdb::Stencil st, stT; // circulant storage of Theta_K and Theta_K^T (convolution fast path only)
   wdb::Tiled tA, tAt;   // tiled pattern storage of Theta_K and Theta_K^T (built on demand)
   int tile_waves = 4;   // wavefronts per tile of the tiled kernels
+  wdb::Tiled qA, qAt;   // the same with 16-bit values (built on demand when valtype != 0)
+  int tile_waves16 = 4;
+  std::vector<float> qscale;  // host copy of the per-subband scales of the 16-bit values
   int q_group = 0;      // lanes per row of the packed kernels (0: default)
   bool has_L = false;
   double L = 0.0;
@@ -297,7 +301,12 @@ void build_stencils(wdb_theta* th, const std::vector<CircGen>& gens, const std::
 constexpr int kStencil = 1;  // kernel "group" value selecting the stencil kernels
 constexpr int kTiled = 3;    // kernel "group" value selecting the tiled pattern kernels
 bool tiled_supported(const wdb_theta* th);
-void build_tiled(wdb_theta* th);  // builds tA / tAt from cA / cAt if not built yet
+void build_tiled(wdb_theta* th);    // builds tA / tAt from cA / cAt if not built yet
+void build_tiled16(wdb_theta* th);  // builds qA / qAt (16-bit values, scales qscale) if not built yet
+void launch_res_tiled16(const wdb_theta* th, const float* y, const float* b, float* r, int* kdev, int scale_out,
+                        hipStream_t s);
+void launch_prox_tiled16(const wdb_theta* th, const float* rs, float* x, float* y, float tau, float thr,
+                         const int* kdev, const float* pinv, const float* tw, hipStream_t s);
 void launch_res_tiled(const wdb_theta* th, bool transpose, const float* y, const float* b, float* r, int* kdev,
                       hipStream_t s);
 void launch_prox_tiled(const wdb_theta* th, const float* r, float* x, float* y, float tau, float thr, float beta,

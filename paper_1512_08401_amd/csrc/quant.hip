@@ -101,6 +101,9 @@ extern "C" wdb_status wdb_set_precision(wdb_theta* th, int32_t valtype) {
   th->wrow = nullptr;
   th->pA.free_all();
   th->pAt.free_all();
+  th->qA.free_all();
+  th->qAt.free_all();
+  th->qscale.clear();
   th->valtype = WDB_VAL_F32;
   if (valtype == WDB_VAL_F32) return WDB_OK;
   const std::vector<Subband> lay = layout(th->n, th->levels);
@@ -144,5 +147,7 @@ extern "C" wdb_status wdb_set_precision(wdb_theta* th, int32_t valtype) {
   th->val16T = v16T.release();
   th->wrow = wrow.release();
   th->valtype = valtype;
+  th->qscale = ub;
+  if (th->q_group == kTiled) build_tiled16(th);  // the 16-bit tiled layout in use: rebuild for the new values
   WDB_API_END
 }

@@ -840,6 +840,12 @@ Check objective_check(wdb_theta* th, const float* x, const float* x0, double lam
 // gets no counter and extrapolates with beta = 0 (plain proximal gradient).
 void launch_iteration(wdb_theta* th, float* x, bool pre, bool ista, float tau, float thr, hipStream_t s) {
   const int* kp = ista ? nullptr : th->ws_k;
+  if (th->valtype != WDB_VAL_F32 && th->pA.word && packed_group(th) == kTiled) {
+    launch_res_tiled16(th, th->ws_y, th->ws_x0, th->ws_r, th->ws_k, 1, s);
+    launch_prox_tiled16(th, th->ws_r, x, th->ws_y, tau, thr, kp, pre ? th->pinv : nullptr,
+                        threshold_weights(th, pre), s);
+    return;
+  }
   if (th->valtype != WDB_VAL_F32 && th->pA.word && packed_group(th) > 0) {
     const int G = packed_group(th);
     launch_res_packed(th, G, th->ws_y, th->ws_x0, th->ws_r, th->ws_k, 1, s);
@@ -1035,6 +1041,11 @@ wdb_status wdb_theta_apply(wdb_theta* th, int32_t transpose, const float* x, con
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (th->valtype != WDB_VAL_F32) {
     WDB_REQUIRE(!transpose, WDB_ERR_ARG, "transposed apply is not available with 16-bit values");
+    if (th->pA.word && wdb::packed_group(th) == wdb::kTiled) {
+      for (int i = 0; i < repeat; ++i) wdb::launch_res_tiled16(th, x, b, y, nullptr, 0, s);
+      WDB_HIP(hipGetLastError());
+      return WDB_OK;
+    }
     if (th->pA.word && wdb::packed_group(th) > 0) {
       for (int i = 0; i < repeat; ++i) wdb::launch_res_packed(th, wdb::packed_group(th), x, b, y, nullptr, 0, s);
       WDB_HIP(hipGetLastError());

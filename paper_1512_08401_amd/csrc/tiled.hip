@@ -24,6 +24,7 @@
 // whose code does not fit (displacement beyond 16 or level gap beyond 3) go to
 // a per-row escape list read by the first wavefront.
 #include <algorithm>
+#include <cstring>
 #include <exception>
 #include <thread>
 #include <tuple>
@@ -43,7 +44,8 @@ constexpr int kHasEsc = 1 << 30; // flag: some row of the tile has escape entrie
 struct TiledView {
   const int4* __restrict__ desc;
   const uint4* __restrict__ code;
-  const float4* __restrict__ val;
+  const float4* __restrict__ val;   // float32 values, groups of 4 codes
+  const uint4* __restrict__ val16;  // 16-bit values, groups of 8 codes
   const int* __restrict__ erp;
   const int* __restrict__ ec;
   const float* __restrict__ ev;
@@ -51,7 +53,14 @@ struct TiledView {
 
 TiledView tview(const Tiled& t) {
   return TiledView{reinterpret_cast<const int4*>(t.desc), reinterpret_cast<const uint4*>(t.code),
-                   reinterpret_cast<const float4*>(t.val), t.erp, t.ec, t.ev};
+                   reinterpret_cast<const float4*>(t.val), reinterpret_cast<const uint4*>(t.val16), t.erp, t.ec,
+                   t.ev};
+}
+
+template <int FMT>
+__device__ __forceinline__ float dq16(uint32_t h) {
+  if constexpr (FMT == WDB_VAL_BF16) return __uint_as_float(h << 16);
+  else return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(h)));
 }
 
 // Row of lane t of a tile, or -1 for an idle lane of a small subband.
@@ -61,12 +70,30 @@ __host__ __device__ inline int tile_row(const int4& d, int t) {
   return d.z + ((t >> 3) << ls) + (t & 7);
 }
 
-// Dot product of the lane's row with x, summed over the W wavefronts of the
-// block; the result is complete in wavefront 0.
+// Partial sums of the W wavefronts added in wavefront order, then the
+// row's escape entries; the result is complete in wavefront 0.
+template <int W>
+__device__ __forceinline__ float tile_finish(const TiledView& T, const int4& d, int row, int lane, int wv, float acc,
+                                             const float* __restrict__ x) {
+  if constexpr (W > 1) {
+    __shared__ float part[W][64];
+    part[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0) {
+#pragma unroll
+      for (int w = 1; w < W; ++w) acc += part[w][lane];
+    }
+  }
+  if (wv == 0 && row >= 0 && (d.w & kHasEsc))
+    for (int k = T.erp[row]; k < T.erp[row + 1]; ++k) acc = fmaf(T.ev[k], x[T.ec[k]], acc);
+  return acc;
+}
+
+// Dot product of the lane's row with x over float32 values (groups of 4
+// codes, two groups in flight per wavefront).
 template <int W>
 __device__ __forceinline__ float tile_dot(const TiledView& T, const Geo& g, const int4& d, int row, int lane,
                                           int wv, const float* __restrict__ x) {
-  __shared__ float part[W > 1 ? W : 1][64];
   const RowCode rc = row_code(g, pos_of(g, row >= 0 ? row : d.z));
   constexpr int U = 2;
   float acc = 0.f;
@@ -88,17 +115,27 @@ __device__ __forceinline__ float tile_dot(const TiledView& T, const Geo& g, cons
       acc = fmaf(v[u].w, x[decode_col(g, rc, c[u].w)], acc);
     }
   }
-  if constexpr (W > 1) {
-    part[wv][lane] = acc;
-    __syncthreads();
-    if (wv == 0) {
+  return tile_finish<W>(T, d, row, lane, wv, acc, x);
+}
+
+// The same over 16-bit values: groups of 8 codes, one 16-byte vector of 8
+// values per lane and group.
+template <int W, int FMT>
+__device__ __forceinline__ float tile_dot16(const TiledView& T, const Geo& g, const int4& d, int row, int lane,
+                                            int wv, const float* __restrict__ x) {
+  const RowCode rc = row_code(g, pos_of(g, row >= 0 ? row : d.z));
+  float acc = 0.f;
+  const int g1 = d.y >> 3;
+  for (int k = (d.x >> 3) + wv; k < g1; k += W) {
+    const uint4 c0 = T.code[2 * k], c1 = T.code[2 * k + 1];
+    const uint4 v = T.val16[static_cast<int64_t>(k) * 64 + lane];
+    const uint32_t cs[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+    const uint32_t vs[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-      for (int w = 1; w < W; ++w) acc += part[w][lane];
-    }
+    for (int e = 0; e < 8; ++e)
+      acc = fmaf(dq16<FMT>((vs[e >> 1] >> (16 * (e & 1))) & 0xFFFFu), x[decode_col(g, rc, cs[e])], acc);
   }
-  if (wv == 0 && row >= 0 && (d.w & kHasEsc))
-    for (int k = T.erp[row]; k < T.erp[row + 1]; ++k) acc = fmaf(T.ev[k], x[T.ec[k]], acc);
-  return acc;
+  return tile_finish<W>(T, d, row, lane, wv, acc, x);
 }
 
 template <int W>
@@ -125,6 +162,51 @@ __global__ __launch_bounds__(64 * W) void k_prox_tl(TiledView T, Geo g, const fl
   const int row = tile_row(d, lane);
   const float gr = tile_dot<W>(T, g, d, row, lane, wv, r);
   if (wv != 0 || row < 0) return;
+  if (kdev) {
+    const int k = *kdev;
+    beta = static_cast<float>((static_cast<double>(k) - 1.0) / (static_cast<double>(k) + 2.0));
+  }
+  const float pi = PRE ? pinv[row] : 1.0f;
+  const float z = y[row] - (tau * pi) * gr;
+  const float t = thr * (tw ? tw[row] : pi);
+  const float xn = copysignf(fmaxf(fabsf(z) - t, 0.0f), z);
+  const float xo = x[row];
+  x[row] = xn;
+  y[row] = xn + beta * (xn - xo);
+}
+
+// 16-bit values scaled by a power of two u per scale block (row subband for
+// Theta_K, column subband for Theta_K^T): r = w (Q y) - b with w = 1 / u of
+// the row, stored times w when scale_out (the input of the transposed kernel).
+template <int W, int FMT>
+__global__ __launch_bounds__(64 * W) void k_res_tl16(TiledView T, Geo g, const float* __restrict__ wrow,
+                                                     const float* __restrict__ y, const float* __restrict__ b,
+                                                     float* __restrict__ r, int* __restrict__ kdev, int scale_out) {
+  if (kdev && blockIdx.x == 0 && threadIdx.x == 0) *kdev += 1;
+  const int4 d = T.desc[blockIdx.x];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int row = tile_row(d, lane);
+  const float acc = tile_dot16<W, FMT>(T, g, d, row, lane, wv, y);
+  if (wv != 0 || row < 0) return;
+  const float w = wrow[row];
+  const float rr = b ? w * acc - b[row] : w * acc;
+  r[row] = scale_out ? rr * w : rr;
+}
+
+// g = Q^T (w r); x_k = S(y - tau g / P); y = x_k + beta_k (x_k - x_{k-1}).
+template <int W, int FMT, bool PRE>
+__global__ __launch_bounds__(64 * W) void k_prox_tl16(TiledView T, Geo g, const float* __restrict__ rs,
+                                                      float* __restrict__ x, float* __restrict__ y, float tau,
+                                                      float thr, const int* __restrict__ kdev,
+                                                      const float* __restrict__ pinv, const float* __restrict__ tw) {
+  const int4 d = T.desc[blockIdx.x];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int row = tile_row(d, lane);
+  const float gr = tile_dot16<W, FMT>(T, g, d, row, lane, wv, rs);
+  if (wv != 0 || row < 0) return;
+  float beta = 0.0f;  // no counter: no extrapolation (ISTA)
   if (kdev) {
     const int k = *kdev;
     beta = static_cast<float>((static_cast<double>(k) - 1.0) / (static_cast<double>(k) + 2.0));
@@ -179,9 +261,13 @@ struct TileOut {
 
 // Encode the tiles [t0, t1) of the tile list into `o` (pattern indices local
 // to `o`; the caller rebases them).
+// grp: codes per value group (4 for float32, 8 for 16-bit values); ub: the
+// power-of-two scale of each subband (canonical order) that multiplies the
+// values, taken from the row's subband (by_col false) or the column's, or
+// null for no scaling.
 void encode_tiles(const Geo& g, const std::vector<int4>& tiles, size_t t0, size_t t1,
                   const std::vector<int64_t>& rp, const std::vector<int32_t>& col, const std::vector<float>& val,
-                  TileOut& o) {
+                  int grp, const std::vector<float>* ub, bool by_col, TileOut& o) {
   std::vector<std::pair<uint32_t, int>> ent;  // (code, lane) per kept entry of the tile
   std::vector<float> ent_v;
   std::vector<uint32_t> u;
@@ -194,17 +280,24 @@ void encode_tiles(const Geo& g, const std::vector<int4>& tiles, size_t t0, size_
       const int row = tile_row(d, t);
       if (row < 0) continue;
       const Pos p = pos_of(g, row);
+      const float urow = ub ? (*ub)[band_index(g, p.level, p.orient)] : 1.0f;
       for (int64_t k = rp[row]; k < rp[row + 1]; ++k) {
         if (val[k] == 0.0f) continue;  // padding of the float32 copy
+        float u = urow;
+        if (ub && by_col) {
+          const Pos q = pos_of(g, col[k]);
+          u = (*ub)[band_index(g, q.level, q.orient)];
+        }
+        const float v = val[k] * u;  // exact: u is a power of two
         const int c = encode_col(g, p, col[k]);
         if (c < 0) {
           o.erow.push_back(row);
           o.ecol.push_back(col[k]);
-          o.eval.push_back(val[k]);
+          o.eval.push_back(v);
           esc = true;
         } else {
           ent.emplace_back(static_cast<uint32_t>(c), t);
-          ent_v.push_back(val[k]);
+          ent_v.push_back(v);
         }
       }
     }
@@ -213,14 +306,14 @@ void encode_tiles(const Geo& g, const std::vector<int4>& tiles, size_t t0, size_
     std::sort(u.begin(), u.end());
     u.erase(std::unique(u.begin(), u.end()), u.end());
     const size_t npat = u.size();
-    while (u.size() % 4) u.push_back(kPadCode);
+    while (u.size() % grp) u.push_back(kPadCode);
     const int pb = static_cast<int>(o.code.size());
     o.code.insert(o.code.end(), u.begin(), u.end());
     o.val.resize(o.val.size() + u.size() * 64, 0.0f);
     for (size_t e = 0; e < ent.size(); ++e) {
       const int p = static_cast<int>(std::lower_bound(u.begin(), u.begin() + npat, ent[e].first) - u.begin());
       const int64_t q = pb + p;
-      o.val[((q >> 2) * 64 + ent[e].second) * 4 + (q & 3)] = ent_v[e];
+      o.val[((q / grp) * 64 + ent[e].second) * grp + (q % grp)] = ent_v[e];
     }
     d.x = pb;
     d.y = pb + static_cast<int>(u.size());
@@ -229,7 +322,36 @@ void encode_tiles(const Geo& g, const std::vector<int4>& tiles, size_t t0, size_
   }
 }
 
-void build_one(const wdb_theta* th, const Csr32& src, Tiled* out) {
+uint16_t round16(float f, int fmt) {
+  if (fmt == WDB_VAL_BF16) {
+    uint32_t b;
+    std::memcpy(&b, &f, 4);
+    b += 0x7FFFu + ((b >> 16) & 1u);  // round to nearest even
+    return static_cast<uint16_t>(b >> 16);
+  }
+  const _Float16 h = static_cast<_Float16>(f);
+  uint16_t r;
+  std::memcpy(&r, &h, 2);
+  return r;
+}
+
+float widen16(uint16_t h, int fmt) {
+  if (fmt == WDB_VAL_BF16) {
+    const uint32_t b = static_cast<uint32_t>(h) << 16;
+    float f;
+    std::memcpy(&f, &b, 4);
+    return f;
+  }
+  _Float16 v;
+  std::memcpy(&v, &h, 2);
+  return static_cast<float>(v);
+}
+
+// fmt: WDB_VAL_F32 (values as float32, groups of 4 codes) or a 16-bit format
+// (values times the scale of `ub`, rounded; groups of 8 codes).
+void build_one(const wdb_theta* th, const Csr32& src, Tiled* out, int fmt = WDB_VAL_F32,
+               const std::vector<float>* ub = nullptr, bool by_col = false) {
+  const int grp = fmt == WDB_VAL_F32 ? 4 : 8;
   const Geo g = geo_of(th);
   const int64_t N = src.nrows;
   std::vector<int64_t> rp(N + 1);
@@ -249,7 +371,7 @@ void build_one(const wdb_theta* th, const Csr32& src, Tiled* out) {
   for (size_t p = 0; p < parts; ++p)
     pool.emplace_back([&, p]() {
       try {
-        encode_tiles(g, tiles, nt * p / parts, nt * (p + 1) / parts, rp, col, val, res[p]);
+        encode_tiles(g, tiles, nt * p / parts, nt * (p + 1) / parts, rp, col, val, grp, ub, by_col, res[p]);
       } catch (...) {
         errs[p] = std::current_exception();
       }
@@ -288,7 +410,8 @@ void build_one(const wdb_theta* th, const Csr32& src, Tiled* out) {
     });
     for (const auto& e : all) {
       ec[at[std::get<0>(e)]] = std::get<1>(e);
-      ev[at[std::get<0>(e)]++] = std::get<2>(e);
+      const float v = std::get<2>(e);
+      ev[at[std::get<0>(e)]++] = fmt == WDB_VAL_F32 ? v : widen16(round16(v, fmt), fmt);
     }
   }
   Tiled t;
@@ -299,14 +422,25 @@ void build_one(const wdb_theta* th, const Csr32& src, Tiled* out) {
     t.nkept = src.nnz;
     WDB_HIP(hipMalloc(reinterpret_cast<void**>(&t.desc), std::max<size_t>(desc.size(), 1) * sizeof(int4)));
     WDB_HIP(hipMalloc(reinterpret_cast<void**>(&t.code), std::max<size_t>(code.size(), 4) * sizeof(uint32_t)));
-    WDB_HIP(hipMalloc(reinterpret_cast<void**>(&t.val), std::max<int64_t>(nval, 4) * sizeof(float)));
     WDB_HIP(hipMemcpy(t.desc, desc.data(), desc.size() * sizeof(int4), hipMemcpyHostToDevice));
     if (!code.empty()) WDB_HIP(hipMemcpy(t.code, code.data(), code.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
     int64_t at = 0;
-    for (auto& r : res) {
-      if (!r.val.empty())
-        WDB_HIP(hipMemcpy(t.val + at, r.val.data(), r.val.size() * sizeof(float), hipMemcpyHostToDevice));
-      at += static_cast<int64_t>(r.val.size());
+    if (fmt == WDB_VAL_F32) {
+      WDB_HIP(hipMalloc(reinterpret_cast<void**>(&t.val), std::max<int64_t>(nval, 4) * sizeof(float)));
+      for (auto& r : res) {
+        if (!r.val.empty())
+          WDB_HIP(hipMemcpy(t.val + at, r.val.data(), r.val.size() * sizeof(float), hipMemcpyHostToDevice));
+        at += static_cast<int64_t>(r.val.size());
+      }
+    } else {
+      WDB_HIP(hipMalloc(reinterpret_cast<void**>(&t.val16), std::max<int64_t>(nval, 8) * sizeof(uint16_t)));
+      std::vector<uint16_t> h;
+      for (auto& r : res) {
+        h.resize(r.val.size());
+        for (size_t i = 0; i < r.val.size(); ++i) h[i] = round16(r.val[i], fmt);
+        if (!h.empty()) WDB_HIP(hipMemcpy(t.val16 + at, h.data(), h.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+        at += static_cast<int64_t>(h.size());
+      }
     }
     if (nesc) {
       WDB_HIP(hipMalloc(reinterpret_cast<void**>(&t.erp), (N + 1) * sizeof(int32_t)));
@@ -328,11 +462,12 @@ void build_one(const wdb_theta* th, const Csr32& src, Tiled* out) {
 
 void Tiled::free_all() {
   for (void* p : {static_cast<void*>(desc), static_cast<void*>(code), static_cast<void*>(val),
-                  static_cast<void*>(erp), static_cast<void*>(ec), static_cast<void*>(ev)})
+                  static_cast<void*>(val16), static_cast<void*>(erp), static_cast<void*>(ec), static_cast<void*>(ev)})
     if (p) (void)hipFree(p);
   desc = nullptr;
   code = nullptr;
   val = nullptr;
+  val16 = nullptr;
   erp = ec = nullptr;
   ev = nullptr;
   ntiles = npat = nesc = nkept = 0;
@@ -345,6 +480,58 @@ void build_tiled(wdb_theta* th) {
   if (th->tA.desc && th->tAt.desc) return;
   build_one(th, th->cA, &th->tA);
   build_one(th, th->cAt, &th->tAt);
+}
+
+void build_tiled16(wdb_theta* th) {
+  WDB_REQUIRE(tiled_supported(th), WDB_ERR_ARG, "tiled storage needs subbands of side >= 1 at every level");
+  WDB_REQUIRE(th->valtype != WDB_VAL_F32 && !th->qscale.empty(), WDB_ERR_ARG,
+              "the 16-bit tiled layout needs 16-bit values (wdb_set_precision)");
+  if (th->qA.desc && th->qAt.desc) return;
+  build_one(th, th->cA, &th->qA, th->valtype, &th->qscale, false);
+  build_one(th, th->cAt, &th->qAt, th->valtype, &th->qscale, true);
+}
+
+void launch_res_tiled16(const wdb_theta* th, const float* y, const float* b, float* r, int* kdev, int scale_out,
+                        hipStream_t s) {
+  const Tiled& T = th->qA;
+  WDB_REQUIRE(T.desc && T.val16, WDB_ERR_ARG, "16-bit tiled storage not built");
+  const Geo g = geo_of(th);
+  with_waves(th->tile_waves16, [&](auto Wc) {
+    constexpr int W = decltype(Wc)::value;
+    const dim3 grid(static_cast<unsigned>(T.ntiles)), block(64 * W);
+    if (th->valtype == WDB_VAL_BF16)
+      hipLaunchKernelGGL((k_res_tl16<W, WDB_VAL_BF16>), grid, block, 0, s, tview(T), g, th->wrow, y, b, r, kdev,
+                         scale_out);
+    else
+      hipLaunchKernelGGL((k_res_tl16<W, WDB_VAL_F16>), grid, block, 0, s, tview(T), g, th->wrow, y, b, r, kdev,
+                         scale_out);
+  });
+}
+
+void launch_prox_tiled16(const wdb_theta* th, const float* rs, float* x, float* y, float tau, float thr,
+                         const int* kdev, const float* pinv, const float* tw, hipStream_t s) {
+  const Tiled& T = th->qAt;
+  WDB_REQUIRE(T.desc && T.val16, WDB_ERR_ARG, "16-bit tiled storage not built");
+  const Geo g = geo_of(th);
+  with_waves(th->tile_waves16, [&](auto Wc) {
+    constexpr int W = decltype(Wc)::value;
+    const dim3 grid(static_cast<unsigned>(T.ntiles)), block(64 * W);
+    if (th->valtype == WDB_VAL_BF16) {
+      if (pinv)
+        hipLaunchKernelGGL((k_prox_tl16<W, WDB_VAL_BF16, true>), grid, block, 0, s, tview(T), g, rs, x, y, tau, thr,
+                           kdev, pinv, tw);
+      else
+        hipLaunchKernelGGL((k_prox_tl16<W, WDB_VAL_BF16, false>), grid, block, 0, s, tview(T), g, rs, x, y, tau,
+                           thr, kdev, pinv, tw);
+    } else {
+      if (pinv)
+        hipLaunchKernelGGL((k_prox_tl16<W, WDB_VAL_F16, true>), grid, block, 0, s, tview(T), g, rs, x, y, tau, thr,
+                           kdev, pinv, tw);
+      else
+        hipLaunchKernelGGL((k_prox_tl16<W, WDB_VAL_F16, false>), grid, block, 0, s, tview(T), g, rs, x, y, tau,
+                           thr, kdev, pinv, tw);
+    }
+  });
 }
 
 void launch_res_tiled(const wdb_theta* th, bool transpose, const float* y, const float* b, float* r, int* kdev,
@@ -383,6 +570,7 @@ extern "C" wdb_status wdb_set_tile_waves(wdb_theta* th, int32_t waves) {
   WDB_REQUIRE(th, WDB_ERR_ARG, "null handle");
   WDB_REQUIRE(waves == 1 || waves == 2 || waves == 4 || waves == 8, WDB_ERR_ARG,
               "wavefronts per tile must be 1, 2, 4 or 8");
-  th->tile_waves = waves;
+  if (th->valtype == WDB_VAL_F32) th->tile_waves = waves;
+  else th->tile_waves16 = waves;
   WDB_API_END
 }

@@ -50,7 +50,7 @@ class ThetaDesc(C.Structure):
                 ("precond", C.c_int32), ("valtype", C.c_int32), ("slice", C.c_int32), ("group", C.c_int32),
                 ("group16", C.c_int32), ("escapes", C.c_int64), ("conv_build", C.c_int32),
                 ("l1_weights", C.c_int32), ("rule", C.c_int32), ("circulant", C.c_int64),
-                ("tile_waves", C.c_int32), ("tile_slots", C.c_int64)]
+                ("tile_waves", C.c_int32), ("tile_slots", C.c_int64), ("tile_waves16", C.c_int32)]
 
 
 class SolveOpts(C.Structure):

@@ -649,6 +649,49 @@ def test_packed_16bit_db4_matches_oracle(W, db4_64, fmt):
     _gate(Q, x0.astype(np.float64), lam32, host(xg), xo, fista.objective(Q, x0.astype(np.float64), lam32, xo))
 
 
+@pytest.mark.parametrize("fmt,waves", [("f16", 1), ("f16", 4), ("bf16", 2), ("bf16", 8)])
+def test_tiled_16bit_db4_matches_oracle(W, db4_64, fmt, waves):
+    """16-bit tiled layout (group16 3): products against the oracle's quantised
+    operator, Alg. 1 and Alg. 2 (per-scale P, scale weights) solves."""
+    from oracle import quant
+    A = db4_64["A"]
+    rp, cc, vv = theta.csr_arrays(A)
+    th = W.Theta.from_csr(64, "db4", 3, rp, cc, vv)
+    start = synth.power_start(4096, 5)
+    th.lipschitz(start)
+    th.set_precision(fmt)
+    th.set_packed_group(3)
+    th.set_tile_waves(waves)
+    info = th.info()
+    assert info["group16"] == 3 and info["tile_waves16"] == waves
+    Q = quant.quantize(A, 64, 3, fmt)
+    x = np.random.default_rng(18).standard_normal(4096).astype(np.float32)
+    b = np.random.default_rng(19).standard_normal(4096).astype(np.float32)
+    ref = Q @ x.astype(np.float64) - b
+    y = host(th.apply(dev(x), dev(b)))
+    assert np.max(np.abs(y - ref)) <= 1e-5 * np.max(np.abs(ref))
+    lam = 1e-3
+    lam32 = float(np.float32(lam))
+    x0 = db4_64["x0"].astype(np.float32)
+    A32 = sp.csr_matrix((A.data.astype(np.float32).astype(np.float64), A.indices, A.indptr), shape=A.shape)
+    xg, _ = th.solve_coeffs(dev(x0), lam, 150, check_every=50)
+    Lo, _ = lipschitz.lipschitz(A32, start)
+    xo, _, _ = fista.fista(Q, x0.astype(np.float64), lam32, 1.0 / Lo, 150)
+    _gate(Q, x0.astype(np.float64), lam32, host(xg), xo, fista.objective(Q, x0.astype(np.float64), lam32, xo))
+    th.set_precond("spai_scale", start=start)
+    th.set_l1_weights("scale")
+    assert th.info()["group16"] == 3
+    p = precond.spai_grouped(A32, precond.scale_groups(64, 3))
+    Lp, _ = lipschitz.lipschitz_precond(A32, p, start)
+    w = dwt.scale_index(64, 3).astype(np.float64)
+    xp, _ = th.solve_coeffs(dev(x0), lam, 150, check_every=50, precond=True)
+    xo, _, _ = fista.fista(Q, x0.astype(np.float64), lam32, 1.0 / Lp, 150, p=p, w=w)
+    Eo = fista.objective(Q, x0.astype(np.float64), lam32, xo, w=w)
+    Eg = fista.objective(Q, x0.astype(np.float64), lam32, host(xp), w=w)
+    assert abs(Eg - Eo) <= 1e-5 * Eo
+    assert np.linalg.norm(host(xp) - xo) <= 1e-4 * np.linalg.norm(xo)
+
+
 def test_packed_escapes_match_oracle(W):
     """Columns far from the row's position (random, seeded) do not fit the
     16-bit code and are read from the per-row escape lists (the level-1
@@ -856,6 +899,17 @@ def test_tiled_escapes_and_small_subbands_match_oracle(W):
     lam = float(np.float32(0.05))
     xo, _, _ = fista.fista(A32, x0.astype(np.float64), lam, 1.0 / Lo, 50)
     _gate(A32, x0.astype(np.float64), lam, host(xg), xo, fista.objective(A32, x0.astype(np.float64), lam, xo))
+    # the 16-bit tiled layout: escapes hold the same rounded, scaled values
+    from oracle import quant
+    th.set_precision("f16")
+    th.set_packed_group(3)
+    Q = quant.quantize(A, n, J, "f16")
+    y = host(th.apply(dev(x)))
+    ref = Q @ x.astype(np.float64)
+    assert np.max(np.abs(y - ref)) <= 1e-5 * np.max(np.abs(ref))
+    xq, _ = th.solve_coeffs(dev(x0), 0.05, 50, check_every=0)
+    xo, _, _ = fista.fista(Q, x0.astype(np.float64), lam, 1.0 / Lo, 50)
+    _gate(Q, x0.astype(np.float64), lam, host(xq), xo, fista.objective(Q, x0.astype(np.float64), lam, xo))
 
 
 def test_autotune_picks_a_layout_and_keeps_parity(W, p64, tmp_path):
