@@ -35,11 +35,11 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_label(layout, waves=4):
+def kernel_label(layout, waves=4, unroll=2):
     slice_h, group = layout
     if group == 3:
-        return (f"k_res_tl<{waves}>", f"r = Theta_K y - x0, float32 tiled pattern storage (8x8 coefficient tiles, "
-                f"{waves} wavefronts per tile)")
+        return (f"k_res_tl<{waves}, {unroll}>", f"r = Theta_K y - x0, float32 tiled pattern storage (8x8 coefficient "
+                f"tiles, {waves} wavefronts per tile, {unroll} groups of 4 codes in flight)")
     if group > 0:
         return f"k_res_csr<{group}>", f"r = Theta_K y - x0, float32 CSR, {group} lanes per row"
     return "k_res", f"r = Theta_K y - x0, float32 sliced-ELL, {slice_h} rows per slice"
@@ -225,7 +225,7 @@ def main():
     nnz = info["nnz"]
     alg_bytes = 8 * nnz + 12 * N          # values + indices once, y/x0 read once, r written once
     achieved = alg_bytes / (k_us * 1e-6) / 1e9
-    kname, kdesc = kernel_label(layout, info["tile_waves"])
+    kname, kdesc = kernel_label(layout, th.info()["tile_waves"], th.info()["tile_unroll"])
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": profiled_traffic(wl.name, kname, layout),

@@ -116,6 +116,8 @@ typedef struct {
   int32_t tile_waves;  /* wavefronts per tile of the tiled layout (group 3) */
   int64_t tile_slots;  /* stored values of the tiled copies of Theta_K and Theta_K^T (0: not built) */
   int32_t tile_waves16; /* wavefronts per tile of the 16-bit tiled layout (group16 3) */
+  int32_t tile_unroll;  /* groups of 4 codes in flight per wavefront, tiled layout */
+  int32_t tile_unroll16; /* groups of 8 codes in flight per wavefront, 16-bit tiled layout */
 } wdb_theta_desc;
 
 /* ---------------------------------------------------------------------------
@@ -251,11 +253,13 @@ wdb_status wdb_set_packed_group(wdb_theta* th, int32_t group);
  * its packed copy.  Synchronises.  Errors: WDB_ERR_ARG, _OOM, _HIP. */
 wdb_status wdb_set_kernel_layout(wdb_theta* th, int32_t slice, int32_t group);
 
-/* Wavefronts per tile of the tiled layout (1, 2, 4 or 8; default 4): the
- * codes of a tile are dealt round-robin to the wavefronts and their partial
- * sums added in wavefront order.  Changes only the summation order.  Errors:
- * WDB_ERR_ARG. */
-wdb_status wdb_set_tile_waves(wdb_theta* th, int32_t waves);
+/* Shape of the tiled kernels of the current value type (float32: layout 3;
+ * 16-bit: packed group 3): `waves` wavefronts per tile (1, 2, 4 or 8) share
+ * the tile's code groups round-robin and add their partial sums in
+ * wavefront order; each wavefront keeps `unroll` groups (1, 2 or 4; 0 = the
+ * default, 2 for float32 and 1 for 16-bit values) of loads in flight.
+ * Changes only the summation order.  Errors: WDB_ERR_ARG. */
+wdb_status wdb_set_tile_shape(wdb_theta* th, int32_t waves, int32_t unroll);
 
 /* Project autotuner: times the iteration kernel pair `reps` times for every
  * candidate layout (slices of 64/32/16/8 rows; vector CSR with 4/8/16 lanes)

@@ -124,6 +124,8 @@ wdb_status wdb_theta_info(const wdb_theta* th, wdb_theta_desc* out) {
   out->circulant = th->st.seg ? th->st.nextra : -1;
   out->tile_waves = th->tile_waves;
   out->tile_waves16 = th->tile_waves16;
+  out->tile_unroll = th->tile_unroll;
+  out->tile_unroll16 = th->tile_unroll16;
   out->tile_slots = 64 * (th->tA.npat + th->tAt.npat);
   WDB_API_END
 }

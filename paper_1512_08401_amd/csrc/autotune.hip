@@ -6,7 +6,7 @@
 // slice's rows are neighbouring coefficients whose gathers share cache lines;
 // shorter slices pad less), vector CSR with 2, 4, 8 or 16 lanes per row, the
 // circulant storage of convolution builds and the tiled pattern storage with
-// 1, 2, 4 or 8 wavefronts per tile -- and
+// 1, 2, 4 or 8 wavefronts per tile and 2 or 4 code groups in flight -- and
 // keeps the fastest in the handle (each candidate timed in two alternating
 // passes, its best pass counted, so that one slow pass from a clock or
 // cache transient does not decide).  Decisions can be cached in a text file
@@ -52,10 +52,14 @@ std::string cache_key(const wdb_theta* th) {
   return o.str();
 }
 
+// Shape code of the tiled kernels: W + 10 U (W wavefronts per tile, U code
+// groups in flight per wavefront).
+inline int shape_code(int W, int U) { return W + 10 * U; }
+
 // Layout of the 16-bit iteration: the fastest residual + proximal pair among
 // the packed kernels with 2/4/8/16 lanes per row and the 16-bit tiled layout
-// with 1/2/4/8 wavefronts per tile (cached under the operator's key and
-// format).
+// with 1/2/4/8 wavefronts per tile and 1/2 groups in flight (cached under the
+// operator's key and format).
 void tune_packed(wdb_theta* th, const char* cache_path, const std::string& key, int reps, hipStream_t s) {
   using namespace wdb;
   const std::string qkey = key + "-q" + std::to_string(th->valtype);
@@ -80,11 +84,12 @@ void tune_packed(wdb_theta* th, const char* cache_path, const std::string& key, 
     hipLaunchKernelGGL(k_fill, dim3((N + 255) / 256), dim3(256), 0, s, th->ws_img, N, 0.0f);
     hipLaunchKernelGGL(k_set_one, dim3(1), dim3(1), 0, s, th->ws_k);
     WDB_HIP(hipGetLastError());
-    // (lanes per row, 0) for the packed kernels; (3, wavefronts per tile) for the 16-bit tiled layout
+    // (lanes per row, 0) for the packed kernels; (3, shape code) for the 16-bit tiled layout
     std::vector<std::array<int, 2>> cands = {{2, 0}, {4, 0}, {8, 0}, {16, 0}};
     if (tiled_supported(th)) {
       build_tiled16(th);
-      for (int W : {1, 2, 4, 8}) cands.push_back({kTiled, W});
+      for (int W : {1, 2, 4, 8})
+        for (int U : {1, 2}) cands.push_back({kTiled, shape_code(W, U)});
     }
     std::vector<double> t_min(cands.size(), 1e300);
     hipEvent_t e0, e1;
@@ -94,7 +99,10 @@ void tune_packed(wdb_theta* th, const char* cache_path, const std::string& key, 
       for (int pass = 0; pass < 2; ++pass)
         for (size_t ci = 0; ci < cands.size(); ++ci) {
           const int G = cands[ci][0];
-          if (G == kTiled) th->tile_waves16 = cands[ci][1];
+          if (G == kTiled) {
+            th->tile_waves16 = cands[ci][1] % 10;
+            th->tile_unroll16 = cands[ci][1] / 10;
+          }
           auto pair = [&]() {
             if (G == kTiled) {
               launch_res_tiled16(th, th->ws_y, th->ws_x0, th->ws_r, nullptr, 1, s);
@@ -113,7 +121,7 @@ void tune_packed(wdb_theta* th, const char* cache_path, const std::string& key, 
           WDB_HIP(hipEventElapsedTime(&ms, e0, e1));
           const double us = 1e3 * ms / reps;
           if (std::getenv("WDB_LOG"))
-            std::fprintf(stderr, "[wdb] autotune packed G=%d W=%d: %.2f us per iteration\n", G, cands[ci][1], us);
+            std::fprintf(stderr, "[wdb] autotune packed G=%d shape=%d: %.2f us per iteration\n", G, cands[ci][1], us);
           t_min[ci] = std::min(t_min[ci], us);
         }
       for (size_t ci = 0; ci < cands.size(); ++ci)
@@ -136,7 +144,8 @@ void tune_packed(wdb_theta* th, const char* cache_path, const std::string& key, 
   }
   th->q_group = bestG;
   if (bestG == kTiled) {
-    th->tile_waves16 = bestW;
+    th->tile_waves16 = bestW % 10;
+    th->tile_unroll16 = bestW / 10;
     build_tiled16(th);
   } else {  // the 16-bit tiled copies are only kept when they are the layout in use
     th->qA.free_all();
@@ -183,7 +192,8 @@ extern "C" wdb_status wdb_autotune(wdb_theta* th, const char* cache_path, int32_
     if (th->st.seg) cands.push_back({0, kStencil, 0});  // circulant storage (convolution fast path)
     if (tiled_supported(th)) {
       build_tiled(th);
-      for (int W : {1, 2, 4, 8}) cands.push_back({0, kTiled, W});
+      for (int W : {1, 2, 4, 8})
+        for (int U : {2, 4}) cands.push_back({0, kTiled, shape_code(W, U)});
     }
     hipEvent_t e0, e1;
     WDB_HIP(hipEventCreate(&e0));
@@ -194,7 +204,10 @@ extern "C" wdb_status wdb_autotune(wdb_theta* th, const char* cache_path, int32_
       for (size_t ci = 0; ci < cands.size(); ++ci) {
         const int C = cands[ci][0], G = cands[ci][1];
         if (C) set_slice_height(th, C, s);
-        if (G == kTiled) th->tile_waves = cands[ci][2];
+        if (G == kTiled) {
+          th->tile_waves = cands[ci][2] % 10;
+          th->tile_unroll = cands[ci][2] / 10;
+        }
         auto pair = [&]() {
           if (G == kTiled) {
             launch_res_tiled(th, false, th->ws_y, th->ws_x0, th->ws_r, nullptr, s);
@@ -219,7 +232,7 @@ extern "C" wdb_status wdb_autotune(wdb_theta* th, const char* cache_path, int32_
         WDB_HIP(hipEventElapsedTime(&ms, e0, e1));
         const double us = 1e3 * ms / reps;
         if (std::getenv("WDB_LOG"))
-          std::fprintf(stderr, "[wdb] autotune C=%d G=%d W=%d: %.2f us per iteration\n", C, G, cands[ci][2], us);
+          std::fprintf(stderr, "[wdb] autotune C=%d G=%d shape=%d: %.2f us per iteration\n", C, G, cands[ci][2], us);
         t_min[ci] = std::min(t_min[ci], us);
       }
       for (size_t ci = 0; ci < cands.size(); ++ci)
@@ -246,7 +259,8 @@ extern "C" wdb_status wdb_autotune(wdb_theta* th, const char* cache_path, int32_
   set_slice_height(th, bestC, s);
   th->spmv_group = bestG;
   if (bestG == kTiled) {
-    th->tile_waves = bestW;
+    th->tile_waves = bestW % 10;
+    th->tile_unroll = bestW / 10;
   } else {  // the tiled copies are only kept when they are the layout in use
     th->tA.free_all();
     th->tAt.free_all();

@@ -251,8 +251,10 @@ struct wdb_theta {
   wdb::Stencil st, stT; // circulant storage of Theta_K and Theta_K^T (convolution fast path only)
   wdb::Tiled tA, tAt;   // tiled pattern storage of Theta_K and Theta_K^T (built on demand)
   int tile_waves = 4;   // wavefronts per tile of the tiled kernels
+  int tile_unroll = 2;  // groups of 4 codes in flight per wavefront
   wdb::Tiled qA, qAt;   // the same with 16-bit values (built on demand when valtype != 0)
   int tile_waves16 = 4;
+  int tile_unroll16 = 1;  // groups of 8 codes in flight per wavefront
   std::vector<float> qscale;  // host copy of the per-subband scales of the 16-bit values
   int q_group = 0;      // lanes per row of the packed kernels (0: default)
   bool has_L = false;

@@ -91,11 +91,10 @@ __device__ __forceinline__ float tile_finish(const TiledView& T, const int4& d, 
 
 // Dot product of the lane's row with x over float32 values (groups of 4
 // codes, two groups in flight per wavefront).
-template <int W>
+template <int W, int U>
 __device__ __forceinline__ float tile_dot(const TiledView& T, const Geo& g, const int4& d, int row, int lane,
                                           int wv, const float* __restrict__ x) {
   const RowCode rc = row_code(g, pos_of(g, row >= 0 ? row : d.z));
-  constexpr int U = 2;
   float acc = 0.f;
   const int g1 = d.y >> 2;
   for (int k = (d.x >> 2) + wv; k < g1; k += W * U) {
@@ -120,25 +119,36 @@ __device__ __forceinline__ float tile_dot(const TiledView& T, const Geo& g, cons
 
 // The same over 16-bit values: groups of 8 codes, one 16-byte vector of 8
 // values per lane and group.
-template <int W, int FMT>
+template <int W, int U, int FMT>
 __device__ __forceinline__ float tile_dot16(const TiledView& T, const Geo& g, const int4& d, int row, int lane,
                                             int wv, const float* __restrict__ x) {
   const RowCode rc = row_code(g, pos_of(g, row >= 0 ? row : d.z));
   float acc = 0.f;
   const int g1 = d.y >> 3;
-  for (int k = (d.x >> 3) + wv; k < g1; k += W) {
-    const uint4 c0 = T.code[2 * k], c1 = T.code[2 * k + 1];
-    const uint4 v = T.val16[static_cast<int64_t>(k) * 64 + lane];
-    const uint32_t cs[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
-    const uint32_t vs[4] = {v.x, v.y, v.z, v.w};
+  for (int k = (d.x >> 3) + wv; k < g1; k += W * U) {
+    uint4 c[2 * U], v[U];
 #pragma unroll
-    for (int e = 0; e < 8; ++e)
-      acc = fmaf(dq16<FMT>((vs[e >> 1] >> (16 * (e & 1))) & 0xFFFFu), x[decode_col(g, rc, cs[e])], acc);
+    for (int u = 0; u < U; ++u) {
+      const bool ok = k + u * W < g1;
+      const uint4 pad = make_uint4(kPadCode, kPadCode, kPadCode, kPadCode);
+      c[2 * u] = ok ? T.code[2 * (k + u * W)] : pad;
+      c[2 * u + 1] = ok ? T.code[2 * (k + u * W) + 1] : pad;
+      v[u] = ok ? T.val16[static_cast<int64_t>(k + u * W) * 64 + lane] : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t cs[8] = {c[2 * u].x, c[2 * u].y, c[2 * u].z, c[2 * u].w,
+                              c[2 * u + 1].x, c[2 * u + 1].y, c[2 * u + 1].z, c[2 * u + 1].w};
+      const uint32_t vs[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        acc = fmaf(dq16<FMT>((vs[e >> 1] >> (16 * (e & 1))) & 0xFFFFu), x[decode_col(g, rc, cs[e])], acc);
+    }
   }
   return tile_finish<W>(T, d, row, lane, wv, acc, x);
 }
 
-template <int W>
+template <int W, int U>
 __global__ __launch_bounds__(64 * W) void k_res_tl(TiledView T, Geo g, const float* __restrict__ y,
                                                    const float* __restrict__ b, float* __restrict__ r,
                                                    int* __restrict__ kdev) {
@@ -147,11 +157,45 @@ __global__ __launch_bounds__(64 * W) void k_res_tl(TiledView T, Geo g, const flo
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int row = tile_row(d, lane);
-  const float acc = tile_dot<W>(T, g, d, row, lane, wv, y);
-  if (wv == 0 && row >= 0) r[row] = b ? acc - b[row] : acc;
+  const bool out = wv == 0 && row >= 0;
+  const float bv = b && out ? b[row] : 0.0f;  // issued before the product so its latency overlaps
+  const float acc = tile_dot<W, U>(T, g, d, row, lane, wv, y);
+  if (out) r[row] = acc - bv;
 }
 
-template <int W, bool PRE>
+// Operands of the proximal epilogue, loaded before the product.
+struct ProxIn {
+  float y, x, pi, tw, beta;
+};
+
+template <bool PRE>
+__device__ __forceinline__ ProxIn prox_load(int row, bool out, const float* __restrict__ x,
+                                            const float* __restrict__ y, const int* __restrict__ kdev, float beta,
+                                            const float* __restrict__ pinv, const float* __restrict__ tw) {
+  ProxIn p{0.f, 0.f, 1.f, 1.f, beta};
+  if (out) {
+    p.y = y[row];
+    p.x = x[row];
+    if (PRE) p.pi = pinv[row];
+    p.tw = tw ? tw[row] : p.pi;
+  }
+  if (kdev) {
+    const int k = *kdev;
+    p.beta = static_cast<float>((static_cast<double>(k) - 1.0) / (static_cast<double>(k) + 2.0));
+  }
+  return p;
+}
+
+__device__ __forceinline__ void prox_store(const ProxIn& p, int row, float gr, float tau, float thr,
+                                           float* __restrict__ x, float* __restrict__ y) {
+  const float z = p.y - (tau * p.pi) * gr;
+  const float t = thr * p.tw;
+  const float xn = copysignf(fmaxf(fabsf(z) - t, 0.0f), z);
+  x[row] = xn;
+  y[row] = xn + p.beta * (xn - p.x);
+}
+
+template <int W, int U, bool PRE>
 __global__ __launch_bounds__(64 * W) void k_prox_tl(TiledView T, Geo g, const float* __restrict__ r,
                                                     float* __restrict__ x, float* __restrict__ y, float tau,
                                                     float thr, float beta, const int* __restrict__ kdev,
@@ -160,25 +204,16 @@ __global__ __launch_bounds__(64 * W) void k_prox_tl(TiledView T, Geo g, const fl
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int row = tile_row(d, lane);
-  const float gr = tile_dot<W>(T, g, d, row, lane, wv, r);
-  if (wv != 0 || row < 0) return;
-  if (kdev) {
-    const int k = *kdev;
-    beta = static_cast<float>((static_cast<double>(k) - 1.0) / (static_cast<double>(k) + 2.0));
-  }
-  const float pi = PRE ? pinv[row] : 1.0f;
-  const float z = y[row] - (tau * pi) * gr;
-  const float t = thr * (tw ? tw[row] : pi);
-  const float xn = copysignf(fmaxf(fabsf(z) - t, 0.0f), z);
-  const float xo = x[row];
-  x[row] = xn;
-  y[row] = xn + beta * (xn - xo);
+  const bool out = wv == 0 && row >= 0;
+  const ProxIn p = prox_load<PRE>(row, out, x, y, kdev, beta, pinv, tw);
+  const float gr = tile_dot<W, U>(T, g, d, row, lane, wv, r);
+  if (out) prox_store(p, row, gr, tau, thr, x, y);
 }
 
 // 16-bit values scaled by a power of two u per scale block (row subband for
 // Theta_K, column subband for Theta_K^T): r = w (Q y) - b with w = 1 / u of
 // the row, stored times w when scale_out (the input of the transposed kernel).
-template <int W, int FMT>
+template <int W, int U, int FMT>
 __global__ __launch_bounds__(64 * W) void k_res_tl16(TiledView T, Geo g, const float* __restrict__ wrow,
                                                      const float* __restrict__ y, const float* __restrict__ b,
                                                      float* __restrict__ r, int* __restrict__ kdev, int scale_out) {
@@ -187,15 +222,17 @@ __global__ __launch_bounds__(64 * W) void k_res_tl16(TiledView T, Geo g, const f
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int row = tile_row(d, lane);
-  const float acc = tile_dot16<W, FMT>(T, g, d, row, lane, wv, y);
-  if (wv != 0 || row < 0) return;
-  const float w = wrow[row];
-  const float rr = b ? w * acc - b[row] : w * acc;
+  const bool out = wv == 0 && row >= 0;
+  const float w = out ? wrow[row] : 0.0f;
+  const float bv = b && out ? b[row] : 0.0f;
+  const float acc = tile_dot16<W, U, FMT>(T, g, d, row, lane, wv, y);
+  if (!out) return;
+  const float rr = b ? w * acc - bv : w * acc;
   r[row] = scale_out ? rr * w : rr;
 }
 
 // g = Q^T (w r); x_k = S(y - tau g / P); y = x_k + beta_k (x_k - x_{k-1}).
-template <int W, int FMT, bool PRE>
+template <int W, int U, int FMT, bool PRE>
 __global__ __launch_bounds__(64 * W) void k_prox_tl16(TiledView T, Geo g, const float* __restrict__ rs,
                                                       float* __restrict__ x, float* __restrict__ y, float tau,
                                                       float thr, const int* __restrict__ kdev,
@@ -204,29 +241,28 @@ __global__ __launch_bounds__(64 * W) void k_prox_tl16(TiledView T, Geo g, const 
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int row = tile_row(d, lane);
-  const float gr = tile_dot16<W, FMT>(T, g, d, row, lane, wv, rs);
-  if (wv != 0 || row < 0) return;
-  float beta = 0.0f;  // no counter: no extrapolation (ISTA)
-  if (kdev) {
-    const int k = *kdev;
-    beta = static_cast<float>((static_cast<double>(k) - 1.0) / (static_cast<double>(k) + 2.0));
-  }
-  const float pi = PRE ? pinv[row] : 1.0f;
-  const float z = y[row] - (tau * pi) * gr;
-  const float t = thr * (tw ? tw[row] : pi);
-  const float xn = copysignf(fmaxf(fabsf(z) - t, 0.0f), z);
-  const float xo = x[row];
-  x[row] = xn;
-  y[row] = xn + beta * (xn - xo);
+  const bool out = wv == 0 && row >= 0;
+  const ProxIn p = prox_load<PRE>(row, out, x, y, kdev, 0.0f, pinv, tw);  // no counter: beta = 0 (ISTA)
+  const float gr = tile_dot16<W, U, FMT>(T, g, d, row, lane, wv, rs);
+  if (out) prox_store(p, row, gr, tau, thr, x, y);
 }
 
+// Wavefronts per tile W and groups in flight per wavefront U.
 template <typename F>
-void with_waves(int W, F&& f) {
+void with_shape(int W, int U, F&& f) {
+  auto w = [&](auto Wc) {
+    switch (U) {
+      case 1: f(Wc, std::integral_constant<int, 1>{}); return;
+      case 2: f(Wc, std::integral_constant<int, 2>{}); return;
+      case 4: f(Wc, std::integral_constant<int, 4>{}); return;
+      default: fail(WDB_ERR_ARG, "unsupported groups in flight %d (1, 2 or 4)", U);
+    }
+  };
   switch (W) {
-    case 1: f(std::integral_constant<int, 1>{}); return;
-    case 2: f(std::integral_constant<int, 2>{}); return;
-    case 4: f(std::integral_constant<int, 4>{}); return;
-    case 8: f(std::integral_constant<int, 8>{}); return;
+    case 1: w(std::integral_constant<int, 1>{}); return;
+    case 2: w(std::integral_constant<int, 2>{}); return;
+    case 4: w(std::integral_constant<int, 4>{}); return;
+    case 8: w(std::integral_constant<int, 8>{}); return;
     default: fail(WDB_ERR_ARG, "unsupported wavefronts per tile %d (1, 2, 4 or 8)", W);
   }
 }
@@ -496,14 +532,14 @@ void launch_res_tiled16(const wdb_theta* th, const float* y, const float* b, flo
   const Tiled& T = th->qA;
   WDB_REQUIRE(T.desc && T.val16, WDB_ERR_ARG, "16-bit tiled storage not built");
   const Geo g = geo_of(th);
-  with_waves(th->tile_waves16, [&](auto Wc) {
-    constexpr int W = decltype(Wc)::value;
+  with_shape(th->tile_waves16, th->tile_unroll16, [&](auto Wc, auto Uc) {
+    constexpr int W = decltype(Wc)::value, U = decltype(Uc)::value;
     const dim3 grid(static_cast<unsigned>(T.ntiles)), block(64 * W);
     if (th->valtype == WDB_VAL_BF16)
-      hipLaunchKernelGGL((k_res_tl16<W, WDB_VAL_BF16>), grid, block, 0, s, tview(T), g, th->wrow, y, b, r, kdev,
+      hipLaunchKernelGGL((k_res_tl16<W, U, WDB_VAL_BF16>), grid, block, 0, s, tview(T), g, th->wrow, y, b, r, kdev,
                          scale_out);
     else
-      hipLaunchKernelGGL((k_res_tl16<W, WDB_VAL_F16>), grid, block, 0, s, tview(T), g, th->wrow, y, b, r, kdev,
+      hipLaunchKernelGGL((k_res_tl16<W, U, WDB_VAL_F16>), grid, block, 0, s, tview(T), g, th->wrow, y, b, r, kdev,
                          scale_out);
   });
 }
@@ -513,22 +549,22 @@ void launch_prox_tiled16(const wdb_theta* th, const float* rs, float* x, float* 
   const Tiled& T = th->qAt;
   WDB_REQUIRE(T.desc && T.val16, WDB_ERR_ARG, "16-bit tiled storage not built");
   const Geo g = geo_of(th);
-  with_waves(th->tile_waves16, [&](auto Wc) {
-    constexpr int W = decltype(Wc)::value;
+  with_shape(th->tile_waves16, th->tile_unroll16, [&](auto Wc, auto Uc) {
+    constexpr int W = decltype(Wc)::value, U = decltype(Uc)::value;
     const dim3 grid(static_cast<unsigned>(T.ntiles)), block(64 * W);
     if (th->valtype == WDB_VAL_BF16) {
       if (pinv)
-        hipLaunchKernelGGL((k_prox_tl16<W, WDB_VAL_BF16, true>), grid, block, 0, s, tview(T), g, rs, x, y, tau, thr,
-                           kdev, pinv, tw);
+        hipLaunchKernelGGL((k_prox_tl16<W, U, WDB_VAL_BF16, true>), grid, block, 0, s, tview(T), g, rs, x, y, tau,
+                           thr, kdev, pinv, tw);
       else
-        hipLaunchKernelGGL((k_prox_tl16<W, WDB_VAL_BF16, false>), grid, block, 0, s, tview(T), g, rs, x, y, tau,
+        hipLaunchKernelGGL((k_prox_tl16<W, U, WDB_VAL_BF16, false>), grid, block, 0, s, tview(T), g, rs, x, y, tau,
                            thr, kdev, pinv, tw);
     } else {
       if (pinv)
-        hipLaunchKernelGGL((k_prox_tl16<W, WDB_VAL_F16, true>), grid, block, 0, s, tview(T), g, rs, x, y, tau, thr,
-                           kdev, pinv, tw);
+        hipLaunchKernelGGL((k_prox_tl16<W, U, WDB_VAL_F16, true>), grid, block, 0, s, tview(T), g, rs, x, y, tau,
+                           thr, kdev, pinv, tw);
       else
-        hipLaunchKernelGGL((k_prox_tl16<W, WDB_VAL_F16, false>), grid, block, 0, s, tview(T), g, rs, x, y, tau,
+        hipLaunchKernelGGL((k_prox_tl16<W, U, WDB_VAL_F16, false>), grid, block, 0, s, tview(T), g, rs, x, y, tau,
                            thr, kdev, pinv, tw);
     }
   });
@@ -539,10 +575,10 @@ void launch_res_tiled(const wdb_theta* th, bool transpose, const float* y, const
   const Tiled& T = transpose ? th->tAt : th->tA;
   WDB_REQUIRE(T.desc, WDB_ERR_ARG, "tiled storage not built");
   const Geo g = geo_of(th);
-  with_waves(th->tile_waves, [&](auto Wc) {
-    constexpr int W = decltype(Wc)::value;
-    hipLaunchKernelGGL(k_res_tl<W>, dim3(static_cast<unsigned>(T.ntiles)), dim3(64 * W), 0, s, tview(T), g, y, b,
-                       r, kdev);
+  with_shape(th->tile_waves, th->tile_unroll, [&](auto Wc, auto Uc) {
+    constexpr int W = decltype(Wc)::value, U = decltype(Uc)::value;
+    hipLaunchKernelGGL((k_res_tl<W, U>), dim3(static_cast<unsigned>(T.ntiles)), dim3(64 * W), 0, s, tview(T), g, y,
+                       b, r, kdev);
   });
 }
 
@@ -551,26 +587,33 @@ void launch_prox_tiled(const wdb_theta* th, const float* r, float* x, float* y, 
   const Tiled& T = th->tAt;
   WDB_REQUIRE(T.desc, WDB_ERR_ARG, "tiled storage not built");
   const Geo g = geo_of(th);
-  with_waves(th->tile_waves, [&](auto Wc) {
-    constexpr int W = decltype(Wc)::value;
+  with_shape(th->tile_waves, th->tile_unroll, [&](auto Wc, auto Uc) {
+    constexpr int W = decltype(Wc)::value, U = decltype(Uc)::value;
     const dim3 grid(static_cast<unsigned>(T.ntiles)), block(64 * W);
     if (pinv)
-      hipLaunchKernelGGL((k_prox_tl<W, true>), grid, block, 0, s, tview(T), g, r, x, y, tau, thr, beta, kdev, pinv,
-                         tw);
+      hipLaunchKernelGGL((k_prox_tl<W, U, true>), grid, block, 0, s, tview(T), g, r, x, y, tau, thr, beta, kdev,
+                         pinv, tw);
     else
-      hipLaunchKernelGGL((k_prox_tl<W, false>), grid, block, 0, s, tview(T), g, r, x, y, tau, thr, beta, kdev,
+      hipLaunchKernelGGL((k_prox_tl<W, U, false>), grid, block, 0, s, tview(T), g, r, x, y, tau, thr, beta, kdev,
                          pinv, tw);
   });
 }
 
 }  // namespace wdb
 
-extern "C" wdb_status wdb_set_tile_waves(wdb_theta* th, int32_t waves) {
+extern "C" wdb_status wdb_set_tile_shape(wdb_theta* th, int32_t waves, int32_t unroll) {
   WDB_API_BEGIN
   WDB_REQUIRE(th, WDB_ERR_ARG, "null handle");
   WDB_REQUIRE(waves == 1 || waves == 2 || waves == 4 || waves == 8, WDB_ERR_ARG,
               "wavefronts per tile must be 1, 2, 4 or 8");
-  if (th->valtype == WDB_VAL_F32) th->tile_waves = waves;
-  else th->tile_waves16 = waves;
+  WDB_REQUIRE(unroll == 0 || unroll == 1 || unroll == 2 || unroll == 4, WDB_ERR_ARG,
+              "groups in flight must be 0 (default), 1, 2 or 4");
+  if (th->valtype == WDB_VAL_F32) {
+    th->tile_waves = waves;
+    th->tile_unroll = unroll ? unroll : 2;
+  } else {
+    th->tile_waves16 = waves;
+    th->tile_unroll16 = unroll ? unroll : 1;
+  }
   WDB_API_END
 }

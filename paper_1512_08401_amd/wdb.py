@@ -50,7 +50,8 @@ class ThetaDesc(C.Structure):
                 ("precond", C.c_int32), ("valtype", C.c_int32), ("slice", C.c_int32), ("group", C.c_int32),
                 ("group16", C.c_int32), ("escapes", C.c_int64), ("conv_build", C.c_int32),
                 ("l1_weights", C.c_int32), ("rule", C.c_int32), ("circulant", C.c_int64),
-                ("tile_waves", C.c_int32), ("tile_slots", C.c_int64), ("tile_waves16", C.c_int32)]
+                ("tile_waves", C.c_int32), ("tile_slots", C.c_int64), ("tile_waves16", C.c_int32),
+                ("tile_unroll", C.c_int32), ("tile_unroll16", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -94,7 +95,7 @@ _SIGS = {
     "wdb_set_precision": [_vp, _i32],
     "wdb_set_kernel_layout": [_vp, _i32, _i32],
     "wdb_set_packed_group": [_vp, _i32],
-    "wdb_set_tile_waves": [_vp, _i32],
+    "wdb_set_tile_shape": [_vp, _i32, _i32],
     "wdb_set_l1_weights": [_vp, _i32, _vp],
     "wdb_autotune": [_vp, C.c_char_p, _i32, C.POINTER(_i32), C.POINTER(_i32), _pd],
     "wdb_cnn_create": [_i32, _i32, _i32, C.c_uint64, C.POINTER(_vp)],
@@ -268,9 +269,10 @@ class Theta:
         """Lanes per row of the packed 16-bit kernels (2/4/8/16; 0 = default)."""
         _check("wdb_set_packed_group", _lib.wdb_set_packed_group(self._h, int(group)))
 
-    def set_tile_waves(self, waves: int = 4):
-        """Wavefronts per tile of the tiled layout (group 3): 1, 2, 4 or 8."""
-        _check("wdb_set_tile_waves", _lib.wdb_set_tile_waves(self._h, int(waves)))
+    def set_tile_shape(self, waves: int = 4, unroll: int = 0):
+        """Tiled kernels of the current value type: wavefronts per tile (1/2/4/8) and
+        code groups in flight per wavefront (1/2/4; 0 = default)."""
+        _check("wdb_set_tile_shape", _lib.wdb_set_tile_shape(self._h, int(waves), int(unroll)))
 
     def autotune(self, cache_path: str | None = None, reps: int = 20):
         """Pick the fastest iteration layout for this operator; returns (slice, group, us)."""

@@ -649,8 +649,8 @@ def test_packed_16bit_db4_matches_oracle(W, db4_64, fmt):
     _gate(Q, x0.astype(np.float64), lam32, host(xg), xo, fista.objective(Q, x0.astype(np.float64), lam32, xo))
 
 
-@pytest.mark.parametrize("fmt,waves", [("f16", 1), ("f16", 4), ("bf16", 2), ("bf16", 8)])
-def test_tiled_16bit_db4_matches_oracle(W, db4_64, fmt, waves):
+@pytest.mark.parametrize("fmt,waves,unroll", [("f16", 1, 1), ("f16", 4, 2), ("bf16", 2, 2), ("bf16", 8, 1)])
+def test_tiled_16bit_db4_matches_oracle(W, db4_64, fmt, waves, unroll):
     """16-bit tiled layout (group16 3): products against the oracle's quantised
     operator, Alg. 1 and Alg. 2 (per-scale P, scale weights) solves."""
     from oracle import quant
@@ -661,9 +661,9 @@ def test_tiled_16bit_db4_matches_oracle(W, db4_64, fmt, waves):
     th.lipschitz(start)
     th.set_precision(fmt)
     th.set_packed_group(3)
-    th.set_tile_waves(waves)
+    th.set_tile_shape(waves, unroll)
     info = th.info()
-    assert info["group16"] == 3 and info["tile_waves16"] == waves
+    assert info["group16"] == 3 and info["tile_waves16"] == waves and info["tile_unroll16"] == unroll
     Q = quant.quantize(A, 64, 3, fmt)
     x = np.random.default_rng(18).standard_normal(4096).astype(np.float32)
     b = np.random.default_rng(19).standard_normal(4096).astype(np.float32)
@@ -826,14 +826,14 @@ def test_layouts_match_oracle(W, p64, slice_h, group):
     assert np.max(np.abs(th.precond() - po) / po) <= 1e-10
 
 
-@pytest.mark.parametrize("waves", [1, 2, 4, 8])
-def test_tiled_layout_matches_oracle(W, p64, waves):
+@pytest.mark.parametrize("waves,unroll", [(1, 2), (2, 4), (4, 2), (8, 4)])
+def test_tiled_layout_matches_oracle(W, p64, waves, unroll):
     """Tiled pattern storage (layout 3): products, FISTA, and the proximal
     epilogue with the preconditioner and scale weights, against the oracle."""
     th = imported(W, p64)
     th.set_kernel_layout(8, 3)
-    th.set_tile_waves(waves)
-    assert th.info()["group"] == 3
+    th.set_tile_shape(waves, unroll)
+    assert th.info()["group"] == 3 and th.info()["tile_unroll"] == unroll
     A32 = p64["A32"]
     rng = np.random.default_rng(waves)
     x = rng.standard_normal(4096).astype(np.float32)
@@ -884,7 +884,7 @@ def test_tiled_escapes_and_small_subbands_match_oracle(W):
     A32 = sp.csr_matrix((A.data.astype(np.float32).astype(np.float64), A.indices, A.indptr), shape=A.shape)
     x = rng.standard_normal(N).astype(np.float32)
     for waves in (1, 4):
-        th.set_tile_waves(waves)
+        th.set_tile_shape(waves)
         y = host(th.apply(dev(x)))
         ref = A32 @ x.astype(np.float64)
         assert np.max(np.abs(y - ref)) <= 1e-5 * np.max(np.abs(ref)), waves
