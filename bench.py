@@ -45,26 +45,29 @@ def kernel_label(layout, waves=4, unroll=2):
     return "k_res", f"r = Theta_K y - x0, float32 sliced-ELL, {slice_h} rows per slice"
 
 
+KERNEL_SOURCES = ("paper_1512_08401_amd/csrc/solve.hip", "paper_1512_08401_amd/csrc/tiled.hip",
+                  "paper_1512_08401_amd/csrc/codes.hpp", "paper_1512_08401_amd/csrc/common.hpp")
+
+
 def profiled_traffic(workload, kernel, layout):
-    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when that
-    summary was taken on other kernel sources, another layout or workload."""
+    """HBM bytes per launch of ``kernel`` from a committed rocprofv3 counter
+    summary under profiles/ (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None
+    when no summary was taken on these kernel sources, layout and workload."""
+    import glob
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"k_res_{workload}.md")
-    try:
-        text = open(path).read()
-    except OSError:
-        return None
-    fields = dict(line.strip().split(": ", 1) for line in text.splitlines()
-                  if line.startswith("    ") and ": " in line)
     dig = hashlib.sha256()
-    for rel in ("paper_1512_08401_amd/csrc/solve.hip", "paper_1512_08401_amd/csrc/common.hpp"):
+    for rel in KERNEL_SOURCES:
         with open(os.path.join(ROOT, rel), "rb") as f:
             dig.update(f.read())
-    if (fields.get("source_sha256") != dig.hexdigest() or fields.get("kernel") != kernel
-            or fields.get("layout") != f"slice={layout[0]} group={layout[1]}" or fields.get("workload") != workload):
-        return None
-    return int(fields["traffic_bytes_per_launch"])
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        text = open(path).read()
+        fields = dict(line.strip().split(": ", 1) for line in text.splitlines()
+                      if line.startswith("    ") and ": " in line)
+        if (fields.get("source_sha256") == dig.hexdigest() and fields.get("kernel") == kernel
+                and fields.get("layout") == f"slice={layout[0]} group={layout[1]}"
+                and fields.get("workload") == workload and "traffic_bytes_per_launch" in fields):
+            return int(fields["traffic_bytes_per_launch"])
+    return None
 
 
 def cpu_model():
@@ -161,6 +164,7 @@ def main():
     if not args.no_autotune:
         th.autotune(reps=10)
     layout = (th.info()["slice"], th.info()["group"])
+    tile_shape = (th.info()["tile_waves"], th.info()["tile_unroll"])
     t_tune = time.perf_counter() - t0
     t0 = time.perf_counter()
     L, l_iters = th.lipschitz(synth.power_start(N, wl.power_seed))
@@ -211,9 +215,13 @@ def main():
     kt1.record(stream)
     torch.cuda.synchronize()
     kt_us = kt0.elapsed_time(kt1) * 1e3 / reps
-    half_us = {}
+    half_us, half_layout = {}, {}
     for vt in ("bf16", "f16"):
         th.set_precision(vt)
+        th.autotune(reps=10)   # picks the 16-bit layout too (packed lanes per row or 16-bit tiles)
+        hi = th.info()
+        half_layout[vt] = ({"tiled": {"waves": hi["tile_waves16"], "unroll": hi["tile_unroll16"]}}
+                           if hi["group16"] == 3 else {"packed_lanes_per_row": hi["group16"]})
         th.apply(y, u0, out=r, repeat=20)
         h0, h1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         h0.record(stream)
@@ -222,10 +230,11 @@ def main():
         torch.cuda.synchronize()
         half_us[vt] = h0.elapsed_time(h1) * 1e3 / reps
     th.set_precision("f32")
+    th.autotune(reps=10)
     nnz = info["nnz"]
     alg_bytes = 8 * nnz + 12 * N          # values + indices once, y/x0 read once, r written once
     achieved = alg_bytes / (k_us * 1e-6) / 1e9
-    kname, kdesc = kernel_label(layout, th.info()["tile_waves"], th.info()["tile_unroll"])
+    kname, kdesc = kernel_label(layout, *tile_shape)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": profiled_traffic(wl.name, kname, layout),
@@ -235,6 +244,7 @@ def main():
                 "transpose_kernel_us": round(kt_us, 2),
                 "layout": {"slice": layout[0], "lanes_per_row": layout[1]},
                 "k_res_16bit_us": {k: round(v, 2) for k, v in half_us.items()},
+                "k_res_16bit_layout": half_layout,
                 "k_res_16bit_gbs": {k: round((6 * nnz + 12 * N) / (v * 1e-6) / 1e9, 1) for k, v in half_us.items()}}
 
     ttt = None if args.no_ttt else time_to_tolerance(th, u0, wl, torch, wdb, synth, N)
@@ -294,6 +304,8 @@ def time_to_tolerance(th, u0, wl, torch, wdb, synth, N, targets=(1e-4, 1e-6)):
     x = torch.empty(N, device=u0.device)
     for form, pre, vt in forms:
         th.set_precision(vt)
+        if vt != "f32":
+            th.autotune(reps=10)   # the fastest 16-bit layout for this operator
         cap = 6000
         _, tr = th.solve(u0, wl.lam, cap, check_every=10, precond=pre, trace_cap=cap // 10)
         rho = (tr["trace"][:, 1] - Estar) / E0

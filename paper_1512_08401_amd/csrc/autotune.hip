@@ -9,7 +9,8 @@
 // 1, 2, 4 or 8 wavefronts per tile and 2 or 4 code groups in flight -- and
 // keeps the fastest in the handle (each candidate timed in two alternating
 // passes, its best pass counted, so that one slow pass from a clock or
-// cache transient does not decide).  Decisions can be cached in a text file
+// cache transient does not decide; of candidates within 2% of the fastest
+// the first in list order is kept).  Decisions can be cached in a text file
 // keyed by the operator's shape and a hash of its row pointer.
 #include <algorithm>
 #include <array>
@@ -51,6 +52,8 @@ std::string cache_key(const wdb_theta* th) {
   o << th->n << "-" << th->levels << "-" << th->wavelet << "-" << th->nnz << "-" << std::hex << h;
   return o.str();
 }
+
+constexpr double kTieMargin = 1.02;
 
 // Shape code of the tiled kernels: W + 10 U (W wavefronts per tile, U code
 // groups in flight per wavefront).
@@ -124,11 +127,15 @@ void tune_packed(wdb_theta* th, const char* cache_path, const std::string& key, 
             std::fprintf(stderr, "[wdb] autotune packed G=%d shape=%d: %.2f us per iteration\n", G, cands[ci][1], us);
           t_min[ci] = std::min(t_min[ci], us);
         }
+      // the first candidate (in list order) within 2% of the fastest: near-ties
+      // resolve the same way from run to run
+      const double fastest = *std::min_element(t_min.begin(), t_min.end());
       for (size_t ci = 0; ci < cands.size(); ++ci)
-        if (t_min[ci] < best) {
+        if (t_min[ci] <= kTieMargin * fastest) {
           best = t_min[ci];
           bestG = cands[ci][0];
           bestW = cands[ci][1];
+          break;
         }
     } catch (...) {
       (void)hipEventDestroy(e0);
@@ -235,12 +242,14 @@ extern "C" wdb_status wdb_autotune(wdb_theta* th, const char* cache_path, int32_
           std::fprintf(stderr, "[wdb] autotune C=%d G=%d shape=%d: %.2f us per iteration\n", C, G, cands[ci][2], us);
         t_min[ci] = std::min(t_min[ci], us);
       }
+      const double fastest = *std::min_element(t_min.begin(), t_min.end());
       for (size_t ci = 0; ci < cands.size(); ++ci)
-        if (t_min[ci] < best) {
+        if (t_min[ci] <= kTieMargin * fastest) {
           best = t_min[ci];
           bestC = cands[ci][0];
           bestG = cands[ci][1];
           bestW = cands[ci][2];
+          break;
         }
       if (bestC == 0) bestC = th->A.C;  // a CSR or circulant layout keeps the current slice height
 
