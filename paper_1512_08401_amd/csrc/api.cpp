@@ -76,7 +76,7 @@ void free_workspace(wdb_theta* th) {
   float* fs[] = {th->ws_x0, th->ws_r, th->ws_y, th->ws_img, th->ws_img2, th->pinv};
   for (float* p : fs)
     if (p) (void)hipFree(p);
-  double* ds[] = {th->ws_r64, th->ws_v64, th->ws_partial, th->ws_scalar, th->p64};
+  double* ds[] = {th->ws_r64, th->ws_v64, th->ws_partial, th->ws_scalar, th->p64, th->ws_checks};
   for (double* p : ds)
     if (p) (void)hipFree(p);
   if (th->host_scalar) (void)hipHostFree(th->host_scalar);
@@ -87,7 +87,8 @@ void free_workspace(wdb_theta* th) {
   th->ws_rho = nullptr;
   th->capture_stream = nullptr;
   th->ws_x0 = th->ws_r = th->ws_y = th->ws_img = th->ws_img2 = th->pinv = nullptr;
-  th->ws_r64 = th->ws_v64 = th->ws_partial = th->ws_scalar = th->p64 = nullptr;
+  th->ws_r64 = th->ws_v64 = th->ws_partial = th->ws_scalar = th->p64 = th->ws_checks = nullptr;
+  th->ws_ncheck = 0;
   th->host_scalar = nullptr;
 }
 

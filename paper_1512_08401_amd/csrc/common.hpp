@@ -278,6 +278,8 @@ struct wdb_theta {
   float* ws_img = nullptr;       // n*n scratch for transforms
   float* ws_img2 = nullptr;
   int* ws_k = nullptr;           // device iteration counter
+  double* ws_checks = nullptr;   // device, 4 scalars per recorded check of a solve without a stopping test
+  int64_t ws_ncheck = 0;
   double* ws_rho = nullptr;      // power-iteration history (64 entries)
   int64_t ws_nblocks = 0;
   hipStream_t capture_stream = nullptr;
@@ -305,6 +307,12 @@ constexpr int kTiled = 3;    // kernel "group" value selecting the tiled pattern
 bool tiled_supported(const wdb_theta* th);
 void build_tiled(wdb_theta* th);    // builds tA / tAt from cA / cAt if not built yet
 void build_tiled16(wdb_theta* th);  // builds qA / qAt (16-bit values, scales qscale) if not built yet
+// Float64 stopping-test products over the tiles: partials of ||r||^2, <r, x0>,
+// sum w|x| at part[0..3 nb) and of max |g_i| / w_i at part[3 nb, 4 nb), one
+// per tile (nb = tiled_check_blocks).
+int64_t tiled_check_blocks(const wdb_theta* th);
+void launch_objective_tiled(const wdb_theta* th, const float* x, const float* x0, double* r64, double* part,
+                            int64_t nb, hipStream_t s);
 void launch_res_tiled16(const wdb_theta* th, const float* y, const float* b, float* r, int* kdev, int scale_out,
                         hipStream_t s);
 void launch_prox_tiled16(const wdb_theta* th, const float* rs, float* x, float* y, float tau, float thr,

@@ -709,8 +709,9 @@ uint64_t splitmix64(uint64_t& state) {
 void ensure_workspace(wdb_theta* th) {
   if (th->ws_x0) return;
   const int64_t N = th->N;
-  // enough partial-sum blocks for any slice height up to 64
-  const int64_t nb = (N + 64 + kBlock - 1) / kBlock;
+  // enough partial-sum blocks for any slice height up to 64, and one per tile
+  // of the tiled storage (N / 64 full tiles plus one per small subband)
+  const int64_t nb = std::max<int64_t>((N + 64 + kBlock - 1) / kBlock, (N + 63) / 64 + 3 * th->levels + 1);
   th->ws_nblocks = std::max<int64_t>(nb, 1);
   try {
     WDB_HIP(hipMalloc(reinterpret_cast<void**>(&th->ws_x0), N * sizeof(float)));
@@ -807,12 +808,18 @@ struct Check {
   double E, rel_gap;
 };
 
-Check objective_check(wdb_theta* th, const float* x, const float* x0, double lambda, hipStream_t s) {
+// Enqueue the float64 stopping-test products and their reduction into four
+// device doubles at `dst`: ||r||^2, <r, x0>, sum w|x|, max |g_i| / w_i.
+void enqueue_check(wdb_theta* th, const float* x, const float* x0, double* dst, hipStream_t s) {
   const SellView A = view(th->A), At = view(th->At);
+  const bool tiled = kernel_group(th) == kTiled;
   const int G = check_group(th);
-  const int64_t nb = G > 0 ? csr_check_blocks(th, G) : partial_blocks(A, At);
+  const int64_t nb = tiled ? tiled_check_blocks(th) : G > 0 ? csr_check_blocks(th, G) : partial_blocks(A, At);
+  WDB_REQUIRE(nb <= th->ws_nblocks, WDB_ERR_ARG, "partial-sum workspace too small");
   double* part = th->ws_partial;
-  if (G > 0) {
+  if (tiled) {
+    launch_objective_tiled(th, x, x0, th->ws_r64, part, nb, s);
+  } else if (G > 0) {
     with_group(G, [&](auto g) {
       constexpr int GG = decltype(g)::value;
       hipLaunchKernelGGL(k_obj_fwd_csr<GG>, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, cview(th->cA), x,
@@ -824,16 +831,25 @@ Check objective_check(wdb_theta* th, const float* x, const float* x0, double lam
     hipLaunchKernelGGL(k_obj_fwd, slot_grid(A), dim3(kBlock), 0, s, A, x, x0, th->l1w, th->ws_r64, part, nb);
     hipLaunchKernelGGL(k_obj_bwd, slot_grid(At), dim3(kBlock), 0, s, At, th->ws_r64, th->l1w, part + 3 * nb, nb);
   }
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, part, nb, 4, 0x8u, th->ws_scalar);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, part, nb, 4, 0x8u, dst);
   WDB_HIP(hipGetLastError());
-  WDB_HIP(hipMemcpyAsync(th->host_scalar, th->ws_scalar, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
-  WDB_HIP(hipStreamSynchronize(s));
-  const double rr = th->host_scalar[0], rb = th->host_scalar[1], l1 = th->host_scalar[2], gmax = th->host_scalar[3];
+}
+
+// E and the relative duality gap from the four reduced scalars.
+Check check_from(const double* q, double lambda) {
+  const double rr = q[0], rb = q[1], l1 = q[2], gmax = q[3];
   const double E = 0.5 * rr + lambda * l1;
   const double sc = gmax <= lambda ? 1.0 : lambda / gmax;
   const double D = -0.5 * sc * sc * rr - sc * rb;
   const double gap = E - D;
   return Check{E, E > 0 ? gap / E : 0.0};
+}
+
+Check objective_check(wdb_theta* th, const float* x, const float* x0, double lambda, hipStream_t s) {
+  enqueue_check(th, x, x0, th->ws_scalar, s);
+  WDB_HIP(hipMemcpyAsync(th->host_scalar, th->ws_scalar, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+  WDB_HIP(hipStreamSynchronize(s));
+  return check_from(th->host_scalar, lambda);
 }
 
 // One iteration of Alg. 1 (Alg. 2 with `pre`); with `ista` the proximal kernel
@@ -933,6 +949,21 @@ wdb_status solve_impl(wdb_theta* th, const float* x0_src, bool from_image, float
       WDB_HIP(hipStreamEndCapture(th->capture_stream, &graph));
       WDB_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
     }
+    // Without a stopping test the checks are only recorded: their scalars go to
+    // a device array and are read once at the end, so the host never waits
+    // between the graph launches.
+    const bool stop_test = opts->tol_rel_gap > 0 || opts->target_objective > 0;
+    std::vector<int> at_iter;
+    if (!stop_test) {
+      const int64_t ncheck = (c > 0 ? total / c : 0) + 1;
+      if (ncheck > th->ws_ncheck) {
+        if (th->ws_checks) (void)hipFree(th->ws_checks);
+        th->ws_checks = nullptr;
+        th->ws_ncheck = 0;
+        WDB_HIP(hipMalloc(reinterpret_cast<void**>(&th->ws_checks), 4 * ncheck * sizeof(double)));
+        th->ws_ncheck = ncheck;
+      }
+    }
     while (done < total) {
       int step = total - done;
       if (c > 0) step = std::min(step, c - (done % c));
@@ -944,7 +975,10 @@ wdb_status solve_impl(wdb_theta* th, const float* x0_src, bool from_image, float
       }
       done += step;
       const bool at_check = (c > 0 && done % c == 0) || done == total;
-      if (at_check) {
+      if (at_check && !stop_test) {
+        enqueue_check(th, x_out, th->ws_x0, th->ws_checks + 4 * at_iter.size(), s);
+        at_iter.push_back(done);
+      } else if (at_check) {
         last = objective_check(th, x_out, th->ws_x0, lambda, s);
         ++checks;
         if (opts->trace && checks <= opts->trace_cap) {
@@ -959,6 +993,22 @@ wdb_status solve_impl(wdb_theta* th, const float* x0_src, bool from_image, float
           converged = true;
           break;
         }
+      }
+    }
+    if (!at_iter.empty()) {
+      std::vector<double> q(4 * at_iter.size());
+      WDB_HIP(hipMemcpyAsync(q.data(), th->ws_checks, q.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      WDB_HIP(hipStreamSynchronize(s));
+      for (size_t j = 0; j < at_iter.size(); ++j) {
+        last = check_from(&q[4 * j], lambda);
+        ++checks;
+        if (opts->trace && checks <= opts->trace_cap) {
+          opts->trace[3 * (checks - 1) + 0] = static_cast<double>(k0 - 1 + at_iter[j]);
+          opts->trace[3 * (checks - 1) + 1] = last.E;
+          opts->trace[3 * (checks - 1) + 2] = last.rel_gap;
+        }
+        WDB_REQUIRE(std::isfinite(last.E), WDB_ERR_DIVERGED, "objective became non-finite at iteration %d",
+                    k0 - 1 + at_iter[j]);
       }
     }
     if (total == 0) {

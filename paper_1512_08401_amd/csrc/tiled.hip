@@ -72,11 +72,11 @@ __host__ __device__ inline int tile_row(const int4& d, int t) {
 
 // Partial sums of the W wavefronts added in wavefront order, then the
 // row's escape entries; the result is complete in wavefront 0.
-template <int W>
-__device__ __forceinline__ float tile_finish(const TiledView& T, const int4& d, int row, int lane, int wv, float acc,
-                                             const float* __restrict__ x) {
+template <int W, typename A, typename X>
+__device__ __forceinline__ A tile_finish(const TiledView& T, const int4& d, int row, int lane, int wv, A acc,
+                                         const X* __restrict__ x) {
   if constexpr (W > 1) {
-    __shared__ float part[W][64];
+    __shared__ A part[W][64];
     part[wv][lane] = acc;
     __syncthreads();
     if (wv == 0) {
@@ -85,7 +85,7 @@ __device__ __forceinline__ float tile_finish(const TiledView& T, const int4& d, 
     }
   }
   if (wv == 0 && row >= 0 && (d.w & kHasEsc))
-    for (int k = T.erp[row]; k < T.erp[row + 1]; ++k) acc = fmaf(T.ev[k], x[T.ec[k]], acc);
+    for (int k = T.erp[row]; k < T.erp[row + 1]; ++k) acc = fma(static_cast<A>(T.ev[k]), static_cast<A>(x[T.ec[k]]), acc);
   return acc;
 }
 
@@ -114,7 +114,7 @@ __device__ __forceinline__ float tile_dot(const TiledView& T, const Geo& g, cons
       acc = fmaf(v[u].w, x[decode_col(g, rc, c[u].w)], acc);
     }
   }
-  return tile_finish<W>(T, d, row, lane, wv, acc, x);
+  return tile_finish<W, float>(T, d, row, lane, wv, acc, x);
 }
 
 // The same over 16-bit values: groups of 8 codes, one 16-byte vector of 8
@@ -145,7 +145,89 @@ __device__ __forceinline__ float tile_dot16(const TiledView& T, const Geo& g, co
         acc = fmaf(dq16<FMT>((vs[e >> 1] >> (16 * (e & 1))) & 0xFFFFu), x[decode_col(g, rc, cs[e])], acc);
     }
   }
-  return tile_finish<W>(T, d, row, lane, wv, acc, x);
+  return tile_finish<W, float>(T, d, row, lane, wv, acc, x);
+}
+
+// Float64 accumulation over the float32 tiles (the stopping test): x is
+// float32 (forward product) or float64 (the transposed product of the
+// float64 residual).
+template <int W, int U, typename X>
+__device__ __forceinline__ double tile_dot64(const TiledView& T, const Geo& g, const int4& d, int row, int lane,
+                                             int wv, const X* __restrict__ x) {
+  const RowCode rc = row_code(g, pos_of(g, row >= 0 ? row : d.z));
+  double acc = 0.0;
+  const int g1 = d.y >> 2;
+  for (int k = (d.x >> 2) + wv; k < g1; k += W * U) {
+    uint4 c[U];
+    float4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool ok = k + u * W < g1;
+      c[u] = ok ? T.code[k + u * W] : make_uint4(kPadCode, kPadCode, kPadCode, kPadCode);
+      v[u] = ok ? T.val[static_cast<int64_t>(k + u * W) * 64 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      acc = fma(static_cast<double>(v[u].x), static_cast<double>(x[decode_col(g, rc, c[u].x)]), acc);
+      acc = fma(static_cast<double>(v[u].y), static_cast<double>(x[decode_col(g, rc, c[u].y)]), acc);
+      acc = fma(static_cast<double>(v[u].z), static_cast<double>(x[decode_col(g, rc, c[u].z)]), acc);
+      acc = fma(static_cast<double>(v[u].w), static_cast<double>(x[decode_col(g, rc, c[u].w)]), acc);
+    }
+  }
+  return tile_finish<W, double>(T, d, row, lane, wv, acc, x);
+}
+
+// Sum (or max) of a float64 over the lanes of wavefront 0, written to
+// partial[blockIdx.x] by lane 0.
+template <bool MAX>
+__device__ __forceinline__ void wave0_partial(double v, int lane, double* __restrict__ partial) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_xor(v, off);
+    v = MAX ? fmax(v, o) : v + o;
+  }
+  if (lane == 0) partial[blockIdx.x] = v;
+}
+
+// Stopping test, forward half: r64 = Theta_K x - x0 in float64 and per-tile
+// partials of ||r||^2, <r, x0> and sum_i w_i |x_i|.
+template <int W, int U>
+__global__ __launch_bounds__(64 * W) void k_obj_fwd_tl(TiledView T, Geo g, const float* __restrict__ x,
+                                                       const float* __restrict__ b, const float* __restrict__ w,
+                                                       double* __restrict__ r64, double* __restrict__ partial,
+                                                       int64_t nblocks) {
+  const int4 d = T.desc[blockIdx.x];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int row = tile_row(d, lane);
+  const double acc = tile_dot64<W, U>(T, g, d, row, lane, wv, x);
+  if (wv != 0) return;
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+  if (row >= 0) {
+    const double bb = static_cast<double>(b[row]);
+    const double rr = acc - bb;
+    r64[row] = rr;
+    v0 = rr * rr;
+    v1 = rr * bb;
+    v2 = fabs(static_cast<double>(x[row])) * (w ? static_cast<double>(w[row]) : 1.0);
+  }
+  wave0_partial<false>(v0, lane, partial);
+  wave0_partial<false>(v1, lane, partial + nblocks);
+  wave0_partial<false>(v2, lane, partial + 2 * nblocks);
+}
+
+// Backward half: per-tile max of |(Theta_K^T r64)_i| / w_i.
+template <int W, int U>
+__global__ __launch_bounds__(64 * W) void k_obj_bwd_tl(TiledView T, Geo g, const double* __restrict__ r64,
+                                                       const float* __restrict__ w, double* __restrict__ partial) {
+  const int4 d = T.desc[blockIdx.x];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int row = tile_row(d, lane);
+  const double gr = tile_dot64<W, U>(T, g, d, row, lane, wv, r64);
+  if (wv != 0) return;
+  const double v = row >= 0 ? fabs(gr) / (w ? static_cast<double>(w[row]) : 1.0) : 0.0;
+  wave0_partial<true>(v, lane, partial);
 }
 
 template <int W, int U>
@@ -567,6 +649,24 @@ void launch_prox_tiled16(const wdb_theta* th, const float* rs, float* x, float* 
         hipLaunchKernelGGL((k_prox_tl16<W, U, WDB_VAL_F16, false>), grid, block, 0, s, tview(T), g, rs, x, y, tau,
                            thr, kdev, pinv, tw);
     }
+  });
+}
+
+int64_t tiled_check_blocks(const wdb_theta* th) {
+  WDB_REQUIRE(th->tA.desc && th->tAt.desc && th->tA.ntiles == th->tAt.ntiles, WDB_ERR_ARG,
+              "tiled storage not built");
+  return th->tA.ntiles;
+}
+
+void launch_objective_tiled(const wdb_theta* th, const float* x, const float* x0, double* r64, double* part,
+                            int64_t nb, hipStream_t s) {
+  WDB_REQUIRE(nb == tiled_check_blocks(th), WDB_ERR_ARG, "partial count does not match the tiles");
+  const Geo g = geo_of(th);
+  with_shape(th->tile_waves, th->tile_unroll, [&](auto Wc, auto Uc) {
+    constexpr int W = decltype(Wc)::value, U = decltype(Uc)::value;
+    const dim3 grid(static_cast<unsigned>(nb)), block(64 * W);
+    hipLaunchKernelGGL((k_obj_fwd_tl<W, U>), grid, block, 0, s, tview(th->tA), g, x, x0, th->l1w, r64, part, nb);
+    hipLaunchKernelGGL((k_obj_bwd_tl<W, U>), grid, block, 0, s, tview(th->tAt), g, r64, th->l1w, part + 3 * nb);
   });
 }
 

@@ -361,8 +361,13 @@ def test_lipschitz_matches_oracle(W, p64):
     assert abs(L - ev) <= 1e-8 * ev
 
 
-def test_objective_and_gap_match_oracle(W, p64):
+@pytest.mark.parametrize("layout", [None, (8, 3)])
+def test_objective_and_gap_match_oracle(W, p64, layout):
+    """The float64 stopping test on the default layout and on the tiled one
+    (its own float64 tile kernels), with uniform and scale weights."""
     th = imported(W, p64)
+    if layout:
+        th.set_kernel_layout(*layout)
     A32 = p64["A32"]
     x0 = p64["x0"].astype(np.float32)
     lam = p64["wl"].lam
@@ -372,6 +377,29 @@ def test_objective_and_gap_match_oracle(W, p64):
         Eo, Do, gap, relo = fista.duality_gap(A32, x0.astype(np.float64), np.float64(np.float32(lam)), x.astype(np.float64))
         assert abs(E - Eo) <= 1e-12 * Eo
         assert abs(rel - relo) <= 1e-10
+    th.set_l1_weights("scale")
+    w = dwt.scale_index(64, 3).astype(np.float64)
+    x = (np.random.default_rng(2).standard_normal(4096) * 0.01).astype(np.float32)
+    E, rel = th.objective(dev(x), dev(x0), lam)
+    Eo, Do, gap, relo = fista.duality_gap(A32, x0.astype(np.float64), np.float64(np.float32(lam)), x.astype(np.float64),
+                                          w=w)
+    assert abs(E - Eo) <= 1e-12 * Eo
+    assert abs(rel - relo) <= 1e-10
+
+
+def test_recorded_checks_match_synchronous_checks(W, p64):
+    """Without a stopping test the checks are read once at the end; the trace
+    equals the one of a solve whose stopping test never fires (synchronous
+    checks), check by check."""
+    th = imported(W, p64)
+    th.set_kernel_layout(8, 3)
+    wl = p64["wl"]
+    th.lipschitz(synth.power_start(4096, wl.power_seed))
+    x0 = p64["x0"].astype(np.float32)
+    xa, ia = th.solve_coeffs(dev(x0), wl.lam, 200, check_every=20, trace_cap=20)
+    xb, ib = th.solve_coeffs(dev(x0), wl.lam, 200, check_every=20, trace_cap=20, tol=1e-300)
+    assert np.array_equal(ia["trace"], ib["trace"]) and ia["objective"] == ib["objective"]
+    assert np.array_equal(host(xa), host(xb))
 
 
 # ---------------------------------------------------------------------------
