@@ -21,7 +21,7 @@ import numpy as np
 
 __all__ = [
     "piecewise_image", "noise", "psf_isotropic", "psf_rotating", "PsfField",
-    "power_start", "banded_operator", "Workload", "WORKLOADS", "batched_problems",
+    "power_start", "banded_operator", "local_operator", "Workload", "WORKLOADS", "batched_problems",
 ]
 
 
@@ -136,6 +136,93 @@ def banded_operator(size: int, nnz_per_row: float, seed: int, far_fraction: floa
     np.add.at(rowptr, r + 1, 1)
     rowptr = np.cumsum(rowptr)
     return rowptr, c, val
+
+
+def _bands(n: int, levels: int):
+    """(level, orientation, side, first index) of each subband in canonical
+    order: the coarsest approximation, then per level J..1 the three details."""
+    out = [(levels, 3, n >> levels, 0)]
+    for lev in range(levels, 0, -1):
+        sd = n >> lev
+        for o in range(3):
+            out.append((lev, o, sd, (o + 1) * sd * sd))
+    return out
+
+
+def local_operator(n: int, levels: int, nnz_per_px: float, seed: int, radius: int = 3):
+    """A seeded sparse N x N matrix (N = n^2, rows and columns in canonical
+    subband order) with the storage-relevant structure of a thresholded
+    wavelet-domain operator of a slowly varying blur, at full size.
+
+    Row a (subband of level la, position (i, j)) keeps entries in the subbands
+    of levels la - 1 .. la + 1 at displacements |di|, |dj| <= radius around
+    (i, j) scaled to the column subband's side, with magnitude
+    amp * exp(-(di^2 + dj^2) / (2 w^2)): amp = 2^-|level gap| (times 0.35
+    across orientations) and a width w that grows smoothly from 0.7 to 2.3
+    across the image columns.  Entries above one global level tau are kept,
+    tau chosen so that about nnz_per_px * n^2 entries survive; each kept value
+    gets a random sign and 5 % multiplicative noise.  Returns (rowptr int64,
+    col int32, val float64).
+    """
+    rng = np.random.default_rng(seed)
+    N = n * n
+    bands = _bands(n, levels)
+    offs = np.arange(-radius, radius + 1)
+    DI, DJ = (a.ravel() for a in np.meshgrid(offs, offs, indexing="ij"))
+    d2 = (DI * DI + DJ * DJ).astype(np.float64)
+    pairs = [(A, B, 0.5 ** abs(A[0] - B[0]) * (1.0 if A[1] == B[1] else 0.35))
+             for A in bands for B in bands if abs(A[0] - B[0]) <= 1]
+
+    def width(A):
+        sa = A[2]
+        j = np.arange(sa * sa) % sa
+        return 0.7 + 1.6 * (j + 0.5) / sa
+
+    widths = {A[3]: width(A) for A in bands}
+    d2v, d2c = np.unique(d2, return_counts=True)
+
+    cum = np.concatenate([[0], np.cumsum(d2c)])   # entries with d2 below the k-th distinct value
+
+    def count(tau):
+        tot = 0
+        for A, B, amp in pairs:
+            if amp > tau:   # kept iff d2 < 2 w^2 ln(amp / tau)
+                lim = 2.0 * widths[A[3]] ** 2 * math.log(amp / tau)
+                tot += int(cum[np.searchsorted(d2v, lim, side="left")].sum())
+        return tot
+
+    target = nnz_per_px * N
+    lo, hi = 1e-12, 1.0
+    for _ in range(60):
+        mid = math.sqrt(lo * hi)
+        if count(mid) > target:
+            lo = mid
+        else:
+            hi = mid
+    tau = hi
+    rows, cols, mags = [], [], []
+    for A, B, amp in pairs:
+        if amp <= tau:
+            continue
+        (la, oa, sa, fa), (lb, ob, sb, fb) = A, B
+        i, j = np.divmod(np.arange(sa * sa), sa)
+        ci, cj = (i * sb) // sa, (j * sb) // sa
+        mag = amp * np.exp(-d2[None, :] / (2.0 * widths[fa][:, None] ** 2))
+        keep = mag > tau
+        rr, kk = np.nonzero(keep)
+        rows.append(fa + rr)
+        cols.append(fb + ((ci[rr] + DI[kk]) % sb) * sb + (cj[rr] + DJ[kk]) % sb)
+        mags.append(mag[rr, kk])
+    r = np.concatenate(rows).astype(np.int64)
+    c = np.concatenate(cols).astype(np.int64)
+    m = np.concatenate(mags)
+    key, first = np.unique(r * N + c, return_index=True)   # sorted by (row, col); wrap duplicates dropped
+    m = m[first]
+    val = m * np.where(rng.random(m.size) < 0.5, -1.0, 1.0) * (1.0 + 0.05 * rng.standard_normal(m.size))
+    r = key // N
+    rowptr = np.zeros(N + 1, dtype=np.int64)
+    np.add.at(rowptr, r + 1, 1)
+    return np.cumsum(rowptr), (key % N).astype(np.int32), val
 
 
 @dataclass
