@@ -11,9 +11,17 @@
 // float64 checks can be replayed from a captured HIP graph.  Each right-hand
 // side has its own lambda and its own stop flag (a converged problem keeps
 // its iterate while the others continue).
+//
+// Operators whose iteration layout is the tiled pattern storage run their
+// chunks on the tiles instead: one 256-thread block (4 wavefronts) per tile,
+// lane = row, and for every shared column code each lane loads its column's
+// 8 right-hand-side values (32 contiguous bytes; neighbouring lanes of a tile
+// row read neighbouring columns) and the tile value once for all eight.  The
+// float64 checks stay on the sliced-ELL copies.
 #include <cmath>
 #include <map>
 
+#include "codes.hpp"
 #include "common.hpp"
 
 namespace wdb {
@@ -46,6 +54,15 @@ struct ChunkDev {
   float thr[kR];     // tau * lambda_j
   const int* act;    // stop flags (1 = keep iterating) and, at [8], "any active"; written by the host between replays
   double* r64;       // [N][8] float64 residual for the checks
+  // tiled pattern storage of Theta_K / Theta_K^T (ntiles > 0): block b of the chunk is tile b
+  int64_t ntiles;
+  Geo geo;
+  const int4* tdesc[2];
+  const uint4* tcode[2];
+  const float4* tval[2];
+  const int* terp[2];
+  const int* tec[2];
+  const float* tev[2];
 };
 
 __device__ __forceinline__ int chunk_of(const int* __restrict__ first, int nchunks, int blk) {
@@ -86,12 +103,62 @@ __device__ __forceinline__ void slice_mm(const int64_t* __restrict__ soff, const
   }
 }
 
+// Tile `tile` of copy m (0: Theta_K, 1: Theta_K^T) times the [N][8] block V:
+// acc[8] of the lane's row, complete in wavefront 0 (partials of the four
+// wavefronts added in LDS in wavefront order, then the row's escapes).
+__device__ __forceinline__ int tile_mm(const ChunkDev& C, int m, int tile, const float* __restrict__ V,
+                                       float (&acc)[kR]) {
+  __shared__ float part[kWaves][kR][kWave];
+  const int4 d = C.tdesc[m][tile];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int row = tile_row(d, lane);
+  const RowCode rc = row_code(C.geo, pos_of(C.geo, row >= 0 ? row : d.z));
+  const uint4* __restrict__ code = C.tcode[m];
+  const float4* __restrict__ val = C.tval[m];
+  for (int k = (d.x >> 2) + wv; k < (d.y >> 2); k += kWaves) {
+    const uint4 c = code[k];
+    const float4 v = val[static_cast<int64_t>(k) * kWave + lane];
+    gather8(V, decode_col(C.geo, rc, c.x), v.x, acc);
+    gather8(V, decode_col(C.geo, rc, c.y), v.y, acc);
+    gather8(V, decode_col(C.geo, rc, c.z), v.z, acc);
+    gather8(V, decode_col(C.geo, rc, c.w), v.w, acc);
+  }
+#pragma unroll
+  for (int j = 0; j < kR; ++j) part[wv][j][lane] = acc[j];
+  __syncthreads();
+  if (wv == 0) {
+#pragma unroll
+    for (int j = 0; j < kR; ++j) {
+      float a = part[0][j][lane];
+      for (int w = 1; w < kWaves; ++w) a += part[w][j][lane];
+      acc[j] = a;
+    }
+    if (row >= 0 && (d.w & kHasEsc))
+      for (int k = C.terp[m][row]; k < C.terp[m][row + 1]; ++k) gather8(V, C.tec[m][k], C.tev[m][k], acc);
+  }
+  return wv == 0 ? row : -1;
+}
+
 __global__ __launch_bounds__(kBlock) void k_res_batched(const ChunkDev* __restrict__ ch, const int* __restrict__ first,
                                                         int nchunks, int* __restrict__ kdev) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *kdev += 1;
   const int c = chunk_of(first, nchunks, blockIdx.x);
   const ChunkDev& C = ch[c];
   if (!C.act[kR]) return;  // every problem of this chunk has stopped
+  if (C.ntiles) {
+    const int tile = blockIdx.x - first[c];
+    if (tile >= C.ntiles) return;  // the chunk's block range also covers its sliced-ELL checks
+    float acc[kR] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int row = tile_mm(C, 0, tile, C.Y, acc);
+    if (row < 0) return;
+    const float4* b = reinterpret_cast<const float4*>(C.X0 + static_cast<int64_t>(row) * kR);
+    float4* r = reinterpret_cast<float4*>(C.Rr + static_cast<int64_t>(row) * kR);
+    const float4 b0 = b[0], b1 = b[1];
+    r[0] = make_float4(acc[0] - b0.x, acc[1] - b0.y, acc[2] - b0.z, acc[3] - b0.w);
+    r[1] = make_float4(acc[4] - b1.x, acc[5] - b1.y, acc[6] - b1.z, acc[7] - b1.w);
+    return;
+  }
   const int64_t q = static_cast<int64_t>(blockIdx.x - first[c]) * kBlock + threadIdx.x;
   if (q >= (C.nslices << C.cshift)) return;
   const int64_t sl = q >> C.cshift;
@@ -112,13 +179,20 @@ __global__ __launch_bounds__(kBlock) void k_prox_batched(const ChunkDev* __restr
   const int c = chunk_of(first, nchunks, blockIdx.x);
   const ChunkDev& C = ch[c];
   if (!C.act[kR]) return;  // every problem of this chunk has stopped
-  const int64_t q = static_cast<int64_t>(blockIdx.x - first[c]) * kBlock + threadIdx.x;
-  if (q >= (C.nslicesT << C.cshift)) return;
-  const int64_t sl = q >> C.cshift;
-  const int lane = static_cast<int>(q & (C.C - 1));
   float g[kR] = {0, 0, 0, 0, 0, 0, 0, 0};
-  slice_mm(C.soffT, C.valT, C.colT, sl, lane, C.C, C.Rr, g);
-  const int64_t row = slot_row_c(C.permT, C.nrows, q);
+  int64_t row;
+  if (C.ntiles) {
+    const int tile = blockIdx.x - first[c];
+    if (tile >= C.ntiles) return;
+    row = tile_mm(C, 1, tile, C.Rr, g);
+  } else {
+    const int64_t q = static_cast<int64_t>(blockIdx.x - first[c]) * kBlock + threadIdx.x;
+    if (q >= (C.nslicesT << C.cshift)) return;
+    const int64_t sl = q >> C.cshift;
+    const int lane = static_cast<int>(q & (C.C - 1));
+    slice_mm(C.soffT, C.valT, C.colT, sl, lane, C.C, C.Rr, g);
+    row = slot_row_c(C.permT, C.nrows, q);
+  }
   if (row < 0) return;
   const int k = *kdev;
   const float beta = static_cast<float>((static_cast<double>(k) - 1.0) / (static_cast<double>(k) + 2.0));
@@ -331,6 +405,7 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
       h.blocks_res = static_cast<int>((th->A.nslices * th->A.C + kBlock - 1) / kBlock);
       h.blocks_prox = static_cast<int>((th->At.nslices * th->At.C + kBlock - 1) / kBlock);
       h.blocks = std::max(h.blocks_res, h.blocks_prox);
+      if (kernel_group(th) == kTiled) h.blocks = std::max<int>(h.blocks, static_cast<int>(th->tA.ntiles));
       chunks.push_back(std::move(h));
     }
   }
@@ -374,6 +449,21 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
     d.tau = static_cast<float>(tau);
     d.act = h.act.p;
     d.r64 = h.r64.p;
+    d.ntiles = 0;
+    if (kernel_group(th) == kTiled) {  // the operator iterates on its tiled copies
+      WDB_REQUIRE(th->tA.ntiles == th->tAt.ntiles, WDB_ERR_ARG, "mismatched tile lists");
+      d.ntiles = th->tA.ntiles;
+      d.geo = geo_of(th);
+      const Tiled* T[2] = {&th->tA, &th->tAt};
+      for (int m = 0; m < 2; ++m) {
+        d.tdesc[m] = reinterpret_cast<const int4*>(T[m]->desc);
+        d.tcode[m] = reinterpret_cast<const uint4*>(T[m]->code);
+        d.tval[m] = reinterpret_cast<const float4*>(T[m]->val);
+        d.terp[m] = T[m]->erp;
+        d.tec[m] = T[m]->ec;
+        d.tev[m] = T[m]->ev;
+      }
+    }
     const Filter f = make_filter(th->wavelet);
     const size_t q = static_cast<size_t>(th->n / 2) * (th->n / 2);
     std::vector<int>& act = h.act_host;

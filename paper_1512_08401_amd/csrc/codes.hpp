@@ -1,5 +1,5 @@
 // Band-relative column codes shared by the packed 16-bit form and the tiled
-// pattern storage.
+// pattern storage, and the tile descriptors of the latter.
 //
 // An entry theta[a, b] is only large when the supports of the two atoms are
 // close in space and in scale (the decay bound of Sec. 3.2).  For a row
@@ -102,6 +102,19 @@ __host__ __device__ inline int encode_col(const Geo& g, const Pos& p, int64_t co
   if (di < -kDOff || di >= kDOff || dj < -kDOff || dj >= kDOff) return -1;
   const int slot = q.orient == 3 ? 0 : q.orient + 1;
   return ((dL + kLMax) << 13) | (slot << 11) | ((di + kDOff) << 5) | (dj + kDOff);
+}
+
+// Tile descriptors of the tiled pattern storage: int4 {first code, end code,
+// first row, log2 side | flags}.
+constexpr int kSmall = 1 << 8;   // flag: tile = a whole subband of side < 8, rows first + t for t < count
+constexpr int kHasEsc = 1 << 30; // flag: some row of the tile has escape entries
+
+// Row of lane t of a tile (8 x 8 positions, lane t at (t / 8, t mod 8)), or
+// -1 for an idle lane of a small subband.
+__host__ __device__ inline int tile_row(const int4& d, int t) {
+  if (d.w & kSmall) return t < ((d.w >> 16) & 0x7F) ? d.z + t : -1;
+  const int ls = d.w & 0xFF;
+  return d.z + ((t >> 3) << ls) + (t & 7);
 }
 
 inline Geo geo_of(const wdb_theta* th) {

@@ -38,9 +38,6 @@ namespace wdb {
 
 namespace {
 
-constexpr int kSmall = 1 << 8;   // flag: tile = a whole subband of side < 8, rows first + t for t < count
-constexpr int kHasEsc = 1 << 30; // flag: some row of the tile has escape entries
-
 struct TiledView {
   const int4* __restrict__ desc;
   const uint4* __restrict__ code;
@@ -61,13 +58,6 @@ template <int FMT>
 __device__ __forceinline__ float dq16(uint32_t h) {
   if constexpr (FMT == WDB_VAL_BF16) return __uint_as_float(h << 16);
   else return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(h)));
-}
-
-// Row of lane t of a tile, or -1 for an idle lane of a small subband.
-__host__ __device__ inline int tile_row(const int4& d, int t) {
-  if (d.w & kSmall) return t < ((d.w >> 16) & 0x7F) ? d.z + t : -1;
-  const int ls = d.w & 0xFF;
-  return d.z + ((t >> 3) << ls) + (t & 7);
 }
 
 // Partial sums of the W wavefronts added in wavefront order, then the

@@ -775,10 +775,16 @@ def small32():
     return {"field": field, "h": h, "A": A, "A32": A32, "H": blur.blur_matrix(field)}
 
 
-def test_batched_matches_oracle_per_problem(W, p64, small32):
+@pytest.mark.parametrize("tiled64", [False, True])
+def test_batched_matches_oracle_per_problem(W, p64, small32, tiled64):
+    """13 problems on two operators (chunks of 8 + 2 and 3); with tiled64 the
+    64 x 64 operator's chunks run on its tiled copies while the 32 x 32 one
+    stays on sliced ELL, in the same launches."""
     th64 = imported(W, p64)
     rp, cc, vv = theta.csr_arrays(small32["A"])
     th32 = W.Theta.from_csr(32, "haar", 2, rp, cc, vv)
+    if tiled64:
+        th64.set_kernel_layout(8, 3)
     wl = p64["wl"]
     start64, start32 = synth.power_start(4096, 3), synth.power_start(1024, 4)
     th64.lipschitz(start64)
