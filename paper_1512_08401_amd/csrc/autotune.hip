@@ -157,6 +157,8 @@ void tune_packed(wdb_theta* th, const char* cache_path, const std::string& key, 
   } else {  // the 16-bit tiled copies are only kept when they are the layout in use
     th->qA.free_all();
     th->qAt.free_all();
+    th->tile_waves16 = 4;
+    th->tile_unroll16 = 1;
   }
 }
 
@@ -273,6 +275,8 @@ extern "C" wdb_status wdb_autotune(wdb_theta* th, const char* cache_path, int32_
   } else {  // the tiled copies are only kept when they are the layout in use
     th->tA.free_all();
     th->tAt.free_all();
+    th->tile_waves = 4;
+    th->tile_unroll = 2;
   }
   if (th->valtype != WDB_VAL_F32) {
     const int vt = th->valtype;
