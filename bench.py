@@ -279,7 +279,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def time_to_tolerance(th, u0, wl, torch, wdb, synth, N, targets=(1e-4, 1e-6)):
+def time_to_tolerance(th, u0, wl, torch, wdb, synth, N, targets=(1e-4, 1e-6, 1e-8)):
     """Seconds (and iterations) to reach rho_k = (E(x_k) - E*)/E(0) <= target,
     E(0) = ||x0||^2/2 (the same normaliser for every form).
 
