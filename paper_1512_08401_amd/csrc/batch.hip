@@ -104,8 +104,8 @@ __device__ __forceinline__ void slice_mm(const int64_t* __restrict__ soff, const
 }
 
 // Tile `tile` of copy m (0: Theta_K, 1: Theta_K^T) times the [N][8] block V:
-// acc[8] of the lane's row, complete in wavefront 0 (partials of the four
-// wavefronts added in LDS in wavefront order, then the row's escapes).
+// acc[8] of the lane's row, complete in wavefront 0 (the row's escapes dealt
+// to the four wavefronts, whose partials are added in LDS in wavefront order).
 __device__ __forceinline__ int tile_mm(const ChunkDev& C, int m, int tile, const float* __restrict__ V,
                                        float (&acc)[kR]) {
   __shared__ float part[kWaves][kR][kWave];
@@ -124,6 +124,8 @@ __device__ __forceinline__ int tile_mm(const ChunkDev& C, int m, int tile, const
     gather8(V, decode_col(C.geo, rc, c.z), v.z, acc);
     gather8(V, decode_col(C.geo, rc, c.w), v.w, acc);
   }
+  if (row >= 0 && (d.w & kHasEsc))  // escapes dealt round-robin to the wavefronts
+    for (int k = C.terp[m][row] + wv; k < C.terp[m][row + 1]; k += kWaves) gather8(V, C.tec[m][k], C.tev[m][k], acc);
 #pragma unroll
   for (int j = 0; j < kR; ++j) part[wv][j][lane] = acc[j];
   __syncthreads();
@@ -134,8 +136,6 @@ __device__ __forceinline__ int tile_mm(const ChunkDev& C, int m, int tile, const
       for (int w = 1; w < kWaves; ++w) a += part[w][j][lane];
       acc[j] = a;
     }
-    if (row >= 0 && (d.w & kHasEsc))
-      for (int k = C.terp[m][row]; k < C.terp[m][row + 1]; ++k) gather8(V, C.tec[m][k], C.tev[m][k], acc);
   }
   return wv == 0 ? row : -1;
 }

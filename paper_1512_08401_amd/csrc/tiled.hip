@@ -60,11 +60,15 @@ __device__ __forceinline__ float dq16(uint32_t h) {
   else return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(h)));
 }
 
-// Partial sums of the W wavefronts added in wavefront order, then the
-// row's escape entries; the result is complete in wavefront 0.
+// The row's escape entries (wavefront w takes entries w, w + W, ...), then the
+// partial sums of the W wavefronts added in wavefront order; the result is
+// complete in wavefront 0.
 template <int W, typename A, typename X>
 __device__ __forceinline__ A tile_finish(const TiledView& T, const int4& d, int row, int lane, int wv, A acc,
                                          const X* __restrict__ x) {
+  if (row >= 0 && (d.w & kHasEsc))  // the row's escape entries, dealt round-robin to the wavefronts
+    for (int k = T.erp[row] + wv; k < T.erp[row + 1]; k += W)
+      acc = fma(static_cast<A>(T.ev[k]), static_cast<A>(x[T.ec[k]]), acc);
   if constexpr (W > 1) {
     __shared__ A part[W][64];
     part[wv][lane] = acc;
@@ -74,8 +78,6 @@ __device__ __forceinline__ A tile_finish(const TiledView& T, const int4& d, int 
       for (int w = 1; w < W; ++w) acc += part[w][lane];
     }
   }
-  if (wv == 0 && row >= 0 && (d.w & kHasEsc))
-    for (int k = T.erp[row]; k < T.erp[row + 1]; ++k) acc = fma(static_cast<A>(T.ev[k]), static_cast<A>(x[T.ec[k]]), acc);
   return acc;
 }
 
