@@ -73,6 +73,7 @@ void Csr::free_all() {
 }
 
 void free_workspace(wdb_theta* th) {
+  drop_graph(th);
   float* fs[] = {th->ws_x0, th->ws_r, th->ws_y, th->ws_img, th->ws_img2, th->pinv};
   for (float* p : fs)
     if (p) (void)hipFree(p);

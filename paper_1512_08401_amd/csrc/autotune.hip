@@ -169,6 +169,7 @@ extern "C" wdb_status wdb_autotune(wdb_theta* th, const char* cache_path, int32_
   using namespace wdb;
   WDB_API_BEGIN
   WDB_REQUIRE(th, WDB_ERR_ARG, "null handle");
+  wdb::drop_graph(th);  // the cached iteration graph may refer to what this call changes
   WDB_REQUIRE(reps >= 1, WDB_ERR_ARG, "reps must be >= 1");
   WDB_HIP(hipSetDevice(th->device));
   ensure_workspace(th);
@@ -295,6 +296,7 @@ extern "C" wdb_status wdb_set_kernel_layout(wdb_theta* th, int32_t slice, int32_
   using namespace wdb;
   WDB_API_BEGIN
   WDB_REQUIRE(th, WDB_ERR_ARG, "null handle");
+  wdb::drop_graph(th);  // the cached iteration graph may refer to what this call changes
   WDB_REQUIRE(slice >= 8 && slice <= kSliceMax && (slice & (slice - 1)) == 0, WDB_ERR_ARG,
               "slice height must be 8, 16, 32 or 64");
   WDB_REQUIRE(group == 0 || group == 2 || group == 4 || group == 8 || group == 16 || group == 32 || group == 64 ||

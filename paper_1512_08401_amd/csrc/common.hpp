@@ -283,10 +283,20 @@ struct wdb_theta {
   double* ws_rho = nullptr;      // power-iteration history (64 entries)
   int64_t ws_nblocks = 0;
   hipStream_t capture_stream = nullptr;
+  // Instantiated graph of `g_c` iterations of the last graph-replayed solve and
+  // the parameters it was captured with; dropped by every call that changes the
+  // handle (layout, precision, preconditioner, weights, L), so a replay only
+  // ever sees the storage it was captured on.
+  hipGraph_t g_graph = nullptr;
+  hipGraphExec_t g_exec = nullptr;
+  const float* g_x = nullptr;
+  int g_c = 0, g_pre = 0, g_ista = 0;
+  float g_tau = 0.0f, g_thr = 0.0f;
 };
 
 namespace wdb {
 void ensure_workspace(wdb_theta* th);
+void drop_graph(wdb_theta* th);  // destroys the cached iteration graph (if any)
 void free_workspace(wdb_theta* th);
 void finish_theta(wdb_theta* th, hipStream_t s);   // builds A/At from csr
 void set_slice_height(wdb_theta* th, int C, hipStream_t s);  // rebuilds A/At with slices of C rows

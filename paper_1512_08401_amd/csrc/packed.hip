@@ -317,6 +317,7 @@ void launch_prox_packed(const wdb_theta* th, int G, const float* rs, float* x, f
 extern "C" wdb_status wdb_set_packed_group(wdb_theta* th, int32_t group) {
   WDB_API_BEGIN
   WDB_REQUIRE(th, WDB_ERR_ARG, "null handle");
+  wdb::drop_graph(th);  // the cached iteration graph may refer to what this call changes
   WDB_REQUIRE(group == 0 || group == 2 || group == 4 || group == 8 || group == 16 || group == wdb::kTiled, WDB_ERR_ARG,
               "lanes per row of the packed kernels must be 0, 2, 4, 8 or 16, or 3 (16-bit tiled layout)");
   if (group == wdb::kTiled) wdb::build_tiled16(th);

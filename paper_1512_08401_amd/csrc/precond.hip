@@ -95,6 +95,7 @@ extern "C" wdb_status wdb_set_precond(wdb_theta* th, int32_t kind, double eps, c
   using namespace wdb;
   WDB_API_BEGIN
   WDB_REQUIRE(th, WDB_ERR_ARG, "null handle");
+  wdb::drop_graph(th);  // the cached iteration graph may refer to what this call changes
   WDB_REQUIRE(kind >= WDB_PRECOND_NONE && kind <= WDB_PRECOND_JACOBI, WDB_ERR_ARG, "unknown preconditioner %d", kind);
   WDB_HIP(hipSetDevice(th->device));
   if (kind == WDB_PRECOND_NONE) {

@@ -91,6 +91,7 @@ extern "C" wdb_status wdb_set_precision(wdb_theta* th, int32_t valtype) {
   using namespace wdb;
   WDB_API_BEGIN
   WDB_REQUIRE(th, WDB_ERR_ARG, "null handle");
+  wdb::drop_graph(th);  // the cached iteration graph may refer to what this call changes
   WDB_REQUIRE(valtype == WDB_VAL_F32 || valtype == WDB_VAL_BF16 || valtype == WDB_VAL_F16, WDB_ERR_ARG,
               "unknown value type %d", valtype);
   WDB_HIP(hipSetDevice(th->device));

@@ -706,6 +706,15 @@ uint64_t splitmix64(uint64_t& state) {
 
 }  // namespace
 
+void drop_graph(wdb_theta* th) {
+  if (th->g_exec) (void)hipGraphExecDestroy(th->g_exec);
+  if (th->g_graph) (void)hipGraphDestroy(th->g_graph);
+  th->g_exec = nullptr;
+  th->g_graph = nullptr;
+  th->g_x = nullptr;
+  th->g_c = 0;
+}
+
 void ensure_workspace(wdb_theta* th) {
   if (th->ws_x0) return;
   const int64_t N = th->N;
@@ -933,21 +942,35 @@ wdb_status solve_impl(wdb_theta* th, const float* x0_src, bool from_image, float
   Check last{0.0, 0.0};
   bool converged = false;
   hipGraphExec_t exec = nullptr;
-  hipGraph_t graph = nullptr;
-  auto cleanup = [&]() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    exec = nullptr;
-    graph = nullptr;
-  };
   try {
     const bool use_graph = opts->use_graph && c > 1;
     if (use_graph && total >= c) {
-      if (!th->capture_stream) WDB_HIP(hipStreamCreateWithFlags(&th->capture_stream, hipStreamNonBlocking));
-      WDB_HIP(hipStreamBeginCapture(th->capture_stream, hipStreamCaptureModeThreadLocal));
-      for (int i = 0; i < c; ++i) launch_iteration(th, x_out, pre, opts->ista != 0, tau_f, thr_f, th->capture_stream);
-      WDB_HIP(hipStreamEndCapture(th->capture_stream, &graph));
-      WDB_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+      const int ista = opts->ista != 0 ? 1 : 0;
+      if (!(th->g_exec && th->g_x == x_out && th->g_c == c && th->g_pre == (pre ? 1 : 0) && th->g_ista == ista &&
+            th->g_tau == tau_f && th->g_thr == thr_f)) {
+        drop_graph(th);
+        if (!th->capture_stream) WDB_HIP(hipStreamCreateWithFlags(&th->capture_stream, hipStreamNonBlocking));
+        WDB_HIP(hipStreamBeginCapture(th->capture_stream, hipStreamCaptureModeThreadLocal));
+        try {
+          for (int i = 0; i < c; ++i) launch_iteration(th, x_out, pre, ista != 0, tau_f, thr_f, th->capture_stream);
+        } catch (...) {  // end the capture so the stream stays usable
+          hipGraph_t g = nullptr;
+          (void)hipStreamEndCapture(th->capture_stream, &g);
+          if (g) (void)hipGraphDestroy(g);
+          throw;
+        }
+        hipGraph_t graph = nullptr;
+        WDB_HIP(hipStreamEndCapture(th->capture_stream, &graph));
+        th->g_graph = graph;
+        WDB_HIP(hipGraphInstantiate(&th->g_exec, graph, nullptr, nullptr, 0));
+        th->g_x = x_out;
+        th->g_c = c;
+        th->g_pre = pre ? 1 : 0;
+        th->g_ista = ista;
+        th->g_tau = tau_f;
+        th->g_thr = thr_f;
+      }
+      exec = th->g_exec;
     }
     // Without a stopping test the checks are only recorded: their scalars go to
     // a device array and are read once at the end, so the host never waits
@@ -1016,10 +1039,10 @@ wdb_status solve_impl(wdb_theta* th, const float* x0_src, bool from_image, float
       ++checks;
     }
   } catch (...) {
-    cleanup();
+    (void)hipStreamSynchronize(s);  // no replay in flight when the graph goes
+    drop_graph(th);                 // a failed capture or replay leaves no graph behind
     throw;
   }
-  cleanup();
   if (info) {
     info->iters = done;
     info->checks = checks;
@@ -1044,6 +1067,7 @@ wdb_status wdb_theta_lipschitz(wdb_theta* th, const double* start, double tol, i
                                int32_t* iters_out) {
   WDB_API_BEGIN
   WDB_REQUIRE(th, WDB_ERR_ARG, "null handle");
+  wdb::drop_graph(th);  // the cached iteration graph may refer to what this call changes
   WDB_HIP(hipSetDevice(th->device));
   int it = 0;
   const double L = wdb::power_iteration(th, start, nullptr, tol, max_iters, &it, nullptr);

@@ -696,6 +696,7 @@ void launch_prox_tiled(const wdb_theta* th, const float* r, float* x, float* y, 
 extern "C" wdb_status wdb_set_tile_shape(wdb_theta* th, int32_t waves, int32_t unroll) {
   WDB_API_BEGIN
   WDB_REQUIRE(th, WDB_ERR_ARG, "null handle");
+  wdb::drop_graph(th);  // the cached iteration graph may refer to what this call changes
   WDB_REQUIRE(waves == 1 || waves == 2 || waves == 4 || waves == 8, WDB_ERR_ARG,
               "wavefronts per tile must be 1, 2, 4 or 8");
   WDB_REQUIRE(unroll == 0 || unroll == 1 || unroll == 2 || unroll == 4, WDB_ERR_ARG,

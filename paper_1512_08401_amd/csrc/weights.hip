@@ -42,6 +42,7 @@ extern "C" wdb_status wdb_set_l1_weights(wdb_theta* th, int32_t kind, const floa
   using namespace wdb;
   WDB_API_BEGIN
   WDB_REQUIRE(th, WDB_ERR_ARG, "null handle");
+  wdb::drop_graph(th);  // the cached iteration graph may refer to what this call changes
   WDB_REQUIRE(kind >= WDB_L1_UNIFORM && kind <= WDB_L1_GIVEN, WDB_ERR_ARG, "unknown weight kind %d", kind);
   WDB_REQUIRE(kind != WDB_L1_GIVEN || w, WDB_ERR_ARG, "weights array is null");
   WDB_HIP(hipSetDevice(th->device));

@@ -387,6 +387,39 @@ def test_objective_and_gap_match_oracle(W, p64, layout):
     assert abs(rel - relo) <= 1e-10
 
 
+def test_cached_graph_replays_and_follows_changes(W, p64):
+    """A graph-replayed solve keeps its instantiated graph in the handle: a
+    second solve with the same parameters replays it, other parameters or any
+    change of the handle (layout, preconditioner, weights) capture a new one;
+    every result equals the solve without a graph, bit for bit."""
+    th = imported(W, p64)
+    th.set_kernel_layout(8, 3)
+    wl = p64["wl"]
+    start = synth.power_start(4096, wl.power_seed)
+    th.lipschitz(start)
+    x0 = dev(p64["x0"].astype(np.float32))
+    out = torch.empty(4096, device="cuda")
+
+    def both(lam, **kw):
+        ref, _ = th.solve_coeffs(x0, lam, 100, check_every=20, **kw)
+        ref = host(ref)
+        for _ in range(2):   # capture, then replay of the cached graph
+            x, _ = th.solve_coeffs(x0, lam, 100, check_every=20, use_graph=True, out=out, **kw)
+            assert np.array_equal(host(x), ref)
+        return ref
+
+    a = both(wl.lam)
+    b = both(2 * wl.lam)
+    assert not np.array_equal(a, b)
+    th.set_kernel_layout(8, 4)
+    both(wl.lam)
+    th.set_precond("spai_scale", start=start)
+    both(wl.lam, precond=True)
+    th.set_l1_weights("scale")
+    both(wl.lam, precond=True)
+    both(wl.lam, ista=True)
+
+
 def test_recorded_checks_match_synchronous_checks(W, p64):
     """Without a stopping test the checks are read once at the end; the trace
     equals the one of a solve whose stopping test never fires (synchronous
