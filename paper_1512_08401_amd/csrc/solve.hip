@@ -454,25 +454,35 @@ __global__ __launch_bounds__(kBlock) void k_obj_bwd(SellView At, const double* _
 }
 
 // Single block: out[k] = reduction of partial[k * nblocks ...] in a fixed order.
-__global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ partial, int64_t nblocks, int nv,
-                                                   unsigned maxmask, double* __restrict__ out) {
-  __shared__ double sh[kBlock];
-  for (int k = 0; k < nv; ++k) {
-    const bool mx = (maxmask >> k) & 1u;
-    double acc = mx ? 0.0 : 0.0;
-    for (int64_t i = threadIdx.x; i < nblocks; i += kBlock) {
-      const double p = partial[k * nblocks + i];
-      acc = mx ? fmax(acc, p) : acc + p;
+// Final reduction of the stopping test's per-block partials: out[k] = sum (or
+// max, bit k of maxmask) of partial[k * nblocks + i] over i, for k < 4.  One
+// block of 1024 threads; each thread folds its strided share of all four rows
+// at once (every load of a pass independent of the others), then a fixed tree.
+constexpr int kReduceThreads = 1024;
+__global__ __launch_bounds__(kReduceThreads) void k_reduce4(const double* __restrict__ partial, int64_t nblocks,
+                                                            unsigned maxmask, double* __restrict__ out) {
+  __shared__ double sh[4][kReduceThreads];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t i = threadIdx.x; i < nblocks; i += kReduceThreads) {
+    double p[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) p[k] = partial[k * nblocks + i];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] = ((maxmask >> k) & 1u) ? fmax(acc[k], p[k]) : acc[k] + p[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int w = kReduceThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        sh[k][threadIdx.x] = ((maxmask >> k) & 1u) ? fmax(sh[k][threadIdx.x], sh[k][threadIdx.x + w])
+                                                   : sh[k][threadIdx.x] + sh[k][threadIdx.x + w];
     }
-    sh[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-      if (threadIdx.x < w) sh[threadIdx.x] = mx ? fmax(sh[threadIdx.x], sh[threadIdx.x + w]) : sh[threadIdx.x] + sh[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) out[k] = sh[0];
     __syncthreads();
   }
+  if (threadIdx.x < 4) out[threadIdx.x] = sh[threadIdx.x][0];
 }
 
 // ---------------------------------------------------------------------------
@@ -840,7 +850,7 @@ void enqueue_check(wdb_theta* th, const float* x, const float* x0, double* dst, 
     hipLaunchKernelGGL(k_obj_fwd, slot_grid(A), dim3(kBlock), 0, s, A, x, x0, th->l1w, th->ws_r64, part, nb);
     hipLaunchKernelGGL(k_obj_bwd, slot_grid(At), dim3(kBlock), 0, s, At, th->ws_r64, th->l1w, part + 3 * nb, nb);
   }
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, part, nb, 4, 0x8u, dst);
+  hipLaunchKernelGGL(k_reduce4, dim3(1), dim3(kReduceThreads), 0, s, part, nb, 0x8u, dst);
   WDB_HIP(hipGetLastError());
 }
 
