@@ -1,12 +1,14 @@
 // Periodic separable 2D orthogonal wavelet transform on the GPU (Sec. 2:
 // tensor-product wavelets at one scale, circular boundaries), float32.
 //
-// One launch per level.  Forward: every thread owns one output position
-// (i, j) of the four subbands of the level and evaluates
+// One launch per level.  Forward: each block owns an 8 x 64 tile of output
+// positions (i, j) of the level's four subbands,
 //   c_e[i][j] = sum_{m, m'} f_erow[m] f_ecol[m'] A[(2i+m) mod M][(2j+m') mod M]
-// with f_0 = h (low-pass) and f_1 = g (high-pass), reading the L x L input
-// footprint once for all four subbands (the footprints of neighbouring
-// threads overlap and are served by the L1/L2 caches).  Inverse: every thread
+// with f_0 = h (low-pass) and f_1 = g (high-pass): it stages the tile's input
+// footprint (16 + L - 2 rows of 128 + L - 2 columns, periodic) in LDS with
+// coalesced loads, filters the rows (low and high pass, every input row of
+// the footprint once) into LDS, then the columns, and writes the four
+// subbands row-contiguously.  Inverse: every thread
 // owns one output pixel and gathers the (L/2)^2 coefficients of each subband
 // whose footprint covers it (the transpose of the forward map).
 #include "common.hpp"
@@ -30,33 +32,53 @@ Taps to_taps(const Filter& f) {
   return t;
 }
 
+constexpr int kTI = 8, kTJ = 64;                    // output tile of a forward block
+constexpr int kRI = 2 * kTI + kMaxTaps - 2;          // input rows of its footprint (at most)
+constexpr int kCI = 2 * kTJ + kMaxTaps - 2;          // input columns of its footprint (at most)
+
 __global__ __launch_bounds__(256) void k_dwt_fwd_level(const float* __restrict__ A, int M,
                                                        float* __restrict__ LL, float* __restrict__ d01,
                                                        float* __restrict__ d10, float* __restrict__ d11,
                                                        Taps t) {
+  __shared__ float in[kRI][kCI];
+  __shared__ float lo[kRI][kTJ], hi[kRI][kTJ];
   const int Mh = M >> 1;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y;
-  if (j >= Mh) return;
-  float a00 = 0.f, a01 = 0.f, a10 = 0.f, a11 = 0.f;
-  for (int m = 0; m < t.L; ++m) {
-    const float* row = A + static_cast<size_t>((2 * i + m) & (M - 1)) * M;
-    float lo = 0.f, hi = 0.f;
-    for (int m2 = 0; m2 < t.L; ++m2) {
-      const float v = row[(2 * j + m2) & (M - 1)];
-      lo = fmaf(t.h[m2], v, lo);
-      hi = fmaf(t.g[m2], v, hi);
-    }
-    a00 = fmaf(t.h[m], lo, a00);
-    a01 = fmaf(t.h[m], hi, a01);
-    a10 = fmaf(t.g[m], lo, a10);
-    a11 = fmaf(t.g[m], hi, a11);
+  const int i0 = blockIdx.y * kTI, j0 = blockIdx.x * kTJ;
+  const int rows = 2 * kTI + t.L - 2, cols = 2 * kTJ + t.L - 2;
+  for (int idx = threadIdx.x; idx < rows * cols; idx += blockDim.x) {
+    const int r = idx / cols, c = idx - r * cols;
+    in[r][c] = A[static_cast<size_t>((2 * i0 + r) & (M - 1)) * M + ((2 * j0 + c) & (M - 1))];
   }
-  const size_t o = static_cast<size_t>(i) * Mh + j;
-  LL[o] = a00;
-  d01[o] = a01;
-  d10[o] = a10;
-  d11[o] = a11;
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < rows * kTJ; idx += blockDim.x) {
+    const int r = idx / kTJ, j = idx - r * kTJ;
+    float l = 0.f, h = 0.f;
+    for (int m2 = 0; m2 < t.L; ++m2) {
+      const float v = in[r][2 * j + m2];
+      l = fmaf(t.h[m2], v, l);
+      h = fmaf(t.g[m2], v, h);
+    }
+    lo[r][j] = l;
+    hi[r][j] = h;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < kTI * kTJ; idx += blockDim.x) {
+    const int i = idx / kTJ, j = idx - i * kTJ;
+    if (i0 + i >= Mh || j0 + j >= Mh) continue;
+    float a00 = 0.f, a01 = 0.f, a10 = 0.f, a11 = 0.f;
+    for (int m = 0; m < t.L; ++m) {
+      const float l = lo[2 * i + m][j], h = hi[2 * i + m][j];
+      a00 = fmaf(t.h[m], l, a00);
+      a01 = fmaf(t.h[m], h, a01);
+      a10 = fmaf(t.g[m], l, a10);
+      a11 = fmaf(t.g[m], h, a11);
+    }
+    const size_t o = static_cast<size_t>(i0 + i) * Mh + j0 + j;
+    LL[o] = a00;
+    d01[o] = a01;
+    d10[o] = a10;
+    d11[o] = a11;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_dwt_inv_level(const float* __restrict__ LL,
@@ -108,9 +130,9 @@ void dwt_forward(int n, int levels, const Filter& f, const float* in, float* out
     int64_t off[3];
     level_offsets(n, levels, lev, off);
     float* ll = (lev == levels) ? out : bufs[lev & 1];
-    const int block = Mh < 256 ? Mh : 256;
-    hipLaunchKernelGGL(k_dwt_fwd_level, grid_for(Mh, Mh, block), dim3(block), 0, s, src, M, ll,
-                       out + off[0], out + off[1], out + off[2], t);
+    const dim3 grid((Mh + kTJ - 1) / kTJ, (Mh + kTI - 1) / kTI);
+    hipLaunchKernelGGL(k_dwt_fwd_level, grid, dim3(256), 0, s, src, M, ll, out + off[0], out + off[1],
+                       out + off[2], t);
     WDB_HIP(hipGetLastError());
     src = ll;
   }
