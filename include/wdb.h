@@ -118,6 +118,7 @@ typedef struct {
   int32_t tile_waves16; /* wavefronts per tile of the 16-bit tiled layout (group16 3) */
   int32_t tile_unroll;  /* groups of 4 codes in flight per wavefront, tiled layout */
   int32_t tile_unroll16; /* groups of 8 codes in flight per wavefront, 16-bit tiled layout */
+  int64_t tile_escapes; /* entries of the tiled copies kept in per-row escape lists */
 } wdb_theta_desc;
 
 /* ---------------------------------------------------------------------------

@@ -128,6 +128,7 @@ wdb_status wdb_theta_info(const wdb_theta* th, wdb_theta_desc* out) {
   out->tile_waves16 = th->tile_waves16;
   out->tile_unroll = th->tile_unroll;
   out->tile_unroll16 = th->tile_unroll16;
+  out->tile_escapes = th->tA.nesc + th->tAt.nesc;
   out->tile_slots = 64 * (th->tA.npat + th->tAt.npat);
   WDB_API_END
 }

@@ -1,5 +1,6 @@
 // Band-relative column codes shared by the packed 16-bit form and the tiled
-// pattern storage, and the tile descriptors of the latter.
+// pattern storage (with wider displacement fields in the latter's 32-bit
+// codes), and the tile descriptors of the tiled storage.
 //
 // An entry theta[a, b] is only large when the supports of the two atoms are
 // close in space and in scale (the decay bound of Sec. 3.2).  For a row
@@ -20,11 +21,26 @@
 
 namespace wdb {
 
-constexpr int kDOff = 16;  // displacements in [-16, 15]
-constexpr int kLMax = 3;
-// Padding word of a partial step: value 0, column = a valid coefficient (a
-// detail subband of the row's own level, which every level has).
-constexpr uint32_t kPadCode = (static_cast<uint32_t>(kLMax) << 13) | (1u << 11) | (kDOff << 5) | kDOff;
+constexpr int kLMax = 3;  // level differences in [-3, 3]
+
+// Bit layout of a column code: DB bits per displacement (stored plus 2^(DB-1)),
+// dj at bit 0, di at bit DB, the band slot at bit QS, the level difference
+// plus 3 at bit QS + 2.  The packed 16-bit form uses 5-bit displacements
+// ([-16, 15]); the tiles, whose codes are 32-bit words, 8-bit ones ([-128, 127]).
+template <int DB, int QS>
+struct CodeLayout {
+  static constexpr int kDB = DB, kQS = QS, kOff = 1 << (DB - 1);
+  static constexpr uint32_t kMask = (1u << DB) - 1u;
+  // Padding code: value 0, column = a valid coefficient (a detail subband of
+  // the row's own level, which every level has).
+  static constexpr uint32_t kPad = (static_cast<uint32_t>(kLMax) << (QS + 2)) | (1u << QS) |
+                                   (static_cast<uint32_t>(kOff) << DB) | static_cast<uint32_t>(kOff);
+};
+using Code16 = CodeLayout<5, 11>;
+using CodeTile = CodeLayout<8, 16>;
+constexpr int kDOff = Code16::kOff;
+constexpr uint32_t kPadCode = Code16::kPad;
+constexpr uint32_t kPadCodeTile = CodeTile::kPad;
 
 struct Geo {
   int logn, J, L1;  // log2 of the image side, levels, filter length - 1
@@ -78,20 +94,22 @@ __host__ __device__ inline RowCode row_code(const Geo& g, const Pos& p) {
 // displacement is added modulo the side.  lb is clamped to [1, J] so that
 // any code decodes to an index below n^2 (the encoder only emits levels in
 // range, where the clamp is the identity).
-__host__ __device__ inline int decode_col(const Geo& g, const RowCode& rc, uint32_t code) {
-  const int lb = min(max(rc.lb0 + static_cast<int>((code >> 13) & 7u), 1), g.J);
+template <class F>
+__host__ __device__ inline int decode_col_as(const Geo& g, const RowCode& rc, uint32_t code) {
+  const int lb = min(max(rc.lb0 + static_cast<int>((code >> (F::kQS + 2)) & 7u), 1), g.J);
   const int ls = g.logn - lb;
   const int t = (1 - g.L1) * (1 << lb);
   const int ci = (rc.pi + t) >> (lb + 1);
   const int cj = (rc.pj + t) >> (lb + 1);
   const int m = (1 << ls) - 1;
-  const int ib = (ci - kDOff + static_cast<int>((code >> 5) & 31u)) & m;
-  const int jb = (cj - kDOff + static_cast<int>(code & 31u)) & m;
-  return (static_cast<int>((code >> 11) & 3u) << (2 * ls)) + (ib << ls) + jb;
+  const int ib = (ci - F::kOff + static_cast<int>((code >> F::kDB) & F::kMask)) & m;
+  const int jb = (cj - F::kOff + static_cast<int>(code & F::kMask)) & m;
+  return (static_cast<int>((code >> F::kQS) & 3u) << (2 * ls)) + (ib << ls) + jb;
 }
 
 // Code of column `col` for row position p, or -1 if it does not fit.
-__host__ __device__ inline int encode_col(const Geo& g, const Pos& p, int64_t col) {
+template <class F>
+__host__ __device__ inline int encode_col_as(const Geo& g, const Pos& p, int64_t col) {
   const Pos q = pos_of(g, col);
   const int dL = q.level - p.level;
   if (dL < -kLMax || dL > kLMax) return -1;
@@ -99,9 +117,22 @@ __host__ __device__ inline int encode_col(const Geo& g, const Pos& p, int64_t co
   const int s = 1 << ls, m = s - 1, h = s >> 1;
   const int di = ((q.i - centre_at(g, p.i, p.level, q.level) + h) & m) - h;
   const int dj = ((q.j - centre_at(g, p.j, p.level, q.level) + h) & m) - h;
-  if (di < -kDOff || di >= kDOff || dj < -kDOff || dj >= kDOff) return -1;
+  if (di < -F::kOff || di >= F::kOff || dj < -F::kOff || dj >= F::kOff) return -1;
   const int slot = q.orient == 3 ? 0 : q.orient + 1;
-  return ((dL + kLMax) << 13) | (slot << 11) | ((di + kDOff) << 5) | (dj + kDOff);
+  return ((dL + kLMax) << (F::kQS + 2)) | (slot << F::kQS) | ((di + F::kOff) << F::kDB) | (dj + F::kOff);
+}
+
+__host__ __device__ inline int decode_col(const Geo& g, const RowCode& rc, uint32_t code) {
+  return decode_col_as<Code16>(g, rc, code);
+}
+__host__ __device__ inline int encode_col(const Geo& g, const Pos& p, int64_t col) {
+  return encode_col_as<Code16>(g, p, col);
+}
+__host__ __device__ inline int decode_col_tile(const Geo& g, const RowCode& rc, uint32_t code) {
+  return decode_col_as<CodeTile>(g, rc, code);
+}
+__host__ __device__ inline int encode_col_tile(const Geo& g, const Pos& p, int64_t col) {
+  return encode_col_as<CodeTile>(g, p, col);
 }
 
 // Tile descriptors of the tiled pattern storage: int4 {first code, end code,

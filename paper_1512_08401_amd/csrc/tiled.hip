@@ -4,7 +4,7 @@
 // block of positions when the subband's side is at least 8, else the whole
 // subband.  The blur field varies slowly in space, so neighbouring
 // coefficients of one subband keep entries at nearly the same band-relative
-// displacements (the codes of codes.hpp).  A tile stores the sorted union of
+// displacements (the codes of codes.hpp, with 8-bit displacement fields).  A tile stores the sorted union of
 // its rows' codes once, and one float32 value per (code, row): zero where that
 // row did not keep the entry.  No column index is stored.
 //
@@ -21,7 +21,7 @@
 // that a lane loads one 16-byte vector per group of 4 codes.  The groups of a
 // tile are dealt round-robin to the W wavefronts of its block and the W
 // partial sums are added in LDS in wavefront order (deterministic).  Entries
-// whose code does not fit (displacement beyond 16 or level gap beyond 3) go to
+// whose code does not fit (displacement beyond 128 or level gap beyond 3) go to
 // a per-row escape list read by the first wavefront.
 #include <algorithm>
 #include <cstring>
@@ -95,15 +95,15 @@ __device__ __forceinline__ float tile_dot(const TiledView& T, const Geo& g, cons
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const bool ok = k + u * W < g1;
-      c[u] = ok ? T.code[k + u * W] : make_uint4(kPadCode, kPadCode, kPadCode, kPadCode);
+      c[u] = ok ? T.code[k + u * W] : make_uint4(kPadCodeTile, kPadCodeTile, kPadCodeTile, kPadCodeTile);
       v[u] = ok ? T.val[static_cast<int64_t>(k + u * W) * 64 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      acc = fmaf(v[u].x, x[decode_col(g, rc, c[u].x)], acc);
-      acc = fmaf(v[u].y, x[decode_col(g, rc, c[u].y)], acc);
-      acc = fmaf(v[u].z, x[decode_col(g, rc, c[u].z)], acc);
-      acc = fmaf(v[u].w, x[decode_col(g, rc, c[u].w)], acc);
+      acc = fmaf(v[u].x, x[decode_col_tile(g, rc, c[u].x)], acc);
+      acc = fmaf(v[u].y, x[decode_col_tile(g, rc, c[u].y)], acc);
+      acc = fmaf(v[u].z, x[decode_col_tile(g, rc, c[u].z)], acc);
+      acc = fmaf(v[u].w, x[decode_col_tile(g, rc, c[u].w)], acc);
     }
   }
   return tile_finish<W, float>(T, d, row, lane, wv, acc, x);
@@ -122,7 +122,7 @@ __device__ __forceinline__ float tile_dot16(const TiledView& T, const Geo& g, co
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const bool ok = k + u * W < g1;
-      const uint4 pad = make_uint4(kPadCode, kPadCode, kPadCode, kPadCode);
+      const uint4 pad = make_uint4(kPadCodeTile, kPadCodeTile, kPadCodeTile, kPadCodeTile);
       c[2 * u] = ok ? T.code[2 * (k + u * W)] : pad;
       c[2 * u + 1] = ok ? T.code[2 * (k + u * W) + 1] : pad;
       v[u] = ok ? T.val16[static_cast<int64_t>(k + u * W) * 64 + lane] : make_uint4(0u, 0u, 0u, 0u);
@@ -134,7 +134,7 @@ __device__ __forceinline__ float tile_dot16(const TiledView& T, const Geo& g, co
       const uint32_t vs[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
 #pragma unroll
       for (int e = 0; e < 8; ++e)
-        acc = fmaf(dq16<FMT>((vs[e >> 1] >> (16 * (e & 1))) & 0xFFFFu), x[decode_col(g, rc, cs[e])], acc);
+        acc = fmaf(dq16<FMT>((vs[e >> 1] >> (16 * (e & 1))) & 0xFFFFu), x[decode_col_tile(g, rc, cs[e])], acc);
     }
   }
   return tile_finish<W, float>(T, d, row, lane, wv, acc, x);
@@ -155,15 +155,15 @@ __device__ __forceinline__ double tile_dot64(const TiledView& T, const Geo& g, c
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const bool ok = k + u * W < g1;
-      c[u] = ok ? T.code[k + u * W] : make_uint4(kPadCode, kPadCode, kPadCode, kPadCode);
+      c[u] = ok ? T.code[k + u * W] : make_uint4(kPadCodeTile, kPadCodeTile, kPadCodeTile, kPadCodeTile);
       v[u] = ok ? T.val[static_cast<int64_t>(k + u * W) * 64 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      acc = fma(static_cast<double>(v[u].x), static_cast<double>(x[decode_col(g, rc, c[u].x)]), acc);
-      acc = fma(static_cast<double>(v[u].y), static_cast<double>(x[decode_col(g, rc, c[u].y)]), acc);
-      acc = fma(static_cast<double>(v[u].z), static_cast<double>(x[decode_col(g, rc, c[u].z)]), acc);
-      acc = fma(static_cast<double>(v[u].w), static_cast<double>(x[decode_col(g, rc, c[u].w)]), acc);
+      acc = fma(static_cast<double>(v[u].x), static_cast<double>(x[decode_col_tile(g, rc, c[u].x)]), acc);
+      acc = fma(static_cast<double>(v[u].y), static_cast<double>(x[decode_col_tile(g, rc, c[u].y)]), acc);
+      acc = fma(static_cast<double>(v[u].z), static_cast<double>(x[decode_col_tile(g, rc, c[u].z)]), acc);
+      acc = fma(static_cast<double>(v[u].w), static_cast<double>(x[decode_col_tile(g, rc, c[u].w)]), acc);
     }
   }
   return tile_finish<W, double>(T, d, row, lane, wv, acc, x);
@@ -399,7 +399,7 @@ void encode_tiles(const Geo& g, const std::vector<int4>& tiles, size_t t0, size_
           u = (*ub)[band_index(g, q.level, q.orient)];
         }
         const float v = val[k] * u;  // exact: u is a power of two
-        const int c = encode_col(g, p, col[k]);
+        const int c = encode_col_tile(g, p, col[k]);
         if (c < 0) {
           o.erow.push_back(row);
           o.ecol.push_back(col[k]);
@@ -416,7 +416,7 @@ void encode_tiles(const Geo& g, const std::vector<int4>& tiles, size_t t0, size_
     std::sort(u.begin(), u.end());
     u.erase(std::unique(u.begin(), u.end()), u.end());
     const size_t npat = u.size();
-    while (u.size() % grp) u.push_back(kPadCode);
+    while (u.size() % grp) u.push_back(kPadCodeTile);
     const int pb = static_cast<int>(o.code.size());
     o.code.insert(o.code.end(), u.begin(), u.end());
     o.val.resize(o.val.size() + u.size() * 64, 0.0f);

@@ -51,7 +51,7 @@ class ThetaDesc(C.Structure):
                 ("group16", C.c_int32), ("escapes", C.c_int64), ("conv_build", C.c_int32),
                 ("l1_weights", C.c_int32), ("rule", C.c_int32), ("circulant", C.c_int64),
                 ("tile_waves", C.c_int32), ("tile_slots", C.c_int64), ("tile_waves16", C.c_int32),
-                ("tile_unroll", C.c_int32), ("tile_unroll16", C.c_int32)]
+                ("tile_unroll", C.c_int32), ("tile_unroll16", C.c_int32), ("tile_escapes", C.c_int64)]
 
 
 class SolveOpts(C.Structure):

@@ -932,13 +932,17 @@ def test_tiled_layout_matches_oracle(W, p64, waves, unroll):
 
 def test_tiled_escapes_and_small_subbands_match_oracle(W):
     """A 128 x 128, 5-level operator: the coarsest subbands are 4 x 4 (one
-    partial tile each), and random far columns go to the escape lists."""
+    partial tile each); random far columns, and for some finest-level rows a
+    column of the coarsest approximation (a level gap of 4, beyond the code),
+    go to the escape lists."""
     n, J, N = 128, 5, 16384
     rng = np.random.default_rng(29)
     rows, cols = [], []
     for r in range(N):
         near = (r + rng.integers(-3, 4, 6)) % N
         far = rng.integers(0, N, rng.integers(0, 3))
+        if r >= N // 4 and rng.random() < 0.05:   # a level-1 row: add an A_J coefficient (16 of them)
+            far = np.concatenate([far, rng.integers(0, 16, 1)])
         cs = np.unique(np.concatenate([near, far]))
         rows.append(np.full(cs.size, r))
         cols.append(cs)
@@ -948,6 +952,7 @@ def test_tiled_escapes_and_small_subbands_match_oracle(W):
     A.sort_indices()
     th = W.Theta.from_csr(n, "haar", J, A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data)
     th.set_kernel_layout(8, 3)
+    assert th.info()["tile_escapes"] > 0
     A32 = sp.csr_matrix((A.data.astype(np.float32).astype(np.float64), A.indices, A.indptr), shape=A.shape)
     x = rng.standard_normal(N).astype(np.float32)
     for waves in (1, 4):
