@@ -35,6 +35,18 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def layout_desc(layout, tile_shape):
+    slice_h, group = layout
+    if group == 3:
+        return {"kind": "tiled", "tile": "8x8 coefficients", "waves_per_tile": tile_shape[0],
+                "groups_in_flight": tile_shape[1]}
+    if group == 1:
+        return {"kind": "circulant"}
+    if group > 0:
+        return {"kind": "csr", "lanes_per_row": group}
+    return {"kind": "sliced_ell", "slice": slice_h}
+
+
 def kernel_label(layout, waves=4, unroll=2):
     slice_h, group = layout
     if group == 3:
@@ -242,7 +254,7 @@ def main():
                 "kernel_us": round(k_us, 2), "algorithmic_bytes": alg_bytes,
                 "stored_slots": th.info()["tile_slots"] // 2 if layout[1] == 3 else info["stored"],
                 "transpose_kernel_us": round(kt_us, 2),
-                "layout": {"slice": layout[0], "lanes_per_row": layout[1]},
+                "layout": layout_desc(layout, tile_shape),
                 "k_res_16bit_us": {k: round(v, 2) for k, v in half_us.items()},
                 "k_res_16bit_layout": half_layout,
                 "k_res_16bit_gbs": {k: round((6 * nnz + 12 * N) / (v * 1e-6) / 1e9, 1) for k, v in half_us.items()}}
