@@ -1,16 +1,18 @@
 // Periodic separable 2D orthogonal wavelet transform on the GPU (Sec. 2:
 // tensor-product wavelets at one scale, circular boundaries), float32.
 //
-// One launch per level.  Forward: each block owns an 8 x 64 tile of output
+// One launch per level.  Forward: each block owns an 8 x 32 tile of output
 // positions (i, j) of the level's four subbands,
 //   c_e[i][j] = sum_{m, m'} f_erow[m] f_ecol[m'] A[(2i+m) mod M][(2j+m') mod M]
 // with f_0 = h (low-pass) and f_1 = g (high-pass): it stages the tile's input
-// footprint (16 + L - 2 rows of 128 + L - 2 columns, periodic) in LDS with
+// footprint (16 + L - 2 rows of 64 + L - 2 columns, periodic) in LDS with
 // coalesced loads, filters the rows (low and high pass, every input row of
 // the footprint once) into LDS, then the columns, and writes the four
-// subbands row-contiguously.  Inverse: every thread
-// owns one output pixel and gathers the (L/2)^2 coefficients of each subband
-// whose footprint covers it (the transpose of the forward map).
+// subbands row-contiguously.  Inverse (the transpose of the forward map):
+// each block owns an 8 x 32 tile of output pixels, stages the four subbands'
+// half-resolution footprint (4 + 6 rows of 16 + 6 columns, periodic) in LDS,
+// and every thread sums the (L/2)^2 coefficients of each subband that cover
+// its pixel from there.
 #include "common.hpp"
 
 namespace wdb {
@@ -32,7 +34,7 @@ Taps to_taps(const Filter& f) {
   return t;
 }
 
-constexpr int kTI = 8, kTJ = 64;                    // output tile of a forward block
+constexpr int kTI = 8, kTJ = 32;                    // output tile of a forward block
 constexpr int kRI = 2 * kTI + kMaxTaps - 2;          // input rows of its footprint (at most)
 constexpr int kCI = 2 * kTJ + kMaxTaps - 2;          // input columns of its footprint (at most)
 
@@ -81,32 +83,47 @@ __global__ __launch_bounds__(256) void k_dwt_fwd_level(const float* __restrict__
   }
 }
 
+constexpr int kTP = 8, kTQ = 32;                   // output tile of an inverse block (full resolution)
+constexpr int kHalo = kMaxTaps / 2;                  // half-resolution rows / columns below the tile
+constexpr int kRP = kTP / 2 + kHalo, kCQ = kTQ / 2 + kHalo;
+
 __global__ __launch_bounds__(256) void k_dwt_inv_level(const float* __restrict__ LL,
                                                        const float* __restrict__ d01,
                                                        const float* __restrict__ d10,
                                                        const float* __restrict__ d11, int Mh,
                                                        float* __restrict__ out, Taps t) {
+  __shared__ float sb[4][kRP][kCQ];
   const int M = Mh << 1;
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  const int p = blockIdx.y;
-  if (q >= M) return;
-  float acc = 0.f;
-  for (int m = p & 1; m < t.L; m += 2) {
-    const int i = ((p - m) >> 1) & (Mh - 1);
-    const float hr = t.h[m], gr = t.g[m];
-    for (int m2 = q & 1; m2 < t.L; m2 += 2) {
-      const int jj = ((q - m2) >> 1) & (Mh - 1);
-      const size_t idx = static_cast<size_t>(i) * Mh + jj;
-      acc = fmaf(hr * t.h[m2], LL[idx], acc);
-      acc = fmaf(hr * t.g[m2], d01[idx], acc);
-      acc = fmaf(gr * t.h[m2], d10[idx], acc);
-      acc = fmaf(gr * t.g[m2], d11[idx], acc);
-    }
+  const int p0 = blockIdx.y * kTP, q0 = blockIdx.x * kTQ;
+  const int ib = (p0 >> 1) - kHalo, jb = (q0 >> 1) - kHalo;  // half-resolution origin of the footprint
+  for (int idx = threadIdx.x; idx < kRP * kCQ; idx += blockDim.x) {
+    const int r = idx / kCQ, c = idx - r * kCQ;
+    const size_t g = static_cast<size_t>((ib + r) & (Mh - 1)) * Mh + ((jb + c) & (Mh - 1));
+    sb[0][r][c] = LL[g];
+    sb[1][r][c] = d01[g];
+    sb[2][r][c] = d10[g];
+    sb[3][r][c] = d11[g];
   }
-  out[static_cast<size_t>(p) * M + q] = acc;
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < kTP * kTQ; idx += blockDim.x) {
+    const int pp = idx / kTQ, qq = idx - pp * kTQ;
+    const int p = p0 + pp, q = q0 + qq;
+    if (p >= M || q >= M) continue;
+    float acc = 0.f;
+    for (int m = p & 1; m < t.L; m += 2) {
+      const int r = ((p - m) >> 1) - ib;
+      const float hr = t.h[m], gr = t.g[m];
+      for (int m2 = q & 1; m2 < t.L; m2 += 2) {
+        const int c = ((q - m2) >> 1) - jb;
+        acc = fmaf(hr * t.h[m2], sb[0][r][c], acc);
+        acc = fmaf(hr * t.g[m2], sb[1][r][c], acc);
+        acc = fmaf(gr * t.h[m2], sb[2][r][c], acc);
+        acc = fmaf(gr * t.g[m2], sb[3][r][c], acc);
+      }
+    }
+    out[static_cast<size_t>(p) * M + q] = acc;
+  }
 }
-
-dim3 grid_for(int cols, int rows, int block) { return dim3((cols + block - 1) / block, rows); }
 
 }  // namespace
 
@@ -149,9 +166,9 @@ void dwt_inverse(int n, int levels, const Filter& f, const float* in, float* out
     int64_t off[3];
     level_offsets(n, levels, lev, off);
     float* dst = (lev == 1) ? out : bufs[lev & 1];
-    const int block = M < 256 ? M : 256;
-    hipLaunchKernelGGL(k_dwt_inv_level, grid_for(M, M, block), dim3(block), 0, s, ll, in + off[0],
-                       in + off[1], in + off[2], Mh, dst, t);
+    const dim3 grid((M + kTQ - 1) / kTQ, (M + kTP - 1) / kTP);
+    hipLaunchKernelGGL(k_dwt_inv_level, grid, dim3(256), 0, s, ll, in + off[0], in + off[1], in + off[2], Mh,
+                       dst, t);
     WDB_HIP(hipGetLastError());
     ll = dst;
   }
