@@ -312,7 +312,7 @@ def time_to_tolerance(th, u0, wl, torch, wdb, synth, N, targets=(1e-4, 1e-6, 1e-
            "E_star_rel_gap": inf["rel_gap"], "E0": E0, "normaliser": "E(0) = ||x0||^2/2"}
     stream = torch.cuda.current_stream()
     forms = (("plain_f32", False, "f32"), ("spai_scale_f32", True, "f32"), ("plain_bf16", False, "bf16"),
-             ("spai_scale_bf16", True, "bf16"), ("plain_f16", False, "f16"))
+             ("spai_scale_bf16", True, "bf16"), ("plain_f16", False, "f16"), ("spai_scale_f16", True, "f16"))
     x = torch.empty(N, device=u0.device)
     for form, pre, vt in forms:
         th.set_precision(vt)
