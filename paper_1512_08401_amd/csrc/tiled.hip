@@ -1,12 +1,14 @@
-// Tiled pattern storage of Theta_K and Theta_K^T for the float32 iteration.
+// Tiled pattern storage of Theta_K and Theta_K^T for the iteration (float32
+// values, or scaled 16-bit values for the mixed-precision iteration).
 //
 // Rows are grouped in tiles of up to 64 coefficients of one subband: an 8 x 8
 // block of positions when the subband's side is at least 8, else the whole
 // subband.  The blur field varies slowly in space, so neighbouring
 // coefficients of one subband keep entries at nearly the same band-relative
-// displacements (the codes of codes.hpp, with 8-bit displacement fields).  A tile stores the sorted union of
-// its rows' codes once, and one float32 value per (code, row): zero where that
-// row did not keep the entry.  No column index is stored.
+// displacements (the codes of codes.hpp, with 8-bit displacement fields).  A
+// tile stores the sorted union of its rows' codes once, and one value per
+// (code, row): zero where that row did not keep the entry.  No column index
+// is stored.
 //
 // One wavefront covers a tile's rows (lane t = row t).  For each code every
 // lane decodes its own column with a few integer operations on the row's
@@ -15,14 +17,15 @@
 // coefficients (coarser columns) or on a comb of stride 2^k (finer columns),
 // instead of 64 unrelated addresses as in a row-wise CSR product.
 //
-// Layout per matrix: per tile an int4 {first pattern, end pattern (both
-// multiples of 4), first row, log2 side | flags}; codes as uint32 in groups
-// of 4 (padded with a code of value 0); values as [group][lane][4] float32 so
-// that a lane loads one 16-byte vector per group of 4 codes.  The groups of a
-// tile are dealt round-robin to the W wavefronts of its block and the W
-// partial sums are added in LDS in wavefront order (deterministic).  Entries
-// whose code does not fit (displacement beyond 128 or level gap beyond 3) go to
-// a per-row escape list read by the first wavefront.
+// Layout per matrix: per tile an int4 {first code, end code (multiples of the
+// group size), first row, log2 side | flags}; codes as uint32 in groups of 4
+// (float32) or 8 (16-bit values), padded with a code of value 0; values as
+// [group][lane][group size] so that a lane loads one 16-byte vector per
+// group.  The groups of a tile are dealt round-robin to the W wavefronts of
+// its block and the W partial sums are added in LDS in wavefront order
+// (deterministic).  Entries whose code does not fit (displacement beyond 128
+// or level gap beyond 3) go to per-row escape lists, whose entries are dealt
+// round-robin to the wavefronts as well.
 #include <algorithm>
 #include <cstring>
 #include <exception>
