@@ -188,10 +188,12 @@ class Theta:
     def __init__(self, handle: C.c_void_p):
         self._h = handle
 
-    def __del__(self):
+    # The free routine is bound at class creation: at interpreter exit the
+    # module's globals may already be cleared when a handle is collected.
+    def __del__(self, _free=_lib.wdb_theta_free):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            _lib.wdb_theta_free(h)
+            _free(h)
             self._h = None
 
     def free(self):
@@ -375,10 +377,10 @@ class Cnn:
         _check("wdb_cnn_param_count", _lib.wdb_cnn_param_count(self._h, C.byref(cnt)))
         self.nparam = cnt.value
 
-    def __del__(self):
+    def __del__(self, _free=_lib.wdb_cnn_free):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            _lib.wdb_cnn_free(h)
+            _free(h)
             self._h = None
 
     def set_params(self, p):
