@@ -113,7 +113,7 @@ __device__ __forceinline__ int tile_mm(const ChunkDev& C, int m, int tile, const
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int row = tile_row(d, lane);
-  const RowCode rc = row_code(C.geo, pos_of(C.geo, row >= 0 ? row : d.z));
+  const RowCode rc = tile_row_code(C.geo, d, row);
   const uint4* __restrict__ code = C.tcode[m];
   const float4* __restrict__ val = C.tval[m];
   for (int k = (d.x >> 2) + wv; k < (d.y >> 2); k += kWaves) {

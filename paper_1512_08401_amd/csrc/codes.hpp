@@ -94,16 +94,20 @@ __host__ __device__ inline RowCode row_code(const Geo& g, const Pos& p) {
 // displacement is added modulo the side.  lb is clamped to [1, J] so that
 // any code decodes to an index below n^2 (the encoder only emits levels in
 // range, where the clamp is the identity).
+// Terms that depend on the code and the row level only (lb, the side, t, the
+// mask, the displacements, the band offset) are grouped apart from the
+// row's centre numerators, so that where the level is the same for all
+// lanes (tile_row_code) they are computed once per wavefront.
 template <class F>
 __host__ __device__ inline int decode_col_as(const Geo& g, const RowCode& rc, uint32_t code) {
   const int lb = min(max(rc.lb0 + static_cast<int>((code >> (F::kQS + 2)) & 7u), 1), g.J);
   const int ls = g.logn - lb;
   const int t = (1 - g.L1) * (1 << lb);
-  const int ci = (rc.pi + t) >> (lb + 1);
-  const int cj = (rc.pj + t) >> (lb + 1);
   const int m = (1 << ls) - 1;
-  const int ib = (ci - F::kOff + static_cast<int>((code >> F::kDB) & F::kMask)) & m;
-  const int jb = (cj - F::kOff + static_cast<int>(code & F::kMask)) & m;
+  const int di = static_cast<int>((code >> F::kDB) & F::kMask) - F::kOff;
+  const int dj = static_cast<int>(code & F::kMask) - F::kOff;
+  const int ib = (((rc.pi + t) >> (lb + 1)) + di) & m;
+  const int jb = (((rc.pj + t) >> (lb + 1)) + dj) & m;
   return (static_cast<int>((code >> F::kQS) & 3u) << (2 * ls)) + (ib << ls) + jb;
 }
 
@@ -146,6 +150,16 @@ __host__ __device__ inline int tile_row(const int4& d, int t) {
   if (d.w & kSmall) return t < ((d.w >> 16) & 0x7F) ? d.z + t : -1;
   const int ls = d.w & 0xFF;
   return d.z + ((t >> 3) << ls) + (t & 7);
+}
+
+// Decode constants of `row` in tile d (an idle lane takes the tile's first
+// row).  Every row of a tile lies in the tile's subband, so the row level is
+// read from the descriptor: the same value as pos_of gives, but visibly
+// uniform across the wavefront.
+__host__ __device__ inline RowCode tile_row_code(const Geo& g, const int4& d, int row) {
+  RowCode rc = row_code(g, pos_of(g, row >= 0 ? row : d.z));
+  rc.lb0 = g.logn - (d.w & 0xFF) - kLMax;
+  return rc;
 }
 
 inline Geo geo_of(const wdb_theta* th) {

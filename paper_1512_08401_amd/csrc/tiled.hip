@@ -84,60 +84,124 @@ __device__ __forceinline__ A tile_finish(const TiledView& T, const int4& d, int 
   return acc;
 }
 
+// x[i] as the vector's base plus a 32-bit byte offset (i < 2^28 and elements
+// of at most 8 bytes, so the offset fits): the gathers then take the form
+// with the base in scalar registers and one offset register per lane.
+template <typename X>
+__device__ __forceinline__ X ld_at(const X* __restrict__ x, int i) {
+  const uint32_t off = static_cast<uint32_t>(i) * static_cast<uint32_t>(sizeof(X));
+  return *reinterpret_cast<const X*>(reinterpret_cast<const char*>(x) + off);
+}
+
+// Codes and values of the U groups k, k + W, ... of a float32 tile (padding
+// past g1).
+template <int W, int U>
+__device__ __forceinline__ void tile_load(const TiledView& T, int k, int g1, int lane, uint4 (&c)[U],
+                                          float4 (&v)[U]) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const bool ok = k + u * W < g1;
+    c[u] = ok ? T.code[k + u * W] : make_uint4(kPadCodeTile, kPadCodeTile, kPadCodeTile, kPadCodeTile);
+    v[u] = ok ? T.val[static_cast<int64_t>(k + u * W) * 64 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+}
+
 // Dot product of the lane's row with x over float32 values (groups of 4
-// codes, two groups in flight per wavefront).
+// codes, U groups per step).  A step decodes its columns, issues the
+// gathers, then the loads of the next step's codes and values, and only
+// then waits for the gathers: the next loads are in flight during the
+// multiply-adds and the next decode.  Waits on scalar loads cover every
+// scalar load in flight, so the next codes are requested only after this
+// step's codes are used (the scheduling barriers keep that order).
 template <int W, int U>
 __device__ __forceinline__ float tile_dot(const TiledView& T, const Geo& g, const int4& d, int row, int lane,
                                           int wv, const float* __restrict__ x) {
-  const RowCode rc = row_code(g, pos_of(g, row >= 0 ? row : d.z));
+  const RowCode rc = tile_row_code(g, d, row);
   float acc = 0.f;
   const int g1 = d.y >> 2;
-  for (int k = (d.x >> 2) + wv; k < g1; k += W * U) {
-    uint4 c[U];
-    float4 v[U];
+  int k = (d.x >> 2) + wv;
+  uint4 c[U];
+  float4 v[U];
+  tile_load<W, U>(T, k, g1, lane, c, v);
+  for (; k < g1; k += W * U) {
+    float xs[4 * U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const bool ok = k + u * W < g1;
-      c[u] = ok ? T.code[k + u * W] : make_uint4(kPadCodeTile, kPadCodeTile, kPadCodeTile, kPadCodeTile);
-      v[u] = ok ? T.val[static_cast<int64_t>(k + u * W) * 64 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+      xs[4 * u] = ld_at(x, decode_col_tile(g, rc, c[u].x));
+      xs[4 * u + 1] = ld_at(x, decode_col_tile(g, rc, c[u].y));
+      xs[4 * u + 2] = ld_at(x, decode_col_tile(g, rc, c[u].z));
+      xs[4 * u + 3] = ld_at(x, decode_col_tile(g, rc, c[u].w));
     }
+    __builtin_amdgcn_sched_barrier(0);
+    float4 vn[U];
+    tile_load<W, U>(T, k + W * U, g1, lane, c, vn);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      acc = fmaf(v[u].x, x[decode_col_tile(g, rc, c[u].x)], acc);
-      acc = fmaf(v[u].y, x[decode_col_tile(g, rc, c[u].y)], acc);
-      acc = fmaf(v[u].z, x[decode_col_tile(g, rc, c[u].z)], acc);
-      acc = fmaf(v[u].w, x[decode_col_tile(g, rc, c[u].w)], acc);
+      acc = fmaf(v[u].x, xs[4 * u], acc);
+      acc = fmaf(v[u].y, xs[4 * u + 1], acc);
+      acc = fmaf(v[u].z, xs[4 * u + 2], acc);
+      acc = fmaf(v[u].w, xs[4 * u + 3], acc);
+      v[u] = vn[u];
     }
   }
   return tile_finish<W, float>(T, d, row, lane, wv, acc, x);
 }
 
+// The 8 codes of a 16-bit group, read as one 32-byte unit.
+struct Codes8 {
+  uint4 a, b;
+};
+
+// Codes and values of the U groups of a 16-bit tile (8 codes per group).
+template <int W, int U>
+__device__ __forceinline__ void tile_load16(const TiledView& T, int k, int g1, int lane, uint4 (&c)[2 * U],
+                                            uint4 (&v)[U]) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (k + u * W < g1) {
+      const Codes8 cc = reinterpret_cast<const Codes8*>(T.code)[k + u * W];
+      c[2 * u] = cc.a;
+      c[2 * u + 1] = cc.b;
+      v[u] = T.val16[static_cast<int64_t>(k + u * W) * 64 + lane];
+    } else {
+      c[2 * u] = c[2 * u + 1] = make_uint4(kPadCodeTile, kPadCodeTile, kPadCodeTile, kPadCodeTile);
+      v[u] = make_uint4(0u, 0u, 0u, 0u);
+    }
+  }
+}
+
 // The same over 16-bit values: groups of 8 codes, one 16-byte vector of 8
-// values per lane and group.
+// values per lane and group, in the same step order as tile_dot.
 template <int W, int U, int FMT>
 __device__ __forceinline__ float tile_dot16(const TiledView& T, const Geo& g, const int4& d, int row, int lane,
                                             int wv, const float* __restrict__ x) {
-  const RowCode rc = row_code(g, pos_of(g, row >= 0 ? row : d.z));
+  const RowCode rc = tile_row_code(g, d, row);
   float acc = 0.f;
   const int g1 = d.y >> 3;
-  for (int k = (d.x >> 3) + wv; k < g1; k += W * U) {
-    uint4 c[2 * U], v[U];
+  int k = (d.x >> 3) + wv;
+  uint4 c[2 * U], v[U];
+  tile_load16<W, U>(T, k, g1, lane, c, v);
+  for (; k < g1; k += W * U) {
+    float xs[8 * U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const bool ok = k + u * W < g1;
-      const uint4 pad = make_uint4(kPadCodeTile, kPadCodeTile, kPadCodeTile, kPadCodeTile);
-      c[2 * u] = ok ? T.code[2 * (k + u * W)] : pad;
-      c[2 * u + 1] = ok ? T.code[2 * (k + u * W) + 1] : pad;
-      v[u] = ok ? T.val16[static_cast<int64_t>(k + u * W) * 64 + lane] : make_uint4(0u, 0u, 0u, 0u);
+    for (int u = 0; u < 2 * U; ++u) {
+      xs[4 * u] = ld_at(x, decode_col_tile(g, rc, c[u].x));
+      xs[4 * u + 1] = ld_at(x, decode_col_tile(g, rc, c[u].y));
+      xs[4 * u + 2] = ld_at(x, decode_col_tile(g, rc, c[u].z));
+      xs[4 * u + 3] = ld_at(x, decode_col_tile(g, rc, c[u].w));
     }
+    __builtin_amdgcn_sched_barrier(0);
+    uint4 vn[U];
+    tile_load16<W, U>(T, k + W * U, g1, lane, c, vn);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const uint32_t cs[8] = {c[2 * u].x, c[2 * u].y, c[2 * u].z, c[2 * u].w,
-                              c[2 * u + 1].x, c[2 * u + 1].y, c[2 * u + 1].z, c[2 * u + 1].w};
       const uint32_t vs[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
 #pragma unroll
       for (int e = 0; e < 8; ++e)
-        acc = fmaf(dq16<FMT>((vs[e >> 1] >> (16 * (e & 1))) & 0xFFFFu), x[decode_col_tile(g, rc, cs[e])], acc);
+        acc = fmaf(dq16<FMT>((vs[e >> 1] >> (16 * (e & 1))) & 0xFFFFu), xs[8 * u + e], acc);
+      v[u] = vn[u];
     }
   }
   return tile_finish<W, float>(T, d, row, lane, wv, acc, x);
@@ -149,7 +213,7 @@ __device__ __forceinline__ float tile_dot16(const TiledView& T, const Geo& g, co
 template <int W, int U, typename X>
 __device__ __forceinline__ double tile_dot64(const TiledView& T, const Geo& g, const int4& d, int row, int lane,
                                              int wv, const X* __restrict__ x) {
-  const RowCode rc = row_code(g, pos_of(g, row >= 0 ? row : d.z));
+  const RowCode rc = tile_row_code(g, d, row);
   double acc = 0.0;
   const int g1 = d.y >> 2;
   for (int k = (d.x >> 2) + wv; k < g1; k += W * U) {
@@ -229,7 +293,6 @@ template <int W, int U>
 __global__ __launch_bounds__(64 * W) void k_res_tl(TiledView T, Geo g, const float* __restrict__ y,
                                                    const float* __restrict__ b, float* __restrict__ r,
                                                    int* __restrict__ kdev) {
-  if (kdev && blockIdx.x == 0 && threadIdx.x == 0) *kdev += 1;
   const int4 d = T.desc[blockIdx.x];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -238,6 +301,9 @@ __global__ __launch_bounds__(64 * W) void k_res_tl(TiledView T, Geo g, const flo
   const float bv = b && out ? b[row] : 0.0f;  // issued before the product so its latency overlaps
   const float acc = tile_dot<W, U>(T, g, d, row, lane, wv, y);
   if (out) r[row] = acc - bv;
+  // the iteration counter moves after the product: a global store ahead of
+  // the loop would keep the code loads off the scalar path
+  if (kdev && blockIdx.x == 0 && threadIdx.x == 0) *kdev += 1;
 }
 
 // Operands of the proximal epilogue, loaded before the product.
@@ -294,7 +360,6 @@ template <int W, int U, int FMT>
 __global__ __launch_bounds__(64 * W) void k_res_tl16(TiledView T, Geo g, const float* __restrict__ wrow,
                                                      const float* __restrict__ y, const float* __restrict__ b,
                                                      float* __restrict__ r, int* __restrict__ kdev, int scale_out) {
-  if (kdev && blockIdx.x == 0 && threadIdx.x == 0) *kdev += 1;
   const int4 d = T.desc[blockIdx.x];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -303,6 +368,7 @@ __global__ __launch_bounds__(64 * W) void k_res_tl16(TiledView T, Geo g, const f
   const float w = out ? wrow[row] : 0.0f;
   const float bv = b && out ? b[row] : 0.0f;
   const float acc = tile_dot16<W, U, FMT>(T, g, d, row, lane, wv, y);
+  if (kdev && blockIdx.x == 0 && threadIdx.x == 0) *kdev += 1;
   if (!out) return;
   const float rr = b ? w * acc - bv : w * acc;
   r[row] = scale_out ? rr * w : rr;
