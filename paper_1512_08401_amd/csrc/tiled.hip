@@ -106,6 +106,32 @@ __device__ __forceinline__ void tile_load(const TiledView& T, int k, int g1, int
   }
 }
 
+// Columns of 4 codes.  When the 4 share the level and band fields (the
+// common case: a tile's codes are sorted, so codes come in runs with the
+// same level and band), the lane shifts its centre once for the group and
+// each code only adds its displacements; otherwise each code is decoded in
+// full.  Both give decode_col_tile's columns.
+__device__ __forceinline__ int4 group_cols(const Geo& g, const RowCode& rc, const uint4& c) {
+  using F = CodeTile;
+  if ((((c.x ^ c.y) | (c.x ^ c.z) | (c.x ^ c.w)) >> F::kQS) == 0) {
+    const int lb = min(max(rc.lb0 + static_cast<int>((c.x >> (F::kQS + 2)) & 7u), 1), g.J);
+    const int ls = g.logn - lb;
+    const int t = (1 - g.L1) * (1 << lb);
+    const int m = (1 << ls) - 1;
+    const int ci = (rc.pi + t) >> (lb + 1);
+    const int cj = (rc.pj + t) >> (lb + 1);
+    const int qoff = static_cast<int>((c.x >> F::kQS) & 3u) << (2 * ls);
+    const auto at = [&](uint32_t code) {
+      const int di = static_cast<int>((code >> F::kDB) & F::kMask) - F::kOff;
+      const int dj = static_cast<int>(code & F::kMask) - F::kOff;
+      return qoff + (((ci + di) & m) << ls) + ((cj + dj) & m);
+    };
+    return make_int4(at(c.x), at(c.y), at(c.z), at(c.w));
+  }
+  return make_int4(decode_col_tile(g, rc, c.x), decode_col_tile(g, rc, c.y), decode_col_tile(g, rc, c.z),
+                   decode_col_tile(g, rc, c.w));
+}
+
 // Dot product of the lane's row with x over float32 values (groups of 4
 // codes, U groups per step).  A step decodes its columns, issues the
 // gathers, then the loads of the next step's codes and values, and only
@@ -124,13 +150,11 @@ __device__ __forceinline__ float tile_dot(const TiledView& T, const Geo& g, cons
   float4 v[U];
   tile_load<W, U>(T, k, g1, lane, c, v);
   for (; k < g1; k += W * U) {
-    float xs[4 * U];
+    float4 xs[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      xs[4 * u] = ld_at(x, decode_col_tile(g, rc, c[u].x));
-      xs[4 * u + 1] = ld_at(x, decode_col_tile(g, rc, c[u].y));
-      xs[4 * u + 2] = ld_at(x, decode_col_tile(g, rc, c[u].z));
-      xs[4 * u + 3] = ld_at(x, decode_col_tile(g, rc, c[u].w));
+      const int4 col = group_cols(g, rc, c[u]);
+      xs[u] = make_float4(ld_at(x, col.x), ld_at(x, col.y), ld_at(x, col.z), ld_at(x, col.w));
     }
     __builtin_amdgcn_sched_barrier(0);
     float4 vn[U];
@@ -138,10 +162,10 @@ __device__ __forceinline__ float tile_dot(const TiledView& T, const Geo& g, cons
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      acc = fmaf(v[u].x, xs[4 * u], acc);
-      acc = fmaf(v[u].y, xs[4 * u + 1], acc);
-      acc = fmaf(v[u].z, xs[4 * u + 2], acc);
-      acc = fmaf(v[u].w, xs[4 * u + 3], acc);
+      acc = fmaf(v[u].x, xs[u].x, acc);
+      acc = fmaf(v[u].y, xs[u].y, acc);
+      acc = fmaf(v[u].z, xs[u].z, acc);
+      acc = fmaf(v[u].w, xs[u].w, acc);
       v[u] = vn[u];
     }
   }
