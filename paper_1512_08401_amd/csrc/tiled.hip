@@ -196,7 +196,8 @@ __device__ __forceinline__ void tile_load16(const TiledView& T, int k, int g1, i
 }
 
 // The same over 16-bit values: groups of 8 codes, one 16-byte vector of 8
-// values per lane and group, in the same step order as tile_dot.
+// values per lane and group, in the same step order as tile_dot (the columns
+// of each half group of 4 codes from group_cols).
 template <int W, int U, int FMT>
 __device__ __forceinline__ float tile_dot16(const TiledView& T, const Geo& g, const int4& d, int row, int lane,
                                             int wv, const float* __restrict__ x) {
@@ -210,10 +211,11 @@ __device__ __forceinline__ float tile_dot16(const TiledView& T, const Geo& g, co
     float xs[8 * U];
 #pragma unroll
     for (int u = 0; u < 2 * U; ++u) {
-      xs[4 * u] = ld_at(x, decode_col_tile(g, rc, c[u].x));
-      xs[4 * u + 1] = ld_at(x, decode_col_tile(g, rc, c[u].y));
-      xs[4 * u + 2] = ld_at(x, decode_col_tile(g, rc, c[u].z));
-      xs[4 * u + 3] = ld_at(x, decode_col_tile(g, rc, c[u].w));
+      const int4 col = group_cols(g, rc, c[u]);
+      xs[4 * u] = ld_at(x, col.x);
+      xs[4 * u + 1] = ld_at(x, col.y);
+      xs[4 * u + 2] = ld_at(x, col.z);
+      xs[4 * u + 3] = ld_at(x, col.w);
     }
     __builtin_amdgcn_sched_barrier(0);
     uint4 vn[U];
@@ -251,10 +253,11 @@ __device__ __forceinline__ double tile_dot64(const TiledView& T, const Geo& g, c
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      acc = fma(static_cast<double>(v[u].x), static_cast<double>(x[decode_col_tile(g, rc, c[u].x)]), acc);
-      acc = fma(static_cast<double>(v[u].y), static_cast<double>(x[decode_col_tile(g, rc, c[u].y)]), acc);
-      acc = fma(static_cast<double>(v[u].z), static_cast<double>(x[decode_col_tile(g, rc, c[u].z)]), acc);
-      acc = fma(static_cast<double>(v[u].w), static_cast<double>(x[decode_col_tile(g, rc, c[u].w)]), acc);
+      const int4 col = group_cols(g, rc, c[u]);
+      acc = fma(static_cast<double>(v[u].x), static_cast<double>(ld_at(x, col.x)), acc);
+      acc = fma(static_cast<double>(v[u].y), static_cast<double>(ld_at(x, col.y)), acc);
+      acc = fma(static_cast<double>(v[u].z), static_cast<double>(ld_at(x, col.z)), acc);
+      acc = fma(static_cast<double>(v[u].w), static_cast<double>(ld_at(x, col.w)), acc);
     }
   }
   return tile_finish<W, double>(T, d, row, lane, wv, acc, x);
