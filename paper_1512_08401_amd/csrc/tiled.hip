@@ -135,10 +135,11 @@ __device__ __forceinline__ int4 group_cols(const Geo& g, const RowCode& rc, cons
 // Dot product of the lane's row with x over float32 values (groups of 4
 // codes, U groups per step).  A step decodes its columns, issues the
 // gathers, then the loads of the next step's codes and values, and only
-// then waits for the gathers: the next loads are in flight during the
-// multiply-adds and the next decode.  Waits on scalar loads cover every
-// scalar load in flight, so the next codes are requested only after this
-// step's codes are used (the scheduling barriers keep that order).
+// then waits for the gathers: the latency of the next loads overlaps the
+// wait for this step's gathers instead of following it.  Waits on scalar
+// loads cover every scalar load in flight, so the next codes are requested
+// only after this step's codes are used (the scheduling barriers keep that
+// order).
 template <int W, int U>
 __device__ __forceinline__ float tile_dot(const TiledView& T, const Geo& g, const int4& d, int row, int lane,
                                           int wv, const float* __restrict__ x) {
