@@ -466,6 +466,42 @@ struct TileOut {
   std::vector<float> eval;
 };
 
+// Launch order of the tiles.  Workgroups are dealt round-robin to the 8
+// XCDs (block b to XCD b mod 8), each with its own L2.  Band by band (the
+// coarse bands first, as in the tile list), the band's tiles are cut into 8
+// contiguous runs and position p of the launch takes the next tile of run
+// p mod 8, so each XCD works on one spatial run of every band and the x
+// windows of its tiles overlap; a run that is used up hands its positions to
+// the others.  Returns the tile-list index of each launch position.
+std::vector<int> xcd_order(const Geo& g, const std::vector<int4>& tiles) {
+  constexpr int kX = 8;
+  std::vector<int> order;
+  order.reserve(tiles.size());
+  size_t b0 = 0;
+  while (b0 < tiles.size()) {
+    size_t b1 = b0 + 1;  // tiles of one band are adjacent in the list, with the same side and band base
+    const int ls = tiles[b0].w & 0xFF;
+    const int base = tiles[b0].z & ~((1 << (2 * ls)) - 1);
+    while (b1 < tiles.size() && (tiles[b1].w & 0xFF) == ls && (tiles[b1].z & ~((1 << (2 * ls)) - 1)) == base &&
+           !(tiles[b1].w & kSmall))
+      ++b1;
+    const size_t n = b1 - b0;
+    size_t next[kX], end[kX];
+    for (int k = 0; k < kX; ++k) {
+      next[k] = b0 + n * k / kX;
+      end[k] = b0 + n * (k + 1) / kX;
+    }
+    for (size_t done = 0; done < n; ++done) {
+      int k = static_cast<int>(order.size() % kX);
+      for (int tries = 0; tries < kX && next[k] == end[k]; ++tries) k = (k + 1) % kX;
+      order.push_back(static_cast<int>(next[k]++));
+    }
+    b0 = b1;
+  }
+  (void)g;
+  return order;
+}
+
 // Encode the tiles [t0, t1) of the tile list into `o` (pattern indices local
 // to `o`; the caller rebases them).
 // grp: codes per value group (4 for float32, 8 for 16-bit values); ub: the
@@ -569,7 +605,11 @@ void build_one(const wdb_theta* th, const Csr32& src, Tiled* out, int fmt = WDB_
     WDB_HIP(hipMemcpy(col.data(), src.col, src.stored * sizeof(int32_t), hipMemcpyDeviceToHost));
     WDB_HIP(hipMemcpy(val.data(), src.val, src.stored * sizeof(float), hipMemcpyDeviceToHost));
   }
-  const std::vector<int4> tiles = tile_list(g);
+  std::vector<int4> tiles;
+  {
+    const std::vector<int4> listed = tile_list(g);
+    for (int t : xcd_order(g, listed)) tiles.push_back(listed[t]);
+  }
   const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   const size_t nt = tiles.size(), parts = std::min<size_t>(hw, std::max<size_t>(1, nt / 64));
   std::vector<TileOut> res(parts);
