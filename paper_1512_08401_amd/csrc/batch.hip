@@ -119,10 +119,11 @@ __device__ __forceinline__ int tile_mm(const ChunkDev& C, int m, int tile, const
   for (int k = (d.x >> 2) + wv; k < (d.y >> 2); k += kWaves) {
     const uint4 c = code[k];
     const float4 v = val[static_cast<int64_t>(k) * kWave + lane];
-    gather8(V, decode_col_tile(C.geo, rc, c.x), v.x, acc);
-    gather8(V, decode_col_tile(C.geo, rc, c.y), v.y, acc);
-    gather8(V, decode_col_tile(C.geo, rc, c.z), v.z, acc);
-    gather8(V, decode_col_tile(C.geo, rc, c.w), v.w, acc);
+    const int4 col = group_cols(C.geo, rc, c);
+    gather8(V, col.x, v.x, acc);
+    gather8(V, col.y, v.y, acc);
+    gather8(V, col.z, v.z, acc);
+    gather8(V, col.w, v.w, acc);
   }
   if (row >= 0 && (d.w & kHasEsc))  // escapes dealt round-robin to the wavefronts
     for (int k = C.terp[m][row] + wv; k < C.terp[m][row + 1]; k += kWaves) gather8(V, C.tec[m][k], C.tev[m][k], acc);

@@ -162,6 +162,32 @@ __host__ __device__ inline RowCode tile_row_code(const Geo& g, const int4& d, in
   return rc;
 }
 
+// Columns of 4 codes.  When the 4 share the level and band fields (the
+// common case: a tile's codes are sorted, so codes come in runs with the
+// same level and band), the lane shifts its centre once for the group and
+// each code only adds its displacements; otherwise each code is decoded in
+// full.  Both give decode_col_tile's columns.
+__host__ __device__ inline int4 group_cols(const Geo& g, const RowCode& rc, const uint4& c) {
+  using F = CodeTile;
+  if ((((c.x ^ c.y) | (c.x ^ c.z) | (c.x ^ c.w)) >> F::kQS) == 0) {
+    const int lb = min(max(rc.lb0 + static_cast<int>((c.x >> (F::kQS + 2)) & 7u), 1), g.J);
+    const int ls = g.logn - lb;
+    const int t = (1 - g.L1) * (1 << lb);
+    const int m = (1 << ls) - 1;
+    const int ci = (rc.pi + t) >> (lb + 1);
+    const int cj = (rc.pj + t) >> (lb + 1);
+    const int qoff = static_cast<int>((c.x >> F::kQS) & 3u) << (2 * ls);
+    const auto at = [&](uint32_t code) {
+      const int di = static_cast<int>((code >> F::kDB) & F::kMask) - F::kOff;
+      const int dj = static_cast<int>(code & F::kMask) - F::kOff;
+      return qoff + (((ci + di) & m) << ls) + ((cj + dj) & m);
+    };
+    return make_int4(at(c.x), at(c.y), at(c.z), at(c.w));
+  }
+  return make_int4(decode_col_tile(g, rc, c.x), decode_col_tile(g, rc, c.y), decode_col_tile(g, rc, c.z),
+                   decode_col_tile(g, rc, c.w));
+}
+
 inline Geo geo_of(const wdb_theta* th) {
   return Geo{floor_log2(static_cast<uint64_t>(th->n)), th->levels,
              static_cast<int>(make_filter(th->wavelet).h.size()) - 1};

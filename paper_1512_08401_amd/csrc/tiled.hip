@@ -106,32 +106,6 @@ __device__ __forceinline__ void tile_load(const TiledView& T, int k, int g1, int
   }
 }
 
-// Columns of 4 codes.  When the 4 share the level and band fields (the
-// common case: a tile's codes are sorted, so codes come in runs with the
-// same level and band), the lane shifts its centre once for the group and
-// each code only adds its displacements; otherwise each code is decoded in
-// full.  Both give decode_col_tile's columns.
-__device__ __forceinline__ int4 group_cols(const Geo& g, const RowCode& rc, const uint4& c) {
-  using F = CodeTile;
-  if ((((c.x ^ c.y) | (c.x ^ c.z) | (c.x ^ c.w)) >> F::kQS) == 0) {
-    const int lb = min(max(rc.lb0 + static_cast<int>((c.x >> (F::kQS + 2)) & 7u), 1), g.J);
-    const int ls = g.logn - lb;
-    const int t = (1 - g.L1) * (1 << lb);
-    const int m = (1 << ls) - 1;
-    const int ci = (rc.pi + t) >> (lb + 1);
-    const int cj = (rc.pj + t) >> (lb + 1);
-    const int qoff = static_cast<int>((c.x >> F::kQS) & 3u) << (2 * ls);
-    const auto at = [&](uint32_t code) {
-      const int di = static_cast<int>((code >> F::kDB) & F::kMask) - F::kOff;
-      const int dj = static_cast<int>(code & F::kMask) - F::kOff;
-      return qoff + (((ci + di) & m) << ls) + ((cj + dj) & m);
-    };
-    return make_int4(at(c.x), at(c.y), at(c.z), at(c.w));
-  }
-  return make_int4(decode_col_tile(g, rc, c.x), decode_col_tile(g, rc, c.y), decode_col_tile(g, rc, c.z),
-                   decode_col_tile(g, rc, c.w));
-}
-
 // Dot product of the lane's row with x over float32 values (groups of 4
 // codes, U groups per step).  A step decodes its columns, issues the
 // gathers, then the loads of the next step's codes and values, and only
