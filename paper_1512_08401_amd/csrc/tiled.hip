@@ -25,7 +25,10 @@
 // its block and the W partial sums are added in LDS in wavefront order
 // (deterministic).  Entries whose code does not fit (displacement beyond 128
 // or level gap beyond 3) go to per-row escape lists, whose entries are dealt
-// round-robin to the wavefronts as well.
+// round-robin to the wavefronts as well.  The tiles are stored and launched
+// in an XCD-aware order (xcd_order): each XCD works on one horizontal stripe
+// of every subband, so its L2 serves overlapping windows of the gathered
+// vector.
 #include <algorithm>
 #include <cstring>
 #include <exception>
@@ -447,7 +450,7 @@ struct TileOut {
 // p mod 8, so each XCD works on one spatial run of every band and the x
 // windows of its tiles overlap; a run that is used up hands its positions to
 // the others.  Returns the tile-list index of each launch position.
-std::vector<int> xcd_order(const Geo& g, const std::vector<int4>& tiles) {
+std::vector<int> xcd_order(const std::vector<int4>& tiles) {
   constexpr int kX = 8;
   std::vector<int> order;
   order.reserve(tiles.size());
@@ -472,7 +475,6 @@ std::vector<int> xcd_order(const Geo& g, const std::vector<int4>& tiles) {
     }
     b0 = b1;
   }
-  (void)g;
   return order;
 }
 
@@ -582,7 +584,7 @@ void build_one(const wdb_theta* th, const Csr32& src, Tiled* out, int fmt = WDB_
   std::vector<int4> tiles;
   {
     const std::vector<int4> listed = tile_list(g);
-    for (int t : xcd_order(g, listed)) tiles.push_back(listed[t]);
+    for (int t : xcd_order(listed)) tiles.push_back(listed[t]);
   }
   const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   const size_t nt = tiles.size(), parts = std::min<size_t>(hw, std::max<size_t>(1, nt / 64));

@@ -106,7 +106,7 @@ void check(int logn, int J, int L1, std::mt19937_64& rng) {
   for (int c : cover) once = once && c == 1;
   expect(once, "every coefficient in exactly one tile", logn, J);
 
-  const std::vector<int> order = xcd_order(g, listed);
+  const std::vector<int> order = xcd_order(listed);
   std::vector<int> sorted(order);
   std::sort(sorted.begin(), sorted.end());
   bool perm = sorted.size() == listed.size();
