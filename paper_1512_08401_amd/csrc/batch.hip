@@ -307,28 +307,26 @@ __global__ __launch_bounds__(kBlock) void k_check_bwd(const ChunkDev* __restrict
   if (threadIdx.x < kR) part[(3 * kR + threadIdx.x) * nblocks + blockIdx.x] = out[threadIdx.x];
 }
 
-// One block per chunk: reduce that chunk's block range for 4 x 8 values.
+// One block per chunk and value: reduce that chunk's block range for one of
+// its 4 x 8 values (sums, or the maximum for the last 8).
 __global__ __launch_bounds__(kBlock) void k_check_reduce(const int* __restrict__ first, const double* __restrict__ part,
                                                          int64_t nblocks, double* __restrict__ out) {
   __shared__ double sh[kBlock];
-  const int c = blockIdx.x;
+  const int c = blockIdx.x / (4 * kR), v = blockIdx.x % (4 * kR);
   const int b0 = first[c], b1 = first[c + 1];
-  for (int v = 0; v < 4 * kR; ++v) {
-    const bool mx = v >= 3 * kR;
-    double acc = 0.0;
-    for (int b = b0 + threadIdx.x; b < b1; b += kBlock) {
-      const double p = part[static_cast<int64_t>(v) * nblocks + b];
-      acc = mx ? fmax(acc, p) : acc + p;
-    }
-    sh[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-      if (threadIdx.x < w) sh[threadIdx.x] = mx ? fmax(sh[threadIdx.x], sh[threadIdx.x + w]) : sh[threadIdx.x] + sh[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) out[c * 4 * kR + v] = sh[0];
+  const bool mx = v >= 3 * kR;
+  double acc = 0.0;
+  for (int b = b0 + threadIdx.x; b < b1; b += kBlock) {
+    const double p = part[static_cast<int64_t>(v) * nblocks + b];
+    acc = mx ? fmax(acc, p) : acc + p;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] = mx ? fmax(sh[threadIdx.x], sh[threadIdx.x + w]) : sh[threadIdx.x] + sh[threadIdx.x + w];
     __syncthreads();
   }
+  if (threadIdx.x == 0) out[c * 4 * kR + v] = sh[0];
 }
 
 __global__ void k_interleave(const float* __restrict__ src, float* __restrict__ dst, int64_t N, int j) {
@@ -540,7 +538,7 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
                          part.p, nblocks);
       hipLaunchKernelGGL(k_check_bwd, dim3(static_cast<unsigned>(nblocks)), dim3(kBlock), 0, s, dch.p, dfirst.p, nch,
                          part.p, nblocks);
-      hipLaunchKernelGGL(k_check_reduce, dim3(nch), dim3(kBlock), 0, s, dfirst.p, part.p, nblocks, red.p);
+      hipLaunchKernelGGL(k_check_reduce, dim3(nch * 4 * kR), dim3(kBlock), 0, s, dfirst.p, part.p, nblocks, red.p);
       WDB_HIP(hipGetLastError());
       WDB_HIP(hipMemcpyAsync(hred.data(), red.p, hred.size() * sizeof(double), hipMemcpyDeviceToHost, s));
       WDB_HIP(hipStreamSynchronize(s));
