@@ -211,7 +211,7 @@ wdb_status wdb_set_precond(wdb_theta* th, int32_t kind, double eps, const double
  * u_A for every column subband B.  The iteration reads a packed copy: one
  * 32-bit word per entry, q in the high half and a band-relative column code in
  * the low half (column level minus row level in [-3, 3], orientation, and the
- * 2-D displacement in [-22, 22]^2 from the point of that level nearest to the
+ * 2-D displacement in [-16, 15]^2 from the point of that level nearest to the
  * row's atom, modulo the subband side), so 4 bytes per entry; entries outside
  * the code (counted in wdb_theta_desc.escapes) are read from a per-row list
  * with int32 columns.  The columns decode exactly, so the product is that of
@@ -250,8 +250,10 @@ wdb_status wdb_set_packed_group(wdb_theta* th, int32_t group);
  * built on first use, about 1.6 x K float32 values per matrix for the
  * smoothly varying fields of Sec. 5).  The float64 checks and the power
  * iteration use vector CSR under layouts 1 and 3, else the same choice; the
- * batched solver always uses the sliced-ELL copy and the 16-bit iteration
- * its packed copy.  Synchronises.  Errors: WDB_ERR_ARG, _OOM, _HIP. */
+ * batched solver runs an operator's packs on its tiled copies under layout 3
+ * and on the sliced-ELL copies otherwise; the 16-bit iteration reads its
+ * packed copy or its 16-bit tiles (wdb_set_precision).  Synchronises.
+ * Errors: WDB_ERR_ARG, _OOM, _HIP. */
 wdb_status wdb_set_kernel_layout(wdb_theta* th, int32_t slice, int32_t group);
 
 /* Shape of the tiled kernels of the current value type (float32: layout 3;
@@ -262,10 +264,15 @@ wdb_status wdb_set_kernel_layout(wdb_theta* th, int32_t slice, int32_t group);
  * Changes only the summation order.  Errors: WDB_ERR_ARG. */
 wdb_status wdb_set_tile_shape(wdb_theta* th, int32_t waves, int32_t unroll);
 
-/* Project autotuner: times the iteration kernel pair `reps` times for every
- * candidate layout (slices of 64/32/16/8 rows; vector CSR with 4/8/16 lanes)
- * on this operator and keeps the fastest; with 16-bit values set it then also
- * picks the packed kernels' lanes per row (2/4/8/16).  If cache_path is not NULL the
+/* Project autotuner: times the iteration kernel pair `reps` times (two
+ * alternating passes, the better pass counted) for every candidate layout on
+ * this operator -- sliced ELL with 64/32/16/8 rows per slice; vector CSR with
+ * 2/4/8/16 lanes per row; the circulant storage when the operator came from
+ * the convolution fast path; the tiled pattern storage with 1/2/4/8
+ * wavefronts per tile and 2/4 code groups in flight -- and keeps the first
+ * candidate in that order within 2% of the fastest.  With 16-bit values set
+ * it instead picks among the packed kernels (2/4/8/16 lanes per row) and the
+ * 16-bit tiles (1/2/4/8 wavefronts, 1/2 groups in flight).  If cache_path is not NULL the
  * decision is looked up in / appended to that text file, keyed by the
  * operator's shape and a hash of its row pointer.  Outputs (optional): the
  * chosen slice height and lanes per row, and the time of one iteration pair in
@@ -446,10 +453,14 @@ const char* wdb_last_error(void);
 const char* wdb_version(void);
 
 /* Low-pass analysis filter the library uses for `wavelet` (derived in
- * float64; Daubechies by spectral factorisation), written to h_out (host,
- * room for 8 doubles); *len_out receives the number of taps.  Host only: no
- * device is touched. */
-wdb_status wdb_wavelet_filter(int32_t wavelet, double* h_out, int32_t* len_out);
+ * float64; Daubechies and Symmlet by spectral factorisation).  h_out is a
+ * host array of `capacity` doubles (taps: 2 for Haar, 8 for db4, 12 for
+ * sym6; 12 covers every wavelet); *len_out always receives the number of
+ * taps.  h_out = NULL with capacity = 0 only queries the length.  Errors:
+ * WDB_ERR_ARG for an unknown wavelet, a null len_out, or capacity below the
+ * number of taps (h_out is then not written).  Host only: no device is
+ * touched. */
+wdb_status wdb_wavelet_filter(int32_t wavelet, double* h_out, int32_t capacity, int32_t* len_out);
 
 #ifdef __cplusplus
 }

@@ -236,11 +236,17 @@ std::vector<Subband> layout(int32_t n, int32_t levels) {
 
 }  // namespace wdb
 
-extern "C" wdb_status wdb_wavelet_filter(int32_t wavelet, double* h_out, int32_t* len_out) {
+extern "C" wdb_status wdb_wavelet_filter(int32_t wavelet, double* h_out, int32_t capacity,
+                                         int32_t* len_out) {
   WDB_API_BEGIN
-  WDB_REQUIRE(h_out && len_out, WDB_ERR_ARG, "null output pointer");
+  WDB_REQUIRE(len_out, WDB_ERR_ARG, "null len_out");
+  WDB_REQUIRE(capacity >= 0, WDB_ERR_ARG, "negative capacity");
   wdb::Filter f = wdb::make_filter(wavelet);
-  for (size_t i = 0; i < f.h.size(); ++i) h_out[i] = f.h[i];
-  *len_out = static_cast<int32_t>(f.h.size());
+  const int32_t taps = static_cast<int32_t>(f.h.size());
+  *len_out = taps;
+  if (h_out == nullptr && capacity == 0) return WDB_OK;  // length query
+  WDB_REQUIRE(h_out, WDB_ERR_ARG, "null h_out with non-zero capacity");
+  WDB_REQUIRE(capacity >= taps, WDB_ERR_ARG, "h_out holds %d doubles, the filter has %d taps", capacity, taps);
+  for (int32_t i = 0; i < taps; ++i) h_out[i] = f.h[i];
   WDB_API_END
 }

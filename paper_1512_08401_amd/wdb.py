@@ -91,7 +91,7 @@ _SIGS = {
     "wdb_synthesize": [_vp, _vp, _vp, _vp],
     "wdb_dwt": [_i32, _i32, _i32, _vp, _vp, _i32, _vp],
     "wdb_blur": [C.POINTER(PsfFieldC), _vp, _vp, _vp],
-    "wdb_wavelet_filter": [_i32, _pd, C.POINTER(_i32)],
+    "wdb_wavelet_filter": [_i32, _pd, _i32, C.POINTER(_i32)],
     "wdb_set_precision": [_vp, _i32],
     "wdb_set_kernel_layout": [_vp, _i32, _i32],
     "wdb_set_packed_group": [_vp, _i32],
@@ -130,10 +130,12 @@ def version() -> str:
 
 def wavelet_filter(name: str) -> np.ndarray:
     """Low-pass analysis filter the library derives for ``name`` (host only)."""
-    h = np.zeros(16)
     ln = C.c_int32(0)
-    _check("wdb_wavelet_filter", _lib.wdb_wavelet_filter(WAVELETS[name], h.ctypes.data_as(_pd), C.byref(ln)))
-    return h[: ln.value].copy()
+    _check("wdb_wavelet_filter", _lib.wdb_wavelet_filter(WAVELETS[name], None, 0, C.byref(ln)))
+    h = np.zeros(ln.value)
+    _check("wdb_wavelet_filter", _lib.wdb_wavelet_filter(WAVELETS[name], h.ctypes.data_as(_pd), ln.value,
+                                                         C.byref(ln)))
+    return h
 
 
 # --------------------------------------------------------------------------

@@ -46,12 +46,33 @@ def test_library_symlet_matches_oracle():
     assert len(h) == 12 and np.max(np.abs(h - filters.sym6())) < 1e-13
 
 
+def test_wavelet_filter_honours_the_documented_capacity(lib):
+    """The header's buffer contract: 12 doubles hold every filter (sym6 has 12
+    taps); a smaller capacity is refused without writing past it, and a
+    length query writes nothing."""
+    from paper_1512_08401_amd import wdb
+    pd = C.POINTER(C.c_double)
+    ln = C.c_int32(-1)
+    assert lib.wdb_wavelet_filter(wdb.WAVELETS["sym6"], None, 0, C.byref(ln)) == wdb.WDB_OK
+    assert ln.value == 12
+    buf = np.full(14, 7.0)          # 12 documented doubles plus two guard entries
+    assert lib.wdb_wavelet_filter(wdb.WAVELETS["sym6"], buf.ctypes.data_as(pd), 12, C.byref(ln)) == wdb.WDB_OK
+    assert ln.value == 12 and np.all(buf[12:] == 7.0) and abs(buf[:12].sum() - 2 ** 0.5) < 1e-14
+    small = np.full(10, 7.0)
+    assert lib.wdb_wavelet_filter(wdb.WAVELETS["sym6"], small.ctypes.data_as(pd), 8, C.byref(ln)) == wdb.WDB_ERR_ARG
+    assert ln.value == 12 and np.all(small == 7.0)
+    assert "12 taps" in lib.wdb_last_error().decode()
+    for name, taps in (("haar", 2), ("db4", 8)):
+        assert lib.wdb_wavelet_filter(wdb.WAVELETS[name], buf.ctypes.data_as(pd), 12, C.byref(ln)) == wdb.WDB_OK
+        assert ln.value == taps
+
+
 def test_host_validation_errors(lib):
     from paper_1512_08401_amd import wdb
     fake = C.c_void_p(16)   # never dereferenced: validation fails first
     h = np.zeros(8)
     ln = C.c_int32()
-    assert lib.wdb_wavelet_filter(7, h.ctypes.data_as(C.POINTER(C.c_double)), C.byref(ln)) == wdb.WDB_ERR_ARG
+    assert lib.wdb_wavelet_filter(7, h.ctypes.data_as(C.POINTER(C.c_double)), 8, C.byref(ln)) == wdb.WDB_ERR_ARG
     assert "unknown wavelet" in lib.wdb_last_error().decode()
     assert lib.wdb_dwt(48, 0, 1, fake, C.c_void_p(32), 0, None) == wdb.WDB_ERR_SIZE
     assert lib.wdb_dwt(64, 1, 5, fake, C.c_void_p(32), 0, None) == wdb.WDB_ERR_LEVELS   # 64/16 < 8 taps
