@@ -303,6 +303,17 @@ typedef struct {
   double target_objective; /* > 0: also stop at the first check with E <= target     */
   int32_t ista;          /* 1: no extrapolation, x_k = prox(x_{k-1} - tau grad) (ISTA, the
                             un-accelerated baseline of the paper's comparison)     */
+  int32_t plain_iterate; /* 0 (default): with float32 values the iterate is held as a
+                            float64 anchor plus a float32 displacement, moved into the
+                            anchor at every check, so the float64 stopping test can
+                            certify gaps far below what a float32 iterate's rounding
+                            allows (one extra 8-byte read per coefficient and
+                            iteration); 1: float32 iterate only.  16-bit values and
+                            the batched solver always use the float32 iterate.    */
+  double* x64_out;       /* device, N doubles, or NULL: receives the float64 iterate the
+                            last check scored (the anchor; x_out is its float32
+                            rounding, whose own gap can be larger); with a plain
+                            float32 iterate, x_out widened to float64             */
 } wdb_solve_opts;
 
 typedef struct {

@@ -74,10 +74,10 @@ void Csr::free_all() {
 
 void free_workspace(wdb_theta* th) {
   drop_graph(th);
-  float* fs[] = {th->ws_x0, th->ws_r, th->ws_y, th->ws_img, th->ws_img2, th->pinv};
+  float* fs[] = {th->ws_x0, th->ws_r, th->ws_y, th->ws_img, th->ws_img2, th->pinv, th->ws_c};
   for (float* p : fs)
     if (p) (void)hipFree(p);
-  double* ds[] = {th->ws_r64, th->ws_v64, th->ws_partial, th->ws_scalar, th->p64, th->ws_checks};
+  double* ds[] = {th->ws_r64, th->ws_v64, th->ws_partial, th->ws_scalar, th->p64, th->ws_checks, th->ws_a64};
   for (double* p : ds)
     if (p) (void)hipFree(p);
   if (th->host_scalar) (void)hipHostFree(th->host_scalar);
@@ -87,8 +87,8 @@ void free_workspace(wdb_theta* th) {
   th->ws_k = nullptr;
   th->ws_rho = nullptr;
   th->capture_stream = nullptr;
-  th->ws_x0 = th->ws_r = th->ws_y = th->ws_img = th->ws_img2 = th->pinv = nullptr;
-  th->ws_r64 = th->ws_v64 = th->ws_partial = th->ws_scalar = th->p64 = th->ws_checks = nullptr;
+  th->ws_x0 = th->ws_r = th->ws_y = th->ws_img = th->ws_img2 = th->pinv = th->ws_c = nullptr;
+  th->ws_r64 = th->ws_v64 = th->ws_partial = th->ws_scalar = th->p64 = th->ws_checks = th->ws_a64 = nullptr;
   th->ws_ncheck = 0;
   th->host_scalar = nullptr;
 }

@@ -28,7 +28,7 @@ int kernel_group(const wdb_theta* th);
 void launch_res(int G, const Sell& sell, const Csr32& csr, const float* y, const float* b, float* r, int* kdev,
                 hipStream_t s);
 void launch_prox(int G, const Sell& sell, const Csr32& csr, const float* r, float* x, float* y, float tau, float thr,
-                 float beta, const int* kdev, const float* pinv, const float* tw, hipStream_t s);
+                 float beta, const int* kdev, const float* pinv, const float* tw, const double* anc, hipStream_t s);
 }  // namespace wdb
 
 namespace {
@@ -221,17 +221,19 @@ extern "C" wdb_status wdb_autotune(wdb_theta* th, const char* cache_path, int32_
         auto pair = [&]() {
           if (G == kTiled) {
             launch_res_tiled(th, false, th->ws_y, th->ws_x0, th->ws_r, nullptr, s);
-            launch_prox_tiled(th, th->ws_r, th->ws_img, th->ws_y, 1e-3f, 1e-6f, 0.5f, nullptr, nullptr, nullptr, s);
+            launch_prox_tiled(th, th->ws_r, th->ws_img, th->ws_y, 1e-3f, 1e-6f, 0.5f, nullptr, nullptr, nullptr,
+                              th->ws_a64, s);
             return;
           }
           if (G == kStencil) {
             launch_res_stencil(th, false, th->ws_y, th->ws_x0, th->ws_r, nullptr, s);
-            launch_prox_stencil(th, th->ws_r, th->ws_img, th->ws_y, 1e-3f, 1e-6f, 0.5f, nullptr, nullptr, nullptr, s);
+            launch_prox_stencil(th, th->ws_r, th->ws_img, th->ws_y, 1e-3f, 1e-6f, 0.5f, nullptr, nullptr, nullptr,
+                                th->ws_a64, s);
             return;
           }
           launch_res(G, th->A, th->cA, th->ws_y, th->ws_x0, th->ws_r, nullptr, s);
           launch_prox(G, th->At, th->cAt, th->ws_r, th->ws_img, th->ws_y, 1e-3f, 1e-6f, 0.5f, nullptr, nullptr,
-                      nullptr, s);
+                      nullptr, th->ws_a64, s);
         };
         for (int i = 0; i < 3; ++i) pair();
         WDB_HIP(hipEventRecord(e0, s));

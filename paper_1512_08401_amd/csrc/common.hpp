@@ -271,6 +271,8 @@ struct wdb_theta {
   float* ws_r = nullptr;
   float* ws_y = nullptr;
   double* ws_r64 = nullptr;
+  double* ws_a64 = nullptr;      // float64 anchor of the iterate (x = anchor + float32 displacement)
+  float* ws_c = nullptr;         // x0 - Theta_K anchor (right-hand side of the displacement iteration)
   double* ws_v64 = nullptr;
   double* ws_partial = nullptr;  // per-block partial reductions (4 per block)
   double* ws_scalar = nullptr;   // device scalars
@@ -290,7 +292,7 @@ struct wdb_theta {
   hipGraph_t g_graph = nullptr;
   hipGraphExec_t g_exec = nullptr;
   const float* g_x = nullptr;
-  int g_c = 0, g_pre = 0, g_ista = 0;
+  int g_c = 0, g_pre = 0, g_ista = 0, g_anchor = 0;
   float g_tau = 0.0f, g_thr = 0.0f;
 };
 
@@ -323,6 +325,8 @@ void build_tiled16(wdb_theta* th);  // builds qA / qAt (16-bit values, scales qs
 int64_t tiled_check_blocks(const wdb_theta* th);
 void launch_objective_tiled(const wdb_theta* th, const float* x, const float* x0, double* r64, double* part,
                             int64_t nb, hipStream_t s);
+void launch_objective_tiled(const wdb_theta* th, const double* x, const float* x0, double* r64, double* part,
+                            int64_t nb, hipStream_t s);
 void launch_res_tiled16(const wdb_theta* th, const float* y, const float* b, float* r, int* kdev, int scale_out,
                         hipStream_t s);
 void launch_prox_tiled16(const wdb_theta* th, const float* rs, float* x, float* y, float tau, float thr,
@@ -330,11 +334,11 @@ void launch_prox_tiled16(const wdb_theta* th, const float* rs, float* x, float* 
 void launch_res_tiled(const wdb_theta* th, bool transpose, const float* y, const float* b, float* r, int* kdev,
                       hipStream_t s);
 void launch_prox_tiled(const wdb_theta* th, const float* r, float* x, float* y, float tau, float thr, float beta,
-                       const int* kdev, const float* pinv, const float* tw, hipStream_t s);
+                       const int* kdev, const float* pinv, const float* tw, const double* anc, hipStream_t s);
 void launch_res_stencil(const wdb_theta* th, bool transpose, const float* y, const float* b, float* r, int* kdev,
                         hipStream_t s);
 void launch_prox_stencil(const wdb_theta* th, const float* r, float* x, float* y, float tau, float thr, float beta,
-                         const int* kdev, const float* pinv, const float* tw, hipStream_t s);
+                         const int* kdev, const float* pinv, const float* tw, const double* anc, hipStream_t s);
 
 // Per-row threshold multipliers of the proximal step: w (l1 weights) or w / P
 // (with the preconditioner), or null for uniform weights.
@@ -343,6 +347,19 @@ const float* threshold_weights(const wdb_theta* th, bool pre);
 void refresh_threshold_weights(wdb_theta* th);
 int default_slice_height();
 int kernel_group(const wdb_theta* th);  // lanes per row in use (0: sliced ELL)
+// Lanczos on D A^T A D (d = nullptr: identity), float64, full
+// reorthogonalisation within a cycle: the largest Ritz value theta, the residual bound
+// resid = beta_m |s_m| of its Ritz pair (some eigenvalue lies within resid of
+// theta), the steps taken, and whether resid <= tol * theta was met.
+struct LanczosResult {
+  double theta, resid;
+  int steps;
+  bool converged;
+};
+// Restarted every `cycle` steps from the top Ritz vector (the basis then
+// holds cycle + 1 vectors of N doubles).
+LanczosResult lanczos_max(wdb_theta* th, const double* start_host, const double* dinv_sqrt, double tol, int max_steps,
+                          hipStream_t s, int cycle = 48);
 // Power iteration on D^-1/2 A^T A D^-1/2 (d = nullptr: identity), float64.
 double power_iteration(wdb_theta* th, const double* start_host, const double* dinv_sqrt,
                        double tol, int max_iters, int* iters_out, hipStream_t s);

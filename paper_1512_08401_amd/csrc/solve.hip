@@ -13,11 +13,15 @@
 // Gathers go through the caches and every row is accumulated in float32 in a
 // fixed order, so results are bitwise reproducible (no atomics on values).
 // The 16-bit form uses the packed kernels of packed.hip instead.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <limits>
 #include <type_traits>
 
 #include "common.hpp"
+#include "prox.hpp"
+#include "tridiag.hpp"
 
 namespace wdb {
 
@@ -148,7 +152,7 @@ template <bool PRE>
 __global__ __launch_bounds__(kBlock) void k_prox(SellView At, const float* __restrict__ r, float* __restrict__ x,
                                                  float* __restrict__ y, float tau, float thr, float beta,
                                                  const int* __restrict__ kdev, const float* __restrict__ pinv,
-                                                 const float* __restrict__ tw) {
+                                                 const float* __restrict__ tw, const double* __restrict__ anc) {
   const int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   const int64_t sl = q >> At.cshift;
   const int lane = static_cast<int>(q & (At.C - 1));
@@ -161,9 +165,9 @@ __global__ __launch_bounds__(kBlock) void k_prox(SellView At, const float* __res
     beta = static_cast<float>((static_cast<double>(k) - 1.0) / (static_cast<double>(k) + 2.0));
   }
   const float pi = PRE ? pinv[row] : 1.0f;
-  const float z = y[row] - (tau * pi) * g;
+  const float sg = (tau * pi) * g;
   const float t = thr * (tw ? tw[row] : pi);
-  const float xn = copysignf(fmaxf(fabsf(z) - t, 0.0f), z);
+  const float xn = anc ? prox_anchored(anc[row], y[row], sg, t) : prox_plain(y[row], sg, t);
   const float xo = x[row];
   x[row] = xn;
   y[row] = xn + beta * (xn - xo);
@@ -321,7 +325,8 @@ template <int G, bool PRE>
 __global__ __launch_bounds__(kBlock) void k_prox_csr(CsrView At, const float* __restrict__ r,
                                                      float* __restrict__ x, float* __restrict__ y, float tau,
                                                      float thr, float beta, const int* __restrict__ kdev,
-                                                     const float* __restrict__ pinv, const float* __restrict__ tw) {
+                                                     const float* __restrict__ pinv, const float* __restrict__ tw,
+                                                     const double* __restrict__ anc) {
   const int64_t row = static_cast<int64_t>(blockIdx.x) * (kBlock / G) + threadIdx.x / G;
   const int gl = threadIdx.x % G;
   const float g = group_dot<G>(At, row, gl, r);
@@ -331,9 +336,9 @@ __global__ __launch_bounds__(kBlock) void k_prox_csr(CsrView At, const float* __
     beta = static_cast<float>((static_cast<double>(k) - 1.0) / (static_cast<double>(k) + 2.0));
   }
   const float pi = PRE ? pinv[row] : 1.0f;
-  const float z = y[row] - (tau * pi) * g;
+  const float sg = (tau * pi) * g;
   const float t = thr * (tw ? tw[row] : pi);
-  const float xn = copysignf(fmaxf(fabsf(z) - t, 0.0f), z);
+  const float xn = anc ? prox_anchored(anc[row], y[row], sg, t) : prox_plain(y[row], sg, t);
   const float xo = x[row];
   x[row] = xn;
   y[row] = xn + beta * (xn - xo);
@@ -347,13 +352,14 @@ void launch_res_csr(const CsrView& A, const float* y, const float* b, float* r, 
 
 template <int G>
 void launch_prox_csr(const CsrView& At, const float* r, float* x, float* y, float tau, float thr, float beta,
-                     const int* kdev, const float* pinv, const float* tw, hipStream_t s) {
+                     const int* kdev, const float* pinv, const float* tw, const double* anc, hipStream_t s) {
   const dim3 grid(static_cast<unsigned>((At.nrows + kBlock / G - 1) / (kBlock / G)));
   if (pinv)
-    hipLaunchKernelGGL((k_prox_csr<G, true>), grid, dim3(kBlock), 0, s, At, r, x, y, tau, thr, beta, kdev, pinv, tw);
+    hipLaunchKernelGGL((k_prox_csr<G, true>), grid, dim3(kBlock), 0, s, At, r, x, y, tau, thr, beta, kdev, pinv, tw,
+                       anc);
   else
     hipLaunchKernelGGL((k_prox_csr<G, false>), grid, dim3(kBlock), 0, s, At, r, x, y, tau, thr, beta, kdev, pinv,
-                       tw);
+                       tw, anc);
 }
 
 }  // namespace
@@ -389,22 +395,22 @@ void launch_res(int G, const Sell& sell, const Csr32& csr, const float* y, const
 }
 
 void launch_prox(int G, const Sell& sell, const Csr32& csr, const float* r, float* x, float* y, float tau, float thr,
-                 float beta, const int* kdev, const float* pinv, const float* tw, hipStream_t s) {
+                 float beta, const int* kdev, const float* pinv, const float* tw, const double* anc, hipStream_t s) {
   switch (G) {
-    case 2: launch_prox_csr<2>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, tw, s); return;
-    case 4: launch_prox_csr<4>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, tw, s); return;
-    case 8: launch_prox_csr<8>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, tw, s); return;
-    case 16: launch_prox_csr<16>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, tw, s); return;
-    case 32: launch_prox_csr<32>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, tw, s); return;
-    case 64: launch_prox_csr<64>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, tw, s); return;
+    case 2: launch_prox_csr<2>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, tw, anc, s); return;
+    case 4: launch_prox_csr<4>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, tw, anc, s); return;
+    case 8: launch_prox_csr<8>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, tw, anc, s); return;
+    case 16: launch_prox_csr<16>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, tw, anc, s); return;
+    case 32: launch_prox_csr<32>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, tw, anc, s); return;
+    case 64: launch_prox_csr<64>(cview(csr), r, x, y, tau, thr, beta, kdev, pinv, tw, anc, s); return;
     default: {
       const SellView At = view(sell);
       if (pinv)
         hipLaunchKernelGGL(k_prox<true>, slot_grid(At), dim3(kBlock), 0, s, At, r, x, y, tau, thr, beta,
-                           kdev, pinv, tw);
+                           kdev, pinv, tw, anc);
       else
         hipLaunchKernelGGL(k_prox<false>, slot_grid(At), dim3(kBlock), 0, s, At, r, x, y, tau, thr,
-                           beta, kdev, pinv, tw);
+                           beta, kdev, pinv, tw, anc);
     }
   }
 }
@@ -416,7 +422,8 @@ namespace {
 // ---------------------------------------------------------------------------
 // With l1 weights w (null = uniform): the l1 sum is sum_i w_i |x_i| and the
 // dual scaling uses max_i |g_i| / w_i.
-__global__ __launch_bounds__(kBlock) void k_obj_fwd(SellView A, const float* __restrict__ x, const float* __restrict__ b,
+template <typename X>
+__global__ __launch_bounds__(kBlock) void k_obj_fwd(SellView A, const X* __restrict__ x, const float* __restrict__ b,
                                                     const float* __restrict__ w, double* __restrict__ r64,
                                                     double* __restrict__ partial, int64_t nblocks) {
   const int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
@@ -613,8 +620,8 @@ __device__ __forceinline__ int64_t csr_tiles(const CsrView& A) {
   return (A.nrows + kBlock / G - 1) / (kBlock / G);
 }
 
-template <int G>
-__global__ __launch_bounds__(kBlock) void k_obj_fwd_csr(CsrView A, const float* __restrict__ x,
+template <int G, typename X>
+__global__ __launch_bounds__(kBlock) void k_obj_fwd_csr(CsrView A, const X* __restrict__ x,
                                                         const float* __restrict__ b, const float* __restrict__ w,
                                                         double* __restrict__ r64, double* __restrict__ partial,
                                                         int64_t nblocks) {
@@ -707,6 +714,48 @@ int64_t csr_check_blocks(const wdb_theta* th, int G) {
 
 __global__ void k_set_int(int* p, int v) { *p = v; }
 
+// Anchored iterate (x = a + d, a float64, d float32; see prox.hpp).
+// Start: a = 0 and c = x0, so the displacement iteration is the plain one.
+__global__ __launch_bounds__(kBlock) void k_anchor_init(double* __restrict__ a, float* __restrict__ c,
+                                                        const float* __restrict__ x0, int64_t N) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= N) return;
+  a[i] = 0.0;
+  c[i] = x0[i];
+}
+
+// Moves the displacement into the anchor: a += d, y -= d, d = 0 (x and the
+// extrapolated point y keep their values as sums).
+__global__ __launch_bounds__(kBlock) void k_reanchor(double* __restrict__ a, float* __restrict__ d,
+                                                     float* __restrict__ y, int64_t N) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= N) return;
+  const float di = d[i];
+  a[i] += static_cast<double>(di);
+  y[i] -= di;
+  d[i] = 0.0f;
+}
+
+// Right-hand side of the displacement iteration after a check on the anchor:
+// r64 = Theta_K a - x0 (float64), so r = Theta_K d - c with c = -r64.
+__global__ __launch_bounds__(kBlock) void k_anchor_rhs(const double* __restrict__ r64, float* __restrict__ c,
+                                                       int64_t N) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < N) c[i] = static_cast<float>(-r64[i]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_widen(const float* __restrict__ x, double* __restrict__ x64, int64_t N) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < N) x64[i] = static_cast<double>(x[i]);
+}
+
+// x = a rounded to float32 (the displacement is zero after a re-anchor).
+__global__ __launch_bounds__(kBlock) void k_anchor_out(const double* __restrict__ a, float* __restrict__ x,
+                                                       int64_t N) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < N) x[i] = static_cast<float>(a[i]);
+}
+
 uint64_t splitmix64(uint64_t& state) {
   uint64_t z = (state += 0x9e3779b97f4a7c15ull);
   z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
@@ -739,6 +788,9 @@ void ensure_workspace(wdb_theta* th) {
     WDB_HIP(hipMalloc(reinterpret_cast<void**>(&th->ws_img), N * sizeof(float)));
     WDB_HIP(hipMalloc(reinterpret_cast<void**>(&th->ws_img2), N * sizeof(float)));
     WDB_HIP(hipMalloc(reinterpret_cast<void**>(&th->ws_r64), N * sizeof(double)));
+    WDB_HIP(hipMalloc(reinterpret_cast<void**>(&th->ws_a64), N * sizeof(double)));
+    WDB_HIP(hipMalloc(reinterpret_cast<void**>(&th->ws_c), N * sizeof(float)));
+    WDB_HIP(hipMemset(th->ws_a64, 0, N * sizeof(double)));
     WDB_HIP(hipMalloc(reinterpret_cast<void**>(&th->ws_v64), 3 * N * sizeof(double)));
     WDB_HIP(hipMalloc(reinterpret_cast<void**>(&th->ws_partial), 4 * th->ws_nblocks * sizeof(double)));
     WDB_HIP(hipMalloc(reinterpret_cast<void**>(&th->ws_scalar), 16 * sizeof(double)));
@@ -823,13 +875,238 @@ double power_iteration(wdb_theta* th, const double* start_host, const double* di
 
 namespace {
 
+// ---------------------------------------------------------------------------
+// Lanczos for lambda_max of M = D Theta_K^T Theta_K D (float64, full
+// reorthogonalisation), the largest Ritz value of the tridiagonal projection.
+// ---------------------------------------------------------------------------
+constexpr int kDotChunk = 8192;  // elements per block of the basis dot products
+
+// partial[i * nchunk + c] = sum over chunk c of V_i . u, for basis vectors i < m.
+__global__ __launch_bounds__(kBlock) void k_basis_dots(const double* __restrict__ V, int64_t N,
+                                                       const double* __restrict__ u, double* __restrict__ partial,
+                                                       int64_t nchunk) {
+  const int i = blockIdx.y;
+  const double* __restrict__ v = V + static_cast<int64_t>(i) * N;
+  const int64_t beg = static_cast<int64_t>(blockIdx.x) * kDotChunk;
+  const int64_t end = min(beg + kDotChunk, N);
+  double acc = 0.0;
+  for (int64_t k = beg + threadIdx.x; k < end; k += kBlock) acc = fma(v[k], u[k], acc);
+  double vv[1] = {acc};
+  __shared__ double sh[kWaves];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  for (int off = kWave / 2; off > 0; off >>= 1) vv[0] += __shfl_xor(vv[0], off);
+  if (lane == 0) sh[wid] = vv[0];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = sh[0];
+    for (int w = 1; w < kWaves; ++w) t += sh[w];
+    partial[static_cast<int64_t>(i) * nchunk + blockIdx.x] = t;
+  }
+}
+
+// h[i] = sum_c partial[i * nchunk + c], one block per basis vector (fixed order).
+__global__ __launch_bounds__(kBlock) void k_basis_dots_fin(const double* __restrict__ partial, int64_t nchunk,
+                                                           double* __restrict__ h) {
+  __shared__ double sh[kBlock];
+  double acc = 0.0;
+  for (int64_t c = threadIdx.x; c < nchunk; c += kBlock) acc += partial[static_cast<int64_t>(blockIdx.x) * nchunk + c];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) h[blockIdx.x] = sh[0];
+}
+
+// u -= sum_{i < m} h[i] V_i, and the block partials of ||u||^2 after the update.
+__global__ __launch_bounds__(kBlock) void k_basis_orth(const double* __restrict__ V, int64_t N, int m,
+                                                       const double* __restrict__ h, double* __restrict__ u,
+                                                       double* __restrict__ partial, int64_t nblocks) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  double v[1] = {0.0};
+  if (k < N) {
+    double acc = u[k];
+    for (int i = 0; i < m; ++i) acc = fma(-h[i], V[static_cast<int64_t>(i) * N + k], acc);
+    u[k] = acc;
+    v[0] = acc * acc;
+  }
+  block_partials<1, 0u>(v, partial, nblocks);
+}
+
+// dst = src * scal[0]; vd = d .* dst (or dst; vd may alias src).
+__global__ __launch_bounds__(kBlock) void k_basis_next(const double* src, const double* __restrict__ scal,
+                                                       double* __restrict__ dst, const double* __restrict__ d,
+                                                       double* vd, int64_t N) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (k >= N) return;
+  const double v = src[k] * scal[0];
+  dst[k] = v;
+  vd[k] = d ? v * d[k] : v;
+}
+
+// out = sum_{i < m} s[i] V_i (the Ritz vector of the restart).
+__global__ __launch_bounds__(kBlock) void k_ritz_vector(const double* __restrict__ V, int64_t N, int m,
+                                                        const double* __restrict__ sv, double* __restrict__ out) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (k >= N) return;
+  double acc = 0.0;
+  for (int i = 0; i < m; ++i) acc = fma(sv[i], V[static_cast<int64_t>(i) * N + k], acc);
+  out[k] = acc;
+}
+
+// Block partials of ||u||^2.
+__global__ __launch_bounds__(kBlock) void k_sq_partials(const double* __restrict__ u, int64_t N,
+                                                        double* __restrict__ partial, int64_t nblocks) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  double v[1] = {k < N ? u[k] * u[k] : 0.0};
+  block_partials<1, 0u>(v, partial, nblocks);
+}
+
+// scal[0] = 1 / sqrt(sum of partials) (0 for a zero vector), scal[1] = the norm.
+__global__ __launch_bounds__(kBlock) void k_inv_norm(const double* __restrict__ partial, int64_t nblocks,
+                                                     double* __restrict__ scal) {
+  __shared__ double sh[kBlock];
+  double a = 0.0;
+  for (int64_t i = threadIdx.x; i < nblocks; i += kBlock) a += partial[i];
+  sh[threadIdx.x] = a;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double nrm = sqrt(sh[0]);
+    scal[0] = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    scal[1] = nrm;
+  }
+}
+
+}  // namespace
+
+LanczosResult lanczos_max(wdb_theta* th, const double* start_host, const double* dinv_sqrt, double tol, int max_steps,
+                          hipStream_t s, int cycle) {
+  ensure_workspace(th);
+  const int64_t N = th->N;
+  WDB_REQUIRE(max_steps >= 1, WDB_ERR_ARG, "max_steps must be >= 1");
+  WDB_REQUIRE(tol >= 0 && std::isfinite(tol), WDB_ERR_ARG, "tol must be finite and >= 0");
+  std::vector<double> v(N);
+  if (start_host) {
+    for (int64_t i = 0; i < N; ++i) {
+      WDB_REQUIRE(std::isfinite(start_host[i]), WDB_ERR_NONFINITE, "non-finite start vector");
+      v[i] = start_host[i];
+    }
+  } else {
+    uint64_t st = 0x5eedull;
+    for (int64_t i = 0; i < N; ++i) v[i] = static_cast<double>(splitmix64(st) >> 11) * 0x1.0p-52 - 1.0;
+  }
+  double nrm = 0.0;
+  for (double x : v) nrm += x * x;
+  nrm = std::sqrt(nrm);
+  WDB_REQUIRE(nrm > 0.0, WDB_ERR_ARG, "Lanczos start vector is zero");
+  for (double& x : v) x /= nrm;
+  // a cycle builds at most k steps from its start vector, then restarts from
+  // the top Ritz vector: the basis holds k + 1 vectors of N doubles
+  const int k = static_cast<int>(std::min<int64_t>(std::max(cycle, 2), N));
+  DevBuf<double> V(static_cast<size_t>(k + 1) * N);
+  double* vd = th->ws_v64;
+  double* w = vd + N;
+  double* u = w + N;
+  const int64_t nchunk = (N + kDotChunk - 1) / kDotChunk;
+  DevBuf<double> dpart(static_cast<size_t>(k + 1) * nchunk);
+  DevBuf<double> hh(2 * static_cast<size_t>(k + 1));
+  DevBuf<double> sv(static_cast<size_t>(k + 1));
+  const int64_t nbv = vec_grid(N).x;
+  DevBuf<double> npart(nbv);
+  DevBuf<double> scal(2);
+  WDB_HIP(hipMemcpyAsync(V.p, v.data(), N * sizeof(double), hipMemcpyHostToDevice, s));
+  const SellView A = view(th->A), At = view(th->At);
+  const int G = check_group(th);
+  const int64_t nb = G > 0 ? csr_check_blocks(th, G) : partial_blocks(A, At);
+  double* part = th->ws_partial;
+  LanczosResult res{0.0, 0.0, 0, false};
+  double hstep[2], bn[2];
+  while (res.steps < max_steps) {
+    // vd = D v_0 of this cycle
+    WDB_HIP(hipMemcpyAsync(vd, V.p, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (dinv_sqrt) hipLaunchKernelGGL(k_mul, vec_grid(N), dim3(kBlock), 0, s, vd, dinv_sqrt, N);
+    std::vector<double> alpha, beta;
+    TopRitz tr{0.0, 1.0, {}};
+    bool done = false;
+    for (int j = 0; j < k && res.steps < max_steps; ++j) {
+      // u = D A^T A D v_j (vd = D v_j)
+      if (G > 0) {
+        with_group(G, [&](auto g) {
+          constexpr int GG = decltype(g)::value;
+          hipLaunchKernelGGL(k_pi_fwd_csr<GG>, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, cview(th->cA),
+                             vd, w, part, nb);
+          hipLaunchKernelGGL(k_pi_bwd_csr<GG>, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s,
+                             cview(th->cAt), w, dinv_sqrt, u, part + nb, nb);
+        });
+      } else {
+        hipLaunchKernelGGL(k_pi_fwd, slot_grid(A), dim3(kBlock), 0, s, A, vd, w, part, nb);
+        hipLaunchKernelGGL(k_pi_bwd, slot_grid(At), dim3(kBlock), 0, s, At, w, dinv_sqrt, u, part + nb, nb);
+      }
+      // two passes of classical Gram-Schmidt against v_0..v_j; the
+      // coefficients of v_j add up to alpha_j
+      const int m = j + 1;
+      for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL(k_basis_dots, dim3(static_cast<unsigned>(nchunk), static_cast<unsigned>(m)), dim3(kBlock),
+                           0, s, V.p, N, u, dpart.p, nchunk);
+        hipLaunchKernelGGL(k_basis_dots_fin, dim3(static_cast<unsigned>(m)), dim3(kBlock), 0, s, dpart.p, nchunk,
+                           hh.p + pass * (k + 1));
+        hipLaunchKernelGGL(k_basis_orth, vec_grid(N), dim3(kBlock), 0, s, V.p, N, m, hh.p + pass * (k + 1), u,
+                           npart.p, nbv);
+      }
+      hipLaunchKernelGGL(k_inv_norm, dim3(1), dim3(kBlock), 0, s, npart.p, nbv, scal.p);
+      WDB_HIP(hipGetLastError());
+      WDB_HIP(hipMemcpyAsync(&hstep[0], hh.p + j, sizeof(double), hipMemcpyDeviceToHost, s));
+      WDB_HIP(hipMemcpyAsync(&hstep[1], hh.p + (k + 1) + j, sizeof(double), hipMemcpyDeviceToHost, s));
+      WDB_HIP(hipMemcpyAsync(bn, scal.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+      WDB_HIP(hipStreamSynchronize(s));
+      ++res.steps;
+      alpha.push_back(hstep[0] + hstep[1]);
+      WDB_REQUIRE(std::isfinite(alpha.back()) && std::isfinite(bn[1]), WDB_ERR_DIVERGED,
+                  "Lanczos produced a non-finite value");
+      const double bj = bn[1];
+      tr = top_ritz(alpha, beta);
+      res.theta = tr.theta;
+      res.resid = bj * std::fabs(tr.last);
+      if (res.resid <= tol * std::fabs(tr.theta) || bj == 0.0) {
+        res.converged = true;
+        done = true;
+        break;
+      }
+      beta.push_back(bj);
+      if (j + 1 < k)   // v_{j+1} = u / beta_j, vd = D v_{j+1}
+        hipLaunchKernelGGL(k_basis_next, vec_grid(N), dim3(kBlock), 0, s, u, scal.p,
+                           V.p + static_cast<int64_t>(j + 1) * N, dinv_sqrt, vd, N);
+    }
+    if (done || res.steps >= max_steps) break;
+    // restart from the top Ritz vector V s (normalised)
+    const int m = static_cast<int>(tr.vec.size());
+    WDB_HIP(hipMemcpyAsync(sv.p, tr.vec.data(), m * sizeof(double), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_ritz_vector, vec_grid(N), dim3(kBlock), 0, s, V.p, N, m, sv.p, u);
+    hipLaunchKernelGGL(k_sq_partials, vec_grid(N), dim3(kBlock), 0, s, u, N, npart.p, nbv);
+    hipLaunchKernelGGL(k_inv_norm, dim3(1), dim3(kBlock), 0, s, npart.p, nbv, scal.p);
+    hipLaunchKernelGGL(k_basis_next, vec_grid(N), dim3(kBlock), 0, s, u, scal.p, V.p, static_cast<const double*>(nullptr),
+                       u, N);
+    WDB_HIP(hipGetLastError());
+  }
+  WDB_HIP(hipStreamSynchronize(s));
+  return res;
+}
+
+namespace {
+
 struct Check {
   double E, rel_gap;
 };
 
 // Enqueue the float64 stopping-test products and their reduction into four
 // device doubles at `dst`: ||r||^2, <r, x0>, sum w|x|, max |g_i| / w_i.
-void enqueue_check(wdb_theta* th, const float* x, const float* x0, double* dst, hipStream_t s) {
+template <typename X>
+void enqueue_check(wdb_theta* th, const X* x, const float* x0, double* dst, hipStream_t s) {
   const SellView A = view(th->A), At = view(th->At);
   const bool tiled = kernel_group(th) == kTiled;
   const int G = check_group(th);
@@ -841,13 +1118,13 @@ void enqueue_check(wdb_theta* th, const float* x, const float* x0, double* dst, 
   } else if (G > 0) {
     with_group(G, [&](auto g) {
       constexpr int GG = decltype(g)::value;
-      hipLaunchKernelGGL(k_obj_fwd_csr<GG>, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, cview(th->cA), x,
-                         x0, th->l1w, th->ws_r64, part, nb);
+      hipLaunchKernelGGL((k_obj_fwd_csr<GG, X>), dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, cview(th->cA),
+                         x, x0, th->l1w, th->ws_r64, part, nb);
       hipLaunchKernelGGL(k_obj_bwd_csr<GG>, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, cview(th->cAt),
                          th->ws_r64, th->l1w, part + 3 * nb, nb);
     });
   } else {
-    hipLaunchKernelGGL(k_obj_fwd, slot_grid(A), dim3(kBlock), 0, s, A, x, x0, th->l1w, th->ws_r64, part, nb);
+    hipLaunchKernelGGL(k_obj_fwd<X>, slot_grid(A), dim3(kBlock), 0, s, A, x, x0, th->l1w, th->ws_r64, part, nb);
     hipLaunchKernelGGL(k_obj_bwd, slot_grid(At), dim3(kBlock), 0, s, At, th->ws_r64, th->l1w, part + 3 * nb, nb);
   }
   hipLaunchKernelGGL(k_reduce4, dim3(1), dim3(kReduceThreads), 0, s, part, nb, 0x8u, dst);
@@ -864,7 +1141,8 @@ Check check_from(const double* q, double lambda) {
   return Check{E, E > 0 ? gap / E : 0.0};
 }
 
-Check objective_check(wdb_theta* th, const float* x, const float* x0, double lambda, hipStream_t s) {
+template <typename X>
+Check objective_check(wdb_theta* th, const X* x, const float* x0, double lambda, hipStream_t s) {
   enqueue_check(th, x, x0, th->ws_scalar, s);
   WDB_HIP(hipMemcpyAsync(th->host_scalar, th->ws_scalar, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
   WDB_HIP(hipStreamSynchronize(s));
@@ -873,7 +1151,10 @@ Check objective_check(wdb_theta* th, const float* x, const float* x0, double lam
 
 // One iteration of Alg. 1 (Alg. 2 with `pre`); with `ista` the proximal kernel
 // gets no counter and extrapolates with beta = 0 (plain proximal gradient).
-void launch_iteration(wdb_theta* th, float* x, bool pre, bool ista, float tau, float thr, hipStream_t s) {
+// With `anchored` (float32 values only) x and y hold displacements from the
+// float64 anchor ws_a64 and the residual subtracts c = x0 - Theta_K a.
+void launch_iteration(wdb_theta* th, float* x, bool pre, bool ista, float tau, float thr, hipStream_t s,
+                      bool anchored = false) {
   const int* kp = ista ? nullptr : th->ws_k;
   if (th->valtype != WDB_VAL_F32 && th->pA.word && packed_group(th) == kTiled) {
     launch_res_tiled16(th, th->ws_y, th->ws_x0, th->ws_r, th->ws_k, 1, s);
@@ -891,21 +1172,23 @@ void launch_iteration(wdb_theta* th, float* x, bool pre, bool ista, float tau, f
   if (th->valtype == WDB_VAL_BF16) return launch_iteration_q<WDB_VAL_BF16>(th, x, pre, kp, tau, thr, s);
   if (th->valtype == WDB_VAL_F16) return launch_iteration_q<WDB_VAL_F16>(th, x, pre, kp, tau, thr, s);
   const int G = kernel_group(th);
+  const float* b = anchored ? th->ws_c : th->ws_x0;
+  const double* anc = anchored ? th->ws_a64 : nullptr;
   if (G == kTiled) {
-    launch_res_tiled(th, false, th->ws_y, th->ws_x0, th->ws_r, th->ws_k, s);
+    launch_res_tiled(th, false, th->ws_y, b, th->ws_r, th->ws_k, s);
     launch_prox_tiled(th, th->ws_r, x, th->ws_y, tau, thr, 0.0f, kp, pre ? th->pinv : nullptr,
-                      threshold_weights(th, pre), s);
+                      threshold_weights(th, pre), anc, s);
     return;
   }
   if (G == kStencil) {
-    launch_res_stencil(th, false, th->ws_y, th->ws_x0, th->ws_r, th->ws_k, s);
+    launch_res_stencil(th, false, th->ws_y, b, th->ws_r, th->ws_k, s);
     launch_prox_stencil(th, th->ws_r, x, th->ws_y, tau, thr, 0.0f, kp, pre ? th->pinv : nullptr,
-                        threshold_weights(th, pre), s);
+                        threshold_weights(th, pre), anc, s);
     return;
   }
-  launch_res(G, th->A, th->cA, th->ws_y, th->ws_x0, th->ws_r, th->ws_k, s);
+  launch_res(G, th->A, th->cA, th->ws_y, b, th->ws_r, th->ws_k, s);
   launch_prox(G, th->At, th->cAt, th->ws_r, x, th->ws_y, tau, thr, 0.0f, kp, pre ? th->pinv : nullptr,
-              threshold_weights(th, pre), s);
+              threshold_weights(th, pre), anc, s);
 }
 
 void ensure_lipschitz(wdb_theta* th, hipStream_t s) {
@@ -942,6 +1225,27 @@ wdb_status solve_impl(wdb_theta* th, const float* x0_src, bool from_image, float
     WDB_HIP(hipMemcpyAsync(th->ws_x0, x0_src, N * sizeof(float), hipMemcpyDeviceToDevice, s));
   }
   hipLaunchKernelGGL(k_copy_or_zero, vec_grid(N), dim3(kBlock), 0, s, opts->x_init, x_out, th->ws_y, N);
+  // Float32 values keep the iterate anchored (float64 anchor + float32
+  // displacement, re-centred at every check) unless the caller asks for the
+  // plain float32 iterate; the 16-bit forms always iterate plainly.
+  const bool anchored = th->valtype == WDB_VAL_F32 && opts->plain_iterate == 0;
+  if (anchored) hipLaunchKernelGGL(k_anchor_init, vec_grid(N), dim3(kBlock), 0, s, th->ws_a64, th->ws_c, th->ws_x0, N);
+  // A check: with the anchored iterate the displacement first moves into the
+  // anchor, the float64 products run on the anchor, and their residual gives
+  // the next right-hand side.
+  auto enqueue_point = [&](double* dst) {
+    if (!anchored) return enqueue_check(th, static_cast<const float*>(x_out), th->ws_x0, dst, s);
+    hipLaunchKernelGGL(k_reanchor, vec_grid(N), dim3(kBlock), 0, s, th->ws_a64, x_out, th->ws_y, N);
+    enqueue_check(th, static_cast<const double*>(th->ws_a64), th->ws_x0, dst, s);
+    hipLaunchKernelGGL(k_anchor_rhs, vec_grid(N), dim3(kBlock), 0, s, th->ws_r64, th->ws_c, N);
+    WDB_HIP(hipGetLastError());
+  };
+  auto check_point = [&]() {
+    enqueue_point(th->ws_scalar);
+    WDB_HIP(hipMemcpyAsync(th->host_scalar, th->ws_scalar, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    WDB_HIP(hipStreamSynchronize(s));
+    return check_from(th->host_scalar, lambda);
+  };
   const int k0 = opts->k0 > 0 ? opts->k0 : 1;
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, th->ws_k, k0 - 1);
   WDB_HIP(hipGetLastError());
@@ -957,12 +1261,13 @@ wdb_status solve_impl(wdb_theta* th, const float* x0_src, bool from_image, float
     if (use_graph && total >= c) {
       const int ista = opts->ista != 0 ? 1 : 0;
       if (!(th->g_exec && th->g_x == x_out && th->g_c == c && th->g_pre == (pre ? 1 : 0) && th->g_ista == ista &&
-            th->g_tau == tau_f && th->g_thr == thr_f)) {
+            th->g_anchor == (anchored ? 1 : 0) && th->g_tau == tau_f && th->g_thr == thr_f)) {
         drop_graph(th);
         if (!th->capture_stream) WDB_HIP(hipStreamCreateWithFlags(&th->capture_stream, hipStreamNonBlocking));
         WDB_HIP(hipStreamBeginCapture(th->capture_stream, hipStreamCaptureModeThreadLocal));
         try {
-          for (int i = 0; i < c; ++i) launch_iteration(th, x_out, pre, ista != 0, tau_f, thr_f, th->capture_stream);
+          for (int i = 0; i < c; ++i)
+            launch_iteration(th, x_out, pre, ista != 0, tau_f, thr_f, th->capture_stream, anchored);
         } catch (...) {  // end the capture so the stream stays usable
           hipGraph_t g = nullptr;
           (void)hipStreamEndCapture(th->capture_stream, &g);
@@ -977,6 +1282,7 @@ wdb_status solve_impl(wdb_theta* th, const float* x0_src, bool from_image, float
         th->g_c = c;
         th->g_pre = pre ? 1 : 0;
         th->g_ista = ista;
+        th->g_anchor = anchored ? 1 : 0;
         th->g_tau = tau_f;
         th->g_thr = thr_f;
       }
@@ -1003,16 +1309,16 @@ wdb_status solve_impl(wdb_theta* th, const float* x0_src, bool from_image, float
       if (exec && step == c) {
         WDB_HIP(hipGraphLaunch(exec, s));
       } else {
-        for (int i = 0; i < step; ++i) launch_iteration(th, x_out, pre, opts->ista != 0, tau_f, thr_f, s);
+        for (int i = 0; i < step; ++i) launch_iteration(th, x_out, pre, opts->ista != 0, tau_f, thr_f, s, anchored);
         WDB_HIP(hipGetLastError());
       }
       done += step;
       const bool at_check = (c > 0 && done % c == 0) || done == total;
       if (at_check && !stop_test) {
-        enqueue_check(th, x_out, th->ws_x0, th->ws_checks + 4 * at_iter.size(), s);
+        enqueue_point(th->ws_checks + 4 * at_iter.size());
         at_iter.push_back(done);
       } else if (at_check) {
-        last = objective_check(th, x_out, th->ws_x0, lambda, s);
+        last = check_point();
         ++checks;
         if (opts->trace && checks <= opts->trace_cap) {
           opts->trace[3 * (checks - 1) + 0] = static_cast<double>(k0 - 1 + done);
@@ -1045,9 +1351,17 @@ wdb_status solve_impl(wdb_theta* th, const float* x0_src, bool from_image, float
       }
     }
     if (total == 0) {
-      last = objective_check(th, x_out, th->ws_x0, lambda, s);
+      last = check_point();
       ++checks;
     }
+    if (anchored) {  // every solve ends on a check, which leaves a zero displacement
+      hipLaunchKernelGGL(k_anchor_out, vec_grid(N), dim3(kBlock), 0, s, th->ws_a64, x_out, N);
+      if (opts->x64_out)
+        WDB_HIP(hipMemcpyAsync(opts->x64_out, th->ws_a64, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    } else if (opts->x64_out) {
+      hipLaunchKernelGGL(k_widen, vec_grid(N), dim3(kBlock), 0, s, x_out, opts->x64_out, N);
+    }
+    WDB_HIP(hipGetLastError());
   } catch (...) {
     (void)hipStreamSynchronize(s);  // no replay in flight when the graph goes
     drop_graph(th);                 // a failed capture or replay leaves no graph behind
@@ -1172,13 +1486,13 @@ wdb_status wdb_prox_step(wdb_theta* th, const float* r, float* x, float* y, floa
   const float thr = tau * lambda;
   if (wdb::kernel_group(th) == wdb::kTiled)
     wdb::launch_prox_tiled(th, r, x, y, tau, thr, beta, nullptr, use_precond ? th->pinv : nullptr,
-                           wdb::threshold_weights(th, use_precond != 0), s);
+                           wdb::threshold_weights(th, use_precond != 0), nullptr, s);
   else if (wdb::kernel_group(th) == wdb::kStencil)
     wdb::launch_prox_stencil(th, r, x, y, tau, thr, beta, nullptr, use_precond ? th->pinv : nullptr,
-                             wdb::threshold_weights(th, use_precond != 0), s);
+                             wdb::threshold_weights(th, use_precond != 0), nullptr, s);
   else
     wdb::launch_prox(wdb::kernel_group(th), th->At, th->cAt, r, x, y, tau, thr, beta, nullptr,
-                     use_precond ? th->pinv : nullptr, wdb::threshold_weights(th, use_precond != 0), s);
+                     use_precond ? th->pinv : nullptr, wdb::threshold_weights(th, use_precond != 0), nullptr, s);
   WDB_HIP(hipGetLastError());
   WDB_API_END
 }

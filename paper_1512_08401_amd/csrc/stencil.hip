@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "prox.hpp"
 
 namespace wdb {
 
@@ -145,7 +146,8 @@ template <int G, bool PRE>
 __global__ __launch_bounds__(kBlock) void k_prox_st(StencilView S, const float* __restrict__ r,
                                                     float* __restrict__ x, float* __restrict__ y, float tau,
                                                     float thr, float beta, const int* __restrict__ kdev,
-                                                    const float* __restrict__ pinv, const float* __restrict__ tw) {
+                                                    const float* __restrict__ pinv, const float* __restrict__ tw,
+                                                    const double* __restrict__ anc) {
   const int64_t row = static_cast<int64_t>(blockIdx.x) * (kBlock / G) + threadIdx.x / G;
   const int gl = threadIdx.x % G;
   const float g = stencil_dot<G>(S, row, gl, r);
@@ -155,9 +157,9 @@ __global__ __launch_bounds__(kBlock) void k_prox_st(StencilView S, const float* 
     beta = static_cast<float>((static_cast<double>(k) - 1.0) / (static_cast<double>(k) + 2.0));
   }
   const float pi = PRE ? pinv[row] : 1.0f;
-  const float z = y[row] - (tau * pi) * g;
+  const float sg = (tau * pi) * g;
   const float t = thr * (tw ? tw[row] : pi);
-  const float xn = copysignf(fmaxf(fabsf(z) - t, 0.0f), z);
+  const float xn = anc ? prox_anchored(anc[row], y[row], sg, t) : prox_plain(y[row], sg, t);
   const float xo = x[row];
   x[row] = xn;
   y[row] = xn + beta * (xn - xo);
@@ -324,14 +326,16 @@ void launch_res_stencil(const wdb_theta* th, bool transpose, const float* y, con
 }
 
 void launch_prox_stencil(const wdb_theta* th, const float* r, float* x, float* y, float tau, float thr, float beta,
-                         const int* kdev, const float* pinv, const float* tw, hipStream_t s) {
+                         const int* kdev, const float* pinv, const float* tw, const double* anc, hipStream_t s) {
   const StencilView S = sview(th->stT, th);
   constexpr int G = 4;
   const dim3 grid(static_cast<unsigned>((S.nrows + kBlock / G - 1) / (kBlock / G)));
   if (pinv)
-    hipLaunchKernelGGL((k_prox_st<G, true>), grid, dim3(kBlock), 0, s, S, r, x, y, tau, thr, beta, kdev, pinv, tw);
+    hipLaunchKernelGGL((k_prox_st<G, true>), grid, dim3(kBlock), 0, s, S, r, x, y, tau, thr, beta, kdev, pinv, tw,
+                       anc);
   else
-    hipLaunchKernelGGL((k_prox_st<G, false>), grid, dim3(kBlock), 0, s, S, r, x, y, tau, thr, beta, kdev, pinv, tw);
+    hipLaunchKernelGGL((k_prox_st<G, false>), grid, dim3(kBlock), 0, s, S, r, x, y, tau, thr, beta, kdev, pinv, tw,
+                       anc);
 }
 
 }  // namespace wdb

@@ -39,6 +39,7 @@
 
 #include "codes.hpp"
 #include "common.hpp"
+#include "prox.hpp"
 
 namespace wdb {
 
@@ -255,8 +256,8 @@ __device__ __forceinline__ void wave0_partial(double v, int lane, double* __rest
 
 // Stopping test, forward half: r64 = Theta_K x - x0 in float64 and per-tile
 // partials of ||r||^2, <r, x0> and sum_i w_i |x_i|.
-template <int W, int U>
-__global__ __launch_bounds__(64 * W) void k_obj_fwd_tl(TiledView T, Geo g, const float* __restrict__ x,
+template <int W, int U, typename X>
+__global__ __launch_bounds__(64 * W) void k_obj_fwd_tl(TiledView T, Geo g, const X* __restrict__ x,
                                                        const float* __restrict__ b, const float* __restrict__ w,
                                                        double* __restrict__ r64, double* __restrict__ partial,
                                                        int64_t nblocks) {
@@ -311,21 +312,25 @@ __global__ __launch_bounds__(64 * W) void k_res_tl(TiledView T, Geo g, const flo
   if (kdev && blockIdx.x == 0 && threadIdx.x == 0) *kdev += 1;
 }
 
-// Operands of the proximal epilogue, loaded before the product.
+// Operands of the proximal epilogue, loaded before the product (a: the
+// float64 anchor of the coefficient when the iterate is anchored).
 struct ProxIn {
+  double a;
   float y, x, pi, tw, beta;
 };
 
 template <bool PRE>
 __device__ __forceinline__ ProxIn prox_load(int row, bool out, const float* __restrict__ x,
                                             const float* __restrict__ y, const int* __restrict__ kdev, float beta,
-                                            const float* __restrict__ pinv, const float* __restrict__ tw) {
-  ProxIn p{0.f, 0.f, 1.f, 1.f, beta};
+                                            const float* __restrict__ pinv, const float* __restrict__ tw,
+                                            const double* __restrict__ anc) {
+  ProxIn p{0.0, 0.f, 0.f, 1.f, 1.f, beta};
   if (out) {
     p.y = y[row];
     p.x = x[row];
     if (PRE) p.pi = pinv[row];
     p.tw = tw ? tw[row] : p.pi;
+    if (anc) p.a = anc[row];
   }
   if (kdev) {
     const int k = *kdev;
@@ -335,10 +340,10 @@ __device__ __forceinline__ ProxIn prox_load(int row, bool out, const float* __re
 }
 
 __device__ __forceinline__ void prox_store(const ProxIn& p, int row, float gr, float tau, float thr,
-                                           float* __restrict__ x, float* __restrict__ y) {
-  const float z = p.y - (tau * p.pi) * gr;
+                                           float* __restrict__ x, float* __restrict__ y, bool anchored) {
+  const float sg = (tau * p.pi) * gr;
   const float t = thr * p.tw;
-  const float xn = copysignf(fmaxf(fabsf(z) - t, 0.0f), z);
+  const float xn = anchored ? prox_anchored(p.a, p.y, sg, t) : prox_plain(p.y, sg, t);
   x[row] = xn;
   y[row] = xn + p.beta * (xn - p.x);
 }
@@ -347,15 +352,16 @@ template <int W, int U, bool PRE>
 __global__ __launch_bounds__(64 * W) void k_prox_tl(TiledView T, Geo g, const float* __restrict__ r,
                                                     float* __restrict__ x, float* __restrict__ y, float tau,
                                                     float thr, float beta, const int* __restrict__ kdev,
-                                                    const float* __restrict__ pinv, const float* __restrict__ tw) {
+                                                    const float* __restrict__ pinv, const float* __restrict__ tw,
+                                                    const double* __restrict__ anc) {
   const int4 d = T.desc[blockIdx.x];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int row = tile_row(d, lane);
   const bool out = wv == 0 && row >= 0;
-  const ProxIn p = prox_load<PRE>(row, out, x, y, kdev, beta, pinv, tw);
+  const ProxIn p = prox_load<PRE>(row, out, x, y, kdev, beta, pinv, tw, anc);
   const float gr = tile_dot<W, U>(T, g, d, row, lane, wv, r);
-  if (out) prox_store(p, row, gr, tau, thr, x, y);
+  if (out) prox_store(p, row, gr, tau, thr, x, y, anc != nullptr);
 }
 
 // 16-bit values scaled by a power of two u per scale block (row subband for
@@ -390,9 +396,9 @@ __global__ __launch_bounds__(64 * W) void k_prox_tl16(TiledView T, Geo g, const 
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int row = tile_row(d, lane);
   const bool out = wv == 0 && row >= 0;
-  const ProxIn p = prox_load<PRE>(row, out, x, y, kdev, 0.0f, pinv, tw);  // no counter: beta = 0 (ISTA)
+  const ProxIn p = prox_load<PRE>(row, out, x, y, kdev, 0.0f, pinv, tw, nullptr);  // no counter: beta = 0 (ISTA)
   const float gr = tile_dot16<W, U, FMT>(T, g, d, row, lane, wv, rs);
-  if (out) prox_store(p, row, gr, tau, thr, x, y);
+  if (out) prox_store(p, row, gr, tau, thr, x, y, false);
 }
 
 // Wavefronts per tile W and groups in flight per wavefront U.
@@ -763,16 +769,29 @@ int64_t tiled_check_blocks(const wdb_theta* th) {
   return th->tA.ntiles;
 }
 
-void launch_objective_tiled(const wdb_theta* th, const float* x, const float* x0, double* r64, double* part,
-                            int64_t nb, hipStream_t s) {
+namespace {
+template <typename X>
+void objective_tiled(const wdb_theta* th, const X* x, const float* x0, double* r64, double* part, int64_t nb,
+                     hipStream_t s) {
   WDB_REQUIRE(nb == tiled_check_blocks(th), WDB_ERR_ARG, "partial count does not match the tiles");
   const Geo g = geo_of(th);
   with_shape(th->tile_waves, th->tile_unroll, [&](auto Wc, auto Uc) {
     constexpr int W = decltype(Wc)::value, U = decltype(Uc)::value;
     const dim3 grid(static_cast<unsigned>(nb)), block(64 * W);
-    hipLaunchKernelGGL((k_obj_fwd_tl<W, U>), grid, block, 0, s, tview(th->tA), g, x, x0, th->l1w, r64, part, nb);
+    hipLaunchKernelGGL((k_obj_fwd_tl<W, U, X>), grid, block, 0, s, tview(th->tA), g, x, x0, th->l1w, r64, part, nb);
     hipLaunchKernelGGL((k_obj_bwd_tl<W, U>), grid, block, 0, s, tview(th->tAt), g, r64, th->l1w, part + 3 * nb);
   });
+}
+}  // namespace
+
+void launch_objective_tiled(const wdb_theta* th, const float* x, const float* x0, double* r64, double* part,
+                            int64_t nb, hipStream_t s) {
+  objective_tiled(th, x, x0, r64, part, nb, s);
+}
+
+void launch_objective_tiled(const wdb_theta* th, const double* x, const float* x0, double* r64, double* part,
+                            int64_t nb, hipStream_t s) {
+  objective_tiled(th, x, x0, r64, part, nb, s);
 }
 
 void launch_res_tiled(const wdb_theta* th, bool transpose, const float* y, const float* b, float* r, int* kdev,
@@ -788,7 +807,7 @@ void launch_res_tiled(const wdb_theta* th, bool transpose, const float* y, const
 }
 
 void launch_prox_tiled(const wdb_theta* th, const float* r, float* x, float* y, float tau, float thr, float beta,
-                       const int* kdev, const float* pinv, const float* tw, hipStream_t s) {
+                       const int* kdev, const float* pinv, const float* tw, const double* anc, hipStream_t s) {
   const Tiled& T = th->tAt;
   WDB_REQUIRE(T.desc, WDB_ERR_ARG, "tiled storage not built");
   const Geo g = geo_of(th);
@@ -797,10 +816,10 @@ void launch_prox_tiled(const wdb_theta* th, const float* r, float* x, float* y, 
     const dim3 grid(static_cast<unsigned>(T.ntiles)), block(64 * W);
     if (pinv)
       hipLaunchKernelGGL((k_prox_tl<W, U, true>), grid, block, 0, s, tview(T), g, r, x, y, tau, thr, beta, kdev,
-                         pinv, tw);
+                         pinv, tw, anc);
     else
       hipLaunchKernelGGL((k_prox_tl<W, U, false>), grid, block, 0, s, tview(T), g, r, x, y, tau, thr, beta, kdev,
-                         pinv, tw);
+                         pinv, tw, anc);
   });
 }
 

@@ -58,7 +58,8 @@ class SolveOpts(C.Structure):
     _fields_ = [("max_iters", C.c_int32), ("check_every", C.c_int32), ("tol_rel_gap", C.c_double),
                 ("x_init", C.c_void_p), ("k0", C.c_int32), ("use_precond", C.c_int32),
                 ("stream", C.c_void_p), ("trace", C.POINTER(C.c_double)), ("trace_cap", C.c_int32),
-                ("use_graph", C.c_int32), ("target_objective", C.c_double), ("ista", C.c_int32)]
+                ("use_graph", C.c_int32), ("target_objective", C.c_double), ("ista", C.c_int32),
+                ("plain_iterate", C.c_int32), ("x64_out", C.c_void_p)]
 
 
 class ProblemC(C.Structure):
@@ -165,6 +166,18 @@ def _dev(t, numel=None, name="tensor"):
     return C.c_void_p(t.data_ptr())
 
 
+def _dev64(t, numel=None, name="tensor"):
+    """Device pointer of a contiguous float64 ROCm tensor (checked)."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous float64")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return C.c_void_p(t.data_ptr())
+
+
 def _field_struct(field):
     n = int(field.n)
     arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(n * n))
@@ -251,6 +264,11 @@ class Theta:
         _check("wdb_theta_lipschitz", _lib.wdb_theta_lipschitz(self._h, p, tol, max_iters, C.byref(L), C.byref(it)))
         return L.value, it.value
 
+    def lipschitz_info(self, start=None, tol: float = 1e-12, max_iters: int = 20000) -> dict:
+        """L by the power iteration, with whether it met tol before max_iters."""
+        L, it = self.lipschitz(start, tol, max_iters)
+        return {"L": L, "method": "power", "iters": it, "converged": it < max_iters}
+
     def set_precond(self, kind: str, eps: float = 0.0, start=None, tol: float = 1e-12, max_iters: int = 20000):
         p, keep = _f64ptr(start)
         _check("wdb_set_precond", _lib.wdb_set_precond(self._h, PRECOND[kind], eps, p, tol, max_iters))
@@ -323,7 +341,7 @@ class Theta:
         return E.value, g.value
 
     def _solve(self, fn, src, lam, iters, check_every, tol, x_init, k0, precond, use_graph, trace_cap, out,
-               stream, target=0.0, ista=False):
+               stream, target=0.0, ista=False, plain_iterate=False, x64_out=None):
         torch = _torch()
         N = self.N
         x = torch.empty(N, device=src.device, dtype=torch.float32) if out is None else out
@@ -331,7 +349,8 @@ class Theta:
         o = SolveOpts(int(iters), int(check_every), float(tol),
                       None if x_init is None else _dev(x_init, N, "x_init").value, int(k0),
                       1 if precond else 0, _stream(stream).value, trace.ctypes.data_as(_pd), int(trace_cap),
-                      1 if use_graph else 0, float(target), 1 if ista else 0)
+                      1 if use_graph else 0, float(target), 1 if ista else 0, 1 if plain_iterate else 0,
+                      None if x64_out is None else _dev64(x64_out, N, "x64_out").value)
         info = SolveInfo()
         st = getattr(_lib, fn)(self._h, _dev(src, name="input"), float(lam), C.byref(o), _dev(x, N, "x_out"),
                                C.byref(info))
@@ -346,17 +365,20 @@ class Theta:
 
     def solve(self, u, lam: float, iters: int, check_every: int = 20, tol: float = 0.0, x_init=None, k0: int = 1,
               precond: bool = False, use_graph: bool = False, trace_cap: int = 0, out=None, stream=None,
-              target: float = 0.0, ista: bool = False):
-        """FISTA (ISTA with ista=True) from a blurred image u (device n*n float32); returns (x, info)."""
+              target: float = 0.0, ista: bool = False, plain_iterate: bool = False, x64_out=None):
+        """FISTA (ISTA with ista=True) from a blurred image u (device n*n float32); returns (x, info).
+        plain_iterate=True keeps the float32 iterate without its float64 anchor; x64_out (device
+        float64, N) receives the float64 iterate the last check scored."""
         return self._solve("wdb_solve", u, lam, iters, check_every, tol, x_init, k0, precond, use_graph,
-                           trace_cap, out, stream, target, ista)
+                           trace_cap, out, stream, target, ista, plain_iterate, x64_out)
 
     def solve_coeffs(self, x0, lam: float, iters: int, check_every: int = 20, tol: float = 0.0, x_init=None,
                      k0: int = 1, precond: bool = False, use_graph: bool = False, trace_cap: int = 0, out=None,
-                     stream=None, target: float = 0.0, ista: bool = False):
+                     stream=None, target: float = 0.0, ista: bool = False, plain_iterate: bool = False,
+                     x64_out=None):
         """FISTA (ISTA with ista=True) from wavelet-domain data x0 (device N float32); returns (x, info)."""
         return self._solve("wdb_solve_coeffs", x0, lam, iters, check_every, tol, x_init, k0, precond, use_graph,
-                           trace_cap, out, stream, target, ista)
+                           trace_cap, out, stream, target, ista, plain_iterate, x64_out)
 
     def synthesize(self, x, out=None, stream=None):
         torch = _torch()

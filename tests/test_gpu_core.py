@@ -514,15 +514,75 @@ def test_resume_matches_single_run(W, p64):
 
 
 def test_tolerance_stop(W, p64):
+    """The stopping test scores the float64 iterate (the anchor), returned in
+    x64_out; x_out is its float32 rounding, with the same objective to
+    rounding.  The plain float32 iterate is scored as it is."""
     th = imported(W, p64)
     wl = p64["wl"]
-    x, info = th.solve_coeffs(dev(p64["x0"]), wl.lam, 5000, check_every=20, tol=1e-3)
+    A32, lam = p64["A32"], float(np.float32(wl.lam))
+    x0 = p64["x0"].astype(np.float32).astype(np.float64)
+    x64 = torch.empty(4096, device="cuda", dtype=torch.float64)
+    x, info = th.solve_coeffs(dev(p64["x0"]), wl.lam, 5000, check_every=20, tol=1e-3, x64_out=x64)
     assert info["converged"] and info["rel_gap"] <= 1e-3 and info["iters"] % 20 == 0
-    E, D, gap, rel = fista.duality_gap(p64["A32"], p64["x0"].astype(np.float32).astype(np.float64),
-                                       float(np.float32(wl.lam)), host(x))
-    assert abs(rel - info["rel_gap"]) <= 1e-9
+    E, D, gap, rel = fista.duality_gap(A32, x0, lam, host(x64))
+    assert abs(rel - info["rel_gap"]) <= 1e-9 and abs(E - info["objective"]) <= 1e-12 * E
+    assert np.array_equal(host(x), host(x64).astype(np.float32).astype(np.float64))
+    assert abs(fista.objective(A32, x0, lam, host(x)) - E) <= 1e-9 * E
+    xp, ip = th.solve_coeffs(dev(p64["x0"]), wl.lam, 5000, check_every=20, tol=1e-3, plain_iterate=True,
+                             x64_out=x64)
+    assert ip["converged"]
+    E, D, gap, rel = fista.duality_gap(A32, x0, lam, host(xp))
+    assert abs(rel - ip["rel_gap"]) <= 1e-9 and np.array_equal(host(x64), host(xp))
     x, info = th.solve_coeffs(dev(p64["x0"]), wl.lam, 20, check_every=20, tol=1e-9)
     assert not info["converged"]
+
+
+@pytest.fixture(scope="module")
+def db4_32():
+    """Small db4 problem with large approximation coefficients relative to
+    lambda (3 levels, lambda 5e-4): the float32 iterate's rounding sets a gap
+    floor near 1e-3 here."""
+    n, J, lam = 32, 3, 5e-4
+    h = filters.db4()
+    field = synth.psf_rotating(n, 3.0, 1.0)
+    T = theta.theta_dense(field, h, J)
+    r, c, v = theta.top_k(T, 20 * n * n)
+    A32 = sp.csr_matrix((v.astype(np.float32).astype(np.float64), (r, c)), shape=(n * n, n * n))
+    u0 = blur.observe(field, synth.piecewise_image(n, 1), synth.noise(n, 0.005, 2))
+    x0 = dwt.dwt2(u0, h, J).astype(np.float32)
+    return dict(n=n, J=J, lam=lam, A32=A32, x0=x0, rcv=(r, c, v))
+
+
+def test_anchored_iterate_follows_the_float64_gap(W, db4_32):
+    """Alg. 1 with the float64 anchor certifies the duality gap the float64
+    oracle's own iterates reach (here about 1e-5 after 10000 iterations),
+    while the plain float32 iterate stalls at its rounding floor.  The gap of
+    the returned float64 iterate is recomputed by the oracle."""
+    P = db4_32
+    n, lam = P["n"], float(np.float32(P["lam"]))
+    A32, x0 = P["A32"], P["x0"].astype(np.float64)
+    rp, cc, vv = theta.csr_arrays(A32)
+    th = W.Theta.from_csr(n, "db4", P["J"], rp, cc, vv)
+    start = synth.power_start(n * n, 3)
+    L, _ = th.lipschitz(start)
+    iters, c = 10000, 500
+    x64 = torch.empty(n * n, device="cuda", dtype=torch.float64)
+    _, ia = th.solve_coeffs(dev(P["x0"]), lam, iters, check_every=c, trace_cap=iters // c, x64_out=x64)
+    _, ip = th.solve_coeffs(dev(P["x0"]), lam, iters, check_every=c, trace_cap=iters // c, plain_iterate=True)
+    gaps_o = []
+
+    def cb(k, x):
+        if k % c == 0:
+            gaps_o.append(fista.duality_gap(A32, x0, lam, x)[3])
+    Lo, _ = lipschitz.lipschitz(A32, start)
+    fista.fista(A32, x0, lam, 1.0 / Lo, iters, callback=cb)
+    ga, gp, go = ia["trace"][:, 2], ip["trace"][:, 2], np.array(gaps_o)
+    assert go[-1] <= 3e-5                                 # the float64 iteration's own gap
+    assert ga[-1] <= 1.5 * go[-1]                         # anchored: follows it
+    assert np.min(gp) >= 10 * go[-1]                      # float32 iterate: stalls at its floor
+    assert np.all(ga <= 1.5 * go + 1e-7)
+    E, D, gap, rel = fista.duality_gap(A32, x0, lam, host(x64))
+    assert abs(rel - ia["rel_gap"]) <= 1e-9
 
 
 @pytest.mark.parametrize("kind", ["spai", "spai_scale", "jacobi"])
@@ -592,15 +652,16 @@ def test_weighted_l1_solve_matches_oracle(W, p64, pre):
         Lp, _ = lipschitz.lipschitz_precond(A32, p, start)
     x0 = p64["x0"].astype(np.float32)
     lam = float(np.float32(wl.lam))
-    xg, info = th.solve_coeffs(dev(x0), wl.lam, 200, check_every=50, precond=pre)
+    x64 = torch.empty(4096, device="cuda", dtype=torch.float64)
+    xg, info = th.solve_coeffs(dev(x0), wl.lam, 200, check_every=50, precond=pre, x64_out=x64)
     L, _ = lipschitz.lipschitz(A32, start)
     xo, _, _ = fista.fista(A32, x0.astype(np.float64), lam, 1.0 / (Lp if pre else L), 200, p=p, w=w)
     Eo = fista.objective(A32, x0.astype(np.float64), lam, xo, w)
     Eg = fista.objective(A32, x0.astype(np.float64), lam, host(xg), w)
     assert abs(Eg - Eo) <= 1e-5 * Eo
     assert np.linalg.norm(host(xg) - xo) <= 1e-4 * np.linalg.norm(xo)
-    # the float64 check is the weighted objective and gap of the returned iterate
-    E, _, _, rel = fista.duality_gap(A32, x0.astype(np.float64), lam, host(xg), w)
+    # the float64 check is the weighted objective and gap of the float64 iterate
+    E, _, _, rel = fista.duality_gap(A32, x0.astype(np.float64), lam, host(x64), w)
     assert abs(info["objective"] - E) <= 1e-10 * E and abs(info["rel_gap"] - rel) <= 1e-9
     # uniform weights again give the unweighted solve
     th.set_l1_weights("uniform")
