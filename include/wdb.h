@@ -179,9 +179,29 @@ wdb_status wdb_theta_info(const wdb_theta* th, wdb_theta_desc* out);
  * ||Theta_K^T w||; stops at the first k >= 2 with |rho_k - rho_{k-1}| <=
  * tol * rho_k, or at max_iters.  `start` is a host array of N doubles (NULL:
  * a fixed SplitMix64-derived vector).  Stores L in the handle and returns it.
- * Synchronises. */
+ * When max_iters is reached without meeting tol the call returns
+ * WDB_ERR_NOT_CONVERGED, still storing and returning the last quotient (a
+ * lower bound of ||Theta_K||^2: a step 1/L from it may be too long; prefer
+ * wdb_theta_lipschitz_lanczos).  Synchronises. */
 wdb_status wdb_theta_lipschitz(wdb_theta* th, const double* start, double tol,
                                int32_t max_iters, double* L_out, int32_t* iters_out);
+
+/* The same constant by restarted Lanczos in float64 (the solver's default
+ * when a handle has no L): cycles of up to 48 steps on Theta_K^T Theta_K
+ * from v_0 = start/||start|| (NULL: as above), each step one product pair
+ * and two passes of Gram-Schmidt against the cycle's basis; after each step
+ * the largest eigenvalue theta of the tridiagonal projection and the residual
+ * bound resid = beta_m |s_m| of its Ritz pair (some eigenvalue of
+ * Theta_K^T Theta_K lies within resid of theta); a cycle restarts from the
+ * top Ritz vector.  Stops when resid <= tol * theta or after max_steps steps
+ * in all.  Stores L = theta + resid in the handle (an upper bound of
+ * lambda_max when the Ritz pair approximates the top eigenvector, which a
+ * random start gives with probability one) and returns it in L_out, with the
+ * steps taken and resid.  WDB_ERR_NOT_CONVERGED (outputs still written, L
+ * stored) when max_steps ends the run first.  Device memory: 49 vectors of N
+ * doubles for the basis.  Synchronises. */
+wdb_status wdb_theta_lipschitz_lanczos(wdb_theta* th, const double* start, double tol, int32_t max_steps,
+                                       double* L_out, int32_t* steps_out, double* resid_out);
 
 /* Diagonal preconditioner P for Alg. 2 (Sec. 4), from M = Theta_K^T Theta_K:
  *   WDB_PRECOND_NONE      remove it;
@@ -190,8 +210,9 @@ wdb_status wdb_theta_lipschitz(wdb_theta* th, const double* start, double tol,
  *                         p_s = sum_s M^2_ii / sum_s M_ii, the minimiser of the
  *                         same Frobenius objective under that constraint;
  *   WDB_PRECOND_JACOBI    P = max(M_ii, eps) (Sec. 4.2).
- * Also computes L_P = lambda_max(P^-1/2 M P^-1/2) by the power iteration
- * above (start as in wdb_theta_lipschitz).  Synchronises. */
+ * Also computes L_P = lambda_max(P^-1/2 M P^-1/2) by the restarted Lanczos
+ * of wdb_theta_lipschitz_lanczos (start as there; tol and max_iters are its
+ * tolerance and step cap), storing theta + resid.  Synchronises. */
 typedef enum {
   WDB_PRECOND_NONE = 0,
   WDB_PRECOND_SPAI = 1,

@@ -383,9 +383,9 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
   for (wdb_theta* th : order) {
     WDB_HIP(hipSetDevice(th->device));
     ensure_workspace(th);
-    if (!th->has_L) {
-      int it = 0;
-      th->L = power_iteration(th, nullptr, nullptr, 1e-12, 20000, &it, s);
+    if (!th->has_L) {   // the solver's default step (as wdb_solve)
+      const LanczosResult r = lanczos_max(th, nullptr, nullptr, 1e-12, 2000, s);
+      th->L = r.theta + r.resid;
       th->has_L = true;
     }
     const std::vector<int>& m = members[th];

@@ -362,7 +362,7 @@ LanczosResult lanczos_max(wdb_theta* th, const double* start_host, const double*
                           hipStream_t s, int cycle = 48);
 // Power iteration on D^-1/2 A^T A D^-1/2 (d = nullptr: identity), float64.
 double power_iteration(wdb_theta* th, const double* start_host, const double* dinv_sqrt,
-                       double tol, int max_iters, int* iters_out, hipStream_t s);
+                       double tol, int max_iters, int* iters_out, hipStream_t s, bool* converged_out = nullptr);
 // Forward/inverse float32 transform on device (scratch of n*n/4 * 2 floats).
 void dwt_forward(int n, int levels, const Filter& f, const float* in, float* out,
                  float* scratch_a, float* scratch_b, hipStream_t s);

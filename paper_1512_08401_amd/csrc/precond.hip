@@ -158,8 +158,8 @@ extern "C" wdb_status wdb_set_precond(wdb_theta* th, int32_t kind, double eps, c
   WDB_HIP(hipMemcpy(th->p64, p.data(), N * sizeof(double), hipMemcpyHostToDevice));
   hipLaunchKernelGGL(k_to_float_inv, dim3((N + kBlock - 1) / kBlock), dim3(kBlock), 0, s, th->p64, th->pinv, dsq.p, N);
   WDB_HIP(hipGetLastError());
-  int it = 0;
-  th->Lp = power_iteration(th, start, dsq.p, tol, max_iters, &it, s);
+  const LanczosResult r = lanczos_max(th, start, dsq.p, tol, max_iters, s);
+  th->Lp = r.theta + r.resid;
   th->precond = kind;
   refresh_threshold_weights(th);
   WDB_API_END

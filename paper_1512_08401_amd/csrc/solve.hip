@@ -804,7 +804,8 @@ void ensure_workspace(wdb_theta* th) {
 }
 
 double power_iteration(wdb_theta* th, const double* start_host, const double* dinv_sqrt, double tol, int max_iters,
-                       int* iters_out, hipStream_t s) {
+                       int* iters_out, hipStream_t s, bool* converged_out) {
+  if (converged_out) *converged_out = false;
   ensure_workspace(th);
   const int64_t N = th->N;
   WDB_REQUIRE(max_iters >= 1, WDB_ERR_ARG, "max_iters must be >= 1");
@@ -863,6 +864,7 @@ double power_iteration(wdb_theta* th, const double* start_host, const double* di
       WDB_REQUIRE(std::isfinite(rho), WDB_ERR_DIVERGED, "power iteration produced a non-finite value");
       if (kk >= 2 && std::fabs(rho - prev) <= tol * rho) {
         if (iters_out) *iters_out = kk;
+        if (converged_out) *converged_out = true;
         return rho;
       }
       prev = rho;
@@ -1191,10 +1193,13 @@ void launch_iteration(wdb_theta* th, float* x, bool pre, bool ista, float tau, f
               threshold_weights(th, pre), anc, s);
 }
 
+// Default step: the Lanczos bound theta + resid (an upper bound of
+// lambda_max once the top Ritz pair has converged; larger than needed, never
+// smaller, if it has not).
 void ensure_lipschitz(wdb_theta* th, hipStream_t s) {
   if (th->has_L) return;
-  int it = 0;
-  th->L = power_iteration(th, nullptr, nullptr, 1e-12, 20000, &it, s);
+  const LanczosResult r = lanczos_max(th, nullptr, nullptr, 1e-12, 2000, s);
+  th->L = r.theta + r.resid;
   th->has_L = true;
 }
 
@@ -1394,11 +1399,33 @@ wdb_status wdb_theta_lipschitz(wdb_theta* th, const double* start, double tol, i
   wdb::drop_graph(th);  // the cached iteration graph may refer to what this call changes
   WDB_HIP(hipSetDevice(th->device));
   int it = 0;
-  const double L = wdb::power_iteration(th, start, nullptr, tol, max_iters, &it, nullptr);
+  bool converged = false;
+  const double L = wdb::power_iteration(th, start, nullptr, tol, max_iters, &it, nullptr, &converged);
   th->L = L;
   th->has_L = true;
   if (L_out) *L_out = L;
   if (iters_out) *iters_out = it;
+  if (!converged)
+    wdb::fail(WDB_ERR_NOT_CONVERGED, "power iteration reached max_iters = %d without a relative change <= %.3g "
+              "(L = %.17g is a lower bound of ||Theta_K||^2)", max_iters, tol, L);
+  WDB_API_END
+}
+
+wdb_status wdb_theta_lipschitz_lanczos(wdb_theta* th, const double* start, double tol, int32_t max_steps,
+                                       double* L_out, int32_t* steps_out, double* resid_out) {
+  WDB_API_BEGIN
+  WDB_REQUIRE(th, WDB_ERR_ARG, "null handle");
+  wdb::drop_graph(th);  // the cached iteration graph may refer to what this call changes
+  WDB_HIP(hipSetDevice(th->device));
+  const wdb::LanczosResult r = wdb::lanczos_max(th, start, nullptr, tol, max_steps, nullptr);
+  th->L = r.theta + r.resid;
+  th->has_L = true;
+  if (L_out) *L_out = th->L;
+  if (steps_out) *steps_out = r.steps;
+  if (resid_out) *resid_out = r.resid;
+  if (!r.converged)
+    wdb::fail(WDB_ERR_NOT_CONVERGED, "Lanczos reached max_steps = %d with residual %.3e > tol * theta "
+              "(theta = %.17g; L = theta + residual stored)", max_steps, r.resid, r.theta);
   WDB_API_END
 }
 

@@ -82,6 +82,7 @@ _SIGS = {
     "wdb_theta_export": [_vp, _vp, _vp, _vp],
     "wdb_theta_info": [_vp, C.POINTER(ThetaDesc)],
     "wdb_theta_lipschitz": [_vp, _vp, _f64, _i32, _pd, C.POINTER(_i32)],
+    "wdb_theta_lipschitz_lanczos": [_vp, _vp, _f64, _i32, _pd, C.POINTER(_i32), _pd],
     "wdb_set_precond": [_vp, _i32, _f64, _vp, _f64, _i32],
     "wdb_get_precond": [_vp, _vp],
     "wdb_solve": [_vp, _vp, _f32, C.POINTER(SolveOpts), _vp, C.POINTER(SolveInfo)],
@@ -257,17 +258,30 @@ class Theta:
                                                          C.c_void_p(cc.ctypes.data), C.c_void_p(vv.ctypes.data)))
         return rp, cc[: d["nnz"]], vv[: d["nnz"]]
 
-    def lipschitz(self, start=None, tol: float = 1e-12, max_iters: int = 20000):
+    def lipschitz(self, start=None, tol: float = 1e-12, max_iters: int = 20000, require: bool = True):
+        """L by the power iteration; returns (L, iterations).  A run that hits
+        max_iters raises unless require=False (the handle keeps the quotient)."""
         p, keep = _f64ptr(start)
         L = C.c_double(0.0)
         it = C.c_int32(0)
-        _check("wdb_theta_lipschitz", _lib.wdb_theta_lipschitz(self._h, p, tol, max_iters, C.byref(L), C.byref(it)))
+        st = _lib.wdb_theta_lipschitz(self._h, p, tol, max_iters, C.byref(L), C.byref(it))
+        if not (st == WDB_ERR_NOT_CONVERGED and not require):
+            _check("wdb_theta_lipschitz", st)
         return L.value, it.value
 
-    def lipschitz_info(self, start=None, tol: float = 1e-12, max_iters: int = 20000) -> dict:
-        """L by the power iteration, with whether it met tol before max_iters."""
-        L, it = self.lipschitz(start, tol, max_iters)
-        return {"L": L, "method": "power", "iters": it, "converged": it < max_iters}
+    def lipschitz_lanczos(self, start=None, tol: float = 1e-12, max_steps: int = 2000) -> dict:
+        """L = theta + resid by restarted Lanczos (the solver's default)."""
+        p, keep = _f64ptr(start)
+        L, res = C.c_double(0.0), C.c_double(0.0)
+        st = C.c_int32(0)
+        status = _lib.wdb_theta_lipschitz_lanczos(self._h, p, tol, max_steps, C.byref(L), C.byref(st), C.byref(res))
+        if status != WDB_ERR_NOT_CONVERGED:
+            _check("wdb_theta_lipschitz_lanczos", status)
+        return {"L": L.value, "theta": L.value - res.value, "resid": res.value, "method": "lanczos",
+                "steps": st.value, "converged": status == 0}
+
+    def lipschitz_info(self, start=None, tol: float = 1e-12, max_steps: int = 2000) -> dict:
+        return self.lipschitz_lanczos(start, tol, max_steps)
 
     def set_precond(self, kind: str, eps: float = 0.0, start=None, tol: float = 1e-12, max_iters: int = 20000):
         p, keep = _f64ptr(start)

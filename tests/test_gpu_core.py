@@ -361,6 +361,51 @@ def test_lipschitz_matches_oracle(W, p64):
     assert abs(L - ev) <= 1e-8 * ev
 
 
+def test_lanczos_matches_the_largest_singular_value(W, p64):
+    """The restarted Lanczos estimate (the solver's default step) against the
+    largest singular value squared of the same float32 operator; the stored
+    L = theta + resid bounds it from above, and a solve without an explicit
+    L uses it."""
+    th = imported(W, p64)
+    start = synth.power_start(4096, p64["wl"].power_seed)
+    r = th.lipschitz_lanczos(start)
+    ev = np.linalg.norm(p64["A32"].toarray(), 2) ** 2
+    assert r["converged"] and r["resid"] <= 1e-12 * r["theta"]
+    assert abs(r["theta"] - ev) <= 1e-11 * ev and r["L"] >= ev * (1 - 1e-13)
+    th2 = imported(W, p64)
+    _, info = th2.solve_coeffs(dev(p64["x0"]), p64["wl"].lam, 20, check_every=20)
+    assert abs(info["lipschitz"] - ev) <= 1e-11 * ev
+
+
+def test_clustered_top_eigenvalues_lanczos_vs_power_iteration(W):
+    """A diagonal operator with known spectrum whose two largest eigenvalues of
+    A^T A are 1e-3 apart (about the relative gap of the 1024 x 1024
+    workload's operator, where the power iteration used all 20000
+    iterations): the power iteration reports that it stopped at its cap with
+    a lower bound, the restarted Lanczos converges to the exact top value and
+    the stored L bounds it from above."""
+    n, J = 64, 3
+    N = n * n
+    rng = np.random.default_rng(5)
+    lam = rng.uniform(0.0, 0.99, N)
+    lam[17], lam[2900] = 1.0, 1.0 - 1e-3
+    sig = np.sqrt(lam).astype(np.float32).astype(np.float64)   # the stored float32 values
+    top = float(np.max(sig) ** 2)
+    rp = np.arange(N + 1, dtype=np.int64)
+    th = W.Theta.from_csr(n, "haar", J, rp, np.arange(N, dtype=np.int32), sig)
+    start = synth.power_start(N, 9)
+    Lp, it = th.lipschitz(start, max_iters=5000, require=False)
+    assert it == 5000 and Lp < top
+    with pytest.raises(W.WdbError):
+        th.lipschitz(start, max_iters=5000)
+    r = th.lipschitz_lanczos(start)
+    print(f"Lanczos: {r}; power iteration {Lp!r} after {it}", flush=True)
+    assert r["converged"] and r["steps"] < 5000
+    assert abs(r["theta"] - top) <= 1e-12 * top and r["L"] >= top * (1 - 1e-15)
+    r = th.lipschitz_lanczos(start, max_steps=10)
+    assert not r["converged"] and r["steps"] == 10 and r["theta"] <= top * (1 + 1e-15)
+
+
 @pytest.mark.parametrize("layout", [None, (8, 3)])
 def test_objective_and_gap_match_oracle(W, p64, layout):
     """The float64 stopping test on the default layout and on the tiled one
