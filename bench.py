@@ -63,7 +63,14 @@ KERNEL_SOURCES = ("paper_1512_08401_amd/csrc/solve.hip", "paper_1512_08401_amd/c
                   "paper_1512_08401_amd/csrc/prox.hpp")
 
 
-def profiled_traffic(workload, kernel, layout):
+def layout_key(layout, tile_shape):
+    """Text key of the iteration layout, as the profile summaries record it."""
+    if layout[1] == 3:
+        return f"tiled waves={tile_shape[0]} unroll={tile_shape[1]}"
+    return f"slice={layout[0]} group={layout[1]}"
+
+
+def profiled_traffic(workload, kernel, key):
     """HBM bytes per launch of ``kernel`` (for "fista_iteration": per iteration,
     both kernels) from a committed rocprofv3 counter summary under profiles/
     (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when no summary was
@@ -79,7 +86,7 @@ def profiled_traffic(workload, kernel, layout):
         fields = dict(line.strip().split(": ", 1) for line in text.splitlines()
                       if line.startswith("    ") and ": " in line)
         if (fields.get("source_sha256") == dig.hexdigest() and fields.get("kernel") == kernel
-                and fields.get("layout") == f"slice={layout[0]} group={layout[1]}"
+                and fields.get("layout") == key
                 and fields.get("workload") == workload and "traffic_bytes_per_launch" in fields):
             return int(fields["traffic_bytes_per_launch"])
     return None
@@ -274,14 +281,15 @@ def main():
     torch.cuda.synchronize()
     k_us = k0e.elapsed_time(k1e) * 1e3 / reps
     kname, kdesc = kernel_label(layout, *tile_shape)
-    traffic = profiled_traffic(wl.name, "fista_iteration", layout)
+    lkey = layout_key(layout, tile_shape)
+    traffic = profiled_traffic(wl.name, "fista_iteration", lkey)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": f"one FISTA iteration inside the solve: {kname} ({kdesc}) + the transposed kernel "
                           f"with the proximal epilogue",
                 "iteration_us": round(it_us, 2), "algorithmic_bytes": it_bytes,
                 "copy_ceiling_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
-                "layout": layout_desc(layout, tile_shape),
+                "layout": layout_desc(layout, tile_shape), "layout_key": lkey,
                 "cached_loop": {"kernel": kname, "kernel_us": round(k_us, 2),
                                 "algorithmic_bytes": 8 * nnz + 12 * N,
                                 "gbs": round((8 * nnz + 12 * N) / (k_us * 1e-6) / 1e9, 1),

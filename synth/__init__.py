@@ -149,51 +149,40 @@ def _bands(n: int, levels: int):
     return out
 
 
-def local_operator(n: int, levels: int, nnz_per_px: float, seed: int, radius: int = 3, max_gap: int = 1,
-                   spread: bool = False, far: int = 0, decay: float = 0.5):
+def local_operator(n: int, levels: int, nnz_per_px: float, seed: int, radius: int = 3, coarse_from: int = 0,
+                   far: int = 0):
     """A seeded sparse N x N matrix (N = n^2, rows and columns in canonical
     subband order) with the storage-relevant structure of a thresholded
     wavelet-domain operator of a slowly varying blur, at full size.
 
     Row a (subband of level la, position (i, j)) keeps entries in the subbands
-    of levels la - max_gap .. la + max_gap at displacements |di|, |dj| <= R
-    around (i, j) scaled to the column subband's side, with magnitude
-    amp * exp(-(di^2 + dj^2) / (2 (w f)^2)): amp = decay^|level gap| (times 0.35
-    across orientations), a width w that grows smoothly from 0.7 to 2.3 across
-    the image columns, and R = radius, f = 1; with ``spread`` a column subband
-    finer than the row's by g levels gets R = radius 2^g and f = 2^g (a coarse
-    atom overlaps that many fine positions), so coarse rows keep long runs of
-    finer columns.  Entries above one global level tau are kept, tau chosen
-    so that about nnz_per_px * n^2 entries survive; each kept value gets a
-    random sign and 5 % multiplicative noise.  ``far`` extra entries (value
-    tau) join rows of the finest level: half at a level gap of 4 (when the
-    transform has the levels), the others at a displacement of 129..200
-    positions in a column subband of side >= 512, beyond any short
+    of levels la - 1 .. la + 1 at displacements |di|, |dj| <= radius around
+    (i, j) scaled to the column subband's side, with magnitude
+    amp * exp(-(di^2 + dj^2) / (2 w^2)): amp = 2^-|level gap| (times 0.35
+    across orientations) and a width w that grows smoothly from 0.7 to 2.3
+    across the image columns.  The largest of these are kept (ties in a seeded
+    random order), as many as make nnz_per_px * n^2 entries in all with the
+    additions below (fewer only where wrapping on a small subband repeats an
+    entry); each kept value gets a random sign and 5 % multiplicative noise.
+
+    With ``coarse_from`` > 0, every row of a detail subband of level
+    >= coarse_from also keeps, like the long rows of a coarse atom that
+    overlaps many finer ones, entries in the same orientation two levels finer
+    at every displacement in [-8, 8]^2 and three levels finer on the lattice
+    {-24, -18, ..., 24}^2 (magnitude just above the smallest kept one).
+    ``far`` extra entries (that magnitude) join rows of the finest level: half at a level gap of 4
+    (when the transform has 5 levels or more), the others at a displacement of
+    129..200 positions in a column subband of side >= 512, beyond any short
     band-relative code.  Returns (rowptr int64, col int32, val float64).
     """
     rng = np.random.default_rng(seed)
     N = n * n
     bands = _bands(n, levels)
-    pairs = []
-    for A in bands:
-        for B in bands:
-            gap = abs(A[0] - B[0])
-            if gap > max_gap:
-                continue
-            g = max(0, A[0] - B[0]) if spread else 0
-            pairs.append((A, B, decay ** gap * (1.0 if A[1] == B[1] else 0.35), (2 * radius) << g if g else radius,
-                          1.6 * (1 << g) if g else 1.0))
-
-    grids = {}
-
-    def grid(R):
-        if R not in grids:
-            offs = np.arange(-R, R + 1)
-            DI, DJ = (a.ravel() for a in np.meshgrid(offs, offs, indexing="ij"))
-            d2 = (DI * DI + DJ * DJ).astype(np.float64)
-            d2v, d2c = np.unique(d2, return_counts=True)
-            grids[R] = (DI, DJ, d2, d2v, np.concatenate([[0], np.cumsum(d2c)]))
-        return grids[R]
+    offs = np.arange(-radius, radius + 1)
+    DI, DJ = (a.ravel() for a in np.meshgrid(offs, offs, indexing="ij"))
+    d2 = (DI * DI + DJ * DJ).astype(np.float64)
+    pairs = [(A, B, 0.5 ** abs(A[0] - B[0]) * (1.0 if A[1] == B[1] else 0.35))
+             for A in bands for B in bands if abs(A[0] - B[0]) <= 1]
 
     def width(A):
         sa = A[2]
@@ -201,47 +190,34 @@ def local_operator(n: int, levels: int, nnz_per_px: float, seed: int, radius: in
         return 0.7 + 1.6 * (j + 0.5) / sa
 
     widths = {A[3]: width(A) for A in bands}
+    d2v, d2c = np.unique(d2, return_counts=True)
+
+    cum = np.concatenate([[0], np.cumsum(d2c)])   # entries with d2 below the k-th distinct value
 
     def count(tau):
         tot = 0
-        for A, B, amp, R, f in pairs:
-            if amp > tau:   # kept iff d2 < 2 (w f)^2 ln(amp / tau)
-                _, _, _, d2v, cum = grid(R)
-                lim = 2.0 * (widths[A[3]] * f) ** 2 * math.log(amp / tau)
+        for A, B, amp in pairs:
+            if amp > tau:   # kept iff d2 < 2 w^2 ln(amp / tau)
+                lim = 2.0 * widths[A[3]] ** 2 * math.log(amp / tau)
                 tot += int(cum[np.searchsorted(d2v, lim, side="left")].sum())
         return tot
 
-    target = nnz_per_px * N - far
-    lo, hi = 1e-12, 1.0
-    for _ in range(60):
-        mid = math.sqrt(lo * hi)
-        if count(mid) > target:
-            lo = mid
-        else:
-            hi = mid
-    tau = hi
-    rows, cols, mags = [], [], []
-    for A, B, amp, R, f in pairs:
-        if amp <= tau:
-            continue
-        (la, oa, sa, fa), (lb, ob, sb, fb) = A, B
-        DI, DJ, d2, _, _ = grid(R)
-        i, j = np.divmod(np.arange(sa * sa), sa)
-        ci, cj = (i * sb) // sa, (j * sb) // sa
-        w = widths[fa] * f
-        lim = 2.0 * w * w * math.log(amp / tau)
-        for c0 in range(0, sa * sa, 4096):   # rows in chunks: coarse rows of a spread grid are long
-            sl = slice(c0, min(c0 + 4096, sa * sa))
-            mag = amp * np.exp(-d2[None, :] / (2.0 * w[sl, None] ** 2))
-            keep = d2[None, :] < lim[sl, None]
-            rr, kk = np.nonzero(keep)
-            rr = rr + c0
-            rows.append(fa + rr)
-            cols.append(fb + ((ci[rr] + DI[kk]) % sb) * sb + (cj[rr] + DJ[kk]) % sb)
-            mags.append(mag[rr - c0, kk])
+    # the coarse rows' long runs of finer columns (added below, outside the threshold)
+    runs = []
+    if coarse_from > 0:
+        o2 = np.arange(-8, 9)
+        o3 = np.arange(-24, 25, 6)
+        for A in bands:
+            la, oa, sa, fa = A
+            if oa == 3 or la < coarse_from:
+                continue
+            for g, oo in ((2, o2), (3, o3)):
+                B = [b for b in bands if b[0] == la - g and b[1] == oa]
+                if B:
+                    runs.append((A, B[0], oo))
+    far_rows, far_cols = [], []
     if far:
         fine = [B for B in bands if B[0] == 1]
-        far_rows, far_cols = [], []
         for t in range(far):
             A = fine[t % 3]
             a = A[3] + int(rng.integers(0, A[2] * A[2]))
@@ -256,9 +232,48 @@ def local_operator(n: int, levels: int, nnz_per_px: float, seed: int, radius: in
                 d = int(rng.integers(129, 201)) * (1 if rng.random() < 0.5 else -1)
                 far_cols.append(B[3] + ((i + d) % B[2]) * B[2] + j)
             far_rows.append(a)
-        rows.append(np.array(far_rows, dtype=np.int64))
-        cols.append(np.array(far_cols, dtype=np.int64))
-        mags.append(np.full(len(far_rows), tau))
+    extra = sum(A[2] * A[2] * oo.size ** 2 for A, B, oo in runs) + len(far_rows)
+    target = nnz_per_px * N - extra
+    lo, hi = 1e-12, 1.0
+    for _ in range(60):
+        mid = math.sqrt(lo * hi)
+        if count(mid) > target:
+            lo = mid
+        else:
+            hi = mid
+    tau = lo   # count(lo) > target: generate above lo, then keep the target's largest
+    rows, cols, mags = [], [], []
+    for A, B, amp in pairs:
+        if amp <= tau:
+            continue
+        (la, oa, sa, fa), (lb, ob, sb, fb) = A, B
+        i, j = np.divmod(np.arange(sa * sa), sa)
+        ci, cj = (i * sb) // sa, (j * sb) // sa
+        mag = amp * np.exp(-d2[None, :] / (2.0 * widths[fa][:, None] ** 2))
+        keep = d2[None, :] < (2.0 * widths[fa] ** 2 * math.log(amp / tau))[:, None]   # as count() decides
+        rr, kk = np.nonzero(keep)
+        rows.append(fa + rr)
+        cols.append(fb + ((ci[rr] + DI[kk]) % sb) * sb + (cj[rr] + DJ[kk]) % sb)
+        mags.append(mag[rr, kk])
+    if rows:   # the base entries: the `target` largest magnitudes (ties in a seeded random order)
+        r0, c0, m0 = np.concatenate(rows), np.concatenate(cols), np.concatenate(mags)
+        t = max(min(int(target), m0.size), 0)
+        key = m0 * (1.0 + 1e-9 * rng.random(m0.size))   # seeded tie-break; selection only
+        keep = np.sort(np.argpartition(-key, t - 1)[:t]) if 0 < t < m0.size else np.arange(t)
+        rows, cols, mags = [r0[keep]], [c0[keep]], [m0[keep]]
+    floor = float(np.min(mags[0])) if rows and mags[0].size else 1.0   # smallest kept base magnitude
+    for A, B, oo in runs:
+        (la, oa, sa, fa), (lb, ob, sb, fb) = A, B
+        EI, EJ = (a.ravel() for a in np.meshgrid(oo, oo, indexing="ij"))
+        i, j = np.divmod(np.arange(sa * sa), sa)
+        ci, cj = (i * sb) // sa, (j * sb) // sa
+        rows.append(np.repeat(fa + np.arange(sa * sa), EI.size))
+        cols.append(fb + ((np.repeat(ci, EI.size) + np.tile(EI, sa * sa)) % sb) * sb
+                    + (np.repeat(cj, EI.size) + np.tile(EJ, sa * sa)) % sb)
+        mags.append(np.full(sa * sa * EI.size, 1.2 * floor))
+    rows.append(np.array(far_rows, dtype=np.int64))
+    cols.append(np.array(far_cols, dtype=np.int64))
+    mags.append(np.full(len(far_rows), floor))
     r = np.concatenate(rows).astype(np.int64)
     c = np.concatenate(cols).astype(np.int64)
     m = np.concatenate(mags)

@@ -9,10 +9,14 @@ Two kinds of input:
   set against the threshold: every kept entry of the column is at least the
   threshold and every dropped one at most it);
 * a seeded full-size stand-in operator from ``synth.local_operator`` (the
-  workload's size and about its non-zero count, with the locality and slowly
-  varying pattern of a thresholded wavelet-domain operator), for the products,
-  the 16-bit products, the float64 stopping test and 100 FISTA iterations
-  against the oracle, so that no oracle input comes from the GPU.
+  workload's size and non-zero count, with the locality and slowly varying
+  pattern of a thresholded wavelet-domain operator, long coarse rows reaching
+  two and three levels finer at displacements beyond 16, and a few entries no
+  tile code can express), for the products, the 16-bit products, the float64
+  stopping test and 100 FISTA iterations against the oracle, so that no
+  oracle input comes from the GPU.  A test checks that the stand-in's
+  structure (level gaps, displacements, codes per tile, escapes) covers that
+  of the workloads' own operators built on the GPU.
 
 Float32 products: max abs error <= 1e-5 max |reference|; solver gate as in
 test_gpu_core (relative objective 1e-5, relative ||x - x_o|| 1e-4).
@@ -22,14 +26,15 @@ import pytest
 import scipy.sparse as sp
 
 import synth
+import tilestats
 from oracle import dwt, filters, fista, lipschitz, quant, theta
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-# workload -> (n, levels, nnz per pixel, stand-in seed)
-SIZES = {"precision512": (512, 5, 30, 7), "scale1024": (1024, 6, 20, 8)}
+# workload -> (n, levels, nnz per pixel, stand-in seed, first level of the long coarse rows)
+SIZES = {"precision512": (512, 5, 30, 7, 4), "scale1024": (1024, 6, 20, 8, 5)}
 
 
 @pytest.fixture(scope="module")
@@ -51,9 +56,9 @@ def host(t):
 @pytest.fixture(scope="module", params=list(SIZES))
 def standin(request):
     name = request.param
-    n, J, per_px, seed = SIZES[name]
+    n, J, per_px, seed, coarse = SIZES[name]
     print(f"stand-in operator {name}: n={n} J={J}", flush=True)
-    rp, cc, vv = synth.local_operator(n, J, per_px, seed)
+    rp, cc, vv = synth.local_operator(n, J, per_px, seed, coarse_from=coarse, far=64)
     vv = vv.copy()
     vv[rp[0]:rp[1]][cc[rp[0]:rp[1]] == 0] *= 20.0   # one dominant entry: a clear top singular value
     N = n * n
@@ -128,8 +133,6 @@ def test_fullsize_fista_matches_oracle(W, standin):
     layout, HIP-graph replay between checks) against the oracle; each side
     computes L by its own power iteration."""
     S = standin
-    if S["name"] != "precision512":
-        pytest.skip("the 100-iteration oracle run is taken on the 512 x 512 operator (CPU time)")
     n, J, N = S["n"], S["J"], S["n"] ** 2
     th = W.Theta.from_csr(n, "db4", J, S["rp"], S["cc"], S["vv"])
     th.autotune(reps=5)
@@ -183,3 +186,33 @@ def test_fullsize_build_sampled_columns_match_oracle(W):
         kept[a] = True
         assert np.all(np.abs(col[kept]) >= thr * (1 - 1e-12))
         assert np.all(np.abs(col[~kept]) <= thr * (1 + 1e-12))
+
+
+def test_standin_structure_covers_the_workload_operators(W, standin):
+    """The stand-in operator exercises at least the storage cases the
+    workload's own Theta_K (built on the GPU) needs: its largest level gap,
+    its largest displacement from the centred point, its largest number of
+    codes per tile, and at least one entry no tile code can hold (the built
+    operators have none), with as many non-zeros.  The decay theorem of
+    Sec. 3.2 is what confines the built operator to this range."""
+    S = standin
+    wl = synth.WORKLOADS[S["name"]]
+    th = W.build_theta(wl.psf(), wl.wavelet, wl.levels, wl.nnz)
+    rp, cc, _ = th.export()
+    del th
+    taps = len(filters.by_name(wl.wavelet))
+    real = tilestats.stats(rp, cc, wl.n, wl.levels, taps)
+    stand = tilestats.stats(S["rp"], S["cc"], S["n"], S["J"], taps)
+    print(f"{S['name']}: built {real}\n  stand-in {stand}", flush=True)
+    assert stand["nnz"] == real["nnz"] == wl.nnz
+    assert stand["max_level_gap"] >= max(real["max_level_gap"], 3)
+    assert stand["max_disp"] > max(real["max_disp"], 16)
+    assert stand["max_codes_per_coarse_tile"] >= real["max_codes_per_coarse_tile"]
+    assert stand["escapes"] >= 1 and stand["entries_gap_2_or_more"] >= 1
+    # the library's tiled copies keep exactly those entries (and their
+    # transposes) in escape lists
+    At = S["A"].T.tocsr()
+    esc_t = tilestats.stats(At.indptr, At.indices, S["n"], S["J"], taps)["escapes"]
+    th = W.Theta.from_csr(S["n"], "db4", S["J"], S["rp"], S["cc"], S["vv"])
+    th.set_kernel_layout(8, 3)
+    assert th.info()["tile_escapes"] == stand["escapes"] + esc_t
