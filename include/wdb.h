@@ -431,6 +431,17 @@ wdb_status wdb_synthesize(const wdb_theta* th, const float* x, float* u_hat, voi
 wdb_status wdb_dwt(int32_t n, int32_t wavelet, int32_t levels, const float* in, float* out,
                    int32_t inverse, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * transform as wdb_dwt, bit for bit, with its level-to-level intermediates
+ * in a fixed device array of the library (8 MiB per GPU, held until the
+ * process ends) instead of a per-call allocation.  n <= 2048 (WDB_ERR_SIZE
+ * otherwise, before any GPU work).  No allocation, no synchronisation: the
+ * work is only enqueued on `stream`.  Calls that overlap on one GPU share the
+ * array and race; serialise them.  Errors: as wdb_dwt. */
+wdb_status wdb_dwt_noalloc(int32_t n, int32_t wavelet, int32_t levels, const float* in, float* out,
+                           int32_t inverse, void* stream);
+
 /* out = H u for the PSF field (Sec. 3.1, column convention), float64
  * arithmetic, float32 storage; u, out: device n*n floats, must not alias.
  * Synchronises `stream` (uploads the field).  Errors: as wdb_build_theta. */

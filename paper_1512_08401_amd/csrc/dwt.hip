@@ -13,6 +13,8 @@
 // half-resolution footprint (4 + 6 rows of 16 + 6 columns, periodic) in LDS,
 // and every thread sums the (L/2)^2 coefficients of each subband that cover
 // its pixel from there.
+#include <mutex>
+
 #include "common.hpp"
 
 namespace wdb {
@@ -206,5 +208,59 @@ extern "C" wdb_status wdb_synthesize(const wdb_theta* th, const float* x, float*
   const size_t q = static_cast<size_t>(th->n / 2) * (th->n / 2);
   wdb::dwt_inverse(th->n, th->levels, f, x, u_hat, t->ws_img, t->ws_img + q,
                    static_cast<hipStream_t>(stream));
+  WDB_API_END
+}
+
+// ---------------------------------------------------------------------------
+// Transform without allocation.  The level-to-level intermediates live in a
+// fixed device array instead of a per-call allocation: each GPU the library
+// runs on holds its own copy (kNoAllocScratch floats, 8 MiB, enough for
+// n <= 2048) until the process ends.  Host code never passes the array's name
+// to a kernel: its device address is looked up once per device with
+// hipGetSymbolAddress and only that address is used.  Every level writes the
+// intermediate it later reads, so the array needs no clearing; calls that
+// overlap on one GPU (different streams or threads) share it and race.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kNoAllocMaxN = 2048;
+constexpr size_t kNoAllocScratch = 2 * static_cast<size_t>(kNoAllocMaxN / 2) * (kNoAllocMaxN / 2);
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) float scratch[kNoAllocScratch];
+
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array (looked up on first use).
+float* scratch_address() {
+  int dev = 0;
+  WDB_HIP(hipGetDevice(&dev));
+  WDB_REQUIRE(dev >= 0 && dev < kMaxDevices, WDB_ERR_ARG, "device index %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    WDB_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    WDB_REQUIRE(ptr != nullptr, WDB_ERR_HIP, "no device address for the transform scratch array");
+    g_scratch_ptr[dev] = static_cast<float*>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" wdb_status wdb_dwt_noalloc(int32_t n, int32_t wavelet, int32_t levels, const float* in, float* out,
+                                      int32_t inverse, void* stream) {
+  WDB_API_BEGIN
+  WDB_REQUIRE(in && out, WDB_ERR_ARG, "null buffer");
+  WDB_REQUIRE(in != out, WDB_ERR_ARG, "in and out must not alias");
+  wdb::Filter f = wdb::make_filter(wavelet);
+  wdb::check_geometry(n, levels, static_cast<int>(f.h.size()));
+  WDB_REQUIRE(n <= kNoAllocMaxN, WDB_ERR_SIZE,
+              "wdb_dwt_noalloc: image side %d exceeds the fixed scratch limit of %d (use wdb_dwt)", n, kNoAllocMaxN);
+  float* sc = scratch_address();
+  const size_t q = static_cast<size_t>(n / 2) * (n / 2);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (inverse)
+    wdb::dwt_inverse(n, levels, f, in, out, sc, sc + q, s);
+  else
+    wdb::dwt_forward(n, levels, f, in, out, sc, sc + q, s);
   WDB_API_END
 }
