@@ -329,8 +329,9 @@ typedef struct {
                             anchor at every check, so the float64 stopping test can
                             certify gaps far below what a float32 iterate's rounding
                             allows (one extra 8-byte read per coefficient and
-                            iteration); 1: float32 iterate only.  16-bit values and
-                            the batched solver always use the float32 iterate.    */
+                            iteration); 1: float32 iterate only.  16-bit values
+                            always use the float32 iterate; the batched solver
+                            always anchors.                                       */
   double* x64_out;       /* device, N doubles, or NULL: receives the float64 iterate the
                             last check scored (the anchor; x_out is its float32
                             rounding, whose own gap can be larger); with a plain
@@ -375,6 +376,9 @@ typedef struct {
   double target_objective; /* > 0: this problem stops at the first check with E <= target */
   const float* x0;       /* device, N coefficients Psi^* u given directly (u is then
                             not read), or NULL to transform u on the device   */
+  double* x64_out;       /* device, N doubles, or NULL: the float64 iterate the
+                            problem's last check scored (x_out is its float32
+                            rounding)                                         */
 } wdb_problem;
 
 /* Solve many problems in one call (Alg. 1 for each).  Problems sharing a
@@ -446,6 +450,45 @@ wdb_status wdb_dwt_noalloc(int32_t n, int32_t wavelet, int32_t levels, const flo
  * arithmetic, float32 storage; u, out: device n*n floats, must not alias.
  * Synchronises `stream` (uploads the field).  Errors: as wdb_build_theta. */
 wdb_status wdb_blur(const wdb_psf_field* field, const float* u, float* out, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Exact-operator baseline (Sec. 1.2; the "Exact" columns of the experiments
+ * of Sec. 5): Alg. 1 on the wavelet coefficients with the gradient of
+ * 1/2 ||H Psi x - u0||^2 computed from the blur itself,
+ * g = Psi^* H^* (H Psi y - u0), instead of from Theta_K.  Psi is orthogonal,
+ * so this is the problem before thresholding (Theta = Psi^* H Psi, all of
+ * it).  H and H^* evaluate the truncated PSFs of the field on the fly in
+ * float64 (the formula and cut-off of wdb_blur), accumulating in float64;
+ * images and coefficients are float32.  Device memory: about 40 N bytes.
+ * ------------------------------------------------------------------------- */
+typedef struct wdb_exact wdb_exact;
+
+/* Handle for the PSF field (host arrays, read during the call) with the
+ * given wavelet and levels.  Synchronises `stream`.  Errors: as
+ * wdb_build_theta. */
+wdb_status wdb_exact_create(const wdb_psf_field* field, int32_t wavelet, int32_t levels, void* stream,
+                            wdb_exact** out);
+/* out = H in (adjoint = 0) or H^* in (adjoint = 1) on n*n images (device
+ * float32, must not alias); no synchronisation. */
+wdb_status wdb_exact_apply(wdb_exact* ex, int32_t adjoint, const float* in, float* out, void* stream);
+/* L = ||H||^2 (= ||Psi^* H Psi||^2) by the restarted Lanczos of
+ * wdb_theta_lipschitz_lanczos on H^* H in float64; stores L = theta + resid.
+ * WDB_ERR_NOT_CONVERGED (outputs written) when max_steps ends the run first. */
+wdb_status wdb_exact_lipschitz(wdb_exact* ex, const double* start, double tol, int32_t max_steps, double* L_out,
+                               int32_t* steps_out, double* resid_out);
+/* Alg. 1 with the exact gradient from the blurred image u (device n*n) into
+ * x_out (device N coefficients).  opts: max_iters, check_every (objective
+ * E = 1/2 ||H Psi x - u0||^2 + lambda ||x||_1 and relative duality gap, from
+ * float32 products with float64 sums, one gradient evaluation per check; the
+ * float32 residual puts the gap's accuracy near 1e-3 relative at the
+ * workloads' lambda, the objective's near 1e-7),
+ * tol_rel_gap, target_objective, x_init, k0, ista, trace/trace_cap, stream;
+ * use_precond is refused, use_graph and plain_iterate are ignored (float32
+ * iterate, launches issued per iteration).  Computes L on first use.
+ * Synchronises at each check.  Errors: as wdb_solve. */
+wdb_status wdb_exact_solve(wdb_exact* ex, const float* u, float lambda, const wdb_solve_opts* opts, float* x_out,
+                           wdb_solve_info* info);
+void wdb_exact_free(wdb_exact* ex);
 
 /* ---------------------------------------------------------------------------
  * Warm start (not in the paper): a small network on wavelet coefficients that

@@ -16,13 +16,20 @@
 // chunks on the tiles instead: one 256-thread block (4 wavefronts) per tile,
 // lane = row, and for every shared column code each lane loads its column's
 // 8 right-hand-side values (32 contiguous bytes; neighbouring lanes of a tile
-// row read neighbouring columns) and the tile value once for all eight.  The
-// float64 checks stay on the sliced-ELL copies.
+// row read neighbouring columns) and the tile value once for all eight.  Their
+// float64 checks run on the tiles too (64 contiguous bytes per column).
+//
+// Each problem's iterate is anchored as in the single solve: a float64 anchor
+// [N][8] plus the float32 displacement X; the residual subtracts
+// c = x0 - Theta_K anchor, the proximal step thresholds anchor + y - tau g in
+// float64, and every check first moves X into the anchor, then scores the
+// anchor and takes the next c from its float64 residual.
 #include <cmath>
 #include <map>
 
 #include "codes.hpp"
 #include "common.hpp"
+#include "prox.hpp"
 
 namespace wdb {
 
@@ -45,9 +52,11 @@ struct ChunkDev {
   const int32_t* permT;
   int64_t nslicesT;
   int C, cshift;     // slice height of both copies and its log2
-  float* X;          // [N][8] iterate
-  float* Y;          // [N][8] extrapolated point
+  float* X;          // [N][8] iterate (displacement from the anchor)
+  float* Y;          // [N][8] extrapolated point (displacement from the anchor)
   const float* X0;   // [N][8] data
+  float* Cr;         // [N][8] right-hand side of the displacement iteration, x0 - Theta_K anchor
+  double* Anc;       // [N][8] float64 anchor
   float* Rr;         // [N][8] residual
   const float* pinv; // N or null
   float tau;
@@ -153,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_res_batched(const ChunkDev* __restri
     float acc[kR] = {0, 0, 0, 0, 0, 0, 0, 0};
     const int row = tile_mm(C, 0, tile, C.Y, acc);
     if (row < 0) return;
-    const float4* b = reinterpret_cast<const float4*>(C.X0 + static_cast<int64_t>(row) * kR);
+    const float4* b = reinterpret_cast<const float4*>(C.Cr + static_cast<int64_t>(row) * kR);
     float4* r = reinterpret_cast<float4*>(C.Rr + static_cast<int64_t>(row) * kR);
     const float4 b0 = b[0], b1 = b[1];
     r[0] = make_float4(acc[0] - b0.x, acc[1] - b0.y, acc[2] - b0.z, acc[3] - b0.w);
@@ -168,7 +177,7 @@ __global__ __launch_bounds__(kBlock) void k_res_batched(const ChunkDev* __restri
   slice_mm(C.soff, C.val, C.col, sl, lane, C.C, C.Y, acc);
   const int64_t row = slot_row_c(C.perm, C.nrows, q);
   if (row < 0) return;
-  const float4* b = reinterpret_cast<const float4*>(C.X0 + row * kR);
+  const float4* b = reinterpret_cast<const float4*>(C.Cr + row * kR);
   float4* r = reinterpret_cast<float4*>(C.Rr + row * kR);
   const float4 b0 = b[0], b1 = b[1];
   r[0] = make_float4(acc[0] - b0.x, acc[1] - b0.y, acc[2] - b0.z, acc[3] - b0.w);
@@ -200,12 +209,11 @@ __global__ __launch_bounds__(kBlock) void k_prox_batched(const ChunkDev* __restr
   const float pi = C.pinv ? C.pinv[row] : 1.0f;
   float* X = C.X + row * kR;
   float* Y = C.Y + row * kR;
+  const double* An = C.Anc + row * kR;
 #pragma unroll
   for (int j = 0; j < kR; ++j) {
     if (!C.act[j]) continue;
-    const float z = Y[j] - (C.tau * pi) * g[j];
-    const float t = C.thr[j] * pi;
-    const float xn = copysignf(fmaxf(fabsf(z) - t, 0.0f), z);
+    const float xn = prox_anchored(An[j], Y[j], (C.tau * pi) * g[j], C.thr[j] * pi);
     const float xo = X[j];
     X[j] = xn;
     Y[j] = xn + beta * (xn - xo);
@@ -235,29 +243,81 @@ __device__ __forceinline__ void block_reduce8(double (&v)[kR], bool is_max, doub
   __syncthreads();
 }
 
+// Tile `tile` of copy m times an [N][8] block V in float64 (V float64, or
+// float32 widened): acc[8] of the lane's row, complete in wavefront 0 (escapes
+// dealt to the four wavefronts; partials added in LDS in wavefront order).
+// Called by every thread of the block.
+template <typename T>
+__device__ __forceinline__ int tile_mm64(const ChunkDev& C, int m, int tile, const T* __restrict__ V,
+                                         double (&acc)[kR]) {
+  __shared__ double part[kWaves][kR][kWave];
+  const int4 d = C.tdesc[m][tile];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int row = tile_row(d, lane);
+  const RowCode rc = tile_row_code(C.geo, d, row);
+  const uint4* __restrict__ code = C.tcode[m];
+  const float4* __restrict__ val = C.tval[m];
+  auto add = [&](int col, float w) {
+    const T* p = V + static_cast<int64_t>(col) * kR;
+#pragma unroll
+    for (int j = 0; j < kR; ++j) acc[j] = fma(static_cast<double>(w), static_cast<double>(p[j]), acc[j]);
+  };
+  for (int k = (d.x >> 2) + wv; k < (d.y >> 2); k += kWaves) {
+    const uint4 c = code[k];
+    const float4 v = val[static_cast<int64_t>(k) * kWave + lane];
+    const int4 col = group_cols(C.geo, rc, c);
+    add(col.x, v.x);
+    add(col.y, v.y);
+    add(col.z, v.z);
+    add(col.w, v.w);
+  }
+  if (row >= 0 && (d.w & kHasEsc))
+    for (int k = C.terp[m][row] + wv; k < C.terp[m][row + 1]; k += kWaves) add(C.tec[m][k], C.tev[m][k]);
+#pragma unroll
+  for (int j = 0; j < kR; ++j) part[wv][j][lane] = acc[j];
+  __syncthreads();
+  if (wv == 0) {
+#pragma unroll
+    for (int j = 0; j < kR; ++j) {
+      double a = part[0][j][lane];
+      for (int w = 1; w < kWaves; ++w) a += part[w][j][lane];
+      acc[j] = a;
+    }
+  }
+  return wv == 0 ? row : -1;
+}
+
+// Forward half of the float64 check on the anchors: r64 = Theta_K anchor - x0
+// and per-block sums of r^2, r.x0, |anchor| per right-hand side.
 __global__ __launch_bounds__(kBlock) void k_check_fwd(const ChunkDev* __restrict__ ch, const int* __restrict__ first,
                                                       int nchunks, double* __restrict__ part, int64_t nblocks) {
   const int c = chunk_of(first, nchunks, blockIdx.x);
   const ChunkDev& C = ch[c];
   if (!C.act[kR]) return;  // every problem of this chunk has stopped
-  const int64_t q = static_cast<int64_t>(blockIdx.x - first[c]) * kBlock + threadIdx.x;
-  const int64_t sl = q >> C.cshift;
-  const int lane = static_cast<int>(q & (C.C - 1));
   double a[kR], rr[kR], rb[kR], l1[kR];
   for (int j = 0; j < kR; ++j) a[j] = rr[j] = rb[j] = l1[j] = 0.0;
   int64_t row = -1;
-  if (q < (C.nslices << C.cshift)) {
-    const int64_t beg = C.soff[sl] >> 2, end = C.soff[sl + 1] >> 2;
-    for (int64_t jj = beg + lane; jj < end; jj += C.C) {
-      const float4 v = C.val[jj];
-      const int4 cc = C.col[jj];
-      const float vv[4] = {v.x, v.y, v.z, v.w};
-      const int ci[4] = {cc.x, cc.y, cc.z, cc.w};
-      for (int t = 0; t < 4; ++t)
-        for (int j = 0; j < kR; ++j)
-          a[j] = fma(static_cast<double>(vv[t]), static_cast<double>(C.X[static_cast<int64_t>(ci[t]) * kR + j]), a[j]);
+  if (C.ntiles) {
+    const int tile = blockIdx.x - first[c];
+    if (tile < C.ntiles) row = tile_mm64(C, 0, tile, C.Anc, a);
+  } else {
+    const int64_t q = static_cast<int64_t>(blockIdx.x - first[c]) * kBlock + threadIdx.x;
+    const int64_t sl = q >> C.cshift;
+    const int lane = static_cast<int>(q & (C.C - 1));
+    if (q < (C.nslices << C.cshift)) {
+      const int64_t beg = C.soff[sl] >> 2, end = C.soff[sl + 1] >> 2;
+      for (int64_t jj = beg + lane; jj < end; jj += C.C) {
+        const float4 v = C.val[jj];
+        const int4 cc = C.col[jj];
+        const float vv[4] = {v.x, v.y, v.z, v.w};
+        const int ci[4] = {cc.x, cc.y, cc.z, cc.w};
+        for (int t = 0; t < 4; ++t)
+          for (int j = 0; j < kR; ++j)
+            a[j] = fma(static_cast<double>(vv[t]), C.Anc[static_cast<int64_t>(ci[t]) * kR + j], a[j]);
+      }
+      row = slot_row_c(C.perm, C.nrows, q);
     }
-    row = slot_row_c(C.perm, C.nrows, q);
   }
   if (row >= 0) {
     for (int j = 0; j < kR; ++j) {
@@ -266,7 +326,7 @@ __global__ __launch_bounds__(kBlock) void k_check_fwd(const ChunkDev* __restrict
       C.r64[row * kR + j] = r;
       rr[j] = r * r;
       rb[j] = r * b;
-      l1[j] = fabs(static_cast<double>(C.X[row * kR + j]));
+      l1[j] = fabs(C.Anc[row * kR + j]);
     }
   }
   double out[kR];
@@ -283,28 +343,62 @@ __global__ __launch_bounds__(kBlock) void k_check_bwd(const ChunkDev* __restrict
   const int c = chunk_of(first, nchunks, blockIdx.x);
   const ChunkDev& C = ch[c];
   if (!C.act[kR]) return;  // every problem of this chunk has stopped
-  const int64_t q = static_cast<int64_t>(blockIdx.x - first[c]) * kBlock + threadIdx.x;
-  const int64_t sl = q >> C.cshift;
-  const int lane = static_cast<int>(q & (C.C - 1));
   double g[kR];
   for (int j = 0; j < kR; ++j) g[j] = 0.0;
-  if (q < (C.nslicesT << C.cshift)) {
-    const int64_t beg = C.soffT[sl] >> 2, end = C.soffT[sl + 1] >> 2;
-    for (int64_t jj = beg + lane; jj < end; jj += C.C) {
-      const float4 v = C.valT[jj];
-      const int4 cc = C.colT[jj];
-      const float vv[4] = {v.x, v.y, v.z, v.w};
-      const int ci[4] = {cc.x, cc.y, cc.z, cc.w};
-      for (int t = 0; t < 4; ++t)
-        for (int j = 0; j < kR; ++j) g[j] = fma(static_cast<double>(vv[t]), C.r64[static_cast<int64_t>(ci[t]) * kR + j], g[j]);
-    }
-    if (slot_row_c(C.permT, C.nrows, q) < 0)
+  if (C.ntiles) {
+    const int tile = blockIdx.x - first[c];
+    int row = -1;
+    if (tile < C.ntiles) row = tile_mm64(C, 1, tile, static_cast<const double*>(C.r64), g);
+    if (row < 0)
       for (int j = 0; j < kR; ++j) g[j] = 0.0;
+  } else {
+    const int64_t q = static_cast<int64_t>(blockIdx.x - first[c]) * kBlock + threadIdx.x;
+    const int64_t sl = q >> C.cshift;
+    const int lane = static_cast<int>(q & (C.C - 1));
+    if (q < (C.nslicesT << C.cshift)) {
+      const int64_t beg = C.soffT[sl] >> 2, end = C.soffT[sl + 1] >> 2;
+      for (int64_t jj = beg + lane; jj < end; jj += C.C) {
+        const float4 v = C.valT[jj];
+        const int4 cc = C.colT[jj];
+        const float vv[4] = {v.x, v.y, v.z, v.w};
+        const int ci[4] = {cc.x, cc.y, cc.z, cc.w};
+        for (int t = 0; t < 4; ++t)
+          for (int j = 0; j < kR; ++j)
+            g[j] = fma(static_cast<double>(vv[t]), C.r64[static_cast<int64_t>(ci[t]) * kR + j], g[j]);
+      }
+      if (slot_row_c(C.permT, C.nrows, q) < 0)
+        for (int j = 0; j < kR; ++j) g[j] = 0.0;
+    }
   }
   for (int j = 0; j < kR; ++j) g[j] = fabs(g[j]);
   double out[kR];
   block_reduce8(g, true, out);
   if (threadIdx.x < kR) part[(3 * kR + threadIdx.x) * nblocks + blockIdx.x] = out[threadIdx.x];
+}
+
+// Anchored iterate, elementwise over a chunk's [N][8] vectors.
+__global__ void k_anchor_init8(double* __restrict__ anc, float* __restrict__ cr, const float* __restrict__ x0,
+                               int64_t n8) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n8) return;
+  anc[i] = 0.0;
+  cr[i] = x0[i];
+}
+
+// anchor += X; Y -= X; X = 0 (the iterate and the extrapolated point keep their values as sums)
+__global__ void k_reanchor8(double* __restrict__ anc, float* __restrict__ x, float* __restrict__ y, int64_t n8) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n8) return;
+  const float d = x[i];
+  anc[i] += static_cast<double>(d);
+  y[i] -= d;
+  x[i] = 0.0f;
+}
+
+// c = -r64 = x0 - Theta_K anchor
+__global__ void k_anchor_rhs8(const double* __restrict__ r64, float* __restrict__ cr, int64_t n8) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n8) cr[i] = static_cast<float>(-r64[i]);
 }
 
 // One block per chunk and value: reduce that chunk's block range for one of
@@ -334,9 +428,14 @@ __global__ void k_interleave(const float* __restrict__ src, float* __restrict__ 
   if (i < N) dst[i * kR + j] = src ? src[i] : 0.0f;
 }
 
-__global__ void k_deinterleave(const float* __restrict__ src, float* __restrict__ dst, int64_t N, int j) {
+// Problem j's iterate: the anchor rounded to float32 (and as float64 when asked).
+__global__ void k_deinterleave(const double* __restrict__ src, float* __restrict__ dst, double* __restrict__ dst64,
+                               int64_t N, int j) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < N) dst[i] = src[i * kR + j];
+  if (i >= N) return;
+  const double v = src[i * kR + j];
+  dst[i] = static_cast<float>(v);
+  if (dst64) dst64[i] = v;
 }
 
 __global__ void k_set(int* p, int v) { *p = v; }
@@ -373,8 +472,8 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
   struct Host {
     wdb_theta* th;
     std::vector<int> idx;
-    DevBuf<float> X, Y, X0, Rr;
-    DevBuf<double> r64;
+    DevBuf<float> X, Y, X0, Rr, Cr;
+    DevBuf<double> r64, Anc;
     DevBuf<int> act;
     std::vector<int> act_host;  // flags of the eight slots, then "any slot active"
     int blocks_res, blocks_prox, blocks;
@@ -398,7 +497,9 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
       h.Y.alloc(N * kR);
       h.X0.alloc(N * kR);
       h.Rr.alloc(N * kR);
+      h.Cr.alloc(N * kR);
       h.r64.alloc(N * kR);
+      h.Anc.alloc(N * kR);
       h.act.alloc(kR + 1);
       h.act_host.assign(kR + 1, 0);
       h.blocks_res = static_cast<int>((th->A.nslices * th->A.C + kBlock - 1) / kBlock);
@@ -443,6 +544,8 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
     d.X = h.X.p;
     d.Y = h.Y.p;
     d.X0 = h.X0.p;
+    d.Cr = h.Cr.p;
+    d.Anc = h.Anc.p;
     d.Rr = h.Rr.p;
     d.pinv = pre ? th->pinv : nullptr;
     d.tau = static_cast<float>(tau);
@@ -490,6 +593,7 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
       }
     }
     act[kR] = h.idx.empty() ? 0 : 1;
+    hipLaunchKernelGGL(k_anchor_init8, dim3((N * kR + 255) / 256), dim3(256), 0, s, h.Anc.p, h.Cr.p, h.X0.p, N * kR);
     WDB_HIP(hipGetLastError());
     WDB_HIP(hipMemcpyAsync(h.act.p, act.data(), (kR + 1) * sizeof(int), hipMemcpyHostToDevice, s));
   }
@@ -534,11 +638,21 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
       done += step;
       const bool at_check = (c > 0 && done % c == 0) || done == total;
       if (!at_check) continue;
+      for (int ci = 0; ci < nch; ++ci) {
+        const int64_t n8 = chunks[ci].th->N * kR;
+        hipLaunchKernelGGL(k_reanchor8, dim3((n8 + 255) / 256), dim3(256), 0, s, chunks[ci].Anc.p, chunks[ci].X.p,
+                           chunks[ci].Y.p, n8);
+      }
       hipLaunchKernelGGL(k_check_fwd, dim3(static_cast<unsigned>(nblocks)), dim3(kBlock), 0, s, dch.p, dfirst.p, nch,
                          part.p, nblocks);
       hipLaunchKernelGGL(k_check_bwd, dim3(static_cast<unsigned>(nblocks)), dim3(kBlock), 0, s, dch.p, dfirst.p, nch,
                          part.p, nblocks);
       hipLaunchKernelGGL(k_check_reduce, dim3(nch * 4 * kR), dim3(kBlock), 0, s, dfirst.p, part.p, nblocks, red.p);
+      for (int ci = 0; ci < nch; ++ci) {
+        const int64_t n8 = chunks[ci].th->N * kR;
+        hipLaunchKernelGGL(k_anchor_rhs8, dim3((n8 + 255) / 256), dim3(256), 0, s, chunks[ci].r64.p,
+                           chunks[ci].Cr.p, n8);
+      }
       WDB_HIP(hipGetLastError());
       WDB_HIP(hipMemcpyAsync(hred.data(), red.p, hred.size() * sizeof(double), hipMemcpyDeviceToHost, s));
       WDB_HIP(hipStreamSynchronize(s));
@@ -592,7 +706,8 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
     Host& h = chunks[ci];
     const int64_t N = h.th->N;
     for (int j = 0; j < static_cast<int>(h.idx.size()); ++j)
-      hipLaunchKernelGGL(k_deinterleave, dim3((N + 255) / 256), dim3(256), 0, s, h.X.p, probs[h.idx[j]].x_out, N, j);
+      hipLaunchKernelGGL(k_deinterleave, dim3((N + 255) / 256), dim3(256), 0, s, h.Anc.p, probs[h.idx[j]].x_out,
+                         probs[h.idx[j]].x64_out, N, j);
   }
   WDB_HIP(hipGetLastError());
   WDB_HIP(hipStreamSynchronize(s));

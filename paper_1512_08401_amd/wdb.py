@@ -64,7 +64,8 @@ class SolveOpts(C.Structure):
 
 class ProblemC(C.Structure):
     _fields_ = [("theta", C.c_void_p), ("u", C.c_void_p), ("lam", C.c_float), ("x_init", C.c_void_p),
-                ("x_out", C.c_void_p), ("target_objective", C.c_double), ("x0", C.c_void_p)]
+                ("x_out", C.c_void_p), ("target_objective", C.c_double), ("x0", C.c_void_p),
+                ("x64_out", C.c_void_p)]
 
 
 class SolveInfo(C.Structure):
@@ -83,6 +84,10 @@ _SIGS = {
     "wdb_theta_info": [_vp, C.POINTER(ThetaDesc)],
     "wdb_theta_lipschitz": [_vp, _vp, _f64, _i32, _pd, C.POINTER(_i32)],
     "wdb_theta_lipschitz_lanczos": [_vp, _vp, _f64, _i32, _pd, C.POINTER(_i32), _pd],
+    "wdb_exact_create": [C.POINTER(PsfFieldC), _i32, _i32, _vp, C.POINTER(_vp)],
+    "wdb_exact_apply": [_vp, _i32, _vp, _vp, _vp],
+    "wdb_exact_lipschitz": [_vp, _vp, _f64, _i32, _pd, C.POINTER(_i32), _pd],
+    "wdb_exact_solve": [_vp, _vp, _f32, C.POINTER(SolveOpts), _vp, C.POINTER(SolveInfo)],
     "wdb_set_precond": [_vp, _i32, _f64, _vp, _f64, _i32],
     "wdb_get_precond": [_vp, _vp],
     "wdb_solve": [_vp, _vp, _f32, C.POINTER(SolveOpts), _vp, C.POINTER(SolveInfo)],
@@ -117,6 +122,8 @@ _lib.wdb_cnn_free.argtypes = [_vp]
 _lib.wdb_cnn_free.restype = None
 _lib.wdb_theta_free.argtypes = [_vp]
 _lib.wdb_theta_free.restype = None
+_lib.wdb_exact_free.argtypes = [_vp]
+_lib.wdb_exact_free.restype = None
 _lib.wdb_last_error.restype = C.c_char_p
 _lib.wdb_version.restype = C.c_char_p
 
@@ -404,6 +411,63 @@ class Theta:
         return u
 
 
+class Exact:
+    """Owns a wdb_exact handle: Alg. 1 with the exact-operator gradient (the baseline)."""
+
+    def __init__(self, field, wavelet: str, levels: int, stream=None):
+        self._h = C.c_void_p()
+        st, keep = _field_struct(field)
+        _check("wdb_exact_create", _lib.wdb_exact_create(C.byref(st), WAVELETS[wavelet], levels, _stream(stream),
+                                                         C.byref(self._h)))
+        self.n, self.N, self.levels = int(field.n), int(field.n) ** 2, levels
+
+    def __del__(self, _free=_lib.wdb_exact_free):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _free(h)
+            self._h = None
+
+    def apply(self, u, adjoint: bool = False, out=None, stream=None):
+        """H u (or H^* u) on an image (device float32, n*n)."""
+        torch = _torch()
+        y = torch.empty(self.N, device=u.device, dtype=torch.float32) if out is None else out
+        _check("wdb_exact_apply", _lib.wdb_exact_apply(self._h, 1 if adjoint else 0, _dev(u, self.N, "in"),
+                                                       _dev(y, self.N, "out"), _stream(stream)))
+        return y
+
+    def lipschitz(self, start=None, tol: float = 1e-12, max_steps: int = 2000) -> dict:
+        p, keep = _f64ptr(start)
+        L, res = C.c_double(0.0), C.c_double(0.0)
+        st = C.c_int32(0)
+        status = _lib.wdb_exact_lipschitz(self._h, p, tol, max_steps, C.byref(L), C.byref(st), C.byref(res))
+        if status != WDB_ERR_NOT_CONVERGED:
+            _check("wdb_exact_lipschitz", status)
+        return {"L": L.value, "theta": L.value - res.value, "resid": res.value, "steps": st.value,
+                "converged": status == 0}
+
+    def solve(self, u, lam: float, iters: int, check_every: int = 20, tol: float = 0.0, x_init=None, k0: int = 1,
+              trace_cap: int = 0, out=None, stream=None, target: float = 0.0, ista: bool = False):
+        """Alg. 1 with the exact gradient from a blurred image u (device n*n float32); returns (x, info)."""
+        torch = _torch()
+        x = torch.empty(self.N, device=u.device, dtype=torch.float32) if out is None else out
+        trace = np.zeros(3 * max(trace_cap, 1))
+        o = SolveOpts(int(iters), int(check_every), float(tol),
+                      None if x_init is None else _dev(x_init, self.N, "x_init").value, int(k0), 0,
+                      _stream(stream).value, trace.ctypes.data_as(_pd), int(trace_cap), 0, float(target),
+                      1 if ista else 0)
+        info = SolveInfo()
+        st = _lib.wdb_exact_solve(self._h, _dev(u, self.N, "u"), float(lam), C.byref(o), _dev(x, self.N, "x_out"),
+                                  C.byref(info))
+        res = {k: getattr(info, k) for k, _ in SolveInfo._fields_}
+        res["trace"] = trace[: 3 * min(info.checks, trace_cap)].reshape(-1, 3)
+        if st == WDB_ERR_NOT_CONVERGED:
+            res["converged"] = False
+            return x, res
+        _check("wdb_exact_solve", st)
+        res["converged"] = tol > 0 or target > 0
+        return x, res
+
+
 class Cnn:
     """Owns a wdb_cnn handle (warm-start network)."""
 
@@ -457,11 +521,13 @@ class Cnn:
 
 
 def solve_batched(problems, iters: int, check_every: int = 20, tol: float = 0.0, k0: int = 1,
-                  precond: bool = False, use_graph: bool = False, outs=None, stream=None, coeffs: bool = False):
+                  precond: bool = False, use_graph: bool = False, outs=None, stream=None, coeffs: bool = False,
+                  outs64=None):
     """Batched Alg. 1.  ``problems``: list of (theta, u, lam[, x_init[, target_objective]]).
     With ``coeffs`` the second entry of every problem is the wavelet-domain
-    data x0 = Psi^* u (N coefficients) instead of the image.
-    Returns (list of x tensors, list of info dicts)."""
+    data x0 = Psi^* u (N coefficients) instead of the image.  ``outs64``
+    (optional list of float64 device tensors) receive the float64 iterates the
+    last checks scored.  Returns (list of x tensors, list of info dicts)."""
     torch = _torch()
     n = len(problems)
     arr = (ProblemC * n)()
@@ -476,7 +542,8 @@ def solve_batched(problems, iters: int, check_every: int = 20, tol: float = 0.0,
         data = _dev(u, N, "x0" if coeffs else "u").value
         arr[i] = ProblemC(th.handle.value, None if coeffs else data, float(lam),
                           None if xi is None else _dev(xi, N, "x_init").value, _dev(x, N, "x_out").value, tgt,
-                          data if coeffs else None)
+                          data if coeffs else None,
+                          None if outs64 is None or outs64[i] is None else _dev64(outs64[i], N, "x64_out").value)
     o = SolveOpts(int(iters), int(check_every), float(tol), None, int(k0), 1 if precond else 0,
                   _stream(stream).value, None, 0, 1 if use_graph else 0, 0.0, 0)
     infos = (SolveInfo * n)()

@@ -939,11 +939,13 @@ def test_batched_matches_oracle_per_problem(W, p64, small32, tiled64):
         lam = float(np.float32(10.0 ** (-3.5 + 0.15 * i)))
         probs.append((th, dev(u0).reshape(-1), lam))
         oracle_inputs.append((A32, dwt.dwt2(u0.astype(np.float64), h, J), lam, start))
-    xs, infos = W.solve_batched(probs, 150, check_every=50, use_graph=True)
+    o64 = [torch.empty(p[0].N, device="cuda", dtype=torch.float64) for p in probs]
+    c64 = [torch.empty(p[0].N, device="cuda", dtype=torch.float64) for p in probs]
+    xs, infos = W.solve_batched(probs, 150, check_every=50, use_graph=True, outs64=o64)
     # the same problems with x0 handed over directly (the oracle's transform, in float32)
     x0s = [x0.astype(np.float32) for (_A, x0, _l, _s) in oracle_inputs]
     xc, infc = W.solve_batched([(p[0], dev(x0s[i]), p[2]) for i, p in enumerate(probs)], 150, check_every=50,
-                               use_graph=True, coeffs=True)
+                               use_graph=True, coeffs=True, outs64=c64)
     for i, (A32, x0, lam, start) in enumerate(oracle_inputs):
         L, _ = lipschitz.lipschitz(A32, start)
         xo, _, _ = fista.fista(A32, x0, lam, 1.0 / L, 150)
@@ -952,22 +954,33 @@ def test_batched_matches_oracle_per_problem(W, p64, small32, tiled64):
         # (about 1e-6 absolute per coefficient away from the float64 one): E moves
         # by ~1e-7 relative, but the dual scaling s = lam / ||A^T r||_inf magnifies
         # the shift of the relative gap to ~2.5e-4 on these problems.
-        E, _, _, rel = fista.duality_gap(A32, x0, lam, host(xs[i]))
+        E, _, _, rel = fista.duality_gap(A32, x0, lam, host(o64[i]))
         assert abs(infos[i]["objective"] - E) <= 1e-6 * E and abs(infos[i]["rel_gap"] - rel) <= 1e-3
+        assert np.array_equal(host(xs[i]), host(o64[i]).astype(np.float32).astype(np.float64))
         # From identical float32 coefficients the float64 checks agree to rounding.
         x0f = x0s[i].astype(np.float64)
         xof, _, _ = fista.fista(A32, x0f, lam, 1.0 / L, 150)
         _gate(A32, x0f, lam, host(xc[i]), xof, fista.objective(A32, x0f, lam, xof))
-        E, _, _, rel = fista.duality_gap(A32, x0f, lam, host(xc[i]))
+        E, _, _, rel = fista.duality_gap(A32, x0f, lam, host(c64[i]))
         assert abs(infc[i]["objective"] - E) <= 1e-9 * E and abs(infc[i]["rel_gap"] - rel) <= 1e-8
     # per-problem stop flags: every problem ends below the tolerance, frozen at its own check
-    xs, infos = W.solve_batched(probs, 3000, check_every=20, tol=2e-3)
+    xs, infos = W.solve_batched(probs, 3000, check_every=20, tol=2e-3, outs64=o64)
     assert all(r["converged"] for r in infos)
     its = [r["iters"] for r in infos]
     assert len(set(its)) > 1 and all(k % 20 == 0 for k in its)
     for i, (A32, x0, lam, start) in enumerate(oracle_inputs):
-        _, _, _, rel = fista.duality_gap(A32, x0, lam, host(xs[i]))
+        _, _, _, rel = fista.duality_gap(A32, x0, lam, host(o64[i]))
         assert rel <= 2e-3 * (1 + 1e-6)
+    # the anchored iterates certify gaps a float32 iterate cannot (its floor is
+    # near 1e-4 on these problems): every problem to 1e-5, from the same float32
+    # coefficients as the oracle, which recomputes each gap
+    xs, infos = W.solve_batched([(p[0], dev(x0s[i]), p[2]) for i, p in enumerate(probs)], 40000,
+                                check_every=100, tol=1e-5, outs64=c64, use_graph=True, coeffs=True)
+    print("batched to 1e-5:", [(r["iters"], r["rel_gap"]) for r in infos], flush=True)
+    assert all(r["converged"] for r in infos)
+    for i, (A32, x0, lam, start) in enumerate(oracle_inputs):
+        _, _, _, rel = fista.duality_gap(A32, x0s[i].astype(np.float64), lam, host(c64[i]))
+        assert rel <= 1e-5 + 1e-8
 
 
 # ---------------------------------------------------------------------------
