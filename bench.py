@@ -164,7 +164,7 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance measurement")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default kernel layout")
-    ap.add_argument("--form", default="plain", choices=["plain", "batched", "learned", "conv", "tuned"],
+    ap.add_argument("--form", default="plain", choices=["plain", "batched", "learned", "conv", "tuned", "exact"],
                     help="plain: the single-problem solve (default); batched / learned: the extension workloads")
     ap.add_argument("--train-images", type=int, default=4096)
     ap.add_argument("--heldout-images", type=int, default=512)
@@ -183,7 +183,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.form != "plain":
-        res = {"batched": run_batched, "learned": run_learned, "conv": run_conv, "tuned": run_tuned}[args.form](args)
+        res = {"batched": run_batched, "learned": run_learned, "conv": run_conv, "tuned": run_tuned,
+               "exact": run_exact}[args.form](args)
         print(json.dumps(res), flush=True)
         return
     dev = torch.device("cuda:0")
@@ -448,8 +449,8 @@ def run_batched(args):
             meta.append((gi, n))
         log(f"group {gi}: n={n} levels={g['levels']} nnz/px={g['nnz_per_px']} field={kind}")
     t_setup = time.perf_counter() - t0
-    # E* per problem: long batched run to a relative gap of 1e-9
-    xs, inf = wdb.solve_batched([p[:3] for p in probs], 20000, check_every=100, tol=1e-9, use_graph=True)
+    # E* per problem: long batched run to a relative gap of 1e-8
+    xs, inf = wdb.solve_batched([p[:3] for p in probs], 40000, check_every=100, tol=1e-8, use_graph=True)
     E0 = []
     for i, p in enumerate(probs):
         x0 = wdb.dwt(p[1], "db4", p[0].info()["levels"])
@@ -492,8 +493,11 @@ def run_batched(args):
 
 
 def run_learned(args):
-    """Warm start: train on solver-generated targets (4096 images), then time to
-    relative objective 1e-4 on 512 held-out images from the prediction vs from zero."""
+    """Warm start: train on solver-generated targets (4096 images solved to a
+    relative duality gap of 1e-6), then iterations and time to relative
+    objective 1e-4 / 1e-6 / 1e-8 on 512 held-out images from the prediction
+    (network inference included) vs from zero, located at iteration
+    resolution for 1e-4 (float64 check after every iteration)."""
     import torch
     import synth
     from paper_1512_08401_amd import wdb, warmstart
@@ -501,20 +505,23 @@ def run_learned(args):
     n, J, lam = wl.n, wl.levels, wl.lam
     field = wl.psf()
     th = wdb.build_theta(field, wl.wavelet, J, wl.nnz)
-    th.lipschitz(synth.power_start(n * n, wl.power_seed))
+    th.lipschitz_lanczos(synth.power_start(n * n, wl.power_seed))
     th.autotune(reps=5)
     ntrain = args.train_images
     t0 = time.perf_counter()
     U = [_observe(wdb, torch, field, n, 50000 + i, 150000 + i, wl.noise_sigma) for i in range(ntrain)]
     X0 = torch.stack([wdb.dwt(u, wl.wavelet, J) for u in U])
     T = torch.empty_like(X0)
+    tgt_iters, tgt_conv = [], []
     for b in range(0, ntrain, 512):
-        # targets: the solver's own iterate after a fixed long run (the duality
-        # gap converges far more slowly than the objective, so no gap test)
-        xs, _ = wdb.solve_batched([(th, u, lam) for u in U[b:b + 512]], args.target_iters,
-                                  check_every=args.target_iters, use_graph=True,
-                                  outs=[T[i] for i in range(b, min(ntrain, b + 512))])
-        log(f"targets {min(ntrain, b + 512)}/{ntrain}")
+        # targets: the solver's own solutions, to the stated relative duality gap
+        _, inf = wdb.solve_batched([(th, u, lam) for u in U[b:b + 512]], 40000, check_every=100,
+                                   tol=args.target_tol, use_graph=True,
+                                   outs=[T[i] for i in range(b, min(ntrain, b + 512))])
+        tgt_iters += [r["iters"] for r in inf]
+        tgt_conv += [r["converged"] for r in inf]
+        log(f"targets {min(ntrain, b + 512)}/{ntrain}: mean {np.mean(tgt_iters):.0f} iterations, "
+            f"converged {sum(tgt_conv)}/{len(tgt_conv)}")
     t_targets = time.perf_counter() - t0
     del U
     net = wdb.Cnn(n, J, 32, seed=1)
@@ -525,8 +532,7 @@ def run_learned(args):
     nh = args.heldout_images
     Uh = [_observe(wdb, torch, field, n, 60000 + i, 160000 + i, wl.noise_sigma) for i in range(nh)]
     X0h = torch.stack([wdb.dwt(u, wl.wavelet, J) for u in Uh])
-    xstar, star = wdb.solve_batched([(th, u, lam) for u in Uh], 4 * args.target_iters,
-                                    check_every=args.target_iters, use_graph=True)
+    xstar, star = wdb.solve_batched([(th, u, lam) for u in Uh], 40000, check_every=100, tol=1e-8, use_graph=True)
     E0 = 0.5 * (X0h.double() ** 2).sum(dim=1).cpu().numpy()
     Xs = torch.stack(xstar)
     pred_h = net.predict(X0h.reshape(-1).contiguous()).reshape(nh, -1)
@@ -535,18 +541,19 @@ def run_learned(args):
     log(f"held-out MSE to the solution: {mse}")
     ev = lambda: torch.cuda.Event(enable_timing=True)
     out = {}
-    for target in (1e-4, 1e-6, 1e-8):
+    for target, every in ((1e-4, 1), (1e-6, 5), (1e-8, 10)):
         tgt = [star[i]["objective"] + target * E0[i] for i in range(nh)]
-        out[f"{target:.0e}"] = {}
+        out[f"{target:.0e}"] = {"check_every": every}
         for form in ("zero", "warm"):
-            e0, e1 = ev(), ev()
-            torch.cuda.synchronize()
-            e0.record()
-            init = net.predict(X0h.reshape(-1).contiguous()).reshape(nh, -1) if form == "warm" else None
-            _, r = wdb.solve_batched([(th, Uh[i], lam, None if init is None else init[i].contiguous(), tgt[i])
-                                      for i in range(nh)], 4 * args.target_iters, check_every=10, use_graph=True)
-            e1.record()
-            torch.cuda.synchronize()
+            for rep in range(2):   # the first run captures the graph
+                e0, e1 = ev(), ev()
+                torch.cuda.synchronize()
+                e0.record()
+                init = net.predict(X0h.reshape(-1).contiguous()).reshape(nh, -1) if form == "warm" else None
+                _, r = wdb.solve_batched([(th, Uh[i], lam, None if init is None else init[i].contiguous(), tgt[i])
+                                          for i in range(nh)], 40000, check_every=every, use_graph=every > 1)
+                e1.record()
+                torch.cuda.synchronize()
             out[f"{target:.0e}"][form] = {"seconds": e0.elapsed_time(e1) / 1e3,
                                           "iters_mean": float(np.mean([x["iters"] for x in r])),
                                           "iters_median": float(np.median([x["iters"] for x in r]))}
@@ -557,8 +564,12 @@ def run_learned(args):
             "value": round(out["1e-04"]["warm"]["seconds"], 4), "unit": "s", "higher_is_better": False, "n_gpus": 1,
             "dtype": "f32 solver, bf16 network", "data": "synthetic",
             "config": {"workload": f"learned256: {n}x{n}, db4 {J} levels, isotropic 1..3 field, {wl.nnz} nnz, "
-                                   f"lambda {lam}; {ntrain} training / {nh} held-out images; {args.epochs} epochs"},
+                                   f"lambda {lam}; {ntrain} training images solved to relative gap "
+                                   f"{args.target_tol:g} / {nh} held-out images; {args.epochs} epochs"},
             "targets": out, "heldout_mse_to_solution": mse,
+            "training_targets": {"iters_mean": float(np.mean(tgt_iters)), "converged": int(sum(tgt_conv)),
+                                 "of": len(tgt_conv), "tol_rel_gap": args.target_tol},
+            "E_star_converged": int(sum(r["converged"] for r in star)),
             "train_loss_first_last": [hist[0], hist[-1]], "targets_s": round(t_targets, 2),
             "train_s": round(t_train, 2)}
 
@@ -652,6 +663,78 @@ def run_tuned(args):
             "value": res["tuned"]["fista_iters_per_s"], "unit": "iters/s", "higher_is_better": True, "n_gpus": 1,
             "dtype": "f32", "data": "synthetic",
             "config": {"workload": f"precision512 field and image, {wl.nnz} nnz, lambda {lam}"}, "forms": res}
+
+
+def run_exact(args):
+    """The exact-operator baseline against Theta_K on the 1024x1024 workload:
+    time per iteration of Alg. 1 with the exact gradient Psi^* H^* (H Psi y - u0)
+    and with Theta_K (the sparsification speed-up of the paper's Tables 1-2),
+    and iterations / seconds to relative objective 1e-4 and 1e-6 for each
+    problem against its own E* (float64 objective after every iteration)."""
+    import torch
+    import synth
+    from paper_1512_08401_amd import wdb
+    wl = synth.WORKLOADS[args.workload]
+    n, N = wl.n, wl.n * wl.n
+    field = wl.psf()
+    u0 = _observe(wdb, torch, field, n, wl.image_seed, wl.noise_seed, wl.noise_sigma)
+    th = wdb.build_theta(field, wl.wavelet, wl.levels, wl.nnz)
+    th.autotune(reps=5)
+    lt = th.lipschitz_lanczos(synth.power_start(N, wl.power_seed))
+    ex = wdb.Exact(field, wl.wavelet, wl.levels)
+    le = ex.lipschitz(synth.power_start(N, wl.power_seed))
+    log(f"L: Theta_K {lt}, exact {le}")
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    x = torch.empty(N, device="cuda")
+
+    def per_iter(solve, k1, k2):
+        ts = []
+        for k in (k1, k2):
+            solve(k)
+            e0, e1 = ev(), ev()
+            e0.record()
+            solve(k)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e3)
+        return (ts[1] - ts[0]) / (k2 - k1)
+
+    ex_us = per_iter(lambda k: ex.solve(u0, wl.lam, k, check_every=0, out=x), 10, 60)
+    th_us = per_iter(lambda k: th.solve(u0, wl.lam, k, check_every=0, out=x), 100, 1100)
+    log(f"per iteration: exact {ex_us:.1f} us, Theta_K {th_us:.1f} us")
+    x0 = wdb.dwt(u0, wl.wavelet, wl.levels)
+    E0 = 0.5 * float(torch.dot(x0.double(), x0.double()))
+    res = {}
+    for name, solve, long_iters in (("theta_k", lambda k, **kw: th.solve(u0, wl.lam, k, out=x, **kw), 20000),
+                                    ("exact", lambda k, **kw: ex.solve(u0, wl.lam, k, out=x, **kw), 3000)):
+        _, star = solve(long_iters, check_every=100, trace_cap=long_iters // 100)
+        Estar = float(star["trace"][:, 1].min())
+        cap = 300
+        _, tr = solve(cap, check_every=1, trace_cap=cap)
+        rho = (tr["trace"][:, 1] - Estar) / E0
+        r = {"E_star": Estar, "E_star_iters": long_iters, "best_rel_objective": float(rho.min())}
+        for target in (1e-4, 1e-6):
+            hit = np.nonzero(rho <= target)[0]
+            if hit.size == 0:
+                r[f"{target:.0e}"] = {"reached": False, "iters_checked": cap}
+                continue
+            k = int(tr["trace"][hit[0], 0])
+            solve(k, check_every=k)
+            e0, e1 = ev(), ev()
+            e0.record()
+            solve(k, check_every=k)
+            e1.record()
+            torch.cuda.synchronize()
+            r[f"{target:.0e}"] = {"reached": True, "iters": k, "seconds": e0.elapsed_time(e1) / 1e3}
+        res[name] = r
+        log(f"{name}: {r}")
+    return {"metric": "time per FISTA iteration, exact operator vs Theta_K (sparsification speed-up)",
+            "value": round(ex_us / th_us, 2), "unit": "x", "higher_is_better": True, "n_gpus": 1,
+            "dtype": "f32 (exact: float64 PSF weights)", "data": "synthetic",
+            "config": {"workload": f"{wl.name}: {n}x{n}, {wl.wavelet} {wl.levels} levels, {wl.field} field "
+                                   f"{wl.field_args}, Theta_K {wl.nnz} nnz, lambda {wl.lam}"},
+            "exact_iteration_us": round(ex_us, 1), "theta_k_iteration_us": round(th_us, 2),
+            "lipschitz": {"theta_k": lt, "exact": le}, "time_to_rel_objective": res}
 
 
 def th_x0(th, u0, wl, wdb):

@@ -22,7 +22,7 @@ LIB = os.path.join(HERE, "libwdb.so")
 ARCH = "gfx950"
 
 SOURCES = ["api.cpp", "filters.cpp", "dwt.hip", "psf.hip", "build.hip", "sparse.hip", "solve.hip",
-           "precond.hip", "quant.hip", "packed.hip", "weights.hip", "stencil.hip", "tiled.hip", "batch.hip", "cnn.hip", "autotune.hip"]
+           "precond.hip", "quant.hip", "packed.hip", "weights.hip", "stencil.hip", "tiled.hip", "batch.hip", "cnn.hip", "autotune.hip", "exact.hip"]
 
 
 def hipcc() -> str:

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -360,6 +361,11 @@ struct LanczosResult {
 // holds cycle + 1 vectors of N doubles).
 LanczosResult lanczos_max(wdb_theta* th, const double* start_host, const double* dinv_sqrt, double tol, int max_steps,
                           hipStream_t s, int cycle = 48);
+// The same for any symmetric positive semidefinite M of size N given by
+// apply(v, u): u = M v (device float64 vectors; the basis vector v must not be
+// written).
+LanczosResult lanczos_core(int64_t N, const std::function<void(const double*, double*)>& apply,
+                           const double* start_host, double tol, int max_steps, hipStream_t s, int cycle = 48);
 // Power iteration on D^-1/2 A^T A D^-1/2 (d = nullptr: identity), float64.
 double power_iteration(wdb_theta* th, const double* start_host, const double* dinv_sqrt,
                        double tol, int max_iters, int* iters_out, hipStream_t s, bool* converged_out = nullptr);

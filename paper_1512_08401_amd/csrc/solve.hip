@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <functional>
 #include <limits>
 #include <type_traits>
 
@@ -986,10 +987,8 @@ __global__ __launch_bounds__(kBlock) void k_inv_norm(const double* __restrict__ 
 
 }  // namespace
 
-LanczosResult lanczos_max(wdb_theta* th, const double* start_host, const double* dinv_sqrt, double tol, int max_steps,
-                          hipStream_t s, int cycle) {
-  ensure_workspace(th);
-  const int64_t N = th->N;
+LanczosResult lanczos_core(int64_t N, const std::function<void(const double*, double*)>& apply,
+                           const double* start_host, double tol, int max_steps, hipStream_t s, int cycle) {
   WDB_REQUIRE(max_steps >= 1, WDB_ERR_ARG, "max_steps must be >= 1");
   WDB_REQUIRE(tol >= 0 && std::isfinite(tol), WDB_ERR_ARG, "tol must be finite and >= 0");
   std::vector<double> v(N);
@@ -1011,9 +1010,8 @@ LanczosResult lanczos_max(wdb_theta* th, const double* start_host, const double*
   // the top Ritz vector: the basis holds k + 1 vectors of N doubles
   const int k = static_cast<int>(std::min<int64_t>(std::max(cycle, 2), N));
   DevBuf<double> V(static_cast<size_t>(k + 1) * N);
-  double* vd = th->ws_v64;
-  double* w = vd + N;
-  double* u = w + N;
+  DevBuf<double> ub(N);
+  double* u = ub.p;
   const int64_t nchunk = (N + kDotChunk - 1) / kDotChunk;
   DevBuf<double> dpart(static_cast<size_t>(k + 1) * nchunk);
   DevBuf<double> hh(2 * static_cast<size_t>(k + 1));
@@ -1022,33 +1020,14 @@ LanczosResult lanczos_max(wdb_theta* th, const double* start_host, const double*
   DevBuf<double> npart(nbv);
   DevBuf<double> scal(2);
   WDB_HIP(hipMemcpyAsync(V.p, v.data(), N * sizeof(double), hipMemcpyHostToDevice, s));
-  const SellView A = view(th->A), At = view(th->At);
-  const int G = check_group(th);
-  const int64_t nb = G > 0 ? csr_check_blocks(th, G) : partial_blocks(A, At);
-  double* part = th->ws_partial;
   LanczosResult res{0.0, 0.0, 0, false};
   double hstep[2], bn[2];
   while (res.steps < max_steps) {
-    // vd = D v_0 of this cycle
-    WDB_HIP(hipMemcpyAsync(vd, V.p, N * sizeof(double), hipMemcpyDeviceToDevice, s));
-    if (dinv_sqrt) hipLaunchKernelGGL(k_mul, vec_grid(N), dim3(kBlock), 0, s, vd, dinv_sqrt, N);
     std::vector<double> alpha, beta;
     TopRitz tr{0.0, 1.0, {}};
     bool done = false;
     for (int j = 0; j < k && res.steps < max_steps; ++j) {
-      // u = D A^T A D v_j (vd = D v_j)
-      if (G > 0) {
-        with_group(G, [&](auto g) {
-          constexpr int GG = decltype(g)::value;
-          hipLaunchKernelGGL(k_pi_fwd_csr<GG>, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, cview(th->cA),
-                             vd, w, part, nb);
-          hipLaunchKernelGGL(k_pi_bwd_csr<GG>, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s,
-                             cview(th->cAt), w, dinv_sqrt, u, part + nb, nb);
-        });
-      } else {
-        hipLaunchKernelGGL(k_pi_fwd, slot_grid(A), dim3(kBlock), 0, s, A, vd, w, part, nb);
-        hipLaunchKernelGGL(k_pi_bwd, slot_grid(At), dim3(kBlock), 0, s, At, w, dinv_sqrt, u, part + nb, nb);
-      }
+      apply(V.p + static_cast<int64_t>(j) * N, u);   // u = M v_j
       // two passes of classical Gram-Schmidt against v_0..v_j; the
       // coefficients of v_j add up to alpha_j
       const int m = j + 1;
@@ -1080,9 +1059,10 @@ LanczosResult lanczos_max(wdb_theta* th, const double* start_host, const double*
         break;
       }
       beta.push_back(bj);
-      if (j + 1 < k)   // v_{j+1} = u / beta_j, vd = D v_{j+1}
+      if (j + 1 < k)   // v_{j+1} = u / beta_j
         hipLaunchKernelGGL(k_basis_next, vec_grid(N), dim3(kBlock), 0, s, u, scal.p,
-                           V.p + static_cast<int64_t>(j + 1) * N, dinv_sqrt, vd, N);
+                           V.p + static_cast<int64_t>(j + 1) * N, static_cast<const double*>(nullptr),
+                           V.p + static_cast<int64_t>(j + 1) * N, N);
     }
     if (done || res.steps >= max_steps) break;
     // restart from the top Ritz vector V s (normalised)
@@ -1092,11 +1072,41 @@ LanczosResult lanczos_max(wdb_theta* th, const double* start_host, const double*
     hipLaunchKernelGGL(k_sq_partials, vec_grid(N), dim3(kBlock), 0, s, u, N, npart.p, nbv);
     hipLaunchKernelGGL(k_inv_norm, dim3(1), dim3(kBlock), 0, s, npart.p, nbv, scal.p);
     hipLaunchKernelGGL(k_basis_next, vec_grid(N), dim3(kBlock), 0, s, u, scal.p, V.p, static_cast<const double*>(nullptr),
-                       u, N);
+                       V.p, N);
     WDB_HIP(hipGetLastError());
   }
   WDB_HIP(hipStreamSynchronize(s));
   return res;
+}
+
+LanczosResult lanczos_max(wdb_theta* th, const double* start_host, const double* dinv_sqrt, double tol, int max_steps,
+                          hipStream_t s, int cycle) {
+  ensure_workspace(th);
+  const int64_t N = th->N;
+  double* vd = th->ws_v64;
+  double* w = vd + N;
+  const SellView A = view(th->A), At = view(th->At);
+  const int G = check_group(th);
+  const int64_t nb = G > 0 ? csr_check_blocks(th, G) : partial_blocks(A, At);
+  double* part = th->ws_partial;
+  // u = D A^T A D v
+  auto apply = [&](const double* v, double* u) {
+    WDB_HIP(hipMemcpyAsync(vd, v, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (dinv_sqrt) hipLaunchKernelGGL(k_mul, vec_grid(N), dim3(kBlock), 0, s, vd, dinv_sqrt, N);
+    if (G > 0) {
+      with_group(G, [&](auto g) {
+        constexpr int GG = decltype(g)::value;
+        hipLaunchKernelGGL(k_pi_fwd_csr<GG>, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, cview(th->cA), vd,
+                           w, part, nb);
+        hipLaunchKernelGGL(k_pi_bwd_csr<GG>, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, cview(th->cAt), w,
+                           dinv_sqrt, u, part + nb, nb);
+      });
+    } else {
+      hipLaunchKernelGGL(k_pi_fwd, slot_grid(A), dim3(kBlock), 0, s, A, vd, w, part, nb);
+      hipLaunchKernelGGL(k_pi_bwd, slot_grid(At), dim3(kBlock), 0, s, At, w, dinv_sqrt, u, part + nb, nb);
+    }
+  };
+  return lanczos_core(N, apply, start_host, tol, max_steps, s, cycle);
 }
 
 namespace {
