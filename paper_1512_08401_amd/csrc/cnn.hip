@@ -77,6 +77,76 @@ __global__ __launch_bounds__(kBlk) void k_conv_fwd(const float* __restrict__ in,
   for (int o = 0; o < CO; ++o) ob[o * per] = acc[o] + (rb ? rb[o * per] : 0.0f);
 }
 
+// The hidden 32 -> 32 convolution on the matrix cores (f32 32x32x2 MFMA: the
+// float32 products and float32 sums of the vector kernel, in another order).
+// A block of 4 wavefronts takes TR x TC positions of one image (TC = min(s,
+// 32), TR = 128 / TC, s >= 16); the input tile with a one-pixel circular
+// halo (ReLU applied on load if in_relu) and the weights as [k = d * 32 + c][o]
+// are staged in LDS; a wavefront accumulates the 32 outputs of its 32
+// positions over k = 288 in 144 steps: D[o][p] += W[o][k] X[k][p], lane l
+// giving W[l mod 32][k] and X[k][p = l mod 32] for the step's two k values
+// (k = step * 2 + l / 32), and holding D[8 (j / 4) + 4 (l / 32) + j mod 4][l mod 32]
+// in its accumulator j.  FLIP: the data gradient of the same layer, which is
+// the convolution of g with W'[c][o][d] = W[o][c][8 - d], masked by a > 0.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+constexpr int kMP = 33;                    // LDS floats per staged position (32 channels; odd stride)
+constexpr int kMaxTilePos = 6 * 34;        // (TR + 2) (TC + 2) for TC = 32 (204 >= 10 * 18 for TC = 16)
+
+template <bool FLIP>
+__global__ __launch_bounds__(256) void k_conv32_mfma(const float* __restrict__ in, int64_t in_bs, int in_relu, int s,
+                                                     const uint16_t* __restrict__ w, const uint16_t* __restrict__ bias,
+                                                     float* __restrict__ out, int64_t out_bs,
+                                                     const float* __restrict__ resid, int64_t res_bs,
+                                                     const float* __restrict__ mask, int64_t m_bs) {
+  __shared__ float sx[kMaxTilePos * kMP];
+  __shared__ float swt[9 * kF * kF];
+  const int TC = min(s, 32), TR = 128 / TC;
+  const int tiles_x = s / TC;
+  const int b = blockIdx.y;
+  const int ty0 = (static_cast<int>(blockIdx.x) / tiles_x) * TR, tx0 = (static_cast<int>(blockIdx.x) % tiles_x) * TC;
+  const int64_t per = static_cast<int64_t>(s) * s;
+  for (int e = threadIdx.x; e < 9 * kF * kF; e += 256) {
+    const int k = e >> 5, o = e & 31, d = k >> 5, c = k & 31;
+    swt[e] = bf2f(FLIP ? w[(c * kF + o) * 9 + (8 - d)] : w[(o * kF + c) * 9 + d]);
+  }
+  const int W2 = TC + 2, H2 = TR + 2, P2 = W2 * H2;
+  const float* __restrict__ inb = in + b * in_bs;
+  for (int e = threadIdx.x; e < kF * P2; e += 256) {
+    const int c = e / P2, q = e - c * P2;
+    const int yy = q / W2, xx = q - yy * W2;
+    const int gy = (ty0 + yy - 1) & (s - 1), gx = (tx0 + xx - 1) & (s - 1);
+    float v = inb[c * per + static_cast<int64_t>(gy) * s + gx];
+    if (in_relu) v = fmaxf(v, 0.0f);
+    sx[q * kMP + c] = v;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int pl = wv * 32 + (lane & 31);
+  const int ty = pl / TC, tx = pl - ty * TC;
+  const int kh = lane >> 5;
+  f32x16 acc = {};
+  for (int d = 0; d < 9; ++d) {
+    const float* xr = sx + ((ty + d / 3) * W2 + tx + d % 3) * kMP + kh;
+    const float* wr = swt + (d * kF + kh) * kF + (lane & 31);
+#pragma unroll
+    for (int cb = 0; cb < kF / 2; ++cb)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(wr[2 * cb * kF], xr[2 * cb], acc, 0, 0, 0);
+  }
+  const int64_t gpos = static_cast<int64_t>(ty0 + ty) * s + tx0 + tx;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int o = 8 * (j >> 2) + 4 * kh + (j & 3);
+    float v = acc[j];
+    if (FLIP) {
+      if (mask && !(mask[b * m_bs + o * per + gpos] > 0.0f)) v = 0.0f;
+    } else {
+      v += bf2f(bias[o]);
+      if (resid) v += resid[b * res_bs + o * per + gpos];
+    }
+    out[b * out_bs + o * per + gpos] = v;
+  }
+}
+
 // gin[b, c] = sum_{o, d} W[o, c, d] g[b, o, shifted]  (times [a_in > 0] if mask given).
 template <int CO, int CI>
 __global__ __launch_bounds__(kBlk) void k_conv_bwd_data(const float* __restrict__ g, int64_t g_bs, int s, int B,
@@ -176,6 +246,86 @@ __global__ __launch_bounds__(kBlk) void k_conv_bwd_w(const float* __restrict__ a
     const int idx = threadIdx.x + k * kBlk;
     if (idx < NT) partial[static_cast<int64_t>(blockIdx.x) * NT + idx] = acc[k];
   }
+}
+
+// Weight gradient of the hidden 32 -> 32 layer on the matrix cores: per block
+// the partial sums over the 128-position tiles it takes (tile t = blockIdx.x,
+// + gridDim.x, ...), in the partial layout of k_conv_bwd_w.  Wavefront w of a
+// tile contracts its 32 positions two at a time: for offset d the product
+// D_d[o][c] += G[o][p] A_d[p][c], lane l giving G[l mod 32][p] = g[p][o] and
+// A_d[p][l mod 32] = act[p + off(d)][c] for p = 2 step + l / 32.  The four
+// wavefronts' sums are added in LDS in a fixed order, so the result does not
+// depend on scheduling.
+constexpr int kTileMax = 128;
+constexpr int kRedFloats = 9 * kF * kF + kF;
+constexpr int kWStage = kMaxTilePos * kMP + kTileMax * kMP;
+static_assert(kWStage >= kRedFloats, "the reduction buffer reuses the staging buffer");
+
+__global__ __launch_bounds__(256) void k_conv32_bwd_w_mfma(const float* __restrict__ act, int64_t a_bs,
+                                                           int act_relu, const float* __restrict__ g, int64_t g_bs,
+                                                           int s, int ntiles, float* __restrict__ partial) {
+  __shared__ float buf[kWStage];
+  float* sx = buf;                          // act tile with halo, [pos][c]
+  float* sg = buf + kMaxTilePos * kMP;      // g tile, [pos][o]
+  const int TC = min(s, 32), TR = 128 / TC;
+  const int tiles_x = s / TC, per_img = (s / TR) * tiles_x;
+  const int W2 = TC + 2, H2 = TR + 2, P2 = W2 * H2;
+  const int64_t per = static_cast<int64_t>(s) * s;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, kh = lane >> 5, l32 = lane & 31;
+  f32x16 acc[9];
+#pragma unroll
+  for (int d = 0; d < 9; ++d) acc[d] = f32x16{};
+  float bsum = 0.0f;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int b = t / per_img, ti = t - b * per_img;
+    const int ty0 = (ti / tiles_x) * TR, tx0 = (ti % tiles_x) * TC;
+    const float* __restrict__ ab = act + b * a_bs;
+    for (int e = threadIdx.x; e < kF * P2; e += 256) {
+      const int c = e / P2, q = e - c * P2;
+      const int yy = q / W2, xx = q - yy * W2;
+      const int gy = (ty0 + yy - 1) & (s - 1), gx = (tx0 + xx - 1) & (s - 1);
+      float v = ab[c * per + static_cast<int64_t>(gy) * s + gx];
+      if (act_relu) v = fmaxf(v, 0.0f);
+      sx[q * kMP + c] = v;
+    }
+    const float* __restrict__ gb = g + b * g_bs;
+    for (int e = threadIdx.x; e < kF * kTileMax; e += 256) {
+      const int o = e >> 7, q = e & (kTileMax - 1);
+      const int yy = q / TC, xx = q - yy * TC;
+      sg[q * kMP + o] = gb[o * per + static_cast<int64_t>(ty0 + yy) * s + tx0 + xx];
+    }
+    __syncthreads();
+    for (int st = 0; st < 16; ++st) {
+      const int q = wv * 32 + 2 * st + kh;
+      const int ty = q / TC, tx = q - ty * TC;
+      const float a = sg[q * kMP + l32];
+#pragma unroll
+      for (int d = 0; d < 9; ++d)
+        acc[d] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, sx[((ty + d / 3) * W2 + tx + d % 3) * kMP + l32], acc[d],
+                                                      0, 0, 0);
+    }
+    if (kh == 0)
+      for (int p = 0; p < 32; ++p) bsum += sg[(wv * 32 + p) * kMP + l32];
+    __syncthreads();
+  }
+  // fixed-order sum of the four wavefronts: wave 0 stores, waves 1..3 add in turn
+  float* red = buf;
+  for (int w = 0; w < 4; ++w) {
+    if (wv == w) {
+#pragma unroll
+      for (int d = 0; d < 9; ++d)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const int o = 8 * (j >> 2) + 4 * kh + (j & 3);
+          const int idx = o * (kF * 9) + l32 * 9 + d;
+          red[idx] = (w == 0 ? 0.0f : red[idx]) + acc[d][j];
+        }
+      if (kh == 0) red[9 * kF * kF + l32] = (w == 0 ? 0.0f : red[9 * kF * kF + l32]) + bsum;
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < kRedFloats; e += 256)
+    partial[static_cast<int64_t>(blockIdx.x) * kRedFloats + e] = red[e];
 }
 
 __global__ void k_sum_partials(const float* __restrict__ partial, int nblocks, int NT, float* __restrict__ out) {
@@ -294,9 +444,19 @@ void cnn_ensure(wdb_cnn* c, int B) {
   c->bcap = B;
 }
 
+// Grid of the matrix-core kernel: the block tiles of an image by the batch.
+dim3 mfma_grid(int s, int B) { return dim3(static_cast<unsigned>((s * s) / 128), static_cast<unsigned>(B)); }
+
 template <int CI, int CO>
 void conv_fwd(const float* in, int64_t in_bs, int in_relu, int s, int B, const uint16_t* w, const uint16_t* b,
               float* out, int64_t out_bs, const float* resid, int64_t res_bs, hipStream_t st) {
+  if constexpr (CI == kF && CO == kF) {
+    if (s >= 16) {   // the hidden layer on the matrix cores
+      hipLaunchKernelGGL(k_conv32_mfma<false>, mfma_grid(s, B), dim3(256), 0, st, in, in_bs, in_relu, s, w, b, out,
+                         out_bs, resid, res_bs, static_cast<const float*>(nullptr), int64_t{0});
+      return;
+    }
+  }
   hipLaunchKernelGGL((k_conv_fwd<CI, CO>), grid_for(static_cast<int64_t>(B) * s * s), dim3(kBlk), 0, st, in, in_bs,
                      in_relu, s, B, w, b, out, out_bs, resid, res_bs);
 }
@@ -304,6 +464,14 @@ void conv_fwd(const float* in, int64_t in_bs, int in_relu, int s, int B, const u
 template <int CO, int CI>
 void conv_bwd_data(const float* g, int64_t g_bs, int s, int B, const uint16_t* w, const float* mask, int64_t m_bs,
                    float* gin, int64_t gin_bs, hipStream_t st) {
+  if constexpr (CI == kF && CO == kF) {
+    if (s >= 16) {
+      hipLaunchKernelGGL(k_conv32_mfma<true>, mfma_grid(s, B), dim3(256), 0, st, g, g_bs, 0, s, w,
+                         static_cast<const uint16_t*>(nullptr), gin, gin_bs, static_cast<const float*>(nullptr),
+                         int64_t{0}, mask, m_bs);
+      return;
+    }
+  }
   hipLaunchKernelGGL((k_conv_bwd_data<CO, CI>), grid_for(static_cast<int64_t>(B) * s * s), dim3(kBlk), 0, st, g,
                      g_bs, s, B, w, mask, m_bs, gin, gin_bs);
 }
@@ -312,10 +480,20 @@ template <int CI, int CO>
 void conv_bwd_w(const float* act, int64_t a_bs, int act_relu, const float* g, int64_t g_bs, int s, int B,
                 float* partial, float* out, hipStream_t st) {
   const int64_t T = static_cast<int64_t>(B) * s * s;
+  const int NT = CO * CI * 9 + CO;
+  if constexpr (CI == kF && CO == kF) {
+    if (s >= 16) {   // the hidden layer on the matrix cores
+      const int ntiles = static_cast<int>(T / kTileMax);
+      const int nb = std::min(kWGridMax, ntiles);
+      hipLaunchKernelGGL(k_conv32_bwd_w_mfma, dim3(nb), dim3(256), 0, st, act, a_bs, act_relu, g, g_bs, s, ntiles,
+                         partial);
+      hipLaunchKernelGGL(k_sum_partials, dim3((NT + 255) / 256), dim3(256), 0, st, partial, nb, NT, out);
+      return;
+    }
+  }
   const int nb = static_cast<int>(std::min<int64_t>(kWGridMax, (T + kP - 1) / kP));
   hipLaunchKernelGGL((k_conv_bwd_w<CI, CO>), dim3(nb), dim3(kBlk), 0, st, act, a_bs, act_relu, g, g_bs, s, B,
                      partial);
-  const int NT = CO * CI * 9 + CO;
   hipLaunchKernelGGL(k_sum_partials, dim3((NT + 255) / 256), dim3(256), 0, st, partial, nb, NT, out);
 }
 
