@@ -549,14 +549,12 @@ def solve_batched(problems, iters: int, check_every: int = 20, tol: float = 0.0,
     infos = (SolveInfo * n)()
     st = _lib.wdb_solve_batched(n, arr, C.byref(o), infos)
     res = [{k: getattr(inf, k) for k, _ in SolveInfo._fields_} for inf in infos]
-    if st == WDB_ERR_NOT_CONVERGED:
-        for r in res:
-            r["converged"] = False
-        return xs, res
-    _check("wdb_solve_batched", st)
-    stopping = tol > 0 or any(len(p) > 4 and p[4] > 0 for p in problems)
-    for r in res:
-        r["converged"] = stopping
+    if st != WDB_ERR_NOT_CONVERGED:
+        _check("wdb_solve_batched", st)
+    # per problem: met its own stopping test (tolerance, or its objective target)
+    for p, r in zip(problems, res):
+        tgt = float(p[4]) if len(p) > 4 else 0.0
+        r["converged"] = (tol > 0 and r["rel_gap"] <= tol) or (tgt > 0 and r["objective"] <= tgt)
     return xs, res
 
 
