@@ -77,60 +77,97 @@ __global__ __launch_bounds__(kBlk) void k_conv_fwd(const float* __restrict__ in,
   for (int o = 0; o < CO; ++o) ob[o * per] = acc[o] + (rb ? rb[o * per] : 0.0f);
 }
 
-// The hidden 32 -> 32 convolution on the matrix cores (f32 32x32x2 MFMA: the
-// float32 products and float32 sums of the vector kernel, in another order).
-// A block of 4 wavefronts takes TR x TC positions of one image (TC = min(s,
-// 32), TR = 128 / TC, s >= 16); the input tile with a one-pixel circular
-// halo (ReLU applied on load if in_relu) and the weights as [k = d * 32 + c][o]
-// are staged in LDS; a wavefront accumulates the 32 outputs of its 32
-// positions over k = 288 in 144 steps: D[o][p] += W[o][k] X[k][p], lane l
-// giving W[l mod 32][k] and X[k][p = l mod 32] for the step's two k values
-// (k = step * 2 + l / 32), and holding D[8 (j / 4) + 4 (l / 32) + j mod 4][l mod 32]
-// in its accumulator j.  FLIP: the data gradient of the same layer, which is
-// the convolution of g with W'[c][o][d] = W[o][c][8 - d], masked by a > 0.
+// Convolutions into the 32 hidden channels on the matrix cores (f32 32x32x2
+// MFMA: the float32 products and float32 sums of the vector kernels, in
+// another order), for CI = 1, 3 or 32 input channels.  A block of 4
+// wavefronts takes TR x TC positions of one image (TC = min(s, 32), TR = 128 /
+// TC, s >= 16); the input tile with a one-pixel circular halo (ReLU applied on
+// load if in_relu) and the weights as [k = d * CI + c][o] (tap d, channel c;
+// K = 9 CI rows, padded to an even count with a zero row) are staged in LDS;
+// a wavefront accumulates the 32 outputs of its 32 positions over k, two k a
+// step: D[o][p] += W[o][k] X[k][p], lane l giving W[l mod 32][k] and
+// X[k][p = l mod 32] for k = 2 step + l / 32, and holding
+// D[8 (j / 4) + 4 (l / 32) + j mod 4][l mod 32] in its accumulator j.
+// FLIP: the data gradient of a layer with 32 input channels and CI outputs,
+// which is the convolution of g with W'[c][o][d] = W[c][o][8 - d] (W in the
+// layer's own [out][in][tap] layout), masked by a > 0.
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kMP = 33;                    // LDS floats per staged position (32 channels; odd stride)
 constexpr int kMaxTilePos = 6 * 34;        // (TR + 2) (TC + 2) for TC = 32 (204 >= 10 * 18 for TC = 16)
+constexpr int kTileMax = 128;              // positions per block tile
 
-template <bool FLIP>
-__global__ __launch_bounds__(256) void k_conv32_mfma(const float* __restrict__ in, int64_t in_bs, int in_relu, int s,
-                                                     const uint16_t* __restrict__ w, const uint16_t* __restrict__ bias,
-                                                     float* __restrict__ out, int64_t out_bs,
-                                                     const float* __restrict__ resid, int64_t res_bs,
-                                                     const float* __restrict__ mask, int64_t m_bs) {
-  __shared__ float sx[kMaxTilePos * kMP];
-  __shared__ float swt[9 * kF * kF];
-  const int TC = min(s, 32), TR = 128 / TC;
-  const int tiles_x = s / TC;
-  const int b = blockIdx.y;
-  const int ty0 = (static_cast<int>(blockIdx.x) / tiles_x) * TR, tx0 = (static_cast<int>(blockIdx.x) % tiles_x) * TC;
-  const int64_t per = static_cast<int64_t>(s) * s;
-  for (int e = threadIdx.x; e < 9 * kF * kF; e += 256) {
-    const int k = e >> 5, o = e & 31, d = k >> 5, c = k & 31;
-    swt[e] = bf2f(FLIP ? w[(c * kF + o) * 9 + (8 - d)] : w[(o * kF + c) * 9 + d]);
-  }
-  const int W2 = TC + 2, H2 = TR + 2, P2 = W2 * H2;
-  const float* __restrict__ inb = in + b * in_bs;
-  for (int e = threadIdx.x; e < kF * P2; e += 256) {
-    const int c = e / P2, q = e - c * P2;
-    const int yy = q / W2, xx = q - yy * W2;
+struct TileGeo {
+  int TC, TR, W2, P2;
+};
+__device__ __forceinline__ TileGeo tile_geo(int s) {
+  const int TC = min(s, 32), TR = kTileMax / TC;
+  return TileGeo{TC, TR, TC + 2, (TC + 2) * (TR + 2)};
+}
+
+// Stage channels [0, CH) of the tile at (ty0, tx0) with its circular halo as
+// dst[q * stride + c], q = halo row * W2 + halo column.
+template <int CH>
+__device__ __forceinline__ void stage_halo(const float* __restrict__ src, int64_t per, int s, const TileGeo& tg,
+                                           int ty0, int tx0, int relu, float* __restrict__ dst, int stride) {
+  for (int e = threadIdx.x; e < CH * tg.P2; e += 256) {
+    const int c = e / tg.P2, q = e - c * tg.P2;
+    const int yy = q / tg.W2, xx = q - yy * tg.W2;
     const int gy = (ty0 + yy - 1) & (s - 1), gx = (tx0 + xx - 1) & (s - 1);
-    float v = inb[c * per + static_cast<int64_t>(gy) * s + gx];
-    if (in_relu) v = fmaxf(v, 0.0f);
-    sx[q * kMP + c] = v;
+    float v = src[c * per + static_cast<int64_t>(gy) * s + gx];
+    if (relu) v = fmaxf(v, 0.0f);
+    dst[q * stride + c] = v;
   }
+}
+
+template <int CI, bool FLIP>
+__global__ __launch_bounds__(256) void k_conv_mfma_in(const float* __restrict__ in, int64_t in_bs, int in_relu, int s,
+                                                      const uint16_t* __restrict__ w,
+                                                      const uint16_t* __restrict__ bias, float* __restrict__ out,
+                                                      int64_t out_bs, const float* __restrict__ resid,
+                                                      int64_t res_bs, const float* __restrict__ mask, int64_t m_bs) {
+  constexpr int K = 9 * CI, KP = K + (K & 1);
+  constexpr int XS = CI == kF ? kMP : CI;   // LDS floats per staged position
+  __shared__ float sx[kMaxTilePos * XS];
+  __shared__ float swt[KP * kF];
+  const TileGeo tg = tile_geo(s);
+  const int tiles_x = s / tg.TC;
+  const int b = blockIdx.y;
+  const int ty0 = (static_cast<int>(blockIdx.x) / tiles_x) * tg.TR;
+  const int tx0 = (static_cast<int>(blockIdx.x) % tiles_x) * tg.TC;
+  const int64_t per = static_cast<int64_t>(s) * s;
+  for (int e = threadIdx.x; e < KP * kF; e += 256) {
+    const int k = e >> 5, o = e & 31;
+    float v = 0.0f;
+    if (k < K) {
+      const int d = k / CI, c = k - d * CI;
+      v = bf2f(FLIP ? w[(c * kF + o) * 9 + (8 - d)] : w[(o * CI + c) * 9 + d]);
+    }
+    swt[e] = v;
+  }
+  stage_halo<CI>(in + b * in_bs, per, s, tg, ty0, tx0, in_relu, sx, XS);
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int pl = wv * 32 + (lane & 31);
-  const int ty = pl / TC, tx = pl - ty * TC;
+  const int ty = pl / tg.TC, tx = pl - ty * tg.TC;
   const int kh = lane >> 5;
   f32x16 acc = {};
-  for (int d = 0; d < 9; ++d) {
-    const float* xr = sx + ((ty + d / 3) * W2 + tx + d % 3) * kMP + kh;
-    const float* wr = swt + (d * kF + kh) * kF + (lane & 31);
+  if constexpr (CI == kF) {
+    for (int d = 0; d < 9; ++d) {
+      const float* xr = sx + ((ty + d / 3) * tg.W2 + tx + d % 3) * XS + kh;
+      const float* wr = swt + (d * kF + kh) * kF + (lane & 31);
 #pragma unroll
-    for (int cb = 0; cb < kF / 2; ++cb)
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(wr[2 * cb * kF], xr[2 * cb], acc, 0, 0, 0);
+      for (int cb = 0; cb < kF / 2; ++cb)
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(wr[2 * cb * kF], xr[2 * cb], acc, 0, 0, 0);
+    }
+  } else {
+#pragma unroll
+    for (int st = 0; st < KP / 2; ++st) {
+      const int k = 2 * st + kh;
+      const int dk = k / CI, c = k - dk * CI;   // k = K (the zero row) reads tap 8, channel 0
+      const int d = min(dk, 8);
+      const float xv = sx[((ty + d / 3) * tg.W2 + tx + d % 3) * XS + c];
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(swt[k * kF + (lane & 31)], xv, acc, 0, 0, 0);
+    }
   }
   const int64_t gpos = static_cast<int64_t>(ty0 + ty) * s + tx0 + tx;
 #pragma unroll
@@ -143,6 +180,64 @@ __global__ __launch_bounds__(256) void k_conv32_mfma(const float* __restrict__ i
       v += bf2f(bias[o]);
       if (resid) v += resid[b * res_bs + o * per + gpos];
     }
+    out[b * out_bs + o * per + gpos] = v;
+  }
+}
+
+// The last convolution of a stack (32 -> CO channels, CO = 1 or 3) on the
+// matrix cores: first the per-tap products T[m = 9 o + d][q] = sum_c W[o][c][d]
+// x[q][c] at every position q of the tile and its halo (an MFMA over the 32
+// channels, rows m >= 9 CO zero), then out[o][p] = b[o] + resid[o][p] +
+// sum_d T[9 o + d][p + off(d)] on the vector units.
+template <int CO>
+__global__ __launch_bounds__(256) void k_conv_mfma_out(const float* __restrict__ in, int64_t in_bs, int in_relu,
+                                                       int s, const uint16_t* __restrict__ w,
+                                                       const uint16_t* __restrict__ bias, float* __restrict__ out,
+                                                       int64_t out_bs, const float* __restrict__ resid,
+                                                       int64_t res_bs) {
+  constexpr int M = 9 * CO;   // rows used of the 32 (and the LDS stride of T: odd)
+  __shared__ float sx[kMaxTilePos * kMP];
+  __shared__ float sT[8 * 32 * M];
+  __shared__ float swt[kF * kF];
+  const TileGeo tg = tile_geo(s);
+  const int tiles_x = s / tg.TC;
+  const int b = blockIdx.y;
+  const int ty0 = (static_cast<int>(blockIdx.x) / tiles_x) * tg.TR;
+  const int tx0 = (static_cast<int>(blockIdx.x) % tiles_x) * tg.TC;
+  const int64_t per = static_cast<int64_t>(s) * s;
+  for (int e = threadIdx.x; e < kF * kF; e += 256) {
+    const int c = e >> 5, m = e & 31;
+    swt[e] = m < M ? bf2f(w[((m / 9) * kF + c) * 9 + m % 9]) : 0.0f;
+  }
+  stage_halo<kF>(in + b * in_bs, per, s, tg, ty0, tx0, in_relu, sx, kMP);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, kh = lane >> 5, l32 = lane & 31;
+  for (int gq = wv; gq * 32 < tg.P2; gq += 4) {   // groups of 32 halo positions, wave-uniform bound
+    const int q = gq * 32 + l32;
+    const int qr = min(q, tg.P2 - 1);
+    f32x16 acc = {};
+#pragma unroll
+    for (int cb = 0; cb < kF / 2; ++cb)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(swt[(2 * cb + kh) * kF + l32], sx[qr * kMP + 2 * cb + kh], acc, 0,
+                                                 0, 0);
+    if (q < tg.P2) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int m = 8 * (j >> 2) + 4 * kh + (j & 3);
+        if (m < M) sT[q * M + m] = acc[j];
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kTileMax * CO; e += 256) {
+    const int p = e & (kTileMax - 1), o = e / kTileMax;
+    const int ty = p / tg.TC, tx = p - ty * tg.TC;
+    float v = 0.0f;
+#pragma unroll
+    for (int d = 0; d < 9; ++d) v += sT[((ty + d / 3) * tg.W2 + tx + d % 3) * M + o * 9 + d];
+    v += bf2f(bias[o]);
+    const int64_t gpos = static_cast<int64_t>(ty0 + ty) * s + tx0 + tx;
+    if (resid) v += resid[b * res_bs + o * per + gpos];
     out[b * out_bs + o * per + gpos] = v;
   }
 }
@@ -256,7 +351,6 @@ __global__ __launch_bounds__(kBlk) void k_conv_bwd_w(const float* __restrict__ a
 // A_d[p][l mod 32] = act[p + off(d)][c] for p = 2 step + l / 32.  The four
 // wavefronts' sums are added in LDS in a fixed order, so the result does not
 // depend on scheduling.
-constexpr int kTileMax = 128;
 constexpr int kRedFloats = 9 * kF * kF + kF;
 constexpr int kWStage = kMaxTilePos * kMP + kTileMax * kMP;
 static_assert(kWStage >= kRedFloats, "the reduction buffer reuses the staging buffer");
@@ -328,12 +422,101 @@ __global__ __launch_bounds__(256) void k_conv32_bwd_w_mfma(const float* __restri
     partial[static_cast<int64_t>(blockIdx.x) * kRedFloats + e] = red[e];
 }
 
-__global__ void k_sum_partials(const float* __restrict__ partial, int nblocks, int NT, float* __restrict__ out) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= NT) return;
+// Weight gradients of a stack's thin convolutions (C = 1 or 3 channels on one
+// side, 32 on the other) on the matrix cores, per block the partial sums over
+// its tiles in the partial layout of k_conv_bwd_w.  A wavefront contracts its
+// 32 positions p two at a time, D[m][n] += A[m][p] B[p][n], with A the
+// 32-channel operand at p and B the C-channel operand at p shifted by tap d:
+//   first convolution (C -> 32): m = o, n = 9 c + d,
+//     D = sum_p g[p][o] z[p + off(d)][c], bias sum_p g[p][o];
+//   last convolution (32 -> C, L3): m = c, n = 9 o + d,
+//     D = sum_p relu(a)[p][c] g[p - off(d)][o] (the same sum over p + off(d)), bias sum_p g[p][o].
+// Columns n >= 9 C are zero.  The four wavefronts' sums are added in a fixed order.
+template <int C, bool L3>
+__global__ __launch_bounds__(256) void k_bwd_w_thin(const float* __restrict__ act, int64_t a_bs, int act_relu,
+                                                    const float* __restrict__ g, int64_t g_bs, int s, int ntiles,
+                                                    float* __restrict__ partial) {
+  constexpr int NN = 9 * C;
+  constexpr int NT = NN * kF + (L3 ? C : kF);
+  __shared__ float sw[kTileMax * kMP];     // the 32-channel operand, [p][ch]
+  __shared__ float sn[kMaxTilePos * C];    // the C-channel operand with halo, [q][ch]
+  __shared__ float red[NT];
+  const float* __restrict__ wide = L3 ? act : g;
+  const float* __restrict__ thin = L3 ? g : act;
+  const int64_t wide_bs = L3 ? a_bs : g_bs, thin_bs = L3 ? g_bs : a_bs;
+  const int wide_relu = L3 ? act_relu : 0, thin_relu = L3 ? 0 : act_relu;
+  const TileGeo tg = tile_geo(s);
+  const int tiles_x = s / tg.TC, per_img = (s / tg.TR) * tiles_x;
+  const int64_t per = static_cast<int64_t>(s) * s;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, kh = lane >> 5, l32 = lane & 31;
+  const bool nv = l32 < NN;
+  const int nc = nv ? l32 / 9 : 0;                               // c (first) or o (last)
+  const int nd = nv ? (L3 ? 8 - l32 % 9 : l32 % 9) : 4;          // tap of the shift
+  f32x16 acc = {};
+  float bsum = 0.0f;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int b = t / per_img, ti = t - b * per_img;
+    const int ty0 = (ti / tiles_x) * tg.TR, tx0 = (ti % tiles_x) * tg.TC;
+    const float* __restrict__ wb = wide + b * wide_bs;
+    for (int e = threadIdx.x; e < kF * kTileMax; e += 256) {
+      const int c = e >> 7, q = e & (kTileMax - 1);
+      const int yy = q / tg.TC, xx = q - yy * tg.TC;
+      float v = wb[c * per + static_cast<int64_t>(ty0 + yy) * s + tx0 + xx];
+      if (wide_relu) v = fmaxf(v, 0.0f);
+      sw[q * kMP + c] = v;
+    }
+    stage_halo<C>(thin + b * thin_bs, per, s, tg, ty0, tx0, thin_relu, sn, C);
+    __syncthreads();
+#pragma unroll
+    for (int st = 0; st < 16; ++st) {
+      const int p = wv * 32 + 2 * st + kh;
+      const int ty = p / tg.TC, tx = p - ty * tg.TC;
+      const float bv = nv ? sn[((ty + nd / 3) * tg.W2 + tx + nd % 3) * C + nc] : 0.0f;
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(sw[p * kMP + l32], bv, acc, 0, 0, 0);
+    }
+    if (kh == 0) {
+      if (!L3) {
+        for (int p = 0; p < 32; ++p) bsum += sw[(wv * 32 + p) * kMP + l32];
+      } else if (l32 < C) {
+        for (int p = 0; p < 32; ++p) {
+          const int q = wv * 32 + p, ty = q / tg.TC, tx = q - ty * tg.TC;
+          bsum += sn[((ty + 1) * tg.W2 + tx + 1) * C + l32];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int w = 0; w < 4; ++w) {
+    if (wv == w) {
+      if (nv) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const int m = 8 * (j >> 2) + 4 * kh + (j & 3);
+          const int idx = L3 ? (l32 / 9) * (kF * 9) + m * 9 + l32 % 9 : m * NN + l32;
+          red[idx] = (w == 0 ? 0.0f : red[idx]) + acc[j];
+        }
+      }
+      if (kh == 0 && l32 < (L3 ? C : kF)) red[NN * kF + l32] = (w == 0 ? 0.0f : red[NN * kF + l32]) + bsum;
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < NT; e += 256) partial[static_cast<int64_t>(blockIdx.x) * NT + e] = red[e];
+}
+
+// out[i] = sum over the partial rows b of partial[b][i]: a block takes 64
+// consecutive i, its four wavefronts the rows b = w, w + 4, ..., and the four
+// sums are added in a fixed order.
+__global__ __launch_bounds__(256) void k_sum_partials(const float* __restrict__ partial, int nblocks, int NT,
+                                                      float* __restrict__ out) {
+  __shared__ float red[4][64];
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + l;
   float a = 0.0f;
-  for (int b = 0; b < nblocks; ++b) a += partial[static_cast<int64_t>(b) * NT + idx];
-  out[idx] = a;
+  if (i < NT)
+    for (int b = w; b < nblocks; b += 4) a += partial[static_cast<int64_t>(b) * NT + i];
+  red[w][l] = a;
+  __syncthreads();
+  if (w == 0 && i < NT) out[i] = (red[0][l] + red[1][l]) + (red[2][l] + red[3][l]);
 }
 
 // g = 2 (pred - target) / (B N); per-block partial sums of (pred - target)^2 in float64.
@@ -450,10 +633,14 @@ dim3 mfma_grid(int s, int B) { return dim3(static_cast<unsigned>((s * s) / 128),
 template <int CI, int CO>
 void conv_fwd(const float* in, int64_t in_bs, int in_relu, int s, int B, const uint16_t* w, const uint16_t* b,
               float* out, int64_t out_bs, const float* resid, int64_t res_bs, hipStream_t st) {
-  if constexpr (CI == kF && CO == kF) {
-    if (s >= 16) {   // the hidden layer on the matrix cores
-      hipLaunchKernelGGL(k_conv32_mfma<false>, mfma_grid(s, B), dim3(256), 0, st, in, in_bs, in_relu, s, w, b, out,
-                         out_bs, resid, res_bs, static_cast<const float*>(nullptr), int64_t{0});
+  if (s >= 16) {   // on the matrix cores
+    if constexpr (CO == kF) {
+      hipLaunchKernelGGL((k_conv_mfma_in<CI, false>), mfma_grid(s, B), dim3(256), 0, st, in, in_bs, in_relu, s, w, b,
+                         out, out_bs, resid, res_bs, static_cast<const float*>(nullptr), int64_t{0});
+      return;
+    } else if constexpr (CI == kF) {
+      hipLaunchKernelGGL(k_conv_mfma_out<CO>, mfma_grid(s, B), dim3(256), 0, st, in, in_bs, in_relu, s, w, b, out,
+                         out_bs, resid, res_bs);
       return;
     }
   }
@@ -461,12 +648,14 @@ void conv_fwd(const float* in, int64_t in_bs, int in_relu, int s, int B, const u
                      in_relu, s, B, w, b, out, out_bs, resid, res_bs);
 }
 
+// Data gradient of a layer with CI inputs and CO outputs: a convolution of the
+// CO-channel gradient into CI channels.
 template <int CO, int CI>
 void conv_bwd_data(const float* g, int64_t g_bs, int s, int B, const uint16_t* w, const float* mask, int64_t m_bs,
                    float* gin, int64_t gin_bs, hipStream_t st) {
-  if constexpr (CI == kF && CO == kF) {
+  if constexpr (CI == kF) {
     if (s >= 16) {
-      hipLaunchKernelGGL(k_conv32_mfma<true>, mfma_grid(s, B), dim3(256), 0, st, g, g_bs, 0, s, w,
+      hipLaunchKernelGGL((k_conv_mfma_in<CO, true>), mfma_grid(s, B), dim3(256), 0, st, g, g_bs, 0, s, w,
                          static_cast<const uint16_t*>(nullptr), gin, gin_bs, static_cast<const float*>(nullptr),
                          int64_t{0}, mask, m_bs);
       return;
@@ -481,20 +670,25 @@ void conv_bwd_w(const float* act, int64_t a_bs, int act_relu, const float* g, in
                 float* partial, float* out, hipStream_t st) {
   const int64_t T = static_cast<int64_t>(B) * s * s;
   const int NT = CO * CI * 9 + CO;
-  if constexpr (CI == kF && CO == kF) {
-    if (s >= 16) {   // the hidden layer on the matrix cores
-      const int ntiles = static_cast<int>(T / kTileMax);
-      const int nb = std::min(kWGridMax, ntiles);
+  if (s >= 16) {   // on the matrix cores
+    const int ntiles = static_cast<int>(T / kTileMax);
+    const int nb = std::min(kWGridMax, ntiles);
+    if constexpr (CI == kF && CO == kF)
       hipLaunchKernelGGL(k_conv32_bwd_w_mfma, dim3(nb), dim3(256), 0, st, act, a_bs, act_relu, g, g_bs, s, ntiles,
                          partial);
-      hipLaunchKernelGGL(k_sum_partials, dim3((NT + 255) / 256), dim3(256), 0, st, partial, nb, NT, out);
-      return;
-    }
+    else if constexpr (CI == kF)
+      hipLaunchKernelGGL((k_bwd_w_thin<CO, true>), dim3(nb), dim3(256), 0, st, act, a_bs, act_relu, g, g_bs, s,
+                         ntiles, partial);
+    else
+      hipLaunchKernelGGL((k_bwd_w_thin<CI, false>), dim3(nb), dim3(256), 0, st, act, a_bs, act_relu, g, g_bs, s,
+                         ntiles, partial);
+    hipLaunchKernelGGL(k_sum_partials, dim3((NT + 63) / 64), dim3(256), 0, st, partial, nb, NT, out);
+    return;
   }
   const int nb = static_cast<int>(std::min<int64_t>(kWGridMax, (T + kP - 1) / kP));
   hipLaunchKernelGGL((k_conv_bwd_w<CI, CO>), dim3(nb), dim3(kBlk), 0, st, act, a_bs, act_relu, g, g_bs, s, B,
                      partial);
-  hipLaunchKernelGGL(k_sum_partials, dim3((NT + 255) / 256), dim3(256), 0, st, partial, nb, NT, out);
+  hipLaunchKernelGGL(k_sum_partials, dim3((NT + 63) / 64), dim3(256), 0, st, partial, nb, NT, out);
 }
 
 void forward(wdb_cnn* c, const float* x0, int B, float* pred, hipStream_t st) {
