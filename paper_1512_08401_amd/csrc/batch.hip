@@ -423,19 +423,42 @@ __global__ __launch_bounds__(kBlock) void k_check_reduce(const int* __restrict__
   if (threadIdx.x == 0) out[c * 4 * kR + v] = sh[0];
 }
 
-__global__ void k_interleave(const float* __restrict__ src, float* __restrict__ dst, int64_t N, int j) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < N) dst[i * kR + j] = src ? src[i] : 0.0f;
-}
-
-// Problem j's iterate: the anchor rounded to float32 (and as float64 when asked).
-__global__ void k_deinterleave(const double* __restrict__ src, float* __restrict__ dst, double* __restrict__ dst64,
-                               int64_t N, int j) {
+// The eight slots of a chunk's [N][8] block from eight vectors (null: zeros),
+// written to dst and, if given, dst2.
+struct Src8 {
+  const float* p[kR];
+};
+__global__ void k_interleave8(Src8 src, float* __restrict__ dst, float* __restrict__ dst2, int64_t N) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= N) return;
-  const double v = src[i * kR + j];
-  dst[i] = static_cast<float>(v);
-  if (dst64) dst64[i] = v;
+  float v[kR];
+#pragma unroll
+  for (int j = 0; j < kR; ++j) v[j] = src.p[j] ? src.p[j][i] : 0.0f;
+  float4* d = reinterpret_cast<float4*>(dst + i * kR);
+  d[0] = make_float4(v[0], v[1], v[2], v[3]);
+  d[1] = make_float4(v[4], v[5], v[6], v[7]);
+  if (dst2) {
+    float4* e = reinterpret_cast<float4*>(dst2 + i * kR);
+    e[0] = d[0];
+    e[1] = d[1];
+  }
+}
+
+// The problems' iterates: the anchors rounded to float32 (and as float64 where asked).
+struct Dst8 {
+  float* p[kR];
+  double* p64[kR];
+};
+__global__ void k_deinterleave8(const double* __restrict__ src, Dst8 dst, int nslots, int64_t N) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+#pragma unroll
+  for (int j = 0; j < kR; ++j) {
+    if (j >= nslots) break;
+    const double v = src[i * kR + j];
+    dst.p[j][i] = static_cast<float>(v);
+    if (dst.p64[j]) dst.p64[j][i] = v;
+  }
 }
 
 __global__ void k_set(int* p, int v) { *p = v; }
@@ -469,16 +492,17 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
     if (!members.count(p.theta)) order.push_back(p.theta);
     members[p.theta].push_back(i);
   }
+  // Chunks of up to eight problems per operator; every chunk's [N][8] vectors
+  // live at its offset in one pool per vector kind, so the elementwise steps
+  // run over all chunks in one launch.
   struct Host {
     wdb_theta* th;
     std::vector<int> idx;
-    DevBuf<float> X, Y, X0, Rr, Cr;
-    DevBuf<double> r64, Anc;
-    DevBuf<int> act;
-    std::vector<int> act_host;  // flags of the eight slots, then "any slot active"
+    int64_t off;   // first element of the chunk's [N][8] block in the pools
     int blocks_res, blocks_prox, blocks;
   };
   std::vector<Host> chunks;
+  int64_t tot8 = 0;
   for (wdb_theta* th : order) {
     WDB_HIP(hipSetDevice(th->device));
     ensure_workspace(th);
@@ -492,16 +516,8 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
       Host h;
       h.th = th;
       h.idx.assign(m.begin() + b, m.begin() + std::min(m.size(), b + kR));
-      const int64_t N = th->N;
-      h.X.alloc(N * kR);
-      h.Y.alloc(N * kR);
-      h.X0.alloc(N * kR);
-      h.Rr.alloc(N * kR);
-      h.Cr.alloc(N * kR);
-      h.r64.alloc(N * kR);
-      h.Anc.alloc(N * kR);
-      h.act.alloc(kR + 1);
-      h.act_host.assign(kR + 1, 0);
+      h.off = tot8;
+      tot8 += th->N * kR;
       h.blocks_res = static_cast<int>((th->A.nslices * th->A.C + kBlock - 1) / kBlock);
       h.blocks_prox = static_cast<int>((th->At.nslices * th->At.C + kBlock - 1) / kBlock);
       h.blocks = std::max(h.blocks_res, h.blocks_prox);
@@ -510,6 +526,10 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
     }
   }
   const int nch = static_cast<int>(chunks.size());
+  DevBuf<float> pX(tot8), pY(tot8), pX0(tot8), pRr(tot8), pCr(tot8);
+  DevBuf<double> pR64(tot8), pAnc(tot8);
+  DevBuf<int> pAct(static_cast<size_t>(nch) * (kR + 1));
+  std::vector<int> act_host(static_cast<size_t>(nch) * (kR + 1), 0);   // per chunk: eight slot flags, then "any"
   std::vector<ChunkDev> hd(nch);
   std::vector<int> first(nch + 1, 0);
   for (int c = 0; c < nch; ++c) first[c + 1] = first[c] + chunks[c].blocks;
@@ -518,7 +538,6 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
   DevBuf<int> dfirst(nch + 1);
   DevBuf<double> part(static_cast<size_t>(4 * kR) * nblocks), red(static_cast<size_t>(nch) * 4 * kR);
   DevBuf<int> kdev(1);
-  std::vector<float> tmp;
   for (int c = 0; c < nch; ++c) {
     Host& h = chunks[c];
     wdb_theta* th = h.th;
@@ -541,16 +560,16 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
     WDB_REQUIRE(th->A.C == th->At.C, WDB_ERR_HIP, "mismatched slice heights");
     d.C = th->A.C;
     d.cshift = __builtin_ctz(static_cast<unsigned>(th->A.C));
-    d.X = h.X.p;
-    d.Y = h.Y.p;
-    d.X0 = h.X0.p;
-    d.Cr = h.Cr.p;
-    d.Anc = h.Anc.p;
-    d.Rr = h.Rr.p;
+    d.X = pX.p + h.off;
+    d.Y = pY.p + h.off;
+    d.X0 = pX0.p + h.off;
+    d.Cr = pCr.p + h.off;
+    d.Anc = pAnc.p + h.off;
+    d.Rr = pRr.p + h.off;
     d.pinv = pre ? th->pinv : nullptr;
     d.tau = static_cast<float>(tau);
-    d.act = h.act.p;
-    d.r64 = h.r64.p;
+    d.act = pAct.p + static_cast<int64_t>(c) * (kR + 1);
+    d.r64 = pR64.p + h.off;
     d.ntiles = 0;
     if (kernel_group(th) == kTiled) {  // the operator iterates on its tiled copies
       WDB_REQUIRE(th->tA.ntiles == th->tAt.ntiles, WDB_ERR_ARG, "mismatched tile lists");
@@ -568,35 +587,32 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
     }
     const Filter f = make_filter(th->wavelet);
     const size_t q = static_cast<size_t>(th->n / 2) * (th->n / 2);
-    std::vector<int>& act = h.act_host;
+    int* act = act_host.data() + static_cast<size_t>(c) * (kR + 1);
+    Src8 x0s{}, inits{};
     for (int j = 0; j < kR; ++j) {
       d.thr[j] = 0.0f;
       if (j < static_cast<int>(h.idx.size())) {
         const wdb_problem& p = probs[h.idx[j]];
         d.thr[j] = static_cast<float>(tau * static_cast<double>(p.lambda));
         act[j] = 1;
-        const float* x0 = p.x0;
-        if (!x0) {
-          dwt_forward(th->n, th->levels, f, p.u, th->ws_x0, th->ws_img, th->ws_img + q, s);
-          x0 = th->ws_x0;
+        x0s.p[j] = p.x0;
+        if (!x0s.p[j]) {   // the data term x0 = Psi^* u, staged in the chunk's X block (filled below)
+          float* dst = d.X + static_cast<int64_t>(j) * N;
+          dwt_forward(th->n, th->levels, f, p.u, dst, th->ws_img, th->ws_img + q, s);
+          x0s.p[j] = dst;
         }
-        hipLaunchKernelGGL(k_interleave, dim3((N + 255) / 256), dim3(256), 0, s, x0, h.X0.p, N, j);
-        hipLaunchKernelGGL(k_interleave, dim3((N + 255) / 256), dim3(256), 0, s, p.x_init, h.X.p, N, j);
-        hipLaunchKernelGGL(k_interleave, dim3((N + 255) / 256), dim3(256), 0, s, p.x_init, h.Y.p, N, j);
-      } else {
-        hipLaunchKernelGGL(k_interleave, dim3((N + 255) / 256), dim3(256), 0, s, static_cast<const float*>(nullptr),
-                           h.X0.p, N, j);
-        hipLaunchKernelGGL(k_interleave, dim3((N + 255) / 256), dim3(256), 0, s, static_cast<const float*>(nullptr),
-                           h.X.p, N, j);
-        hipLaunchKernelGGL(k_interleave, dim3((N + 255) / 256), dim3(256), 0, s, static_cast<const float*>(nullptr),
-                           h.Y.p, N, j);
+        inits.p[j] = p.x_init;
       }
     }
+    const dim3 g8(static_cast<unsigned>((N + 255) / 256));
+    hipLaunchKernelGGL(k_interleave8, g8, dim3(256), 0, s, x0s, pX0.p + h.off, static_cast<float*>(nullptr), N);
+    hipLaunchKernelGGL(k_interleave8, g8, dim3(256), 0, s, inits, d.X, d.Y, N);
     act[kR] = h.idx.empty() ? 0 : 1;
-    hipLaunchKernelGGL(k_anchor_init8, dim3((N * kR + 255) / 256), dim3(256), 0, s, h.Anc.p, h.Cr.p, h.X0.p, N * kR);
-    WDB_HIP(hipGetLastError());
-    WDB_HIP(hipMemcpyAsync(h.act.p, act.data(), (kR + 1) * sizeof(int), hipMemcpyHostToDevice, s));
   }
+  hipLaunchKernelGGL(k_anchor_init8, dim3(static_cast<unsigned>((tot8 + 255) / 256)), dim3(256), 0, s, pAnc.p, pCr.p,
+                     pX0.p, tot8);
+  WDB_HIP(hipGetLastError());
+  WDB_HIP(hipMemcpyAsync(pAct.p, act_host.data(), act_host.size() * sizeof(int), hipMemcpyHostToDevice, s));
   WDB_HIP(hipMemcpyAsync(dch.p, hd.data(), nch * sizeof(ChunkDev), hipMemcpyHostToDevice, s));
   WDB_HIP(hipMemcpyAsync(dfirst.p, first.data(), (nch + 1) * sizeof(int), hipMemcpyHostToDevice, s));
   const int k0 = opts->k0 > 0 ? opts->k0 : 1;
@@ -638,30 +654,22 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
       done += step;
       const bool at_check = (c > 0 && done % c == 0) || done == total;
       if (!at_check) continue;
-      for (int ci = 0; ci < nch; ++ci) {
-        const int64_t n8 = chunks[ci].th->N * kR;
-        hipLaunchKernelGGL(k_reanchor8, dim3((n8 + 255) / 256), dim3(256), 0, s, chunks[ci].Anc.p, chunks[ci].X.p,
-                           chunks[ci].Y.p, n8);
-      }
+      const dim3 gall(static_cast<unsigned>((tot8 + 255) / 256));
+      hipLaunchKernelGGL(k_reanchor8, gall, dim3(256), 0, s, pAnc.p, pX.p, pY.p, tot8);
       hipLaunchKernelGGL(k_check_fwd, dim3(static_cast<unsigned>(nblocks)), dim3(kBlock), 0, s, dch.p, dfirst.p, nch,
                          part.p, nblocks);
       hipLaunchKernelGGL(k_check_bwd, dim3(static_cast<unsigned>(nblocks)), dim3(kBlock), 0, s, dch.p, dfirst.p, nch,
                          part.p, nblocks);
       hipLaunchKernelGGL(k_check_reduce, dim3(nch * 4 * kR), dim3(kBlock), 0, s, dfirst.p, part.p, nblocks, red.p);
-      for (int ci = 0; ci < nch; ++ci) {
-        const int64_t n8 = chunks[ci].th->N * kR;
-        hipLaunchKernelGGL(k_anchor_rhs8, dim3((n8 + 255) / 256), dim3(256), 0, s, chunks[ci].r64.p,
-                           chunks[ci].Cr.p, n8);
-      }
+      hipLaunchKernelGGL(k_anchor_rhs8, gall, dim3(256), 0, s, pR64.p, pCr.p, tot8);
       WDB_HIP(hipGetLastError());
       WDB_HIP(hipMemcpyAsync(hred.data(), red.p, hred.size() * sizeof(double), hipMemcpyDeviceToHost, s));
       WDB_HIP(hipStreamSynchronize(s));
       ++checks;
-      bool any_active = false;
+      bool any_active = false, changed = false;
       for (int ci = 0; ci < nch; ++ci) {
         Host& h = chunks[ci];
-        std::vector<int>& act = h.act_host;
-        bool changed = false;
+        int* act = act_host.data() + static_cast<size_t>(ci) * (kR + 1);
         for (int j = 0; j < static_cast<int>(h.idx.size()); ++j) {
           const int pi = h.idx[j];
           if (done_at[pi] >= 0) continue;  // already stopped
@@ -686,8 +694,9 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
           act[kR] |= act[j];
         }
         any_active |= act[kR] != 0;
-        if (changed) WDB_HIP(hipMemcpyAsync(h.act.p, act.data(), (kR + 1) * sizeof(int), hipMemcpyHostToDevice, s));
       }
+      if (changed)
+        WDB_HIP(hipMemcpyAsync(pAct.p, act_host.data(), act_host.size() * sizeof(int), hipMemcpyHostToDevice, s));
       if (stopping && !any_active) {
         all_conv = true;
         break;
@@ -705,9 +714,13 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
   for (int ci = 0; ci < nch; ++ci) {
     Host& h = chunks[ci];
     const int64_t N = h.th->N;
-    for (int j = 0; j < static_cast<int>(h.idx.size()); ++j)
-      hipLaunchKernelGGL(k_deinterleave, dim3((N + 255) / 256), dim3(256), 0, s, h.Anc.p, probs[h.idx[j]].x_out,
-                         probs[h.idx[j]].x64_out, N, j);
+    Dst8 dst{};
+    for (int j = 0; j < static_cast<int>(h.idx.size()); ++j) {
+      dst.p[j] = probs[h.idx[j]].x_out;
+      dst.p64[j] = probs[h.idx[j]].x64_out;
+    }
+    hipLaunchKernelGGL(k_deinterleave8, dim3(static_cast<unsigned>((N + 255) / 256)), dim3(256), 0, s,
+                       pAnc.p + h.off, dst, static_cast<int>(h.idx.size()), N);
   }
   WDB_HIP(hipGetLastError());
   WDB_HIP(hipStreamSynchronize(s));
