@@ -164,7 +164,7 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance measurement")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default kernel layout")
-    ap.add_argument("--form", default="plain", choices=["plain", "batched", "learned", "conv", "tuned", "exact"],
+    ap.add_argument("--form", default="plain", choices=["plain", "batched", "learned", "conv", "tuned", "exact", "cnn"],
                     help="plain: the single-problem solve (default); batched / learned: the extension workloads")
     ap.add_argument("--train-images", type=int, default=4096)
     ap.add_argument("--heldout-images", type=int, default=512)
@@ -184,7 +184,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.form != "plain":
         res = {"batched": run_batched, "learned": run_learned, "conv": run_conv, "tuned": run_tuned,
-               "exact": run_exact}[args.form](args)
+               "exact": run_exact, "cnn": run_cnn}[args.form](args)
         print(json.dumps(res), flush=True)
         return
     dev = torch.device("cuda:0")
@@ -440,7 +440,7 @@ def run_batched(args):
         kind, kw = g["field"]
         field = synth.psf_isotropic(n, **kw) if kind == "isotropic" else synth.psf_rotating(n, **kw)
         th = wdb.build_theta(field, "db4", g["levels"], g["nnz_per_px"] * n * n)
-        th.lipschitz(synth.power_start(n * n, 1000 + gi))
+        th.lipschitz_lanczos(synth.power_start(n * n, 1000 + gi))
         th.autotune(reps=5)
         total_nnz += th.info()["nnz"]
         for j in range(8):
@@ -611,7 +611,7 @@ def run_conv(args):
     os.environ.pop("WDB_BUILD_GENERAL", None)
     th = wdb.build_theta(field, "db4", J, K)
     th.autotune(reps=5)
-    th.lipschitz(synth.power_start(n * n, 22))
+    th.lipschitz_lanczos(synth.power_start(n * n, 22))
     u0 = _observe(wdb, torch, field, n, 21, 22, 0.005)
     rate, info = _solve_rate(th, u0, lam, 500, torch)
     return {"metric": "Theta build time, stationary blur (Alg. 3 fast path)", "value": out["fast"]["build_s"],
@@ -621,6 +621,70 @@ def run_conv(args):
                                    f"pixel, Theta_K 20 nnz/px ({K}), lambda {lam}"},
             "builds": out, "speedup": round(out["general"]["build_s"] / out["fast"]["build_s"], 2),
             "fista_iters_per_s": round(rate, 1), "layout": [th.info()["slice"], th.info()["group"]]}
+
+
+def cnn_flops(n, levels, F=32):
+    """Algorithmic FLOPs per image of the warm-start network: (inference,
+    training step).  Per position of a stack with C channels the three
+    convolutions cost 2*9*C*F, 2*9*F*F and 2*9*F*C; a training step runs the
+    forward pass, the stack's recomputed first two convolutions, both
+    gradients of the last two and the weight gradient of the first."""
+    sides = [n >> levels] + [n >> l for l in range(levels, 0, -1)]
+    chans = [1] + [3] * levels
+    inf = train = 0
+    for s, C in zip(sides, chans):
+        c1, c2, c3 = 18 * C * F, 18 * F * F, 18 * F * C
+        inf += s * s * (c1 + c2 + c3)
+        train += s * s * (3 * c1 + 4 * c2 + 3 * c3)
+    return inf, train
+
+
+def run_cnn(args):
+    """The warm-start network's kernels alone, on the learned workload's
+    shapes (256x256 coefficients, 4 levels, 32 channels) with a batch of 32:
+    K timed Adam training steps, then K timed inference passes, inputs resident
+    in HBM.  Roofline: the convolutions' algorithmic FLOPs per step over the
+    step time, against the float32 matrix-core peak (the hidden 32 -> 32
+    layers run on f32 MFMA; the 1- and 3-channel layers on the vector units)."""
+    import torch
+    import synth
+    from paper_1512_08401_amd import wdb
+    wl = synth.WORKLOADS["learned256"]
+    n, J, B = wl.n, wl.levels, 32
+    net = wdb.Cnn(n, J, 32, seed=1)
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    x0 = 0.1 * torch.randn(B * n * n, device="cuda", generator=gen)
+    tgt = x0 + 0.01 * torch.randn(B * n * n, device="cuda", generator=gen)
+    pred = torch.empty_like(x0)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    for _ in range(max(args.warmup, 1)):
+        net.train_step(x0, tgt, 1e-4)
+        net.predict(x0, out=pred)
+    torch.cuda.synchronize()
+    e0, e1, e2 = ev(), ev(), ev()
+    e0.record()
+    for _ in range(args.steps):
+        net.train_step(x0, tgt, 1e-4)
+    e1.record()
+    for _ in range(args.steps):
+        net.predict(x0, out=pred)
+    e2.record()
+    torch.cuda.synchronize()
+    t_train = e0.elapsed_time(e1) / 1e3 / args.steps
+    t_inf = e1.elapsed_time(e2) / 1e3 / args.steps
+    f_inf, f_train = cnn_flops(n, J)
+    ach = B * f_train / t_train / 1e12
+    log(f"train step {t_train * 1e3:.3f} ms, inference {t_inf * 1e3:.3f} ms (batch {B})")
+    return {"metric": "warm-start network training steps/s", "value": round(1.0 / t_train, 2), "unit": "steps/s",
+            "higher_is_better": True, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(t_train * 1e3, 4), "dtype": "bf16 weights, f32 compute", "data": "synthetic",
+            "config": {"workload": f"cnn256: {n}x{n} coefficients, {J} levels, 32 channels, batch {B}"},
+            "inference_ms": round(t_inf * 1e3, 4), "images_per_s_inference": round(B / t_inf, 1),
+            "roofline": {"bound": "mfma", "achieved": round(ach, 3), "peak": 157.3, "unit": "TFLOP/s",
+                         "frac": round(ach / 157.3, 4), "traffic": None,
+                         "kernel": "whole training step (convolution FLOPs / step time)",
+                         "flops_per_step": B * f_train},
+            "inference_tflops": round(B * f_inf / t_inf / 1e12, 3)}
 
 
 def run_tuned(args):
@@ -643,7 +707,7 @@ def run_tuned(args):
         torch.cuda.synchronize()
         t_build = time.perf_counter() - t0
         th.autotune(reps=5)
-        th.lipschitz(synth.power_start(n * n, wl.power_seed))
+        th.lipschitz_lanczos(synth.power_start(n * n, wl.power_seed))
         th.set_l1_weights(weights)
         rate, _ = _solve_rate(th, u0, lam, 500, torch)
         x0 = wdb.dwt(u0, wav, J)
