@@ -97,6 +97,32 @@ __device__ __forceinline__ X ld_at(const X* __restrict__ x, int i) {
   return *reinterpret_cast<const X*>(reinterpret_cast<const char*>(x) + off);
 }
 
+// Word 3 of a raw buffer resource on gfx9-family chips: data format 32-bit,
+// no swizzle, no index stride.
+constexpr int kBufWord3 = 0x00020000;
+
+// x at the 4 columns of a group: one 16-byte load when the columns are
+// consecutive in every lane of the wavefront (a quad of codes that differ
+// only in dj, away from the subband's edge), two 8-byte loads when they are
+// two such pairs, else four gathers.  The vector loads are buffer loads over
+// x's n^2 floats (4-byte aligned; a buffer load also returns zeros rather
+// than reading past the records).
+__device__ __forceinline__ float4 ld_group(const float* __restrict__ x, const Geo& g, const int4& col) {
+  const bool p1 = col.y == col.x + 1, p2 = col.w == col.z + 1;
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(x), 0, 4 << (2 * g.logn), kBufWord3);
+  if (__all(p1 && p2 && col.z == col.x + 2)) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, col.x * 4, 0, 0);
+    return make_float4(__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]), __uint_as_float(v[3]));
+  }
+  if (__all(p1 && p2)) {
+    const auto a = __builtin_amdgcn_raw_buffer_load_b64(rs, col.x * 4, 0, 0);
+    const auto b = __builtin_amdgcn_raw_buffer_load_b64(rs, col.z * 4, 0, 0);
+    return make_float4(__uint_as_float(a[0]), __uint_as_float(a[1]), __uint_as_float(b[0]), __uint_as_float(b[1]));
+  }
+  return make_float4(ld_at(x, col.x), ld_at(x, col.y), ld_at(x, col.z), ld_at(x, col.w));
+}
+
 // Codes and values of the U groups k, k + W, ... of a float32 tile (padding
 // past g1).
 template <int W, int U>
@@ -132,8 +158,7 @@ __device__ __forceinline__ float tile_dot(const TiledView& T, const Geo& g, cons
     float4 xs[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int4 col = group_cols(g, rc, c[u]);
-      xs[u] = make_float4(ld_at(x, col.x), ld_at(x, col.y), ld_at(x, col.z), ld_at(x, col.w));
+      xs[u] = ld_group(x, g, group_cols(g, rc, c[u]));
     }
     __builtin_amdgcn_sched_barrier(0);
     float4 vn[U];
@@ -190,11 +215,11 @@ __device__ __forceinline__ float tile_dot16(const TiledView& T, const Geo& g, co
     float xs[8 * U];
 #pragma unroll
     for (int u = 0; u < 2 * U; ++u) {
-      const int4 col = group_cols(g, rc, c[u]);
-      xs[4 * u] = ld_at(x, col.x);
-      xs[4 * u + 1] = ld_at(x, col.y);
-      xs[4 * u + 2] = ld_at(x, col.z);
-      xs[4 * u + 3] = ld_at(x, col.w);
+      const float4 q = ld_group(x, g, group_cols(g, rc, c[u]));
+      xs[4 * u] = q.x;
+      xs[4 * u + 1] = q.y;
+      xs[4 * u + 2] = q.z;
+      xs[4 * u + 3] = q.w;
     }
     __builtin_amdgcn_sched_barrier(0);
     uint4 vn[U];
@@ -484,6 +509,47 @@ std::vector<int> xcd_order(const std::vector<int4>& tiles) {
   return order;
 }
 
+// Order of a tile's codes in its value groups.  `u` holds the tile's distinct
+// codes in ascending order, so codes that differ only in dj (the low field)
+// and follow each other in dj form runs; every lane's columns for such a run
+// are consecutive in x (unless they wrap around the subband's side).  Each
+// run is cut into quads of 4 consecutive codes (with `extend`, a last part of
+// 3 is completed by the next code, value 0 in every lane, when dj has room:
+// more 16-byte loads for 7% more stored values on the workloads here, which
+// pays for 16-bit values, whose kernels are bound by the gathers, but not for
+// float32 ones, bound by the value stream), and what is left into pairs of 2
+// consecutive codes and single codes.  Groups of 4 are
+// then the quads, two pairs each, and the singles four at a time (the last
+// group mixing what remains); a group of 8 (16-bit values) is two such
+// groups.  The sequence is padded with kPadCodeTile to a multiple of grp.
+std::vector<uint32_t> group_runs(const std::vector<uint32_t>& u, int grp, bool extend) {
+  using F = CodeTile;
+  std::vector<uint32_t> quads, pairs, singles;
+  for (size_t a = 0; a < u.size();) {
+    size_t b = a + 1;
+    while (b < u.size() && u[b] == u[b - 1] + 1 && (u[b] & F::kMask) != 0) ++b;   // same fields above dj
+    size_t k = a;
+    for (; k + 4 <= b; k += 4)
+      for (int e = 0; e < 4; ++e) quads.push_back(u[k] + e);
+    if (extend && b - k == 3 && (u[k] & F::kMask) + 3 <= F::kMask) {
+      for (int e = 0; e < 4; ++e) quads.push_back(u[k] + e);
+      k = b;
+    }
+    if (b - k >= 2) {
+      pairs.push_back(u[k]);
+      pairs.push_back(u[k + 1]);
+      k += 2;
+    }
+    for (; k < b; ++k) singles.push_back(u[k]);
+    a = b;
+  }
+  std::vector<uint32_t> seq(quads);
+  seq.insert(seq.end(), pairs.begin(), pairs.end());
+  seq.insert(seq.end(), singles.begin(), singles.end());
+  while (seq.size() % grp) seq.push_back(kPadCodeTile);
+  return seq;
+}
+
 // Encode the tiles [t0, t1) of the tile list into `o` (pattern indices local
 // to `o`; the caller rebases them).
 // grp: codes per value group (4 for float32, 8 for 16-bit values); ub: the
@@ -530,18 +596,26 @@ void encode_tiles(const Geo& g, const std::vector<int4>& tiles, size_t t0, size_
     for (const auto& e : ent) u.push_back(e.first);
     std::sort(u.begin(), u.end());
     u.erase(std::unique(u.begin(), u.end()), u.end());
-    const size_t npat = u.size();
-    while (u.size() % grp) u.push_back(kPadCodeTile);
+    const std::vector<uint32_t> seq = group_runs(u, grp, grp == 8);
+    // position of each kept code in the sequence (extension and padding codes carry value 0)
+    std::vector<std::pair<uint32_t, int>> at;
+    at.reserve(u.size());
+    for (size_t q = 0; q < seq.size(); ++q)
+      if (std::binary_search(u.begin(), u.end(), seq[q])) at.emplace_back(seq[q], static_cast<int>(q));
+    std::sort(at.begin(), at.end());
+    at.erase(std::unique(at.begin(), at.end(),
+                         [](const auto& a, const auto& b) { return a.first == b.first; }),
+             at.end());
     const int pb = static_cast<int>(o.code.size());
-    o.code.insert(o.code.end(), u.begin(), u.end());
-    o.val.resize(o.val.size() + u.size() * 64, 0.0f);
+    o.code.insert(o.code.end(), seq.begin(), seq.end());
+    o.val.resize(o.val.size() + seq.size() * 64, 0.0f);
     for (size_t e = 0; e < ent.size(); ++e) {
-      const int p = static_cast<int>(std::lower_bound(u.begin(), u.begin() + npat, ent[e].first) - u.begin());
-      const int64_t q = pb + p;
+      const auto it = std::lower_bound(at.begin(), at.end(), std::make_pair(ent[e].first, -1));
+      const int64_t q = pb + it->second;
       o.val[((q / grp) * 64 + ent[e].second) * grp + (q % grp)] = ent_v[e];
     }
     d.x = pb;
-    d.y = pb + static_cast<int>(u.size());
+    d.y = pb + static_cast<int>(seq.size());
     if (esc) d.w |= kHasEsc;
     o.desc.push_back(d);
   }
