@@ -435,6 +435,17 @@ wdb_status wdb_synthesize(const wdb_theta* th, const float* x, float* u_hat, voi
 wdb_status wdb_dwt(int32_t n, int32_t wavelet, int32_t levels, const float* in, float* out,
                    int32_t inverse, void* stream);
 
+/* The same transform for `count` images at once (Sec. 2, applied image by
+ * image): in/out are device arrays of count * n * n floats, image i at i n^2,
+ * and must not overlap.  Up to 8 images share each level's launch, so a
+ * batch costs a few launches per level instead of one per image and level.
+ * Results equal wdb_dwt's for each image, bit for bit.  Allocates 2 n^2 / 4
+ * floats of scratch per image of a launch (at most 8) and synchronises
+ * `stream` before returning.  Errors: as wdb_dwt, and WDB_ERR_ARG for
+ * count < 1. */
+wdb_status wdb_dwt_batched(int32_t n, int32_t wavelet, int32_t levels, int32_t count, const float* in,
+                           float* out, int32_t inverse, void* stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * transform as wdb_dwt, bit for bit, with its level-to-level intermediates

@@ -374,4 +374,11 @@ void dwt_forward(int n, int levels, const Filter& f, const float* in, float* out
                  float* scratch_a, float* scratch_b, hipStream_t s);
 void dwt_inverse(int n, int levels, const Filter& f, const float* in, float* out,
                  float* scratch_a, float* scratch_b, hipStream_t s);
+// The same for `count` images, up to 8 per launch (one launch per level and
+// group of 8); scratch_a[i], scratch_b[i]: n*n/4 floats each for image i, and
+// images in one group of 8 must not share scratch.
+void dwt_forward_many(int n, int levels, const Filter& f, int count, const float* const* in, float* const* out,
+                      float* const* scratch_a, float* const* scratch_b, hipStream_t s);
+void dwt_inverse_many(int n, int levels, const Filter& f, int count, const float* const* in, float* const* out,
+                      float* const* scratch_a, float* const* scratch_b, hipStream_t s);
 }  // namespace wdb

@@ -13,7 +13,9 @@
 // half-resolution footprint (4 + 6 rows of 16 + 6 columns, periodic) in LDS,
 // and every thread sums the (L/2)^2 coefficients of each subband that cover
 // its pixel from there.
+#include <algorithm>
 #include <mutex>
+#include <vector>
 
 #include "common.hpp"
 
@@ -40,10 +42,27 @@ constexpr int kTI = 8, kTJ = 32;                    // output tile of a forward 
 constexpr int kRI = 2 * kTI + kMaxTaps - 2;          // input rows of its footprint (at most)
 constexpr int kCI = 2 * kTJ + kMaxTaps - 2;          // input columns of its footprint (at most)
 
-__global__ __launch_bounds__(256) void k_dwt_fwd_level(const float* __restrict__ A, int M,
-                                                       float* __restrict__ LL, float* __restrict__ d01,
-                                                       float* __restrict__ d10, float* __restrict__ d11,
+// Up to kBatch images per launch (blockIdx.z): per image the level's input,
+// its approximation output and the coefficient vector holding its details.
+constexpr int kBatch = 8;
+struct FwdPtrs {
+  const float* src[kBatch];
+  float* ll[kBatch];
+  float* out[kBatch];
+};
+struct InvPtrs {
+  const float* ll[kBatch];
+  const float* in[kBatch];
+  float* dst[kBatch];
+};
+
+__global__ __launch_bounds__(256) void k_dwt_fwd_level(FwdPtrs P, int M, int64_t o01, int64_t o10, int64_t o11,
                                                        Taps t) {
+  const float* __restrict__ A = P.src[blockIdx.z];
+  float* __restrict__ LL = P.ll[blockIdx.z];
+  float* __restrict__ d01 = P.out[blockIdx.z] + o01;
+  float* __restrict__ d10 = P.out[blockIdx.z] + o10;
+  float* __restrict__ d11 = P.out[blockIdx.z] + o11;
   __shared__ float in[kRI][kCI];
   __shared__ float lo[kRI][kTJ], hi[kRI][kTJ];
   const int Mh = M >> 1;
@@ -89,11 +108,13 @@ constexpr int kTP = 8, kTQ = 32;                   // output tile of an inverse 
 constexpr int kHalo = kMaxTaps / 2;                  // half-resolution rows / columns below the tile
 constexpr int kRP = kTP / 2 + kHalo, kCQ = kTQ / 2 + kHalo;
 
-__global__ __launch_bounds__(256) void k_dwt_inv_level(const float* __restrict__ LL,
-                                                       const float* __restrict__ d01,
-                                                       const float* __restrict__ d10,
-                                                       const float* __restrict__ d11, int Mh,
-                                                       float* __restrict__ out, Taps t) {
+__global__ __launch_bounds__(256) void k_dwt_inv_level(InvPtrs P, int64_t o01, int64_t o10, int64_t o11, int Mh,
+                                                       Taps t) {
+  const float* __restrict__ LL = P.ll[blockIdx.z];
+  const float* __restrict__ d01 = P.in[blockIdx.z] + o01;
+  const float* __restrict__ d10 = P.in[blockIdx.z] + o10;
+  const float* __restrict__ d11 = P.in[blockIdx.z] + o11;
+  float* __restrict__ out = P.dst[blockIdx.z];
   __shared__ float sb[4][kRP][kCQ];
   const int M = Mh << 1;
   const int p0 = blockIdx.y * kTP, q0 = blockIdx.x * kTQ;
@@ -138,42 +159,62 @@ static void level_offsets(int n, int levels, int lev, int64_t off[3]) {
     }
 }
 
+void dwt_forward_many(int n, int levels, const Filter& f, int count, const float* const* in, float* const* out,
+                      float* const* scratch_a, float* const* scratch_b, hipStream_t s) {
+  const Taps t = to_taps(f);
+  for (int b0 = 0; b0 < count; b0 += kBatch) {
+    const int nb = std::min(kBatch, count - b0);
+    FwdPtrs P{};
+    for (int z = 0; z < nb; ++z) P.src[z] = in[b0 + z];
+    for (int lev = 1; lev <= levels; ++lev) {
+      const int M = n >> (lev - 1);
+      const int Mh = M >> 1;
+      int64_t off[3];
+      level_offsets(n, levels, lev, off);
+      for (int z = 0; z < nb; ++z) {
+        P.out[z] = out[b0 + z];
+        P.ll[z] = (lev == levels) ? out[b0 + z] : ((lev & 1) ? scratch_b : scratch_a)[b0 + z];
+      }
+      const dim3 grid((Mh + kTJ - 1) / kTJ, (Mh + kTI - 1) / kTI, nb);
+      hipLaunchKernelGGL(k_dwt_fwd_level, grid, dim3(256), 0, s, P, M, off[0], off[1], off[2], t);
+      WDB_HIP(hipGetLastError());
+      for (int z = 0; z < nb; ++z) P.src[z] = P.ll[z];
+    }
+  }
+}
+
+void dwt_inverse_many(int n, int levels, const Filter& f, int count, const float* const* in, float* const* out,
+                      float* const* scratch_a, float* const* scratch_b, hipStream_t s) {
+  const Taps t = to_taps(f);
+  for (int b0 = 0; b0 < count; b0 += kBatch) {
+    const int nb = std::min(kBatch, count - b0);
+    InvPtrs P{};
+    for (int z = 0; z < nb; ++z) {
+      P.ll[z] = in[b0 + z];  // A_J sits at offset 0
+      P.in[z] = in[b0 + z];
+    }
+    for (int lev = levels; lev >= 1; --lev) {
+      const int Mh = n >> lev;
+      const int M = Mh << 1;
+      int64_t off[3];
+      level_offsets(n, levels, lev, off);
+      for (int z = 0; z < nb; ++z) P.dst[z] = (lev == 1) ? out[b0 + z] : ((lev & 1) ? scratch_b : scratch_a)[b0 + z];
+      const dim3 grid((M + kTQ - 1) / kTQ, (M + kTP - 1) / kTP, nb);
+      hipLaunchKernelGGL(k_dwt_inv_level, grid, dim3(256), 0, s, P, off[0], off[1], off[2], Mh, t);
+      WDB_HIP(hipGetLastError());
+      for (int z = 0; z < nb; ++z) P.ll[z] = P.dst[z];
+    }
+  }
+}
+
 void dwt_forward(int n, int levels, const Filter& f, const float* in, float* out, float* scratch_a,
                  float* scratch_b, hipStream_t s) {
-  const Taps t = to_taps(f);
-  const float* src = in;
-  float* bufs[2] = {scratch_a, scratch_b};
-  for (int lev = 1; lev <= levels; ++lev) {
-    const int M = n >> (lev - 1);
-    const int Mh = M >> 1;
-    int64_t off[3];
-    level_offsets(n, levels, lev, off);
-    float* ll = (lev == levels) ? out : bufs[lev & 1];
-    const dim3 grid((Mh + kTJ - 1) / kTJ, (Mh + kTI - 1) / kTI);
-    hipLaunchKernelGGL(k_dwt_fwd_level, grid, dim3(256), 0, s, src, M, ll, out + off[0], out + off[1],
-                       out + off[2], t);
-    WDB_HIP(hipGetLastError());
-    src = ll;
-  }
+  dwt_forward_many(n, levels, f, 1, &in, &out, &scratch_a, &scratch_b, s);
 }
 
 void dwt_inverse(int n, int levels, const Filter& f, const float* in, float* out, float* scratch_a,
                  float* scratch_b, hipStream_t s) {
-  const Taps t = to_taps(f);
-  const float* ll = in;  // A_J sits at offset 0
-  float* bufs[2] = {scratch_a, scratch_b};
-  for (int lev = levels; lev >= 1; --lev) {
-    const int Mh = n >> lev;
-    const int M = Mh << 1;
-    int64_t off[3];
-    level_offsets(n, levels, lev, off);
-    float* dst = (lev == 1) ? out : bufs[lev & 1];
-    const dim3 grid((M + kTQ - 1) / kTQ, (M + kTP - 1) / kTP);
-    hipLaunchKernelGGL(k_dwt_inv_level, grid, dim3(256), 0, s, ll, in + off[0], in + off[1], in + off[2], Mh,
-                       dst, t);
-    WDB_HIP(hipGetLastError());
-    ll = dst;
-  }
+  dwt_inverse_many(n, levels, f, 1, &in, &out, &scratch_a, &scratch_b, s);
 }
 
 }  // namespace wdb
@@ -192,6 +233,39 @@ extern "C" wdb_status wdb_dwt(int32_t n, int32_t wavelet, int32_t levels, const 
     wdb::dwt_inverse(n, levels, f, in, out, scratch.p, scratch.p + q, s);
   else
     wdb::dwt_forward(n, levels, f, in, out, scratch.p, scratch.p + q, s);
+  WDB_HIP(hipStreamSynchronize(s));
+  WDB_API_END
+}
+
+extern "C" wdb_status wdb_dwt_batched(int32_t n, int32_t wavelet, int32_t levels, int32_t count, const float* in,
+                                      float* out, int32_t inverse, void* stream) {
+  WDB_API_BEGIN
+  WDB_REQUIRE(in && out, WDB_ERR_ARG, "null buffer");
+  WDB_REQUIRE(count >= 1, WDB_ERR_ARG, "count %d must be >= 1", count);
+  wdb::Filter f = wdb::make_filter(wavelet);
+  wdb::check_geometry(n, levels, static_cast<int>(f.h.size()));
+  const int64_t N = static_cast<int64_t>(n) * n;
+  const char* ib = reinterpret_cast<const char*>(in);
+  const char* ie = reinterpret_cast<const char*>(in + N * count);
+  const char* ob = reinterpret_cast<const char*>(out);
+  const char* oe = reinterpret_cast<const char*>(out + N * count);
+  WDB_REQUIRE(ie <= ob || oe <= ib, WDB_ERR_ARG, "in and out must not overlap");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t q = static_cast<size_t>(n / 2) * (n / 2);
+  const int nsc = std::min(count, 8);
+  wdb::DevBuf<float> scratch(2 * q * nsc);
+  std::vector<const float*> ip(count);
+  std::vector<float*> op(count), sa(count), sb(count);
+  for (int i = 0; i < count; ++i) {
+    ip[i] = in + N * i;
+    op[i] = out + N * i;
+    sa[i] = scratch.p + 2 * q * (i % nsc);   // images of one launch use distinct scratch; launches are in order
+    sb[i] = sa[i] + q;
+  }
+  if (inverse)
+    wdb::dwt_inverse_many(n, levels, f, count, ip.data(), op.data(), sa.data(), sb.data(), s);
+  else
+    wdb::dwt_forward_many(n, levels, f, count, ip.data(), op.data(), sa.data(), sb.data(), s);
   WDB_HIP(hipStreamSynchronize(s));
   WDB_API_END
 }

@@ -97,6 +97,7 @@ _SIGS = {
     "wdb_prox_step": [_vp, _vp, _vp, _vp, _f32, _f32, _f32, _i32, _vp],
     "wdb_synthesize": [_vp, _vp, _vp, _vp],
     "wdb_dwt": [_i32, _i32, _i32, _vp, _vp, _i32, _vp],
+    "wdb_dwt_batched": [_i32, _i32, _i32, _i32, _vp, _vp, _i32, _vp],
     "wdb_blur": [C.POINTER(PsfFieldC), _vp, _vp, _vp],
     "wdb_wavelet_filter": [_i32, _pd, _i32, C.POINTER(_i32)],
     "wdb_set_precision": [_vp, _i32],
@@ -568,6 +569,18 @@ def dwt(u, wavelet: str, levels: int, inverse: bool = False, out=None, stream=No
     y = torch.empty(n * n, device=u.device, dtype=torch.float32) if out is None else out
     _check("wdb_dwt", _lib.wdb_dwt(n, WAVELETS[wavelet], levels, _dev(u, n * n, "in"), _dev(y, n * n, "out"),
                                    1 if inverse else 0, _stream(stream)))
+    return y
+
+
+def dwt_batched(u, wavelet: str, levels: int, inverse: bool = False, out=None, stream=None):
+    """The transform of every row of a (count, n*n) float32 device tensor."""
+    torch = _torch()
+    count, N = u.shape
+    n = int(round(N ** 0.5))
+    y = torch.empty((count, N), device=u.device, dtype=torch.float32) if out is None else out
+    _check("wdb_dwt_batched", _lib.wdb_dwt_batched(n, WAVELETS[wavelet], levels, count, _dev(u, count * N, "in"),
+                                                   _dev(y, count * N, "out"), 1 if inverse else 0,
+                                                   _stream(stream)))
     return y
 
 

@@ -68,6 +68,24 @@ def test_dwt_forward_inverse(W, name, n, J):
     assert np.max(np.abs(v - vo)) <= 2e-6 * np.max(np.abs(vo))
 
 
+@pytest.mark.parametrize("name,n,J,count", [("db4", 64, 3, 11), ("sym6", 128, 4, 8), ("haar", 32, 5, 1)])
+def test_dwt_batched_matches_single(W, name, n, J, count):
+    """The batched transform (8 images per launch, a ragged last group when
+    count = 11) against the oracle per image, and bit for bit against the
+    single-image entry point, both directions."""
+    print(f"dwt batched {name} n={n} J={J} count={count}", flush=True)
+    u = np.random.default_rng(count).random((count, n * n)).astype(np.float32)
+    x = host(W.dwt_batched(dev(u), name, J))
+    for i in range(count):
+        xo = dwt.dwt2(u[i].reshape(n, n).astype(np.float64), filters.by_name(name), J)
+        assert np.max(np.abs(x[i] - xo)) <= 2e-6 * np.max(np.abs(xo))
+        assert np.array_equal(x[i], host(W.dwt(dev(u[i]), name, J)))
+    v = host(W.dwt_batched(dev(x), name, J, inverse=True))
+    for i in range(count):
+        assert np.array_equal(v[i], host(W.dwt(dev(x[i]), name, J, inverse=True)))
+        assert np.max(np.abs(v[i] - u[i])) <= 2e-6
+
+
 @pytest.mark.parametrize("field", [synth.psf_isotropic(64, 1.0, 3.0), synth.psf_rotating(128, 4.0, 1.0),
                                    synth.psf_rotating(32, 2.5, 0.7)])
 def test_blur_matches_oracle(W, field):
