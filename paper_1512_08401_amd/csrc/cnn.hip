@@ -13,6 +13,10 @@
 // Parameters are flattened stack by stack: W1, b1, W2, b2, W3, b3.
 #include <cmath>
 #include <cstring>
+#include <algorithm>
+#include <mutex>
+#include <map>
+#include <type_traits>
 
 #include "common.hpp"
 
@@ -20,7 +24,7 @@ namespace {
 constexpr int kF = 32;       // hidden channels
 constexpr int kBlk = 256;
 constexpr int kP = 32;       // positions per weight-gradient chunk
-constexpr int kWGridMax = 512;
+constexpr int kWGridMax = 1024;   // partial rows of a weight gradient (blocks of its kernel)
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
 
@@ -90,98 +94,173 @@ __global__ __launch_bounds__(kBlk) void k_conv_fwd(const float* __restrict__ in,
 // D[8 (j / 4) + 4 (l / 32) + j mod 4][l mod 32] in its accumulator j.
 // FLIP: the data gradient of a layer with 32 input channels and CI outputs,
 // which is the convolution of g with W'[c][o][d] = W[c][o][8 - d] (W in the
-// layer's own [out][in][tap] layout), masked by a > 0.
+// layer's own [out][in][tap] layout), masked by a > 0.  `w` holds the weights
+// already in the kernel's [k][o] order (packed_weight), KP rows of 32.
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kMP = 33;                    // LDS floats per staged position (32 channels; odd stride)
 constexpr int kMaxTilePos = 6 * 34;        // (TR + 2) (TC + 2) for TC = 32 (204 >= 10 * 18 for TC = 16)
 constexpr int kTileMax = 128;              // positions per block tile
 
-struct TileGeo {
-  int TC, TR, W2, P2;
+// Block tiles: TC x TR positions, TC = 16 for a side of 16 and 32 above (a
+// compile-time width, so the staging loops divide by constants).
+template <int TC>
+struct TileG {
+  static constexpr int TR = kTileMax / TC, W2 = TC + 2, P2 = (TC + 2) * (kTileMax / TC + 2);
 };
-__device__ __forceinline__ TileGeo tile_geo(int s) {
-  const int TC = min(s, 32), TR = kTileMax / TC;
-  return TileGeo{TC, TR, TC + 2, (TC + 2) * (TR + 2)};
+
+// Image and origin of tile t of the batch (tiles of an image in row-major order).
+template <int TC>
+__device__ __forceinline__ void tile_origin(int t, int s, int& b, int& ty0, int& tx0) {
+  const int tiles_x = s / TC, per_img = (s / TileG<TC>::TR) * tiles_x;
+  b = t / per_img;
+  const int ti = t - b * per_img;
+  ty0 = (ti / tiles_x) * TileG<TC>::TR;
+  tx0 = (ti % tiles_x) * TC;
 }
 
 // Stage channels [0, CH) of the tile at (ty0, tx0) with its circular halo as
-// dst[q * stride + c], q = halo row * W2 + halo column.
-template <int CH>
-__device__ __forceinline__ void stage_halo(const float* __restrict__ src, int64_t per, int s, const TileGeo& tg,
-                                           int ty0, int tx0, int relu, float* __restrict__ dst, int stride) {
-  for (int e = threadIdx.x; e < CH * tg.P2; e += 256) {
-    const int c = e / tg.P2, q = e - c * tg.P2;
-    const int yy = q / tg.W2, xx = q - yy * tg.W2;
-    const int gy = (ty0 + yy - 1) & (s - 1), gx = (tx0 + xx - 1) & (s - 1);
-    float v = src[c * per + static_cast<int64_t>(gy) * s + gx];
-    if (relu) v = fmaxf(v, 0.0f);
-    dst[q * stride + c] = v;
+// dst[q * stride + c], q = halo row * W2 + halo column.  NT threads; every
+// thread issues all its loads before its first LDS store, so their latencies
+// overlap instead of adding up.
+template <int CH, int TC, int NT = 256>
+__device__ __forceinline__ void stage_halo(const float* __restrict__ src, int64_t per, int s, int ty0, int tx0,
+                                           int relu, float* __restrict__ dst, int stride) {
+  using G = TileG<TC>;
+  constexpr int NE = CH * G::P2, NIT = (NE + NT - 1) / NT;
+  float v[NIT];
+#pragma unroll
+  for (int i = 0; i < NIT; ++i) {
+    const int e = static_cast<int>(threadIdx.x) + i * NT;
+    if (e < NE) {
+      const int c = e / G::P2, q = e - c * G::P2;
+      const int yy = q / G::W2, xx = q - yy * G::W2;
+      const int gy = (ty0 + yy - 1) & (s - 1), gx = (tx0 + xx - 1) & (s - 1);
+      v[i] = src[c * per + static_cast<int64_t>(gy) * s + gx];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NIT; ++i) {
+    const int e = static_cast<int>(threadIdx.x) + i * NT;
+    if (e < NE) {
+      const int c = e / G::P2, q = e - c * G::P2;
+      dst[q * stride + c] = relu ? fmaxf(v[i], 0.0f) : v[i];
+    }
   }
 }
 
-template <int CI, bool FLIP>
+// Stage the 32 channels of the tile's own 128 positions as dst[p * kMP + c]
+// (ReLU on load if relu), loads first as above.
+template <int TC, int NT = 256>
+__device__ __forceinline__ void stage_tile32(const float* __restrict__ src, int64_t per, int s, int ty0, int tx0,
+                                             int relu, float* __restrict__ dst) {
+  constexpr int NE = kF * kTileMax, NIT = (NE + NT - 1) / NT;
+  float v[NIT];
+#pragma unroll
+  for (int i = 0; i < NIT; ++i) {
+    const int e = static_cast<int>(threadIdx.x) + i * NT;
+    if (e < NE) {
+      const int c = e / kTileMax, q = e % kTileMax;
+      const int yy = q / TC, xx = q - yy * TC;
+      v[i] = src[c * per + static_cast<int64_t>(ty0 + yy) * s + tx0 + xx];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NIT; ++i) {
+    const int e = static_cast<int>(threadIdx.x) + i * NT;
+    if (e < NE) dst[(e % kTileMax) * kMP + e / kTileMax] = relu ? fmaxf(v[i], 0.0f) : v[i];
+  }
+}
+
+// Blocks of the convolution kernels: each takes tiles t = blockIdx.x,
+// + gridDim.x, ... of the batch, its weights staged once.  The grid is as
+// many blocks as the device holds at once (so every compute unit gets the
+// same number of tiles, within one), at most kWGridMax.
+
+template <int CI, bool FLIP, int TC>
 __global__ __launch_bounds__(256) void k_conv_mfma_in(const float* __restrict__ in, int64_t in_bs, int in_relu, int s,
-                                                      const uint16_t* __restrict__ w,
+                                                      int ntiles, const uint16_t* __restrict__ w,
                                                       const uint16_t* __restrict__ bias, float* __restrict__ out,
                                                       int64_t out_bs, const float* __restrict__ resid,
                                                       int64_t res_bs, const float* __restrict__ mask, int64_t m_bs) {
+  using G = TileG<TC>;
   constexpr int K = 9 * CI, KP = K + (K & 1);
   constexpr int XS = CI == kF ? kMP : CI;   // LDS floats per staged position
-  __shared__ float sx[kMaxTilePos * XS];
-  __shared__ float swt[KP * kF];
-  const TileGeo tg = tile_geo(s);
-  const int tiles_x = s / tg.TC;
-  const int b = blockIdx.y;
-  const int ty0 = (static_cast<int>(blockIdx.x) / tiles_x) * tg.TR;
-  const int tx0 = (static_cast<int>(blockIdx.x) % tiles_x) * tg.TC;
+  __shared__ float sx[G::P2 * XS];
+  __shared__ __align__(16) uint16_t swt[KP * kF];   // bfloat16 weights, [k][o]
   const int64_t per = static_cast<int64_t>(s) * s;
-  for (int e = threadIdx.x; e < KP * kF; e += 256) {
-    const int k = e >> 5, o = e & 31;
-    float v = 0.0f;
-    if (k < K) {
-      const int d = k / CI, c = k - d * CI;
-      v = bf2f(FLIP ? w[(c * kF + o) * 9 + (8 - d)] : w[(o * CI + c) * 9 + d]);
-    }
-    swt[e] = v;
-  }
-  stage_halo<CI>(in + b * in_bs, per, s, tg, ty0, tx0, in_relu, sx, XS);
-  __syncthreads();
+  static_assert((KP * kF) % 8 == 0, "the packed weights copy in 16-byte pieces");
+  for (int e = threadIdx.x; e < KP * kF / 8; e += 256)
+    reinterpret_cast<uint4*>(swt)[e] = reinterpret_cast<const uint4*>(w)[e];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int pl = wv * 32 + (lane & 31);
-  const int ty = pl / tg.TC, tx = pl - ty * tg.TC;
+  const int ty = pl / TC, tx = pl - ty * TC;
   const int kh = lane >> 5;
-  f32x16 acc = {};
-  if constexpr (CI == kF) {
-    for (int d = 0; d < 9; ++d) {
-      const float* xr = sx + ((ty + d / 3) * tg.W2 + tx + d % 3) * XS + kh;
-      const float* wr = swt + (d * kF + kh) * kF + (lane & 31);
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    int b, ty0, tx0;
+    tile_origin<TC>(t, s, b, ty0, tx0);
+    stage_halo<CI, TC>(in + b * in_bs, per, s, ty0, tx0, in_relu, sx, XS);
+    __syncthreads();
+    f32x16 acc = {};
+    if constexpr (CI == kF) {
 #pragma unroll
-      for (int cb = 0; cb < kF / 2; ++cb)
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(wr[2 * cb * kF], xr[2 * cb], acc, 0, 0, 0);
-    }
-  } else {
+      for (int d = 0; d < 9; ++d) {
+        const float* xr = sx + ((ty + d / 3) * G::W2 + tx + d % 3) * XS + kh;
+        const uint16_t* wr = swt + (d * kF + kh) * kF + (lane & 31);
 #pragma unroll
-    for (int st = 0; st < KP / 2; ++st) {
-      const int k = 2 * st + kh;
-      const int dk = k / CI, c = k - dk * CI;   // k = K (the zero row) reads tap 8, channel 0
-      const int d = min(dk, 8);
-      const float xv = sx[((ty + d / 3) * tg.W2 + tx + d % 3) * XS + c];
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(swt[k * kF + (lane & 31)], xv, acc, 0, 0, 0);
-    }
-  }
-  const int64_t gpos = static_cast<int64_t>(ty0 + ty) * s + tx0 + tx;
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const int o = 8 * (j >> 2) + 4 * kh + (j & 3);
-    float v = acc[j];
-    if (FLIP) {
-      if (mask && !(mask[b * m_bs + o * per + gpos] > 0.0f)) v = 0.0f;
+        for (int cb = 0; cb < kF / 2; ++cb)
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(bf2f(wr[2 * cb * kF]), xr[2 * cb], acc, 0, 0, 0);
+      }
     } else {
-      v += bf2f(bias[o]);
-      if (resid) v += resid[b * res_bs + o * per + gpos];
+#pragma unroll
+      for (int st = 0; st < KP / 2; ++st) {
+        const int k = 2 * st + kh;
+        const int dk = k / CI, c = k - dk * CI;   // k = K (the zero row) reads tap 8, channel 0
+        const int d = min(dk, 8);
+        const float xv = sx[((ty + d / 3) * G::W2 + tx + d % 3) * XS + c];
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(bf2f(swt[k * kF + (lane & 31)]), xv, acc, 0, 0, 0);
+      }
     }
-    out[b * out_bs + o * per + gpos] = v;
+    __syncthreads();   // every wavefront is done with sx before the next tile is staged
+    const int64_t gpos = static_cast<int64_t>(ty0 + ty) * s + tx0 + tx;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int o = 8 * (j >> 2) + 4 * kh + (j & 3);
+      float v = acc[j];
+      if (FLIP) {
+        if (mask && !(mask[b * m_bs + o * per + gpos] > 0.0f)) v = 0.0f;
+      } else {
+        v += bf2f(bias[o]);
+        if (resid) v += resid[b * res_bs + o * per + gpos];
+      }
+      out[b * out_bs + o * per + gpos] = v;
+    }
   }
+}
+
+// Weight (k, o) of the matrix-core kernel for CI input channels, k = d CI + c
+// (zero for the padding row k >= 9 CI), from a layer's [out][in][tap] weights;
+// flip: the data-gradient form W'[c][o][d] = W[c][o][8 - d] of a layer with
+// 32 inputs.
+__device__ __forceinline__ uint16_t packed_weight(const uint16_t* __restrict__ w, int CI, bool flip, int k, int o) {
+  if (k >= 9 * CI) return 0;
+  const int d = k / CI, c = k - d * CI;
+  return flip ? w[(c * kF + o) * 9 + (8 - d)] : w[(o * CI + c) * 9 + d];
+}
+
+// The four packed matrices of one stack (blockIdx.y): W1 (CI = C), W2, W2
+// flipped (CI = 32), W3 flipped (CI = C).
+__global__ void k_pack_stack(const uint16_t* __restrict__ w1, const uint16_t* __restrict__ w2,
+                             const uint16_t* __restrict__ w3, int C, uint16_t* __restrict__ o1,
+                             uint16_t* __restrict__ o2, uint16_t* __restrict__ o2f, uint16_t* __restrict__ o3f) {
+  const int seg = blockIdx.y;
+  const int CI = (seg == 1 || seg == 2) ? kF : C;
+  const int KP = 9 * CI + ((9 * CI) & 1);
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= KP * kF) return;
+  const int k = e >> 5, o = e & 31;
+  const uint16_t* w = seg == 0 ? w1 : (seg == 3 ? w3 : w2);
+  uint16_t* out = seg == 0 ? o1 : (seg == 1 ? o2 : (seg == 2 ? o2f : o3f));
+  out[e] = packed_weight(w, CI, seg >= 2, k, o);
 }
 
 // The last convolution of a stack (32 -> CO channels, CO = 1 or 3) on the
@@ -189,56 +268,57 @@ __global__ __launch_bounds__(256) void k_conv_mfma_in(const float* __restrict__ 
 // x[q][c] at every position q of the tile and its halo (an MFMA over the 32
 // channels, rows m >= 9 CO zero), then out[o][p] = b[o] + resid[o][p] +
 // sum_d T[9 o + d][p + off(d)] on the vector units.
-template <int CO>
+template <int CO, int TC>
 __global__ __launch_bounds__(256) void k_conv_mfma_out(const float* __restrict__ in, int64_t in_bs, int in_relu,
-                                                       int s, const uint16_t* __restrict__ w,
+                                                       int s, int ntiles, const uint16_t* __restrict__ w,
                                                        const uint16_t* __restrict__ bias, float* __restrict__ out,
                                                        int64_t out_bs, const float* __restrict__ resid,
                                                        int64_t res_bs) {
+  using G = TileG<TC>;
   constexpr int M = 9 * CO;   // rows used of the 32 (and the LDS stride of T: odd)
-  __shared__ float sx[kMaxTilePos * kMP];
-  __shared__ float sT[8 * 32 * M];
+  constexpr int NG = (G::P2 + 31) / 32;   // groups of 32 halo positions
+  __shared__ float sx[G::P2 * kMP];
+  __shared__ float sT[NG * 32 * M];
   __shared__ float swt[kF * kF];
-  const TileGeo tg = tile_geo(s);
-  const int tiles_x = s / tg.TC;
-  const int b = blockIdx.y;
-  const int ty0 = (static_cast<int>(blockIdx.x) / tiles_x) * tg.TR;
-  const int tx0 = (static_cast<int>(blockIdx.x) % tiles_x) * tg.TC;
   const int64_t per = static_cast<int64_t>(s) * s;
   for (int e = threadIdx.x; e < kF * kF; e += 256) {
     const int c = e >> 5, m = e & 31;
     swt[e] = m < M ? bf2f(w[((m / 9) * kF + c) * 9 + m % 9]) : 0.0f;
   }
-  stage_halo<kF>(in + b * in_bs, per, s, tg, ty0, tx0, in_relu, sx, kMP);
-  __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, kh = lane >> 5, l32 = lane & 31;
-  for (int gq = wv; gq * 32 < tg.P2; gq += 4) {   // groups of 32 halo positions, wave-uniform bound
-    const int q = gq * 32 + l32;
-    const int qr = min(q, tg.P2 - 1);
-    f32x16 acc = {};
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    int b, ty0, tx0;
+    tile_origin<TC>(t, s, b, ty0, tx0);
+    stage_halo<kF, TC>(in + b * in_bs, per, s, ty0, tx0, in_relu, sx, kMP);
+    __syncthreads();
+    for (int gq = wv; gq < NG; gq += 4) {   // wave-uniform
+      const int q = gq * 32 + l32;
+      const int qr = min(q, G::P2 - 1);
+      f32x16 acc = {};
 #pragma unroll
-    for (int cb = 0; cb < kF / 2; ++cb)
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(swt[(2 * cb + kh) * kF + l32], sx[qr * kMP + 2 * cb + kh], acc, 0,
-                                                 0, 0);
-    if (q < tg.P2) {
+      for (int cb = 0; cb < kF / 2; ++cb)
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(swt[(2 * cb + kh) * kF + l32], sx[qr * kMP + 2 * cb + kh], acc,
+                                                   0, 0, 0);
+      if (q < G::P2) {
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const int m = 8 * (j >> 2) + 4 * kh + (j & 3);
-        if (m < M) sT[q * M + m] = acc[j];
+        for (int j = 0; j < 16; ++j) {
+          const int m = 8 * (j >> 2) + 4 * kh + (j & 3);
+          if (m < M) sT[q * M + m] = acc[j];
+        }
       }
     }
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < kTileMax * CO; e += 256) {
-    const int p = e & (kTileMax - 1), o = e / kTileMax;
-    const int ty = p / tg.TC, tx = p - ty * tg.TC;
-    float v = 0.0f;
+    __syncthreads();   // T complete; sx is free for the next tile (the sums below read only T)
+    for (int e = threadIdx.x; e < kTileMax * CO; e += 256) {
+      const int p = e & (kTileMax - 1), o = e / kTileMax;
+      const int ty = p / TC, tx = p - ty * TC;
+      float v = 0.0f;
 #pragma unroll
-    for (int d = 0; d < 9; ++d) v += sT[((ty + d / 3) * tg.W2 + tx + d % 3) * M + o * 9 + d];
-    v += bf2f(bias[o]);
-    const int64_t gpos = static_cast<int64_t>(ty0 + ty) * s + tx0 + tx;
-    if (resid) v += resid[b * res_bs + o * per + gpos];
-    out[b * out_bs + o * per + gpos] = v;
+      for (int d = 0; d < 9; ++d) v += sT[((ty + d / 3) * G::W2 + tx + d % 3) * M + o * 9 + d];
+      v += bf2f(bias[o]);
+      const int64_t gpos = static_cast<int64_t>(ty0 + ty) * s + tx0 + tx;
+      if (resid) v += resid[b * res_bs + o * per + gpos];
+      out[b * out_bs + o * per + gpos] = v;
+    }
   }
 }
 
@@ -345,81 +425,54 @@ __global__ __launch_bounds__(kBlk) void k_conv_bwd_w(const float* __restrict__ a
 
 // Weight gradient of the hidden 32 -> 32 layer on the matrix cores: per block
 // the partial sums over the 128-position tiles it takes (tile t = blockIdx.x,
-// + gridDim.x, ...), in the partial layout of k_conv_bwd_w.  Wavefront w of a
-// tile contracts its 32 positions two at a time: for offset d the product
-// D_d[o][c] += G[o][p] A_d[p][c], lane l giving G[l mod 32][p] = g[p][o] and
-// A_d[p][l mod 32] = act[p + off(d)][c] for p = 2 step + l / 32.  The four
-// wavefronts' sums are added in LDS in a fixed order, so the result does not
+// + gridDim.x, ...), in the partial layout of k_conv_bwd_w.  A block has one
+// wavefront per tap d (9 wavefronts); wavefront d contracts the tile's 128
+// positions two at a time, D_d[o][c] += G[o][p] A_d[p][c], lane l giving
+// G[l mod 32][p] = g[p][o] and A_d[p][l mod 32] = act[p + off(d)][c] for
+// p = 2 step + l / 32.  Each wavefront owns its tap's outputs (wavefront 0
+// also the bias sums), so no sum crosses wavefronts and the result does not
 // depend on scheduling.
 constexpr int kRedFloats = 9 * kF * kF + kF;
-constexpr int kWStage = kMaxTilePos * kMP + kTileMax * kMP;
-static_assert(kWStage >= kRedFloats, "the reduction buffer reuses the staging buffer");
+constexpr int kBwdWaves = 9;
+constexpr int kBwdThreads = 64 * kBwdWaves;
 
-__global__ __launch_bounds__(256) void k_conv32_bwd_w_mfma(const float* __restrict__ act, int64_t a_bs,
-                                                           int act_relu, const float* __restrict__ g, int64_t g_bs,
-                                                           int s, int ntiles, float* __restrict__ partial) {
-  __shared__ float buf[kWStage];
-  float* sx = buf;                          // act tile with halo, [pos][c]
-  float* sg = buf + kMaxTilePos * kMP;      // g tile, [pos][o]
-  const int TC = min(s, 32), TR = 128 / TC;
-  const int tiles_x = s / TC, per_img = (s / TR) * tiles_x;
-  const int W2 = TC + 2, H2 = TR + 2, P2 = W2 * H2;
+template <int TC>
+__global__ __launch_bounds__(kBwdThreads) void k_conv32_bwd_w_mfma(const float* __restrict__ act, int64_t a_bs,
+                                                                   int act_relu, const float* __restrict__ g,
+                                                                   int64_t g_bs, int s, int ntiles,
+                                                                   float* __restrict__ partial) {
+  constexpr int W2 = TileG<TC>::W2, P2 = TileG<TC>::P2;
+  __shared__ float sx[P2 * kMP];            // act tile with halo, [pos][c]
+  __shared__ float sg[kTileMax * kMP];      // g tile, [pos][o]
   const int64_t per = static_cast<int64_t>(s) * s;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, kh = lane >> 5, l32 = lane & 31;
-  f32x16 acc[9];
-#pragma unroll
-  for (int d = 0; d < 9; ++d) acc[d] = f32x16{};
+  const int lane = threadIdx.x & 63, d = threadIdx.x >> 6, kh = lane >> 5, l32 = lane & 31;
+  f32x16 acc = {};
   float bsum = 0.0f;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int b = t / per_img, ti = t - b * per_img;
-    const int ty0 = (ti / tiles_x) * TR, tx0 = (ti % tiles_x) * TC;
-    const float* __restrict__ ab = act + b * a_bs;
-    for (int e = threadIdx.x; e < kF * P2; e += 256) {
-      const int c = e / P2, q = e - c * P2;
-      const int yy = q / W2, xx = q - yy * W2;
-      const int gy = (ty0 + yy - 1) & (s - 1), gx = (tx0 + xx - 1) & (s - 1);
-      float v = ab[c * per + static_cast<int64_t>(gy) * s + gx];
-      if (act_relu) v = fmaxf(v, 0.0f);
-      sx[q * kMP + c] = v;
-    }
-    const float* __restrict__ gb = g + b * g_bs;
-    for (int e = threadIdx.x; e < kF * kTileMax; e += 256) {
-      const int o = e >> 7, q = e & (kTileMax - 1);
-      const int yy = q / TC, xx = q - yy * TC;
-      sg[q * kMP + o] = gb[o * per + static_cast<int64_t>(ty0 + yy) * s + tx0 + xx];
-    }
+    int b, ty0, tx0;
+    tile_origin<TC>(t, s, b, ty0, tx0);
+    stage_halo<kF, TC, kBwdThreads>(act + b * a_bs, per, s, ty0, tx0, act_relu, sx, kMP);
+    stage_tile32<TC, kBwdThreads>(g + b * g_bs, per, s, ty0, tx0, 0, sg);
     __syncthreads();
-    for (int st = 0; st < 16; ++st) {
-      const int q = wv * 32 + 2 * st + kh;
+    const int dy = d / 3, dx = d % 3;
+#pragma unroll 8
+    for (int st = 0; st < kTileMax / 2; ++st) {
+      const int q = 2 * st + kh;
       const int ty = q / TC, tx = q - ty * TC;
-      const float a = sg[q * kMP + l32];
-#pragma unroll
-      for (int d = 0; d < 9; ++d)
-        acc[d] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, sx[((ty + d / 3) * W2 + tx + d % 3) * kMP + l32], acc[d],
-                                                      0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(sg[q * kMP + l32], sx[((ty + dy) * W2 + tx + dx) * kMP + l32], acc,
+                                                 0, 0, 0);
     }
-    if (kh == 0)
-      for (int p = 0; p < 32; ++p) bsum += sg[(wv * 32 + p) * kMP + l32];
+    if (d == 0 && kh == 0)
+      for (int p = 0; p < kTileMax; ++p) bsum += sg[p * kMP + l32];
     __syncthreads();
   }
-  // fixed-order sum of the four wavefronts: wave 0 stores, waves 1..3 add in turn
-  float* red = buf;
-  for (int w = 0; w < 4; ++w) {
-    if (wv == w) {
+  float* pr = partial + static_cast<int64_t>(blockIdx.x) * kRedFloats;
 #pragma unroll
-      for (int d = 0; d < 9; ++d)
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          const int o = 8 * (j >> 2) + 4 * kh + (j & 3);
-          const int idx = o * (kF * 9) + l32 * 9 + d;
-          red[idx] = (w == 0 ? 0.0f : red[idx]) + acc[d][j];
-        }
-      if (kh == 0) red[9 * kF * kF + l32] = (w == 0 ? 0.0f : red[9 * kF * kF + l32]) + bsum;
-    }
-    __syncthreads();
+  for (int j = 0; j < 16; ++j) {
+    const int o = 8 * (j >> 2) + 4 * kh + (j & 3);
+    pr[o * (kF * 9) + l32 * 9 + d] = acc[j];
   }
-  for (int e = threadIdx.x; e < kRedFloats; e += 256)
-    partial[static_cast<int64_t>(blockIdx.x) * kRedFloats + e] = red[e];
+  if (d == 0 && kh == 0) pr[9 * kF * kF + l32] = bsum;
 }
 
 // Weight gradients of a stack's thin convolutions (C = 1 or 3 channels on one
@@ -432,7 +485,7 @@ __global__ __launch_bounds__(256) void k_conv32_bwd_w_mfma(const float* __restri
 //   last convolution (32 -> C, L3): m = c, n = 9 o + d,
 //     D = sum_p relu(a)[p][c] g[p - off(d)][o] (the same sum over p + off(d)), bias sum_p g[p][o].
 // Columns n >= 9 C are zero.  The four wavefronts' sums are added in a fixed order.
-template <int C, bool L3>
+template <int C, bool L3, int TC>
 __global__ __launch_bounds__(256) void k_bwd_w_thin(const float* __restrict__ act, int64_t a_bs, int act_relu,
                                                     const float* __restrict__ g, int64_t g_bs, int s, int ntiles,
                                                     float* __restrict__ partial) {
@@ -445,8 +498,7 @@ __global__ __launch_bounds__(256) void k_bwd_w_thin(const float* __restrict__ ac
   const float* __restrict__ thin = L3 ? g : act;
   const int64_t wide_bs = L3 ? a_bs : g_bs, thin_bs = L3 ? g_bs : a_bs;
   const int wide_relu = L3 ? act_relu : 0, thin_relu = L3 ? 0 : act_relu;
-  const TileGeo tg = tile_geo(s);
-  const int tiles_x = s / tg.TC, per_img = (s / tg.TR) * tiles_x;
+  using G = TileG<TC>;
   const int64_t per = static_cast<int64_t>(s) * s;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, kh = lane >> 5, l32 = lane & 31;
   const bool nv = l32 < NN;
@@ -455,23 +507,16 @@ __global__ __launch_bounds__(256) void k_bwd_w_thin(const float* __restrict__ ac
   f32x16 acc = {};
   float bsum = 0.0f;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int b = t / per_img, ti = t - b * per_img;
-    const int ty0 = (ti / tiles_x) * tg.TR, tx0 = (ti % tiles_x) * tg.TC;
-    const float* __restrict__ wb = wide + b * wide_bs;
-    for (int e = threadIdx.x; e < kF * kTileMax; e += 256) {
-      const int c = e >> 7, q = e & (kTileMax - 1);
-      const int yy = q / tg.TC, xx = q - yy * tg.TC;
-      float v = wb[c * per + static_cast<int64_t>(ty0 + yy) * s + tx0 + xx];
-      if (wide_relu) v = fmaxf(v, 0.0f);
-      sw[q * kMP + c] = v;
-    }
-    stage_halo<C>(thin + b * thin_bs, per, s, tg, ty0, tx0, thin_relu, sn, C);
+    int b, ty0, tx0;
+    tile_origin<TC>(t, s, b, ty0, tx0);
+    stage_tile32<TC>(wide + b * wide_bs, per, s, ty0, tx0, wide_relu, sw);
+    stage_halo<C, TC>(thin + b * thin_bs, per, s, ty0, tx0, thin_relu, sn, C);
     __syncthreads();
 #pragma unroll
     for (int st = 0; st < 16; ++st) {
       const int p = wv * 32 + 2 * st + kh;
-      const int ty = p / tg.TC, tx = p - ty * tg.TC;
-      const float bv = nv ? sn[((ty + nd / 3) * tg.W2 + tx + nd % 3) * C + nc] : 0.0f;
+      const int ty = p / TC, tx = p - ty * TC;
+      const float bv = nv ? sn[((ty + nd / 3) * G::W2 + tx + nd % 3) * C + nc] : 0.0f;
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(sw[p * kMP + l32], bv, acc, 0, 0, 0);
     }
     if (kh == 0) {
@@ -479,8 +524,8 @@ __global__ __launch_bounds__(256) void k_bwd_w_thin(const float* __restrict__ ac
         for (int p = 0; p < 32; ++p) bsum += sw[(wv * 32 + p) * kMP + l32];
       } else if (l32 < C) {
         for (int p = 0; p < 32; ++p) {
-          const int q = wv * 32 + p, ty = q / tg.TC, tx = q - ty * tg.TC;
-          bsum += sn[((ty + 1) * tg.W2 + tx + 1) * C + l32];
+          const int q = wv * 32 + p, ty = q / TC, tx = q - ty * TC;
+          bsum += sn[((ty + 1) * G::W2 + tx + 1) * C + l32];
         }
       }
     }
@@ -503,20 +548,34 @@ __global__ __launch_bounds__(256) void k_bwd_w_thin(const float* __restrict__ ac
   for (int e = threadIdx.x; e < NT; e += 256) partial[static_cast<int64_t>(blockIdx.x) * NT + e] = red[e];
 }
 
-// out[i] = sum over the partial rows b of partial[b][i]: a block takes 64
-// consecutive i, its four wavefronts the rows b = w, w + 4, ..., and the four
-// sums are added in a fixed order.
-__global__ __launch_bounds__(256) void k_sum_partials(const float* __restrict__ partial, int nblocks, int NT,
-                                                      float* __restrict__ out) {
-  __shared__ float red[4][64];
+// out[i] = sum over the partial rows b of partial[b][i]: a block of 16
+// wavefronts takes 64 consecutive i, wavefront w the rows b = w, w + 16, ...
+// (eight loads in flight per step), and the 16 sums are added in a fixed order.
+constexpr int kSumWaves = 16;
+__global__ __launch_bounds__(64 * kSumWaves) void k_sum_partials(const float* __restrict__ partial, int nblocks,
+                                                                 int NT, float* __restrict__ out) {
+  __shared__ float red[kSumWaves][64];
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i = blockIdx.x * 64 + l;
   float a = 0.0f;
-  if (i < NT)
-    for (int b = w; b < nblocks; b += 4) a += partial[static_cast<int64_t>(b) * NT + i];
+  if (i < NT) {
+    int b = w;
+    for (; b + 7 * kSumWaves < nblocks; b += 8 * kSumWaves) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = partial[static_cast<int64_t>(b + u * kSumWaves) * NT + i];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a += v[u];
+    }
+    for (; b < nblocks; b += kSumWaves) a += partial[static_cast<int64_t>(b) * NT + i];
+  }
   red[w][l] = a;
   __syncthreads();
-  if (w == 0 && i < NT) out[i] = (red[0][l] + red[1][l]) + (red[2][l] + red[3][l]);
+  if (w == 0 && i < NT) {
+    float t = 0.0f;
+    for (int k = 0; k < kSumWaves; ++k) t += red[k][l];
+    out[i] = t;
+  }
 }
 
 // g = 2 (pred - target) / (B N); per-block partial sums of (pred - target)^2 in float64.
@@ -571,11 +630,14 @@ struct wdb_cnn {
     int64_t off;
     int C, s;
     int64_t p[6];  // offsets of W1, b1, W2, b2, W3, b3
+    int64_t pk[4]; // offsets in wpk of the [k][o] weights: W1, W2, W2 flipped, W3 flipped
   };
   std::vector<Stack> stacks;
   int64_t nparam = 0;
   float* master = nullptr;
   uint16_t* wbf = nullptr;
+  uint16_t* wpk = nullptr;   // the matrix-core kernels' weights, [k][o] per stack (see pack_weights)
+  int64_t npk = 0;
   float* m = nullptr;
   float* v = nullptr;
   float* grad = nullptr;
@@ -627,20 +689,59 @@ void cnn_ensure(wdb_cnn* c, int B) {
   c->bcap = B;
 }
 
-// Grid of the matrix-core kernel: the block tiles of an image by the batch.
-dim3 mfma_grid(int s, int B) { return dim3(static_cast<unsigned>((s * s) / 128), static_cast<unsigned>(B)); }
+// Blocks of `kernel` (threads per block) resident on the current device at
+// once, looked up once per kernel.
+int resident_blocks(const void* kernel, int threads) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, int> cache;
+  int dev = 0;
+  WDB_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find({kernel, dev});
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  WDB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0));
+  WDB_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int n = std::max(1, std::min(kWGridMax, std::max(per_cu, 1) * std::max(cus, 1)));
+  cache[{kernel, dev}] = n;
+  return n;
+}
 
+template <class K>
+dim3 conv_grid(K kernel, int threads, int ntiles) {
+  return dim3(static_cast<unsigned>(std::min(ntiles, resident_blocks(reinterpret_cast<const void*>(kernel), threads))));
+}
+
+// The matrix-core kernels take 128-position tiles of 16 x 8 (side 16) or
+// 32 x 4 (larger sides) positions; with_tc calls f with that width.
+template <class F>
+void with_tc(int s, F&& f) {
+  if (s == 16)
+    f(std::integral_constant<int, 16>{});
+  else
+    f(std::integral_constant<int, 32>{});
+}
+
+// w: the layer's [out][in][tap] weights; wpk: the same packed for the
+// matrix-core kernel (layers with 32 outputs; unused otherwise).
 template <int CI, int CO>
 void conv_fwd(const float* in, int64_t in_bs, int in_relu, int s, int B, const uint16_t* w, const uint16_t* b,
-              float* out, int64_t out_bs, const float* resid, int64_t res_bs, hipStream_t st) {
+              const uint16_t* wpk, float* out, int64_t out_bs, const float* resid, int64_t res_bs, hipStream_t st) {
   if (s >= 16) {   // on the matrix cores
+    const int ntiles = static_cast<int>(static_cast<int64_t>(B) * s * s / kTileMax);
     if constexpr (CO == kF) {
-      hipLaunchKernelGGL((k_conv_mfma_in<CI, false>), mfma_grid(s, B), dim3(256), 0, st, in, in_bs, in_relu, s, w, b,
-                         out, out_bs, resid, res_bs, static_cast<const float*>(nullptr), int64_t{0});
+      with_tc(s, [&](auto tc) {
+        auto* k = k_conv_mfma_in<CI, false, decltype(tc)::value>;
+        hipLaunchKernelGGL(k, conv_grid(k, 256, ntiles), dim3(256), 0, st, in, in_bs, in_relu, s, ntiles, wpk, b, out,
+                           out_bs, resid, res_bs, static_cast<const float*>(nullptr), int64_t{0});
+      });
       return;
     } else if constexpr (CI == kF) {
-      hipLaunchKernelGGL(k_conv_mfma_out<CO>, mfma_grid(s, B), dim3(256), 0, st, in, in_bs, in_relu, s, w, b, out,
-                         out_bs, resid, res_bs);
+      with_tc(s, [&](auto tc) {
+        auto* k = k_conv_mfma_out<CO, decltype(tc)::value>;
+        hipLaunchKernelGGL(k, conv_grid(k, 256, ntiles), dim3(256), 0, st, in, in_bs, in_relu, s, ntiles, w, b, out,
+                           out_bs, resid, res_bs);
+      });
       return;
     }
   }
@@ -651,13 +752,17 @@ void conv_fwd(const float* in, int64_t in_bs, int in_relu, int s, int B, const u
 // Data gradient of a layer with CI inputs and CO outputs: a convolution of the
 // CO-channel gradient into CI channels.
 template <int CO, int CI>
-void conv_bwd_data(const float* g, int64_t g_bs, int s, int B, const uint16_t* w, const float* mask, int64_t m_bs,
-                   float* gin, int64_t gin_bs, hipStream_t st) {
+void conv_bwd_data(const float* g, int64_t g_bs, int s, int B, const uint16_t* w, const uint16_t* wpk,
+                   const float* mask, int64_t m_bs, float* gin, int64_t gin_bs, hipStream_t st) {
   if constexpr (CI == kF) {
     if (s >= 16) {
-      hipLaunchKernelGGL((k_conv_mfma_in<CO, true>), mfma_grid(s, B), dim3(256), 0, st, g, g_bs, 0, s, w,
-                         static_cast<const uint16_t*>(nullptr), gin, gin_bs, static_cast<const float*>(nullptr),
-                         int64_t{0}, mask, m_bs);
+      const int ntiles = static_cast<int>(static_cast<int64_t>(B) * s * s / kTileMax);
+      with_tc(s, [&](auto tc) {
+        auto* k = k_conv_mfma_in<CO, true, decltype(tc)::value>;
+        hipLaunchKernelGGL(k, conv_grid(k, 256, ntiles), dim3(256), 0, st, g, g_bs, 0, s, ntiles, wpk,
+                           static_cast<const uint16_t*>(nullptr), gin, gin_bs, static_cast<const float*>(nullptr),
+                           int64_t{0}, mask, m_bs);
+      });
       return;
     }
   }
@@ -672,23 +777,40 @@ void conv_bwd_w(const float* act, int64_t a_bs, int act_relu, const float* g, in
   const int NT = CO * CI * 9 + CO;
   if (s >= 16) {   // on the matrix cores
     const int ntiles = static_cast<int>(T / kTileMax);
-    const int nb = std::min(kWGridMax, ntiles);
-    if constexpr (CI == kF && CO == kF)
-      hipLaunchKernelGGL(k_conv32_bwd_w_mfma, dim3(nb), dim3(256), 0, st, act, a_bs, act_relu, g, g_bs, s, ntiles,
-                         partial);
-    else if constexpr (CI == kF)
-      hipLaunchKernelGGL((k_bwd_w_thin<CO, true>), dim3(nb), dim3(256), 0, st, act, a_bs, act_relu, g, g_bs, s,
-                         ntiles, partial);
-    else
-      hipLaunchKernelGGL((k_bwd_w_thin<CI, false>), dim3(nb), dim3(256), 0, st, act, a_bs, act_relu, g, g_bs, s,
-                         ntiles, partial);
-    hipLaunchKernelGGL(k_sum_partials, dim3((NT + 63) / 64), dim3(256), 0, st, partial, nb, NT, out);
+    int nb = 0;
+    with_tc(s, [&](auto tc) {
+      constexpr int TC = decltype(tc)::value;
+      if constexpr (CI == kF && CO == kF) {
+        auto* k = k_conv32_bwd_w_mfma<TC>;
+        const dim3 grid = conv_grid(k, kBwdThreads, ntiles);
+        nb = static_cast<int>(grid.x);
+        hipLaunchKernelGGL(k, grid, dim3(kBwdThreads), 0, st, act, a_bs, act_relu, g, g_bs, s, ntiles, partial);
+      } else {
+        auto* k = k_bwd_w_thin<CI == kF ? CO : CI, CI == kF, TC>;
+        const dim3 grid = conv_grid(k, 256, ntiles);
+        nb = static_cast<int>(grid.x);
+        hipLaunchKernelGGL(k, grid, dim3(256), 0, st, act, a_bs, act_relu, g, g_bs, s, ntiles, partial);
+      }
+    });
+    hipLaunchKernelGGL(k_sum_partials, dim3((NT + 63) / 64), dim3(64 * kSumWaves), 0, st, partial, nb, NT, out);
     return;
   }
   const int nb = static_cast<int>(std::min<int64_t>(kWGridMax, (T + kP - 1) / kP));
   hipLaunchKernelGGL((k_conv_bwd_w<CI, CO>), dim3(nb), dim3(kBlk), 0, st, act, a_bs, act_relu, g, g_bs, s, B,
                      partial);
-  hipLaunchKernelGGL(k_sum_partials, dim3((NT + 63) / 64), dim3(256), 0, st, partial, nb, NT, out);
+  hipLaunchKernelGGL(k_sum_partials, dim3((NT + 63) / 64), dim3(64 * kSumWaves), 0, st, partial, nb, NT, out);
+}
+
+// Refresh the packed [k][o] weights of the matrix-core kernels from the
+// bfloat16 parameters (after every change of wbf).
+void pack_weights(wdb_cnn* c, hipStream_t st) {
+  for (auto& S : c->stacks) {
+    uint16_t* pk = c->wpk;
+    const dim3 grid((9 * kF * kF + 255) / 256, 4);
+    hipLaunchKernelGGL(k_pack_stack, grid, dim3(256), 0, st, c->wbf + S.p[0], c->wbf + S.p[2], c->wbf + S.p[4], S.C,
+                       pk + S.pk[0], pk + S.pk[1], pk + S.pk[2], pk + S.pk[3]);
+  }
+  WDB_HIP(hipGetLastError());
 }
 
 void forward(wdb_cnn* c, const float* x0, int B, float* pred, hipStream_t st) {
@@ -697,12 +819,13 @@ void forward(wdb_cnn* c, const float* x0, int B, float* pred, hipStream_t st) {
     const int64_t per = static_cast<int64_t>(S.s) * S.s;
     const float* z = x0 + S.off;
     const uint16_t* w = c->wbf;
+    const uint16_t* pk = c->wpk;
     const int64_t hb = static_cast<int64_t>(kF) * per;
-    if (S.C == 1) conv_fwd<1, kF>(z, N, 0, S.s, B, w + S.p[0], w + S.p[1], c->a1, hb, nullptr, 0, st);
-    else conv_fwd<3, kF>(z, N, 0, S.s, B, w + S.p[0], w + S.p[1], c->a1, hb, nullptr, 0, st);
-    conv_fwd<kF, kF>(c->a1, hb, 1, S.s, B, w + S.p[2], w + S.p[3], c->a2, hb, nullptr, 0, st);
-    if (S.C == 1) conv_fwd<kF, 1>(c->a2, hb, 1, S.s, B, w + S.p[4], w + S.p[5], pred + S.off, N, z, N, st);
-    else conv_fwd<kF, 3>(c->a2, hb, 1, S.s, B, w + S.p[4], w + S.p[5], pred + S.off, N, z, N, st);
+    if (S.C == 1) conv_fwd<1, kF>(z, N, 0, S.s, B, w + S.p[0], w + S.p[1], pk + S.pk[0], c->a1, hb, nullptr, 0, st);
+    else conv_fwd<3, kF>(z, N, 0, S.s, B, w + S.p[0], w + S.p[1], pk + S.pk[0], c->a1, hb, nullptr, 0, st);
+    conv_fwd<kF, kF>(c->a1, hb, 1, S.s, B, w + S.p[2], w + S.p[3], pk + S.pk[1], c->a2, hb, nullptr, 0, st);
+    if (S.C == 1) conv_fwd<kF, 1>(c->a2, hb, 1, S.s, B, w + S.p[4], w + S.p[5], nullptr, pred + S.off, N, z, N, st);
+    else conv_fwd<kF, 3>(c->a2, hb, 1, S.s, B, w + S.p[4], w + S.p[5], nullptr, pred + S.off, N, z, N, st);
   }
   WDB_HIP(hipGetLastError());
 }
@@ -722,23 +845,24 @@ double loss_grad(wdb_cnn* c, const float* x0, const float* tgt, int B, hipStream
     const int64_t hb = static_cast<int64_t>(kF) * per;
     const float* z = x0 + S.off;
     const uint16_t* w = c->wbf;
+    const uint16_t* pk = c->wpk;
     // recompute this stack's activations
-    if (S.C == 1) conv_fwd<1, kF>(z, N, 0, S.s, B, w + S.p[0], w + S.p[1], c->a1, hb, nullptr, 0, st);
-    else conv_fwd<3, kF>(z, N, 0, S.s, B, w + S.p[0], w + S.p[1], c->a1, hb, nullptr, 0, st);
-    conv_fwd<kF, kF>(c->a1, hb, 1, S.s, B, w + S.p[2], w + S.p[3], c->a2, hb, nullptr, 0, st);
+    if (S.C == 1) conv_fwd<1, kF>(z, N, 0, S.s, B, w + S.p[0], w + S.p[1], pk + S.pk[0], c->a1, hb, nullptr, 0, st);
+    else conv_fwd<3, kF>(z, N, 0, S.s, B, w + S.p[0], w + S.p[1], pk + S.pk[0], c->a1, hb, nullptr, 0, st);
+    conv_fwd<kF, kF>(c->a1, hb, 1, S.s, B, w + S.p[2], w + S.p[3], pk + S.pk[1], c->a2, hb, nullptr, 0, st);
     const float* g = c->gout + S.off;
     float* gr = c->grad;
     // layer 3: out = z + conv(h2; W3, b3)
     if (S.C == 1) {
       conv_bwd_w<kF, 1>(c->a2, hb, 1, g, N, S.s, B, c->partial, gr + S.p[4], st);
-      conv_bwd_data<1, kF>(g, N, S.s, B, w + S.p[4], c->a2, hb, c->ga, hb, st);
+      conv_bwd_data<1, kF>(g, N, S.s, B, w + S.p[4], pk + S.pk[3], c->a2, hb, c->ga, hb, st);
     } else {
       conv_bwd_w<kF, 3>(c->a2, hb, 1, g, N, S.s, B, c->partial, gr + S.p[4], st);
-      conv_bwd_data<3, kF>(g, N, S.s, B, w + S.p[4], c->a2, hb, c->ga, hb, st);
+      conv_bwd_data<3, kF>(g, N, S.s, B, w + S.p[4], pk + S.pk[3], c->a2, hb, c->ga, hb, st);
     }
     // layer 2
     conv_bwd_w<kF, kF>(c->a1, hb, 1, c->ga, hb, S.s, B, c->partial, gr + S.p[2], st);
-    conv_bwd_data<kF, kF>(c->ga, hb, S.s, B, w + S.p[2], c->a1, hb, c->gb, hb, st);
+    conv_bwd_data<kF, kF>(c->ga, hb, S.s, B, w + S.p[2], pk + S.pk[2], c->a1, hb, c->gb, hb, st);
     // layer 1
     if (S.C == 1) conv_bwd_w<1, kF>(z, N, 0, c->gb, hb, S.s, B, c->partial, gr + S.p[0], st);
     else conv_bwd_w<3, kF>(z, N, 0, c->gb, hb, S.s, B, c->partial, gr + S.p[0], st);
@@ -776,12 +900,19 @@ wdb_status wdb_cnn_create(int32_t n, int32_t levels, int32_t features, uint64_t 
     c->N = static_cast<int64_t>(n) * n;
     const std::vector<Subband> lay = layout(n, levels);
     int64_t pos = 0;
+    int64_t pkpos = 0;
     auto add = [&](int64_t off, int C, int s) {
-      wdb_cnn::Stack S{off, C, s, {0, 0, 0, 0, 0, 0}};
+      wdb_cnn::Stack S{off, C, s, {0, 0, 0, 0, 0, 0}, {0, 0, 0, 0}};
       const int64_t sizes[6] = {int64_t(kF) * C * 9, kF, int64_t(kF) * kF * 9, kF, int64_t(C) * kF * 9, C};
       for (int k = 0; k < 6; ++k) {
         S.p[k] = pos;
         pos += sizes[k];
+      }
+      const int kpc = 9 * C + ((9 * C) & 1);
+      const int64_t pks[4] = {int64_t(kpc) * kF, int64_t(9) * kF * kF, int64_t(9) * kF * kF, int64_t(kpc) * kF};
+      for (int k = 0; k < 4; ++k) {
+        S.pk[k] = pkpos;
+        pkpos += pks[k];   // multiples of 32 entries: every matrix starts 64-byte aligned
       }
       c->stacks.push_back(S);
     };
@@ -808,6 +939,8 @@ wdb_status wdb_cnn_create(int32_t n, int32_t levels, int32_t features, uint64_t 
     }
     WDB_HIP(hipMalloc(reinterpret_cast<void**>(&c->master), pos * sizeof(float)));
     WDB_HIP(hipMalloc(reinterpret_cast<void**>(&c->wbf), pos * sizeof(uint16_t)));
+    c->npk = pkpos;
+    WDB_HIP(hipMalloc(reinterpret_cast<void**>(&c->wpk), pkpos * sizeof(uint16_t)));
     WDB_HIP(hipMalloc(reinterpret_cast<void**>(&c->m), pos * sizeof(float)));
     WDB_HIP(hipMalloc(reinterpret_cast<void**>(&c->v), pos * sizeof(float)));
     WDB_HIP(hipMalloc(reinterpret_cast<void**>(&c->grad), pos * sizeof(float)));
@@ -815,6 +948,7 @@ wdb_status wdb_cnn_create(int32_t n, int32_t levels, int32_t features, uint64_t 
     WDB_HIP(hipMemset(c->m, 0, pos * sizeof(float)));
     WDB_HIP(hipMemset(c->v, 0, pos * sizeof(float)));
     hipLaunchKernelGGL(k_round_bf16, grid_for(pos), dim3(kBlk), 0, nullptr, c->master, c->wbf, pos);
+    pack_weights(c, nullptr);
     WDB_HIP(hipGetLastError());
     WDB_HIP(hipDeviceSynchronize());
   } catch (...) {
@@ -844,6 +978,7 @@ wdb_status wdb_cnn_set_params(wdb_cnn* c, const float* host, int64_t count) {
   WDB_HIP(hipMemset(c->v, 0, count * sizeof(float)));
   c->t = 0;
   hipLaunchKernelGGL(k_round_bf16, grid_for(count), dim3(kBlk), 0, nullptr, c->master, c->wbf, count);
+  pack_weights(c, nullptr);
   WDB_HIP(hipGetLastError());
   WDB_HIP(hipDeviceSynchronize());
   WDB_API_END
@@ -906,6 +1041,7 @@ wdb_status wdb_cnn_train_step(wdb_cnn* c, const float* x0, const float* target, 
   const float c2 = static_cast<float>(1.0 - std::pow(b2, static_cast<double>(c->t)));
   hipLaunchKernelGGL(k_adam, grid_for(c->nparam), dim3(kBlk), 0, st, c->master, c->m, c->v, c->grad, c->nparam, lr,
                      static_cast<float>(b1), static_cast<float>(b2), c1, c2, 1e-8f, c->wbf);
+  pack_weights(c, st);
   WDB_HIP(hipGetLastError());
   if (loss) *loss = L;
   WDB_API_END
@@ -920,6 +1056,7 @@ void wdb_cnn_free(wdb_cnn* c) {
   for (float* p : fs)
     if (p) (void)hipFree(p);
   if (c->wbf) (void)hipFree(c->wbf);
+  if (c->wpk) (void)hipFree(c->wpk);
   delete c;
 }
 
