@@ -207,17 +207,35 @@ __global__ __launch_bounds__(kBlock) void k_prox_batched(const ChunkDev* __restr
   const int k = *kdev;
   const float beta = static_cast<float>((static_cast<double>(k) - 1.0) / (static_cast<double>(k) + 2.0));
   const float pi = C.pinv ? C.pinv[row] : 1.0f;
-  float* X = C.X + row * kR;
-  float* Y = C.Y + row * kR;
-  const double* An = C.Anc + row * kR;
+  // the row's eight slots as whole 16-byte vectors (a stopped problem's slots
+  // are written back unchanged), so every store fills its 32-byte segments
+  float4* X4 = reinterpret_cast<float4*>(C.X + row * kR);
+  float4* Y4 = reinterpret_cast<float4*>(C.Y + row * kR);
+  const double2* A2 = reinterpret_cast<const double2*>(C.Anc + row * kR);
+  float x[kR], y[kR];
+  double a[kR];
+  {
+    const float4 x0 = X4[0], x1 = X4[1], y0 = Y4[0], y1 = Y4[1];
+    x[0] = x0.x; x[1] = x0.y; x[2] = x0.z; x[3] = x0.w; x[4] = x1.x; x[5] = x1.y; x[6] = x1.z; x[7] = x1.w;
+    y[0] = y0.x; y[1] = y0.y; y[2] = y0.z; y[3] = y0.w; y[4] = y1.x; y[5] = y1.y; y[6] = y1.z; y[7] = y1.w;
+#pragma unroll
+    for (int j = 0; j < kR / 2; ++j) {
+      const double2 v = A2[j];
+      a[2 * j] = v.x;
+      a[2 * j + 1] = v.y;
+    }
+  }
 #pragma unroll
   for (int j = 0; j < kR; ++j) {
     if (!C.act[j]) continue;
-    const float xn = prox_anchored(An[j], Y[j], (C.tau * pi) * g[j], C.thr[j] * pi);
-    const float xo = X[j];
-    X[j] = xn;
-    Y[j] = xn + beta * (xn - xo);
+    const float xn = prox_anchored(a[j], y[j], (C.tau * pi) * g[j], C.thr[j] * pi);
+    y[j] = xn + beta * (xn - x[j]);
+    x[j] = xn;
   }
+  X4[0] = make_float4(x[0], x[1], x[2], x[3]);
+  X4[1] = make_float4(x[4], x[5], x[6], x[7]);
+  Y4[0] = make_float4(y[0], y[1], y[2], y[3]);
+  Y4[1] = make_float4(y[4], y[5], y[6], y[7]);
 }
 
 // float64 checks: per right-hand side sums of r^2, r.x0, |x| (forward) and
@@ -589,6 +607,12 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
     const size_t q = static_cast<size_t>(th->n / 2) * (th->n / 2);
     int* act = act_host.data() + static_cast<size_t>(c) * (kR + 1);
     Src8 x0s{}, inits{};
+    // data terms x0 = Psi^* u of the problems given as images: transformed
+    // together into the chunk's X block (slot j at j N), with the Y block as
+    // their scratch; both blocks are filled below
+    const float* us[kR];
+    float *xs[kR], *sa[kR], *sb[kR];
+    int nu = 0;
     for (int j = 0; j < kR; ++j) {
       d.thr[j] = 0.0f;
       if (j < static_cast<int>(h.idx.size())) {
@@ -596,14 +620,18 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
         d.thr[j] = static_cast<float>(tau * static_cast<double>(p.lambda));
         act[j] = 1;
         x0s.p[j] = p.x0;
-        if (!x0s.p[j]) {   // the data term x0 = Psi^* u, staged in the chunk's X block (filled below)
-          float* dst = d.X + static_cast<int64_t>(j) * N;
-          dwt_forward(th->n, th->levels, f, p.u, dst, th->ws_img, th->ws_img + q, s);
-          x0s.p[j] = dst;
+        if (!x0s.p[j]) {
+          us[nu] = p.u;
+          xs[nu] = d.X + static_cast<int64_t>(j) * N;
+          sa[nu] = d.Y + static_cast<int64_t>(j) * N;
+          sb[nu] = sa[nu] + q;
+          x0s.p[j] = xs[nu];
+          ++nu;
         }
         inits.p[j] = p.x_init;
       }
     }
+    if (nu) dwt_forward_many(th->n, th->levels, f, nu, us, xs, sa, sb, s);
     const dim3 g8(static_cast<unsigned>((N + 255) / 256));
     hipLaunchKernelGGL(k_interleave8, g8, dim3(256), 0, s, x0s, pX0.p + h.off, static_cast<float*>(nullptr), N);
     hipLaunchKernelGGL(k_interleave8, g8, dim3(256), 0, s, inits, d.X, d.Y, N);
