@@ -70,7 +70,11 @@ def layout_key(layout, tile_shape):
     return f"slice={layout[0]} group={layout[1]}"
 
 
-def profiled_traffic(workload, kernel, key):
+BATCHED_SOURCES = ("paper_1512_08401_amd/csrc/batch.hip", "paper_1512_08401_amd/csrc/codes.hpp",
+                   "paper_1512_08401_amd/csrc/common.hpp", "paper_1512_08401_amd/csrc/prox.hpp")
+
+
+def profiled_traffic(workload, kernel, key, sources=KERNEL_SOURCES):
     """HBM bytes per launch of ``kernel`` (for "fista_iteration": per iteration,
     both kernels) from a committed rocprofv3 counter summary under profiles/
     (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when no summary was
@@ -78,7 +82,7 @@ def profiled_traffic(workload, kernel, key):
     import glob
     import hashlib
     dig = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in sources:
         with open(os.path.join(ROOT, rel), "rb") as f:
             dig.update(f.read())
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
@@ -168,7 +172,7 @@ def main():
                     help="plain: the single-problem solve (default); batched / learned: the extension workloads")
     ap.add_argument("--train-images", type=int, default=4096)
     ap.add_argument("--heldout-images", type=int, default=512)
-    ap.add_argument("--epochs", type=int, default=24)
+    ap.add_argument("--epochs", type=int, default=64)
     ap.add_argument("--target-tol", type=float, default=1e-6,
                     help="relative duality gap of the warm-start training targets (learned form)")
     args = ap.parse_args()
@@ -449,6 +453,41 @@ def run_batched(args):
             meta.append((gi, n))
         log(f"group {gi}: n={n} levels={g['levels']} nnz/px={g['nnz_per_px']} field={kind}")
     t_setup = time.perf_counter() - t0
+    # one batched iteration (both phases over all packs): slope between two
+    # fixed-length runs without checks, and its algorithmic bytes: per pack the
+    # operator's values and indices once per product (16 B per non-zero) and
+    # 8 right-hand sides x 40 B per coefficient (as in a single iteration)
+    packs = {}
+    for p in probs:
+        packs[id(p[0])] = p[0]
+    alg = sum(16 * t.info()["nnz"] + 8 * 40 * t.N for t in packs.values())
+    plain = [p[:3] for p in probs]
+    ts = []
+    for its in (100, 300):
+        wdb.solve_batched(plain, its, check_every=0)
+        e0, e1 = ev_pair(torch)
+        e0.record()
+        wdb.solve_batched(plain, its, check_every=0)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+    it_us = (ts[1] - ts[0]) / 200 * 1e6
+    ach = alg / (it_us * 1e-6) / 1e9
+    ceil = copy_ceiling(torch)
+    log(f"batched iteration {it_us:.1f} us, {ach:.0f} GB/s algorithmic")
+    roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": 8000.0, "unit": "GB/s",
+            "frac": round(ach / 8000.0, 4),
+            "traffic": profiled_traffic("batched", "batched_iteration", "packs of 8", BATCHED_SOURCES),
+            "kernel": "one batched iteration: k_res_batched + k_prox_batched over the 8 packs of 8",
+            "iteration_us": round(it_us, 2), "algorithmic_bytes": alg,
+            "copy_ceiling_gbs": round(ceil, 1), "frac_of_copy": round(ach / ceil, 3)}
+    config = {"workload": "batched: 8 operators (n in {128,256,512,1024}, db4, levels log2(n)-4, "
+                          "20-40 nnz/px) x 8 right-hand sides, lambda logU[1e-4,1e-2]",
+              "total_nnz": total_nnz}
+    if args.no_ttt:
+        return {"metric": "batched FISTA iteration, 64 problems", "value": round(1e6 / it_us, 1),
+                "unit": "batched iters/s", "higher_is_better": True, "n_gpus": 1, "dtype": "f32",
+                "data": "synthetic", "config": config, "roofline": roof, "setup_s": round(t_setup, 2)}
     # E* per problem: long batched run to a relative gap of 1e-8
     xs, inf = wdb.solve_batched([p[:3] for p in probs], 40000, check_every=100, tol=1e-8, use_graph=True)
     E0 = []
@@ -481,15 +520,17 @@ def run_batched(args):
         res[f"{target:.0e}"] = {"batched_s": round(t_batched, 4), "single_solves_s": round(t_single, 4),
                                 "speedup": round(t_single / t_batched, 2),
                                 "iters_batched_mean": float(np.mean([r["iters"] for r in binf])),
-                                "iters_single_mean": float(np.mean(single_iters))}
+                                "iters_single_mean": float(np.mean(single_iters)),
+                                # per operator (pack of 8): the pack iterates until its slowest problem stops
+                                "iters_by_operator": [[int(binf[8 * g + j]["iters"]) for j in range(8)]
+                                                      for g in range(len(groups))]}
         log(f"target {target:.0e}: batched {t_batched:.3f} s, 64 single solves {t_single:.3f} s")
     return {"metric": "time to rel. objective 1e-4, 64 problems (batched vs single)",
             "value": res["1e-04"]["batched_s"], "unit": "s", "higher_is_better": False, "n_gpus": 1,
             "dtype": "f32", "data": "synthetic",
-            "config": {"workload": "batched: 8 operators (n in {128,256,512,1024}, db4, levels log2(n)-4, "
-                                   "20-40 nnz/px) x 8 right-hand sides, lambda logU[1e-4,1e-2]",
-                       "total_nnz": total_nnz},
-            "targets": res, "E_star_converged": all(r["converged"] for r in inf), "setup_s": round(t_setup, 2)}
+            "config": config,
+            "targets": res, "E_star_converged": all(r["converged"] for r in inf), "setup_s": round(t_setup, 2),
+            "roofline": roof}
 
 
 def run_learned(args):
@@ -497,7 +538,10 @@ def run_learned(args):
     relative duality gap of 1e-6), then iterations and time to relative
     objective 1e-4 / 1e-6 / 1e-8 on 512 held-out images from the prediction
     (network inference included) vs from zero, located at iteration
-    resolution for 1e-4 (float64 check after every iteration)."""
+    resolution for 1e-4 (float64 check after every iteration).  Both timed
+    forms start from the images: the warm form transforms the batch once and
+    hands the coefficients to the network and to the solver, the zero form
+    hands the images to the solver, which transforms them."""
     import torch
     import synth
     from paper_1512_08401_amd import wdb, warmstart
@@ -510,7 +554,7 @@ def run_learned(args):
     ntrain = args.train_images
     t0 = time.perf_counter()
     U = [_observe(wdb, torch, field, n, 50000 + i, 150000 + i, wl.noise_sigma) for i in range(ntrain)]
-    X0 = torch.stack([wdb.dwt(u, wl.wavelet, J) for u in U])
+    X0 = wdb.dwt_batched(torch.stack(U), wl.wavelet, J)
     T = torch.empty_like(X0)
     tgt_iters, tgt_conv = [], []
     for b in range(0, ntrain, 512):
@@ -526,12 +570,13 @@ def run_learned(args):
     del U
     net = wdb.Cnn(n, J, 32, seed=1)
     t0 = time.perf_counter()
-    hist = warmstart.train(net, X0, T, args.epochs, 32, 1e-3, seed=2, log=log)
+    hist = warmstart.train(net, X0, T, args.epochs, 32, 1e-3, seed=2, log=log, final_lr=1e-5)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     nh = args.heldout_images
     Uh = [_observe(wdb, torch, field, n, 60000 + i, 160000 + i, wl.noise_sigma) for i in range(nh)]
-    X0h = torch.stack([wdb.dwt(u, wl.wavelet, J) for u in Uh])
+    Ub = torch.stack(Uh)
+    X0h = wdb.dwt_batched(Ub, wl.wavelet, J)
     xstar, star = wdb.solve_batched([(th, u, lam) for u in Uh], 40000, check_every=100, tol=1e-8, use_graph=True)
     E0 = 0.5 * (X0h.double() ** 2).sum(dim=1).cpu().numpy()
     Xs = torch.stack(xstar)
@@ -549,9 +594,15 @@ def run_learned(args):
                 e0, e1 = ev(), ev()
                 torch.cuda.synchronize()
                 e0.record()
-                init = net.predict(X0h.reshape(-1).contiguous()).reshape(nh, -1) if form == "warm" else None
-                _, r = wdb.solve_batched([(th, Uh[i], lam, None if init is None else init[i].contiguous(), tgt[i])
-                                          for i in range(nh)], 40000, check_every=every, use_graph=every > 1)
+                if form == "warm":
+                    # x0 = Psi^* u once for the batch, shared by the network and the solver
+                    X0t = wdb.dwt_batched(Ub, wl.wavelet, J)
+                    init = net.predict(X0t.reshape(-1)).reshape(nh, -1)
+                    _, r = wdb.solve_batched([(th, X0t[i], lam, init[i], tgt[i]) for i in range(nh)], 40000,
+                                             check_every=every, use_graph=every > 1, coeffs=True)
+                else:
+                    _, r = wdb.solve_batched([(th, Uh[i], lam, None, tgt[i]) for i in range(nh)], 40000,
+                                             check_every=every, use_graph=every > 1)
                 e1.record()
                 torch.cuda.synchronize()
             out[f"{target:.0e}"][form] = {"seconds": e0.elapsed_time(e1) / 1e3,
@@ -570,6 +621,8 @@ def run_learned(args):
             "training_targets": {"iters_mean": float(np.mean(tgt_iters)), "converged": int(sum(tgt_conv)),
                                  "of": len(tgt_conv), "tol_rel_gap": args.target_tol},
             "E_star_converged": int(sum(r["converged"] for r in star)),
+            # the relative duality gap bounds E* - E_min relative to E, hence the uncertainty of every rho
+            "E_star_rel_gap_max": float(max(r["rel_gap"] for r in star)),
             "train_loss_first_last": [hist[0], hist[-1]], "targets_s": round(t_targets, 2),
             "train_s": round(t_train, 2)}
 
