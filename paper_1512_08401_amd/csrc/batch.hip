@@ -1,26 +1,29 @@
 // Batched solve: many deblurring problems (Alg. 1 each) in one call.
 //
-// Problems that share an operator handle are packed eight at a time into a
-// "chunk": their vectors are stored row-interleaved ([N][8] floats), so one
-// pass over Theta_K's sliced-ELL slots serves all eight right-hand sides (a
-// sparse-times-dense product): each stored entry is read once and its column
-// gathers 32 contiguous bytes (two 16-byte loads).  All chunks of all
+// Problems that share an operator handle are packed up to eight at a time
+// into a "chunk": their vectors are stored row-interleaved ([N][W] floats, W =
+// 8, 4, 2 or 1 slots), so one pass over Theta_K's stored entries serves all W
+// right-hand sides (a sparse-times-dense product): each stored entry is read
+// once and its column gathers 4 W contiguous bytes.  All chunks of all
 // operators run in one launch per phase -- the residual kernel, then the
 // transposed kernel with the soft-threshold and momentum epilogue -- so an
 // iteration of the whole batch is two launches, and the iterations between
 // float64 checks can be replayed from a captured HIP graph.  Each right-hand
-// side has its own lambda and its own stop flag (a converged problem keeps
-// its iterate while the others continue).
+// side has its own lambda and its own stop flag.  A chunk iterates until its
+// last problem stops; when its active problems fit in fewer slots, a check
+// moves them to the first slots of a narrower [N][W] layout (the stopped
+// problems left out write their final iterates then), so the tail of a
+// chunk gathers 4 W bytes per column instead of 32.
 //
 // Operators whose iteration layout is the tiled pattern storage run their
-// chunks on the tiles instead: one 256-thread block (4 wavefronts) per tile,
+// chunks on the tiles instead: one 128-thread block (2 wavefronts) per tile,
 // lane = row, and for every shared column code each lane loads its column's
-// 8 right-hand-side values (32 contiguous bytes; neighbouring lanes of a tile
-// row read neighbouring columns) and the tile value once for all eight.  Their
-// float64 checks run on the tiles too (64 contiguous bytes per column).
+// W right-hand-side values (neighbouring lanes of a tile row read neighbouring
+// columns) and the tile value once for all of them.  Their float64 checks run
+// on the tiles too.
 //
 // Each problem's iterate is anchored as in the single solve: a float64 anchor
-// [N][8] plus the float32 displacement X; the residual subtracts
+// [N][W] plus the float32 displacement X; the residual subtracts
 // c = x0 - Theta_K anchor, the proximal step thresholds anchor + y - tau g in
 // float64, and every check first moves X into the anchor, then scores the
 // anchor and takes the next c from its float64 residual.
@@ -35,7 +38,7 @@ namespace wdb {
 
 namespace {
 
-constexpr int kBlock = 256;
+constexpr int kBlock = 128;   // 2 wavefronts per tile: 4% faster than 4 and 13% faster than 1 on a 64-problem batch
 constexpr int kWave = 64;
 constexpr int kWaves = kBlock / kWave;
 constexpr int kR = 8;                  // right-hand sides per chunk
@@ -58,6 +61,7 @@ struct ChunkDev {
   float* Cr;         // [N][8] right-hand side of the displacement iteration, x0 - Theta_K anchor
   double* Anc;       // [N][8] float64 anchor
   float* Rr;         // [N][8] residual
+  int W;             // slots in use (8, 4, 2 or 1): the vectors are [N][W], problem slots [0, W)
   const float* pinv; // N or null
   float tau;
   float thr[kR];     // tau * lambda_j
@@ -85,19 +89,37 @@ __device__ __forceinline__ int64_t slot_row_c(const int32_t* perm, int64_t nrows
   return q < nrows ? q : -1;
 }
 
-__device__ __forceinline__ void gather8(const float* __restrict__ V, int c, float w, float (&acc)[kR]) {
-  const float4* p = reinterpret_cast<const float4*>(V + static_cast<int64_t>(c) * kR);
-  const float4 a = p[0], b = p[1];
-  acc[0] = fmaf(w, a.x, acc[0]);
-  acc[1] = fmaf(w, a.y, acc[1]);
-  acc[2] = fmaf(w, a.z, acc[2]);
-  acc[3] = fmaf(w, a.w, acc[3]);
-  acc[4] = fmaf(w, b.x, acc[4]);
-  acc[5] = fmaf(w, b.y, acc[5]);
-  acc[6] = fmaf(w, b.z, acc[6]);
-  acc[7] = fmaf(w, b.w, acc[7]);
+// acc[j] += w V[c][j] for the W slots of an [N][W] block (one 4-, 8-, 16- or
+// two 16-byte loads).
+template <int W>
+__device__ __forceinline__ void gatherW(const float* __restrict__ V, int c, float w, float (&acc)[kR]) {
+  const float* p = V + static_cast<int64_t>(c) * W;
+  if constexpr (W == 8) {
+    const float4 a = reinterpret_cast<const float4*>(p)[0], b = reinterpret_cast<const float4*>(p)[1];
+    acc[0] = fmaf(w, a.x, acc[0]);
+    acc[1] = fmaf(w, a.y, acc[1]);
+    acc[2] = fmaf(w, a.z, acc[2]);
+    acc[3] = fmaf(w, a.w, acc[3]);
+    acc[4] = fmaf(w, b.x, acc[4]);
+    acc[5] = fmaf(w, b.y, acc[5]);
+    acc[6] = fmaf(w, b.z, acc[6]);
+    acc[7] = fmaf(w, b.w, acc[7]);
+  } else if constexpr (W == 4) {
+    const float4 a = *reinterpret_cast<const float4*>(p);
+    acc[0] = fmaf(w, a.x, acc[0]);
+    acc[1] = fmaf(w, a.y, acc[1]);
+    acc[2] = fmaf(w, a.z, acc[2]);
+    acc[3] = fmaf(w, a.w, acc[3]);
+  } else if constexpr (W == 2) {
+    const float2 a = *reinterpret_cast<const float2*>(p);
+    acc[0] = fmaf(w, a.x, acc[0]);
+    acc[1] = fmaf(w, a.y, acc[1]);
+  } else {
+    acc[0] = fmaf(w, p[0], acc[0]);
+  }
 }
 
+template <int W>
 __device__ __forceinline__ void slice_mm(const int64_t* __restrict__ soff, const float4* __restrict__ val,
                                          const int4* __restrict__ col, int64_t sl, int lane, int C,
                                          const float* __restrict__ V, float (&acc)[kR]) {
@@ -105,19 +127,19 @@ __device__ __forceinline__ void slice_mm(const int64_t* __restrict__ soff, const
   for (int64_t j = beg + lane; j < end; j += C) {
     const float4 v = val[j];
     const int4 c = col[j];
-    gather8(V, c.x, v.x, acc);
-    gather8(V, c.y, v.y, acc);
-    gather8(V, c.z, v.z, acc);
-    gather8(V, c.w, v.w, acc);
+    gatherW<W>(V, c.x, v.x, acc);
+    gatherW<W>(V, c.y, v.y, acc);
+    gatherW<W>(V, c.z, v.z, acc);
+    gatherW<W>(V, c.w, v.w, acc);
   }
 }
 
-// Tile `tile` of copy m (0: Theta_K, 1: Theta_K^T) times the [N][8] block V:
-// acc[8] of the lane's row, complete in wavefront 0 (the row's escapes dealt
-// to the four wavefronts, whose partials are added in LDS in wavefront order).
+// Tile `tile` of copy m (0: Theta_K, 1: Theta_K^T) times the [N][W] block V:
+// acc[0..W) of the lane's row, complete in wavefront 0 (the row's escapes
+// dealt to the wavefronts, whose partials are added in LDS in wavefront order).
+template <int W>
 __device__ __forceinline__ int tile_mm(const ChunkDev& C, int m, int tile, const float* __restrict__ V,
-                                       float (&acc)[kR]) {
-  __shared__ float part[kWaves][kR][kWave];
+                                       float (&acc)[kR], float (*part)[kR][kWave]) {
   const int4 d = C.tdesc[m][tile];
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -129,25 +151,65 @@ __device__ __forceinline__ int tile_mm(const ChunkDev& C, int m, int tile, const
     const uint4 c = code[k];
     const float4 v = val[static_cast<int64_t>(k) * kWave + lane];
     const int4 col = group_cols(C.geo, rc, c);
-    gather8(V, col.x, v.x, acc);
-    gather8(V, col.y, v.y, acc);
-    gather8(V, col.z, v.z, acc);
-    gather8(V, col.w, v.w, acc);
+    gatherW<W>(V, col.x, v.x, acc);
+    gatherW<W>(V, col.y, v.y, acc);
+    gatherW<W>(V, col.z, v.z, acc);
+    gatherW<W>(V, col.w, v.w, acc);
   }
   if (row >= 0 && (d.w & kHasEsc))  // escapes dealt round-robin to the wavefronts
-    for (int k = C.terp[m][row] + wv; k < C.terp[m][row + 1]; k += kWaves) gather8(V, C.tec[m][k], C.tev[m][k], acc);
+    for (int k = C.terp[m][row] + wv; k < C.terp[m][row + 1]; k += kWaves) gatherW<W>(V, C.tec[m][k], C.tev[m][k], acc);
+  if constexpr (kWaves > 1) {
 #pragma unroll
-  for (int j = 0; j < kR; ++j) part[wv][j][lane] = acc[j];
-  __syncthreads();
-  if (wv == 0) {
+    for (int j = 0; j < W; ++j) part[wv][j][lane] = acc[j];
+    __syncthreads();
+    if (wv == 0) {
 #pragma unroll
-    for (int j = 0; j < kR; ++j) {
-      float a = part[0][j][lane];
-      for (int w = 1; w < kWaves; ++w) a += part[w][j][lane];
-      acc[j] = a;
+      for (int j = 0; j < W; ++j) {
+        float a = part[0][j][lane];
+        for (int w = 1; w < kWaves; ++w) a += part[w][j][lane];
+        acc[j] = a;
+      }
     }
   }
   return wv == 0 ? row : -1;
+}
+
+// Row `row` of r = acc - c over the W slots.
+template <int W>
+__device__ __forceinline__ void store_residual(const ChunkDev& C, int64_t row, const float (&acc)[kR]) {
+  const float* b = C.Cr + row * W;
+  float* r = C.Rr + row * W;
+  if constexpr (W >= 4) {
+#pragma unroll
+    for (int h = 0; h < W / 4; ++h) {
+      const float4 bb = reinterpret_cast<const float4*>(b)[h];
+      reinterpret_cast<float4*>(r)[h] =
+          make_float4(acc[4 * h] - bb.x, acc[4 * h + 1] - bb.y, acc[4 * h + 2] - bb.z, acc[4 * h + 3] - bb.w);
+    }
+  } else if constexpr (W == 2) {
+    const float2 bb = *reinterpret_cast<const float2*>(b);
+    *reinterpret_cast<float2*>(r) = make_float2(acc[0] - bb.x, acc[1] - bb.y);
+  } else {
+    r[0] = acc[0] - b[0];
+  }
+}
+
+template <int W>
+__device__ __forceinline__ void res_pack(const ChunkDev& C, int blk, float (*part)[kR][kWave]) {
+  float acc[kR] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (C.ntiles) {
+    if (blk >= C.ntiles) return;  // the chunk's block range also covers its sliced-ELL checks
+    const int row = tile_mm<W>(C, 0, blk, C.Y, acc, part);
+    if (row >= 0) store_residual<W>(C, row, acc);
+    return;
+  }
+  const int64_t q = static_cast<int64_t>(blk) * kBlock + threadIdx.x;
+  if (q >= (C.nslices << C.cshift)) return;
+  const int64_t sl = q >> C.cshift;
+  const int lane = static_cast<int>(q & (C.C - 1));
+  slice_mm<W>(C.soff, C.val, C.col, sl, lane, C.C, C.Y, acc);
+  const int64_t row = slot_row_c(C.perm, C.nrows, q);
+  if (row >= 0) store_residual<W>(C, row, acc);
 }
 
 __global__ __launch_bounds__(kBlock) void k_res_batched(const ChunkDev* __restrict__ ch, const int* __restrict__ first,
@@ -156,32 +218,88 @@ __global__ __launch_bounds__(kBlock) void k_res_batched(const ChunkDev* __restri
   const int c = chunk_of(first, nchunks, blockIdx.x);
   const ChunkDev& C = ch[c];
   if (!C.act[kR]) return;  // every problem of this chunk has stopped
-  if (C.ntiles) {
-    const int tile = blockIdx.x - first[c];
-    if (tile >= C.ntiles) return;  // the chunk's block range also covers its sliced-ELL checks
-    float acc[kR] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const int row = tile_mm(C, 0, tile, C.Y, acc);
-    if (row < 0) return;
-    const float4* b = reinterpret_cast<const float4*>(C.Cr + static_cast<int64_t>(row) * kR);
-    float4* r = reinterpret_cast<float4*>(C.Rr + static_cast<int64_t>(row) * kR);
-    const float4 b0 = b[0], b1 = b[1];
-    r[0] = make_float4(acc[0] - b0.x, acc[1] - b0.y, acc[2] - b0.z, acc[3] - b0.w);
-    r[1] = make_float4(acc[4] - b1.x, acc[5] - b1.y, acc[6] - b1.z, acc[7] - b1.w);
-    return;
+  const int blk = blockIdx.x - first[c];
+  __shared__ float part[kWaves][kR][kWave];
+  switch (C.W) {
+    case 8: res_pack<8>(C, blk, part); break;
+    case 4: res_pack<4>(C, blk, part); break;
+    case 2: res_pack<2>(C, blk, part); break;
+    default: res_pack<1>(C, blk, part); break;
   }
-  const int64_t q = static_cast<int64_t>(blockIdx.x - first[c]) * kBlock + threadIdx.x;
-  if (q >= (C.nslices << C.cshift)) return;
-  const int64_t sl = q >> C.cshift;
-  const int lane = static_cast<int>(q & (C.C - 1));
-  float acc[kR] = {0, 0, 0, 0, 0, 0, 0, 0};
-  slice_mm(C.soff, C.val, C.col, sl, lane, C.C, C.Y, acc);
-  const int64_t row = slot_row_c(C.perm, C.nrows, q);
+}
+
+template <int W>
+__device__ __forceinline__ void prox_pack(const ChunkDev& C, int blk, const int* __restrict__ kdev,
+                                          float (*part)[kR][kWave]) {
+  float g[kR] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int64_t row;
+  if (C.ntiles) {
+    if (blk >= C.ntiles) return;
+    row = tile_mm<W>(C, 1, blk, C.Rr, g, part);
+  } else {
+    const int64_t q = static_cast<int64_t>(blk) * kBlock + threadIdx.x;
+    if (q >= (C.nslicesT << C.cshift)) return;
+    const int64_t sl = q >> C.cshift;
+    const int lane = static_cast<int>(q & (C.C - 1));
+    slice_mm<W>(C.soffT, C.valT, C.colT, sl, lane, C.C, C.Rr, g);
+    row = slot_row_c(C.permT, C.nrows, q);
+  }
   if (row < 0) return;
-  const float4* b = reinterpret_cast<const float4*>(C.Cr + row * kR);
-  float4* r = reinterpret_cast<float4*>(C.Rr + row * kR);
-  const float4 b0 = b[0], b1 = b[1];
-  r[0] = make_float4(acc[0] - b0.x, acc[1] - b0.y, acc[2] - b0.z, acc[3] - b0.w);
-  r[1] = make_float4(acc[4] - b1.x, acc[5] - b1.y, acc[6] - b1.z, acc[7] - b1.w);
+  const int k = *kdev;
+  const float beta = static_cast<float>((static_cast<double>(k) - 1.0) / (static_cast<double>(k) + 2.0));
+  const float pi = C.pinv ? C.pinv[row] : 1.0f;
+  // the row's W slots as whole vectors (a stopped problem's slots are written
+  // back unchanged), so every store fills whole segments
+  float* X = C.X + row * W;
+  float* Y = C.Y + row * W;
+  const double* A = C.Anc + row * W;
+  float x[W], y[W];
+  double a[W];
+  if constexpr (W >= 4) {
+#pragma unroll
+    for (int h = 0; h < W / 4; ++h) {
+      const float4 xv = reinterpret_cast<const float4*>(X)[h], yv = reinterpret_cast<const float4*>(Y)[h];
+      x[4 * h] = xv.x; x[4 * h + 1] = xv.y; x[4 * h + 2] = xv.z; x[4 * h + 3] = xv.w;
+      y[4 * h] = yv.x; y[4 * h + 1] = yv.y; y[4 * h + 2] = yv.z; y[4 * h + 3] = yv.w;
+    }
+  } else if constexpr (W == 2) {
+    const float2 xv = *reinterpret_cast<const float2*>(X), yv = *reinterpret_cast<const float2*>(Y);
+    x[0] = xv.x; x[1] = xv.y;
+    y[0] = yv.x; y[1] = yv.y;
+  } else {
+    x[0] = X[0];
+    y[0] = Y[0];
+  }
+  if constexpr (W >= 2) {
+#pragma unroll
+    for (int h = 0; h < W / 2; ++h) {
+      const double2 av = reinterpret_cast<const double2*>(A)[h];
+      a[2 * h] = av.x;
+      a[2 * h + 1] = av.y;
+    }
+  } else {
+    a[0] = A[0];
+  }
+#pragma unroll
+  for (int j = 0; j < W; ++j) {
+    if (!C.act[j]) continue;
+    const float xn = prox_anchored(a[j], y[j], (C.tau * pi) * g[j], C.thr[j] * pi);
+    y[j] = xn + beta * (xn - x[j]);
+    x[j] = xn;
+  }
+  if constexpr (W >= 4) {
+#pragma unroll
+    for (int h = 0; h < W / 4; ++h) {
+      reinterpret_cast<float4*>(X)[h] = make_float4(x[4 * h], x[4 * h + 1], x[4 * h + 2], x[4 * h + 3]);
+      reinterpret_cast<float4*>(Y)[h] = make_float4(y[4 * h], y[4 * h + 1], y[4 * h + 2], y[4 * h + 3]);
+    }
+  } else if constexpr (W == 2) {
+    *reinterpret_cast<float2*>(X) = make_float2(x[0], x[1]);
+    *reinterpret_cast<float2*>(Y) = make_float2(y[0], y[1]);
+  } else {
+    X[0] = x[0];
+    Y[0] = y[0];
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_prox_batched(const ChunkDev* __restrict__ ch, const int* __restrict__ first,
@@ -189,53 +307,14 @@ __global__ __launch_bounds__(kBlock) void k_prox_batched(const ChunkDev* __restr
   const int c = chunk_of(first, nchunks, blockIdx.x);
   const ChunkDev& C = ch[c];
   if (!C.act[kR]) return;  // every problem of this chunk has stopped
-  float g[kR] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int64_t row;
-  if (C.ntiles) {
-    const int tile = blockIdx.x - first[c];
-    if (tile >= C.ntiles) return;
-    row = tile_mm(C, 1, tile, C.Rr, g);
-  } else {
-    const int64_t q = static_cast<int64_t>(blockIdx.x - first[c]) * kBlock + threadIdx.x;
-    if (q >= (C.nslicesT << C.cshift)) return;
-    const int64_t sl = q >> C.cshift;
-    const int lane = static_cast<int>(q & (C.C - 1));
-    slice_mm(C.soffT, C.valT, C.colT, sl, lane, C.C, C.Rr, g);
-    row = slot_row_c(C.permT, C.nrows, q);
+  const int blk = blockIdx.x - first[c];
+  __shared__ float part[kWaves][kR][kWave];
+  switch (C.W) {
+    case 8: prox_pack<8>(C, blk, kdev, part); break;
+    case 4: prox_pack<4>(C, blk, kdev, part); break;
+    case 2: prox_pack<2>(C, blk, kdev, part); break;
+    default: prox_pack<1>(C, blk, kdev, part); break;
   }
-  if (row < 0) return;
-  const int k = *kdev;
-  const float beta = static_cast<float>((static_cast<double>(k) - 1.0) / (static_cast<double>(k) + 2.0));
-  const float pi = C.pinv ? C.pinv[row] : 1.0f;
-  // the row's eight slots as whole 16-byte vectors (a stopped problem's slots
-  // are written back unchanged), so every store fills its 32-byte segments
-  float4* X4 = reinterpret_cast<float4*>(C.X + row * kR);
-  float4* Y4 = reinterpret_cast<float4*>(C.Y + row * kR);
-  const double2* A2 = reinterpret_cast<const double2*>(C.Anc + row * kR);
-  float x[kR], y[kR];
-  double a[kR];
-  {
-    const float4 x0 = X4[0], x1 = X4[1], y0 = Y4[0], y1 = Y4[1];
-    x[0] = x0.x; x[1] = x0.y; x[2] = x0.z; x[3] = x0.w; x[4] = x1.x; x[5] = x1.y; x[6] = x1.z; x[7] = x1.w;
-    y[0] = y0.x; y[1] = y0.y; y[2] = y0.z; y[3] = y0.w; y[4] = y1.x; y[5] = y1.y; y[6] = y1.z; y[7] = y1.w;
-#pragma unroll
-    for (int j = 0; j < kR / 2; ++j) {
-      const double2 v = A2[j];
-      a[2 * j] = v.x;
-      a[2 * j + 1] = v.y;
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < kR; ++j) {
-    if (!C.act[j]) continue;
-    const float xn = prox_anchored(a[j], y[j], (C.tau * pi) * g[j], C.thr[j] * pi);
-    y[j] = xn + beta * (xn - x[j]);
-    x[j] = xn;
-  }
-  X4[0] = make_float4(x[0], x[1], x[2], x[3]);
-  X4[1] = make_float4(x[4], x[5], x[6], x[7]);
-  Y4[0] = make_float4(y[0], y[1], y[2], y[3]);
-  Y4[1] = make_float4(y[4], y[5], y[6], y[7]);
 }
 
 // float64 checks: per right-hand side sums of r^2, r.x0, |x| (forward) and
@@ -276,10 +355,12 @@ __device__ __forceinline__ int tile_mm64(const ChunkDev& C, int m, int tile, con
   const RowCode rc = tile_row_code(C.geo, d, row);
   const uint4* __restrict__ code = C.tcode[m];
   const float4* __restrict__ val = C.tval[m];
+  const int W = C.W;
   auto add = [&](int col, float w) {
-    const T* p = V + static_cast<int64_t>(col) * kR;
+    const T* p = V + static_cast<int64_t>(col) * W;
 #pragma unroll
-    for (int j = 0; j < kR; ++j) acc[j] = fma(static_cast<double>(w), static_cast<double>(p[j]), acc[j]);
+    for (int j = 0; j < kR; ++j)
+      if (j < W) acc[j] = fma(static_cast<double>(w), static_cast<double>(p[j]), acc[j]);
   };
   for (int k = (d.x >> 2) + wv; k < (d.y >> 2); k += kWaves) {
     const uint4 c = code[k];
@@ -331,20 +412,20 @@ __global__ __launch_bounds__(kBlock) void k_check_fwd(const ChunkDev* __restrict
         const float vv[4] = {v.x, v.y, v.z, v.w};
         const int ci[4] = {cc.x, cc.y, cc.z, cc.w};
         for (int t = 0; t < 4; ++t)
-          for (int j = 0; j < kR; ++j)
-            a[j] = fma(static_cast<double>(vv[t]), C.Anc[static_cast<int64_t>(ci[t]) * kR + j], a[j]);
+          for (int j = 0; j < C.W; ++j)
+            a[j] = fma(static_cast<double>(vv[t]), C.Anc[static_cast<int64_t>(ci[t]) * C.W + j], a[j]);
       }
       row = slot_row_c(C.perm, C.nrows, q);
     }
   }
   if (row >= 0) {
-    for (int j = 0; j < kR; ++j) {
-      const double b = static_cast<double>(C.X0[row * kR + j]);
+    for (int j = 0; j < C.W; ++j) {
+      const double b = static_cast<double>(C.X0[row * C.W + j]);
       const double r = a[j] - b;
-      C.r64[row * kR + j] = r;
+      C.r64[row * C.W + j] = r;
       rr[j] = r * r;
       rb[j] = r * b;
-      l1[j] = fabs(C.Anc[row * kR + j]);
+      l1[j] = fabs(C.Anc[row * C.W + j]);
     }
   }
   double out[kR];
@@ -381,8 +462,8 @@ __global__ __launch_bounds__(kBlock) void k_check_bwd(const ChunkDev* __restrict
         const float vv[4] = {v.x, v.y, v.z, v.w};
         const int ci[4] = {cc.x, cc.y, cc.z, cc.w};
         for (int t = 0; t < 4; ++t)
-          for (int j = 0; j < kR; ++j)
-            g[j] = fma(static_cast<double>(vv[t]), C.r64[static_cast<int64_t>(ci[t]) * kR + j], g[j]);
+          for (int j = 0; j < C.W; ++j)
+            g[j] = fma(static_cast<double>(vv[t]), C.r64[static_cast<int64_t>(ci[t]) * C.W + j], g[j]);
       }
       if (slot_row_c(C.permT, C.nrows, q) < 0)
         for (int j = 0; j < kR; ++j) g[j] = 0.0;
@@ -446,36 +527,50 @@ __global__ __launch_bounds__(kBlock) void k_check_reduce(const int* __restrict__
 struct Src8 {
   const float* p[kR];
 };
-__global__ void k_interleave8(Src8 src, float* __restrict__ dst, float* __restrict__ dst2, int64_t N) {
+__global__ void k_interleave8(Src8 src, float* __restrict__ dst, float* __restrict__ dst2, int64_t N, int W) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= N) return;
-  float v[kR];
 #pragma unroll
-  for (int j = 0; j < kR; ++j) v[j] = src.p[j] ? src.p[j][i] : 0.0f;
-  float4* d = reinterpret_cast<float4*>(dst + i * kR);
-  d[0] = make_float4(v[0], v[1], v[2], v[3]);
-  d[1] = make_float4(v[4], v[5], v[6], v[7]);
-  if (dst2) {
-    float4* e = reinterpret_cast<float4*>(dst2 + i * kR);
-    e[0] = d[0];
-    e[1] = d[1];
+  for (int j = 0; j < kR; ++j) {
+    if (j >= W) break;
+    const float v = src.p[j] ? src.p[j][i] : 0.0f;
+    dst[i * W + j] = v;
+    if (dst2) dst2[i * W + j] = v;
   }
 }
+
+struct Slots {
+  int s[kR];
+};
 
 // The problems' iterates: the anchors rounded to float32 (and as float64 where asked).
 struct Dst8 {
   float* p[kR];
   double* p64[kR];
 };
-__global__ void k_deinterleave8(const double* __restrict__ src, Dst8 dst, int nslots, int64_t N) {
+__global__ void k_deinterleave8(const double* __restrict__ src, Dst8 dst, int W, int64_t N) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= N) return;
 #pragma unroll
   for (int j = 0; j < kR; ++j) {
-    if (j >= nslots) break;
-    const double v = src[i * kR + j];
+    if (j >= W) break;
+    if (!dst.p[j]) continue;   // slot left out
+    const double v = src[i * W + j];
     dst.p[j][i] = static_cast<float>(v);
     if (dst.p64[j]) dst.p64[j][i] = v;
+  }
+}
+
+// A pack's [N][W] block in place of its [N][Wold] block, slot j taken from old
+// slot from[j] (src is a copy of the old block; the two may not overlap).
+template <typename T>
+__global__ void k_narrow(const T* __restrict__ src, T* __restrict__ dst, int Wold, int W, Slots from, int64_t N) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+#pragma unroll
+  for (int j = 0; j < kR; ++j) {
+    if (j >= W) break;
+    dst[i * W + j] = src[i * Wold + from.s[j]];
   }
 }
 
@@ -515,10 +610,12 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
   // run over all chunks in one launch.
   struct Host {
     wdb_theta* th;
-    std::vector<int> idx;
-    int64_t off;   // first element of the chunk's [N][8] block in the pools
+    std::vector<int> idx;   // problem of each slot
+    int W;                  // slots in use: the vectors are [N][W]
+    int64_t off;            // first element of the chunk's block (room for [N][8]) in the pools
     int blocks_res, blocks_prox, blocks;
   };
+  auto slots_for = [](int n) { return n > 4 ? 8 : (n > 2 ? 4 : (n > 1 ? 2 : 1)); };
   std::vector<Host> chunks;
   int64_t tot8 = 0;
   for (wdb_theta* th : order) {
@@ -534,6 +631,7 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
       Host h;
       h.th = th;
       h.idx.assign(m.begin() + b, m.begin() + std::min(m.size(), b + kR));
+      h.W = slots_for(static_cast<int>(h.idx.size()));
       h.off = tot8;
       tot8 += th->N * kR;
       h.blocks_res = static_cast<int>((th->A.nslices * th->A.C + kBlock - 1) / kBlock);
@@ -584,6 +682,7 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
     d.Cr = pCr.p + h.off;
     d.Anc = pAnc.p + h.off;
     d.Rr = pRr.p + h.off;
+    d.W = h.W;
     d.pinv = pre ? th->pinv : nullptr;
     d.tau = static_cast<float>(tau);
     d.act = pAct.p + static_cast<int64_t>(c) * (kR + 1);
@@ -633,8 +732,9 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
     }
     if (nu) dwt_forward_many(th->n, th->levels, f, nu, us, xs, sa, sb, s);
     const dim3 g8(static_cast<unsigned>((N + 255) / 256));
-    hipLaunchKernelGGL(k_interleave8, g8, dim3(256), 0, s, x0s, pX0.p + h.off, static_cast<float*>(nullptr), N);
-    hipLaunchKernelGGL(k_interleave8, g8, dim3(256), 0, s, inits, d.X, d.Y, N);
+    hipLaunchKernelGGL(k_interleave8, g8, dim3(256), 0, s, x0s, pX0.p + h.off, static_cast<float*>(nullptr), N,
+                       h.W);
+    hipLaunchKernelGGL(k_interleave8, g8, dim3(256), 0, s, inits, d.X, d.Y, N, h.W);
     act[kR] = h.idx.empty() ? 0 : 1;
   }
   hipLaunchKernelGGL(k_anchor_init8, dim3(static_cast<unsigned>((tot8 + 255) / 256)), dim3(256), 0, s, pAnc.p, pCr.p,
@@ -723,6 +823,64 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
         }
         any_active |= act[kR] != 0;
       }
+      // Narrow the packs whose active problems fit in fewer slots: the active
+      // problems move to the first slots of an [N][W] layout (the residual and
+      // check-residual blocks serve as copies of the old layout); the stopped
+      // problems left out write their final iterates now.
+      bool narrowed = false;
+      for (int ci = 0; ci < nch && changed; ++ci) {
+        Host& h = chunks[ci];
+        int* act = act_host.data() + static_cast<size_t>(ci) * (kR + 1);
+        int na = 0;
+        for (int j = 0; j < static_cast<int>(h.idx.size()); ++j) na += act[j];
+        if (na == 0) continue;
+        const int Wn = slots_for(na);
+        if (Wn >= h.W) continue;
+        Slots from{};
+        std::vector<int> keep, drop;
+        for (int j = 0; j < static_cast<int>(h.idx.size()); ++j) (act[j] ? keep : drop).push_back(j);
+        while (static_cast<int>(keep.size()) < Wn && !drop.empty()) {   // fill the rest with stopped slots
+          keep.push_back(drop.front());
+          drop.erase(drop.begin());
+        }
+        const int64_t N = h.th->N;
+        const dim3 gN(static_cast<unsigned>((N + 255) / 256));
+        if (!drop.empty()) {
+          Dst8 out{};
+          for (int j : drop) {
+            out.p[j] = probs[h.idx[j]].x_out;
+            out.p64[j] = probs[h.idx[j]].x64_out;
+          }
+          hipLaunchKernelGGL(k_deinterleave8, gN, dim3(256), 0, s, pAnc.p + h.off, out, h.W, N);
+        }
+        for (int j = 0; j < kR; ++j) from.s[j] = j < static_cast<int>(keep.size()) ? keep[j] : 0;
+        const size_t nold = static_cast<size_t>(N) * h.W;
+        float* fl[4] = {pX.p + h.off, pY.p + h.off, pX0.p + h.off, pCr.p + h.off};
+        for (float* a : fl) {
+          WDB_HIP(hipMemcpyAsync(pRr.p + h.off, a, nold * sizeof(float), hipMemcpyDeviceToDevice, s));
+          hipLaunchKernelGGL(k_narrow<float>, gN, dim3(256), 0, s, pRr.p + h.off, a, h.W, Wn, from, N);
+        }
+        WDB_HIP(hipMemcpyAsync(pR64.p + h.off, pAnc.p + h.off, nold * sizeof(double), hipMemcpyDeviceToDevice, s));
+        hipLaunchKernelGGL(k_narrow<double>, gN, dim3(256), 0, s, pR64.p + h.off, pAnc.p + h.off, h.W, Wn, from, N);
+        WDB_HIP(hipGetLastError());
+        std::vector<int> idx(keep.size());
+        float thr[kR] = {};
+        int nact[kR + 1] = {};
+        for (size_t j = 0; j < keep.size(); ++j) {
+          idx[j] = h.idx[keep[j]];
+          thr[j] = hd[ci].thr[keep[j]];
+          nact[j] = act[keep[j]];
+        }
+        nact[kR] = 1;
+        h.idx = idx;
+        h.W = Wn;
+        for (int j = 0; j <= kR; ++j) act[j] = nact[j];
+        for (int j = 0; j < kR; ++j) hd[ci].thr[j] = thr[j];
+        hd[ci].W = Wn;
+        narrowed = true;
+      }
+      if (narrowed)
+        WDB_HIP(hipMemcpyAsync(dch.p, hd.data(), nch * sizeof(ChunkDev), hipMemcpyHostToDevice, s));
       if (changed)
         WDB_HIP(hipMemcpyAsync(pAct.p, act_host.data(), act_host.size() * sizeof(int), hipMemcpyHostToDevice, s));
       if (stopping && !any_active) {
@@ -748,7 +906,7 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
       dst.p64[j] = probs[h.idx[j]].x64_out;
     }
     hipLaunchKernelGGL(k_deinterleave8, dim3(static_cast<unsigned>((N + 255) / 256)), dim3(256), 0, s,
-                       pAnc.p + h.off, dst, static_cast<int>(h.idx.size()), N);
+                       pAnc.p + h.off, dst, h.W, N);
   }
   WDB_HIP(hipGetLastError());
   WDB_HIP(hipStreamSynchronize(s));
