@@ -382,16 +382,20 @@ typedef struct {
 } wdb_problem;
 
 /* Solve many problems in one call (Alg. 1 for each).  Problems sharing a
- * handle are packed eight at a time so each iteration reads every stored
- * entry of Theta_K once for eight right-hand sides; all packs of all
- * operators run in one launch per phase (two launches per iteration for the
- * whole batch), replayed from a HIP graph between float64 checks when
- * opts->use_graph is set.  opts is shared (its x_init must be NULL; use the
- * per-problem x_init), each problem has its own lambda, step 1/L of its
+ * handle are packed up to eight at a time so each iteration reads every
+ * stored entry of Theta_K once for all right-hand sides of a pack; all packs
+ * of all operators run in one launch per phase (two launches per iteration
+ * for the whole batch), replayed from a HIP graph between float64 checks
+ * when opts->use_graph is set.  opts is shared (its x_init must be NULL; use
+ * the per-problem x_init), each problem has its own lambda, step 1/L of its
  * handle (computed on first use if absent), and its own stop flag: with
  * tol_rel_gap > 0 a problem stops updating at the first check where its gap
- * is below tolerance (or, with its target_objective > 0, where E <= target).  infos (optional) receives nprob entries.  Handles must
- * hold float32 values.  Synchronises at each check.  Errors: as wdb_solve;
+ * is below tolerance (or, with its target_objective > 0, where E <= target).
+ * A pack whose remaining problems fit in fewer slots continues on a narrower
+ * layout; this changes the cost per iteration, not the iterates.  infos
+ * (optional) receives nprob entries.  Handles must hold float32 values.
+ * Allocates its working vectors (room for eight slots per pack) for the call
+ * and synchronises at each check.  Errors: as wdb_solve;
  * WDB_ERR_NOT_CONVERGED if any problem missed the tolerance (all outputs are
  * still written). */
 wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs, const wdb_solve_opts* opts,
