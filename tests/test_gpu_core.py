@@ -932,6 +932,33 @@ def small32():
     return {"field": field, "h": h, "A": A, "A32": A32, "H": blur.blur_matrix(field)}
 
 
+@pytest.mark.parametrize("tiled", [False, True])
+def test_batched_narrowing_keeps_the_iterates(W, p64, tiled):
+    """A pack narrows (8 -> 4 -> 2 -> 1 slots) as its problems stop; that must
+    change only the cost: each problem's float64 iterate and stopping
+    iteration equal those of the same problem solved alone (a pack of one),
+    bit for bit, since every slot keeps its own sums in the same order."""
+    th = imported(W, p64)
+    if tiled:
+        th.set_kernel_layout(8, 3)
+    wl = p64["wl"]
+    th.lipschitz(synth.power_start(4096, 3))
+    H = blur.blur_matrix(wl.psf())
+    probs = []
+    for i in range(7):
+        u0 = (blur.blur(None, synth.piecewise_image(64, 300 + i), H) + synth.noise(64, 0.01, 400 + i)).astype(np.float32)
+        probs.append((th, dev(u0).reshape(-1), float(np.float32(10.0 ** (-3.6 + 0.25 * i)))))
+    o_all = [torch.empty(4096, device="cuda", dtype=torch.float64) for _ in probs]
+    _, inf_all = W.solve_batched(probs, 4000, check_every=10, tol=1e-3, outs64=o_all)
+    its = [r["iters"] for r in inf_all]
+    assert len(set(its)) >= 3, its          # the pack narrows more than once
+    for i, p in enumerate(probs):
+        o1 = [torch.empty(4096, device="cuda", dtype=torch.float64)]
+        _, inf1 = W.solve_batched([p], 4000, check_every=10, tol=1e-3, outs64=o1)
+        assert inf1[0]["iters"] == its[i]
+        assert torch.equal(o1[0], o_all[i]), i
+
+
 @pytest.mark.parametrize("tiled64", [False, True])
 def test_batched_matches_oracle_per_problem(W, p64, small32, tiled64):
     """13 problems on two operators (chunks of 8 + 2 and 3); with tiled64 the
