@@ -118,56 +118,75 @@ __device__ __forceinline__ void tile_origin(int t, int s, int& b, int& ty0, int&
   tx0 = (ti % tiles_x) * TC;
 }
 
-// Stage channels [0, CH) of the tile at (ty0, tx0) with its circular halo as
-// dst[q * stride + c], q = halo row * W2 + halo column.  NT threads; every
-// thread issues all its loads before its first LDS store, so their latencies
-// overlap instead of adding up.
+// Staging of a tile in two halves, so that the loads of the next tile can be
+// in flight while the matrix cores work on the current one: load_* fills a
+// thread's registers, store_* writes them to LDS (ReLU applied there).
+//
+// Halo: channels [0, CH) of the tile at (ty0, tx0) with its circular halo as
+// dst[q * stride + c], q = halo row * W2 + halo column; NT threads.
 template <int CH, int TC, int NT = 256>
-__device__ __forceinline__ void stage_halo(const float* __restrict__ src, int64_t per, int s, int ty0, int tx0,
-                                           int relu, float* __restrict__ dst, int stride) {
+struct Halo {
+  static constexpr int NE = CH * TileG<TC>::P2, NIT = (NE + NT - 1) / NT;
+};
+
+template <int CH, int TC, int NT = 256>
+__device__ __forceinline__ void load_halo(const float* __restrict__ src, int64_t per, int s, int ty0, int tx0,
+                                          float (&v)[Halo<CH, TC, NT>::NIT]) {
   using G = TileG<TC>;
-  constexpr int NE = CH * G::P2, NIT = (NE + NT - 1) / NT;
-  float v[NIT];
+  using H = Halo<CH, TC, NT>;
 #pragma unroll
-  for (int i = 0; i < NIT; ++i) {
+  for (int i = 0; i < H::NIT; ++i) {
     const int e = static_cast<int>(threadIdx.x) + i * NT;
-    if (e < NE) {
+    if (e < H::NE) {
       const int c = e / G::P2, q = e - c * G::P2;
       const int yy = q / G::W2, xx = q - yy * G::W2;
       const int gy = (ty0 + yy - 1) & (s - 1), gx = (tx0 + xx - 1) & (s - 1);
       v[i] = src[c * per + static_cast<int64_t>(gy) * s + gx];
     }
   }
+}
+
+template <int CH, int TC, int NT = 256>
+__device__ __forceinline__ void store_halo(const float (&v)[Halo<CH, TC, NT>::NIT], int relu, float* __restrict__ dst,
+                                           int stride) {
+  using G = TileG<TC>;
+  using H = Halo<CH, TC, NT>;
 #pragma unroll
-  for (int i = 0; i < NIT; ++i) {
+  for (int i = 0; i < H::NIT; ++i) {
     const int e = static_cast<int>(threadIdx.x) + i * NT;
-    if (e < NE) {
+    if (e < H::NE) {
       const int c = e / G::P2, q = e - c * G::P2;
       dst[q * stride + c] = relu ? fmaxf(v[i], 0.0f) : v[i];
     }
   }
 }
 
-// Stage the 32 channels of the tile's own 128 positions as dst[p * kMP + c]
-// (ReLU on load if relu), loads first as above.
+// Tile32: the 32 channels of the tile's own 128 positions as dst[p * kMP + c].
+template <int NT = 256>
+struct Tile32 {
+  static constexpr int NE = kF * kTileMax, NIT = (NE + NT - 1) / NT;
+};
+
 template <int TC, int NT = 256>
-__device__ __forceinline__ void stage_tile32(const float* __restrict__ src, int64_t per, int s, int ty0, int tx0,
-                                             int relu, float* __restrict__ dst) {
-  constexpr int NE = kF * kTileMax, NIT = (NE + NT - 1) / NT;
-  float v[NIT];
+__device__ __forceinline__ void load_tile32(const float* __restrict__ src, int64_t per, int s, int ty0, int tx0,
+                                            float (&v)[Tile32<NT>::NIT]) {
 #pragma unroll
-  for (int i = 0; i < NIT; ++i) {
+  for (int i = 0; i < Tile32<NT>::NIT; ++i) {
     const int e = static_cast<int>(threadIdx.x) + i * NT;
-    if (e < NE) {
+    if (e < Tile32<NT>::NE) {
       const int c = e / kTileMax, q = e % kTileMax;
       const int yy = q / TC, xx = q - yy * TC;
       v[i] = src[c * per + static_cast<int64_t>(ty0 + yy) * s + tx0 + xx];
     }
   }
+}
+
+template <int NT = 256>
+__device__ __forceinline__ void store_tile32(const float (&v)[Tile32<NT>::NIT], int relu, float* __restrict__ dst) {
 #pragma unroll
-  for (int i = 0; i < NIT; ++i) {
+  for (int i = 0; i < Tile32<NT>::NIT; ++i) {
     const int e = static_cast<int>(threadIdx.x) + i * NT;
-    if (e < NE) dst[(e % kTileMax) * kMP + e / kTileMax] = relu ? fmaxf(v[i], 0.0f) : v[i];
+    if (e < Tile32<NT>::NE) dst[(e % kTileMax) * kMP + e / kTileMax] = relu ? fmaxf(v[i], 0.0f) : v[i];
   }
 }
 
@@ -195,11 +214,21 @@ __global__ __launch_bounds__(256) void k_conv_mfma_in(const float* __restrict__ 
   const int pl = wv * 32 + (lane & 31);
   const int ty = pl / TC, tx = pl - ty * TC;
   const int kh = lane >> 5;
+  float v[Halo<CI, TC>::NIT];
+  int b, ty0, tx0;
+  if (static_cast<int>(blockIdx.x) < ntiles) {
+    tile_origin<TC>(blockIdx.x, s, b, ty0, tx0);
+    load_halo<CI, TC>(in + b * in_bs, per, s, ty0, tx0, v);
+  }
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    int b, ty0, tx0;
     tile_origin<TC>(t, s, b, ty0, tx0);
-    stage_halo<CI, TC>(in + b * in_bs, per, s, ty0, tx0, in_relu, sx, XS);
+    store_halo<CI, TC>(v, in_relu, sx, XS);
     __syncthreads();
+    if (t + static_cast<int>(gridDim.x) < ntiles) {   // the next tile's loads overlap this tile's products
+      int bn, yn, xn;
+      tile_origin<TC>(t + gridDim.x, s, bn, yn, xn);
+      load_halo<CI, TC>(in + bn * in_bs, per, s, yn, xn, v);
+    }
     f32x16 acc = {};
     if constexpr (CI == kF) {
 #pragma unroll
@@ -286,11 +315,21 @@ __global__ __launch_bounds__(256) void k_conv_mfma_out(const float* __restrict__
     swt[e] = m < M ? bf2f(w[((m / 9) * kF + c) * 9 + m % 9]) : 0.0f;
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, kh = lane >> 5, l32 = lane & 31;
+  float v[Halo<kF, TC>::NIT];
+  int b, ty0, tx0;
+  if (static_cast<int>(blockIdx.x) < ntiles) {
+    tile_origin<TC>(blockIdx.x, s, b, ty0, tx0);
+    load_halo<kF, TC>(in + b * in_bs, per, s, ty0, tx0, v);
+  }
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    int b, ty0, tx0;
     tile_origin<TC>(t, s, b, ty0, tx0);
-    stage_halo<kF, TC>(in + b * in_bs, per, s, ty0, tx0, in_relu, sx, kMP);
+    store_halo<kF, TC>(v, in_relu, sx, kMP);
     __syncthreads();
+    if (t + static_cast<int>(gridDim.x) < ntiles) {   // the next tile's loads overlap this tile's products
+      int bn, yn, xn;
+      tile_origin<TC>(t + gridDim.x, s, bn, yn, xn);
+      load_halo<kF, TC>(in + bn * in_bs, per, s, yn, xn, v);
+    }
     for (int gq = wv; gq < NG; gq += 4) {   // wave-uniform
       const int q = gq * 32 + l32;
       const int qr = min(q, G::P2 - 1);
@@ -448,12 +487,23 @@ __global__ __launch_bounds__(kBwdThreads) void k_conv32_bwd_w_mfma(const float* 
   const int lane = threadIdx.x & 63, d = threadIdx.x >> 6, kh = lane >> 5, l32 = lane & 31;
   f32x16 acc = {};
   float bsum = 0.0f;
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  float va[Halo<kF, TC, kBwdThreads>::NIT], vg[Tile32<kBwdThreads>::NIT];
+  if (static_cast<int>(blockIdx.x) < ntiles) {
     int b, ty0, tx0;
-    tile_origin<TC>(t, s, b, ty0, tx0);
-    stage_halo<kF, TC, kBwdThreads>(act + b * a_bs, per, s, ty0, tx0, act_relu, sx, kMP);
-    stage_tile32<TC, kBwdThreads>(g + b * g_bs, per, s, ty0, tx0, 0, sg);
+    tile_origin<TC>(blockIdx.x, s, b, ty0, tx0);
+    load_halo<kF, TC, kBwdThreads>(act + b * a_bs, per, s, ty0, tx0, va);
+    load_tile32<TC, kBwdThreads>(g + b * g_bs, per, s, ty0, tx0, vg);
+  }
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    store_halo<kF, TC, kBwdThreads>(va, act_relu, sx, kMP);
+    store_tile32<kBwdThreads>(vg, 0, sg);
     __syncthreads();
+    if (t + static_cast<int>(gridDim.x) < ntiles) {   // the next tile's loads overlap this tile's products
+      int bn, yn, xn;
+      tile_origin<TC>(t + gridDim.x, s, bn, yn, xn);
+      load_halo<kF, TC, kBwdThreads>(act + bn * a_bs, per, s, yn, xn, va);
+      load_tile32<TC, kBwdThreads>(g + bn * g_bs, per, s, yn, xn, vg);
+    }
     const int dy = d / 3, dx = d % 3;
 #pragma unroll 8
     for (int st = 0; st < kTileMax / 2; ++st) {
@@ -506,12 +556,23 @@ __global__ __launch_bounds__(256) void k_bwd_w_thin(const float* __restrict__ ac
   const int nd = nv ? (L3 ? 8 - l32 % 9 : l32 % 9) : 4;          // tap of the shift
   f32x16 acc = {};
   float bsum = 0.0f;
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  float vw[Tile32<>::NIT], vn[Halo<C, TC>::NIT];
+  if (static_cast<int>(blockIdx.x) < ntiles) {
     int b, ty0, tx0;
-    tile_origin<TC>(t, s, b, ty0, tx0);
-    stage_tile32<TC>(wide + b * wide_bs, per, s, ty0, tx0, wide_relu, sw);
-    stage_halo<C, TC>(thin + b * thin_bs, per, s, ty0, tx0, thin_relu, sn, C);
+    tile_origin<TC>(blockIdx.x, s, b, ty0, tx0);
+    load_tile32<TC>(wide + b * wide_bs, per, s, ty0, tx0, vw);
+    load_halo<C, TC>(thin + b * thin_bs, per, s, ty0, tx0, vn);
+  }
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    store_tile32(vw, wide_relu, sw);
+    store_halo<C, TC>(vn, thin_relu, sn, C);
     __syncthreads();
+    if (t + static_cast<int>(gridDim.x) < ntiles) {   // the next tile's loads overlap this tile's products
+      int bn, yn, xn;
+      tile_origin<TC>(t + gridDim.x, s, bn, yn, xn);
+      load_tile32<TC>(wide + bn * wide_bs, per, s, yn, xn, vw);
+      load_halo<C, TC>(thin + bn * thin_bs, per, s, yn, xn, vn);
+    }
 #pragma unroll
     for (int st = 0; st < 16; ++st) {
       const int p = wv * 32 + 2 * st + kh;
