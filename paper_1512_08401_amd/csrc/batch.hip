@@ -539,10 +539,6 @@ __global__ void k_interleave8(Src8 src, float* __restrict__ dst, float* __restri
   }
 }
 
-struct Slots {
-  int s[kR];
-};
-
 // The problems' iterates: the anchors rounded to float32 (and as float64 where asked).
 struct Dst8 {
   float* p[kR];
@@ -561,17 +557,48 @@ __global__ void k_deinterleave8(const double* __restrict__ src, Dst8 dst, int W,
   }
 }
 
-// A pack's [N][W] block in place of its [N][Wold] block, slot j taken from old
-// slot from[j] (src is a copy of the old block; the two may not overlap).
-template <typename T>
-__global__ void k_narrow(const T* __restrict__ src, T* __restrict__ dst, int Wold, int W, Slots from, int64_t N) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-#pragma unroll
-  for (int j = 0; j < kR; ++j) {
-    if (j >= W) break;
-    dst[i * W + j] = src[i * Wold + from.s[j]];
+// Narrowing of packs, all packs of a check in one launch per step (blockIdx.y
+// = job).  A job moves a pack's [N][Wold] block to an [N][W] block, slot j
+// taken from old slot from[j]; its stopped problems left out are written out
+// first (out: their x_out / x64_out per old slot, null elsewhere).
+struct NarrowJob {
+  int64_t off, N;
+  int Wold, W;
+  int from[kR];
+  Dst8 out;
+};
+
+// Dropped problems' final iterates (the anchors in the old layout).
+__global__ void k_narrow_out(const NarrowJob* __restrict__ jobs, const double* __restrict__ anc) {
+  const NarrowJob& J = jobs[blockIdx.y];
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < J.N;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    for (int j = 0; j < J.Wold; ++j) {
+      if (!J.out.p[j]) continue;
+      const double v = anc[J.off + i * J.Wold + j];
+      J.out.p[j][i] = static_cast<float>(v);
+      if (J.out.p64[j]) J.out.p64[j][i] = v;
+    }
   }
+}
+
+// tmp = the old block of each job's pack (tmp and dst are pools of the same layout).
+template <typename T>
+__global__ void k_narrow_copy(const NarrowJob* __restrict__ jobs, const T* __restrict__ src, T* __restrict__ tmp) {
+  const NarrowJob& J = jobs[blockIdx.y];
+  const int64_t n = J.N * J.Wold;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    tmp[J.off + i] = src[J.off + i];
+}
+
+// dst = the new block, from the copy of the old one.
+template <typename T>
+__global__ void k_narrow_move(const NarrowJob* __restrict__ jobs, const T* __restrict__ tmp, T* __restrict__ dst) {
+  const NarrowJob& J = jobs[blockIdx.y];
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < J.N;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    for (int j = 0; j < J.W; ++j) dst[J.off + i * J.W + j] = tmp[J.off + i * J.Wold + J.from[j]];
 }
 
 __global__ void k_set(int* p, int v) { *p = v; }
@@ -654,6 +681,9 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
   DevBuf<int> dfirst(nch + 1);
   DevBuf<double> part(static_cast<size_t>(4 * kR) * nblocks), red(static_cast<size_t>(nch) * 4 * kR);
   DevBuf<int> kdev(1);
+  DevBuf<NarrowJob> djobs;
+  size_t njobs_cap = 0;
+  std::vector<NarrowJob> jobs;
   for (int c = 0; c < nch; ++c) {
     Host& h = chunks[c];
     wdb_theta* th = h.th;
@@ -827,7 +857,7 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
       // problems move to the first slots of an [N][W] layout (the residual and
       // check-residual blocks serve as copies of the old layout); the stopped
       // problems left out write their final iterates now.
-      bool narrowed = false;
+      jobs.clear();   // (the host table outlives the copy to the device: the next check synchronises first)
       for (int ci = 0; ci < nch && changed; ++ci) {
         Host& h = chunks[ci];
         int* act = act_host.data() + static_cast<size_t>(ci) * (kR + 1);
@@ -836,33 +866,23 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
         if (na == 0) continue;
         const int Wn = slots_for(na);
         if (Wn >= h.W) continue;
-        Slots from{};
         std::vector<int> keep, drop;
         for (int j = 0; j < static_cast<int>(h.idx.size()); ++j) (act[j] ? keep : drop).push_back(j);
         while (static_cast<int>(keep.size()) < Wn && !drop.empty()) {   // fill the rest with stopped slots
           keep.push_back(drop.front());
           drop.erase(drop.begin());
         }
-        const int64_t N = h.th->N;
-        const dim3 gN(static_cast<unsigned>((N + 255) / 256));
-        if (!drop.empty()) {
-          Dst8 out{};
-          for (int j : drop) {
-            out.p[j] = probs[h.idx[j]].x_out;
-            out.p64[j] = probs[h.idx[j]].x64_out;
-          }
-          hipLaunchKernelGGL(k_deinterleave8, gN, dim3(256), 0, s, pAnc.p + h.off, out, h.W, N);
+        NarrowJob J{};
+        J.off = h.off;
+        J.N = h.th->N;
+        J.Wold = h.W;
+        J.W = Wn;
+        for (int j = 0; j < kR; ++j) J.from[j] = j < static_cast<int>(keep.size()) ? keep[j] : 0;
+        for (int j : drop) {
+          J.out.p[j] = probs[h.idx[j]].x_out;
+          J.out.p64[j] = probs[h.idx[j]].x64_out;
         }
-        for (int j = 0; j < kR; ++j) from.s[j] = j < static_cast<int>(keep.size()) ? keep[j] : 0;
-        const size_t nold = static_cast<size_t>(N) * h.W;
-        float* fl[4] = {pX.p + h.off, pY.p + h.off, pX0.p + h.off, pCr.p + h.off};
-        for (float* a : fl) {
-          WDB_HIP(hipMemcpyAsync(pRr.p + h.off, a, nold * sizeof(float), hipMemcpyDeviceToDevice, s));
-          hipLaunchKernelGGL(k_narrow<float>, gN, dim3(256), 0, s, pRr.p + h.off, a, h.W, Wn, from, N);
-        }
-        WDB_HIP(hipMemcpyAsync(pR64.p + h.off, pAnc.p + h.off, nold * sizeof(double), hipMemcpyDeviceToDevice, s));
-        hipLaunchKernelGGL(k_narrow<double>, gN, dim3(256), 0, s, pR64.p + h.off, pAnc.p + h.off, h.W, Wn, from, N);
-        WDB_HIP(hipGetLastError());
+        jobs.push_back(J);
         std::vector<int> idx(keep.size());
         float thr[kR] = {};
         int nact[kR + 1] = {};
@@ -877,10 +897,31 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
         for (int j = 0; j <= kR; ++j) act[j] = nact[j];
         for (int j = 0; j < kR; ++j) hd[ci].thr[j] = thr[j];
         hd[ci].W = Wn;
-        narrowed = true;
       }
-      if (narrowed)
+      if (!jobs.empty()) {
+        // Narrow the packs whose active problems fit in fewer slots: the active
+        // problems move to the first slots of an [N][W] layout (the residual and
+        // check-residual pools serve as copies of the old layout; both are
+        // recomputed before they are read again); the stopped problems left out
+        // write their final iterates first.
+        if (jobs.size() > njobs_cap) {
+          djobs.alloc(jobs.size());
+          njobs_cap = jobs.size();
+        }
+        WDB_HIP(hipMemcpyAsync(djobs.p, jobs.data(), jobs.size() * sizeof(NarrowJob), hipMemcpyHostToDevice, s));
+        const dim3 gj(256, static_cast<unsigned>(jobs.size()));
+        hipLaunchKernelGGL(k_narrow_out, gj, dim3(256), 0, s, djobs.p, pAnc.p);
+        float* fl[4] = {pX.p, pY.p, pX0.p, pCr.p};
+        for (float* a : fl) {
+          hipLaunchKernelGGL(k_narrow_copy<float>, gj, dim3(256), 0, s, djobs.p, a, pRr.p);
+          hipLaunchKernelGGL(k_narrow_move<float>, gj, dim3(256), 0, s, djobs.p, pRr.p, a);
+        }
+        hipLaunchKernelGGL(k_narrow_copy<double>, gj, dim3(256), 0, s, djobs.p, pAnc.p, pR64.p);
+        hipLaunchKernelGGL(k_narrow_move<double>, gj, dim3(256), 0, s, djobs.p, pR64.p, pAnc.p);
+        WDB_HIP(hipGetLastError());
         WDB_HIP(hipMemcpyAsync(dch.p, hd.data(), nch * sizeof(ChunkDev), hipMemcpyHostToDevice, s));
+        // (the job table is rewritten only after the next check's synchronisation)
+      }
       if (changed)
         WDB_HIP(hipMemcpyAsync(pAct.p, act_host.data(), act_host.size() * sizeof(int), hipMemcpyHostToDevice, s));
       if (stopping && !any_active) {
