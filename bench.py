@@ -623,6 +623,7 @@ def run_learned(args):
             "E_star_converged": int(sum(r["converged"] for r in star)),
             # the relative duality gap bounds E* - E_min relative to E, hence the uncertainty of every rho
             "E_star_rel_gap_max": float(max(r["rel_gap"] for r in star)),
+            "rho_uncertainty_max": float(max(r["rel_gap"] * r["objective"] / E0[i] for i, r in enumerate(star))),
             "train_loss_first_last": [hist[0], hist[-1]], "targets_s": round(t_targets, 2),
             "train_s": round(t_train, 2)}
 
