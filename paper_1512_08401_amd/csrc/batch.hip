@@ -344,10 +344,9 @@ __device__ __forceinline__ void block_reduce8(double (&v)[kR], bool is_max, doub
 // float32 widened): acc[8] of the lane's row, complete in wavefront 0 (escapes
 // dealt to the four wavefronts; partials added in LDS in wavefront order).
 // Called by every thread of the block.
-template <typename T>
+template <int W, typename T>
 __device__ __forceinline__ int tile_mm64(const ChunkDev& C, int m, int tile, const T* __restrict__ V,
-                                         double (&acc)[kR]) {
-  __shared__ double part[kWaves][kR][kWave];
+                                         double (&acc)[kR], double (*part)[kR][kWave]) {
   const int4 d = C.tdesc[m][tile];
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -355,12 +354,10 @@ __device__ __forceinline__ int tile_mm64(const ChunkDev& C, int m, int tile, con
   const RowCode rc = tile_row_code(C.geo, d, row);
   const uint4* __restrict__ code = C.tcode[m];
   const float4* __restrict__ val = C.tval[m];
-  const int W = C.W;
   auto add = [&](int col, float w) {
     const T* p = V + static_cast<int64_t>(col) * W;
 #pragma unroll
-    for (int j = 0; j < kR; ++j)
-      if (j < W) acc[j] = fma(static_cast<double>(w), static_cast<double>(p[j]), acc[j]);
+    for (int j = 0; j < W; ++j) acc[j] = fma(static_cast<double>(w), static_cast<double>(p[j]), acc[j]);
   };
   for (int k = (d.x >> 2) + wv; k < (d.y >> 2); k += kWaves) {
     const uint4 c = code[k];
@@ -389,19 +386,17 @@ __device__ __forceinline__ int tile_mm64(const ChunkDev& C, int m, int tile, con
 
 // Forward half of the float64 check on the anchors: r64 = Theta_K anchor - x0
 // and per-block sums of r^2, r.x0, |anchor| per right-hand side.
-__global__ __launch_bounds__(kBlock) void k_check_fwd(const ChunkDev* __restrict__ ch, const int* __restrict__ first,
-                                                      int nchunks, double* __restrict__ part, int64_t nblocks) {
-  const int c = chunk_of(first, nchunks, blockIdx.x);
-  const ChunkDev& C = ch[c];
-  if (!C.act[kR]) return;  // every problem of this chunk has stopped
+template <int W>
+__device__ __forceinline__ void check_fwd_pack(const ChunkDev& C, int blk, double* __restrict__ part,
+                                               int64_t nblocks, double (*tpart)[kR][kWave]) {
   double a[kR], rr[kR], rb[kR], l1[kR];
+#pragma unroll
   for (int j = 0; j < kR; ++j) a[j] = rr[j] = rb[j] = l1[j] = 0.0;
   int64_t row = -1;
   if (C.ntiles) {
-    const int tile = blockIdx.x - first[c];
-    if (tile < C.ntiles) row = tile_mm64(C, 0, tile, C.Anc, a);
+    if (blk < C.ntiles) row = tile_mm64<W>(C, 0, blk, C.Anc, a, tpart);
   } else {
-    const int64_t q = static_cast<int64_t>(blockIdx.x - first[c]) * kBlock + threadIdx.x;
+    const int64_t q = static_cast<int64_t>(blk) * kBlock + threadIdx.x;
     const int64_t sl = q >> C.cshift;
     const int lane = static_cast<int>(q & (C.C - 1));
     if (q < (C.nslices << C.cshift)) {
@@ -411,21 +406,24 @@ __global__ __launch_bounds__(kBlock) void k_check_fwd(const ChunkDev* __restrict
         const int4 cc = C.col[jj];
         const float vv[4] = {v.x, v.y, v.z, v.w};
         const int ci[4] = {cc.x, cc.y, cc.z, cc.w};
+#pragma unroll
         for (int t = 0; t < 4; ++t)
-          for (int j = 0; j < C.W; ++j)
-            a[j] = fma(static_cast<double>(vv[t]), C.Anc[static_cast<int64_t>(ci[t]) * C.W + j], a[j]);
+#pragma unroll
+          for (int j = 0; j < W; ++j)
+            a[j] = fma(static_cast<double>(vv[t]), C.Anc[static_cast<int64_t>(ci[t]) * W + j], a[j]);
       }
       row = slot_row_c(C.perm, C.nrows, q);
     }
   }
   if (row >= 0) {
-    for (int j = 0; j < C.W; ++j) {
-      const double b = static_cast<double>(C.X0[row * C.W + j]);
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      const double b = static_cast<double>(C.X0[row * W + j]);
       const double r = a[j] - b;
-      C.r64[row * C.W + j] = r;
+      C.r64[row * W + j] = r;
       rr[j] = r * r;
       rb[j] = r * b;
-      l1[j] = fabs(C.Anc[row * C.W + j]);
+      l1[j] = fabs(C.Anc[row * W + j]);
     }
   }
   double out[kR];
@@ -437,21 +435,35 @@ __global__ __launch_bounds__(kBlock) void k_check_fwd(const ChunkDev* __restrict
   if (threadIdx.x < kR) part[(2 * kR + threadIdx.x) * nblocks + blockIdx.x] = out[threadIdx.x];
 }
 
-__global__ __launch_bounds__(kBlock) void k_check_bwd(const ChunkDev* __restrict__ ch, const int* __restrict__ first,
+__global__ __launch_bounds__(kBlock) void k_check_fwd(const ChunkDev* __restrict__ ch, const int* __restrict__ first,
                                                       int nchunks, double* __restrict__ part, int64_t nblocks) {
   const int c = chunk_of(first, nchunks, blockIdx.x);
   const ChunkDev& C = ch[c];
   if (!C.act[kR]) return;  // every problem of this chunk has stopped
+  const int blk = blockIdx.x - first[c];
+  __shared__ double tpart[kWaves][kR][kWave];
+  switch (C.W) {
+    case 8: check_fwd_pack<8>(C, blk, part, nblocks, tpart); break;
+    case 4: check_fwd_pack<4>(C, blk, part, nblocks, tpart); break;
+    case 2: check_fwd_pack<2>(C, blk, part, nblocks, tpart); break;
+    default: check_fwd_pack<1>(C, blk, part, nblocks, tpart); break;
+  }
+}
+
+template <int W>
+__device__ __forceinline__ void check_bwd_pack(const ChunkDev& C, int blk, double* __restrict__ part,
+                                               int64_t nblocks, double (*tpart)[kR][kWave]) {
   double g[kR];
+#pragma unroll
   for (int j = 0; j < kR; ++j) g[j] = 0.0;
   if (C.ntiles) {
-    const int tile = blockIdx.x - first[c];
     int row = -1;
-    if (tile < C.ntiles) row = tile_mm64(C, 1, tile, static_cast<const double*>(C.r64), g);
+    if (blk < C.ntiles) row = tile_mm64<W>(C, 1, blk, static_cast<const double*>(C.r64), g, tpart);
     if (row < 0)
+#pragma unroll
       for (int j = 0; j < kR; ++j) g[j] = 0.0;
   } else {
-    const int64_t q = static_cast<int64_t>(blockIdx.x - first[c]) * kBlock + threadIdx.x;
+    const int64_t q = static_cast<int64_t>(blk) * kBlock + threadIdx.x;
     const int64_t sl = q >> C.cshift;
     const int lane = static_cast<int>(q & (C.C - 1));
     if (q < (C.nslicesT << C.cshift)) {
@@ -461,18 +473,37 @@ __global__ __launch_bounds__(kBlock) void k_check_bwd(const ChunkDev* __restrict
         const int4 cc = C.colT[jj];
         const float vv[4] = {v.x, v.y, v.z, v.w};
         const int ci[4] = {cc.x, cc.y, cc.z, cc.w};
+#pragma unroll
         for (int t = 0; t < 4; ++t)
-          for (int j = 0; j < C.W; ++j)
-            g[j] = fma(static_cast<double>(vv[t]), C.r64[static_cast<int64_t>(ci[t]) * C.W + j], g[j]);
+#pragma unroll
+          for (int j = 0; j < W; ++j)
+            g[j] = fma(static_cast<double>(vv[t]), C.r64[static_cast<int64_t>(ci[t]) * W + j], g[j]);
       }
       if (slot_row_c(C.permT, C.nrows, q) < 0)
+#pragma unroll
         for (int j = 0; j < kR; ++j) g[j] = 0.0;
     }
   }
+#pragma unroll
   for (int j = 0; j < kR; ++j) g[j] = fabs(g[j]);
   double out[kR];
   block_reduce8(g, true, out);
   if (threadIdx.x < kR) part[(3 * kR + threadIdx.x) * nblocks + blockIdx.x] = out[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kBlock) void k_check_bwd(const ChunkDev* __restrict__ ch, const int* __restrict__ first,
+                                                      int nchunks, double* __restrict__ part, int64_t nblocks) {
+  const int c = chunk_of(first, nchunks, blockIdx.x);
+  const ChunkDev& C = ch[c];
+  if (!C.act[kR]) return;  // every problem of this chunk has stopped
+  const int blk = blockIdx.x - first[c];
+  __shared__ double tpart[kWaves][kR][kWave];
+  switch (C.W) {
+    case 8: check_bwd_pack<8>(C, blk, part, nblocks, tpart); break;
+    case 4: check_bwd_pack<4>(C, blk, part, nblocks, tpart); break;
+    case 2: check_bwd_pack<2>(C, blk, part, nblocks, tpart); break;
+    default: check_bwd_pack<1>(C, blk, part, nblocks, tpart); break;
+  }
 }
 
 // Anchored iterate, elementwise over a chunk's [N][8] vectors.
