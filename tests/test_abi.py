@@ -78,6 +78,14 @@ def test_host_validation_errors(lib):
     assert lib.wdb_dwt(64, 1, 5, fake, C.c_void_p(32), 0, None) == wdb.WDB_ERR_LEVELS   # 64/16 < 8 taps
     assert lib.wdb_dwt(64, 0, 1, None, C.c_void_p(32), 0, None) == wdb.WDB_ERR_ARG
     assert lib.wdb_dwt(64, 0, 1, fake, fake, 0, None) == wdb.WDB_ERR_ARG                # aliasing
+    big = C.c_void_p(1 << 40)   # far from `fake`: the two batches do not overlap
+    assert lib.wdb_dwt_batched(64, 0, 1, 0, fake, big, 0, None) == wdb.WDB_ERR_ARG        # count < 1
+    assert lib.wdb_dwt_batched(64, 0, 1, 2, None, big, 0, None) == wdb.WDB_ERR_ARG        # null input
+    assert lib.wdb_dwt_batched(48, 0, 1, 2, fake, big, 0, None) == wdb.WDB_ERR_SIZE
+    assert lib.wdb_dwt_batched(64, 1, 5, 2, fake, big, 0, None) == wdb.WDB_ERR_LEVELS
+    # out starts inside the input batch (two images of 64 x 64 floats)
+    assert lib.wdb_dwt_batched(64, 0, 1, 2, fake, C.c_void_p(16 + 4 * 64 * 64), 0, None) == wdb.WDB_ERR_ARG
+    assert "overlap" in lib.wdb_last_error().decode()
     out = C.c_void_p()
     rp = np.zeros(4 * 4 + 1, dtype=np.int64)
     rp[-1] = 1
