@@ -40,7 +40,7 @@ def layout_desc(layout, tile_shape):
     slice_h, group = layout
     if group == 3:
         return {"kind": "tiled", "tile": "8x8 coefficients", "waves_per_tile": tile_shape[0],
-                "groups_in_flight": tile_shape[1]}
+                "groups_in_flight": tile_shape[1], "values": "kept" if tile_shape[2] else "dense"}
     if group == 1:
         return {"kind": "circulant"}
     if group > 0:
@@ -48,11 +48,14 @@ def layout_desc(layout, tile_shape):
     return {"kind": "sliced_ell", "slice": slice_h}
 
 
-def kernel_label(layout, waves=4, unroll=2):
+def kernel_label(layout, waves=4, unroll=2, kept=0):
     slice_h, group = layout
     if group == 3:
-        return (f"k_res_tl<{waves}, {unroll}>", f"r = Theta_K y - x0, float32 tiled pattern storage (8x8 coefficient "
-                f"tiles, {waves} wavefronts per tile, {unroll} groups of 4 codes in flight)")
+        vals = ("kept values with a row mask per code" if kept else
+                "dense values, zeros where a row lacks a code")
+        return (f"k_res_tl<{waves}, {unroll}, {'true' if kept else 'false'}>",
+                f"r = Theta_K y - x0, float32 tiled pattern storage (8x8 coefficient tiles, {vals}, "
+                f"{waves} wavefronts per tile, {unroll} groups of 4 codes in flight)")
     if group > 0:
         return f"k_res_csr<{group}>", f"r = Theta_K y - x0, float32 CSR, {group} lanes per row"
     return "k_res", f"r = Theta_K y - x0, float32 sliced-ELL, {slice_h} rows per slice"
@@ -66,7 +69,8 @@ KERNEL_SOURCES = ("paper_1512_08401_amd/csrc/solve.hip", "paper_1512_08401_amd/c
 def layout_key(layout, tile_shape):
     """Text key of the iteration layout, as the profile summaries record it."""
     if layout[1] == 3:
-        return f"tiled waves={tile_shape[0]} unroll={tile_shape[1]}"
+        return (f"tiled waves={tile_shape[0]} unroll={tile_shape[1]} "
+                f"values={'kept' if tile_shape[2] else 'dense'}")
     return f"slice={layout[0]} group={layout[1]}"
 
 
@@ -213,7 +217,7 @@ def main():
     if not args.no_autotune:
         th.autotune(reps=10)
     layout = (th.info()["slice"], th.info()["group"])
-    tile_shape = (th.info()["tile_waves"], th.info()["tile_unroll"])
+    tile_shape = (th.info()["tile_waves"], th.info()["tile_unroll"], th.info()["tile_kept"])
     t_tune = time.perf_counter() - t0
     t0 = time.perf_counter()
     lip = th.lipschitz_info(synth.power_start(N, wl.power_seed))

@@ -119,6 +119,9 @@ typedef struct {
   int32_t tile_unroll;  /* groups of 4 codes in flight per wavefront, tiled layout */
   int32_t tile_unroll16; /* groups of 8 codes in flight per wavefront, 16-bit tiled layout */
   int64_t tile_escapes; /* entries of the tiled copies kept in per-row escape lists */
+  int32_t tile_kept;    /* 1: the float32 tiled kernels read the kept-value layout, 0: the dense values */
+  int32_t reserved;
+  int64_t tile_kept_values; /* values stored by the kept-value layout of both tiled copies (0: not built) */
 } wdb_theta_desc;
 
 /* ---------------------------------------------------------------------------
@@ -266,10 +269,12 @@ wdb_status wdb_set_packed_group(wdb_theta* th, int32_t group);
  * offsets and values shared by all rows, no per-entry indices), or
  * group = 3: the tiled pattern storage (tiles of 64 coefficients of one
  * subband -- 8 x 8 positions, or a whole subband of side < 8 -- share one
- * sorted list of band-relative column codes, values stored per code and row
- * with zeros where a row lacks the entry; one wavefront per tile, lane = row;
- * built on first use, about 1.6 x K float32 values per matrix for the
- * smoothly varying fields of Sec. 5).  The float64 checks and the power
+ * sorted list of band-relative column codes; one wavefront per tile, lane =
+ * row; built on first use).  The float32 tiles hold two value layouts: dense
+ * (values stored per code and row with zeros where a row lacks the entry,
+ * about 1.6 x K values per matrix for the smoothly varying fields of Sec. 5)
+ * and kept (only the kept values, with a 64-bit row mask per code;
+ * wdb_set_tile_values).  The float64 checks and the power
  * iteration use vector CSR under layouts 1 and 3, else the same choice; the
  * batched solver runs an operator's packs on its tiled copies under layout 3
  * and on the sliced-ELL copies otherwise; the 16-bit iteration reads its
@@ -285,12 +290,25 @@ wdb_status wdb_set_kernel_layout(wdb_theta* th, int32_t slice, int32_t group);
  * Changes only the summation order.  Errors: WDB_ERR_ARG. */
 wdb_status wdb_set_tile_shape(wdb_theta* th, int32_t waves, int32_t unroll);
 
+/* Value layout the float32 tiled kernels read (iteration, float64 checks and
+ * the batched solver): kept = 0 the dense values (per group of 4 codes, 4
+ * values for each of the tile's 64 rows, zeros where a row lacks a code);
+ * kept = 1 only the kept values, lane by lane in code order, with a record
+ * per group of 4 codes holding the codes, a 64-bit row mask per code and the
+ * offset of the group's values (a lane's values start at that offset plus
+ * the kept entries of the rows below it).  Same products, same summation
+ * order; the kept layout streams fewer bytes and spends more instructions per
+ * group.  Both layouts are built with the tiles; the autotuner also picks
+ * between them.  Errors: WDB_ERR_ARG (kept not 0 or 1). */
+wdb_status wdb_set_tile_values(wdb_theta* th, int32_t kept);
+
 /* Project autotuner: times the iteration kernel pair `reps` times (two
  * alternating passes, the better pass counted) for every candidate layout on
  * this operator -- sliced ELL with 64/32/16/8 rows per slice; vector CSR with
  * 2/4/8/16 lanes per row; the circulant storage when the operator came from
- * the convolution fast path; the tiled pattern storage with 1/2/4/8
- * wavefronts per tile and 2/4 code groups in flight -- and keeps the first
+ * the convolution fast path; the tiled pattern storage with dense or kept
+ * values, 1/2/4/8 wavefronts per tile and 1/2/4 code groups in flight -- and
+ * keeps the first
  * candidate in that order within 2% of the fastest.  With 16-bit values set
  * it instead picks among the packed kernels (2/4/8/16 lanes per row) and the
  * 16-bit tiles (1/2/4/8 wavefronts, 1/2 groups in flight).  If cache_path is not NULL the

@@ -130,6 +130,8 @@ wdb_status wdb_theta_info(const wdb_theta* th, wdb_theta_desc* out) {
   out->tile_unroll16 = th->tile_unroll16;
   out->tile_escapes = th->tA.nesc + th->tAt.nesc;
   out->tile_slots = 64 * (th->tA.npat + th->tAt.npat);
+  out->tile_kept = th->tile_kept;
+  out->tile_kept_values = th->tA.nkval + th->tAt.nkval;
   WDB_API_END
 }
 

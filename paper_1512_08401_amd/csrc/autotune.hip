@@ -5,8 +5,9 @@
 // sliced ELL with slice heights 64, 32, 16, 8 (rows in natural order, so a
 // slice's rows are neighbouring coefficients whose gathers share cache lines;
 // shorter slices pad less), vector CSR with 2, 4, 8 or 16 lanes per row, the
-// circulant storage of convolution builds and the tiled pattern storage with
-// 1, 2, 4 or 8 wavefronts per tile and 2 or 4 code groups in flight -- and
+// circulant storage of convolution builds and the tiled pattern storage
+// (dense or kept values) with 1, 2, 4 or 8 wavefronts per tile and 1, 2 or 4
+// code groups in flight -- and
 // keeps the fastest in the handle (each candidate timed in two alternating
 // passes, its best pass counted, so that one slow pass from a clock or
 // cache transient does not decide; of candidates within 2% of the fastest
@@ -55,9 +56,15 @@ std::string cache_key(const wdb_theta* th) {
 
 constexpr double kTieMargin = 1.02;
 
-// Shape code of the tiled kernels: W + 10 U (W wavefronts per tile, U code
-// groups in flight per wavefront).
-inline int shape_code(int W, int U) { return W + 10 * U; }
+// Shape code of the tiled kernels: W + 10 U + 100 K (W wavefronts per tile,
+// U code groups in flight per wavefront, K = 1 for the kept-value layout of
+// the float32 tiles).
+inline int shape_code(int W, int U, int K = 0) { return W + 10 * U + 100 * K; }
+inline void set_tile_shape_code(wdb_theta* th, int code) {
+  th->tile_waves = code % 10;
+  th->tile_unroll = (code / 10) % 10;
+  th->tile_kept = code / 100;
+}
 
 // Layout of the 16-bit iteration: the fastest residual + proximal pair among
 // the packed kernels with 2/4/8/16 lanes per row and the 16-bit tiled layout
@@ -202,8 +209,9 @@ extern "C" wdb_status wdb_autotune(wdb_theta* th, const char* cache_path, int32_
     if (th->st.seg) cands.push_back({0, kStencil, 0});  // circulant storage (convolution fast path)
     if (tiled_supported(th)) {
       build_tiled(th);
-      for (int W : {1, 2, 4, 8})
-        for (int U : {2, 4}) cands.push_back({0, kTiled, shape_code(W, U)});
+      for (int K : {0, 1})
+        for (int W : {1, 2, 4, 8})
+          for (int U : {1, 2, 4}) cands.push_back({0, kTiled, shape_code(W, U, K)});
     }
     hipEvent_t e0, e1;
     WDB_HIP(hipEventCreate(&e0));
@@ -214,10 +222,7 @@ extern "C" wdb_status wdb_autotune(wdb_theta* th, const char* cache_path, int32_
       for (size_t ci = 0; ci < cands.size(); ++ci) {
         const int C = cands[ci][0], G = cands[ci][1];
         if (C) set_slice_height(th, C, s);
-        if (G == kTiled) {
-          th->tile_waves = cands[ci][2] % 10;
-          th->tile_unroll = cands[ci][2] / 10;
-        }
+        if (G == kTiled) set_tile_shape_code(th, cands[ci][2]);
         auto pair = [&]() {
           if (G == kTiled) {
             launch_res_tiled(th, false, th->ws_y, th->ws_x0, th->ws_r, nullptr, s);
@@ -273,13 +278,13 @@ extern "C" wdb_status wdb_autotune(wdb_theta* th, const char* cache_path, int32_
   set_slice_height(th, bestC, s);
   th->spmv_group = bestG;
   if (bestG == kTiled) {
-    th->tile_waves = bestW % 10;
-    th->tile_unroll = bestW / 10;
+    set_tile_shape_code(th, bestW);
   } else {  // the tiled copies are only kept when they are the layout in use
     th->tA.free_all();
     th->tAt.free_all();
     th->tile_waves = 4;
     th->tile_unroll = 2;
+    th->tile_kept = 0;
   }
   if (th->valtype != WDB_VAL_F32) {
     const int vt = th->valtype;

@@ -73,6 +73,10 @@ struct ChunkDev {
   const int4* tdesc[2];
   const uint4* tcode[2];
   const float4* tval[2];
+  const GroupRec* tgrec[2];  // kept-value layout (tkept): group records and kept values
+  const float* tkval[2];
+  uint32_t tkbytes[2];
+  int tkept;
   const int* terp[2];
   const int* tec[2];
   const float* tev[2];
@@ -134,6 +138,19 @@ __device__ __forceinline__ void slice_mm(const int64_t* __restrict__ soff, const
   }
 }
 
+// Codes and the lane's 4 values of group k of copy m: from the dense values
+// or from the kept-value layout.
+__device__ __forceinline__ void group_at(const ChunkDev& C, int m, int k, int lane, uint4& c, float4& v) {
+  if (C.tkept) {
+    const GroupRec r = C.tgrec[m][k];
+    c = r.code;
+    v = kept_values(r, C.tkval[m], C.tkbytes[m]);
+  } else {
+    c = C.tcode[m][k];
+    v = C.tval[m][static_cast<int64_t>(k) * kWave + lane];
+  }
+}
+
 // Tile `tile` of copy m (0: Theta_K, 1: Theta_K^T) times the [N][W] block V:
 // acc[0..W) of the lane's row, complete in wavefront 0 (the row's escapes
 // dealt to the wavefronts, whose partials are added in LDS in wavefront order).
@@ -145,11 +162,10 @@ __device__ __forceinline__ int tile_mm(const ChunkDev& C, int m, int tile, const
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int row = tile_row(d, lane);
   const RowCode rc = tile_row_code(C.geo, d, row);
-  const uint4* __restrict__ code = C.tcode[m];
-  const float4* __restrict__ val = C.tval[m];
   for (int k = (d.x >> 2) + wv; k < (d.y >> 2); k += kWaves) {
-    const uint4 c = code[k];
-    const float4 v = val[static_cast<int64_t>(k) * kWave + lane];
+    uint4 c;
+    float4 v;
+    group_at(C, m, k, lane, c, v);
     const int4 col = group_cols(C.geo, rc, c);
     gatherW<W>(V, col.x, v.x, acc);
     gatherW<W>(V, col.y, v.y, acc);
@@ -352,16 +368,15 @@ __device__ __forceinline__ int tile_mm64(const ChunkDev& C, int m, int tile, con
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int row = tile_row(d, lane);
   const RowCode rc = tile_row_code(C.geo, d, row);
-  const uint4* __restrict__ code = C.tcode[m];
-  const float4* __restrict__ val = C.tval[m];
   auto add = [&](int col, float w) {
     const T* p = V + static_cast<int64_t>(col) * W;
 #pragma unroll
     for (int j = 0; j < W; ++j) acc[j] = fma(static_cast<double>(w), static_cast<double>(p[j]), acc[j]);
   };
   for (int k = (d.x >> 2) + wv; k < (d.y >> 2); k += kWaves) {
-    const uint4 c = code[k];
-    const float4 v = val[static_cast<int64_t>(k) * kWave + lane];
+    uint4 c;
+    float4 v;
+    group_at(C, m, k, lane, c, v);
     const int4 col = group_cols(C.geo, rc, c);
     add(col.x, v.x);
     add(col.y, v.y);
@@ -749,7 +764,9 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
     d.act = pAct.p + static_cast<int64_t>(c) * (kR + 1);
     d.r64 = pR64.p + h.off;
     d.ntiles = 0;
+    d.tkept = 0;
     if (kernel_group(th) == kTiled) {  // the operator iterates on its tiled copies
+      d.tkept = th->tile_kept;
       WDB_REQUIRE(th->tA.ntiles == th->tAt.ntiles, WDB_ERR_ARG, "mismatched tile lists");
       d.ntiles = th->tA.ntiles;
       d.geo = geo_of(th);
@@ -758,6 +775,9 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
         d.tdesc[m] = reinterpret_cast<const int4*>(T[m]->desc);
         d.tcode[m] = reinterpret_cast<const uint4*>(T[m]->code);
         d.tval[m] = reinterpret_cast<const float4*>(T[m]->val);
+        d.tgrec[m] = static_cast<const GroupRec*>(T[m]->grec);
+        d.tkval[m] = T[m]->kval;
+        d.tkbytes[m] = static_cast<uint32_t>(4 * (T[m]->nkval + 4));
         d.terp[m] = T[m]->erp;
         d.tec[m] = T[m]->ec;
         d.tev[m] = T[m]->ev;

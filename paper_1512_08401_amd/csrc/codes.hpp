@@ -188,6 +188,83 @@ __host__ __device__ inline int4 group_cols(const Geo& g, const RowCode& rc, cons
                    decode_col_tile(g, rc, c.w));
 }
 
+// Kept-value layout of the float32 tiles.  A group of 4 codes stores, instead
+// of 64 rows x 4 values with zeros where a row did not keep a code, only the
+// kept values: lane by lane, each lane's values in code order.  Its record
+// holds the codes, one row mask per code (bit t: row t of the tile keeps
+// it) and the offset of the group's values; lane t finds its values at that
+// offset plus the number of kept entries of the rows below t.
+struct alignas(64) GroupRec {
+  uint4 code;
+  uint64_t m[4];
+  uint32_t voff;
+  uint32_t pad[3];
+};
+
+// A wavefront-uniform 64-bit value in scalar registers (the value of the
+// first active lane; free when the compiler already holds it there).
+__device__ __forceinline__ uint64_t wave_uniform(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+// b if this lane's bit of the wavefront-uniform mask m is set, else a: one
+// select with m itself as the lane condition (m must be uniform: the select
+// reads it from scalar registers).
+__device__ __forceinline__ float sel_lane(uint64_t m, float a, float b) {
+  float r;
+  asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(wave_uniform(m)));
+  return r;
+}
+
+// acc plus the number of set bits of m below this lane.
+__device__ __forceinline__ uint32_t rows_below(uint64_t m, uint32_t acc) {
+  return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
+                                   __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), acc));
+}
+
+// Word 3 of a raw buffer resource on gfx9-family chips: data format 32-bit,
+// no swizzle, no index stride.
+constexpr int kBufWord3 = 0x00020000;
+
+// Byte offset of this lane's kept values of group r.
+__device__ __forceinline__ uint32_t kept_offset(const GroupRec& r) {
+  uint32_t o = r.voff;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) o = rows_below(r.m[j], o);
+  return 4 * o;
+}
+
+// 4 floats at byte offset `off` of the kept values (a buffer load over
+// `bytes`: reads past the end return zeros).
+__device__ __forceinline__ float4 ld_kept(const float* __restrict__ kval, uint32_t bytes, uint32_t off) {
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(kval), 0, static_cast<int>(bytes), kBufWord3);
+  const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+  return make_float4(__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]), __uint_as_float(v[3]));
+}
+
+// The lane's values of the group's 4 codes from its kept values packed in
+// code order at v.x, v.y, ...: code j takes the next packed value if the
+// lane's bit of m[j] is set, else 0.
+__device__ __forceinline__ float4 expand_kept(const uint64_t (&m)[4], const float4& v) {
+  const float z = 0.f;
+  const float e0 = sel_lane(m[0], z, v.x);
+  const float a0 = sel_lane(m[0], v.x, v.y), a1 = sel_lane(m[0], v.y, v.z), a2 = sel_lane(m[0], v.z, v.w);
+  const float e1 = sel_lane(m[1], z, a0);
+  const float b0 = sel_lane(m[1], a0, a1), b1 = sel_lane(m[1], a1, a2);
+  const float e2 = sel_lane(m[2], z, b0);
+  const float c0 = sel_lane(m[2], b0, b1);
+  const float e3 = sel_lane(m[3], z, c0);
+  return make_float4(e0, e1, e2, e3);
+}
+
+// The lane's 4 values of group r (record already loaded).
+__device__ __forceinline__ float4 kept_values(const GroupRec& r, const float* __restrict__ kval, uint32_t bytes) {
+  return expand_kept(r.m, ld_kept(kval, bytes, kept_offset(r)));
+}
+
 inline Geo geo_of(const wdb_theta* th) {
   return Geo{floor_log2(static_cast<uint64_t>(th->n)), th->levels,
              static_cast<int>(make_filter(th->wavelet).h.size()) - 1};

@@ -209,6 +209,12 @@ struct Tiled {
   int* erp = nullptr;        // device, nrows + 1
   int* ec = nullptr;         // device, nesc
   float* ev = nullptr;       // device, nesc
+  // Kept-value layout of the float32 copies (groups of 4 codes): per group a
+  // record with the codes, a row mask per code and the offset of its kept
+  // values, which are stored without the zeros of the dense values.
+  void* grec = nullptr;      // device, one 64-byte record per group
+  float* kval = nullptr;     // device, nkval (+ 4 zeros)
+  int64_t nkval = 0;
   void free_all();
 };
 // Lanes per row of the vector-CSR kernels (0: sliced-ELL kernels).
@@ -253,6 +259,7 @@ struct wdb_theta {
   wdb::Tiled tA, tAt;   // tiled pattern storage of Theta_K and Theta_K^T (built on demand)
   int tile_waves = 4;   // wavefronts per tile of the tiled kernels
   int tile_unroll = 2;  // groups of 4 codes in flight per wavefront
+  int tile_kept = 0;    // float32 tiles read: 1 the kept-value layout, 0 the dense values
   wdb::Tiled qA, qAt;   // the same with 16-bit values (built on demand when valtype != 0)
   int tile_waves16 = 4;
   int tile_unroll16 = 1;  // groups of 8 codes in flight per wavefront

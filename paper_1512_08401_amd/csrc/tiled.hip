@@ -30,6 +30,7 @@
 // of every subband, so its L2 serves overlapping windows of the gathered
 // vector.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <exception>
 #include <thread>
@@ -48,17 +49,20 @@ namespace {
 struct TiledView {
   const int4* __restrict__ desc;
   const uint4* __restrict__ code;
-  const float4* __restrict__ val;   // float32 values, groups of 4 codes
+  const float4* __restrict__ val;   // float32 values, groups of 4 codes (dense layout)
   const uint4* __restrict__ val16;  // 16-bit values, groups of 8 codes
   const int* __restrict__ erp;
   const int* __restrict__ ec;
   const float* __restrict__ ev;
+  const GroupRec* __restrict__ grec;  // kept-value layout: group records
+  const float* __restrict__ kval;     // and the kept values
+  uint32_t kbytes;                    // bytes of kval readable by a buffer load
 };
 
 TiledView tview(const Tiled& t) {
   return TiledView{reinterpret_cast<const int4*>(t.desc), reinterpret_cast<const uint4*>(t.code),
                    reinterpret_cast<const float4*>(t.val), reinterpret_cast<const uint4*>(t.val16), t.erp, t.ec,
-                   t.ev};
+                   t.ev, static_cast<const GroupRec*>(t.grec), t.kval, static_cast<uint32_t>(4 * (t.nkval + 4))};
 }
 
 template <int FMT>
@@ -97,10 +101,6 @@ __device__ __forceinline__ X ld_at(const X* __restrict__ x, int i) {
   return *reinterpret_cast<const X*>(reinterpret_cast<const char*>(x) + off);
 }
 
-// Word 3 of a raw buffer resource on gfx9-family chips: data format 32-bit,
-// no swizzle, no index stride.
-constexpr int kBufWord3 = 0x00020000;
-
 // x at the 4 columns of a group: one 16-byte load when the columns are
 // consecutive in every lane of the wavefront (a quad of codes that differ
 // only in dj, away from the subband's edge), two 8-byte loads when they are
@@ -123,8 +123,8 @@ __device__ __forceinline__ float4 ld_group(const float* __restrict__ x, const Ge
   return make_float4(ld_at(x, col.x), ld_at(x, col.y), ld_at(x, col.z), ld_at(x, col.w));
 }
 
-// Codes and values of the U groups k, k + W, ... of a float32 tile (padding
-// past g1).
+// Codes and values of the U groups k, k + W, ... of a float32 tile with the
+// dense [group][lane][4] values (padding past g1).
 template <int W, int U>
 __device__ __forceinline__ void tile_load(const TiledView& T, int k, int g1, int lane, uint4 (&c)[U],
                                           float4 (&v)[U]) {
@@ -136,6 +136,33 @@ __device__ __forceinline__ void tile_load(const TiledView& T, int k, int g1, int
   }
 }
 
+// Group record k of the kept-value layout, or past g1 a record of padding
+// codes with empty masks (whose values expand to zeros).
+__device__ __forceinline__ GroupRec rec_at(const TiledView& T, int k, int g1) {
+  const bool ok = k < g1;
+  GroupRec r = T.grec[ok ? k : 0];
+  if (!ok) {
+    r.code = make_uint4(kPadCodeTile, kPadCodeTile, kPadCodeTile, kPadCodeTile);
+    r.m[0] = r.m[1] = r.m[2] = r.m[3] = 0;
+  }
+  return r;
+}
+
+// Codes, value loads and row masks of the groups of records r (kept-value
+// layout): the 4 floats at the lane's kept values, expanded with the masks
+// when they are used.
+template <int U>
+__device__ __forceinline__ void rec_take(const TiledView& T, const GroupRec (&r)[U], uint4 (&c)[U], float4 (&v)[U],
+                                         uint64_t (&mk)[U][4]) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    c[u] = r[u].code;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) mk[u][j] = r[u].m[j];
+    v[u] = ld_kept(T.kval, T.kbytes, kept_offset(r[u]));
+  }
+}
+
 // Dot product of the lane's row with x over float32 values (groups of 4
 // codes, U groups per step).  A step decodes its columns, issues the
 // gathers, then the loads of the next step's codes and values, and only
@@ -143,8 +170,11 @@ __device__ __forceinline__ void tile_load(const TiledView& T, int k, int g1, int
 // wait for this step's gathers instead of following it.  Waits on scalar
 // loads cover every scalar load in flight, so the next codes are requested
 // only after this step's codes are used (the scheduling barriers keep that
-// order).
-template <int W, int U>
+// order).  With kept values (KEPT) a value load needs its group record
+// first, so the records are requested one step ahead of the values: a step
+// issues the next step's value loads from records that arrived during this
+// one, then requests the records of the step after.
+template <int W, int U, bool KEPT>
 __device__ __forceinline__ float tile_dot(const TiledView& T, const Geo& g, const int4& d, int row, int lane,
                                           int wv, const float* __restrict__ x) {
   const RowCode rc = tile_row_code(g, d, row);
@@ -153,7 +183,17 @@ __device__ __forceinline__ float tile_dot(const TiledView& T, const Geo& g, cons
   int k = (d.x >> 2) + wv;
   uint4 c[U];
   float4 v[U];
-  tile_load<W, U>(T, k, g1, lane, c, v);
+  uint64_t mk[U][4];
+  GroupRec rn[U];
+  if constexpr (KEPT) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) rn[u] = rec_at(T, k + u * W, g1);
+    rec_take<U>(T, rn, c, v, mk);
+#pragma unroll
+    for (int u = 0; u < U; ++u) rn[u] = rec_at(T, k + (U + u) * W, g1);
+  } else {
+    tile_load<W, U>(T, k, g1, lane, c, v);
+  }
   for (; k < g1; k += W * U) {
     float4 xs[U];
 #pragma unroll
@@ -162,15 +202,31 @@ __device__ __forceinline__ float tile_dot(const TiledView& T, const Geo& g, cons
     }
     __builtin_amdgcn_sched_barrier(0);
     float4 vn[U];
-    tile_load<W, U>(T, k + W * U, g1, lane, c, vn);
+    uint64_t mn[U][4];
+    if constexpr (KEPT) {
+      uint4 cn[U];
+      rec_take<U>(T, rn, cn, vn, mn);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        rn[u] = rec_at(T, k + (2 * U + u) * W, g1);
+        c[u] = cn[u];
+      }
+    } else {
+      tile_load<W, U>(T, k + W * U, g1, lane, c, vn);
+    }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      acc = fmaf(v[u].x, xs[u].x, acc);
-      acc = fmaf(v[u].y, xs[u].y, acc);
-      acc = fmaf(v[u].z, xs[u].z, acc);
-      acc = fmaf(v[u].w, xs[u].w, acc);
+      const float4 e = KEPT ? expand_kept(mk[u], v[u]) : v[u];
+      acc = fmaf(e.x, xs[u].x, acc);
+      acc = fmaf(e.y, xs[u].y, acc);
+      acc = fmaf(e.z, xs[u].z, acc);
+      acc = fmaf(e.w, xs[u].w, acc);
       v[u] = vn[u];
+      if constexpr (KEPT) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) mk[u][j] = mn[u][j];
+      }
     }
   }
   return tile_finish<W, float>(T, d, row, lane, wv, acc, x);
@@ -240,7 +296,7 @@ __device__ __forceinline__ float tile_dot16(const TiledView& T, const Geo& g, co
 // Float64 accumulation over the float32 tiles (the stopping test): x is
 // float32 (forward product) or float64 (the transposed product of the
 // float64 residual).
-template <int W, int U, typename X>
+template <int W, int U, bool KEPT, typename X>
 __device__ __forceinline__ double tile_dot64(const TiledView& T, const Geo& g, const int4& d, int row, int lane,
                                              int wv, const X* __restrict__ x) {
   const RowCode rc = tile_row_code(g, d, row);
@@ -249,11 +305,15 @@ __device__ __forceinline__ double tile_dot64(const TiledView& T, const Geo& g, c
   for (int k = (d.x >> 2) + wv; k < g1; k += W * U) {
     uint4 c[U];
     float4 v[U];
+    if constexpr (KEPT) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const bool ok = k + u * W < g1;
-      c[u] = ok ? T.code[k + u * W] : make_uint4(kPadCodeTile, kPadCodeTile, kPadCodeTile, kPadCodeTile);
-      v[u] = ok ? T.val[static_cast<int64_t>(k + u * W) * 64 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int u = 0; u < U; ++u) {
+        const GroupRec r = rec_at(T, k + u * W, g1);
+        c[u] = r.code;
+        v[u] = kept_values(r, T.kval, T.kbytes);
+      }
+    } else {
+      tile_load<W, U>(T, k, g1, lane, c, v);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -281,7 +341,7 @@ __device__ __forceinline__ void wave0_partial(double v, int lane, double* __rest
 
 // Stopping test, forward half: r64 = Theta_K x - x0 in float64 and per-tile
 // partials of ||r||^2, <r, x0> and sum_i w_i |x_i|.
-template <int W, int U, typename X>
+template <int W, int U, bool KEPT, typename X>
 __global__ __launch_bounds__(64 * W) void k_obj_fwd_tl(TiledView T, Geo g, const X* __restrict__ x,
                                                        const float* __restrict__ b, const float* __restrict__ w,
                                                        double* __restrict__ r64, double* __restrict__ partial,
@@ -290,7 +350,7 @@ __global__ __launch_bounds__(64 * W) void k_obj_fwd_tl(TiledView T, Geo g, const
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int row = tile_row(d, lane);
-  const double acc = tile_dot64<W, U>(T, g, d, row, lane, wv, x);
+  const double acc = tile_dot64<W, U, KEPT>(T, g, d, row, lane, wv, x);
   if (wv != 0) return;
   double v0 = 0.0, v1 = 0.0, v2 = 0.0;
   if (row >= 0) {
@@ -307,20 +367,20 @@ __global__ __launch_bounds__(64 * W) void k_obj_fwd_tl(TiledView T, Geo g, const
 }
 
 // Backward half: per-tile max of |(Theta_K^T r64)_i| / w_i.
-template <int W, int U>
+template <int W, int U, bool KEPT>
 __global__ __launch_bounds__(64 * W) void k_obj_bwd_tl(TiledView T, Geo g, const double* __restrict__ r64,
                                                        const float* __restrict__ w, double* __restrict__ partial) {
   const int4 d = T.desc[blockIdx.x];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int row = tile_row(d, lane);
-  const double gr = tile_dot64<W, U>(T, g, d, row, lane, wv, r64);
+  const double gr = tile_dot64<W, U, KEPT>(T, g, d, row, lane, wv, r64);
   if (wv != 0) return;
   const double v = row >= 0 ? fabs(gr) / (w ? static_cast<double>(w[row]) : 1.0) : 0.0;
   wave0_partial<true>(v, lane, partial);
 }
 
-template <int W, int U>
+template <int W, int U, bool KEPT>
 __global__ __launch_bounds__(64 * W) void k_res_tl(TiledView T, Geo g, const float* __restrict__ y,
                                                    const float* __restrict__ b, float* __restrict__ r,
                                                    int* __restrict__ kdev) {
@@ -330,7 +390,7 @@ __global__ __launch_bounds__(64 * W) void k_res_tl(TiledView T, Geo g, const flo
   const int row = tile_row(d, lane);
   const bool out = wv == 0 && row >= 0;
   const float bv = b && out ? b[row] : 0.0f;  // issued before the product so its latency overlaps
-  const float acc = tile_dot<W, U>(T, g, d, row, lane, wv, y);
+  const float acc = tile_dot<W, U, KEPT>(T, g, d, row, lane, wv, y);
   if (out) r[row] = acc - bv;
   // the iteration counter moves after the product: a global store ahead of
   // the loop would keep the code loads off the scalar path
@@ -373,7 +433,7 @@ __device__ __forceinline__ void prox_store(const ProxIn& p, int row, float gr, f
   y[row] = xn + p.beta * (xn - p.x);
 }
 
-template <int W, int U, bool PRE>
+template <int W, int U, bool PRE, bool KEPT>
 __global__ __launch_bounds__(64 * W) void k_prox_tl(TiledView T, Geo g, const float* __restrict__ r,
                                                     float* __restrict__ x, float* __restrict__ y, float tau,
                                                     float thr, float beta, const int* __restrict__ kdev,
@@ -385,7 +445,7 @@ __global__ __launch_bounds__(64 * W) void k_prox_tl(TiledView T, Geo g, const fl
   const int row = tile_row(d, lane);
   const bool out = wv == 0 && row >= 0;
   const ProxIn p = prox_load<PRE>(row, out, x, y, kdev, beta, pinv, tw, anc);
-  const float gr = tile_dot<W, U>(T, g, d, row, lane, wv, r);
+  const float gr = tile_dot<W, U, KEPT>(T, g, d, row, lane, wv, r);
   if (out) prox_store(p, row, gr, tau, thr, x, y, anc != nullptr);
 }
 
@@ -472,6 +532,11 @@ struct TileOut {
   std::vector<float> val;
   std::vector<int32_t> erow, ecol;
   std::vector<float> eval;
+  // float32 tiles only: row mask of each code (bit t: lane t keeps it), the
+  // kept values and each group's offset into them
+  std::vector<uint64_t> gmask;
+  std::vector<float> kval;
+  std::vector<int64_t> koff;
 };
 
 // Launch order of the tiles.  Workgroups are dealt round-robin to the 8
@@ -522,7 +587,8 @@ std::vector<int> xcd_order(const std::vector<int4>& tiles) {
 // then the quads, two pairs each, and the singles four at a time (the last
 // group mixing what remains); a group of 8 (16-bit values) is two such
 // groups.  The sequence is padded with kPadCodeTile to a multiple of grp.
-std::vector<uint32_t> group_runs(const std::vector<uint32_t>& u, int grp, bool extend) {
+std::vector<uint32_t> group_runs(const std::vector<uint32_t>& u, int grp, bool extend,
+                                 const std::vector<uint64_t>* rows = nullptr) {
   using F = CodeTile;
   std::vector<uint32_t> quads, pairs, singles;
   for (size_t a = 0; a < u.size();) {
@@ -543,6 +609,27 @@ std::vector<uint32_t> group_runs(const std::vector<uint32_t>& u, int grp, bool e
     for (; k < b; ++k) singles.push_back(u[k]);
     a = b;
   }
+  if (rows) {
+    // pairs and singles (whose order does not change the column loads)
+    // ordered by their row masks, fuller masks first, so that the codes of a
+    // group tend to be kept by the same rows
+    const auto mask_of = [&](uint32_t c) {
+      return (*rows)[static_cast<size_t>(std::lower_bound(u.begin(), u.end(), c) - u.begin())];
+    };
+    const auto fuller = [](uint64_t a, uint64_t b) {
+      const int pa = __builtin_popcountll(a), pb = __builtin_popcountll(b);
+      return pa != pb ? pa > pb : a < b;
+    };
+    std::vector<std::pair<uint64_t, uint32_t>> pm;
+    for (size_t k = 0; k < pairs.size(); k += 2) pm.emplace_back(mask_of(pairs[k]) | mask_of(pairs[k + 1]), pairs[k]);
+    std::stable_sort(pm.begin(), pm.end(), [&](const auto& x, const auto& y) { return fuller(x.first, y.first); });
+    for (size_t k = 0; k < pm.size(); ++k) {
+      pairs[2 * k] = pm[k].second;
+      pairs[2 * k + 1] = pm[k].second + 1;
+    }
+    std::stable_sort(singles.begin(), singles.end(),
+                     [&](uint32_t x, uint32_t y) { return fuller(mask_of(x), mask_of(y)); });
+  }
   std::vector<uint32_t> seq(quads);
   seq.insert(seq.end(), pairs.begin(), pairs.end());
   seq.insert(seq.end(), singles.begin(), singles.end());
@@ -562,6 +649,7 @@ void encode_tiles(const Geo& g, const std::vector<int4>& tiles, size_t t0, size_
   std::vector<std::pair<uint32_t, int>> ent;  // (code, lane) per kept entry of the tile
   std::vector<float> ent_v;
   std::vector<uint32_t> u;
+  std::vector<uint64_t> umask;
   for (size_t ti = t0; ti < t1; ++ti) {
     int4 d = tiles[ti];
     ent.clear();
@@ -596,7 +684,13 @@ void encode_tiles(const Geo& g, const std::vector<int4>& tiles, size_t t0, size_
     for (const auto& e : ent) u.push_back(e.first);
     std::sort(u.begin(), u.end());
     u.erase(std::unique(u.begin(), u.end()), u.end());
-    const std::vector<uint32_t> seq = group_runs(u, grp, grp == 8);
+    if (grp == 4) {  // row mask of each distinct code
+      umask.assign(u.size(), 0);
+      for (const auto& e : ent)
+        umask[static_cast<size_t>(std::lower_bound(u.begin(), u.end(), e.first) - u.begin())] |= uint64_t{1}
+                                                                                                   << e.second;
+    }
+    const std::vector<uint32_t> seq = group_runs(u, grp, grp == 8, grp == 4 ? &umask : nullptr);
     // position of each kept code in the sequence (extension and padding codes carry value 0)
     std::vector<std::pair<uint32_t, int>> at;
     at.reserve(u.size());
@@ -609,10 +703,22 @@ void encode_tiles(const Geo& g, const std::vector<int4>& tiles, size_t t0, size_
     const int pb = static_cast<int>(o.code.size());
     o.code.insert(o.code.end(), seq.begin(), seq.end());
     o.val.resize(o.val.size() + seq.size() * 64, 0.0f);
+    if (grp == 4) o.gmask.resize(o.code.size(), 0);
     for (size_t e = 0; e < ent.size(); ++e) {
       const auto it = std::lower_bound(at.begin(), at.end(), std::make_pair(ent[e].first, -1));
       const int64_t q = pb + it->second;
       o.val[((q / grp) * 64 + ent[e].second) * grp + (q % grp)] = ent_v[e];
+      if (grp == 4) o.gmask[q] |= uint64_t{1} << ent[e].second;
+    }
+    if (grp == 4) {
+      // the kept values of each group, lane by lane, each lane's in code order
+      for (size_t gi = pb / 4; gi < o.code.size() / 4; ++gi) {
+        const uint64_t* m = &o.gmask[4 * gi];
+        o.koff.push_back(static_cast<int64_t>(o.kval.size()));
+        for (int t = 0; t < 64; ++t)
+          for (int j = 0; j < 4; ++j)
+            if ((m[j] >> t) & 1) o.kval.push_back(o.val[(gi * 64 + t) * 4 + j]);
+      }
     }
     d.x = pb;
     d.y = pb + static_cast<int>(seq.size());
@@ -735,6 +841,36 @@ void build_one(const wdb_theta* th, const Csr32& src, Tiled* out, int fmt = WDB_
           WDB_HIP(hipMemcpy(t.val + at, r.val.data(), r.val.size() * sizeof(float), hipMemcpyHostToDevice));
         at += static_cast<int64_t>(r.val.size());
       }
+      // the kept-value layout: group records and kept values
+      const size_t ng = code.size() / 4;
+      std::vector<GroupRec> rec(ng);
+      int64_t kb = 0;
+      size_t gb = 0;
+      for (auto& r : res) {
+        const size_t n = r.code.size() / 4;
+        for (size_t gi = 0; gi < n; ++gi) {
+          GroupRec& a = rec[gb + gi];
+          a = GroupRec{};
+          a.code = make_uint4(r.code[4 * gi], r.code[4 * gi + 1], r.code[4 * gi + 2], r.code[4 * gi + 3]);
+          for (int j = 0; j < 4; ++j) a.m[j] = r.gmask[4 * gi + j];
+          a.voff = static_cast<uint32_t>(kb + r.koff[gi]);
+        }
+        gb += n;
+        kb += static_cast<int64_t>(r.kval.size());
+      }
+      // kept values are addressed by 32-bit byte offsets of buffer loads
+      WDB_REQUIRE(4 * (kb + 4) < (int64_t{1} << 31), WDB_ERR_ARG, "kept tile values exceed a 2 GiB buffer");
+      t.nkval = kb;
+      WDB_HIP(hipMalloc(&t.grec, std::max<size_t>(ng, 1) * sizeof(GroupRec)));
+      WDB_HIP(hipMalloc(reinterpret_cast<void**>(&t.kval), (kb + 4) * sizeof(float)));
+      if (ng) WDB_HIP(hipMemcpy(t.grec, rec.data(), ng * sizeof(GroupRec), hipMemcpyHostToDevice));
+      WDB_HIP(hipMemset(t.kval, 0, (kb + 4) * sizeof(float)));
+      int64_t ka = 0;
+      for (auto& r : res) {
+        if (!r.kval.empty())
+          WDB_HIP(hipMemcpy(t.kval + ka, r.kval.data(), r.kval.size() * sizeof(float), hipMemcpyHostToDevice));
+        ka += static_cast<int64_t>(r.kval.size());
+      }
     } else {
       WDB_HIP(hipMalloc(reinterpret_cast<void**>(&t.val16), std::max<int64_t>(nval, 8) * sizeof(uint16_t)));
       std::vector<uint16_t> h;
@@ -765,8 +901,12 @@ void build_one(const wdb_theta* th, const Csr32& src, Tiled* out, int fmt = WDB_
 
 void Tiled::free_all() {
   for (void* p : {static_cast<void*>(desc), static_cast<void*>(code), static_cast<void*>(val),
-                  static_cast<void*>(val16), static_cast<void*>(erp), static_cast<void*>(ec), static_cast<void*>(ev)})
+                  static_cast<void*>(val16), static_cast<void*>(erp), static_cast<void*>(ec), static_cast<void*>(ev),
+                  grec, static_cast<void*>(kval)})
     if (p) (void)hipFree(p);
+  grec = nullptr;
+  kval = nullptr;
+  nkval = 0;
   desc = nullptr;
   code = nullptr;
   val = nullptr;
@@ -852,8 +992,16 @@ void objective_tiled(const wdb_theta* th, const X* x, const float* x0, double* r
   with_shape(th->tile_waves, th->tile_unroll, [&](auto Wc, auto Uc) {
     constexpr int W = decltype(Wc)::value, U = decltype(Uc)::value;
     const dim3 grid(static_cast<unsigned>(nb)), block(64 * W);
-    hipLaunchKernelGGL((k_obj_fwd_tl<W, U, X>), grid, block, 0, s, tview(th->tA), g, x, x0, th->l1w, r64, part, nb);
-    hipLaunchKernelGGL((k_obj_bwd_tl<W, U>), grid, block, 0, s, tview(th->tAt), g, r64, th->l1w, part + 3 * nb);
+    if (th->tile_kept) {
+      hipLaunchKernelGGL((k_obj_fwd_tl<W, U, true, X>), grid, block, 0, s, tview(th->tA), g, x, x0, th->l1w, r64,
+                         part, nb);
+      hipLaunchKernelGGL((k_obj_bwd_tl<W, U, true>), grid, block, 0, s, tview(th->tAt), g, r64, th->l1w, part + 3 * nb);
+    } else {
+      hipLaunchKernelGGL((k_obj_fwd_tl<W, U, false, X>), grid, block, 0, s, tview(th->tA), g, x, x0, th->l1w, r64,
+                         part, nb);
+      hipLaunchKernelGGL((k_obj_bwd_tl<W, U, false>), grid, block, 0, s, tview(th->tAt), g, r64, th->l1w,
+                         part + 3 * nb);
+    }
   });
 }
 }  // namespace
@@ -875,8 +1023,11 @@ void launch_res_tiled(const wdb_theta* th, bool transpose, const float* y, const
   const Geo g = geo_of(th);
   with_shape(th->tile_waves, th->tile_unroll, [&](auto Wc, auto Uc) {
     constexpr int W = decltype(Wc)::value, U = decltype(Uc)::value;
-    hipLaunchKernelGGL((k_res_tl<W, U>), dim3(static_cast<unsigned>(T.ntiles)), dim3(64 * W), 0, s, tview(T), g, y,
-                       b, r, kdev);
+    const dim3 grid(static_cast<unsigned>(T.ntiles)), block(64 * W);
+    if (th->tile_kept)
+      hipLaunchKernelGGL((k_res_tl<W, U, true>), grid, block, 0, s, tview(T), g, y, b, r, kdev);
+    else
+      hipLaunchKernelGGL((k_res_tl<W, U, false>), grid, block, 0, s, tview(T), g, y, b, r, kdev);
   });
 }
 
@@ -888,16 +1039,30 @@ void launch_prox_tiled(const wdb_theta* th, const float* r, float* x, float* y, 
   with_shape(th->tile_waves, th->tile_unroll, [&](auto Wc, auto Uc) {
     constexpr int W = decltype(Wc)::value, U = decltype(Uc)::value;
     const dim3 grid(static_cast<unsigned>(T.ntiles)), block(64 * W);
-    if (pinv)
-      hipLaunchKernelGGL((k_prox_tl<W, U, true>), grid, block, 0, s, tview(T), g, r, x, y, tau, thr, beta, kdev,
-                         pinv, tw, anc);
-    else
-      hipLaunchKernelGGL((k_prox_tl<W, U, false>), grid, block, 0, s, tview(T), g, r, x, y, tau, thr, beta, kdev,
-                         pinv, tw, anc);
+    auto go = [&](auto Kc) {
+      constexpr bool KEPT = decltype(Kc)::value;
+      if (pinv)
+        hipLaunchKernelGGL((k_prox_tl<W, U, true, KEPT>), grid, block, 0, s, tview(T), g, r, x, y, tau, thr, beta,
+                           kdev, pinv, tw, anc);
+      else
+        hipLaunchKernelGGL((k_prox_tl<W, U, false, KEPT>), grid, block, 0, s, tview(T), g, r, x, y, tau, thr, beta,
+                           kdev, pinv, tw, anc);
+    };
+    if (th->tile_kept) go(std::true_type{});
+    else go(std::false_type{});
   });
 }
 
 }  // namespace wdb
+
+extern "C" wdb_status wdb_set_tile_values(wdb_theta* th, int32_t kept) {
+  WDB_API_BEGIN
+  WDB_REQUIRE(th, WDB_ERR_ARG, "null handle");
+  WDB_REQUIRE(kept == 0 || kept == 1, WDB_ERR_ARG, "tile value layout must be 0 (dense) or 1 (kept values)");
+  wdb::drop_graph(th);  // the cached iteration graph may refer to what this call changes
+  th->tile_kept = kept;
+  WDB_API_END
+}
 
 extern "C" wdb_status wdb_set_tile_shape(wdb_theta* th, int32_t waves, int32_t unroll) {
   WDB_API_BEGIN

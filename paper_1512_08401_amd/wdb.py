@@ -51,7 +51,8 @@ class ThetaDesc(C.Structure):
                 ("group16", C.c_int32), ("escapes", C.c_int64), ("conv_build", C.c_int32),
                 ("l1_weights", C.c_int32), ("rule", C.c_int32), ("circulant", C.c_int64),
                 ("tile_waves", C.c_int32), ("tile_slots", C.c_int64), ("tile_waves16", C.c_int32),
-                ("tile_unroll", C.c_int32), ("tile_unroll16", C.c_int32), ("tile_escapes", C.c_int64)]
+                ("tile_unroll", C.c_int32), ("tile_unroll16", C.c_int32), ("tile_escapes", C.c_int64),
+                ("tile_kept", C.c_int32), ("reserved", C.c_int32), ("tile_kept_values", C.c_int64)]
 
 
 class SolveOpts(C.Structure):
@@ -104,6 +105,7 @@ _SIGS = {
     "wdb_set_kernel_layout": [_vp, _i32, _i32],
     "wdb_set_packed_group": [_vp, _i32],
     "wdb_set_tile_shape": [_vp, _i32, _i32],
+    "wdb_set_tile_values": [_vp, _i32],
     "wdb_set_l1_weights": [_vp, _i32, _vp],
     "wdb_autotune": [_vp, C.c_char_p, _i32, C.POINTER(_i32), C.POINTER(_i32), _pd],
     "wdb_cnn_create": [_i32, _i32, _i32, C.c_uint64, C.POINTER(_vp)],
@@ -317,6 +319,11 @@ class Theta:
         """Tiled kernels of the current value type: wavefronts per tile (1/2/4/8) and
         code groups in flight per wavefront (1/2/4; 0 = default)."""
         _check("wdb_set_tile_shape", _lib.wdb_set_tile_shape(self._h, int(waves), int(unroll)))
+
+    def set_tile_values(self, kept: bool):
+        """Value layout of the float32 tiled kernels: kept values with row masks
+        (True) or the dense values (False)."""
+        _check("wdb_set_tile_values", _lib.wdb_set_tile_values(self._h, 1 if kept else 0))
 
     def autotune(self, cache_path: str | None = None, reps: int = 20):
         """Pick the fastest iteration layout for this operator; returns (slice, group, us)."""

@@ -1,8 +1,9 @@
 // Host-side checks of the tiled pattern storage (no GPU needed): the tile
 // list covers every coefficient once, the XCD launch order is a permutation
 // of it, the shared group decode gives the same column as the per-code
-// decode for every lane of every group, and the product over the encoded
-// tiles (codes, values, escapes), for both value groupings, equals the
+// decode for every lane of every group, the kept-value layout of the float32
+// tiles reads the same values as their dense layout, and the product over the
+// encoded tiles (codes, values, escapes), for both value groupings, equals the
 // row-wise product of the same sparse matrix exactly: values are multiples
 // of 2^-8 and x of 2^-7, small enough that every float64 sum is exact in any
 // order.
@@ -154,6 +155,34 @@ void check(int logn, int J, int L1, std::mt19937_64& rng) {
       }
     }
     for (size_t k = 0; k < o.erow.size(); ++k) got[o.erow[k]] += static_cast<double>(o.eval[k]) * x[o.ecol[k]];
+    if (grp == 4) {
+      // the kept-value layout, read as a lane reads it: its values start at the
+      // group's offset plus the kept entries of the lanes below, and code j
+      // takes the next one if the lane's bit of mask j is set; every slot must
+      // equal the dense value (zero where the lane lacks the code)
+      bool same_vals = o.gmask.size() == o.code.size() && o.koff.size() == o.code.size() / 4;
+      int64_t kept = 0;
+      for (size_t gi = 0; same_vals && gi < o.koff.size(); ++gi) {
+        const uint64_t* m = &o.gmask[4 * gi];
+        for (int t = 0; t < 64; ++t) {
+          const uint64_t below = (uint64_t{1} << t) - 1;
+          int64_t at = o.koff[gi];
+          for (int j = 0; j < 4; ++j) at += __builtin_popcountll(m[j] & below);
+          for (int j = 0; j < 4; ++j) {
+            const bool has = (m[j] >> t) & 1;
+            const float v = has ? o.kval[at++] : 0.0f;
+            same_vals = same_vals && v == o.val[(gi * 64 + t) * 4 + j];
+            kept += has;
+          }
+        }
+      }
+      int64_t nonzero = 0;
+      for (float v : val) nonzero += v != 0.0f;
+      expect(same_vals, "kept-value layout reads the dense values", logn, J);
+      expect(kept == static_cast<int64_t>(o.kval.size()) &&
+                 kept + static_cast<int64_t>(o.erow.size()) == nonzero,
+             "kept values hold each non-escaped entry once", logn, J);
+    }
     expect(whole, "tile code ranges are whole groups", logn, J);
     expect(same_cols, "group decode equals per-code decode", logn, J);
     expect(in_range, "decoded columns in range", logn, J);

@@ -78,6 +78,9 @@ def test_host_validation_errors(lib):
     assert lib.wdb_dwt(64, 1, 5, fake, C.c_void_p(32), 0, None) == wdb.WDB_ERR_LEVELS   # 64/16 < 8 taps
     assert lib.wdb_dwt(64, 0, 1, None, C.c_void_p(32), 0, None) == wdb.WDB_ERR_ARG
     assert lib.wdb_dwt(64, 0, 1, fake, fake, 0, None) == wdb.WDB_ERR_ARG                # aliasing
+    assert lib.wdb_set_tile_values(None, 1) == wdb.WDB_ERR_ARG
+    assert lib.wdb_set_tile_values(fake, 2) == wdb.WDB_ERR_ARG
+    assert "kept values" in lib.wdb_last_error().decode()
     big = C.c_void_p(1 << 40)   # far from `fake`: the two batches do not overlap
     assert lib.wdb_dwt_batched(64, 0, 1, 0, fake, big, 0, None) == wdb.WDB_ERR_ARG        # count < 1
     assert lib.wdb_dwt_batched(64, 0, 1, 2, None, big, 0, None) == wdb.WDB_ERR_ARG        # null input

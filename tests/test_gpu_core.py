@@ -932,15 +932,17 @@ def small32():
     return {"field": field, "h": h, "A": A, "A32": A32, "H": blur.blur_matrix(field)}
 
 
-@pytest.mark.parametrize("tiled", [False, True])
+@pytest.mark.parametrize("tiled", [False, True, "kept"])
 def test_batched_narrowing_keeps_the_iterates(W, p64, tiled):
     """A pack narrows (8 -> 4 -> 2 -> 1 slots) as its problems stop; that must
     change only the cost: each problem's float64 iterate and stopping
     iteration equal those of the same problem solved alone (a pack of one),
-    bit for bit, since every slot keeps its own sums in the same order."""
+    bit for bit, since every slot keeps its own sums in the same order.  The
+    tiled runs use the dense and the kept-value layouts."""
     th = imported(W, p64)
     if tiled:
         th.set_kernel_layout(8, 3)
+        th.set_tile_values(tiled == "kept")
     wl = p64["wl"]
     th.lipschitz(synth.power_start(4096, 3))
     H = blur.blur_matrix(wl.psf())
@@ -959,16 +961,17 @@ def test_batched_narrowing_keeps_the_iterates(W, p64, tiled):
         assert torch.equal(o1[0], o_all[i]), i
 
 
-@pytest.mark.parametrize("tiled64", [False, True])
+@pytest.mark.parametrize("tiled64", [False, True, "kept"])
 def test_batched_matches_oracle_per_problem(W, p64, small32, tiled64):
     """13 problems on two operators (chunks of 8 + 2 and 3); with tiled64 the
-    64 x 64 operator's chunks run on its tiled copies while the 32 x 32 one
-    stays on sliced ELL, in the same launches."""
+    64 x 64 operator's chunks run on its tiled copies (dense or kept values)
+    while the 32 x 32 one stays on sliced ELL, in the same launches."""
     th64 = imported(W, p64)
     rp, cc, vv = theta.csr_arrays(small32["A"])
     th32 = W.Theta.from_csr(32, "haar", 2, rp, cc, vv)
     if tiled64:
         th64.set_kernel_layout(8, 3)
+        th64.set_tile_values(tiled64 == "kept")
     wl = p64["wl"]
     start64, start32 = synth.power_start(4096, 3), synth.power_start(1024, 4)
     th64.lipschitz(start64)
@@ -1057,14 +1060,19 @@ def test_layouts_match_oracle(W, p64, slice_h, group):
     assert np.max(np.abs(th.precond() - po) / po) <= 1e-10
 
 
-@pytest.mark.parametrize("waves,unroll", [(1, 2), (2, 4), (4, 2), (8, 4)])
-def test_tiled_layout_matches_oracle(W, p64, waves, unroll):
-    """Tiled pattern storage (layout 3): products, FISTA, and the proximal
-    epilogue with the preconditioner and scale weights, against the oracle."""
+@pytest.mark.parametrize("waves,unroll,kept", [(1, 2, 0), (2, 4, 0), (4, 2, 0), (8, 4, 0),
+                                               (2, 1, 1), (1, 2, 1), (4, 4, 1), (8, 1, 1)])
+def test_tiled_layout_matches_oracle(W, p64, waves, unroll, kept):
+    """Tiled pattern storage (layout 3), dense or kept values: products, FISTA,
+    and the proximal epilogue with the preconditioner and scale weights,
+    against the oracle."""
     th = imported(W, p64)
     th.set_kernel_layout(8, 3)
     th.set_tile_shape(waves, unroll)
-    assert th.info()["group"] == 3 and th.info()["tile_unroll"] == unroll
+    th.set_tile_values(kept)
+    info = th.info()
+    assert info["group"] == 3 and info["tile_unroll"] == unroll and info["tile_kept"] == kept
+    assert info["tile_kept_values"] == 2 * p64["A32"].nnz   # every kept entry once per copy, no zeros
     A32 = p64["A32"]
     rng = np.random.default_rng(waves)
     x = rng.standard_normal(4096).astype(np.float32)
@@ -1094,6 +1102,28 @@ def test_tiled_layout_matches_oracle(W, p64, waves, unroll):
     assert np.linalg.norm(host(xp) - xo) <= 1e-4 * np.linalg.norm(xo)
 
 
+def test_tiled_kept_values_match_dense_bit_for_bit(W, p64):
+    """The kept-value layout adds the same products in the same order as the
+    dense values (a missing entry contributes an exact 0 in both), so products,
+    the float64 checks and whole solves agree bit for bit."""
+    th = imported(W, p64)
+    th.set_kernel_layout(8, 3)
+    wl = p64["wl"]
+    th.lipschitz(synth.power_start(4096, wl.power_seed))
+    x = np.random.default_rng(5).standard_normal(4096).astype(np.float32)
+    x0 = p64["x0"].astype(np.float32)
+    out = {}
+    for kept in (0, 1):
+        th.set_tile_values(kept)
+        th.set_tile_shape(2, 1)
+        y = host(th.apply(dev(x), dev(x0)))
+        yt = host(th.apply(dev(x), transpose=True))
+        xs, info = th.solve_coeffs(dev(x0), wl.lam, 120, check_every=20)
+        out[kept] = (y, yt, host(xs), info["objective"], info["rel_gap"])
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(np.asarray(a), np.asarray(b))
+
+
 def test_tiled_escapes_and_small_subbands_match_oracle(W):
     """A 128 x 128, 5-level operator: the coarsest subbands are 4 x 4 (one
     partial tile each); random far columns, and for some finest-level rows a
@@ -1119,14 +1149,17 @@ def test_tiled_escapes_and_small_subbands_match_oracle(W):
     assert th.info()["tile_escapes"] > 0
     A32 = sp.csr_matrix((A.data.astype(np.float32).astype(np.float64), A.indices, A.indptr), shape=A.shape)
     x = rng.standard_normal(N).astype(np.float32)
-    for waves in (1, 4):
-        th.set_tile_shape(waves)
+    for waves, unroll, kept in ((1, 2, 0), (4, 2, 0), (1, 1, 1), (4, 2, 1)):
+        th.set_tile_shape(waves, unroll)
+        th.set_tile_values(kept)
         y = host(th.apply(dev(x)))
         ref = A32 @ x.astype(np.float64)
-        assert np.max(np.abs(y - ref)) <= 1e-5 * np.max(np.abs(ref)), waves
+        assert np.max(np.abs(y - ref)) <= 1e-5 * np.max(np.abs(ref)), (waves, kept)
         yt = host(th.apply(dev(x), transpose=True))
         reft = A32.T @ x.astype(np.float64)
-        assert np.max(np.abs(yt - reft)) <= 1e-5 * np.max(np.abs(reft)), waves
+        assert np.max(np.abs(yt - reft)) <= 1e-5 * np.max(np.abs(reft)), (waves, kept)
+    th.set_tile_shape(1, 2)
+    th.set_tile_values(0)
     start = synth.power_start(N, 6)
     th.lipschitz(start)
     x0 = rng.standard_normal(N).astype(np.float32)

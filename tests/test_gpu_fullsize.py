@@ -86,10 +86,12 @@ def test_fullsize_products_every_layout(W, standin):
           f"{info['tile_waves']}x{info['tile_unroll']}", flush=True)
     _close(host(th.apply(dev(x), dev(b))), ref, "autotuned layout")
     _close(host(th.apply(dev(x), transpose=True)), reft, "autotuned layout, transposed")
-    for lay, shape in (((8, 3), (4, 2)), ((8, 3), (2, 2)), ((8, 4), None), ((8, 0), None)):
+    for lay, shape in (((8, 3), (4, 2, 0)), ((8, 3), (2, 2, 0)), ((8, 3), (2, 1, 1)), ((8, 3), (1, 2, 1)),
+                       ((8, 4), None), ((8, 0), None)):
         th.set_kernel_layout(*lay)
         if shape:
-            th.set_tile_shape(*shape)
+            th.set_tile_shape(*shape[:2])
+            th.set_tile_values(shape[2])
         print(f"  layout {lay} {shape}", flush=True)
         _close(host(th.apply(dev(x), dev(b))), ref, (lay, shape))
         _close(host(th.apply(dev(x), transpose=True)), reft, (lay, shape, "T"))
