@@ -172,6 +172,10 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance measurement")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default kernel layout")
+    ap.add_argument("--tile", default=None, metavar="W,U,K",
+                    help="run the tiled layout with W wavefronts per tile, U code groups in flight and "
+                         "K = 1 kept values (0 dense) instead of the autotuner's choice (profiling runs, "
+                         "whose timing would perturb the autotuner)")
     ap.add_argument("--form", default="plain", choices=["plain", "batched", "learned", "conv", "tuned", "exact", "cnn"],
                     help="plain: the single-problem solve (default); batched / learned: the extension workloads")
     ap.add_argument("--train-images", type=int, default=4096)
@@ -214,7 +218,12 @@ def main():
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
     t0 = time.perf_counter()
-    if not args.no_autotune:
+    if args.tile:
+        tw, tu, tk = (int(v) for v in args.tile.split(","))
+        th.set_kernel_layout(th.info()["slice"], 3)
+        th.set_tile_shape(tw, tu)
+        th.set_tile_values(tk)
+    elif not args.no_autotune:
         th.autotune(reps=10)
     layout = (th.info()["slice"], th.info()["group"])
     tile_shape = (th.info()["tile_waves"], th.info()["tile_unroll"], th.info()["tile_kept"])
