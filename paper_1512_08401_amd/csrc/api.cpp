@@ -84,6 +84,8 @@ void free_workspace(wdb_theta* th) {
   if (th->ws_k) (void)hipFree(th->ws_k);
   if (th->ws_rho) (void)hipFree(th->ws_rho);
   if (th->capture_stream) (void)hipStreamDestroy(th->capture_stream);
+  if (th->check_event) (void)hipEventDestroy(th->check_event);
+  th->check_event = nullptr;
   th->ws_k = nullptr;
   th->ws_rho = nullptr;
   th->capture_stream = nullptr;

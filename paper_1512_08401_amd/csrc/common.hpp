@@ -293,6 +293,7 @@ struct wdb_theta {
   double* ws_rho = nullptr;      // power-iteration history (64 entries)
   int64_t ws_nblocks = 0;
   hipStream_t capture_stream = nullptr;
+  hipEvent_t check_event = nullptr;  // marks a check's scalars on the host while the next block runs
   // Instantiated graph of `g_c` iterations of the last graph-replayed solve and
   // the parameters it was captured with; dropped by every call that changes the
   // handle (layout, precision, preconditioner, weights, L), so a replay only

@@ -1318,10 +1318,18 @@ wdb_status solve_impl(wdb_theta* th, const float* x0_src, bool from_image, float
         th->ws_ncheck = ncheck;
       }
     }
+    // With the anchored iterate the next block of iterations is enqueued before
+    // the host reads a check: the iterations only change the displacement, so
+    // the anchor still holds the checked iterate if the check stops the solve
+    // (the final output is taken from the anchor), and the GPU does not idle
+    // while the host waits for the check's scalars.
+    bool ahead = false;  // the block after the last check is already enqueued
     while (done < total) {
       int step = total - done;
       if (c > 0) step = std::min(step, c - (done % c));
-      if (exec && step == c) {
+      if (ahead) {
+        ahead = false;
+      } else if (exec && step == c) {
         WDB_HIP(hipGraphLaunch(exec, s));
       } else {
         for (int i = 0; i < step; ++i) launch_iteration(th, x_out, pre, opts->ista != 0, tau_f, thr_f, s, anchored);
@@ -1332,8 +1340,19 @@ wdb_status solve_impl(wdb_theta* th, const float* x0_src, bool from_image, float
       if (at_check && !stop_test) {
         enqueue_point(th->ws_checks + 4 * at_iter.size());
         at_iter.push_back(done);
+      } else if (at_check && anchored && exec && total - done >= c) {
+        if (!th->check_event) WDB_HIP(hipEventCreateWithFlags(&th->check_event, hipEventDisableTiming));
+        enqueue_point(th->ws_scalar);
+        WDB_HIP(hipMemcpyAsync(th->host_scalar, th->ws_scalar, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+        WDB_HIP(hipEventRecord(th->check_event, s));
+        WDB_HIP(hipGraphLaunch(exec, s));
+        ahead = true;
+        WDB_HIP(hipEventSynchronize(th->check_event));
+        last = check_from(th->host_scalar, lambda);
       } else if (at_check) {
         last = check_point();
+      }
+      if (at_check && stop_test) {
         ++checks;
         if (opts->trace && checks <= opts->trace_cap) {
           opts->trace[3 * (checks - 1) + 0] = static_cast<double>(k0 - 1 + done);

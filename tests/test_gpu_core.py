@@ -600,6 +600,30 @@ def test_tolerance_stop(W, p64):
     assert not info["converged"]
 
 
+def test_graph_solve_stops_on_the_checked_iterate(W, p64):
+    """With graph replay and the anchored iterate the block after a check is
+    enqueued before the host reads the check.  A stop must still return the
+    checked iterate: the same float32 and float64 iterates, iteration count,
+    objective and gap as the eager solve, and the oracle's gap of that
+    iterate."""
+    th = imported(W, p64)
+    wl = p64["wl"]
+    A32, lam = p64["A32"], float(np.float32(wl.lam))
+    outs = []
+    for g in (False, True):
+        x64 = torch.empty(4096, device="cuda", dtype=torch.float64)
+        x, info = th.solve_coeffs(dev(p64["x0"]), wl.lam, 5000, check_every=20, tol=1e-3, use_graph=g,
+                                  x64_out=x64)
+        torch.cuda.synchronize()
+        outs.append((host(x), host(x64), info))
+    (xa, ya, ia), (xb, yb, ib) = outs
+    assert ia["converged"] and ib["converged"] and 40 <= ia["iters"] < 5000
+    assert ia["iters"] == ib["iters"] and ia["objective"] == ib["objective"] and ia["rel_gap"] == ib["rel_gap"]
+    assert np.array_equal(xa, xb) and np.array_equal(ya, yb)
+    E, D, gap, rel = fista.duality_gap(A32, p64["x0"].astype(np.float32).astype(np.float64), lam, yb)
+    assert abs(rel - ib["rel_gap"]) <= 1e-9
+
+
 @pytest.fixture(scope="module")
 def db4_32():
     """Small db4 problem with large approximation coefficients relative to
