@@ -302,26 +302,59 @@ __device__ __forceinline__ double tile_dot64(const TiledView& T, const Geo& g, c
   const RowCode rc = tile_row_code(g, d, row);
   double acc = 0.0;
   const int g1 = d.y >> 2;
-  for (int k = (d.x >> 2) + wv; k < g1; k += W * U) {
-    uint4 c[U];
-    float4 v[U];
-    if constexpr (KEPT) {
+  int k = (d.x >> 2) + wv;
+  uint4 c[U];
+  float4 v[U];
+  uint64_t mk[U][4];
+  GroupRec rn[U];
+  if constexpr (KEPT) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const GroupRec r = rec_at(T, k + u * W, g1);
-        c[u] = r.code;
-        v[u] = kept_values(r, T.kval, T.kbytes);
-      }
-    } else {
-      tile_load<W, U>(T, k, g1, lane, c, v);
-    }
+    for (int u = 0; u < U; ++u) rn[u] = rec_at(T, k + u * W, g1);
+    rec_take<U>(T, rn, c, v, mk);
+#pragma unroll
+    for (int u = 0; u < U; ++u) rn[u] = rec_at(T, k + (U + u) * W, g1);
+  } else {
+    tile_load<W, U>(T, k, g1, lane, c, v);
+  }
+  // the same step order as tile_dot: gathers, then the next step's loads,
+  // then the float64 sums of this step in code order
+  for (; k < g1; k += W * U) {
+    X xs[U][4];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int4 col = group_cols(g, rc, c[u]);
-      acc = fma(static_cast<double>(v[u].x), static_cast<double>(ld_at(x, col.x)), acc);
-      acc = fma(static_cast<double>(v[u].y), static_cast<double>(ld_at(x, col.y)), acc);
-      acc = fma(static_cast<double>(v[u].z), static_cast<double>(ld_at(x, col.z)), acc);
-      acc = fma(static_cast<double>(v[u].w), static_cast<double>(ld_at(x, col.w)), acc);
+      xs[u][0] = ld_at(x, col.x);
+      xs[u][1] = ld_at(x, col.y);
+      xs[u][2] = ld_at(x, col.z);
+      xs[u][3] = ld_at(x, col.w);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    float4 vn[U];
+    uint64_t mn[U][4];
+    if constexpr (KEPT) {
+      uint4 cn[U];
+      rec_take<U>(T, rn, cn, vn, mn);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        rn[u] = rec_at(T, k + (2 * U + u) * W, g1);
+        c[u] = cn[u];
+      }
+    } else {
+      tile_load<W, U>(T, k + W * U, g1, lane, c, vn);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const float4 e = KEPT ? expand_kept(mk[u], v[u]) : v[u];
+      acc = fma(static_cast<double>(e.x), static_cast<double>(xs[u][0]), acc);
+      acc = fma(static_cast<double>(e.y), static_cast<double>(xs[u][1]), acc);
+      acc = fma(static_cast<double>(e.z), static_cast<double>(xs[u][2]), acc);
+      acc = fma(static_cast<double>(e.w), static_cast<double>(xs[u][3]), acc);
+      v[u] = vn[u];
+      if constexpr (KEPT) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) mk[u][j] = mn[u][j];
+      }
     }
   }
   return tile_finish<W, double>(T, d, row, lane, wv, acc, x);
