@@ -209,9 +209,11 @@ extern "C" wdb_status wdb_autotune(wdb_theta* th, const char* cache_path, int32_
     if (th->st.seg) cands.push_back({0, kStencil, 0});  // circulant storage (convolution fast path)
     if (tiled_supported(th)) {
       build_tiled(th);
-      for (int K : {0, 1})
+      for (int K : {0, 1}) {
+        if (K == 1 && !tiled_kept_available(th)) continue;
         for (int W : {1, 2, 4, 8})
           for (int U : {1, 2, 4}) cands.push_back({0, kTiled, shape_code(W, U, K)});
+      }
     }
     hipEvent_t e0, e1;
     WDB_HIP(hipEventCreate(&e0));
@@ -279,6 +281,7 @@ extern "C" wdb_status wdb_autotune(wdb_theta* th, const char* cache_path, int32_
   th->spmv_group = bestG;
   if (bestG == kTiled) {
     set_tile_shape_code(th, bestW);
+    if (th->tile_kept && !tiled_kept_available(th)) th->tile_kept = 0;  // a cached choice for other tiles
   } else {  // the tiled copies are only kept when they are the layout in use
     th->tA.free_all();
     th->tAt.free_all();

@@ -766,6 +766,7 @@ extern "C" wdb_status wdb_solve_batched(int32_t nprob, const wdb_problem* probs,
     d.ntiles = 0;
     d.tkept = 0;
     if (kernel_group(th) == kTiled) {  // the operator iterates on its tiled copies
+      WDB_REQUIRE(!th->tile_kept || tiled_kept_available(th), WDB_ERR_ARG, "kept-value tiles not built");
       d.tkept = th->tile_kept;
       WDB_REQUIRE(th->tA.ntiles == th->tAt.ntiles, WDB_ERR_ARG, "mismatched tile lists");
       d.ntiles = th->tA.ntiles;

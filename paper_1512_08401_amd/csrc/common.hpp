@@ -327,6 +327,7 @@ constexpr int kStencil = 1;  // kernel "group" value selecting the stencil kerne
 constexpr int kTiled = 3;    // kernel "group" value selecting the tiled pattern kernels
 bool tiled_supported(const wdb_theta* th);
 void build_tiled(wdb_theta* th);    // builds tA / tAt from cA / cAt if not built yet
+bool tiled_kept_available(const wdb_theta* th);  // both tiled copies hold the kept-value layout
 void build_tiled16(wdb_theta* th);  // builds qA / qAt (16-bit values, scales qscale) if not built yet
 // Float64 stopping-test products over the tiles: partials of ||r||^2, <r, x0>,
 // sum w|x| at part[0..3 nb) and of max |g_i| / w_i at part[3 nb, 4 nb), one

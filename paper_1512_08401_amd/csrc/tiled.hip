@@ -891,18 +891,20 @@ void build_one(const wdb_theta* th, const Csr32& src, Tiled* out, int fmt = WDB_
         gb += n;
         kb += static_cast<int64_t>(r.kval.size());
       }
-      // kept values are addressed by 32-bit byte offsets of buffer loads
-      WDB_REQUIRE(4 * (kb + 4) < (int64_t{1} << 31), WDB_ERR_ARG, "kept tile values exceed a 2 GiB buffer");
-      t.nkval = kb;
-      WDB_HIP(hipMalloc(&t.grec, std::max<size_t>(ng, 1) * sizeof(GroupRec)));
-      WDB_HIP(hipMalloc(reinterpret_cast<void**>(&t.kval), (kb + 4) * sizeof(float)));
-      if (ng) WDB_HIP(hipMemcpy(t.grec, rec.data(), ng * sizeof(GroupRec), hipMemcpyHostToDevice));
-      WDB_HIP(hipMemset(t.kval, 0, (kb + 4) * sizeof(float)));
-      int64_t ka = 0;
-      for (auto& r : res) {
-        if (!r.kval.empty())
-          WDB_HIP(hipMemcpy(t.kval + ka, r.kval.data(), r.kval.size() * sizeof(float), hipMemcpyHostToDevice));
-        ka += static_cast<int64_t>(r.kval.size());
+      // kept values are addressed by 32-bit byte offsets of buffer loads: an
+      // operator with more than 2 GiB of them keeps only the dense layout
+      if (4 * (kb + 4) < (int64_t{1} << 31)) {
+        t.nkval = kb;
+        WDB_HIP(hipMalloc(&t.grec, std::max<size_t>(ng, 1) * sizeof(GroupRec)));
+        WDB_HIP(hipMalloc(reinterpret_cast<void**>(&t.kval), (kb + 4) * sizeof(float)));
+        if (ng) WDB_HIP(hipMemcpy(t.grec, rec.data(), ng * sizeof(GroupRec), hipMemcpyHostToDevice));
+        WDB_HIP(hipMemset(t.kval, 0, (kb + 4) * sizeof(float)));
+        int64_t ka = 0;
+        for (auto& r : res) {
+          if (!r.kval.empty())
+            WDB_HIP(hipMemcpy(t.kval + ka, r.kval.data(), r.kval.size() * sizeof(float), hipMemcpyHostToDevice));
+          ka += static_cast<int64_t>(r.kval.size());
+        }
       }
     } else {
       WDB_HIP(hipMalloc(reinterpret_cast<void**>(&t.val16), std::max<int64_t>(nval, 8) * sizeof(uint16_t)));
@@ -956,7 +958,10 @@ void build_tiled(wdb_theta* th) {
   if (th->tA.desc && th->tAt.desc) return;
   build_one(th, th->cA, &th->tA);
   build_one(th, th->cAt, &th->tAt);
+  if (!tiled_kept_available(th)) th->tile_kept = 0;
 }
+
+bool tiled_kept_available(const wdb_theta* th) { return th->tA.grec && th->tAt.grec; }
 
 void build_tiled16(wdb_theta* th) {
   WDB_REQUIRE(tiled_supported(th), WDB_ERR_ARG, "tiled storage needs subbands of side >= 1 at every level");
@@ -1021,6 +1026,7 @@ template <typename X>
 void objective_tiled(const wdb_theta* th, const X* x, const float* x0, double* r64, double* part, int64_t nb,
                      hipStream_t s) {
   WDB_REQUIRE(nb == tiled_check_blocks(th), WDB_ERR_ARG, "partial count does not match the tiles");
+  WDB_REQUIRE(!th->tile_kept || tiled_kept_available(th), WDB_ERR_ARG, "kept-value tiles not built");
   const Geo g = geo_of(th);
   with_shape(th->tile_waves, th->tile_unroll, [&](auto Wc, auto Uc) {
     constexpr int W = decltype(Wc)::value, U = decltype(Uc)::value;
@@ -1052,7 +1058,7 @@ void launch_objective_tiled(const wdb_theta* th, const double* x, const float* x
 void launch_res_tiled(const wdb_theta* th, bool transpose, const float* y, const float* b, float* r, int* kdev,
                       hipStream_t s) {
   const Tiled& T = transpose ? th->tAt : th->tA;
-  WDB_REQUIRE(T.desc, WDB_ERR_ARG, "tiled storage not built");
+  WDB_REQUIRE(T.desc && (!th->tile_kept || T.grec), WDB_ERR_ARG, "tiled storage not built");
   const Geo g = geo_of(th);
   with_shape(th->tile_waves, th->tile_unroll, [&](auto Wc, auto Uc) {
     constexpr int W = decltype(Wc)::value, U = decltype(Uc)::value;
@@ -1067,7 +1073,7 @@ void launch_res_tiled(const wdb_theta* th, bool transpose, const float* y, const
 void launch_prox_tiled(const wdb_theta* th, const float* r, float* x, float* y, float tau, float thr, float beta,
                        const int* kdev, const float* pinv, const float* tw, const double* anc, hipStream_t s) {
   const Tiled& T = th->tAt;
-  WDB_REQUIRE(T.desc, WDB_ERR_ARG, "tiled storage not built");
+  WDB_REQUIRE(T.desc && (!th->tile_kept || T.grec), WDB_ERR_ARG, "tiled storage not built");
   const Geo g = geo_of(th);
   with_shape(th->tile_waves, th->tile_unroll, [&](auto Wc, auto Uc) {
     constexpr int W = decltype(Wc)::value, U = decltype(Uc)::value;
@@ -1092,6 +1098,8 @@ extern "C" wdb_status wdb_set_tile_values(wdb_theta* th, int32_t kept) {
   WDB_API_BEGIN
   WDB_REQUIRE(th, WDB_ERR_ARG, "null handle");
   WDB_REQUIRE(kept == 0 || kept == 1, WDB_ERR_ARG, "tile value layout must be 0 (dense) or 1 (kept values)");
+  WDB_REQUIRE(!kept || !th->tA.desc || wdb::tiled_kept_available(th), WDB_ERR_ARG,
+              "this operator's tiles have no kept-value layout (more than 2 GiB of kept values)");
   wdb::drop_graph(th);  // the cached iteration graph may refer to what this call changes
   th->tile_kept = kept;
   WDB_API_END
