@@ -298,8 +298,10 @@ wdb_status wdb_set_tile_shape(wdb_theta* th, int32_t waves, int32_t unroll);
  * offset of the group's values (a lane's values start at that offset plus
  * the kept entries of the rows below it).  Same products, same summation
  * order; the kept layout streams fewer bytes and spends more instructions per
- * group.  Both layouts are built with the tiles; the autotuner also picks
- * between them.  Errors: WDB_ERR_ARG (kept not 0 or 1). */
+ * group.  Both layouts are built with the tiles (the kept one when its
+ * values fit in 2 GiB, the reach of its 32-bit offsets); the autotuner also
+ * picks between them.  Errors: WDB_ERR_ARG (kept not 0 or 1, or kept = 1 on
+ * tiles built without the kept layout). */
 wdb_status wdb_set_tile_values(wdb_theta* th, int32_t kept);
 
 /* Project autotuner: times the iteration kernel pair `reps` times (two
