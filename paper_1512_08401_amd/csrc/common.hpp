@@ -334,9 +334,9 @@ void build_tiled16(wdb_theta* th);  // builds qA / qAt (16-bit values, scales qs
 // per tile (nb = tiled_check_blocks).
 int64_t tiled_check_blocks(const wdb_theta* th);
 void launch_objective_tiled(const wdb_theta* th, const float* x, const float* x0, double* r64, double* part,
-                            int64_t nb, hipStream_t s);
+                            int64_t nb, hipStream_t s, float* cneg = nullptr);
 void launch_objective_tiled(const wdb_theta* th, const double* x, const float* x0, double* r64, double* part,
-                            int64_t nb, hipStream_t s);
+                            int64_t nb, hipStream_t s, float* cneg = nullptr);
 void launch_res_tiled16(const wdb_theta* th, const float* y, const float* b, float* r, int* kdev, int scale_out,
                         hipStream_t s);
 void launch_prox_tiled16(const wdb_theta* th, const float* rs, float* x, float* y, float tau, float thr,

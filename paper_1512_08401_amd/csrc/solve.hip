@@ -1117,8 +1117,10 @@ struct Check {
 
 // Enqueue the float64 stopping-test products and their reduction into four
 // device doubles at `dst`: ||r||^2, <r, x0>, sum w|x|, max |g_i| / w_i.
+// With `cneg` (tiled layouts only) the forward product also writes -r64 as
+// float32 there; returns whether it did.
 template <typename X>
-void enqueue_check(wdb_theta* th, const X* x, const float* x0, double* dst, hipStream_t s) {
+bool enqueue_check(wdb_theta* th, const X* x, const float* x0, double* dst, hipStream_t s, float* cneg = nullptr) {
   const SellView A = view(th->A), At = view(th->At);
   const bool tiled = kernel_group(th) == kTiled;
   const int G = check_group(th);
@@ -1126,7 +1128,7 @@ void enqueue_check(wdb_theta* th, const X* x, const float* x0, double* dst, hipS
   WDB_REQUIRE(nb <= th->ws_nblocks, WDB_ERR_ARG, "partial-sum workspace too small");
   double* part = th->ws_partial;
   if (tiled) {
-    launch_objective_tiled(th, x, x0, th->ws_r64, part, nb, s);
+    launch_objective_tiled(th, x, x0, th->ws_r64, part, nb, s, cneg);
   } else if (G > 0) {
     with_group(G, [&](auto g) {
       constexpr int GG = decltype(g)::value;
@@ -1141,6 +1143,7 @@ void enqueue_check(wdb_theta* th, const X* x, const float* x0, double* dst, hipS
   }
   hipLaunchKernelGGL(k_reduce4, dim3(1), dim3(kReduceThreads), 0, s, part, nb, 0x8u, dst);
   WDB_HIP(hipGetLastError());
+  return tiled && cneg;
 }
 
 // E and the relative duality gap from the four reduced scalars.
@@ -1249,10 +1252,13 @@ wdb_status solve_impl(wdb_theta* th, const float* x0_src, bool from_image, float
   // anchor, the float64 products run on the anchor, and their residual gives
   // the next right-hand side.
   auto enqueue_point = [&](double* dst) {
-    if (!anchored) return enqueue_check(th, static_cast<const float*>(x_out), th->ws_x0, dst, s);
+    if (!anchored) {
+      enqueue_check(th, static_cast<const float*>(x_out), th->ws_x0, dst, s);
+      return;
+    }
     hipLaunchKernelGGL(k_reanchor, vec_grid(N), dim3(kBlock), 0, s, th->ws_a64, x_out, th->ws_y, N);
-    enqueue_check(th, static_cast<const double*>(th->ws_a64), th->ws_x0, dst, s);
-    hipLaunchKernelGGL(k_anchor_rhs, vec_grid(N), dim3(kBlock), 0, s, th->ws_r64, th->ws_c, N);
+    if (!enqueue_check(th, static_cast<const double*>(th->ws_a64), th->ws_x0, dst, s, th->ws_c))
+      hipLaunchKernelGGL(k_anchor_rhs, vec_grid(N), dim3(kBlock), 0, s, th->ws_r64, th->ws_c, N);
     WDB_HIP(hipGetLastError());
   };
   auto check_point = [&]() {

@@ -378,7 +378,7 @@ template <int W, int U, bool KEPT, typename X>
 __global__ __launch_bounds__(64 * W) void k_obj_fwd_tl(TiledView T, Geo g, const X* __restrict__ x,
                                                        const float* __restrict__ b, const float* __restrict__ w,
                                                        double* __restrict__ r64, double* __restrict__ partial,
-                                                       int64_t nblocks) {
+                                                       int64_t nblocks, float* __restrict__ cneg) {
   const int4 d = T.desc[blockIdx.x];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -390,6 +390,7 @@ __global__ __launch_bounds__(64 * W) void k_obj_fwd_tl(TiledView T, Geo g, const
     const double bb = static_cast<double>(b[row]);
     const double rr = acc - bb;
     r64[row] = rr;
+    if (cneg) cneg[row] = static_cast<float>(-rr);  // the anchored iteration's next right-hand side
     v0 = rr * rr;
     v1 = rr * bb;
     v2 = fabs(static_cast<double>(x[row])) * (w ? static_cast<double>(w[row]) : 1.0);
@@ -1024,7 +1025,7 @@ int64_t tiled_check_blocks(const wdb_theta* th) {
 namespace {
 template <typename X>
 void objective_tiled(const wdb_theta* th, const X* x, const float* x0, double* r64, double* part, int64_t nb,
-                     hipStream_t s) {
+                     hipStream_t s, float* cneg) {
   WDB_REQUIRE(nb == tiled_check_blocks(th), WDB_ERR_ARG, "partial count does not match the tiles");
   WDB_REQUIRE(!th->tile_kept || tiled_kept_available(th), WDB_ERR_ARG, "kept-value tiles not built");
   const Geo g = geo_of(th);
@@ -1033,11 +1034,11 @@ void objective_tiled(const wdb_theta* th, const X* x, const float* x0, double* r
     const dim3 grid(static_cast<unsigned>(nb)), block(64 * W);
     if (th->tile_kept) {
       hipLaunchKernelGGL((k_obj_fwd_tl<W, U, true, X>), grid, block, 0, s, tview(th->tA), g, x, x0, th->l1w, r64,
-                         part, nb);
+                         part, nb, cneg);
       hipLaunchKernelGGL((k_obj_bwd_tl<W, U, true>), grid, block, 0, s, tview(th->tAt), g, r64, th->l1w, part + 3 * nb);
     } else {
       hipLaunchKernelGGL((k_obj_fwd_tl<W, U, false, X>), grid, block, 0, s, tview(th->tA), g, x, x0, th->l1w, r64,
-                         part, nb);
+                         part, nb, cneg);
       hipLaunchKernelGGL((k_obj_bwd_tl<W, U, false>), grid, block, 0, s, tview(th->tAt), g, r64, th->l1w,
                          part + 3 * nb);
     }
@@ -1046,13 +1047,13 @@ void objective_tiled(const wdb_theta* th, const X* x, const float* x0, double* r
 }  // namespace
 
 void launch_objective_tiled(const wdb_theta* th, const float* x, const float* x0, double* r64, double* part,
-                            int64_t nb, hipStream_t s) {
-  objective_tiled(th, x, x0, r64, part, nb, s);
+                            int64_t nb, hipStream_t s, float* cneg) {
+  objective_tiled(th, x, x0, r64, part, nb, s, cneg);
 }
 
 void launch_objective_tiled(const wdb_theta* th, const double* x, const float* x0, double* r64, double* part,
-                            int64_t nb, hipStream_t s) {
-  objective_tiled(th, x, x0, r64, part, nb, s);
+                            int64_t nb, hipStream_t s, float* cneg) {
+  objective_tiled(th, x, x0, r64, part, nb, s, cneg);
 }
 
 void launch_res_tiled(const wdb_theta* th, bool transpose, const float* y, const float* b, float* r, int* kdev,
