@@ -200,6 +200,7 @@ struct alignas(64) GroupRec {
   uint32_t voff;
   uint32_t pad[3];
 };
+static_assert(sizeof(GroupRec) == 64, "one 64-byte record per group");
 
 // A wavefront-uniform 64-bit value in scalar registers (the value of the
 // first active lane; free when the compiler already holds it there).

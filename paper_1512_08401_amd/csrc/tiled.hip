@@ -898,6 +898,7 @@ void build_one(const wdb_theta* th, const Csr32& src, Tiled* out, int fmt = WDB_
         t.nkval = kb;
         WDB_HIP(hipMalloc(&t.grec, std::max<size_t>(ng, 1) * sizeof(GroupRec)));
         WDB_HIP(hipMalloc(reinterpret_cast<void**>(&t.kval), (kb + 4) * sizeof(float)));
+        WDB_HIP(hipMemset(t.grec, 0, sizeof(GroupRec)));  // the record a kernel reads past a tile's end
         if (ng) WDB_HIP(hipMemcpy(t.grec, rec.data(), ng * sizeof(GroupRec), hipMemcpyHostToDevice));
         WDB_HIP(hipMemset(t.kval, 0, (kb + 4) * sizeof(float)));
         int64_t ka = 0;

@@ -349,6 +349,15 @@ def test_empty_and_ragged_operator(W):
     e = W.Theta.from_csr(n, "haar", 2, np.zeros(N + 1, dtype=np.int64), np.zeros(0, np.int32), np.zeros(0))
     b = rng.standard_normal(N).astype(np.float32)
     assert np.array_equal(host(e.apply(dev(x), dev(b))), -b.astype(np.float64))
+    # the same on the tiled storage with dense and kept values (the long row's
+    # far columns go to the escape lists; the empty operator has no groups)
+    for op, ref, reft in ((th, A @ x, A.T @ x), (e, -b.astype(np.float64), np.zeros(N))):
+        op.set_kernel_layout(8, 3)
+        for kept in (0, 1):
+            op.set_tile_values(kept)
+            got = host(op.apply(dev(x), dev(b) if op is e else None))
+            assert np.max(np.abs(got - ref)) <= 1e-4, kept
+            assert np.max(np.abs(host(op.apply(dev(x), transpose=True)) - reft)) <= 1e-4, kept
 
 
 def test_prox_step_matches_oracle(W, p64):
