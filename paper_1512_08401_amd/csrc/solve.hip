@@ -461,22 +461,31 @@ __global__ __launch_bounds__(kBlock) void k_obj_bwd(SellView At, const double* _
   block_partials<1, 1u>(v, partial, nblocks);
 }
 
-// Single block: out[k] = reduction of partial[k * nblocks ...] in a fixed order.
-// Final reduction of the stopping test's per-block partials: out[k] = sum (or
-// max, bit k of maxmask) of partial[k * nblocks + i] over i, for k < 4.  One
-// block of 1024 threads; each thread folds its strided share of all four rows
-// at once (every load of a pass independent of the others), then a fixed tree.
-constexpr int kReduceThreads = 1024;
-__global__ __launch_bounds__(kReduceThreads) void k_reduce4(const double* __restrict__ partial, int64_t nblocks,
-                                                            unsigned maxmask, double* __restrict__ out) {
+// Final reduction of the stopping test's per-block partials in two passes
+// with a fixed order: out[k] = sum (or max, bit k of maxmask) of
+// partial[k * nblocks + i] over i, for k < 4.  Pass 1: block b folds the
+// contiguous range b of kReduceParts ranges (thread t takes i = t, t + T, ...
+// of the range), then a fixed tree, into tmp[k * kReduceParts + b]; pass 2: one
+// block folds the kReduceParts values of each row with a fixed tree.  The max
+// rows hold non-negative values, so 0 is their neutral element.
+constexpr int kReduceParts = 64;
+constexpr int kReduceThreads = 256;
+__device__ __forceinline__ double fold4(unsigned maxmask, int k, double a, double b) {
+  return ((maxmask >> k) & 1u) ? fmax(a, b) : a + b;
+}
+__global__ __launch_bounds__(kReduceThreads) void k_reduce4_part(const double* __restrict__ partial, int64_t nblocks,
+                                                                 unsigned maxmask, double* __restrict__ tmp) {
   __shared__ double sh[4][kReduceThreads];
+  const int64_t len = (nblocks + kReduceParts - 1) / kReduceParts;
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * len;
+  const int64_t i1 = i0 + len < nblocks ? i0 + len : nblocks;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t i = threadIdx.x; i < nblocks; i += kReduceThreads) {
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += kReduceThreads) {
     double p[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) p[k] = partial[k * nblocks + i];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) acc[k] = ((maxmask >> k) & 1u) ? fmax(acc[k], p[k]) : acc[k] + p[k];
+    for (int k = 0; k < 4; ++k) acc[k] = fold4(maxmask, k, acc[k], p[k]);
   }
 #pragma unroll
   for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = acc[k];
@@ -484,9 +493,22 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce4(const double* __rest
   for (int w = kReduceThreads / 2; w > 0; w >>= 1) {
     if (threadIdx.x < w) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
-        sh[k][threadIdx.x] = ((maxmask >> k) & 1u) ? fmax(sh[k][threadIdx.x], sh[k][threadIdx.x + w])
-                                                   : sh[k][threadIdx.x] + sh[k][threadIdx.x + w];
+      for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = fold4(maxmask, k, sh[k][threadIdx.x], sh[k][threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) tmp[threadIdx.x * kReduceParts + blockIdx.x] = sh[threadIdx.x][0];
+}
+__global__ __launch_bounds__(kReduceParts) void k_reduce4_final(const double* __restrict__ tmp, unsigned maxmask,
+                                                                double* __restrict__ out) {
+  __shared__ double sh[4][kReduceParts];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = tmp[k * kReduceParts + threadIdx.x];
+  __syncthreads();
+  for (int w = kReduceParts / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = fold4(maxmask, k, sh[k][threadIdx.x], sh[k][threadIdx.x + w]);
     }
     __syncthreads();
   }
@@ -794,7 +816,7 @@ void ensure_workspace(wdb_theta* th) {
     WDB_HIP(hipMemset(th->ws_a64, 0, N * sizeof(double)));
     WDB_HIP(hipMalloc(reinterpret_cast<void**>(&th->ws_v64), 3 * N * sizeof(double)));
     WDB_HIP(hipMalloc(reinterpret_cast<void**>(&th->ws_partial), 4 * th->ws_nblocks * sizeof(double)));
-    WDB_HIP(hipMalloc(reinterpret_cast<void**>(&th->ws_scalar), 16 * sizeof(double)));
+    WDB_HIP(hipMalloc(reinterpret_cast<void**>(&th->ws_scalar), (16 + 4 * kReduceParts) * sizeof(double)));
     WDB_HIP(hipMalloc(reinterpret_cast<void**>(&th->ws_rho), kRhoChunk * sizeof(double)));
     WDB_HIP(hipMalloc(reinterpret_cast<void**>(&th->ws_k), sizeof(int)));
     WDB_HIP(hipHostMalloc(reinterpret_cast<void**>(&th->host_scalar), 16 * sizeof(double), hipHostMallocDefault));
@@ -1141,7 +1163,9 @@ bool enqueue_check(wdb_theta* th, const X* x, const float* x0, double* dst, hipS
     hipLaunchKernelGGL(k_obj_fwd<X>, slot_grid(A), dim3(kBlock), 0, s, A, x, x0, th->l1w, th->ws_r64, part, nb);
     hipLaunchKernelGGL(k_obj_bwd, slot_grid(At), dim3(kBlock), 0, s, At, th->ws_r64, th->l1w, part + 3 * nb, nb);
   }
-  hipLaunchKernelGGL(k_reduce4, dim3(1), dim3(kReduceThreads), 0, s, part, nb, 0x8u, dst);
+  double* tmp = th->ws_scalar + 16;  // 4 x kReduceParts doubles after the 16 scalars
+  hipLaunchKernelGGL(k_reduce4_part, dim3(kReduceParts), dim3(kReduceThreads), 0, s, part, nb, 0x8u, tmp);
+  hipLaunchKernelGGL(k_reduce4_final, dim3(1), dim3(kReduceParts), 0, s, tmp, 0x8u, dst);
   WDB_HIP(hipGetLastError());
   return tiled && cneg;
 }

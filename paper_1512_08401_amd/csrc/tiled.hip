@@ -21,7 +21,13 @@
 // group size), first row, log2 side | flags}; codes as uint32 in groups of 4
 // (float32) or 8 (16-bit values), padded with a code of value 0; values as
 // [group][lane][group size] so that a lane loads one 16-byte vector per
-// group.  The groups of a tile are dealt round-robin to the W wavefronts of
+// group.  The float32 copies also hold the kept-value layout (codes.hpp,
+// GroupRec): per group of 4 codes a record with the codes, a row mask per code
+// and an offset, and only the kept values, which a lane reads from its offset
+// and spreads over the 4 codes with selects on the masks; the kernels read one
+// layout or the other (wdb_set_tile_values, or the autotuner's pick) and add
+// the same products in the same order.  The groups of a tile are dealt
+// round-robin to the W wavefronts of
 // its block and the W partial sums are added in LDS in wavefront order
 // (deterministic).  Entries whose code does not fit (displacement beyond 128
 // or level gap beyond 3) go to per-row escape lists, whose entries are dealt
