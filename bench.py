@@ -185,7 +185,7 @@ def main():
                     help="relative duality gap of the warm-start training targets (learned form)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU runs are not part of this build",
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
 
